@@ -1,0 +1,61 @@
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def pytest_configure(config):
+    config.addinivalue_line("markers", "gpu: needs an MI355X (gfx950) GPU")
+    config.addinivalue_line("markers", "slow: full-size workload (tens of seconds)")
+
+
+def _ensure_built():
+    """Build the CPU-side libraries if nothing is built yet (gcc only, seconds)."""
+    import prgen
+    import oracle
+    if not os.path.exists(os.path.join(ROOT, "prgen", "libprgen.so")):
+        from prgen.build import build
+        build()
+    if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+        from oracle.build import build as obuild
+        obuild()
+    return prgen, oracle
+
+
+_ensure_built()
+
+
+def l1(a, b):
+    return float(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)).sum())
+
+
+def topk_agree(ref, got, k):
+    """Top-k ranking check with the tie rule: rank by (value desc, id asc) in both
+    vectors; position j may differ only if the two ids' reference values differ by
+    at most 2 * eps_inf, where eps_inf = max |got - ref|.  Returns (ok, swaps, eps)."""
+    ref = np.asarray(ref, dtype=np.float64)
+    got = np.asarray(got, dtype=np.float64)
+    n = ref.size
+    k = min(k, n)
+    ids = np.arange(n)
+    r_order = np.lexsort((ids, -ref))[:k]
+    g_order = np.lexsort((ids, -got))[:k]
+    eps = float(np.abs(got - ref).max())
+    swaps = 0
+    for a, b in zip(r_order, g_order):
+        if a == b:
+            continue
+        swaps += 1
+        if abs(ref[a] - ref[b]) > 2 * eps:
+            return False, swaps, eps
+    return True, swaps, eps
+
+
+@pytest.fixture(scope="session")
+def libs():
+    return _ensure_built()
