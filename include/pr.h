@@ -1,0 +1,194 @@
+/*
+ * pr.h -- C ABI of libpr.so: IFP1 / IFP2 forward-push PageRank and the power
+ * method on one AMD MI355X (gfx950) GPU.
+ *
+ * The method is that of Zhang, Tang, Yao, Liang, "Two Parallel PageRank
+ * Algorithms via Improving Forward Push" (arXiv 2302.03245).  The arguments
+ * follow the problem statement of its forward-push algorithm (section 2.2,
+ * Algorithm 1): a graph G(V, E), the damping factor c, the personalization
+ * vector p and the residual threshold xi; the output is the PageRank vector
+ * pi.  The number of calculation threads K of Algorithms 2 and 3 is not an
+ * argument: it is the GPU launch configuration.
+ *
+ * Conventions
+ *  - Every function returns a pr_status; 0 (PR_OK) is success, PR_ENOCONV (> 0)
+ *    is a warning with a usable result, negative values are errors.
+ *  - On a negative status no output (pi, stats, *out handle) is written.
+ *    pr_last_error() then returns a thread-local message.
+ *  - Vertices are 0 .. n-1.  Edge i -> j is stored in row i of a CSR:
+ *    j = col[row_ptr[i] + k], 0 <= k < row_ptr[i+1] - row_ptr[i].
+ *  - deg(i) is the row length; a self-loop counts toward deg(i); repeated
+ *    edges count with multiplicity unless PR_DEDUPE is given at upload.
+ *    A vertex with deg(i) == 0 is dangling (section 2.1).
+ *  - Sizes: n < 2^31 and m < 2^31 (the device stores 32-bit indices and
+ *    offsets); larger graphs are rejected with PR_EINVAL.
+ *  - Thread safety: distinct graphs may be used concurrently.  Solves on one
+ *    graph from several host threads or streams are allowed (the graph is
+ *    read-only after upload); freeing a graph while a solve runs is undefined.
+ */
+#ifndef PR_H
+#define PR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PR_OK = 0,
+    PR_ENOCONV = 1,  /* max_sweeps reached: pi holds the normalised best estimate, stats->l1_bound its quality */
+    PR_EINVAL = -1,  /* invalid argument (see each function) */
+    PR_ENOMEM = -2,  /* device or host allocation failed */
+    PR_EDEVICE = -3  /* a HIP runtime call failed */
+} pr_status;
+
+typedef struct pr_graph pr_graph; /* opaque, device-resident, owned by the library */
+
+/* residual (pushing mass) precision; the reserved mass and all reductions are always FP64 */
+typedef enum { PR_RES_FP64 = 0, PR_RES_FP32 = 1 } pr_residual;
+
+/* stop rule */
+typedef enum {
+    PR_STOP_XI = 0, /* stop when no non-dangling vertex has residual > xi (Algorithms 2 and 3) */
+    PR_STOP_L1 = 1  /* stop when the certified bound on ||pi - pi_exact||_1 is <= l1_tol */
+} pr_stop;
+
+/* pr_graph_upload flags */
+#define PR_INPUT_DEVICE 0x1u /* row_ptr and col are device pointers */
+#define PR_DEDUPE 0x2u       /* collapse repeated edges (the 0/1 adjacency matrix of section 2.1) */
+
+/* pr_opts.flags */
+#define PR_P_DEVICE 0x1u     /* p is a device pointer (double[n]) */
+#define PR_OUT_DEVICE 0x2u   /* pi is a device pointer */
+#define PR_IFP2_LITERAL 0x4u /* IFP2: drop the leftover residual at normalisation, as Algorithm 3 writes it */
+#define PR_FORCE_PUSH 0x8u   /* every sweep scatters along out-edges with atomic adds */
+#define PR_FORCE_PULL 0x10u  /* every sweep gathers along in-edges (no atomics) */
+#define PR_PROFILE 0x20u     /* time each sweep kernel with HIP events (stats->kernel_*) */
+
+typedef struct {
+    double c;           /* damping factor, 0 < c < 1 (section 2.1) */
+    double xi;          /* PR_STOP_XI threshold on a residual, in units where the initial residual
+                           is n * p_i (1 for every vertex under uniform p, as in Algorithms 2 and 3) */
+    double l1_tol;      /* PR_STOP_L1 target; also the power method's target */
+    int32_t stop;       /* pr_stop */
+    int32_t residual;   /* pr_residual */
+    int32_t max_sweeps; /* 0 -> 100000 */
+    uint32_t flags;     /* PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE */
+    void *stream;       /* hipStream_t to run on; NULL -> the graph's own stream */
+} pr_opts;
+
+typedef struct {
+    int32_t sweeps;             /* synchronous sweeps (one reserve + one push or pull each); power: iterations */
+    int32_t pull_sweeps;        /* of which gathered along in-edges */
+    int64_t edges_processed;    /* sum over sweeps of the valid out-edges of the vertices that pushed,
+                                   plus the in-edges read by IFP2's dangling phase; power: iterations * m */
+    int64_t edges_traversed;    /* edges the kernels actually read (a pull sweep reads every in-edge) */
+    int64_t vertex_pushes;      /* sum over sweeps of the number of vertices that pushed */
+    double residual_l1;         /* final non-dangling residual / total mass (power: last ||x' - x||_1) */
+    double l1_bound;            /* certified upper bound on ||pi - pi_exact||_1 */
+    double seconds_solve;       /* device time from initialisation to the written result */
+    double seconds_preprocess;  /* one-time per-graph preprocessing charged to this method (seconds) */
+    /* PR_PROFILE only (else 0): the scatter (push) and gather (pull) kernels of the sweeps,
+       timed with HIP events on the solve stream; launches that did work, their summed
+       duration, and their algorithmic bytes (edge-index stream + residual traffic) */
+    double push_seconds, push_bytes;
+    int64_t push_launches;
+    double pull_seconds, pull_bytes;
+    int64_t pull_launches;
+} pr_stats;
+
+typedef struct {
+    int64_t n, m;
+    int64_t n_dangling;     /* out-degree 0 */
+    int64_t m_dangling;     /* edges whose target is dangling (invalidated by IFP2) */
+    int64_t n_unreferenced; /* in-degree 0 */
+    int64_t device_bytes;   /* device memory held by the graph */
+    double seconds_upload;  /* whole upload: copies, classification, relabelling, plans */
+    double seconds_split;   /* the IFP2 edge invalidation: stable split of every row into edges
+                               towards non-dangling and towards dangling targets */
+} pr_graph_info_t;
+
+/*
+ * Fill *o with the defaults: c = 0.85 (the experiments' damping factor),
+ * xi = 1e-12, l1_tol = 1e-6, PR_STOP_XI, PR_RES_FP64, max_sweeps 0, flags 0,
+ * stream NULL.
+ */
+void pr_opts_default(pr_opts *o);
+
+/*
+ * Copy a directed graph to the device and prepare it (graph of section 2.1).
+ *   n        number of vertices, 1 <= n < 2^31
+ *   m        number of edges, 0 <= m < 2^31
+ *   row_ptr  int64[n+1], row_ptr[0] == 0, non-decreasing, row_ptr[n] == m
+ *   col      int32[m], every entry in [0, n)   (may be NULL when m == 0)
+ *   flags    PR_INPUT_DEVICE: row_ptr / col are device pointers; PR_DEDUPE
+ *   out      receives the handle
+ * The inputs are copied; the caller keeps ownership of them.  The handle is
+ * owned by the library until pr_graph_free.  Errors: PR_EINVAL for any
+ * violated condition above or an unknown flag, PR_ENOMEM, PR_EDEVICE.
+ */
+pr_status pr_graph_upload(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col,
+                          uint32_t flags, pr_graph **out);
+
+/* Release a graph and its device memory.  NULL is accepted.  */
+pr_status pr_graph_free(pr_graph *g);
+
+/* Shape and cost figures of an uploaded graph (the data-set table columns of section 4.1). */
+pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out);
+
+/*
+ * IFP1 (section 3.2, Algorithm 2): every non-dangling vertex whose residual
+ * exceeds the threshold reserves 100 % of it and pushes c * r / deg(i) to each
+ * out-neighbour; dangling vertices never push; the result is
+ * pi = (pibar + h) / sum(pibar + h), which by Eq. 4 is the PageRank vector of
+ * Eq. 1 for personalization p (dangling mass jumps according to p).
+ *   p    double[n], p >= 0, finite, sum > 0 (normalised by its sum); NULL = uniform e/n
+ *   o    options (NULL = defaults)
+ *   pi   double[n] output (host, or device with PR_OUT_DEVICE)
+ *   st   optional statistics
+ * One GPU sweep processes every vertex above the threshold once (a
+ * synchronous version of one scan of all calculation threads, section 3.3.1).
+ * Errors: PR_EINVAL (bad graph handle, options, p), PR_ENOMEM, PR_EDEVICE;
+ * PR_ENOCONV when max_sweeps ends the iteration.
+ */
+pr_status pr_solve_ifp1(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st);
+
+/*
+ * IFP2 (section 3.4, Algorithm 3): as IFP1, but edges into dangling vertices
+ * are invalidated during the sweeps (phase 1) and every dangling vertex d
+ * gathers c * z_u / deg(u) from its in-neighbours once afterwards (phase 2),
+ * deg being the original out-degree.  z = pibar + h by default;
+ * PR_IFP2_LITERAL uses z = pibar and drops the leftover residual as the
+ * algorithm is written.  Arguments and errors as pr_solve_ifp1.
+ */
+pr_status pr_solve_ifp2(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st);
+
+/*
+ * Power method on P'' = c P' + (1-c) p e^T (Eq. 1), the baseline the paper
+ * compares against (section 4.3): x <- c P x + (c d^T x + (1-c) e^T x) p from
+ * x = p until c / (1-c) * ||x' - x||_1 <= l1_tol; xi and stop are ignored.
+ * Arguments and errors as pr_solve_ifp1; l1_tol must be > 0.
+ */
+pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st);
+
+/*
+ * Single-source personalized PageRank (section 2.1: p = e_s; the mass of
+ * dangling vertices jumps back to s because P' = P + p d^T), solved by IFP2
+ * for each of the k sources.
+ *   sources  int32[k] host array, each in [0, n); k >= 1
+ *   pi       double[k * n], row r is the PPR vector of sources[r]
+ *   st       optional, k entries
+ * Returns the worst status over the k solves.
+ */
+pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_opts *o, double *pi,
+                 pr_stats *st);
+
+/* Message describing the last error on this thread ("" if none). */
+const char *pr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PR_H */

@@ -1,0 +1,281 @@
+"""IFP1 / IFP2 forward-push PageRank on an AMD MI355X (gfx950).
+
+Thin ctypes binding of ``libpr.so`` (C ABI in ``include/pr.h``).  Every step of a
+solve runs in the library's HIP kernels; this module only marshals arguments.
+Host inputs are numpy arrays; device inputs/outputs may be torch CUDA tensors
+(passed by pointer, torch is used only for device memory and streams).
+
+    g = upload(row_ptr, col)                       # CSR, int64[n+1], int32[m]
+    pi, st = ifp2(g, c=0.85, xi=1e-12)             # numpy float64[n]
+    pi, st = ifp2(g, l1_tol=1e-6, residual="fp32", out=torch.empty(n, dtype=torch.float64, device="cuda"))
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpr.so")
+
+PR_OK, PR_ENOCONV, PR_EINVAL, PR_ENOMEM, PR_EDEVICE = 0, 1, -1, -2, -3
+PR_RES_FP64, PR_RES_FP32 = 0, 1
+PR_STOP_XI, PR_STOP_L1 = 0, 1
+PR_INPUT_DEVICE, PR_DEDUPE = 0x1, 0x2
+PR_P_DEVICE, PR_OUT_DEVICE, PR_IFP2_LITERAL = 0x1, 0x2, 0x4
+PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE = 0x8, 0x10, 0x20
+
+# every symbol the two public headers declare
+EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_info", "pr_solve_ifp1",
+            "pr_solve_ifp2", "pr_solve_power", "pr_ppr", "pr_last_error",
+            "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len"]
+
+
+class PRError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"libpr status {status}: {msg}")
+        self.status = status
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("xi", ctypes.c_double), ("l1_tol", ctypes.c_double),
+                ("stop", ctypes.c_int32), ("residual", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("flags", ctypes.c_uint32), ("stream", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("sweeps", ctypes.c_int32), ("pull_sweeps", ctypes.c_int32),
+                ("edges_processed", ctypes.c_int64), ("edges_traversed", ctypes.c_int64),
+                ("vertex_pushes", ctypes.c_int64), ("residual_l1", ctypes.c_double),
+                ("l1_bound", ctypes.c_double), ("seconds_solve", ctypes.c_double),
+                ("seconds_preprocess", ctypes.c_double),
+                ("push_seconds", ctypes.c_double), ("push_bytes", ctypes.c_double),
+                ("push_launches", ctypes.c_int64),
+                ("pull_seconds", ctypes.c_double), ("pull_bytes", ctypes.c_double),
+                ("pull_launches", ctypes.c_int64)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class GraphInfo(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("n_dangling", ctypes.c_int64),
+                ("m_dangling", ctypes.c_int64), ("n_unreferenced", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("seconds_upload", ctypes.c_double),
+                ("seconds_split", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libpr.so; raises if it is not built (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
+                           "(the HIP library is required, there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, u32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p
+    L.pr_opts_default.argtypes = [ctypes.POINTER(Opts)]
+    L.pr_opts_default.restype = None
+    L.pr_graph_upload.argtypes = [i64, i64, vp, vp, u32, ctypes.POINTER(vp)]
+    L.pr_graph_upload.restype = ctypes.c_int
+    L.pr_graph_free.argtypes = [vp]
+    L.pr_graph_free.restype = ctypes.c_int
+    L.pr_graph_info.argtypes = [vp, ctypes.POINTER(GraphInfo)]
+    L.pr_graph_info.restype = ctypes.c_int
+    for name in ("pr_solve_ifp1", "pr_solve_ifp2", "pr_solve_power"):
+        f = getattr(L, name)
+        f.argtypes = [vp, dp, ctypes.POINTER(Opts), dp, ctypes.POINTER(Stats)]
+        f.restype = ctypes.c_int
+    L.pr_ppr.argtypes = [vp, vp, i32, ctypes.POINTER(Opts), dp, ctypes.POINTER(Stats)]
+    L.pr_ppr.restype = ctypes.c_int
+    L.pr_last_error.argtypes = []
+    L.pr_last_error.restype = ctypes.c_char_p
+    L.pr_probe_copy.argtypes = [vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double)]
+    L.pr_probe_copy.restype = ctypes.c_int
+    L.pr_probe_gather.argtypes = [vp, vp, i64, vp, i64, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double)]
+    L.pr_probe_gather.restype = ctypes.c_int
+    L.pr_probe_scatter.argtypes = [vp, vp, i64, ctypes.c_float, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double)]
+    L.pr_probe_scatter.restype = ctypes.c_int
+    L.pr_probe_gather_out_len.argtypes = [i64]
+    L.pr_probe_gather_out_len.restype = i64
+    _lib = L
+    return L
+
+
+def _err(status):
+    return PRError(status, lib().pr_last_error().decode())
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr_host(a, dtype):
+    a = np.ascontiguousarray(a, dtype=dtype)
+    return a, a.ctypes.data
+
+
+def _ptr_any(x, np_dtype, torch_dtype_name):
+    """(keepalive, pointer, on_device) for a numpy array or a torch tensor."""
+    if x is None:
+        return None, None, False
+    if _is_torch(x):
+        if str(x.dtype) != f"torch.{torch_dtype_name}":
+            raise TypeError(f"expected a {torch_dtype_name} tensor")
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return x, x.data_ptr(), x.is_cuda
+    a, p = _ptr_host(x, np_dtype)
+    return a, p, False
+
+
+def _stream_handle(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(stream.cuda_stream)
+
+
+class Graph:
+    """A graph resident in device memory (handle of pr_graph_upload)."""
+
+    def __init__(self, handle, n, m):
+        self._h = handle
+        self.n, self.m = n, m
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph was freed")
+        return self._h
+
+    def info(self) -> dict:
+        gi = GraphInfo()
+        st = lib().pr_graph_info(self.handle, ctypes.byref(gi))
+        if st != PR_OK:
+            raise _err(st)
+        return {k: getattr(gi, k) for k, _ in gi._fields_}
+
+    def free(self):
+        if self._h is not None:
+            lib().pr_graph_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def upload(row_ptr, col, dedupe: bool = False) -> Graph:
+    """Copy a CSR graph (host numpy or device torch tensors) to the device."""
+    rp_keep, rp_ptr, rp_dev = _ptr_any(row_ptr, np.int64, "int64")
+    col_keep, col_ptr, col_dev = _ptr_any(col, np.int32, "int32")
+    if rp_dev != col_dev:
+        raise ValueError("row_ptr and col must both be host or both be device buffers")
+    n = (rp_keep.shape[0] if not _is_torch(rp_keep) else rp_keep.numel()) - 1
+    m = col_keep.shape[0] if not _is_torch(col_keep) else col_keep.numel()
+    flags = (PR_INPUT_DEVICE if rp_dev else 0) | (PR_DEDUPE if dedupe else 0)
+    h = ctypes.c_void_p()
+    st = lib().pr_graph_upload(int(n), int(m), rp_ptr, col_ptr if m else None, flags, ctypes.byref(h))
+    if st != PR_OK:
+        raise _err(st)
+    g = Graph(h.value, int(n), int(m))
+    if dedupe:
+        g.m = g.info()["m"]
+    return g
+
+
+def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, power=False):
+    o = Opts()
+    lib().pr_opts_default(ctypes.byref(o))
+    o.c = c
+    if xi is not None:
+        o.xi = xi
+    if l1_tol is not None:
+        o.l1_tol = l1_tol
+        if not power:
+            o.stop = PR_STOP_L1
+    o.residual = {"fp64": PR_RES_FP64, "fp32": PR_RES_FP32}[residual]
+    o.max_sweeps = max_sweeps
+    o.stream = _stream_handle(stream)
+    flags = 0
+    if literal:
+        flags |= PR_IFP2_LITERAL
+    if mode == "push":
+        flags |= PR_FORCE_PUSH
+    elif mode == "pull":
+        flags |= PR_FORCE_PULL
+    elif mode is not None:
+        raise ValueError("mode must be None, 'push' or 'pull'")
+    if profile:
+        flags |= PR_PROFILE
+    o.flags = flags
+    return o
+
+
+def _solve(fn, g, p, o, out):
+    p_keep, p_ptr, p_dev = _ptr_any(p, np.float64, "float64")
+    if p is not None:
+        n_p = p_keep.numel() if _is_torch(p_keep) else p_keep.shape[0]
+        if n_p != g.n:
+            raise ValueError("p must have n entries")
+    if p_dev:
+        o.flags |= PR_P_DEVICE
+    if out is None:
+        out = np.empty(g.n, dtype=np.float64)
+    out_keep, out_ptr, out_dev = _ptr_any(out, np.float64, "float64")
+    if (out_keep.numel() if _is_torch(out_keep) else out_keep.shape[0]) != g.n:
+        raise ValueError("out must have n entries")
+    if not _is_torch(out) and out_keep is not out:
+        raise ValueError("out must be a contiguous float64 numpy array")
+    if out_dev:
+        o.flags |= PR_OUT_DEVICE
+    st = Stats()
+    status = fn(g.handle, p_ptr, ctypes.byref(o), out_ptr, ctypes.byref(st))
+    if status < 0:
+        raise _err(status)
+    d = st.as_dict()
+    d["status"] = status
+    return out, d
+
+
+def ifp1(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
+         stream=None, mode=None, profile=False):
+    """IFP1 (Algorithm 2).  `l1_tol` switches to the certified-L1 stop rule."""
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, profile)
+    return _solve(lib().pr_solve_ifp1, g, p, o, out)
+
+
+def ifp2(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
+         stream=None, literal=False, mode=None, profile=False):
+    """IFP2 (Algorithm 3).  `literal` drops the leftover residual at normalisation."""
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile)
+    return _solve(lib().pr_solve_ifp2, g, p, o, out)
+
+
+def power(g: Graph, p=None, c=0.85, l1_tol=1e-9, residual="fp64", max_sweeps=0, out=None, stream=None,
+          profile=False):
+    """Power method on P'' until the certified L1 error is <= l1_tol."""
+    o = _opts(c, None, l1_tol, residual, max_sweeps, stream, False, None, profile, power=True)
+    return _solve(lib().pr_solve_power, g, p, o, out)
+
+
+def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, stream=None):
+    """Single-source PPR for each source (IFP2); returns (float64[k, n], list of stats dicts)."""
+    src = np.ascontiguousarray(sources, dtype=np.int32)
+    k = int(src.shape[0])
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, None, False)
+    out = np.empty((k, g.n), dtype=np.float64)
+    st = (Stats * max(k, 1))()
+    status = lib().pr_ppr(g.handle, src.ctypes.data if k else None, k, ctypes.byref(o), out.ctypes.data, st)
+    if status < 0:
+        raise _err(status)
+    return out, [dict(st[i].as_dict(), status=status) for i in range(k)]

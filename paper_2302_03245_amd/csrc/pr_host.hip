@@ -1,0 +1,822 @@
+// pr_host.hip -- host side of libpr.so: the C ABI of include/pr.h, graph
+// upload and preparation, and the sweep loop of each solver.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <climits>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pr.h"
+#include "pr_internal.h"
+
+using namespace prk;
+
+struct pr_graph {
+    Graph g;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+pr_status fail(pr_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+pr_status hip_fail(hipError_t e, const char *what) {
+    return fail(e == hipErrorOutOfMemory ? PR_ENOMEM : PR_EDEVICE,
+                std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIPCHK(...)                                               \
+    do {                                                          \
+        hipError_t _e = (__VA_ARGS__);                            \
+        if (_e != hipSuccess) return hip_fail(_e, #__VA_ARGS__);  \
+    } while (0)
+
+// device buffers freed at scope exit unless released
+struct DevBufs {
+    std::vector<void *> ptrs;
+    ~DevBufs() {
+        for (void *p : ptrs) (void)hipFree(p);
+    }
+    template <typename T>
+    hipError_t alloc(T **p, size_t count) {
+        *p = nullptr;
+        if (count == 0) count = 1;
+        hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+        if (e == hipSuccess) ptrs.push_back((void *)*p);
+        return e;
+    }
+};
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+double elapsed_s(hipEvent_t a, hipEvent_t b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+    return ms * 1e-3;
+}
+
+struct EventPair {
+    hipEvent_t a = nullptr, b = nullptr;
+    EventPair() {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    ~EventPair() {
+        if (a) (void)hipEventDestroy(a);
+        if (b) (void)hipEventDestroy(b);
+    }
+};
+
+// ---------------------------------------------------------------------------
+// graph upload
+// ---------------------------------------------------------------------------
+pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
+                      pr_graph **out) {
+    if (!out) return fail(PR_EINVAL, "out is NULL");
+    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE)) return fail(PR_EINVAL, "unknown upload flag");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(PR_EINVAL, "n must be in [1, 2^31)");
+    if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PR_EINVAL, "m must be in [0, 2^31)");
+    if (!row_ptr) return fail(PR_EINVAL, "row_ptr is NULL");
+    if (m > 0 && !col) return fail(PR_EINVAL, "col is NULL");
+    const bool dev_in = flags & PR_INPUT_DEVICE;
+
+    // row_ptr is validated on the host (host inputs are checked before any HIP call)
+    std::vector<int64_t> hrp;
+    const int64_t *rp = row_ptr;
+    if (dev_in) {
+        hrp.resize((size_t)n + 1);
+        HIPCHK(hipMemcpy(hrp.data(), row_ptr, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost));
+        rp = hrp.data();
+    }
+    if (rp[0] != 0) return fail(PR_EINVAL, "row_ptr[0] != 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] < rp[i]) return fail(PR_EINVAL, "row_ptr is not non-decreasing");
+    if (rp[n] != m) return fail(PR_EINVAL, "row_ptr[n] != m");
+
+    // optional de-duplication (host): sort every row and drop repeats
+    std::vector<int64_t> drp;
+    std::vector<int32_t> dcol;
+    const int32_t *hcol = dev_in ? nullptr : col;
+    if (flags & PR_DEDUPE) {
+        std::vector<int32_t> tmp;
+        if (dev_in) {
+            tmp.resize((size_t)std::max<int64_t>(m, 1));
+            if (m) HIPCHK(hipMemcpy(tmp.data(), col, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+            hcol = tmp.data();
+        }
+        for (int64_t e = 0; e < m; ++e)
+            if (hcol[e] < 0 || hcol[e] >= n) return fail(PR_EINVAL, "col entry out of [0, n)");
+        drp.assign((size_t)n + 1, 0);
+        dcol.reserve((size_t)m);
+        for (int64_t i = 0; i < n; ++i) {
+            size_t b = dcol.size();
+            dcol.insert(dcol.end(), hcol + rp[i], hcol + rp[i + 1]);
+            std::sort(dcol.begin() + b, dcol.end());
+            dcol.erase(std::unique(dcol.begin() + b, dcol.end()), dcol.end());
+            drp[i + 1] = (int64_t)dcol.size();
+        }
+        m = (int64_t)dcol.size();
+        rp = drp.data();
+        hcol = dcol.data();
+    }
+    const bool col_on_device = dev_in && !(flags & PR_DEDUPE);
+    int device = 0;
+    HIPCHK(hipGetDevice(&device));
+
+    std::unique_ptr<pr_graph> hg(new (std::nothrow) pr_graph());
+    if (!hg) return fail(PR_ENOMEM, "host allocation");
+    Graph &G = hg->g;
+    G.n = n;
+    G.m = m;
+    G.device = device;
+    HIPCHK(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
+    hipStream_t s = G.stream;
+    struct StreamGuard {
+        Graph *g;
+        bool keep = false;
+        ~StreamGuard() {
+            if (!keep) {
+                for (void *p : g->allocs) (void)hipFree(p);
+                g->allocs.clear();
+                if (g->stream) (void)hipStreamDestroy(g->stream);
+            }
+        }
+    } guard{&G};
+
+    EventPair ev_all, ev_split;
+    HIPCHK(hipEventRecord(ev_all.a, s));
+
+    DevBufs tmp;
+    int64_t *d_rp64;
+    int32_t *d_col;
+    HIPCHK(tmp.alloc(&d_rp64, (size_t)n + 1));
+    HIPCHK(tmp.alloc(&d_col, (size_t)m));
+    HIPCHK(hipMemcpyAsync(d_rp64, rp, sizeof(int64_t) * (n + 1), hipMemcpyHostToDevice, s));
+    if (m) {
+        if (col_on_device) HIPCHK(hipMemcpyAsync(d_col, col, sizeof(int32_t) * m, hipMemcpyDeviceToDevice, s));
+        else HIPCHK(hipMemcpyAsync(d_col, hcol, sizeof(int32_t) * m, hipMemcpyHostToDevice, s));
+    }
+    // column range check before anything indexes with col
+    unsigned int *d_bad;
+    HIPCHK(tmp.alloc(&d_bad, 1));
+    HIPCHK(hipMemsetAsync(d_bad, 0, sizeof(unsigned int), s));
+    HIPCHK(launch_check_cols(d_col, m, n, d_bad, s));
+    unsigned int h_bad = 0;
+    HIPCHK(hipMemcpyAsync(&h_bad, d_bad, sizeof(unsigned int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (h_bad) return fail(PR_EINVAL, "col entry out of [0, n)");
+
+    auto galloc = [&](auto **p, size_t count) -> hipError_t {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
+        *p = nullptr;
+        size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc((void **)p, bytes);
+        if (e == hipSuccess) {
+            G.allocs.push_back((void *)*p);
+            G.device_bytes += (int64_t)bytes;
+        }
+        return e;
+    };
+
+    uint32_t *d_isN, *d_rank, *d_scan;
+    HIPCHK(tmp.alloc(&d_isN, (size_t)n));
+    HIPCHK(tmp.alloc(&d_rank, (size_t)n + 1));
+    HIPCHK(tmp.alloc(&d_scan, scan_tmp_elems(std::max<int64_t>(n, m) + 1)));
+    HIPCHK(launch_degree_class(d_rp64, n, d_isN, s));
+    HIPCHK(launch_scan_u32(d_isN, d_rank, n, d_scan, s));
+    uint32_t h_nN = 0;
+    HIPCHK(hipMemcpyAsync(&h_nN, d_rank + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    G.nN = (int32_t)h_nN;
+    G.nD = (int32_t)(n - h_nN);
+
+    HIPCHK(galloc(&G.perm, (size_t)n));
+    HIPCHK(galloc(&G.newid, (size_t)n));
+    HIPCHK(launch_relabel(d_isN, d_rank, n, G.nN, G.newid, G.perm, s));
+
+    uint32_t *d_indeg_old, *d_indeg, *d_cnn, *d_cnd, *d_cursor;
+    HIPCHK(tmp.alloc(&d_indeg_old, (size_t)n));
+    HIPCHK(tmp.alloc(&d_indeg, (size_t)n));
+    HIPCHK(hipMemsetAsync(d_indeg_old, 0, sizeof(uint32_t) * n, s));
+    HIPCHK(launch_indegree(d_col, m, d_indeg_old, s));
+
+    HIPCHK(tmp.alloc(&d_cnn, (size_t)G.nN + 1));
+    HIPCHK(tmp.alloc(&d_cnd, (size_t)G.nN + 1));
+    HIPCHK(galloc(&G.deg, (size_t)G.nN));
+    HIPCHK(galloc(&G.rp_nn, (size_t)G.nN + 1));
+    HIPCHK(galloc(&G.rp_nd, (size_t)G.nN + 1));
+    HIPCHK(hipEventRecord(ev_split.a, s));
+    HIPCHK(launch_count_nn(d_rp64, d_col, d_isN, G.perm, G.nN, d_cnn, d_cnd, G.deg, s));
+    HIPCHK(launch_scan_u32(d_cnn, G.rp_nn, G.nN, d_scan, s));
+    HIPCHK(launch_scan_u32(d_cnd, G.rp_nd, G.nN, d_scan, s));
+    uint32_t h_mm[2] = {0, 0};
+    HIPCHK(hipMemcpyAsync(&h_mm[0], G.rp_nn + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&h_mm[1], G.rp_nd + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    G.mNN = h_mm[0];
+    G.mND = h_mm[1];
+    if (G.mNN + G.mND != m) return fail(PR_EDEVICE, "internal: split edge count mismatch");
+    HIPCHK(galloc(&G.col_nn, (size_t)G.mNN));
+    HIPCHK(galloc(&G.col_nd, (size_t)G.mND));
+    HIPCHK(launch_split_rows(d_rp64, d_col, d_isN, G.newid, G.perm, G.nN, G.rp_nn, G.col_nn, G.rp_nd, G.col_nd, s));
+    HIPCHK(hipEventRecord(ev_split.b, s));
+
+    // in-edge lists (N targets first, then D targets)
+    HIPCHK(launch_permute_u32(d_indeg_old, G.perm, n, d_indeg, s));
+    HIPCHK(galloc(&G.in_ptr, (size_t)n + 1));
+    HIPCHK(galloc(&G.in_src, (size_t)m));
+    HIPCHK(launch_scan_u32(d_indeg, G.in_ptr, n, d_scan, s));
+    HIPCHK(tmp.alloc(&d_cursor, (size_t)n));
+    HIPCHK(hipMemcpyAsync(d_cursor, G.in_ptr, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_fill_csc(G.rp_nn, G.col_nn, G.nN, d_cursor, G.in_src, s));
+    HIPCHK(launch_fill_csc(G.rp_nd, G.col_nd, G.nN, d_cursor, G.in_src, s));
+    unsigned long long *d_zero;
+    HIPCHK(tmp.alloc(&d_zero, 1));
+    HIPCHK(hipMemsetAsync(d_zero, 0, sizeof(unsigned long long), s));
+    HIPCHK(launch_count_zero(d_indeg, n, d_zero, s));
+
+    // merge-path plans
+    auto make_plan = [&](MPPlan &p, const uint32_t *rpp, const int32_t *idx, int32_t R, int64_t edges) -> hipError_t {
+        p.rp = rpp;
+        p.idx = idx;
+        p.R = R;
+        p.items = (uint32_t)(R + edges);
+        int32_t blocks = (int32_t)(((int64_t)p.items + kIPB - 1) / kIPB);
+        hipError_t e = galloc(&p.plan, (size_t)blocks + 1);
+        if (e != hipSuccess) return e;
+        if (R == 0) {
+            p.blocks = 0;
+            return hipSuccess;
+        }
+        return launch_plan(p, s);
+    };
+    HIPCHK(make_plan(G.push_nn, G.rp_nn, G.col_nn, G.nN, G.mNN));
+    HIPCHK(make_plan(G.push_nd, G.rp_nd, G.col_nd, G.nN, G.mND));
+    HIPCHK(make_plan(G.pull_all, G.in_ptr, G.in_src, (int32_t)n, m));
+    HIPCHK(make_plan(G.pull_nn, G.in_ptr, G.in_src, G.nN, G.mNN));
+    HIPCHK(make_plan(G.pull_nd, G.in_ptr + G.nN, G.in_src, G.nD, G.mND));
+
+    unsigned long long h_zero = 0;
+    HIPCHK(hipMemcpyAsync(&h_zero, d_zero, sizeof(h_zero), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipEventRecord(ev_all.b, s));
+    HIPCHK(hipStreamSynchronize(s));
+    G.n_unref = (int64_t)h_zero;
+    G.seconds_upload = elapsed_s(ev_all.a, ev_all.b);
+    G.seconds_split = elapsed_s(ev_split.a, ev_split.b);
+    guard.keep = true;
+    *out = hg.release();
+    return PR_OK;
+}
+
+// ---------------------------------------------------------------------------
+// options / inputs
+// ---------------------------------------------------------------------------
+pr_status check_opts(const pr_opts &o, bool power) {
+    if (!(o.c > 0.0 && o.c < 1.0)) return fail(PR_EINVAL, "c must be in (0, 1)");
+    if (o.stop != PR_STOP_XI && o.stop != PR_STOP_L1) return fail(PR_EINVAL, "unknown stop rule");
+    if (o.residual != PR_RES_FP64 && o.residual != PR_RES_FP32) return fail(PR_EINVAL, "unknown residual type");
+    if (o.max_sweeps < 0) return fail(PR_EINVAL, "max_sweeps < 0");
+    const uint32_t known = PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE;
+    if (o.flags & ~known) return fail(PR_EINVAL, "unknown option flag");
+    if ((o.flags & PR_FORCE_PUSH) && (o.flags & PR_FORCE_PULL))
+        return fail(PR_EINVAL, "PR_FORCE_PUSH and PR_FORCE_PULL together");
+    if (power || o.stop == PR_STOP_L1) {
+        if (!(o.l1_tol > 0.0) || !isfinite(o.l1_tol)) return fail(PR_EINVAL, "l1_tol must be > 0 and finite");
+    }
+    if (!power && o.stop == PR_STOP_XI) {
+        if (!(o.xi > 0.0) || !isfinite(o.xi)) return fail(PR_EINVAL, "xi must be > 0 and finite");
+    }
+    return PR_OK;
+}
+
+// Solve workspace: one contiguous device allocation (cached on the graph) plus
+// a pinned host copy of the control block.
+struct Workspace {
+    Graph *g = nullptr;
+    char *base = nullptr;
+    size_t bytes = 0;
+    bool cached = false;
+    Ctl *hctl = nullptr;  // pinned
+    ~Workspace() {
+        if (hctl) (void)hipHostFree(hctl);
+        if (!base) return;
+        if (cached) {
+            std::lock_guard<std::mutex> lk(g->ws_mu);
+            g->ws_busy = false;
+        } else {
+            (void)hipFree(base);
+        }
+    }
+};
+
+pr_status acquire_ws(Graph &G, size_t bytes, Workspace &ws) {
+    ws.g = &G;
+    ws.bytes = bytes;
+    {
+        std::lock_guard<std::mutex> lk(G.ws_mu);
+        if (!G.ws_busy) {
+            if (G.ws_bytes < bytes) {
+                if (G.ws_mem) (void)hipFree(G.ws_mem);
+                G.ws_mem = nullptr;
+                G.ws_bytes = 0;
+                hipError_t e = hipMalloc(&G.ws_mem, bytes);
+                if (e != hipSuccess) return hip_fail(e, "workspace");
+                G.ws_bytes = bytes;
+            }
+            G.ws_busy = true;
+            ws.base = (char *)G.ws_mem;
+            ws.cached = true;
+        }
+    }
+    if (!ws.base) {
+        hipError_t e = hipMalloc((void **)&ws.base, bytes);
+        if (e != hipSuccess) return hip_fail(e, "workspace");
+    }
+    hipError_t e = hipHostMalloc((void **)&ws.hctl, sizeof(Ctl), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "pinned control block");
+    return PR_OK;
+}
+
+struct Carve {
+    char *base;
+    size_t off = 0;
+    template <typename T>
+    T *take(size_t count) {
+        T *p = (T *)(base + off);
+        off += align_up(std::max<size_t>(count, 1) * sizeof(T), 256);
+        return p;
+    }
+};
+
+template <typename T>
+size_t carve_size(size_t count) {
+    return align_up(std::max<size_t>(count, 1) * sizeof(T), 256);
+}
+
+// Validate p (host or device) and place it on the device; returns 1/sum(p).
+pr_status prepare_p(const Graph &G, const double *p, const pr_opts &o, double *pdev, double *sumbad,
+                    const double **p_used, double *pscale, hipStream_t s) {
+    *p_used = nullptr;
+    *pscale = 1.0;
+    if (!p) return PR_OK;
+    double sum = 0.0;
+    if (o.flags & PR_P_DEVICE) {
+        HIPCHK(hipMemsetAsync(sumbad, 0, 2 * sizeof(double), s));
+        HIPCHK(launch_validate_p(p, G.n, sumbad, s));
+        double h[2];
+        HIPCHK(hipMemcpyAsync(h, sumbad, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h[1] != 0.0) return fail(PR_EINVAL, "p has a negative or non-finite entry");
+        sum = h[0];
+        *p_used = p;
+    } else {
+        for (int64_t i = 0; i < G.n; ++i) {
+            if (!(p[i] >= 0.0) || !isfinite(p[i])) return fail(PR_EINVAL, "p has a negative or non-finite entry");
+            sum += p[i];
+        }
+        HIPCHK(hipMemcpyAsync(pdev, p, sizeof(double) * G.n, hipMemcpyHostToDevice, s));
+        *p_used = pdev;
+    }
+    if (!(sum > 0.0) || !isfinite(sum)) return fail(PR_EINVAL, "sum(p) must be > 0");
+    *pscale = 1.0 / sum;
+    return PR_OK;
+}
+
+// Sweep batches: the kernels of sweeps past the stop decision return at once,
+// so the host enqueues a batch, reads the control block, and sizes the next
+// batch from the observed decay of the certified bound.
+int next_batch(int prev_batch, double bound_prev, double bound_now, int swept, double tol, bool l1) {
+    if (l1 && bound_prev > 0 && bound_now > 0 && bound_now < bound_prev && swept > 0) {
+        double rate = pow(bound_now / bound_prev, 1.0 / swept);
+        if (rate > 0 && rate < 1) {
+            double need = log(tol / bound_now) / log(rate);
+            int k = (int)ceil(need) + 1;
+            return std::min(64, std::max(2, k));
+        }
+    }
+    return std::min(64, prev_batch * 2);
+}
+
+struct SweepTimer {
+    bool on = false;
+    std::vector<std::unique_ptr<EventPair>> ev;  // per launch
+    std::vector<int> sweep_of;                   // sweep index of each launch
+    std::vector<int> is_pull;                    // 1 = gather kernel, 0 = scatter kernel
+    hipEvent_t begin(hipStream_t s, int t, int pull) {
+        if (!on) return nullptr;
+        ev.emplace_back(new EventPair());
+        sweep_of.push_back(t);
+        is_pull.push_back(pull);
+        (void)hipEventRecord(ev.back()->a, s);
+        return ev.back()->b;
+    }
+    void end(hipEvent_t b, hipStream_t s) {
+        if (b) (void)hipEventRecord(b, s);
+    }
+};
+
+template <typename T>
+pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
+                      pr_stats *st) {
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
+    const int64_t n = G.n;
+    const int32_t nN = G.nN, nD = G.nD;
+    const bool literal = ifp2 && (o.flags & PR_IFP2_LITERAL);
+    const bool out_dev = o.flags & PR_OUT_DEVICE;
+    const double c = o.c;
+    const bool l1 = o.stop == PR_STOP_L1;
+    // threshold: under the L1 rule, the xi at which an empty frontier already
+    // certifies the bound (residual on N <= nN * xi, total mass >= n)
+    double xi = o.xi;
+    if (l1) {
+        xi = o.l1_tol * (1.0 - c) / (2.0 * c) * (double)n / (double)std::max<int32_t>(nN, 1);
+        xi *= 1.0 - 1e-9;
+    }
+    const double tol = l1 ? o.l1_tol * (1.0 - 1e-6) : 0.0;
+    const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
+
+    size_t bytes = carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
+                   carve_size<double>(nN) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
+                   carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
+                   carve_size<double>(2);
+    Workspace ws;
+    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
+    if (ps != PR_OK) return ps;
+    Carve cv{ws.base};
+    T *h = cv.take<T>(n);
+    T *w = cv.take<T>(nN);
+    double *pibar = cv.take<double>(nN);
+    double *xD = cv.take<double>(nD);
+    double *w2 = cv.take<double>(nN);
+    double *outbuf = cv.take<double>(out_dev ? 0 : n);
+    Ctl *ctl = cv.take<Ctl>(1);
+    Trace *tr = cv.take<Trace>(1);
+    double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
+    double *sumbad = cv.take<double>(2);
+
+    InitArgs a{};
+    a.n = n;
+    a.nN = nN;
+    a.perm = G.perm;
+    a.source = source;
+    a.uniform = (p == nullptr && source < 0);
+    ps = prepare_p(G, p, o, pdev, sumbad, &a.p, &a.pscale, s);
+    if (ps != PR_OK) return ps;
+
+    EventPair ev_solve;
+    SweepTimer timer;
+    timer.on = o.flags & PR_PROFILE;
+    HIPCHK(hipEventRecord(ev_solve.a, s));
+    Ctl hc;
+    memset(&hc, 0, sizeof(hc));
+    hc.stop_after = INT_MAX;
+    hc.sx = (double)n;
+    HIPCHK(hipMemcpyAsync(ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_init_ifp<T>(a, h, pibar, s));
+
+    const MPPlan &pullp = ifp2 ? G.pull_nn : G.pull_all;
+    const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
+    // a pull sweep reads every in-edge; push when the active edges are fewer than this share
+    const unsigned long long pull_edges = (unsigned long long)pullp.edges();
+    const unsigned long long pull_thr = (unsigned long long)(0.5 * (double)pull_edges) + 1;
+    const int check_mode = force == 0;
+    int t = 0;
+    bool stopped = false;
+    if (nN > 0) {
+        int batch = l1 ? 8 : 16;
+        double bound_prev = -1.0;
+        int t_prev = 0;
+        while (t < max_sweeps) {
+            int nb = std::min(batch, max_sweeps - t);
+            for (int k = 0; k < nb; ++k, ++t) {
+                HIPCHK(launch_reserve<T>(t, ctl, tr, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, l1 ? 1 : 0,
+                                         tol, pull_thr, force, pull_edges, s));
+                if (force != 2) {
+                    hipEvent_t e = timer.begin(s, t, 0);
+                    HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, check_mode, s));
+                    if (!ifp2) HIPCHK(launch_push<T>(t, ctl, G.push_nd, w, h, check_mode, s));
+                    timer.end(e, s);
+                }
+                if (force != 1) {
+                    hipEvent_t e = timer.begin(s, t, 1);
+                    HIPCHK(launch_pull<T, T>(t, ctl, pullp, w, h, check_mode, s));
+                    timer.end(e, s);
+                }
+            }
+            HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (ws.hctl->stop_after < t) {
+                stopped = true;
+                break;
+            }
+            batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, l1);
+            bound_prev = ws.hctl->last_bound;
+            t_prev = t;
+        }
+    } else {
+        stopped = true;
+    }
+    if (ifp2 && nD > 0) {
+        HIPCHK(launch_phase2_prep<T>(a, h, pibar, G.deg, c, literal ? 1 : 0, w2, xD, s));
+        HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
+    }
+    double *dst = out_dev ? pi : outbuf;
+    HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, dst, s));
+    HIPCHK(hipEventRecord(ev_solve.b, s));
+    HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Ctl &r = *ws.hctl;
+    if (st) {
+        pr_stats z;
+        memset(&z, 0, sizeof(z));
+        z.sweeps = r.sweeps;
+        z.pull_sweeps = r.pull_sweeps;
+        z.edges_processed = (int64_t)r.tot_edges + (ifp2 ? G.mND : 0);
+        z.edges_traversed = (int64_t)r.tot_traversed + (ifp2 ? G.mND : 0);
+        z.vertex_pushes = (int64_t)r.tot_pushes;
+        z.residual_l1 = r.fin_sum > 0 ? r.fin_sn / r.fin_sum : 0.0;
+        const double k = literal ? 2.0 / (1.0 - c) : 2.0 * c / (1.0 - c);
+        z.l1_bound = r.fin_sum > 0 ? k * r.fin_sn / r.fin_sum : 0.0;
+        z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
+        z.seconds_preprocess = ifp2 ? G.seconds_split : 0.0;
+        if (timer.on) {
+            std::vector<unsigned long long> trc((size_t)std::min(r.sweeps + 1, kMaxTrace));
+            std::vector<unsigned long long> tre(trc.size());
+            if (!trc.empty()) {
+                HIPCHK(hipMemcpy(trc.data(), tr->cnt, sizeof(unsigned long long) * trc.size(), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(tre.data(), tr->edges, sizeof(unsigned long long) * tre.size(), hipMemcpyDeviceToHost));
+            }
+            const double sT = (double)sizeof(T);
+            for (size_t i = 0; i < timer.ev.size(); ++i) {
+                int ts = timer.sweep_of[i];
+                if (ts >= r.sweeps || ts >= (int)trc.size()) continue;
+                bool pulled = (trc[ts] >> 63) != 0;
+                if ((int)pulled != timer.is_pull[i]) continue;
+                double sec = elapsed_s(timer.ev[i]->a, timer.ev[i]->b);
+                if (pulled) {
+                    // every in-edge: source id + gathered weight; every target row: offset + residual update
+                    z.pull_seconds += sec;
+                    z.pull_launches += 1;
+                    z.pull_bytes += (double)pullp.edges() * (4.0 + sT) + (double)pullp.R * (4.0 + 2.0 * sT);
+                } else {
+                    // every pushed edge: target id + residual read-modify-write; every row: offset + weight
+                    int rows = ifp2 ? nN : 2 * nN;
+                    z.push_seconds += sec;
+                    z.push_launches += ifp2 ? 1 : 2;
+                    z.push_bytes += (double)tre[ts] * (4.0 + 2.0 * sT) + (double)rows * (4.0 + sT);
+                }
+            }
+        }
+        *st = z;
+    }
+    return stopped ? PR_OK : PR_ENOCONV;
+}
+
+template <typename WT>
+pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, double *pi, pr_stats *st) {
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
+    const int64_t n = G.n;
+    const int32_t nN = G.nN;
+    const bool out_dev = o.flags & PR_OUT_DEVICE;
+    const double c = o.c;
+    const double tol = o.l1_tol * (1.0 - 1e-6);
+    const int max_it = o.max_sweeps > 0 ? o.max_sweeps : 100000;
+    size_t bytes = carve_size<double>(n) * 2 + carve_size<WT>(nN) + carve_size<double>(out_dev ? 0 : n) +
+                   carve_size<Ctl>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
+                   carve_size<double>(2);
+    Workspace ws;
+    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
+    if (ps != PR_OK) return ps;
+    Carve cv{ws.base};
+    double *x = cv.take<double>(n);
+    double *acc = cv.take<double>(n);
+    WT *y = cv.take<WT>(nN);
+    double *outbuf = cv.take<double>(out_dev ? 0 : n);
+    Ctl *ctl = cv.take<Ctl>(1);
+    double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
+    double *sumbad = cv.take<double>(2);
+    InitArgs a{};
+    a.n = n;
+    a.nN = nN;
+    a.perm = G.perm;
+    a.source = -1;
+    a.uniform = p == nullptr;
+    ps = prepare_p(G, p, o, pdev, sumbad, &a.p, &a.pscale, s);
+    if (ps != PR_OK) return ps;
+
+    EventPair ev_solve;
+    SweepTimer timer;
+    timer.on = o.flags & PR_PROFILE;
+    HIPCHK(hipEventRecord(ev_solve.a, s));
+    Ctl hc;
+    memset(&hc, 0, sizeof(hc));
+    hc.stop_after = INT_MAX;
+    HIPCHK(hipMemcpyAsync(ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_power_init(a, x, acc, s));
+    int t = 0;
+    bool stopped = false;
+    int batch = 8;
+    double bound_prev = -1.0;
+    int t_prev = 0;
+    while (t <= max_it) {
+        int nb = std::min(batch, max_it + 1 - t);
+        for (int k = 0; k < nb; ++k, ++t) {
+            HIPCHK(launch_power_prescale<WT>(t, ctl, a, x, acc, y, G.deg, c, tol, s));
+            if (t < max_it) {
+                hipEvent_t e = timer.begin(s, t, 1);
+                HIPCHK(launch_pull<WT, double>(t, ctl, G.pull_all, y, acc, 0, s));
+                timer.end(e, s);
+            }
+        }
+        HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (ws.hctl->stop_after < t) {
+            stopped = true;
+            break;
+        }
+        batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, true);
+        bound_prev = ws.hctl->last_bound;
+        t_prev = t;
+    }
+    double *dst = out_dev ? pi : outbuf;
+    HIPCHK(launch_final_x(ctl, a, x, dst, s));
+    HIPCHK(hipEventRecord(ev_solve.b, s));
+    HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Ctl &r = *ws.hctl;
+    if (st) {
+        pr_stats z;
+        memset(&z, 0, sizeof(z));
+        z.sweeps = r.sweeps;
+        z.pull_sweeps = r.sweeps;
+        z.edges_processed = (int64_t)r.sweeps * G.m;
+        z.edges_traversed = z.edges_processed;
+        z.vertex_pushes = (int64_t)r.sweeps * nN;
+        z.residual_l1 = r.pw_diff;
+        z.l1_bound = c / (1.0 - c) * r.pw_diff + fabs(1.0 - r.fin_sum);
+        z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
+        if (timer.on) {
+            const double sW = (double)sizeof(WT);
+            for (size_t i = 0; i < timer.ev.size(); ++i) {
+                if (timer.sweep_of[i] >= r.sweeps) continue;
+                z.pull_seconds += elapsed_s(timer.ev[i]->a, timer.ev[i]->b);
+                z.pull_launches += 1;
+                z.pull_bytes += (double)G.m * (4.0 + sW) + (double)n * (4.0 + 16.0);
+            }
+        }
+        *st = z;
+    }
+    return stopped ? PR_OK : PR_ENOCONV;
+}
+
+pr_status opts_or_default(const pr_opts *o, pr_opts *out) {
+    if (o) *out = *o;
+    else pr_opts_default(out);
+    return PR_OK;
+}
+
+pr_status enter(const pr_graph *g) {
+    if (!g) return fail(PR_EINVAL, "graph is NULL");
+    HIPCHK(hipSetDevice(g->g.device));
+    return PR_OK;
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+void pr_opts_default(pr_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->c = 0.85;
+    o->xi = 1e-12;
+    o->l1_tol = 1e-6;
+    o->stop = PR_STOP_XI;
+    o->residual = PR_RES_FP64;
+}
+
+const char *pr_last_error(void) { return g_err.c_str(); }
+
+pr_status pr_graph_upload(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
+                          pr_graph **out) {
+    g_err.clear();
+    try {
+        return upload_impl(n, m, row_ptr, col, flags, out);
+    } catch (const std::bad_alloc &) {
+        return fail(PR_ENOMEM, "host allocation");
+    }
+}
+
+pr_status pr_graph_free(pr_graph *g) {
+    g_err.clear();
+    if (!g) return PR_OK;
+    (void)hipSetDevice(g->g.device);
+    if (g->g.stream) (void)hipStreamSynchronize(g->g.stream);
+    for (void *p : g->g.allocs) (void)hipFree(p);
+    if (g->g.ws_mem) (void)hipFree(g->g.ws_mem);
+    if (g->g.stream) (void)hipStreamDestroy(g->g.stream);
+    delete g;
+    return PR_OK;
+}
+
+pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out) {
+    g_err.clear();
+    if (!g || !out) return fail(PR_EINVAL, "NULL argument");
+    const Graph &G = g->g;
+    out->n = G.n;
+    out->m = G.m;
+    out->n_dangling = G.nD;
+    out->m_dangling = G.mND;
+    out->n_unreferenced = G.n_unref;
+    out->device_bytes = G.device_bytes;
+    out->seconds_upload = G.seconds_upload;
+    out->seconds_split = G.seconds_split;
+    return PR_OK;
+}
+
+static pr_status solve_common(const pr_graph *g, int method, const double *p, const pr_opts *o, double *pi,
+                              pr_stats *st) {
+    g_err.clear();
+    if (!g) return fail(PR_EINVAL, "graph is NULL");
+    if (!pi) return fail(PR_EINVAL, "pi is NULL");
+    pr_opts op;
+    opts_or_default(o, &op);
+    pr_status ps = check_opts(op, method == 3);
+    if (ps != PR_OK) return ps;
+    ps = enter(g);
+    if (ps != PR_OK) return ps;
+    try {
+        const Graph &G = g->g;
+        if (method == 3) {
+            return op.residual == PR_RES_FP32 ? solve_power_t<float>(G, p, op, pi, st)
+                                              : solve_power_t<double>(G, p, op, pi, st);
+        }
+        const bool ifp2 = method == 2;
+        return op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, ifp2, p, -1, op, pi, st)
+                                          : solve_ifp_t<double>(G, ifp2, p, -1, op, pi, st);
+    } catch (const std::bad_alloc &) {
+        return fail(PR_ENOMEM, "host allocation");
+    }
+}
+
+pr_status pr_solve_ifp1(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st) {
+    return solve_common(g, 1, p, o, pi, st);
+}
+
+pr_status pr_solve_ifp2(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st) {
+    return solve_common(g, 2, p, o, pi, st);
+}
+
+pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st) {
+    return solve_common(g, 3, p, o, pi, st);
+}
+
+pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_opts *o, double *pi,
+                 pr_stats *st) {
+    g_err.clear();
+    if (!g) return fail(PR_EINVAL, "graph is NULL");
+    if (!pi) return fail(PR_EINVAL, "pi is NULL");
+    if (!sources || k < 1) return fail(PR_EINVAL, "need k >= 1 sources");
+    const Graph &G = g->g;
+    for (int32_t r = 0; r < k; ++r)
+        if (sources[r] < 0 || sources[r] >= G.n) return fail(PR_EINVAL, "source out of [0, n)");
+    pr_opts op;
+    opts_or_default(o, &op);
+    if (op.flags & PR_P_DEVICE) return fail(PR_EINVAL, "pr_ppr takes no p vector");
+    pr_status ps = check_opts(op, false);
+    if (ps != PR_OK) return ps;
+    ps = enter(g);
+    if (ps != PR_OK) return ps;
+    pr_status worst = PR_OK;
+    try {
+        for (int32_t r = 0; r < k; ++r) {
+            double *row = pi + (size_t)r * (size_t)G.n;
+            pr_stats *sr = st ? st + r : nullptr;
+            pr_status rs = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, sources[r], op, row, sr)
+                                                      : solve_ifp_t<double>(G, true, nullptr, sources[r], op, row, sr);
+            if (rs < 0) return rs;
+            if (rs > worst) worst = rs;
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(PR_ENOMEM, "host allocation");
+    }
+    return worst;
+}
+
+}  // extern "C"

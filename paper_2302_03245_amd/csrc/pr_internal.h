@@ -1,0 +1,148 @@
+// pr_internal.h -- device data layout and kernel launchers shared by the HIP
+// translation units of libpr.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace prk {
+
+constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
+constexpr int kMaxTrace = 4096;   // per-sweep trace entries kept on the device
+constexpr int kMPK = 8;           // merge-path items (rows + edges) per thread
+constexpr int kIPB = kBlock * kMPK;  // merge-path items per workgroup
+
+// Merge-path work split over a CSR-like segment: rows r in [0, R) with edges
+// [rp[r], rp[r+1]).  The item sequence lists the edges of a row followed by an
+// end-of-row marker; item positions are diagonals of the merge of row ends
+// with edge indices.  plan[b] = (row, edge) at diagonal b * items_per_block.
+struct MPPlan {
+    const uint32_t *rp = nullptr;  // device, R + 1 absolute edge offsets
+    const int32_t *idx = nullptr;  // device, edge endpoint array (absolute offsets index it)
+    int32_t R = 0;
+    uint32_t items = 0;            // R + number of edges
+    int32_t blocks = 0;
+    int32_t ipb = 0;               // items per block
+    uint2 *plan = nullptr;         // device, blocks + 1 entries (owned by the graph)
+    int64_t edges() const { return (int64_t)items - R; }
+};
+
+// Control block of one solve (device memory).  Per-sweep accumulators are
+// filled with atomics by every workgroup and consumed and reset by the last one.
+struct alignas(128) Ctl {
+    int32_t stop_after;   // sweeps with index > stop_after do nothing
+    int32_t sweeps;       // sweeps that moved mass
+    int32_t use_pull;     // mode of the current sweep's scatter/gather
+    int32_t pull_sweeps;
+    uint32_t bdone;       // last-block counters
+    uint32_t fdone;
+    uint32_t pad0[2];
+    double acc[4];        // per-sweep FP64 accumulators
+    unsigned long long acc_cnt, acc_edges;
+    double sx;            // running total mass sum(pibar + h) (+ untouched dangling mass for IFP2)
+    double last_bound;    // bound certified at the last reserve
+    unsigned long long tot_pushes, tot_edges, tot_traversed;
+    // power method
+    double pw_b;          // jump weight c * d^T x + (1 - c) * e^T x of the current iterate
+    double pw_diff;       // ||x_t - x_{t-1}||_1 of the last iterate
+    // finalisation
+    double fin_sum, fin_sn;
+    double pad1[4];
+};
+
+struct Trace {
+    unsigned long long cnt[kMaxTrace];
+    unsigned long long edges[kMaxTrace];
+    double sn[kMaxTrace];
+    double bound[kMaxTrace];
+};
+
+// Device-resident graph: vertices relabelled so that the n_N non-dangling
+// vertices come first ([0, n_N), original order kept), dangling after.
+struct Graph {
+    int64_t n = 0, m = 0;
+    int32_t nN = 0, nD = 0;
+    int64_t mNN = 0, mND = 0, n_unref = 0;
+    int32_t *perm = nullptr;      // new id -> original id, [n]
+    int32_t *newid = nullptr;     // original id -> new id, [n]
+    int32_t *deg = nullptr;       // out-degree of non-dangling vertices, [nN]
+    uint32_t *rp_nn = nullptr;    // CSR of edges N -> N, [nN + 1]
+    int32_t *col_nn = nullptr;    // [mNN]
+    uint32_t *rp_nd = nullptr;    // CSR of edges N -> D, [nN + 1]
+    int32_t *col_nd = nullptr;    // [mND]
+    uint32_t *in_ptr = nullptr;   // in-edges of every target (N targets first), [n + 1]
+    int32_t *in_src = nullptr;    // [m]
+    MPPlan push_nn, push_nd, pull_all, pull_nn, pull_nd;
+    int64_t device_bytes = 0;
+    double seconds_upload = 0, seconds_split = 0;
+    hipStream_t stream = nullptr;
+    int device = 0;
+    std::vector<void *> allocs;
+    // cached solve workspace
+    std::mutex ws_mu;
+    bool ws_busy = false;
+    void *ws_mem = nullptr;
+    size_t ws_bytes = 0;
+};
+
+// ---- kernel launchers (pr_kernels.hip) ----
+hipError_t launch_check_cols(const int32_t *col, int64_t m, int64_t n, unsigned int *bad, hipStream_t s);
+hipError_t launch_degree_class(const int64_t *rp64, int64_t n, uint32_t *isN, hipStream_t s);
+hipError_t launch_indegree(const int32_t *col, int64_t m, uint32_t *indeg, hipStream_t s);
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+size_t scan_tmp_elems(int64_t n);
+hipError_t launch_relabel(const uint32_t *isN, const uint32_t *rankN, int64_t n, int32_t nN, int32_t *newid,
+                          int32_t *perm, hipStream_t s);
+hipError_t launch_count_nn(const int64_t *rp64, const int32_t *col, const uint32_t *isN, const int32_t *perm,
+                           int32_t nN, uint32_t *cnt_nn, uint32_t *cnt_nd, int32_t *deg, hipStream_t s);
+hipError_t launch_split_rows(const int64_t *rp64, const int32_t *col, const uint32_t *isN, const int32_t *newid,
+                             const int32_t *perm, int32_t nN, const uint32_t *rp_nn, int32_t *col_nn,
+                             const uint32_t *rp_nd, int32_t *col_nd, hipStream_t s);
+hipError_t launch_permute_u32(const uint32_t *in_old, const int32_t *perm, int64_t n, uint32_t *out_new,
+                              hipStream_t s);
+hipError_t launch_fill_csc(const uint32_t *rp, const int32_t *col, int32_t R, uint32_t *cursor, int32_t *in_src,
+                           hipStream_t s);
+hipError_t launch_count_zero(const uint32_t *a, int64_t n, unsigned long long *out, hipStream_t s);
+hipError_t launch_plan(MPPlan &p, hipStream_t s);
+
+// solve kernels
+struct InitArgs {
+    int64_t n;
+    int32_t nN;
+    int uniform;            // p == NULL
+    const double *p;        // original order (device) when !uniform
+    double pscale;          // 1 / sum(p)
+    const int32_t *perm;
+    int32_t source;         // >= 0: single-source PPR (original id): p = e_source
+};
+template <typename T>
+hipError_t launch_init_ifp(const InitArgs &a, T *h, double *pibar, hipStream_t s);
+template <typename T>
+hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
+                          const uint32_t *rp_nn, double c, double xi, int ifp2, int stop_l1, double tol,
+                          unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
+                          hipStream_t s);
+template <typename T>
+hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s);
+template <typename WT, typename OT>
+hipError_t launch_pull(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
+                       hipStream_t s);
+template <typename T>
+hipError_t launch_phase2_prep(const InitArgs &a, const T *h, const double *pibar, const int32_t *deg, double c,
+                              int literal, double *w2, double *xD, hipStream_t s);
+template <typename T>
+hipError_t launch_final_ifp(Ctl *ctl, const InitArgs &a, const T *h, const double *pibar, const double *xD,
+                            int ifp2, int literal, double *out, hipStream_t s);
+// power method
+template <typename WT>
+hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, double *acc, WT *y,
+                                 const int32_t *deg, double c, double tol, hipStream_t s);
+hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStream_t s);
+hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, hipStream_t s);
+hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s);
+
+}  // namespace prk

@@ -1,0 +1,817 @@
+// pr_kernels.hip -- gfx950 kernels of libpr.so.
+//
+// The path is sparse and memory bound (one multiply-add and one scattered add
+// per edge), so nothing here uses the matrix cores.  Work is organised for
+// 64-wide waves: wave ballots for compaction and row splitting, LDS-staged
+// merge-path tiles for edge streaming, FP64 block reductions finished by the
+// last workgroup of a launch.
+#include "pr_internal.h"
+
+#include <limits.h>
+
+namespace prk {
+
+namespace {
+
+constexpr int W = 64;  // wavefront size on CDNA
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (W - 1); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v) {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, W);
+    return v;
+}
+
+// inclusive scan across one wave
+__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t v) {
+    const int l = lane_id();
+#pragma unroll
+    for (int o = 1; o < W; o <<= 1) {
+        uint32_t u = __shfl_up(v, o, W);
+        if (l >= o) v += u;
+    }
+    return v;
+}
+
+// block-wide sum, result valid in thread 0; sbuf holds kBlock / W entries
+template <typename T>
+__device__ __forceinline__ T block_sum(T v, T *sbuf) {
+    v = wave_sum(v);
+    __syncthreads();
+    if (lane_id() == 0) sbuf[threadIdx.x / W] = v;
+    __syncthreads();
+    T r = 0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < kBlock / W; ++k) r += sbuf[k];
+    }
+    return r;
+}
+
+__device__ __forceinline__ void atomic_add_f64(double *p, double v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void atomic_add_u64(unsigned long long *p, unsigned long long v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ T load_agent(const T *p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+template <typename T>
+__device__ __forceinline__ void store_agent(T *p, T v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Signal completion of this workgroup; returns true in thread 0 of the last one.
+__device__ __forceinline__ bool last_block(uint32_t *counter) {
+    __shared__ int s_last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (prev == gridDim.x - 1);
+        if (s_last) __threadfence();
+    }
+    __syncthreads();
+    return s_last && threadIdx.x == 0;
+}
+
+inline int grid_for(int64_t work, int per_thread, int cap) {
+    int64_t b = (work + (int64_t)kBlock * per_thread - 1) / ((int64_t)kBlock * per_thread);
+    if (b < 1) b = 1;
+    if (b > cap) b = cap;
+    return (int)b;
+}
+
+// ------------------------------------------------------------------------
+// graph preparation
+// ------------------------------------------------------------------------
+__global__ void k_check_cols(const int32_t *col, int64_t m, int64_t n, unsigned int *bad) {
+    unsigned int b = 0;
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock) {
+        int32_t c = col[e];
+        b |= (c < 0 || (int64_t)c >= n);
+    }
+    if (__any(b) && lane_id() == 0) atomicOr(bad, 1u);
+}
+
+__global__ void k_degree_class(const int64_t *rp, int64_t n, uint32_t *isN) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        isN[i] = rp[i + 1] > rp[i] ? 1u : 0u;
+}
+
+__global__ void k_indegree(const int32_t *col, int64_t m, uint32_t *indeg) {
+    for (int64_t e = blockIdx.x * (int64_t)kBlock + threadIdx.x; e < m; e += (int64_t)gridDim.x * kBlock)
+        atomicAdd(indeg + col[e], 1u);
+}
+
+// exclusive scan, 16 elements per thread, 4096 per block
+constexpr int kScanPer = 16;
+constexpr int kScanTile = kBlock * kScanPer;
+
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t *total) {
+    __shared__ uint32_t s_w[kBlock / W];
+    uint32_t inc = wave_incl_scan(v);
+    if (lane_id() == W - 1) s_w[threadIdx.x / W] = inc;
+    __syncthreads();
+    uint32_t off = 0, tot = 0;
+#pragma unroll
+    for (int k = 0; k < kBlock / W; ++k) {
+        uint32_t s = s_w[k];
+        if (k < (int)(threadIdx.x / W)) off += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return off + inc - v;
+}
+
+__global__ void k_scan_partial(const uint32_t *in, int64_t n, uint32_t *partial) {
+    int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * (int64_t)kScanPer;
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k)
+        if (base + k < n) s += in[base + k];
+    __shared__ uint32_t sb[kBlock / W];
+    uint32_t tot = block_sum(s, sb);
+    if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ void k_scan_top(uint32_t *partial, int64_t nb) {
+    uint32_t carry = 0;
+    for (int64_t base = 0; base < nb; base += kBlock) {
+        int64_t i = base + threadIdx.x;
+        uint32_t v = i < nb ? partial[i] : 0u;
+        uint32_t tot;
+        uint32_t ex = block_excl_scan(v, &tot);
+        if (i < nb) partial[i] = carry + ex;
+        carry += tot;
+    }
+}
+
+__global__ void k_scan_final(const uint32_t *in, uint32_t *out, int64_t n, const uint32_t *partial) {
+    int64_t base = blockIdx.x * (int64_t)kScanTile + threadIdx.x * (int64_t)kScanPer;
+    uint32_t vals[kScanPer];
+    uint32_t s = 0;
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        vals[k] = base + k < n ? in[base + k] : 0u;
+        s += vals[k];
+    }
+    uint32_t tot;
+    uint32_t run = partial[blockIdx.x] + block_excl_scan(s, &tot);
+#pragma unroll
+    for (int k = 0; k < kScanPer; ++k) {
+        if (base + k < n) out[base + k] = run;
+        run += vals[k];
+    }
+    if (base <= n - 1 && n - 1 < base + kScanPer) out[n] = run;  // the thread holding the last element
+}
+
+__global__ void k_relabel(const uint32_t *isN, const uint32_t *rankN, int64_t n, int32_t nN, int32_t *newid,
+                          int32_t *perm) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        uint32_t r = rankN[i];
+        int32_t id = isN[i] ? (int32_t)r : (int32_t)(nN + (i - (int64_t)r));
+        newid[i] = id;
+        perm[id] = (int32_t)i;
+    }
+}
+
+// one wave per non-dangling row: number of targets that are non-dangling
+__global__ void k_count_nn(const int64_t *rp, const int32_t *col, const uint32_t *isN, const int32_t *perm,
+                           int32_t nN, uint32_t *cnt_nn, uint32_t *cnt_nd, int32_t *deg) {
+    const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
+    for (int64_t k = wave; k < nN; k += nwaves) {
+        int32_t i = perm[k];
+        int64_t lo = rp[i], hi = rp[i + 1];
+        uint32_t c = 0;
+        for (int64_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
+            bool t = e < hi && isN[col[e]];
+            c += (uint32_t)__popcll(__ballot(t));
+        }
+        if (lane_id() == 0) {
+            cnt_nn[k] = c;
+            cnt_nd[k] = (uint32_t)(hi - lo) - c;
+            deg[k] = (int32_t)(hi - lo);
+        }
+    }
+}
+
+// one wave per non-dangling row: stable split of the row into N targets and D targets (new ids)
+__global__ void k_split_rows(const int64_t *rp, const int32_t *col, const uint32_t *isN, const int32_t *newid,
+                             const int32_t *perm, int32_t nN, const uint32_t *rp_nn, int32_t *col_nn,
+                             const uint32_t *rp_nd, int32_t *col_nd) {
+    const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
+    const unsigned long long lt = (1ull << lane_id()) - 1ull;
+    for (int64_t k = wave; k < nN; k += nwaves) {
+        int32_t i = perm[k];
+        int64_t lo = rp[i], hi = rp[i + 1];
+        uint32_t on = rp_nn[k], od = rp_nd[k];
+        for (int64_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
+            bool valid = e < hi;
+            int32_t t = valid ? col[e] : 0;
+            bool tn = valid && isN[t];
+            unsigned long long mn = __ballot(tn), md = __ballot(valid && !tn);
+            if (tn) col_nn[on + __popcll(mn & lt)] = newid[t];
+            else if (valid) col_nd[od + __popcll(md & lt)] = newid[t];
+            on += (uint32_t)__popcll(mn);
+            od += (uint32_t)__popcll(md);
+        }
+    }
+}
+
+__global__ void k_permute_u32(const uint32_t *in_old, const int32_t *perm, int64_t n, uint32_t *out_new) {
+    for (int64_t k = blockIdx.x * (int64_t)kBlock + threadIdx.x; k < n; k += (int64_t)gridDim.x * kBlock)
+        out_new[k] = in_old[perm[k]];
+}
+
+// one wave per source row: append the source to each target's in-list
+__global__ void k_fill_csc(const uint32_t *rp, const int32_t *col, int32_t R, uint32_t *cursor, int32_t *in_src) {
+    const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
+    for (int64_t k = wave; k < R; k += nwaves) {
+        uint32_t lo = rp[k], hi = rp[k + 1];
+        for (uint32_t e = lo + lane_id(); e < hi; e += W) {
+            uint32_t pos = atomicAdd(cursor + col[e], 1u);
+            in_src[pos] = (int32_t)k;
+        }
+    }
+}
+
+__global__ void k_count_zero(const uint32_t *a, int64_t n, unsigned long long *out) {
+    unsigned long long c = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        c += a[i] == 0u;
+    __shared__ unsigned long long sb[kBlock / W];
+    c = block_sum(c, sb);
+    if (threadIdx.x == 0 && c) atomic_add_u64(out, c);
+}
+
+// merge-path split points: plan[b] = (rows finished before diagonal d, edge at d)
+__global__ void k_plan(const uint32_t *rp, int32_t R, uint32_t items, int32_t ipb, int32_t blocks, uint2 *plan) {
+    const uint32_t rp0 = rp[0];
+    for (int64_t b = blockIdx.x * (int64_t)kBlock + threadIdx.x; b <= blocks; b += (int64_t)gridDim.x * kBlock) {
+        uint64_t dd = (uint64_t)b * (uint64_t)ipb;
+        uint32_t d = dd < items ? (uint32_t)dd : items;
+        int32_t lo = 0, hi = R;
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (rp[mid + 1] - rp0 + (uint32_t)mid < d) lo = mid + 1;
+            else hi = mid;
+        }
+        plan[b] = make_uint2((uint32_t)lo, rp0 + d - (uint32_t)lo);
+    }
+}
+
+// ------------------------------------------------------------------------
+// forward-push sweep kernels
+// ------------------------------------------------------------------------
+
+template <typename T>
+__device__ __forceinline__ double h0_of(const InitArgs &a, int64_t i) {
+    if (a.source >= 0) return a.perm[i] == a.source ? (double)a.n : 0.0;
+    if (a.uniform) return 1.0;
+    return (double)a.n * a.p[a.perm[i]] * a.pscale;
+}
+
+template <typename T>
+__global__ void k_init_ifp(InitArgs a, T *h, double *pibar) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        h[i] = (T)h0_of<T>(a, i);
+        if (i < a.nN) pibar[i] = 0.0;
+    }
+}
+
+// Reserve step of one sweep (the body of the calculation threads' loop):
+// every non-dangling i with h_i > xi moves its residual v into pibar_i and
+// publishes its push weight w_i = c v / deg(i); others publish 0.  The
+// reductions give the residual left on non-dangling vertices after this
+// sweep's pushes, the growth of the total mass, and the work; the last
+// workgroup takes the management decision (stop or continue, push or pull).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w,
+                                                    double *pibar, const int32_t *deg, const uint32_t *rp_nn,
+                                                    double c, T xi, int ifp2, int stop_l1, double tol,
+                                                    unsigned long long pull_thr, int force,
+                                                    unsigned long long pull_edges) {
+    if (t > ctl->stop_after) return;
+    double inact = 0.0, pred = 0.0, sxinc = 0.0;
+    unsigned long long cnt = 0, edges = 0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock) {
+        T hv = h[i];
+        if (hv > xi) {
+            int32_t dg = deg[i];
+            uint32_t dnn = rp_nn[i + 1] - rp_nn[i];
+            double v = (double)hv;
+            pibar[i] += v;
+            h[i] = (T)0;
+            w[i] = (T)(c * v / (double)dg);
+            double fN = (double)dnn / (double)dg;
+            pred += v * fN;
+            sxinc += ifp2 ? v * fN : v;
+            cnt += 1;
+            edges += ifp2 ? dnn : (uint32_t)dg;
+        } else {
+            w[i] = (T)0;
+            inact += (double)hv;
+        }
+    }
+    __shared__ double sd[kBlock / W];
+    __shared__ unsigned long long su[kBlock / W];
+    inact = block_sum(inact, sd);
+    pred = block_sum(pred, sd);
+    sxinc = block_sum(sxinc, sd);
+    cnt = block_sum(cnt, su);
+    edges = block_sum(edges, su);
+    if (threadIdx.x == 0) {
+        if (inact != 0.0) atomic_add_f64(&ctl->acc[0], inact);
+        if (pred != 0.0) atomic_add_f64(&ctl->acc[1], pred);
+        if (sxinc != 0.0) atomic_add_f64(&ctl->acc[2], sxinc);
+        if (cnt) atomic_add_u64(&ctl->acc_cnt, cnt);
+        if (edges) atomic_add_u64(&ctl->acc_edges, edges);
+    }
+    if (last_block(&ctl->bdone)) {
+        double a_in = load_agent(&ctl->acc[0]), a_pr = load_agent(&ctl->acc[1]), a_sx = load_agent(&ctl->acc[2]);
+        unsigned long long a_c = load_agent(&ctl->acc_cnt), a_e = load_agent(&ctl->acc_edges);
+        const double k = 2.0 * c / (1.0 - c);
+        if (a_c == 0) {
+            // nothing above the threshold: the state is unchanged, stop before this sweep's push
+            ctl->stop_after = t - 1;
+            ctl->last_bound = k * a_in / ctl->sx;
+            if (t < kMaxTrace) {
+                tr->cnt[t] = 0;
+                tr->edges[t] = 0;
+                tr->sn[t] = a_in;
+                tr->bound[t] = ctl->last_bound;
+            }
+        } else {
+            double sn = a_in + c * a_pr;
+            double sx = ctl->sx + c * a_sx;
+            double bound = k * sn / sx;
+            ctl->sx = sx;
+            ctl->sweeps = t + 1;
+            ctl->tot_pushes += a_c;
+            ctl->tot_edges += a_e;
+            int pull = force == 1 ? 0 : (force == 2 ? 1 : (a_e >= pull_thr ? 1 : 0));
+            ctl->use_pull = pull;
+            ctl->pull_sweeps += pull;
+            ctl->tot_traversed += pull ? pull_edges : a_e;
+            ctl->last_bound = bound;
+            if (stop_l1 && bound <= tol) ctl->stop_after = t;
+            if (t < kMaxTrace) {
+                tr->cnt[t] = a_c | ((unsigned long long)pull << 63);
+                tr->edges[t] = a_e;
+                tr->sn[t] = sn;
+                tr->bound[t] = bound;
+            }
+        }
+        store_agent(&ctl->acc[0], 0.0);
+        store_agent(&ctl->acc[1], 0.0);
+        store_agent(&ctl->acc[2], 0.0);
+        store_agent(&ctl->acc_cnt, 0ull);
+        store_agent(&ctl->acc_edges, 0ull);
+        store_agent(&ctl->bdone, 0u);
+    }
+}
+
+// Scatter step (push): every edge i -> j of a row with w_i != 0 adds w_i to h_j
+// with a hardware FP atomic.  Merge-path tiles give every workgroup the same
+// number of rows + edges, so a hub row is spread over many workgroups and a run
+// of short rows over few.  The tile's edge indices are staged in LDS with
+// coalesced loads; tiles whose rows are all inactive skip the edge stream.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
+                                                 int32_t R, const int32_t *col, const uint2 *plan, uint32_t items,
+                                                 const T *w, T *h) {
+    if (t >= 0 && (t > ctl->stop_after || (check_mode && ctl->use_pull))) return;
+    __shared__ uint32_t s_end[kIPB + 1];
+    __shared__ int32_t s_col[kIPB];
+    __shared__ T s_w[kIPB + 1];
+    const uint2 a = plan[blockIdx.x], b = plan[blockIdx.x + 1];
+    const int32_t i0 = (int32_t)a.x;
+    const int32_t i1 = min((int32_t)b.x, R - 1);
+    const uint32_t e0 = a.y, e1 = b.y;
+    const uint32_t rp0 = rp[0];
+    const int32_t nr = i1 - i0 + 1;
+    int any = 0;
+    for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
+        int32_t r = i0 + k;
+        s_end[k] = rp[r + 1] - rp0 + (uint32_t)r;
+        T wv = w[r];
+        s_w[k] = wv;
+        any |= (wv != (T)0);
+    }
+    any = __syncthreads_or(any);
+    if (!any) return;
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) s_col[e - e0] = col[e];
+    __syncthreads();
+    uint32_t d = min((uint32_t)(blockIdx.x * kIPB + threadIdx.x * kMPK), items);
+    const uint32_t dend = min(d + (uint32_t)kMPK, items);
+    if (d >= dend) return;
+    int32_t lo = 0, hi = nr;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (s_end[mid] < d) lo = mid + 1;
+        else hi = mid;
+    }
+    int32_t k = lo;
+    uint32_t et = rp0 + d - (uint32_t)(i0 + k);
+    T wr = k < nr ? s_w[k] : (T)0;
+    for (; d < dend; ++d) {
+        if (d == s_end[k]) {
+            ++k;
+            wr = k < nr ? s_w[k] : (T)0;
+        } else {
+            if (wr != (T)0) atomicAdd(h + s_col[et - e0], wr);
+            ++et;
+        }
+    }
+}
+
+// Gather step (pull): out_j += sum over in-edges u -> j of w_u, without
+// atomics except for rows split between threads.  Same merge-path tiling as the
+// push; the in-edge source ids are staged in LDS, the w_u are gathered from
+// global memory, sums are carried in FP64.
+template <typename WT, typename OT>
+__global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
+                                                 int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
+                                                 const WT *w, OT *out) {
+    if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
+    __shared__ uint32_t s_end[kIPB + 1];
+    __shared__ int32_t s_src[kIPB];
+    __shared__ uint32_t s_first;
+    const uint2 a = plan[blockIdx.x], b = plan[blockIdx.x + 1];
+    const int32_t i0 = (int32_t)a.x;
+    const int32_t i1 = min((int32_t)b.x, R - 1);
+    const uint32_t e0 = a.y, e1 = b.y;
+    const uint32_t rp0 = rp[0];
+    const int32_t nr = i1 - i0 + 1;
+    if (threadIdx.x == 0) s_first = rp[i0];
+    for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
+        int32_t r = i0 + k;
+        s_end[k] = rp[r + 1] - rp0 + (uint32_t)r;
+    }
+    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) s_src[e - e0] = src[e];
+    __syncthreads();
+    uint32_t d = min((uint32_t)(blockIdx.x * kIPB + threadIdx.x * kMPK), items);
+    const uint32_t dend = min(d + (uint32_t)kMPK, items);
+    if (d >= dend) return;
+    int32_t lo = 0, hi = nr;
+    while (lo < hi) {
+        int32_t mid = (lo + hi) >> 1;
+        if (s_end[mid] < d) lo = mid + 1;
+        else hi = mid;
+    }
+    int32_t k = lo;
+    uint32_t et = rp0 + d - (uint32_t)(i0 + k);
+    // first edge of row i0 + k
+    uint32_t row_first = k == 0 ? s_first : s_end[k - 1] + rp0 + 1u - (uint32_t)(i0 + k);
+    bool owned = et == row_first;
+    bool touched = false;
+    double acc = 0.0;
+    for (; d < dend; ++d) {
+        if (d == s_end[k]) {
+            if (touched) {
+                OT *o = out + (i0 + k);
+                if (owned) *o = (OT)((double)*o + acc);
+                else atomicAdd(o, (OT)acc);
+            }
+            acc = 0.0;
+            touched = false;
+            owned = true;
+            ++k;
+        } else {
+            acc += (double)w[s_src[et - e0]];
+            touched = true;
+            ++et;
+        }
+    }
+    if (touched) atomicAdd(out + (i0 + k), (OT)acc);
+}
+
+// IFP2 phase 2 inputs: w2_u = c z_u / deg(u) for non-dangling u, and the
+// initial mass of every dangling vertex.
+template <typename T>
+__global__ void k_phase2_prep(InitArgs a, const T *h, const double *pibar, const int32_t *deg, double c,
+                              int literal, double *w2, double *xD) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        if (i < a.nN) {
+            double z = pibar[i] + (literal ? 0.0 : (double)h[i]);
+            w2[i] = c * z / (double)deg[i];
+        } else {
+            xD[i - a.nN] = h0_of<T>(a, i);
+        }
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ double x_ifp(const InitArgs &a, const T *h, const double *pibar, const double *xD,
+                                        int ifp2, int literal, int64_t i) {
+    if (i < a.nN) return pibar[i] + (literal ? 0.0 : (double)h[i]);
+    return ifp2 ? xD[i - a.nN] : (double)h[i];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_final_sum(Ctl *ctl, InitArgs a, const T *h, const double *pibar,
+                                                      const double *xD, int ifp2, int literal) {
+    double s = 0.0, sn = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        s += x_ifp(a, h, pibar, xD, ifp2, literal, i);
+        if (i < a.nN) sn += (double)h[i];
+    }
+    __shared__ double sd[kBlock / W];
+    s = block_sum(s, sd);
+    sn = block_sum(sn, sd);
+    if (threadIdx.x == 0) {
+        atomic_add_f64(&ctl->acc[0], s);
+        atomic_add_f64(&ctl->acc[1], sn);
+    }
+    if (last_block(&ctl->fdone)) {
+        ctl->fin_sum = load_agent(&ctl->acc[0]);
+        ctl->fin_sn = load_agent(&ctl->acc[1]);
+        store_agent(&ctl->acc[0], 0.0);
+        store_agent(&ctl->acc[1], 0.0);
+        store_agent(&ctl->fdone, 0u);
+    }
+}
+
+template <typename T>
+__global__ void k_final_write(const Ctl *ctl, InitArgs a, const T *h, const double *pibar, const double *xD,
+                              int ifp2, int literal, double *out) {
+    const double inv = 1.0 / ctl->fin_sum;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock)
+        out[a.perm[i]] = x_ifp(a, h, pibar, xD, ifp2, literal, i) * inv;
+}
+
+// ------------------------------------------------------------------------
+// power method
+// ------------------------------------------------------------------------
+__device__ __forceinline__ double p_of(const InitArgs &a, int64_t i) {
+    if (a.source >= 0) return a.perm[i] == a.source ? 1.0 : 0.0;
+    if (a.uniform) return 1.0 / (double)a.n;
+    return a.p[a.perm[i]] * a.pscale;
+}
+
+__global__ void k_power_init(InitArgs a, double *x, double *acc) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        x[i] = p_of(a, i);
+        acc[i] = 0.0;
+    }
+}
+
+// Iterate t: x_t = acc + b_{t-1} p (t > 0), ||x_t - x_{t-1}||_1, y = c x_t / deg on
+// non-dangling vertices, the dangling mass and total mass for b_t; acc cleared
+// for the gather that follows.
+template <typename WT>
+__global__ __launch_bounds__(kBlock) void k_power_prescale(int t, Ctl *ctl, InitArgs a, double *x, double *acc,
+                                                           WT *y, const int32_t *deg, double c, double tol) {
+    if (t > ctl->stop_after) return;
+    const double b = ctl->pw_b;
+    double diff = 0.0, dsum = 0.0, xsum = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        double xv = x[i];
+        if (t > 0) {
+            double xn = acc[i] + b * p_of(a, i);
+            diff += fabs(xn - xv);
+            x[i] = xn;
+            xv = xn;
+        }
+        acc[i] = 0.0;
+        xsum += xv;
+        if (i < a.nN) y[i] = (WT)(c * xv / (double)deg[i]);
+        else dsum += xv;
+    }
+    __shared__ double sd[kBlock / W];
+    diff = block_sum(diff, sd);
+    dsum = block_sum(dsum, sd);
+    xsum = block_sum(xsum, sd);
+    if (threadIdx.x == 0) {
+        atomic_add_f64(&ctl->acc[0], diff);
+        atomic_add_f64(&ctl->acc[1], dsum);
+        atomic_add_f64(&ctl->acc[2], xsum);
+    }
+    if (last_block(&ctl->bdone)) {
+        double df = load_agent(&ctl->acc[0]), ds = load_agent(&ctl->acc[1]), xs = load_agent(&ctl->acc[2]);
+        ctl->pw_b = c * ds + (1.0 - c) * xs;
+        if (t > 0) {
+            ctl->pw_diff = df;
+            ctl->sweeps = t;
+            ctl->last_bound = c / (1.0 - c) * df;
+            if (ctl->last_bound <= tol) ctl->stop_after = t - 1;  // x_t is the answer: skip the gather
+        }
+        store_agent(&ctl->acc[0], 0.0);
+        store_agent(&ctl->acc[1], 0.0);
+        store_agent(&ctl->acc[2], 0.0);
+        store_agent(&ctl->bdone, 0u);
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_x_sum(Ctl *ctl, int64_t n, const double *x) {
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) s += x[i];
+    __shared__ double sd[kBlock / W];
+    s = block_sum(s, sd);
+    if (threadIdx.x == 0) atomic_add_f64(&ctl->acc[0], s);
+    if (last_block(&ctl->fdone)) {
+        ctl->fin_sum = load_agent(&ctl->acc[0]);
+        ctl->fin_sn = 0.0;
+        store_agent(&ctl->acc[0], 0.0);
+        store_agent(&ctl->fdone, 0u);
+    }
+}
+
+__global__ void k_final_x_write(const Ctl *ctl, InitArgs a, const double *x, double *out) {
+    const double inv = 1.0 / ctl->fin_sum;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock)
+        out[a.perm[i]] = x[i] * inv;
+}
+
+// p validation: sum_bad[0] += p_i, sum_bad[1] += 1 for every negative or non-finite entry
+__global__ __launch_bounds__(kBlock) void k_validate_p(const double *p, int64_t n, double *sum_bad) {
+    double s = 0.0, bad = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        double v = p[i];
+        if (!(v >= 0.0) || !isfinite(v)) bad += 1.0;
+        else s += v;
+    }
+    __shared__ double sd[kBlock / W];
+    s = block_sum(s, sd);
+    bad = block_sum(bad, sd);
+    if (threadIdx.x == 0) {
+        atomic_add_f64(&sum_bad[0], s);
+        if (bad != 0.0) atomic_add_f64(&sum_bad[1], bad);
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------
+// launchers
+// ------------------------------------------------------------------------
+#define PRK_LAUNCH(kern, grid, ...)                                                   \
+    do {                                                                              \
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);        \
+        return hipGetLastError();                                                     \
+    } while (0)
+
+hipError_t launch_check_cols(const int32_t *col, int64_t m, int64_t n, unsigned int *bad, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    PRK_LAUNCH(k_check_cols, grid_for(m, 8, 8192), col, m, n, bad);
+}
+hipError_t launch_degree_class(const int64_t *rp64, int64_t n, uint32_t *isN, hipStream_t s) {
+    PRK_LAUNCH(k_degree_class, grid_for(n, 4, 8192), rp64, n, isN);
+}
+hipError_t launch_indegree(const int32_t *col, int64_t m, uint32_t *indeg, hipStream_t s) {
+    if (m == 0) return hipSuccess;
+    PRK_LAUNCH(k_indegree, grid_for(m, 8, 8192), col, m, indeg);
+}
+size_t scan_tmp_elems(int64_t n) { return (size_t)((n + kScanTile - 1) / kScanTile) + 1; }
+hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s) {
+    if (n == 0) {
+        // out[0] = 0
+        return hipMemsetAsync(out, 0, sizeof(uint32_t), s);
+    }
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    hipLaunchKernelGGL(k_scan_partial, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb);
+    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, (const uint32_t *)tmp);
+    return hipGetLastError();
+}
+hipError_t launch_relabel(const uint32_t *isN, const uint32_t *rankN, int64_t n, int32_t nN, int32_t *newid,
+                          int32_t *perm, hipStream_t s) {
+    PRK_LAUNCH(k_relabel, grid_for(n, 4, 8192), isN, rankN, n, nN, newid, perm);
+}
+hipError_t launch_count_nn(const int64_t *rp64, const int32_t *col, const uint32_t *isN, const int32_t *perm,
+                           int32_t nN, uint32_t *cnt_nn, uint32_t *cnt_nd, int32_t *deg, hipStream_t s) {
+    if (nN == 0) return hipSuccess;
+    PRK_LAUNCH(k_count_nn, grid_for((int64_t)nN * W, 1, 16384), rp64, col, isN, perm, nN, cnt_nn, cnt_nd, deg);
+}
+hipError_t launch_split_rows(const int64_t *rp64, const int32_t *col, const uint32_t *isN, const int32_t *newid,
+                             const int32_t *perm, int32_t nN, const uint32_t *rp_nn, int32_t *col_nn,
+                             const uint32_t *rp_nd, int32_t *col_nd, hipStream_t s) {
+    if (nN == 0) return hipSuccess;
+    PRK_LAUNCH(k_split_rows, grid_for((int64_t)nN * W, 1, 16384), rp64, col, isN, newid, perm, nN, rp_nn, col_nn,
+               rp_nd, col_nd);
+}
+hipError_t launch_permute_u32(const uint32_t *in_old, const int32_t *perm, int64_t n, uint32_t *out_new,
+                              hipStream_t s) {
+    PRK_LAUNCH(k_permute_u32, grid_for(n, 4, 8192), in_old, perm, n, out_new);
+}
+hipError_t launch_fill_csc(const uint32_t *rp, const int32_t *col, int32_t R, uint32_t *cursor, int32_t *in_src,
+                           hipStream_t s) {
+    if (R == 0) return hipSuccess;
+    PRK_LAUNCH(k_fill_csc, grid_for((int64_t)R * W, 1, 16384), rp, col, R, cursor, in_src);
+}
+hipError_t launch_count_zero(const uint32_t *a, int64_t n, unsigned long long *out, hipStream_t s) {
+    PRK_LAUNCH(k_count_zero, grid_for(n, 8, 4096), a, n, out);
+}
+hipError_t launch_plan(MPPlan &p, hipStream_t s) {
+    p.ipb = kIPB;
+    p.blocks = (int32_t)(((int64_t)p.items + kIPB - 1) / kIPB);
+    PRK_LAUNCH(k_plan, grid_for((int64_t)p.blocks + 1, 1, 4096), p.rp, p.R, p.items, p.ipb, p.blocks, p.plan);
+}
+
+template <typename T>
+hipError_t launch_init_ifp(const InitArgs &a, T *h, double *pibar, hipStream_t s) {
+    PRK_LAUNCH(k_init_ifp<T>, grid_for(a.n, 4, 8192), a, h, pibar);
+}
+
+template <typename T>
+hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
+                          const uint32_t *rp_nn, double c, double xi, int ifp2, int stop_l1, double tol,
+                          unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
+                          hipStream_t s) {
+    PRK_LAUNCH(k_reserve<T>, grid_for(nN, 4, 2048), t, ctl, tr, nN, h, w, pibar, deg, rp_nn, c, (T)xi, ifp2,
+               stop_l1, tol, pull_edges_thr, force, pull_edges);
+}
+
+template <typename T>
+hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s) {
+    if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
+    PRK_LAUNCH(k_push<T>, p.blocks, t, ctl, check_mode, p.rp, p.R, p.idx, (const uint2 *)p.plan, p.items, w, h);
+}
+
+template <typename WT, typename OT>
+hipError_t launch_pull(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
+                       hipStream_t s) {
+    if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
+    auto kern = &k_pull<WT, OT>;
+    hipLaunchKernelGGL(kern, dim3(p.blocks), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R, p.idx,
+                       (const uint2 *)p.plan, p.items, w, out);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_phase2_prep(const InitArgs &a, const T *h, const double *pibar, const int32_t *deg, double c,
+                              int literal, double *w2, double *xD, hipStream_t s) {
+    PRK_LAUNCH(k_phase2_prep<T>, grid_for(a.n, 4, 8192), a, h, pibar, deg, c, literal, w2, xD);
+}
+
+template <typename T>
+hipError_t launch_final_ifp(Ctl *ctl, const InitArgs &a, const T *h, const double *pibar, const double *xD,
+                            int ifp2, int literal, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_final_sum<T>, dim3(grid_for(a.n, 4, 2048)), dim3(kBlock), 0, s, ctl, a, h, pibar, xD, ifp2,
+                       literal);
+    hipLaunchKernelGGL(k_final_write<T>, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, h,
+                       pibar, xD, ifp2, literal, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStream_t s) {
+    PRK_LAUNCH(k_power_init, grid_for(a.n, 4, 8192), a, x, acc);
+}
+
+template <typename WT>
+hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, double *acc, WT *y,
+                                 const int32_t *deg, double c, double tol, hipStream_t s) {
+    PRK_LAUNCH(k_power_prescale<WT>, grid_for(a.n, 4, 2048), t, ctl, a, x, acc, y, deg, c, tol);
+}
+
+hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_final_x_sum, dim3(grid_for(a.n, 4, 2048)), dim3(kBlock), 0, s, ctl, a.n, x);
+    hipLaunchKernelGGL(k_final_x_write, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, x,
+                       out);
+    return hipGetLastError();
+}
+
+hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s) {
+    PRK_LAUNCH(k_validate_p, grid_for(n, 4, 2048), p, n, sum_bad);
+}
+
+// explicit instantiations
+template hipError_t launch_init_ifp<float>(const InitArgs &, float *, double *, hipStream_t);
+template hipError_t launch_init_ifp<double>(const InitArgs &, double *, double *, hipStream_t);
+template hipError_t launch_reserve<float>(int, Ctl *, Trace *, int32_t, float *, float *, double *, const int32_t *,
+                                          const uint32_t *, double, double, int, int, double, unsigned long long,
+                                          int, unsigned long long, hipStream_t);
+template hipError_t launch_reserve<double>(int, Ctl *, Trace *, int32_t, double *, double *, double *,
+                                           const int32_t *, const uint32_t *, double, double, int, int, double,
+                                           unsigned long long, int, unsigned long long, hipStream_t);
+template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t);
+template hipError_t launch_push<double>(int, const Ctl *, const MPPlan &, const double *, double *, int,
+                                        hipStream_t);
+template hipError_t launch_pull<float, float>(int, const Ctl *, const MPPlan &, const float *, float *, int,
+                                              hipStream_t);
+template hipError_t launch_pull<double, double>(int, const Ctl *, const MPPlan &, const double *, double *, int,
+                                                hipStream_t);
+template hipError_t launch_pull<float, double>(int, const Ctl *, const MPPlan &, const float *, double *, int,
+                                               hipStream_t);
+template hipError_t launch_phase2_prep<float>(const InitArgs &, const float *, const double *, const int32_t *,
+                                              double, int, double *, double *, hipStream_t);
+template hipError_t launch_phase2_prep<double>(const InitArgs &, const double *, const double *, const int32_t *,
+                                               double, int, double *, double *, hipStream_t);
+template hipError_t launch_final_ifp<float>(Ctl *, const InitArgs &, const float *, const double *, const double *,
+                                            int, int, double *, hipStream_t);
+template hipError_t launch_final_ifp<double>(Ctl *, const InitArgs &, const double *, const double *,
+                                             const double *, int, int, double *, hipStream_t);
+template hipError_t launch_power_prescale<float>(int, Ctl *, const InitArgs &, double *, double *, float *,
+                                                 const int32_t *, double, double, hipStream_t);
+template hipError_t launch_power_prescale<double>(int, Ctl *, const InitArgs &, double *, double *, double *,
+                                                  const int32_t *, double, double, hipStream_t);
+
+}  // namespace prk

@@ -1,0 +1,303 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle and the exact fixtures.
+
+Tolerances: L1 <= 1e-9 with FP64 residuals, L1 <= 1e-6 with FP32 residuals, the
+top-1000 ranking equal under the tie rule of conftest.topk_agree.
+"""
+import json
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import oracle
+import prgen
+from conftest import l1, topk_agree
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+C = 0.85
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import paper_2302_03245_amd as pr
+    pr.lib()
+    return pr
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+# ----------------------------------------------------------------------------
+# tiny graphs with known answers
+# ----------------------------------------------------------------------------
+def _closed_forms():
+    out = []
+    n = 37
+    k = np.arange(1, n + 1)
+    y = (1 - C ** k) / (1 - C)
+    out.append(("chain37", prgen.from_edges(n, np.arange(n - 1), np.arange(1, n)), y / y.sum()))
+    kk = 40
+    e = np.full(kk + 1, 1 / (1 + kk + C * kk))
+    e[0] = (1 + C * kk) / (1 + kk + C * kk)
+    out.append(("in_star40", prgen.from_edges(kk + 1, np.arange(1, kk + 1), np.zeros(kk, int)), e))
+    kk = 5000  # hub row longer than a merge-path tile
+    e = np.full(kk + 1, (1 + C / kk) / (kk + 1 + C))
+    e[0] = 1 / (kk + 1 + C)
+    out.append(("out_star5000", prgen.from_edges(kk + 1, np.zeros(kk, int), np.arange(1, kk + 1)), e))
+    e = np.full(kk + 1, 1 / (1 + kk + C * kk))
+    e[0] = (1 + C * kk) / (1 + kk + C * kk)
+    out.append(("in_star5000", prgen.from_edges(kk + 1, np.arange(1, kk + 1), np.zeros(kk, int)), e))
+    out.append(("cycle100", prgen.from_edges(100, np.arange(100), (np.arange(100) + 1) % 100), np.full(100, 0.01)))
+    out.append(("two", prgen.from_edges(2, [0], [1]), np.array([1, 1 + C]) / (2 + C)))
+    out.append(("no_edges", prgen.from_edges(5, [], []), np.full(5, 0.2)))
+    out.append(("single", prgen.from_edges(1, [], []), np.array([1.0])))
+    out.append(("single_selfloop", prgen.from_edges(1, [0], [0]), np.array([1.0])))
+    return out
+
+
+CLOSED = _closed_forms()
+
+
+@pytest.mark.parametrize("name,g,expect", CLOSED, ids=[c[0] for c in CLOSED])
+@pytest.mark.parametrize("method", ["ifp1", "ifp2", "power"])
+def test_closed_forms(pr, name, g, expect, method):
+    _say(f"closed form {name} {method}")
+    dg = pr.upload(g.row_ptr, g.col)
+    for mode in ([None, "push", "pull"] if method != "power" else [None]):
+        if method == "power":
+            pi, st = pr.power(dg, c=C, l1_tol=1e-13)
+        else:
+            pi, st = getattr(pr, method)(dg, c=C, xi=1e-15, mode=mode)
+        assert st["status"] == 0
+        assert l1(pi, expect) <= 1e-11, (mode, l1(pi, expect))
+        assert abs(pi.sum() - 1) < 1e-13
+
+
+GOLD = json.load(open(os.path.join(HERE, "golden", "exact_small.json")))["cases"]
+
+
+@pytest.mark.parametrize("case", GOLD, ids=[c["name"] for c in GOLD])
+def test_exact_fixtures(pr, case):
+    _say(f"exact fixture {case['name']}")
+    c = float(Fraction(case["c"]))
+    p = None if case["p"] is None else np.array(case["p"], float)
+    dg = pr.upload(np.array(case["row_ptr"], np.int64), np.array(case["col"], np.int32))
+    ref = np.array(case["pi"])
+    for fn in (pr.ifp1, pr.ifp2):
+        for res, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
+            pi, st = fn(dg, p=p, c=c, xi=1e-15 if res == "fp64" else 1e-9, residual=res)
+            assert l1(pi, ref) <= tol
+    pi, st = pr.power(dg, p=p, c=c, l1_tol=1e-13)
+    assert l1(pi, ref) <= 1e-12
+
+
+# ----------------------------------------------------------------------------
+# random graphs spanning several tiles and a ragged tail
+# ----------------------------------------------------------------------------
+RANDOM = [
+    ("rand_n3001", dict(n=3001, m=24000, seed=1, dangling_frac=0.2, unref_frac=0.1)),
+    ("rand_n20011_selfloops_multi", dict(n=20011, m=150000, seed=2, self_loops=True, multi=True, dangling_frac=0.3)),
+    ("rand_n70001", dict(n=70001, m=420000, seed=3, dangling_frac=0.15, unref_frac=0.1)),
+]
+
+
+@pytest.mark.parametrize("name,kw", RANDOM, ids=[r[0] for r in RANDOM])
+def test_random_graphs(pr, name, kw):
+    g = prgen.random_digraph(**kw)
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    dg = pr.upload(g.row_ptr, g.col)
+    info = dg.info()
+    assert info["n"] == g.n and info["m"] == g.m
+    for method in ("ifp1", "ifp2"):
+        for mode in (None, "push", "pull"):
+            _say(f"{name} {method} mode={mode}")
+            pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
+            assert st["status"] == 0
+            assert l1(pi, ref) <= 1e-9
+            ok, swaps, eps = topk_agree(ref, pi, 1000)
+            assert ok
+            pi32, st32 = getattr(pr, method)(dg, c=C, l1_tol=1e-6, residual="fp32", mode=mode)
+            assert st32["status"] == 0 and st32["l1_bound"] <= 1e-6
+            assert l1(pi32, ref) <= 1e-6
+    pi, st = pr.power(dg, c=C, l1_tol=1e-11)
+    assert l1(pi, ref) <= 1e-9
+    pi, st = pr.power(dg, c=C, l1_tol=1e-6, residual="fp32")
+    assert l1(pi, ref) <= 1e-6
+
+
+def test_rmat_small_workload(pr):
+    """R-MAT n=10,000, 100,000 distinct edges, 10 % forced dangling, c=0.85, uniform p,
+    xi=1e-12, FP64: IFP2 against the FP64 power method run to 1e-13."""
+    _say("rmat small workload")
+    g = prgen.workload_rmat_small(seed=0)
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    dg = pr.upload(g.row_ptr, g.col)
+    pi, st = pr.ifp2(dg, c=C, xi=1e-12)
+    assert st["status"] == 0
+    assert l1(pi, ref) <= 1e-9
+    ok, swaps, eps = topk_agree(ref, pi, 1000)
+    assert ok and eps <= 1e-12
+    pi1, _ = pr.ifp1(dg, c=C, xi=1e-12)
+    assert l1(pi1, ref) <= 1e-9
+    pw, _ = pr.power(dg, c=C, l1_tol=1e-12)
+    assert l1(pw, ref) <= 1e-11
+    # work: IFP2 pushes fewer edges than IFP1 at the same threshold
+    _, st1 = pr.ifp1(dg, c=C, xi=1e-12, mode="push")
+    _, st2 = pr.ifp2(dg, c=C, xi=1e-12, mode="push")
+    assert st2["edges_processed"] < st1["edges_processed"]
+
+
+def test_same_semantics_as_serial_when_nothing_moves(pr):
+    """xi above every initial residual: no vertex pushes, IFP2's phase 2 alone decides
+    the dangling values -- identical to the oracle with the same xi."""
+    g = prgen.random_digraph(5000, 30000, seed=7, dangling_frac=0.3)
+    dg = pr.upload(g.row_ptr, g.col)
+    for method in ("ifp1", "ifp2"):
+        pi, st = getattr(pr, method)(dg, c=C, xi=10.0)
+        ref = getattr(oracle, method)(g, C, xi=10.0)["pi"]
+        assert st["sweeps"] == 0
+        np.testing.assert_allclose(pi, ref, rtol=1e-13, atol=0)
+
+
+# ----------------------------------------------------------------------------
+# personalisation, PPR, device buffers, literal IFP2, damping extremes
+# ----------------------------------------------------------------------------
+def test_personalized_p_host_and_device(pr):
+    import torch
+    g = prgen.workload_rmat_small(seed=1)
+    p = prgen.random_p(g.n, seed=5, zero_frac=0.4)
+    ref, _, _ = oracle.power(g, C, p, tol=1e-13)
+    dg = pr.upload(g.row_ptr, g.col)
+    pi, _ = pr.ifp2(dg, p=p * 7.0, c=C, xi=1e-12)  # p is normalised by its sum
+    assert l1(pi, ref) <= 1e-9
+    pt = torch.tensor(p, dtype=torch.float64, device="cuda")
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    pr.ifp1(dg, p=pt, c=C, xi=1e-12, out=out)
+    torch.cuda.synchronize()
+    assert l1(out.cpu().numpy(), ref) <= 1e-9
+    pw, _ = pr.power(dg, p=pt, c=C, l1_tol=1e-12)
+    assert l1(pw, ref) <= 1e-11
+
+
+def test_upload_from_device_tensors(pr):
+    import torch
+    g = prgen.random_digraph(9000, 60000, seed=8, dangling_frac=0.2)
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    dg = pr.upload(torch.tensor(g.row_ptr, device="cuda"), torch.tensor(g.col, device="cuda"))
+    pi, _ = pr.ifp2(dg, c=C, xi=1e-13)
+    assert l1(pi, ref) <= 1e-9
+
+
+def test_ppr_sources(pr):
+    g = prgen.workload_rmat_small(seed=2)
+    dg = pr.upload(g.row_ptr, g.col)
+    deg = np.diff(g.row_ptr)
+    srcs = [int(np.argmax(deg)), 17, int(np.where(deg == 0)[0][0])]  # hub, ordinary, dangling source
+    out, stats = pr.ppr(dg, srcs, c=C, xi=1e-12)
+    for r, s in enumerate(srcs):
+        p = np.zeros(g.n)
+        p[s] = 1.0
+        ref, _, _ = oracle.power(g, C, p, tol=1e-13)
+        _say(f"ppr source {s}: sweeps {stats[r]['sweeps']}")
+        assert l1(out[r], ref) <= 1e-9
+    out32, _ = pr.ppr(dg, srcs[:1], c=C, l1_tol=1e-6, residual="fp32")
+    p = np.zeros(g.n)
+    p[srcs[0]] = 1.0
+    assert l1(out32[0], oracle.power(g, C, p, tol=1e-13)[0]) <= 1e-6
+
+
+def test_literal_ifp2_matches_oracle_literal(pr):
+    g = prgen.random_digraph(4000, 30000, seed=9, dangling_frac=0.25)
+    dg = pr.upload(g.row_ptr, g.col)
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    pi, st = pr.ifp2(dg, c=C, xi=1e-13, literal=True)
+    assert l1(pi, ref) <= 1e-9
+    assert st["l1_bound"] >= l1(pi, ref)
+
+
+@pytest.mark.parametrize("c", [0.01, 0.5, 0.99])
+def test_damping_extremes(pr, c):
+    g = prgen.random_digraph(3000, 20000, seed=10, dangling_frac=0.2)
+    ref, _, _ = oracle.power(g, c, tol=1e-14)
+    dg = pr.upload(g.row_ptr, g.col)
+    pi, st = pr.ifp2(dg, c=c, l1_tol=1e-10)
+    assert st["status"] == 0
+    assert l1(pi, ref) <= max(st["l1_bound"], 1e-12)
+    pw, _ = pr.power(dg, c=c, l1_tol=1e-10)
+    assert l1(pw, ref) <= 1e-10
+
+
+def test_duplicates_counted_and_dedupe(pr):
+    g = prgen.random_digraph(2000, 16000, seed=11, multi=True, self_loops=True, dangling_frac=0.1)
+    assert np.any(np.diff(g.col) == 0)
+    dg = pr.upload(g.row_ptr, g.col)
+    pi, _ = pr.ifp2(dg, c=C, xi=1e-13)
+    assert l1(pi, oracle.power(g, C, tol=1e-13)[0]) <= 1e-9
+    dd = pr.upload(g.row_ptr, g.col, dedupe=True)
+    deg = np.diff(g.row_ptr)
+    src = np.repeat(np.arange(g.n), deg)
+    key = np.unique(src.astype(np.int64) * g.n + g.col)
+    gu = prgen.from_edges(g.n, key // g.n, key % g.n)
+    assert dd.m == gu.m
+    pi, _ = pr.ifp2(dd, c=C, xi=1e-13)
+    assert l1(pi, oracle.power(gu, C, tol=1e-13)[0]) <= 1e-9
+
+
+def test_max_sweeps_gives_bounded_estimate(pr):
+    g = prgen.workload_rmat_small(seed=3)
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    dg = pr.upload(g.row_ptr, g.col)
+    pi, st = pr.ifp2(dg, c=C, xi=1e-12, max_sweeps=3)
+    assert st["status"] == 1 and st["sweeps"] == 3
+    assert abs(pi.sum() - 1) < 1e-12
+    assert l1(pi, ref) <= st["l1_bound"]
+    pw, stp = pr.power(dg, c=C, l1_tol=1e-14, max_sweeps=2)
+    assert stp["status"] == 1
+    assert l1(pw, ref) <= stp["l1_bound"] + 1e-15
+
+
+def test_invalid_arguments_on_gpu(pr):
+    g = prgen.random_digraph(100, 500, seed=12)
+    bad = g.col.copy()
+    bad[3] = 100
+    with pytest.raises(pr.PRError, match="out of"):
+        pr.upload(g.row_ptr, bad)
+    dg = pr.upload(g.row_ptr, g.col)
+    with pytest.raises(pr.PRError, match="c must"):
+        pr.ifp2(dg, c=1.0)
+    with pytest.raises(pr.PRError, match="xi must"):
+        pr.ifp2(dg, xi=0.0)
+    with pytest.raises(pr.PRError, match="l1_tol"):
+        pr.ifp2(dg, l1_tol=-1.0)
+    p = np.ones(100)
+    p[5] = -1
+    with pytest.raises(pr.PRError, match="negative"):
+        pr.ifp2(dg, p=p)
+    with pytest.raises(pr.PRError, match="sum"):
+        pr.ifp2(dg, p=np.zeros(100))
+    with pytest.raises(pr.PRError, match="source"):
+        pr.ppr(dg, [100])
+    # the graph still works after the rejected calls
+    pi, _ = pr.ifp2(dg, c=C, xi=1e-13)
+    assert l1(pi, oracle.power(g, C, tol=1e-13)[0]) <= 1e-9
+
+
+def test_equation_residual_and_bounds(pr):
+    """A-posteriori check without the oracle: ||pi - c P pi - gamma p||_1 with
+    gamma = 1 - c + c d^T pi (section 3.1), sum 1, pi >= (1-c) p."""
+    import scipy.sparse as sp
+    g = prgen.random_digraph(50000, 400000, seed=13, dangling_frac=0.2, unref_frac=0.1)
+    dg = pr.upload(g.row_ptr, g.col)
+    pi, st = pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32")
+    deg = np.diff(g.row_ptr)
+    src = np.repeat(np.arange(g.n), deg)
+    P = sp.csr_matrix((1.0 / deg[src], (g.col, src)), shape=(g.n, g.n))
+    gamma = 1 - C + C * pi[deg == 0].sum()
+    res = np.abs(pi - C * (P @ pi) - gamma / g.n).sum()
+    assert res <= 2 * st["l1_bound"]
+    assert abs(pi.sum() - 1) < 1e-12
+    assert np.all(pi >= (1 - C) / g.n * (1 - 1e-6))
