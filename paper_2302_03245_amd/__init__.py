@@ -77,6 +77,12 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run __graft_entry__.build() "
                            "(the HIP library is required, there is no CPU fallback)")
+    # One HIP runtime per process: torch ships its own libamdhip64 (same soname).  Loading
+    # torch first makes libpr bind to that copy, so tensors and the library share a runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(LIB_PATH)
     vp, i64, i32, u32, dp = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint32, ctypes.c_void_p
     L.pr_opts_default.argtypes = [ctypes.POINTER(Opts)]

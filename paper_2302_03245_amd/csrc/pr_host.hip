@@ -81,6 +81,46 @@ struct EventPair {
 // ---------------------------------------------------------------------------
 // graph upload
 // ---------------------------------------------------------------------------
+
+// Device vertex order: non-dangling vertices first, by decreasing out-degree
+// (ties by original id), then dangling vertices in original order.  A vertex's
+// out-degree is how often its weight is gathered by a pull sweep (and, on
+// these graphs, tracks how often it is a scatter target), so the most-read
+// entries of the residual-sized vectors share cache lines and stay resident in
+// the per-XCD L2.  Stable LSD radix sort on the complemented degree.
+int32_t degree_order(int64_t n, const int64_t *rp, std::vector<int32_t> &perm, std::vector<int32_t> &newid) {
+    std::vector<int32_t> nd;
+    std::vector<uint32_t> key;
+    nd.reserve((size_t)n);
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] > rp[i]) nd.push_back((int32_t)i);
+    const size_t nN = nd.size();
+    std::vector<int32_t> tmp(nN);
+    std::vector<uint32_t> cnt(1u << 16);
+    for (int pass = 0; pass < 2; ++pass) {
+        const int sh = 16 * pass;
+        std::fill(cnt.begin(), cnt.end(), 0u);
+        auto kf = [&](int32_t v) { return ((~(uint32_t)(rp[v + 1] - rp[v])) >> sh) & 0xffffu; };
+        for (int32_t v : nd) cnt[kf(v)]++;
+        uint32_t run = 0;
+        for (auto &c : cnt) {
+            uint32_t x = c;
+            c = run;
+            run += x;
+        }
+        for (int32_t v : nd) tmp[cnt[kf(v)]++] = v;
+        nd.swap(tmp);
+    }
+    perm.resize((size_t)n);
+    newid.resize((size_t)n);
+    size_t k = 0;
+    for (int32_t v : nd) perm[k++] = v;
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] == rp[i]) perm[k++] = (int32_t)i;
+    for (int64_t j = 0; j < n; ++j) newid[perm[j]] = (int32_t)j;
+    return (int32_t)nN;
+}
+
 pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
                       pr_graph **out) {
     if (!out) return fail(PR_EINVAL, "out is NULL");
@@ -189,21 +229,19 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
         return e;
     };
 
-    uint32_t *d_isN, *d_rank, *d_scan;
+    uint32_t *d_isN, *d_scan;
     HIPCHK(tmp.alloc(&d_isN, (size_t)n));
-    HIPCHK(tmp.alloc(&d_rank, (size_t)n + 1));
     HIPCHK(tmp.alloc(&d_scan, scan_tmp_elems(std::max<int64_t>(n, m) + 1)));
     HIPCHK(launch_degree_class(d_rp64, n, d_isN, s));
-    HIPCHK(launch_scan_u32(d_isN, d_rank, n, d_scan, s));
-    uint32_t h_nN = 0;
-    HIPCHK(hipMemcpyAsync(&h_nN, d_rank + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    G.nN = (int32_t)h_nN;
-    G.nD = (int32_t)(n - h_nN);
 
+    // vertex order on the device (see degree_order)
+    std::vector<int32_t> h_perm, h_newid;
+    G.nN = degree_order(n, rp, h_perm, h_newid);
+    G.nD = (int32_t)(n - G.nN);
     HIPCHK(galloc(&G.perm, (size_t)n));
     HIPCHK(galloc(&G.newid, (size_t)n));
-    HIPCHK(launch_relabel(d_isN, d_rank, n, G.nN, G.newid, G.perm, s));
+    HIPCHK(hipMemcpyAsync(G.perm, h_perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(G.newid, h_newid.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
 
     uint32_t *d_indeg_old, *d_indeg, *d_cnn, *d_cnd, *d_cursor;
     HIPCHK(tmp.alloc(&d_indeg_old, (size_t)n));
@@ -449,7 +487,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     size_t bytes = carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
                    carve_size<double>(nN) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
                    carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
-                   carve_size<double>(2);
+                   carve_size<double>(2) + carve_size<double>(5 * kRedBlocks);
     Workspace ws;
     pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
     if (ps != PR_OK) return ps;
@@ -464,6 +502,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     Trace *tr = cv.take<Trace>(1);
     double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
     double *sumbad = cv.take<double>(2);
+    double *part = cv.take<double>(5 * kRedBlocks);
 
     InitArgs a{};
     a.n = n;
@@ -501,7 +540,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
             int nb = std::min(batch, max_sweeps - t);
             for (int k = 0; k < nb; ++k, ++t) {
                 HIPCHK(launch_reserve<T>(t, ctl, tr, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, l1 ? 1 : 0,
-                                         tol, pull_thr, force, pull_edges, s));
+                                         tol, pull_thr, force, pull_edges, part, s));
                 if (force != 2) {
                     hipEvent_t e = timer.begin(s, t, 0);
                     HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, check_mode, s));
@@ -532,7 +571,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
     }
     double *dst = out_dev ? pi : outbuf;
-    HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, dst, s));
+    HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, dst, part, s));
     HIPCHK(hipEventRecord(ev_solve.b, s));
     HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
@@ -595,7 +634,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     const int max_it = o.max_sweeps > 0 ? o.max_sweeps : 100000;
     size_t bytes = carve_size<double>(n) * 2 + carve_size<WT>(nN) + carve_size<double>(out_dev ? 0 : n) +
                    carve_size<Ctl>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
-                   carve_size<double>(2);
+                   carve_size<double>(2) + carve_size<double>(5 * kRedBlocks);
     Workspace ws;
     pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
     if (ps != PR_OK) return ps;
@@ -607,6 +646,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     Ctl *ctl = cv.take<Ctl>(1);
     double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
     double *sumbad = cv.take<double>(2);
+    double *part = cv.take<double>(5 * kRedBlocks);
     InitArgs a{};
     a.n = n;
     a.nN = nN;
@@ -633,7 +673,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     while (t <= max_it) {
         int nb = std::min(batch, max_it + 1 - t);
         for (int k = 0; k < nb; ++k, ++t) {
-            HIPCHK(launch_power_prescale<WT>(t, ctl, a, x, acc, y, G.deg, c, tol, s));
+            HIPCHK(launch_power_prescale<WT>(t, ctl, a, x, acc, y, G.deg, c, tol, part, s));
             if (t < max_it) {
                 hipEvent_t e = timer.begin(s, t, 1);
                 HIPCHK(launch_pull<WT, double>(t, ctl, G.pull_all, y, acc, 0, s));
@@ -651,7 +691,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
         t_prev = t;
     }
     double *dst = out_dev ? pi : outbuf;
-    HIPCHK(launch_final_x(ctl, a, x, dst, s));
+    HIPCHK(launch_final_x(ctl, a, x, dst, part, s));
     HIPCHK(hipEventRecord(ev_solve.b, s));
     HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
@@ -666,7 +706,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
         z.edges_traversed = z.edges_processed;
         z.vertex_pushes = (int64_t)r.sweeps * nN;
         z.residual_l1 = r.pw_diff;
-        z.l1_bound = c / (1.0 - c) * r.pw_diff + fabs(1.0 - r.fin_sum);
+        z.l1_bound = c / (1.0 - c) * r.pw_diff;
         z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
         if (timer.on) {
             const double sW = (double)sizeof(WT);

@@ -13,6 +13,7 @@ namespace prk {
 
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kMaxTrace = 4096;   // per-sweep trace entries kept on the device
+constexpr int kRedBlocks = 1024;  // max workgroups of a streaming kernel that feeds a reduction
 constexpr int kMPK = 8;           // merge-path items (rows + edges) per thread
 constexpr int kIPB = kBlock * kMPK;  // merge-path items per workgroup
 
@@ -125,7 +126,7 @@ template <typename T>
 hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
                           const uint32_t *rp_nn, double c, double xi, int ifp2, int stop_l1, double tol,
                           unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
-                          hipStream_t s);
+                          double *part, hipStream_t s);
 template <typename T>
 hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s);
 template <typename WT, typename OT>
@@ -136,13 +137,13 @@ hipError_t launch_phase2_prep(const InitArgs &a, const T *h, const double *pibar
                               int literal, double *w2, double *xD, hipStream_t s);
 template <typename T>
 hipError_t launch_final_ifp(Ctl *ctl, const InitArgs &a, const T *h, const double *pibar, const double *xD,
-                            int ifp2, int literal, double *out, hipStream_t s);
+                            int ifp2, int literal, double *out, double *part, hipStream_t s);
 // power method
 template <typename WT>
 hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, double *acc, WT *y,
-                                 const int32_t *deg, double c, double tol, hipStream_t s);
+                                 const int32_t *deg, double c, double tol, double *part, hipStream_t s);
 hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStream_t s);
-hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, hipStream_t s);
+hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, double *part, hipStream_t s);
 hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s);
 
 }  // namespace prk

@@ -65,17 +65,12 @@ __device__ __forceinline__ void store_agent(T *p, T v) {
     __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Signal completion of this workgroup; returns true in thread 0 of the last one.
-__device__ __forceinline__ bool last_block(uint32_t *counter) {
-    __shared__ int s_last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        uint32_t prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (prev == gridDim.x - 1);
-        if (s_last) __threadfence();
-    }
-    __syncthreads();
-    return s_last && threadIdx.x == 0;
+// Deterministic second stage of a two-stage reduction: one workgroup sums
+// nb per-workgroup partials in a fixed order.  Result valid in thread 0.
+__device__ __forceinline__ double reduce_partials(const double *part, int nb, double *sbuf) {
+    double s = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) s += part[b];
+    return block_sum(s, sbuf);
 }
 
 inline int grid_for(int64_t work, int per_thread, int cap) {
@@ -289,16 +284,14 @@ __global__ void k_init_ifp(InitArgs a, T *h, double *pibar) {
 
 // Reserve step of one sweep (the body of the calculation threads' loop):
 // every non-dangling i with h_i > xi moves its residual v into pibar_i and
-// publishes its push weight w_i = c v / deg(i); others publish 0.  The
-// reductions give the residual left on non-dangling vertices after this
-// sweep's pushes, the growth of the total mass, and the work; the last
-// workgroup takes the management decision (stop or continue, push or pull).
+// publishes its push weight w_i = c v / deg(i); others publish 0.  Per
+// workgroup partial sums: residual left on inactive vertices, mass this
+// sweep sends to non-dangling vertices, growth of the total mass, active
+// vertices and their valid edges.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w,
-                                                    double *pibar, const int32_t *deg, const uint32_t *rp_nn,
-                                                    double c, T xi, int ifp2, int stop_l1, double tol,
-                                                    unsigned long long pull_thr, int force,
-                                                    unsigned long long pull_edges) {
+__global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32_t nN, T *h, T *w, double *pibar,
+                                                    const int32_t *deg, const uint32_t *rp_nn, double c, T xi,
+                                                    int ifp2, double *part) {
     if (t > ctl->stop_after) return;
     double inact = 0.0, pred = 0.0, sxinc = 0.0;
     unsigned long long cnt = 0, edges = 0;
@@ -322,60 +315,68 @@ __global__ __launch_bounds__(kBlock) void k_reserve(int t, Ctl *ctl, Trace *tr, 
         }
     }
     __shared__ double sd[kBlock / W];
-    __shared__ unsigned long long su[kBlock / W];
     inact = block_sum(inact, sd);
     pred = block_sum(pred, sd);
     sxinc = block_sum(sxinc, sd);
-    cnt = block_sum(cnt, su);
-    edges = block_sum(edges, su);
+    double dc = block_sum((double)cnt, sd);
+    double de = block_sum((double)edges, sd);
     if (threadIdx.x == 0) {
-        if (inact != 0.0) atomic_add_f64(&ctl->acc[0], inact);
-        if (pred != 0.0) atomic_add_f64(&ctl->acc[1], pred);
-        if (sxinc != 0.0) atomic_add_f64(&ctl->acc[2], sxinc);
-        if (cnt) atomic_add_u64(&ctl->acc_cnt, cnt);
-        if (edges) atomic_add_u64(&ctl->acc_edges, edges);
+        const int nb = gridDim.x, b = blockIdx.x;
+        part[b] = inact;
+        part[nb + b] = pred;
+        part[2 * nb + b] = sxinc;
+        part[3 * nb + b] = dc;
+        part[4 * nb + b] = de;
     }
-    if (last_block(&ctl->bdone)) {
-        double a_in = load_agent(&ctl->acc[0]), a_pr = load_agent(&ctl->acc[1]), a_sx = load_agent(&ctl->acc[2]);
-        unsigned long long a_c = load_agent(&ctl->acc_cnt), a_e = load_agent(&ctl->acc_edges);
-        const double k = 2.0 * c / (1.0 - c);
-        if (a_c == 0) {
-            // nothing above the threshold: the state is unchanged, stop before this sweep's push
-            ctl->stop_after = t - 1;
-            ctl->last_bound = k * a_in / ctl->sx;
-            if (t < kMaxTrace) {
-                tr->cnt[t] = 0;
-                tr->edges[t] = 0;
-                tr->sn[t] = a_in;
-                tr->bound[t] = ctl->last_bound;
-            }
-        } else {
-            double sn = a_in + c * a_pr;
-            double sx = ctl->sx + c * a_sx;
-            double bound = k * sn / sx;
-            ctl->sx = sx;
-            ctl->sweeps = t + 1;
-            ctl->tot_pushes += a_c;
-            ctl->tot_edges += a_e;
-            int pull = force == 1 ? 0 : (force == 2 ? 1 : (a_e >= pull_thr ? 1 : 0));
-            ctl->use_pull = pull;
-            ctl->pull_sweeps += pull;
-            ctl->tot_traversed += pull ? pull_edges : a_e;
-            ctl->last_bound = bound;
-            if (stop_l1 && bound <= tol) ctl->stop_after = t;
-            if (t < kMaxTrace) {
-                tr->cnt[t] = a_c | ((unsigned long long)pull << 63);
-                tr->edges[t] = a_e;
-                tr->sn[t] = sn;
-                tr->bound[t] = bound;
-            }
+}
+
+// Management step of one sweep (one workgroup): sums the reserve partials and
+// decides -- stop (no vertex above the threshold, or the certified L1 bound
+// after this sweep's pushes is met), and push or pull for the scatter.
+__global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *tr, int nb, const double *part,
+                                                       double c, int stop_l1, double tol,
+                                                       unsigned long long pull_thr, int force,
+                                                       unsigned long long pull_edges) {
+    if (t > ctl->stop_after) return;
+    __shared__ double sd[kBlock / W];
+    const double a_in = reduce_partials(part, nb, sd);
+    const double a_pr = reduce_partials(part + nb, nb, sd);
+    const double a_sx = reduce_partials(part + 2 * nb, nb, sd);
+    const double a_cd = reduce_partials(part + 3 * nb, nb, sd);
+    const double a_ed = reduce_partials(part + 4 * nb, nb, sd);
+    if (threadIdx.x != 0) return;
+    const unsigned long long a_c = (unsigned long long)a_cd, a_e = (unsigned long long)a_ed;
+    const double k = 2.0 * c / (1.0 - c);
+    if (a_c == 0) {
+        // nothing above the threshold: the state is unchanged, stop before this sweep's scatter
+        ctl->stop_after = t - 1;
+        ctl->last_bound = k * a_in / ctl->sx;
+        if (t < kMaxTrace) {
+            tr->cnt[t] = 0;
+            tr->edges[t] = 0;
+            tr->sn[t] = a_in;
+            tr->bound[t] = ctl->last_bound;
         }
-        store_agent(&ctl->acc[0], 0.0);
-        store_agent(&ctl->acc[1], 0.0);
-        store_agent(&ctl->acc[2], 0.0);
-        store_agent(&ctl->acc_cnt, 0ull);
-        store_agent(&ctl->acc_edges, 0ull);
-        store_agent(&ctl->bdone, 0u);
+        return;
+    }
+    const double sn = a_in + c * a_pr;
+    const double sx = ctl->sx + c * a_sx;
+    const double bound = k * sn / sx;
+    ctl->sx = sx;
+    ctl->sweeps = t + 1;
+    ctl->tot_pushes += a_c;
+    ctl->tot_edges += a_e;
+    const int pull = force == 1 ? 0 : (force == 2 ? 1 : (a_e >= pull_thr ? 1 : 0));
+    ctl->use_pull = pull;
+    ctl->pull_sweeps += pull;
+    ctl->tot_traversed += pull ? pull_edges : a_e;
+    ctl->last_bound = bound;
+    if (stop_l1 && bound <= tol) ctl->stop_after = t;
+    if (t < kMaxTrace) {
+        tr->cnt[t] = a_c | ((unsigned long long)pull << 63);
+        tr->edges[t] = a_e;
+        tr->sn[t] = sn;
+        tr->bound[t] = bound;
     }
 }
 
@@ -433,10 +434,13 @@ __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int chec
     }
 }
 
-// Gather step (pull): out_j += sum over in-edges u -> j of w_u, without
-// atomics except for rows split between threads.  Same merge-path tiling as the
-// push; the in-edge source ids are staged in LDS, the w_u are gathered from
-// global memory, sums are carried in FP64.
+// Gather step (pull): out_j += sum over in-edges u -> j of w_u, without global
+// atomics except for the first and last row of a tile.  Same merge-path tiling
+// as the push; the in-edge source ids are staged in LDS, the w_u are gathered
+// from global memory, sums are carried in FP64.  A row finished by one thread
+// is written directly; pieces of rows shared by several threads meet in an
+// LDS accumulator (hardware LDS FP64 add), so a hub row costs one global
+// atomic per tile instead of one per thread.
 template <typename WT, typename OT>
 __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
                                                  int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
@@ -444,6 +448,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
     if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
     __shared__ uint32_t s_end[kIPB + 1];
     __shared__ int32_t s_src[kIPB];
+    __shared__ double s_acc[kIPB + 1];
     __shared__ uint32_t s_first;
     const uint2 a = plan[blockIdx.x], b = plan[blockIdx.x + 1];
     const int32_t i0 = (int32_t)a.x;
@@ -455,43 +460,57 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
     for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
         int32_t r = i0 + k;
         s_end[k] = rp[r + 1] - rp0 + (uint32_t)r;
+        s_acc[k] = 0.0;
     }
     for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) s_src[e - e0] = src[e];
     __syncthreads();
     uint32_t d = min((uint32_t)(blockIdx.x * kIPB + threadIdx.x * kMPK), items);
     const uint32_t dend = min(d + (uint32_t)kMPK, items);
-    if (d >= dend) return;
-    int32_t lo = 0, hi = nr;
-    while (lo < hi) {
-        int32_t mid = (lo + hi) >> 1;
-        if (s_end[mid] < d) lo = mid + 1;
-        else hi = mid;
-    }
-    int32_t k = lo;
-    uint32_t et = rp0 + d - (uint32_t)(i0 + k);
-    // first edge of row i0 + k
-    uint32_t row_first = k == 0 ? s_first : s_end[k - 1] + rp0 + 1u - (uint32_t)(i0 + k);
-    bool owned = et == row_first;
-    bool touched = false;
-    double acc = 0.0;
-    for (; d < dend; ++d) {
-        if (d == s_end[k]) {
-            if (touched) {
-                OT *o = out + (i0 + k);
-                if (owned) *o = (OT)((double)*o + acc);
-                else atomicAdd(o, (OT)acc);
-            }
-            acc = 0.0;
-            touched = false;
-            owned = true;
-            ++k;
-        } else {
-            acc += (double)w[s_src[et - e0]];
-            touched = true;
-            ++et;
+    if (d < dend) {
+        int32_t lo = 0, hi = nr;
+        while (lo < hi) {
+            int32_t mid = (lo + hi) >> 1;
+            if (s_end[mid] < d) lo = mid + 1;
+            else hi = mid;
         }
+        int32_t k = lo;
+        uint32_t et = rp0 + d - (uint32_t)(i0 + k);
+        // first edge of row i0 + k
+        uint32_t row_first = k == 0 ? s_first : s_end[k - 1] + rp0 + 1u - (uint32_t)(i0 + k);
+        bool owned = et == row_first;
+        bool touched = false;
+        double acc = 0.0;
+        for (; d < dend; ++d) {
+            if (d == s_end[k]) {
+                if (touched) {
+                    if (owned) {
+                        OT *o = out + (i0 + k);
+                        *o = (OT)((double)*o + acc);
+                    } else {
+                        atomicAdd(s_acc + k, acc);
+                    }
+                }
+                acc = 0.0;
+                touched = false;
+                owned = true;
+                ++k;
+            } else {
+                acc += (double)w[s_src[et - e0]];
+                touched = true;
+                ++et;
+            }
+        }
+        if (touched) atomicAdd(s_acc + k, acc);
     }
-    if (touched) atomicAdd(out + (i0 + k), (OT)acc);
+    __syncthreads();
+    // rows strictly inside the tile belong to this workgroup alone
+    for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
+        double v = s_acc[k];
+        if (v == 0.0) continue;
+        OT *o = out + (i0 + k);
+        if (k == 0 || k == nr - 1) atomicAdd(o, (OT)v);
+        else *o = (OT)((double)*o + v);
+    }
 }
 
 // IFP2 phase 2 inputs: w2_u = c z_u / deg(u) for non-dangling u, and the
@@ -517,8 +536,8 @@ __device__ __forceinline__ double x_ifp(const InitArgs &a, const T *h, const dou
 }
 
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_final_sum(Ctl *ctl, InitArgs a, const T *h, const double *pibar,
-                                                      const double *xD, int ifp2, int literal) {
+__global__ __launch_bounds__(kBlock) void k_final_sum(InitArgs a, const T *h, const double *pibar,
+                                                      const double *xD, int ifp2, int literal, double *part) {
     double s = 0.0, sn = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
         s += x_ifp(a, h, pibar, xD, ifp2, literal, i);
@@ -528,15 +547,19 @@ __global__ __launch_bounds__(kBlock) void k_final_sum(Ctl *ctl, InitArgs a, cons
     s = block_sum(s, sd);
     sn = block_sum(sn, sd);
     if (threadIdx.x == 0) {
-        atomic_add_f64(&ctl->acc[0], s);
-        atomic_add_f64(&ctl->acc[1], sn);
+        part[blockIdx.x] = s;
+        part[gridDim.x + blockIdx.x] = sn;
     }
-    if (last_block(&ctl->fdone)) {
-        ctl->fin_sum = load_agent(&ctl->acc[0]);
-        ctl->fin_sn = load_agent(&ctl->acc[1]);
-        store_agent(&ctl->acc[0], 0.0);
-        store_agent(&ctl->acc[1], 0.0);
-        store_agent(&ctl->fdone, 0u);
+}
+
+// fin_sum = part[0..nb), fin_sn = part[nb..2nb)
+__global__ __launch_bounds__(kBlock) void k_final_decide(Ctl *ctl, int nb, const double *part) {
+    __shared__ double sd[kBlock / W];
+    const double s = reduce_partials(part, nb, sd);
+    const double sn = reduce_partials(part + nb, nb, sd);
+    if (threadIdx.x == 0) {
+        ctl->fin_sum = s;
+        ctl->fin_sn = sn;
     }
 }
 
@@ -568,8 +591,8 @@ __global__ void k_power_init(InitArgs a, double *x, double *acc) {
 // non-dangling vertices, the dangling mass and total mass for b_t; acc cleared
 // for the gather that follows.
 template <typename WT>
-__global__ __launch_bounds__(kBlock) void k_power_prescale(int t, Ctl *ctl, InitArgs a, double *x, double *acc,
-                                                           WT *y, const int32_t *deg, double c, double tol) {
+__global__ __launch_bounds__(kBlock) void k_power_prescale(int t, const Ctl *ctl, InitArgs a, double *x, double *acc,
+                                                           WT *y, const int32_t *deg, double c, double *part) {
     if (t > ctl->stop_after) return;
     const double b = ctl->pw_b;
     double diff = 0.0, dsum = 0.0, xsum = 0.0;
@@ -591,37 +614,39 @@ __global__ __launch_bounds__(kBlock) void k_power_prescale(int t, Ctl *ctl, Init
     dsum = block_sum(dsum, sd);
     xsum = block_sum(xsum, sd);
     if (threadIdx.x == 0) {
-        atomic_add_f64(&ctl->acc[0], diff);
-        atomic_add_f64(&ctl->acc[1], dsum);
-        atomic_add_f64(&ctl->acc[2], xsum);
-    }
-    if (last_block(&ctl->bdone)) {
-        double df = load_agent(&ctl->acc[0]), ds = load_agent(&ctl->acc[1]), xs = load_agent(&ctl->acc[2]);
-        ctl->pw_b = c * ds + (1.0 - c) * xs;
-        if (t > 0) {
-            ctl->pw_diff = df;
-            ctl->sweeps = t;
-            ctl->last_bound = c / (1.0 - c) * df;
-            if (ctl->last_bound <= tol) ctl->stop_after = t - 1;  // x_t is the answer: skip the gather
-        }
-        store_agent(&ctl->acc[0], 0.0);
-        store_agent(&ctl->acc[1], 0.0);
-        store_agent(&ctl->acc[2], 0.0);
-        store_agent(&ctl->bdone, 0u);
+        part[blockIdx.x] = diff;
+        part[gridDim.x + blockIdx.x] = dsum;
+        part[2 * gridDim.x + blockIdx.x] = xsum;
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_final_x_sum(Ctl *ctl, int64_t n, const double *x) {
+// jump weight b_t = c d^T x_t + (1 - c) e^T x_t for the next iterate; stop when
+// c / (1 - c) ||x_t - x_{t-1}||_1 <= tol (x_t is then the answer: skip the gather)
+__global__ __launch_bounds__(kBlock) void k_decide_power(int t, Ctl *ctl, int nb, const double *part, double c,
+                                                         double tol) {
+    if (t > ctl->stop_after) return;
+    __shared__ double sd[kBlock / W];
+    const double df = reduce_partials(part, nb, sd);
+    const double ds = reduce_partials(part + nb, nb, sd);
+    const double xs = reduce_partials(part + 2 * nb, nb, sd);
+    if (threadIdx.x != 0) return;
+    ctl->pw_b = c * ds + (1.0 - c) * xs;
+    if (t > 0) {
+        ctl->pw_diff = df;
+        ctl->sweeps = t;
+        ctl->last_bound = c / (1.0 - c) * df;
+        if (ctl->last_bound <= tol) ctl->stop_after = t - 1;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_final_x_sum(int64_t n, const double *x, double *part) {
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) s += x[i];
     __shared__ double sd[kBlock / W];
     s = block_sum(s, sd);
-    if (threadIdx.x == 0) atomic_add_f64(&ctl->acc[0], s);
-    if (last_block(&ctl->fdone)) {
-        ctl->fin_sum = load_agent(&ctl->acc[0]);
-        ctl->fin_sn = 0.0;
-        store_agent(&ctl->acc[0], 0.0);
-        store_agent(&ctl->fdone, 0u);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = s;
+        part[gridDim.x + blockIdx.x] = 0.0;
     }
 }
 
@@ -725,9 +750,13 @@ template <typename T>
 hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
                           const uint32_t *rp_nn, double c, double xi, int ifp2, int stop_l1, double tol,
                           unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
-                          hipStream_t s) {
-    PRK_LAUNCH(k_reserve<T>, grid_for(nN, 4, 2048), t, ctl, tr, nN, h, w, pibar, deg, rp_nn, c, (T)xi, ifp2,
-               stop_l1, tol, pull_edges_thr, force, pull_edges);
+                          double *part, hipStream_t s) {
+    const int nb = grid_for(nN, 4, kRedBlocks);
+    hipLaunchKernelGGL(k_reserve<T>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, w, pibar, deg, rp_nn,
+                       c, (T)xi, ifp2, part);
+    hipLaunchKernelGGL(k_decide_ifp, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, nb, (const double *)part, c, stop_l1,
+                       tol, pull_edges_thr, force, pull_edges);
+    return hipGetLastError();
 }
 
 template <typename T>
@@ -754,9 +783,10 @@ hipError_t launch_phase2_prep(const InitArgs &a, const T *h, const double *pibar
 
 template <typename T>
 hipError_t launch_final_ifp(Ctl *ctl, const InitArgs &a, const T *h, const double *pibar, const double *xD,
-                            int ifp2, int literal, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_final_sum<T>, dim3(grid_for(a.n, 4, 2048)), dim3(kBlock), 0, s, ctl, a, h, pibar, xD, ifp2,
-                       literal);
+                            int ifp2, int literal, double *out, double *part, hipStream_t s) {
+    const int nb = grid_for(a.n, 4, kRedBlocks);
+    hipLaunchKernelGGL(k_final_sum<T>, dim3(nb), dim3(kBlock), 0, s, a, h, pibar, xD, ifp2, literal, part);
+    hipLaunchKernelGGL(k_final_decide, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
     hipLaunchKernelGGL(k_final_write<T>, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, h,
                        pibar, xD, ifp2, literal, out);
     return hipGetLastError();
@@ -768,12 +798,18 @@ hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStrea
 
 template <typename WT>
 hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, double *acc, WT *y,
-                                 const int32_t *deg, double c, double tol, hipStream_t s) {
-    PRK_LAUNCH(k_power_prescale<WT>, grid_for(a.n, 4, 2048), t, ctl, a, x, acc, y, deg, c, tol);
+                                 const int32_t *deg, double c, double tol, double *part, hipStream_t s) {
+    const int nb = grid_for(a.n, 4, kRedBlocks);
+    hipLaunchKernelGGL(k_power_prescale<WT>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, a, x, acc, y, deg, c,
+                       part);
+    hipLaunchKernelGGL(k_decide_power, dim3(1), dim3(kBlock), 0, s, t, ctl, nb, (const double *)part, c, tol);
+    return hipGetLastError();
 }
 
-hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, hipStream_t s) {
-    hipLaunchKernelGGL(k_final_x_sum, dim3(grid_for(a.n, 4, 2048)), dim3(kBlock), 0, s, ctl, a.n, x);
+hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, double *part, hipStream_t s) {
+    const int nb = grid_for(a.n, 4, kRedBlocks);
+    hipLaunchKernelGGL(k_final_x_sum, dim3(nb), dim3(kBlock), 0, s, a.n, x, part);
+    hipLaunchKernelGGL(k_final_decide, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
     hipLaunchKernelGGL(k_final_x_write, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, x,
                        out);
     return hipGetLastError();
@@ -788,10 +824,10 @@ template hipError_t launch_init_ifp<float>(const InitArgs &, float *, double *, 
 template hipError_t launch_init_ifp<double>(const InitArgs &, double *, double *, hipStream_t);
 template hipError_t launch_reserve<float>(int, Ctl *, Trace *, int32_t, float *, float *, double *, const int32_t *,
                                           const uint32_t *, double, double, int, int, double, unsigned long long,
-                                          int, unsigned long long, hipStream_t);
+                                          int, unsigned long long, double *, hipStream_t);
 template hipError_t launch_reserve<double>(int, Ctl *, Trace *, int32_t, double *, double *, double *,
                                            const int32_t *, const uint32_t *, double, double, int, int, double,
-                                           unsigned long long, int, unsigned long long, hipStream_t);
+                                           unsigned long long, int, unsigned long long, double *, hipStream_t);
 template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t);
 template hipError_t launch_push<double>(int, const Ctl *, const MPPlan &, const double *, double *, int,
                                         hipStream_t);
@@ -806,12 +842,12 @@ template hipError_t launch_phase2_prep<float>(const InitArgs &, const float *, c
 template hipError_t launch_phase2_prep<double>(const InitArgs &, const double *, const double *, const int32_t *,
                                                double, int, double *, double *, hipStream_t);
 template hipError_t launch_final_ifp<float>(Ctl *, const InitArgs &, const float *, const double *, const double *,
-                                            int, int, double *, hipStream_t);
+                                            int, int, double *, double *, hipStream_t);
 template hipError_t launch_final_ifp<double>(Ctl *, const InitArgs &, const double *, const double *,
-                                             const double *, int, int, double *, hipStream_t);
+                                             const double *, int, int, double *, double *, hipStream_t);
 template hipError_t launch_power_prescale<float>(int, Ctl *, const InitArgs &, double *, double *, float *,
-                                                 const int32_t *, double, double, hipStream_t);
+                                                 const int32_t *, double, double, double *, hipStream_t);
 template hipError_t launch_power_prescale<double>(int, Ctl *, const InitArgs &, double *, double *, double *,
-                                                  const int32_t *, double, double, hipStream_t);
+                                                  const int32_t *, double, double, double *, hipStream_t);
 
 }  // namespace prk

@@ -69,7 +69,8 @@ def test_closed_forms(pr, name, g, expect, method):
     dg = pr.upload(g.row_ptr, g.col)
     for mode in ([None, "push", "pull"] if method != "power" else [None]):
         if method == "power":
-            pi, st = pr.power(dg, c=C, l1_tol=1e-13)
+            # 1e-12: below that the order of the FP64 atomic adds into a hub row is visible in ||x' - x||
+            pi, st = pr.power(dg, c=C, l1_tol=1e-12)
         else:
             pi, st = getattr(pr, method)(dg, c=C, xi=1e-15, mode=mode)
         assert st["status"] == 0
@@ -91,7 +92,7 @@ def test_exact_fixtures(pr, case):
         for res, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
             pi, st = fn(dg, p=p, c=c, xi=1e-15 if res == "fp64" else 1e-9, residual=res)
             assert l1(pi, ref) <= tol
-    pi, st = pr.power(dg, p=p, c=c, l1_tol=1e-13)
+    pi, st = pr.power(dg, p=p, c=c, l1_tol=1e-12)
     assert l1(pi, ref) <= 1e-12
 
 
