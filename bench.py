@@ -68,6 +68,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--scale", type=int, default=22)
+    ap.add_argument("--workload", default="rmat", choices=["rmat", "dag"],
+                    help="rmat: the R-MAT scale-22 workload (the bench line); dag: the layered-DAG workload")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--mode", default=None, choices=[None, "push", "pull"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -85,9 +87,17 @@ def main():
     import prgen
 
     c = 0.85
-    log(f"[bench] generating R-MAT scale {args.scale}")
     t0 = time.perf_counter()
-    g = prgen.workload_rmat(scale=args.scale, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=0)
+    if args.workload == "rmat":
+        log(f"[bench] generating R-MAT scale {args.scale}")
+        g = prgen.workload_rmat(scale=args.scale, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=0)
+        wl_name = f"R-MAT scale {args.scale}, edge factor 16, 15% dangling, 10% unreferenced, seed 0"
+        wl_key = f"rmat{args.scale}"
+    else:
+        log("[bench] generating the layered DAG (2^23 vertices, 64 layers, 80M Zipf edges + 2% back edges)")
+        g = prgen.workload_dag()
+        wl_name = "layered DAG: 2^23 vertices in 64 layers, Zipf(2.0) out-degrees capped at 10^4, 80M forward + 2% back edges, seed 0"
+        wl_key = "dag23"
     log(f"[bench] n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f}s")
     dg = pr.upload(g.row_ptr, g.col)
     info = dg.info()
@@ -125,14 +135,18 @@ def main():
     launches = sum(s[f"{kern}_launches"] for s in st_ifp2)
     kbytes = sum(s[f"{kern}_bytes"] for s in st_ifp2)
     achieved = kbytes / secs / 1e9 if secs > 0 else 0.0
-    workload = f"rmat{args.scale}"
-    traffic = traffic_from_profiles(kern, workload)
+    traffic = traffic_from_profiles(kern, wl_key)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": f"k_{kern}<float>",
                 "launches": launches, "avg_launch_us": secs / max(launches, 1) * 1e6,
                 "algorithmic_bytes_per_launch": kbytes / max(launches, 1)}
 
     last = st_ifp2[-1]
+    trace = pr.last_trace()
+    log("[bench] IFP2 sweeps: active edges / residual")
+    for t in range(len(trace["active"])):
+        log(f"  sweep {t:3d} active {trace['active'][t]:9d} edges {trace['edges'][t]:10d} "
+            f"residual {trace['residual'][t]:.3e} bound {trace['bound'][t]:.3e} pull {trace['pulled'][t]}")
     res = {
         "metric": "GTEPS + HBM GB/s, IFP2 vs power method at L1<=1e-6; batched/served p50/p99",
         "value": g.m / t_ifp2 / 1e9,
@@ -146,7 +160,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"R-MAT scale {args.scale}, edge factor 16, 15% dangling, 10% unreferenced, seed 0",
+        "config": {"workload": wl_name,
                    "n": g.n, "m": g.m, "n_dangling": info["n_dangling"], "m_dangling": info["m_dangling"],
                    "n_unreferenced": info["n_unreferenced"], "c": c, "l1_tol": args.tol,
                    "residual": "fp32 residual, fp64 reserve and reductions", "stop": "certified L1"},

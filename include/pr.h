@@ -187,6 +187,19 @@ pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_
 /* Message describing the last error on this thread ("" if none). */
 const char *pr_last_error(void);
 
+/*
+ * Per-sweep record of this thread's last IFP1 / IFP2 / PPR solve run with
+ * PR_PROFILE (the quantities of the convergence analysis, section 3.3):
+ * active[t] = vertices that pushed in sweep t, edges[t] = their valid
+ * out-edges, residual[t] = residual left on non-dangling vertices after the
+ * sweep, bound[t] = certified L1 bound after the sweep, pulled[t] = 1 if the
+ * sweep gathered along in-edges.  Writes min(cap, sweeps) entries of every
+ * non-NULL array (caller-owned) and returns the number of recorded sweeps
+ * (0 when the last solve was not profiled).
+ */
+int32_t pr_last_trace(int32_t cap, int64_t *active, int64_t *edges, double *residual, double *bound,
+                      int32_t *pulled);
+
 #ifdef __cplusplus
 }
 #endif

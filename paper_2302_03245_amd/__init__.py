@@ -28,7 +28,7 @@ PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE = 0x8, 0x10, 0x20
 
 # every symbol the two public headers declare
 EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_info", "pr_solve_ifp1",
-            "pr_solve_ifp2", "pr_solve_power", "pr_ppr", "pr_last_error",
+            "pr_solve_ifp2", "pr_solve_power", "pr_ppr", "pr_last_error", "pr_last_trace",
             "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len"]
 
 
@@ -101,6 +101,8 @@ def lib():
     L.pr_ppr.restype = ctypes.c_int
     L.pr_last_error.argtypes = []
     L.pr_last_error.restype = ctypes.c_char_p
+    L.pr_last_trace.argtypes = [i32, vp, vp, vp, vp, vp]
+    L.pr_last_trace.restype = i32
     L.pr_probe_copy.argtypes = [vp, vp, i64, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double)]
     L.pr_probe_copy.restype = ctypes.c_int
     L.pr_probe_gather.argtypes = [vp, vp, i64, vp, i64, ctypes.c_int, vp, ctypes.POINTER(ctypes.c_double)]
@@ -272,6 +274,19 @@ def power(g: Graph, p=None, c=0.85, l1_tol=1e-9, residual="fp64", max_sweeps=0, 
     """Power method on P'' until the certified L1 error is <= l1_tol."""
     o = _opts(c, None, l1_tol, residual, max_sweeps, stream, False, None, profile, power=True)
     return _solve(lib().pr_solve_power, g, p, o, out)
+
+
+def last_trace() -> dict:
+    """Per-sweep record of this thread's last profiled IFP solve (see pr_last_trace)."""
+    L = lib()
+    n = L.pr_last_trace(0, None, None, None, None, None)
+    active, edges = np.zeros(n, np.int64), np.zeros(n, np.int64)
+    residual, bound = np.zeros(n), np.zeros(n)
+    pulled = np.zeros(n, np.int32)
+    if n:
+        L.pr_last_trace(n, active.ctypes.data, edges.ctypes.data, residual.ctypes.data, bound.ctypes.data,
+                        pulled.ctypes.data)
+    return {"active": active, "edges": edges, "residual": residual, "bound": bound, "pulled": pulled}
 
 
 def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, stream=None):

@@ -26,6 +26,14 @@ namespace {
 
 thread_local std::string g_err;
 
+// per-sweep record of the calling thread's last PR_PROFILE solve
+struct TraceRec {
+    std::vector<int64_t> active, edges;
+    std::vector<double> residual, bound;
+    std::vector<int32_t> pulled;
+};
+thread_local TraceRec g_trace;
+
 pr_status fail(pr_status st, const std::string &msg) {
     g_err = msg;
     return st;
@@ -593,9 +601,20 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         if (timer.on) {
             std::vector<unsigned long long> trc((size_t)std::min(r.sweeps + 1, kMaxTrace));
             std::vector<unsigned long long> tre(trc.size());
+            std::vector<double> trs(trc.size()), trb(trc.size());
             if (!trc.empty()) {
                 HIPCHK(hipMemcpy(trc.data(), tr->cnt, sizeof(unsigned long long) * trc.size(), hipMemcpyDeviceToHost));
                 HIPCHK(hipMemcpy(tre.data(), tr->edges, sizeof(unsigned long long) * tre.size(), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(trs.data(), tr->sn, sizeof(double) * trs.size(), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(trb.data(), tr->bound, sizeof(double) * trb.size(), hipMemcpyDeviceToHost));
+            }
+            g_trace = TraceRec();
+            for (size_t i = 0; i < trc.size() && (int)i < r.sweeps; ++i) {
+                g_trace.active.push_back((int64_t)(trc[i] & ~(1ull << 63)));
+                g_trace.pulled.push_back((int32_t)(trc[i] >> 63));
+                g_trace.edges.push_back((int64_t)tre[i]);
+                g_trace.residual.push_back(trs[i]);
+                g_trace.bound.push_back(trb[i]);
             }
             const double sT = (double)sizeof(T);
             for (size_t i = 0; i < timer.ev.size(); ++i) {
@@ -752,6 +771,20 @@ void pr_opts_default(pr_opts *o) {
 }
 
 const char *pr_last_error(void) { return g_err.c_str(); }
+
+int32_t pr_last_trace(int32_t cap, int64_t *active, int64_t *edges, double *residual, double *bound,
+                      int32_t *pulled) {
+    const int32_t n = (int32_t)g_trace.active.size();
+    const int32_t k = std::min(n, std::max<int32_t>(cap, 0));
+    for (int32_t i = 0; i < k; ++i) {
+        if (active) active[i] = g_trace.active[i];
+        if (edges) edges[i] = g_trace.edges[i];
+        if (residual) residual[i] = g_trace.residual[i];
+        if (bound) bound[i] = g_trace.bound[i];
+        if (pulled) pulled[i] = g_trace.pulled[i];
+    }
+    return n;
+}
 
 pr_status pr_graph_upload(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
                           pr_graph **out) {

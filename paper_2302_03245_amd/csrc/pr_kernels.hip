@@ -409,7 +409,19 @@ __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int chec
     }
     any = __syncthreads_or(any);
     if (!any) return;
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) s_col[e - e0] = col[e];
+    {
+        const int32_t ne = (int32_t)(e1 - e0);
+        if (ne > 0) {
+            int32_t cv[kMPK];
+#pragma unroll
+            for (int j = 0; j < kMPK; ++j) cv[j] = col[e0 + min((int32_t)threadIdx.x + j * kBlock, ne - 1)];
+#pragma unroll
+            for (int j = 0; j < kMPK; ++j) {
+                const int32_t e = threadIdx.x + j * kBlock;
+                if (e < ne) s_col[e] = cv[j];
+            }
+        }
+    }
     __syncthreads();
     uint32_t d = min((uint32_t)(blockIdx.x * kIPB + threadIdx.x * kMPK), items);
     const uint32_t dend = min(d + (uint32_t)kMPK, items);
@@ -436,8 +448,9 @@ __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int chec
 
 // Gather step (pull): out_j += sum over in-edges u -> j of w_u, without global
 // atomics except for the first and last row of a tile.  Same merge-path tiling
-// as the push; the in-edge source ids are staged in LDS, the w_u are gathered
-// from global memory, sums are carried in FP64.  A row finished by one thread
+// as the push; all w_u of the tile's in-edges are first gathered into LDS in
+// one parallel pass, then each thread walks its rows + edges from LDS, with
+// sums carried in FP64.  A row finished by one thread
 // is written directly; pieces of rows shared by several threads meet in an
 // LDS accumulator (hardware LDS FP64 add), so a hub row costs one global
 // atomic per tile instead of one per thread.
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
                                                  const WT *w, OT *out) {
     if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
     __shared__ uint32_t s_end[kIPB + 1];
-    __shared__ int32_t s_src[kIPB];
+    __shared__ WT s_val[kIPB];
     __shared__ double s_acc[kIPB + 1];
     __shared__ uint32_t s_first;
     const uint2 a = plan[blockIdx.x], b = plan[blockIdx.x + 1];
@@ -457,12 +470,37 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
     const uint32_t rp0 = rp[0];
     const int32_t nr = i1 - i0 + 1;
     if (threadIdx.x == 0) s_first = rp[i0];
-    for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
-        int32_t r = i0 + k;
-        s_end[k] = rp[r + 1] - rp0 + (uint32_t)r;
-        s_acc[k] = 0.0;
+    {
+        // nr <= kIPB + 1 rows: kMPK + 1 unconditional (clamped) loads per thread
+        uint32_t rv[kMPK + 1];
+#pragma unroll
+        for (int j = 0; j <= kMPK; ++j) rv[j] = rp[i0 + 1 + min((int32_t)threadIdx.x + j * kBlock, nr - 1)];
+#pragma unroll
+        for (int j = 0; j <= kMPK; ++j) {
+            const int32_t k = threadIdx.x + j * kBlock;
+            if (k < nr) {
+                s_end[k] = rv[j] - rp0 + (uint32_t)(i0 + k);
+                s_acc[k] = 0.0;
+            }
+        }
     }
-    for (uint32_t e = e0 + threadIdx.x; e < e1; e += kBlock) s_src[e - e0] = src[e];
+    // gather phase: every in-edge of the tile at once.  Indices are clamped so
+    // that all loads are unconditional and issue back to back: kMPK coalesced
+    // source-id loads, then kMPK independent weight loads in flight per thread.
+    const int32_t ne = (int32_t)(e1 - e0);
+    if (ne > 0) {
+        int32_t sidx[kMPK];
+        WT v[kMPK];
+#pragma unroll
+        for (int j = 0; j < kMPK; ++j) sidx[j] = src[e0 + min((int32_t)threadIdx.x + j * kBlock, ne - 1)];
+#pragma unroll
+        for (int j = 0; j < kMPK; ++j) v[j] = w[sidx[j]];
+#pragma unroll
+        for (int j = 0; j < kMPK; ++j) {
+            const int32_t e = threadIdx.x + j * kBlock;
+            if (e < ne) s_val[e] = v[j];
+        }
+    }
     __syncthreads();
     uint32_t d = min((uint32_t)(blockIdx.x * kIPB + threadIdx.x * kMPK), items);
     const uint32_t dend = min(d + (uint32_t)kMPK, items);
@@ -495,7 +533,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
                 owned = true;
                 ++k;
             } else {
-                acc += (double)w[s_src[et - e0]];
+                acc += (double)s_val[et - e0];
                 touched = true;
                 ++et;
             }

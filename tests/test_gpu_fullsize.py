@@ -1,0 +1,76 @@
+"""Parity at the full workload sizes, in the configuration bench.py times.
+
+* R-MAT scale 22 (4,194,304 vertices, 16 * 2^22 draws, 15 % dangling, 10 %
+  unreferenced): IFP1 / IFP2 / power with FP32 residuals and the certified
+  L1 <= 1e-6 stop, and IFP2 with FP64 residuals at L1 <= 1e-9.
+* Layered DAG (2^23 vertices, 64 layers, 80M Zipf edges + 2 % back edges):
+  the same FP32 configuration.
+Reference: the FP64 power-method oracle over the whole graph (tens of seconds
+of one host core).  Every GPU result is compared element by element (L1), by
+its top-1000 ranking (tie rule of conftest.topk_agree), and by the
+PageRank-equation residual ||pi - cP pi - gamma p||_1, gamma = 1 - c + c d^T pi.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+import oracle
+import prgen
+from conftest import l1, topk_agree
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+C = 0.85
+
+
+def _eq_residual(g, pi):
+    deg = np.diff(g.row_ptr)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    inv = np.zeros(g.n)
+    inv[deg > 0] = 1.0 / deg[deg > 0]
+    P = sp.csr_matrix((inv[src], (g.col, src)), shape=(g.n, g.n))
+    gamma = 1 - C + C * pi[deg == 0].sum()
+    return float(np.abs(pi - C * (P @ pi) - gamma / g.n).sum())
+
+
+def _check(pr, g, ref, fp64_too):
+    dg = pr.upload(g.row_ptr, g.col)
+    runs = [("ifp2", lambda: pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6),
+            ("ifp1", lambda: pr.ifp1(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6),
+            ("power", lambda: pr.power(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6)]
+    if fp64_too:
+        runs.append(("ifp2_fp64", lambda: pr.ifp2(dg, c=C, l1_tol=1e-9), 1e-9))
+    for name, run, tol in runs:
+        pi, st = run()
+        err = l1(pi, ref)
+        ok, swaps, eps = topk_agree(ref, pi, 1000)
+        print(f"{g.name} {name}: sweeps {st['sweeps']} L1 {err:.3e} bound {st['l1_bound']:.3e} "
+              f"top-1000 swaps {swaps} eps_inf {eps:.2e}", flush=True)
+        assert st["status"] == 0 and st["l1_bound"] <= tol
+        assert err <= tol
+        assert ok
+        assert abs(pi.sum() - 1.0) < 1e-10
+        assert _eq_residual(g, pi) <= 2 * tol
+    dg.free()
+
+
+def test_rmat_scale22(pr_lib):
+    g = prgen.workload_rmat(scale=22, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=0)
+    print(f"R-MAT scale 22: n={g.n} m={g.m}", flush=True)
+    ref, it, delta = oracle.power(g, C, tol=1e-13)
+    print(f"oracle power: {it} iterations, delta {delta:.2e}", flush=True)
+    _check(pr_lib, g, ref, fp64_too=True)
+
+
+def test_layered_dag(pr_lib):
+    g = prgen.workload_dag()
+    print(f"layered DAG: n={g.n} m={g.m} lambda={g.meta['lambda']:.4f}", flush=True)
+    ref, it, delta = oracle.power(g, C, tol=1e-12)
+    print(f"oracle power: {it} iterations, delta {delta:.2e}", flush=True)
+    _check(pr_lib, g, ref, fp64_too=False)
+
+
+@pytest.fixture(scope="module")
+def pr_lib():
+    import paper_2302_03245_amd as pr
+    pr.lib()
+    return pr
