@@ -53,6 +53,7 @@ def _check(pr, g, ref, fp64_too):
     dg.free()
 
 
+@pytest.mark.timeout(300)
 def test_rmat_scale22(pr_lib):
     g = prgen.workload_rmat(scale=22, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=0)
     print(f"R-MAT scale 22: n={g.n} m={g.m}", flush=True)
@@ -61,10 +62,11 @@ def test_rmat_scale22(pr_lib):
     _check(pr_lib, g, ref, fp64_too=True)
 
 
+@pytest.mark.timeout(400)
 def test_layered_dag(pr_lib):
     g = prgen.workload_dag()
     print(f"layered DAG: n={g.n} m={g.m} lambda={g.meta['lambda']:.4f}", flush=True)
-    ref, it, delta = oracle.power(g, C, tol=1e-12)
+    ref, it, delta = oracle.power(g, C, tol=1e-11)
     print(f"oracle power: {it} iterations, delta {delta:.2e}", flush=True)
     _check(pr_lib, g, ref, fp64_too=False)
 
