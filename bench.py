@@ -72,6 +72,7 @@ def main():
                     help="rmat: the R-MAT scale-22 workload (the bench line); dag: the layered-DAG workload")
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--mode", default=None, choices=[None, "push", "pull"])
+    ap.add_argument("--tile-shift", type=int, default=0, help="sweep tile = 256 << s items (s in 2..4; 0 default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="also run the copy / gather / scatter probes")
     args = ap.parse_args()
@@ -99,7 +100,7 @@ def main():
         wl_name = "layered DAG: 2^23 vertices in 64 layers, Zipf(2.0) out-degrees capped at 10^4, 80M forward + 2% back edges, seed 0"
         wl_key = "dag23"
     log(f"[bench] n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f}s")
-    dg = pr.upload(g.row_ptr, g.col)
+    dg = pr.upload(g.row_ptr, g.col, tile_shift=args.tile_shift)
     info = dg.info()
     log(f"[bench] uploaded: {info}")
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")

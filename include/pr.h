@@ -57,6 +57,10 @@ typedef enum {
 /* pr_graph_upload flags */
 #define PR_INPUT_DEVICE 0x1u /* row_ptr and col are device pointers */
 #define PR_DEDUPE 0x2u       /* collapse repeated edges (the 0/1 adjacency matrix of section 2.1) */
+/* sweep tile size: each workgroup of 256 threads takes 256 << s rows + edges per tile,
+   s in {2, 3, 4}; 0 selects the default (s = 3) */
+#define PR_TILE_SHIFT(s) (((uint32_t)(s) & 0x7u) << 8)
+#define PR_TILE_MASK 0x700u
 
 /* pr_opts.flags */
 #define PR_P_DEVICE 0x1u     /* p is a device pointer (double[n]) */

@@ -182,15 +182,17 @@ class Graph:
             pass
 
 
-def upload(row_ptr, col, dedupe: bool = False) -> Graph:
-    """Copy a CSR graph (host numpy or device torch tensors) to the device."""
+def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0) -> Graph:
+    """Copy a CSR graph (host numpy or device torch tensors) to the device.
+
+    `tile_shift` s in {2, 3, 4} sets 256 << s rows + edges per sweep tile (0: default)."""
     rp_keep, rp_ptr, rp_dev = _ptr_any(row_ptr, np.int64, "int64")
     col_keep, col_ptr, col_dev = _ptr_any(col, np.int32, "int32")
     if rp_dev != col_dev:
         raise ValueError("row_ptr and col must both be host or both be device buffers")
     n = (rp_keep.shape[0] if not _is_torch(rp_keep) else rp_keep.numel()) - 1
     m = col_keep.shape[0] if not _is_torch(col_keep) else col_keep.numel()
-    flags = (PR_INPUT_DEVICE if rp_dev else 0) | (PR_DEDUPE if dedupe else 0)
+    flags = (PR_INPUT_DEVICE if rp_dev else 0) | (PR_DEDUPE if dedupe else 0) | ((tile_shift & 7) << 8)
     h = ctypes.c_void_p()
     st = lib().pr_graph_upload(int(n), int(m), rp_ptr, col_ptr if m else None, flags, ctypes.byref(h))
     if st != PR_OK:

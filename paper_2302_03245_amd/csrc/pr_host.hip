@@ -132,7 +132,9 @@ int32_t degree_order(int64_t n, const int64_t *rp, std::vector<int32_t> &perm, s
 pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
                       pr_graph **out) {
     if (!out) return fail(PR_EINVAL, "out is NULL");
-    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE)) return fail(PR_EINVAL, "unknown upload flag");
+    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE | PR_TILE_MASK)) return fail(PR_EINVAL, "unknown upload flag");
+    const uint32_t tile_shift = (flags & PR_TILE_MASK) >> 8;
+    if (tile_shift != 0 && (tile_shift < 2 || tile_shift > 4)) return fail(PR_EINVAL, "tile shift must be 2, 3 or 4");
     if (n < 1 || n >= ((int64_t)1 << 31)) return fail(PR_EINVAL, "n must be in [1, 2^31)");
     if (m < 0 || m >= ((int64_t)1 << 31)) return fail(PR_EINVAL, "m must be in [0, 2^31)");
     if (!row_ptr) return fail(PR_EINVAL, "row_ptr is NULL");
@@ -188,6 +190,7 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
     G.n = n;
     G.m = m;
     G.device = device;
+    G.tile_k = tile_shift ? (1 << tile_shift) : kMPK;
     HIPCHK(hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking));
     hipStream_t s = G.stream;
     struct StreamGuard {
@@ -298,7 +301,8 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
         p.idx = idx;
         p.R = R;
         p.items = (uint32_t)(R + edges);
-        int32_t blocks = (int32_t)(((int64_t)p.items + kIPB - 1) / kIPB);
+        p.ipb = kBlock * G.tile_k;
+        int32_t blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
         hipError_t e = galloc(&p.plan, (size_t)blocks + 1);
         if (e != hipSuccess) return e;
         if (R == 0) {

@@ -14,8 +14,7 @@ namespace prk {
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kMaxTrace = 4096;   // per-sweep trace entries kept on the device
 constexpr int kRedBlocks = 1024;  // max workgroups of a streaming kernel that feeds a reduction
-constexpr int kMPK = 8;           // merge-path items (rows + edges) per thread
-constexpr int kIPB = kBlock * kMPK;  // merge-path items per workgroup
+constexpr int kMPK = 8;           // default merge-path items (rows + edges) per thread (4, 8 or 16)
 
 // Merge-path work split over a CSR-like segment: rows r in [0, R) with edges
 // [rp[r], rp[r+1]).  The item sequence lists the edges of a row followed by an
@@ -27,7 +26,7 @@ struct MPPlan {
     int32_t R = 0;
     uint32_t items = 0;            // R + number of edges
     int32_t blocks = 0;
-    int32_t ipb = 0;               // items per block
+    int32_t ipb = 0;               // items per tile (kBlock x items per thread)
     uint2 *plan = nullptr;         // device, blocks + 1 entries (owned by the graph)
     int64_t edges() const { return (int64_t)items - R; }
 };
@@ -78,6 +77,7 @@ struct Graph {
     uint32_t *in_ptr = nullptr;   // in-edges of every target (N targets first), [n + 1]
     int32_t *in_src = nullptr;    // [m]
     MPPlan push_nn, push_nd, pull_all, pull_nn, pull_nd;
+    int32_t tile_k = kMPK;        // merge-path items per thread of the sweep tiles
     int64_t device_bytes = 0;
     double seconds_upload = 0, seconds_split = 0;
     hipStream_t stream = nullptr;

@@ -9,6 +9,8 @@
 
 #include <limits.h>
 
+#include <algorithm>
+
 namespace prk {
 
 namespace {
@@ -380,174 +382,200 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
     }
 }
 
-// Scatter step (push): every edge i -> j of a row with w_i != 0 adds w_i to h_j
-// with a hardware FP atomic.  Merge-path tiles give every workgroup the same
-// number of rows + edges, so a hub row is spread over many workgroups and a run
-// of short rows over few.  The tile's edge indices are staged in LDS with
-// coalesced loads; tiles whose rows are all inactive skip the edge stream.
+// Streaming loads (edge ids, row offsets): non-temporal, so they do not evict
+// the gathered weights from the caches.
 template <typename T>
+__device__ __forceinline__ T ld_stream(const T *p) {
+    return *p;
+}
+
+// Scatter step (push): every edge i -> j of a row with w_i != 0 adds w_i to h_j
+// with a hardware FP atomic.  Merge-path tiles give every tile the same number
+// of rows + edges, so a hub row is spread over many tiles and a run of short
+// rows over few.  The tile's target ids are staged in LDS with coalesced
+// loads; tiles whose rows are all inactive skip the edge stream.  A capped grid
+// loops over the tiles, so a sweep that gathers instead costs one cheap launch.
+template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
                                                  int32_t R, const int32_t *col, const uint2 *plan, uint32_t items,
-                                                 const T *w, T *h) {
+                                                 int32_t ntiles, const T *w, T *h) {
+    constexpr int IPB = K * kBlock;
     if (t >= 0 && (t > ctl->stop_after || (check_mode && ctl->use_pull))) return;
-    __shared__ uint32_t s_end[kIPB + 1];
-    __shared__ int32_t s_col[kIPB];
-    __shared__ T s_w[kIPB + 1];
-    const uint2 a = plan[blockIdx.x], b = plan[blockIdx.x + 1];
-    const int32_t i0 = (int32_t)a.x;
-    const int32_t i1 = min((int32_t)b.x, R - 1);
-    const uint32_t e0 = a.y, e1 = b.y;
+    __shared__ uint32_t s_end[IPB + 1];
+    __shared__ int32_t s_col[IPB];
+    __shared__ T s_w[IPB + 1];
     const uint32_t rp0 = rp[0];
-    const int32_t nr = i1 - i0 + 1;
-    int any = 0;
-    for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
-        int32_t r = i0 + k;
-        s_end[k] = rp[r + 1] - rp0 + (uint32_t)r;
-        T wv = w[r];
-        s_w[k] = wv;
-        any |= (wv != (T)0);
-    }
-    any = __syncthreads_or(any);
-    if (!any) return;
-    {
+    for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint2 a = plan[tile], b = plan[tile + 1];
+        const int32_t i0 = (int32_t)a.x;
+        const int32_t i1 = min((int32_t)b.x, R - 1);
+        const uint32_t e0 = a.y, e1 = b.y;
+        const int32_t nr = i1 - i0 + 1;
+        int any = 0;
+        {
+            uint32_t rv[K + 1];
+            T wv[K + 1];
+#pragma unroll
+            for (int j = 0; j <= K; ++j) {
+                const int32_t kk = min((int32_t)threadIdx.x + j * kBlock, nr - 1);
+                rv[j] = ld_stream(rp + i0 + 1 + kk);
+                wv[j] = w[i0 + kk];
+            }
+#pragma unroll
+            for (int j = 0; j <= K; ++j) {
+                const int32_t kk = threadIdx.x + j * kBlock;
+                if (kk < nr) {
+                    s_end[kk] = rv[j] - rp0 + (uint32_t)(i0 + kk);
+                    s_w[kk] = wv[j];
+                    any |= (wv[j] != (T)0);
+                }
+            }
+        }
+        any = __syncthreads_or(any);
+        if (!any) continue;  // uniform: every thread saw the same OR
         const int32_t ne = (int32_t)(e1 - e0);
         if (ne > 0) {
-            int32_t cv[kMPK];
+            int32_t cv[K];
 #pragma unroll
-            for (int j = 0; j < kMPK; ++j) cv[j] = col[e0 + min((int32_t)threadIdx.x + j * kBlock, ne - 1)];
+            for (int j = 0; j < K; ++j) cv[j] = ld_stream(col + e0 + min((int32_t)threadIdx.x + j * kBlock, ne - 1));
 #pragma unroll
-            for (int j = 0; j < kMPK; ++j) {
+            for (int j = 0; j < K; ++j) {
                 const int32_t e = threadIdx.x + j * kBlock;
                 if (e < ne) s_col[e] = cv[j];
             }
         }
-    }
-    __syncthreads();
-    uint32_t d = min((uint32_t)(blockIdx.x * kIPB + threadIdx.x * kMPK), items);
-    const uint32_t dend = min(d + (uint32_t)kMPK, items);
-    if (d >= dend) return;
-    int32_t lo = 0, hi = nr;
-    while (lo < hi) {
-        int32_t mid = (lo + hi) >> 1;
-        if (s_end[mid] < d) lo = mid + 1;
-        else hi = mid;
-    }
-    int32_t k = lo;
-    uint32_t et = rp0 + d - (uint32_t)(i0 + k);
-    T wr = k < nr ? s_w[k] : (T)0;
-    for (; d < dend; ++d) {
-        if (d == s_end[k]) {
-            ++k;
-            wr = k < nr ? s_w[k] : (T)0;
-        } else {
-            if (wr != (T)0) atomicAdd(h + s_col[et - e0], wr);
-            ++et;
+        __syncthreads();
+        uint32_t d = min((uint32_t)(tile * IPB + threadIdx.x * K), items);
+        const uint32_t dend = min(d + (uint32_t)K, items);
+        if (d < dend) {
+            int32_t lo = 0, hi = nr;
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (s_end[mid] < d) lo = mid + 1;
+                else hi = mid;
+            }
+            int32_t k = lo;
+            uint32_t et = rp0 + d - (uint32_t)(i0 + k);
+            T wr = k < nr ? s_w[k] : (T)0;
+            for (; d < dend; ++d) {
+                if (d == s_end[k]) {
+                    ++k;
+                    wr = k < nr ? s_w[k] : (T)0;
+                } else {
+                    if (wr != (T)0) atomicAdd(h + s_col[et - e0], wr);
+                    ++et;
+                }
+            }
         }
+        __syncthreads();  // LDS is reused by the next tile
     }
 }
 
 // Gather step (pull): out_j += sum over in-edges u -> j of w_u, without global
 // atomics except for the first and last row of a tile.  Same merge-path tiling
-// as the push; all w_u of the tile's in-edges are first gathered into LDS in
-// one parallel pass, then each thread walks its rows + edges from LDS, with
-// sums carried in FP64.  A row finished by one thread
-// is written directly; pieces of rows shared by several threads meet in an
-// LDS accumulator (hardware LDS FP64 add), so a hub row costs one global
-// atomic per tile instead of one per thread.
-template <typename WT, typename OT>
+// as the push; all w_u of a tile's in-edges are first gathered into LDS in one
+// batched pass, then each thread walks its rows + edges from LDS, with sums
+// carried in FP64.  A row finished by one thread is written directly; pieces
+// of rows shared by several threads meet in an LDS accumulator (hardware LDS
+// FP64 add), so a hub row costs one global atomic per tile instead of one per
+// thread.
+template <typename WT, typename OT, int K>
 __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
                                                  int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
-                                                 const WT *w, OT *out) {
+                                                 int32_t ntiles, const WT *w, OT *out) {
+    constexpr int IPB = K * kBlock;
     if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
-    __shared__ uint32_t s_end[kIPB + 1];
-    __shared__ WT s_val[kIPB];
-    __shared__ double s_acc[kIPB + 1];
-    __shared__ uint32_t s_first;
-    const uint2 a = plan[blockIdx.x], b = plan[blockIdx.x + 1];
-    const int32_t i0 = (int32_t)a.x;
-    const int32_t i1 = min((int32_t)b.x, R - 1);
-    const uint32_t e0 = a.y, e1 = b.y;
+    __shared__ uint32_t s_end[IPB + 1];
+    __shared__ WT s_val[IPB];
+    __shared__ double s_acc[IPB + 1];
     const uint32_t rp0 = rp[0];
-    const int32_t nr = i1 - i0 + 1;
-    if (threadIdx.x == 0) s_first = rp[i0];
-    {
-        // nr <= kIPB + 1 rows: kMPK + 1 unconditional (clamped) loads per thread
-        uint32_t rv[kMPK + 1];
+    for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint2 a = plan[tile], b = plan[tile + 1];
+        const int32_t i0 = (int32_t)a.x;
+        const int32_t i1 = min((int32_t)b.x, R - 1);
+        const uint32_t e0 = a.y, e1 = b.y;
+        const int32_t nr = i1 - i0 + 1;
+        const uint32_t first = rp[i0];  // first edge of row i0
+        {
+            // nr <= IPB + 1 rows: K + 1 unconditional (clamped) loads per thread
+            uint32_t rv[K + 1];
 #pragma unroll
-        for (int j = 0; j <= kMPK; ++j) rv[j] = rp[i0 + 1 + min((int32_t)threadIdx.x + j * kBlock, nr - 1)];
+            for (int j = 0; j <= K; ++j) rv[j] = ld_stream(rp + i0 + 1 + min((int32_t)threadIdx.x + j * kBlock, nr - 1));
 #pragma unroll
-        for (int j = 0; j <= kMPK; ++j) {
-            const int32_t k = threadIdx.x + j * kBlock;
-            if (k < nr) {
-                s_end[k] = rv[j] - rp0 + (uint32_t)(i0 + k);
-                s_acc[k] = 0.0;
-            }
-        }
-    }
-    // gather phase: every in-edge of the tile at once.  Indices are clamped so
-    // that all loads are unconditional and issue back to back: kMPK coalesced
-    // source-id loads, then kMPK independent weight loads in flight per thread.
-    const int32_t ne = (int32_t)(e1 - e0);
-    if (ne > 0) {
-        int32_t sidx[kMPK];
-        WT v[kMPK];
-#pragma unroll
-        for (int j = 0; j < kMPK; ++j) sidx[j] = src[e0 + min((int32_t)threadIdx.x + j * kBlock, ne - 1)];
-#pragma unroll
-        for (int j = 0; j < kMPK; ++j) v[j] = w[sidx[j]];
-#pragma unroll
-        for (int j = 0; j < kMPK; ++j) {
-            const int32_t e = threadIdx.x + j * kBlock;
-            if (e < ne) s_val[e] = v[j];
-        }
-    }
-    __syncthreads();
-    uint32_t d = min((uint32_t)(blockIdx.x * kIPB + threadIdx.x * kMPK), items);
-    const uint32_t dend = min(d + (uint32_t)kMPK, items);
-    if (d < dend) {
-        int32_t lo = 0, hi = nr;
-        while (lo < hi) {
-            int32_t mid = (lo + hi) >> 1;
-            if (s_end[mid] < d) lo = mid + 1;
-            else hi = mid;
-        }
-        int32_t k = lo;
-        uint32_t et = rp0 + d - (uint32_t)(i0 + k);
-        // first edge of row i0 + k
-        uint32_t row_first = k == 0 ? s_first : s_end[k - 1] + rp0 + 1u - (uint32_t)(i0 + k);
-        bool owned = et == row_first;
-        bool touched = false;
-        double acc = 0.0;
-        for (; d < dend; ++d) {
-            if (d == s_end[k]) {
-                if (touched) {
-                    if (owned) {
-                        OT *o = out + (i0 + k);
-                        *o = (OT)((double)*o + acc);
-                    } else {
-                        atomicAdd(s_acc + k, acc);
-                    }
+            for (int j = 0; j <= K; ++j) {
+                const int32_t kk = threadIdx.x + j * kBlock;
+                if (kk < nr) {
+                    s_end[kk] = rv[j] - rp0 + (uint32_t)(i0 + kk);
+                    s_acc[kk] = 0.0;
                 }
-                acc = 0.0;
-                touched = false;
-                owned = true;
-                ++k;
-            } else {
-                acc += (double)s_val[et - e0];
-                touched = true;
-                ++et;
             }
         }
-        if (touched) atomicAdd(s_acc + k, acc);
-    }
-    __syncthreads();
-    // rows strictly inside the tile belong to this workgroup alone
-    for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
-        double v = s_acc[k];
-        if (v == 0.0) continue;
-        OT *o = out + (i0 + k);
-        if (k == 0 || k == nr - 1) atomicAdd(o, (OT)v);
-        else *o = (OT)((double)*o + v);
+        // gather phase: every in-edge of the tile at once.  Indices are clamped so
+        // that all loads are unconditional and issue back to back: K coalesced
+        // source-id loads, then K independent weight loads in flight per thread.
+        const int32_t ne = (int32_t)(e1 - e0);
+        if (ne > 0) {
+            int32_t sidx[K];
+            WT v[K];
+#pragma unroll
+            for (int j = 0; j < K; ++j) sidx[j] = ld_stream(src + e0 + min((int32_t)threadIdx.x + j * kBlock, ne - 1));
+#pragma unroll
+            for (int j = 0; j < K; ++j) v[j] = w[sidx[j]];
+#pragma unroll
+            for (int j = 0; j < K; ++j) {
+                const int32_t e = threadIdx.x + j * kBlock;
+                if (e < ne) s_val[e] = v[j];
+            }
+        }
+        __syncthreads();
+        uint32_t d = min((uint32_t)(tile * IPB + threadIdx.x * K), items);
+        const uint32_t dend = min(d + (uint32_t)K, items);
+        if (d < dend) {
+            int32_t lo = 0, hi = nr;
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (s_end[mid] < d) lo = mid + 1;
+                else hi = mid;
+            }
+            int32_t k = lo;
+            uint32_t et = rp0 + d - (uint32_t)(i0 + k);
+            // first edge of row i0 + k
+            uint32_t row_first = k == 0 ? first : s_end[k - 1] + rp0 + 1u - (uint32_t)(i0 + k);
+            bool owned = et == row_first;
+            bool touched = false;
+            double acc = 0.0;
+            for (; d < dend; ++d) {
+                if (d == s_end[k]) {
+                    if (touched) {
+                        if (owned) {
+                            OT *o = out + (i0 + k);
+                            *o = (OT)((double)*o + acc);
+                        } else {
+                            atomicAdd(s_acc + k, acc);
+                        }
+                    }
+                    acc = 0.0;
+                    touched = false;
+                    owned = true;
+                    ++k;
+                } else {
+                    acc += (double)s_val[et - e0];
+                    touched = true;
+                    ++et;
+                }
+            }
+            if (touched) atomicAdd(s_acc + k, acc);
+        }
+        __syncthreads();
+        // rows strictly inside the tile belong to this workgroup alone
+        for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
+            double v = s_acc[k];
+            if (v == 0.0) continue;
+            OT *o = out + (i0 + k);
+            if (k == 0 || k == nr - 1) atomicAdd(o, (OT)v);
+            else *o = (OT)((double)*o + v);
+        }
+        __syncthreads();  // LDS is reused by the next tile
     }
 }
 
@@ -774,8 +802,7 @@ hipError_t launch_count_zero(const uint32_t *a, int64_t n, unsigned long long *o
     PRK_LAUNCH(k_count_zero, grid_for(n, 8, 4096), a, n, out);
 }
 hipError_t launch_plan(MPPlan &p, hipStream_t s) {
-    p.ipb = kIPB;
-    p.blocks = (int32_t)(((int64_t)p.items + kIPB - 1) / kIPB);
+    p.blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
     PRK_LAUNCH(k_plan, grid_for((int64_t)p.blocks + 1, 1, 4096), p.rp, p.R, p.items, p.ipb, p.blocks, p.plan);
 }
 
@@ -797,20 +824,58 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
     return hipGetLastError();
 }
 
+// Workgroups of a tile-looping sweep kernel: exactly as many as can be resident
+// at once on the device (CUs x workgroups per CU for this kernel's LDS and
+// registers), so every workgroup runs from the start and the tiles are spread
+// evenly; a launch whose sweep mode is not selected costs one short wave of
+// workgroups.
+template <typename K>
+int resident_grid(K kern) {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 1024;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kBlock, 0) != hipSuccess || per_cu <= 0)
+        per_cu = 4;
+    return cus * per_cu;
+}
+
+template <typename T, int K>
+hipError_t launch_push_k(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s) {
+    static const int grid = resident_grid(k_push<T, K>);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_push<T, K>), dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl,
+                       check_mode, p.rp, p.R, p.idx, (const uint2 *)p.plan, p.items, p.blocks, w, h);
+    return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s) {
     if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
-    PRK_LAUNCH(k_push<T>, p.blocks, t, ctl, check_mode, p.rp, p.R, p.idx, (const uint2 *)p.plan, p.items, w, h);
+    switch (p.ipb / kBlock) {
+        case 4: return launch_push_k<T, 4>(t, ctl, p, w, h, check_mode, s);
+        case 16: return launch_push_k<T, 16>(t, ctl, p, w, h, check_mode, s);
+        default: return launch_push_k<T, 8>(t, ctl, p, w, h, check_mode, s);
+    }
+}
+
+template <typename WT, typename OT, int K>
+hipError_t launch_pull_k(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
+                         hipStream_t s) {
+    auto kern = &k_pull<WT, OT, K>;
+    static const int grid = resident_grid(kern);
+    hipLaunchKernelGGL(kern, dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R,
+                       p.idx, (const uint2 *)p.plan, p.items, p.blocks, w, out);
+    return hipGetLastError();
 }
 
 template <typename WT, typename OT>
 hipError_t launch_pull(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
                        hipStream_t s) {
     if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
-    auto kern = &k_pull<WT, OT>;
-    hipLaunchKernelGGL(kern, dim3(p.blocks), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R, p.idx,
-                       (const uint2 *)p.plan, p.items, w, out);
-    return hipGetLastError();
+    switch (p.ipb / kBlock) {
+        case 4: return launch_pull_k<WT, OT, 4>(t, ctl, p, w, out, check_mode, s);
+        case 16: return launch_pull_k<WT, OT, 16>(t, ctl, p, w, out, check_mode, s);
+        default: return launch_pull_k<WT, OT, 8>(t, ctl, p, w, out, check_mode, s);
+    }
 }
 
 template <typename T>

@@ -130,6 +130,20 @@ def test_random_graphs(pr, name, kw):
     assert l1(pi, ref) <= 1e-6
 
 
+@pytest.mark.parametrize("shift", [2, 3, 4])
+def test_tile_sizes(pr, shift):
+    """Every sweep tile size gives the same answer (hub rows spanning tiles included)."""
+    g = prgen.workload_rmat_small(seed=4)
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    dg = pr.upload(g.row_ptr, g.col, tile_shift=shift)
+    for method in ("ifp1", "ifp2"):
+        for mode in ("push", "pull"):
+            pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
+            assert l1(pi, ref) <= 1e-9
+    pw, _ = pr.power(dg, c=C, l1_tol=1e-12)
+    assert l1(pw, ref) <= 1e-11
+
+
 def test_rmat_small_workload(pr):
     """R-MAT n=10,000, 100,000 distinct edges, 10 % forced dangling, c=0.85, uniform p,
     xi=1e-12, FP64: IFP2 against the FP64 power method run to 1e-13."""
