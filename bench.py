@@ -175,6 +175,7 @@ def main():
                   "l1_bound": st_pow[-1]["l1_bound"]},
         "ifp2_over_power": t_pow / t_ifp2,
         "upload_s": info["seconds_upload"],
+        "depth_epochs": info["epochs"], "max_depth": info["max_depth"],
     }
     if args.probes:
         res["probes"] = run_probes(pr, torch, g)

@@ -111,6 +111,9 @@ typedef struct {
     double seconds_upload;  /* whole upload: copies, classification, relabelling, plans */
     double seconds_split;   /* the IFP2 edge invalidation: stable split of every row into edges
                                towards non-dangling and towards dangling targets */
+    int64_t max_depth;      /* largest finite unreferenced depth of a non-dangling vertex (0: a
+                               vertex without non-dangling in-neighbours; -1: none), see below */
+    int64_t epochs;         /* in-edge lists kept for the gather sweeps (1 + compacted copies) */
 } pr_graph_info_t;
 
 /*
@@ -138,7 +141,13 @@ pr_status pr_graph_upload(int64_t n, int64_t m, const int64_t *row_ptr, const in
 /* Release a graph and its device memory.  NULL is accepted.  */
 pr_status pr_graph_free(pr_graph *g);
 
-/* Shape and cost figures of an uploaded graph (the data-set table columns of section 4.1). */
+/*
+ * Shape and cost figures of an uploaded graph (the data-set table columns of section 4.1).
+ * Unreferenced depth (section 3.3.3): 0 for a non-dangling vertex with no non-dangling
+ * in-neighbour, else 1 + the largest depth of those in-neighbours, infinite on or below a
+ * cycle.  After sweep depth(v) a vertex receives no more mass, so the gather sweeps past
+ * the start of an epoch read compacted in-edge lists without such sources.
+ */
 pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out);
 
 /*

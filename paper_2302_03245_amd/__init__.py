@@ -63,7 +63,7 @@ class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("n_dangling", ctypes.c_int64),
                 ("m_dangling", ctypes.c_int64), ("n_unreferenced", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("seconds_upload", ctypes.c_double),
-                ("seconds_split", ctypes.c_double)]
+                ("seconds_split", ctypes.c_double), ("max_depth", ctypes.c_int64), ("epochs", ctypes.c_int64)]
 
 
 _lib = None

@@ -316,6 +316,87 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
     HIPCHK(make_plan(G.pull_all, G.in_ptr, G.in_src, (int32_t)n, m));
     HIPCHK(make_plan(G.pull_nn, G.in_ptr, G.in_src, G.nN, G.mNN));
     HIPCHK(make_plan(G.pull_nd, G.in_ptr + G.nN, G.in_src, G.nD, G.mND));
+    {
+        Epoch e0;
+        e0.t_start = 0;
+        e0.in_ptr = G.in_ptr;
+        e0.in_src = G.in_src;
+        e0.edges_all = m;
+        e0.edges_nn = G.mNN;
+        e0.pull_all = G.pull_all;
+        e0.pull_nn = G.pull_nn;
+        G.epochs.push_back(e0);
+    }
+
+    // Unreferenced depth of every non-dangling vertex (Kahn rounds over the N -> N
+    // edges), then compacted in-edge lists for the sweeps after which whole depth
+    // classes of sources can no longer push (section 3.3.3: unreferenced and weakly
+    // unreferenced vertices leave the computation).
+    HIPCHK(galloc(&G.depth, (size_t)G.nN));
+    if (G.nN > 0) {
+        uint32_t *d_rem, *d_qc;
+        int32_t *d_q0, *d_q1;
+        HIPCHK(tmp.alloc(&d_rem, (size_t)G.nN));
+        HIPCHK(tmp.alloc(&d_q0, (size_t)G.nN));
+        HIPCHK(tmp.alloc(&d_q1, (size_t)G.nN));
+        HIPCHK(tmp.alloc(&d_qc, 2));
+        HIPCHK(hipMemsetAsync(d_qc, 0, 2 * sizeof(uint32_t), s));
+        HIPCHK(launch_depth_init(G.nN, G.in_ptr, d_rem, G.depth, d_q0, d_qc, s));
+        uint32_t qsize = 0;
+        HIPCHK(hipMemcpyAsync(&qsize, d_qc, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        int32_t round = 0;
+        while (qsize > 0) {
+            G.max_depth = round;
+            HIPCHK(hipMemsetAsync(d_qc + 1, 0, sizeof(uint32_t), s));
+            HIPCHK(launch_depth_step(d_q0, qsize, G.rp_nn, G.col_nn, d_rem, G.depth, round, d_q1, d_qc + 1, s));
+            HIPCHK(hipMemcpyAsync(&qsize, d_qc + 1, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            std::swap(d_q0, d_q1);
+            ++round;
+        }
+        // live edges L(t) = sum of out-degrees of sources with depth >= t
+        std::vector<int32_t> h_depth((size_t)G.nN);
+        HIPCHK(hipMemcpy(h_depth.data(), G.depth, sizeof(int32_t) * G.nN, hipMemcpyDeviceToHost));
+        const int32_t dmax = std::max<int32_t>(G.max_depth, 0);
+        std::vector<int64_t> hist((size_t)dmax + 2, 0);  // [0..dmax] finite, [dmax+1] infinite
+        for (int32_t k = 0; k < G.nN; ++k) {
+            const int32_t v = h_perm[k];
+            const int64_t dg = rp[v + 1] - rp[v];
+            const int32_t d = h_depth[k];
+            hist[d == kDepthInf ? (size_t)dmax + 1 : (size_t)d] += dg;
+        }
+        std::vector<int64_t> live((size_t)dmax + 3, 0);  // live[t] = sum_{d >= t} hist[d]
+        for (int32_t t = dmax + 1; t >= 0; --t) live[(size_t)t] = live[(size_t)t + 1] + hist[(size_t)t];
+        std::vector<int32_t> starts;
+        int64_t cur = m;
+        for (int32_t t = 1; t <= dmax + 1 && (int)starts.size() + 1 < kMaxEpochs; ++t) {
+            if ((double)live[(size_t)t] <= 0.97 * (double)cur) {
+                starts.push_back(t);
+                cur = live[(size_t)t];
+            }
+        }
+        uint32_t *d_cnt;
+        HIPCHK(tmp.alloc(&d_cnt, (size_t)n + 1));
+        for (int32_t t0 : starts) {
+            Epoch ep;
+            ep.t_start = t0;
+            HIPCHK(galloc(&ep.in_ptr, (size_t)n + 1));
+            HIPCHK(launch_live_count((int32_t)n, G.in_ptr, G.in_src, G.depth, t0, d_cnt, s));
+            HIPCHK(launch_scan_u32(d_cnt, ep.in_ptr, n, d_scan, s));
+            uint32_t h_e[2] = {0, 0};
+            HIPCHK(hipMemcpyAsync(&h_e[0], ep.in_ptr + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&h_e[1], ep.in_ptr + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            ep.edges_all = h_e[0];
+            ep.edges_nn = h_e[1];
+            HIPCHK(galloc(&ep.in_src, (size_t)ep.edges_all));
+            HIPCHK(launch_live_fill((int32_t)n, G.in_ptr, G.in_src, G.depth, t0, ep.in_ptr, ep.in_src, s));
+            HIPCHK(make_plan(ep.pull_all, ep.in_ptr, ep.in_src, (int32_t)n, ep.edges_all));
+            HIPCHK(make_plan(ep.pull_nn, ep.in_ptr, ep.in_src, G.nN, ep.edges_nn));
+            G.epochs.push_back(ep);
+        }
+    }
 
     unsigned long long h_zero = 0;
     HIPCHK(hipMemcpyAsync(&h_zero, d_zero, sizeof(h_zero), hipMemcpyDeviceToHost, s));
@@ -463,11 +544,13 @@ struct SweepTimer {
     std::vector<std::unique_ptr<EventPair>> ev;  // per launch
     std::vector<int> sweep_of;                   // sweep index of each launch
     std::vector<int> is_pull;                    // 1 = gather kernel, 0 = scatter kernel
-    hipEvent_t begin(hipStream_t s, int t, int pull) {
+    std::vector<double> bytes;                   // algorithmic bytes of a gather launch
+    hipEvent_t begin(hipStream_t s, int t, int pull, double b) {
         if (!on) return nullptr;
         ev.emplace_back(new EventPair());
         sweep_of.push_back(t);
         is_pull.push_back(pull);
+        bytes.push_back(b);
         (void)hipEventRecord(ev.back()->a, s);
         return ev.back()->b;
     }
@@ -536,11 +619,13 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     HIPCHK(hipMemcpyAsync(ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
     HIPCHK(launch_init_ifp<T>(a, h, pibar, s));
 
-    const MPPlan &pullp = ifp2 ? G.pull_nn : G.pull_all;
+    // the gather of sweep t uses the in-edge lists of the last epoch starting at or before t
+    auto pull_plan = [&](int t) -> const MPPlan & {
+        size_t e = 0;
+        while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
+        return ifp2 ? G.epochs[e].pull_nn : G.epochs[e].pull_all;
+    };
     const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
-    // a pull sweep reads every in-edge; push when the active edges are fewer than this share
-    const unsigned long long pull_edges = (unsigned long long)pullp.edges();
-    const unsigned long long pull_thr = (unsigned long long)(0.5 * (double)pull_edges) + 1;
     const int check_mode = force == 0;
     int t = 0;
     bool stopped = false;
@@ -551,16 +636,25 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         while (t < max_sweeps) {
             int nb = std::min(batch, max_sweeps - t);
             for (int k = 0; k < nb; ++k, ++t) {
+                const MPPlan &pullp = pull_plan(t);
+                // a gather reads every live in-edge; scatter when the active edges are fewer than half of them
+                const unsigned long long pull_edges = (unsigned long long)pullp.edges();
+                const unsigned long long pull_thr = (unsigned long long)(0.5 * (double)pull_edges) + 1;
                 HIPCHK(launch_reserve<T>(t, ctl, tr, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, l1 ? 1 : 0,
                                          tol, pull_thr, force, pull_edges, part, s));
                 if (force != 2) {
-                    hipEvent_t e = timer.begin(s, t, 0);
+                    // the scatter is timed when it is forced; in the automatic mode only the
+                    // gather (the dense sweeps' kernel) carries events, to keep their overhead low
+                    hipEvent_t e = force == 1 ? timer.begin(s, t, 0, 0.0) : nullptr;
                     HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, check_mode, s));
                     if (!ifp2) HIPCHK(launch_push<T>(t, ctl, G.push_nd, w, h, check_mode, s));
                     timer.end(e, s);
                 }
                 if (force != 1) {
-                    hipEvent_t e = timer.begin(s, t, 1);
+                    // every live in-edge: source id + gathered weight; every target row: offset + residual update
+                    const double sT = (double)sizeof(T);
+                    hipEvent_t e = timer.begin(s, t, 1,
+                                               (double)pullp.edges() * (4.0 + sT) + (double)pullp.R * (4.0 + 2.0 * sT));
                     HIPCHK(launch_pull<T, T>(t, ctl, pullp, w, h, check_mode, s));
                     timer.end(e, s);
                 }
@@ -628,10 +722,9 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                 if ((int)pulled != timer.is_pull[i]) continue;
                 double sec = elapsed_s(timer.ev[i]->a, timer.ev[i]->b);
                 if (pulled) {
-                    // every in-edge: source id + gathered weight; every target row: offset + residual update
                     z.pull_seconds += sec;
                     z.pull_launches += 1;
-                    z.pull_bytes += (double)pullp.edges() * (4.0 + sT) + (double)pullp.R * (4.0 + 2.0 * sT);
+                    z.pull_bytes += timer.bytes[i];
                 } else {
                     // every pushed edge: target id + residual read-modify-write; every row: offset + weight
                     int rows = ifp2 ? nN : 2 * nN;
@@ -698,7 +791,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
         for (int k = 0; k < nb; ++k, ++t) {
             HIPCHK(launch_power_prescale<WT>(t, ctl, a, x, acc, y, G.deg, c, tol, part, s));
             if (t < max_it) {
-                hipEvent_t e = timer.begin(s, t, 1);
+                hipEvent_t e = timer.begin(s, t, 1, 0.0);
                 HIPCHK(launch_pull<WT, double>(t, ctl, G.pull_all, y, acc, 0, s));
                 timer.end(e, s);
             }
@@ -824,6 +917,8 @@ pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out) {
     out->device_bytes = G.device_bytes;
     out->seconds_upload = G.seconds_upload;
     out->seconds_split = G.seconds_split;
+    out->max_depth = G.max_depth;
+    out->epochs = (int64_t)G.epochs.size();
     return PR_OK;
 }
 

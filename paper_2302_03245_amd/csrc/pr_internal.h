@@ -14,6 +14,8 @@ namespace prk {
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kMaxTrace = 4096;   // per-sweep trace entries kept on the device
 constexpr int kRedBlocks = 1024;  // max workgroups of a streaming kernel that feeds a reduction
+constexpr int32_t kDepthInf = 0x7fffffff;  // unreferenced depth of vertices on or below a cycle
+constexpr int kMaxEpochs = 8;     // compacted in-edge lists kept per graph
 constexpr int kMPK = 8;           // default merge-path items (rows + edges) per thread (4, 8 or 16)
 
 // Merge-path work split over a CSR-like segment: rows r in [0, R) with edges
@@ -61,6 +63,16 @@ struct Trace {
     double bound[kMaxTrace];
 };
 
+// In-edge lists for the sweeps t >= t_start: only sources whose unreferenced
+// depth is >= t_start (the others can no longer push).  Epoch 0 is the full list.
+struct Epoch {
+    int32_t t_start = 0;
+    uint32_t *in_ptr = nullptr;  // [n + 1] (N targets first)
+    int32_t *in_src = nullptr;
+    int64_t edges_all = 0, edges_nn = 0;
+    MPPlan pull_all, pull_nn;
+};
+
 // Device-resident graph: vertices relabelled so that the n_N non-dangling
 // vertices come first ([0, n_N), original order kept), dangling after.
 struct Graph {
@@ -77,6 +89,9 @@ struct Graph {
     uint32_t *in_ptr = nullptr;   // in-edges of every target (N targets first), [n + 1]
     int32_t *in_src = nullptr;    // [m]
     MPPlan push_nn, push_nd, pull_all, pull_nn, pull_nd;
+    int32_t *depth = nullptr;     // unreferenced depth of non-dangling vertices, [nN]
+    int32_t max_depth = -1;       // largest finite depth
+    std::vector<Epoch> epochs;    // epochs[0] aliases the full in-edge lists
     int32_t tile_k = kMPK;        // merge-path items per thread of the sweep tiles
     int64_t device_bytes = 0;
     double seconds_upload = 0, seconds_split = 0;
@@ -109,6 +124,15 @@ hipError_t launch_fill_csc(const uint32_t *rp, const int32_t *col, int32_t R, ui
                            hipStream_t s);
 hipError_t launch_count_zero(const uint32_t *a, int64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_plan(MPPlan &p, hipStream_t s);
+hipError_t launch_depth_init(int32_t nN, const uint32_t *in_ptr, uint32_t *rem, int32_t *depth, int32_t *q,
+                             uint32_t *qcount, hipStream_t s);
+hipError_t launch_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *rp_nn, const int32_t *col_nn,
+                             uint32_t *rem, int32_t *depth, int32_t round, int32_t *next, uint32_t *ncount,
+                             hipStream_t s);
+hipError_t launch_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
+                             int32_t t0, uint32_t *cnt, hipStream_t s);
+hipError_t launch_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
+                            int32_t t0, const uint32_t *out_ptr, int32_t *out_src, hipStream_t s);
 
 // solve kernels
 struct InitArgs {

@@ -249,6 +249,95 @@ __global__ void k_count_zero(const uint32_t *a, int64_t n, unsigned long long *o
     if (threadIdx.x == 0 && c) atomic_add_u64(out, c);
 }
 
+// ---- unreferenced depth of the non-dangling vertices (Kahn rounds on the N -> N edges)
+// depth(v) = 0 without non-dangling in-neighbours, else 1 + max depth of them;
+// vertices on or below a cycle keep kDepthInf.  After sweep depth(v) no mass can
+// reach v again, so from sweep depth(v) + 1 on its push weight is zero.
+
+// append the lanes' items with one atomic per wave
+__device__ __forceinline__ void wave_append(bool take, int32_t v, int32_t *q, uint32_t *count) {
+    const unsigned long long mask = __ballot(take);
+    if (!mask) return;
+    const int leader = __ffsll((long long)mask) - 1;
+    uint32_t base = 0;
+    if (lane_id() == leader) base = atomicAdd(count, (uint32_t)__popcll(mask));
+    base = __shfl(base, leader, W);
+    if (take) q[base + __popcll(mask & ((1ull << lane_id()) - 1ull))] = v;
+}
+
+__global__ void k_depth_init(int32_t nN, const uint32_t *in_ptr, uint32_t *rem, int32_t *depth, int32_t *q,
+                             uint32_t *qcount) {
+    for (int64_t base = blockIdx.x * (int64_t)kBlock; base < nN; base += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = base + threadIdx.x;
+        bool zero = false;
+        if (v < nN) {
+            const uint32_t r = in_ptr[v + 1] - in_ptr[v];
+            rem[v] = r;
+            depth[v] = r == 0 ? 0 : kDepthInf;
+            zero = r == 0;
+        }
+        wave_append(zero, (int32_t)v, q, qcount);
+    }
+}
+
+// one wave per vertex of the current round: release its out-neighbours
+__global__ void k_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *rp_nn, const int32_t *col_nn,
+                             uint32_t *rem, int32_t *depth, int32_t round, int32_t *next, uint32_t *ncount) {
+    const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
+    for (int64_t k = wave; k < qsize; k += nwaves) {
+        const int32_t v = q[k];
+        const uint32_t lo = rp_nn[v], hi = rp_nn[v + 1];
+        for (uint32_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
+            bool done = false;
+            int32_t u = 0;
+            if (e < hi) {
+                u = col_nn[e];
+                if (atomicSub(rem + u, 1u) == 1u) {
+                    depth[u] = round + 1;
+                    done = true;
+                }
+            }
+            wave_append(done, u, next, ncount);
+        }
+    }
+}
+
+// one wave per target row: number of in-edges whose source depth is >= t0
+__global__ void k_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
+                             int32_t t0, uint32_t *cnt) {
+    const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
+    for (int64_t r = wave; r < R; r += nwaves) {
+        const uint32_t lo = in_ptr[r], hi = in_ptr[r + 1];
+        uint32_t c = 0;
+        for (uint32_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
+            bool live = e < hi && depth[in_src[e]] >= t0;
+            c += (uint32_t)__popcll(__ballot(live));
+        }
+        if (lane_id() == 0) cnt[r] = c;
+    }
+}
+
+// one wave per target row: copy the live in-edges, order kept
+__global__ void k_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
+                            int32_t t0, const uint32_t *out_ptr, int32_t *out_src) {
+    const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
+    const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
+    const unsigned long long lt = (1ull << lane_id()) - 1ull;
+    for (int64_t r = wave; r < R; r += nwaves) {
+        const uint32_t lo = in_ptr[r], hi = in_ptr[r + 1];
+        uint32_t o = out_ptr[r];
+        for (uint32_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
+            const int32_t u = e < hi ? in_src[e] : 0;
+            const bool live = e < hi && depth[u] >= t0;
+            const unsigned long long mk = __ballot(live);
+            if (live) out_src[o + __popcll(mk & lt)] = u;
+            o += (uint32_t)__popcll(mk);
+        }
+    }
+}
+
 // merge-path split points: plan[b] = (rows finished before diagonal d, edge at d)
 __global__ void k_plan(const uint32_t *rp, int32_t R, uint32_t items, int32_t ipb, int32_t blocks, uint2 *plan) {
     const uint32_t rp0 = rp[0];
@@ -800,6 +889,28 @@ hipError_t launch_fill_csc(const uint32_t *rp, const int32_t *col, int32_t R, ui
 }
 hipError_t launch_count_zero(const uint32_t *a, int64_t n, unsigned long long *out, hipStream_t s) {
     PRK_LAUNCH(k_count_zero, grid_for(n, 8, 4096), a, n, out);
+}
+hipError_t launch_depth_init(int32_t nN, const uint32_t *in_ptr, uint32_t *rem, int32_t *depth, int32_t *q,
+                             uint32_t *qcount, hipStream_t s) {
+    if (nN == 0) return hipSuccess;
+    PRK_LAUNCH(k_depth_init, grid_for(nN, 4, 8192), nN, in_ptr, rem, depth, q, qcount);
+}
+hipError_t launch_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *rp_nn, const int32_t *col_nn,
+                             uint32_t *rem, int32_t *depth, int32_t round, int32_t *next, uint32_t *ncount,
+                             hipStream_t s) {
+    if (qsize == 0) return hipSuccess;
+    PRK_LAUNCH(k_depth_step, grid_for((int64_t)qsize * W, 1, 16384), q, qsize, rp_nn, col_nn, rem, depth, round, next,
+               ncount);
+}
+hipError_t launch_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
+                             int32_t t0, uint32_t *cnt, hipStream_t s) {
+    if (R == 0) return hipSuccess;
+    PRK_LAUNCH(k_live_count, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, cnt);
+}
+hipError_t launch_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
+                            int32_t t0, const uint32_t *out_ptr, int32_t *out_src, hipStream_t s) {
+    if (R == 0) return hipSuccess;
+    PRK_LAUNCH(k_live_fill, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, out_ptr, out_src);
 }
 hipError_t launch_plan(MPPlan &p, hipStream_t s) {
     p.blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);

@@ -144,6 +144,27 @@ def test_tile_sizes(pr, shift):
     assert l1(pw, ref) <= 1e-11
 
 
+def test_depth_epochs_on_a_dag(pr):
+    """Gather sweeps on compacted in-edge lists (sources past their unreferenced depth
+    dropped) give the oracle's answer; the epochs exist on a layered DAG."""
+    g = prgen.workload_dag(n_layers=12, layer_size=3000, zmax=200, target_edges=300_000, back_frac=0.005, seed=2)
+    dg = pr.upload(g.row_ptr, g.col)
+    info = dg.info()
+    assert info["epochs"] > 1 and info["max_depth"] >= 2
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    for method in ("ifp1", "ifp2"):
+        for mode in (None, "pull"):
+            pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
+            assert st["status"] == 0
+            assert l1(pi, ref) <= 1e-9
+            pi32, _ = getattr(pr, method)(dg, c=C, l1_tol=1e-6, residual="fp32", mode=mode)
+            assert l1(pi32, ref) <= 1e-6
+    p = prgen.random_p(g.n, seed=3, zero_frac=0.5)
+    ref_p, _, _ = oracle.power(g, C, p, tol=1e-13)
+    pi, _ = pr.ifp2(dg, p=p, c=C, xi=1e-13, mode="pull")
+    assert l1(pi, ref_p) <= 1e-9
+
+
 def test_rmat_small_workload(pr):
     """R-MAT n=10,000, 100,000 distinct edges, 10 % forced dangling, c=0.85, uniform p,
     xi=1e-12, FP64: IFP2 against the FP64 power method run to 1e-13."""
