@@ -75,6 +75,8 @@ def main():
     ap.add_argument("--tile-shift", type=int, default=0, help="sweep tile = 256 << s items (s in 2..4; 0 default)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="also run the copy / gather / scatter probes")
+    ap.add_argument("--ppr", type=int, default=16,
+                    help="single-source PPR queries timed one at a time and batched (0 = skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is design-only.",
@@ -177,12 +179,45 @@ def main():
         "upload_s": info["seconds_upload"],
         "depth_epochs": info["epochs"], "max_depth": info["max_depth"],
     }
+    if args.ppr > 0:
+        res["ppr"] = run_ppr(pr, dg, g, c, args)
     if args.probes:
         res["probes"] = run_probes(pr, torch, g)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (serial oracle IFP2)")
         res["cpu_baseline"] = cpu_baseline(g, c, args.tol)
     print(json.dumps(res), flush=True)
+
+
+def run_ppr(pr, dg, g, c, args):
+    """Aggregate throughput of single-source PPR (IFP2, FP32 residuals, certified L1 <= tol):
+    the same queries one call per source, and in one call (batched eight per launch)."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(7)
+    deg = np.diff(g.row_ptr)
+    srcs = rng.choice(np.where(deg > 0)[0], args.ppr, replace=False).astype(np.int32)
+    out = torch.empty((len(srcs), g.n), dtype=torch.float64, device="cuda")  # results stay in HBM
+    pr.ppr(dg, srcs[:2], c=c, l1_tol=args.tol, residual="fp32", out=out[:2])  # warm-up of both paths
+    pr.ppr(dg, srcs[:1], c=c, l1_tol=args.tol, residual="fp32", out=out[:1])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    single = [pr.ppr(dg, srcs[i:i + 1], c=c, l1_tol=args.tol, residual="fp32", out=out[i:i + 1])[1][0]
+              for i in range(len(srcs))]
+    torch.cuda.synchronize()
+    t_single = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, batched = pr.ppr(dg, srcs, c=c, l1_tol=args.tol, residual="fp32", out=out)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    assert all(s["status"] == 0 and s["l1_bound"] <= args.tol for s in single + batched)
+    k = len(srcs)
+    log(f"[bench] PPR x{k}: one at a time {t_single * 1e3:.1f} ms, batched {t_batch * 1e3:.1f} ms")
+    return {"queries": k, "one_at_a_time_ms": t_single * 1e3, "batched_ms": t_batch * 1e3,
+            "one_at_a_time_gteps": k * g.m / t_single / 1e9, "batched_gteps": k * g.m / t_batch / 1e9,
+            "speedup": t_single / t_batch, "batch_width": 8,
+            "mean_sweeps_single": float(np.mean([s["sweeps"] for s in single])),
+            "mean_sweeps_batched": float(np.mean([s["sweeps"] for s in batched]))}
 
 
 def run_probes(pr, torch, g):

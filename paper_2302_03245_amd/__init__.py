@@ -291,14 +291,24 @@ def last_trace() -> dict:
     return {"active": active, "edges": edges, "residual": residual, "bound": bound, "pulled": pulled}
 
 
-def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, stream=None):
-    """Single-source PPR for each source (IFP2); returns (float64[k, n], list of stats dicts)."""
+def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, stream=None,
+        mode=None, out=None):
+    """Single-source PPR for each source (IFP2, sources batched eight at a time);
+    returns (float64[k, n], list of stats dicts).  `out` may be a (k, n) float64 numpy
+    array or torch CUDA tensor."""
     src = np.ascontiguousarray(sources, dtype=np.int32)
     k = int(src.shape[0])
-    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, None, False)
-    out = np.empty((k, g.n), dtype=np.float64)
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, False)
+    if out is None:
+        out = np.empty((k, g.n), dtype=np.float64)
+    out_keep, out_ptr, out_dev = _ptr_any(out, np.float64, "float64")
+    size = out_keep.numel() if _is_torch(out_keep) else out_keep.size
+    if size != k * g.n or (not _is_torch(out) and out_keep is not out):
+        raise ValueError("out must be a contiguous float64 array of k * n entries")
+    if out_dev:
+        o.flags |= PR_OUT_DEVICE
     st = (Stats * max(k, 1))()
-    status = lib().pr_ppr(g.handle, src.ctypes.data if k else None, k, ctypes.byref(o), out.ctypes.data, st)
+    status = lib().pr_ppr(g.handle, src.ctypes.data if k else None, k, ctypes.byref(o), out_ptr, st)
     if status < 0:
         raise _err(status)
     return out, [dict(st[i].as_dict(), status=status) for i in range(k)]

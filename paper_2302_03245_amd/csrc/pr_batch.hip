@@ -1,0 +1,442 @@
+// pr_batch.hip -- IFP2 for B personalization vectors at once (single-source PPR
+// batches).  Vectors are stored column-interleaved, element (v, j) at v * B + j,
+// so one random in-edge gather fetches the B weights of a source as one
+// contiguous 4B / 8B * B segment: the cost of the random access is shared by B
+// queries.  Each column keeps its own stop decision; a stopped column is frozen.
+#include "pr_device.h"
+
+namespace prk {
+namespace {
+
+// per-column sum over the threads of a workgroup that hold column tid % B;
+// results valid in threads 0 .. B-1 (column = threadIdx.x)
+template <int B>
+__device__ __forceinline__ double block_sum_cols(double v, double *sbuf /* [kBlock / W * B] */) {
+#pragma unroll
+    for (int o = B; o < W; o <<= 1) v += __shfl_xor(v, o, W);
+    __syncthreads();
+    if (lane_id() < B) sbuf[(threadIdx.x / W) * B + lane_id()] = v;
+    __syncthreads();
+    double r = 0.0;
+    if (threadIdx.x < B) {
+#pragma unroll
+        for (int k = 0; k < kBlock / W; ++k) r += sbuf[k * B + threadIdx.x];
+    }
+    return r;
+}
+
+template <typename T, int B>
+__global__ void k_init_b(int64_t n, int32_t nN, const int32_t *perm, SrcSet src, T *h, double *pibar) {
+    const int64_t total = n * B;
+    for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = idx / B;
+        const int32_t s = src.s[idx % B];
+        h[idx] = (s >= 0 && perm[v] == s) ? (T)n : (T)0;
+        if (v < nN) pibar[idx] = 0.0;
+    }
+}
+
+// Reserve step for every live column (see k_reserve): partials per column,
+// layout part[(q * B + j) * nb + block] for q = inactive residual, mass sent to
+// non-dangling vertices, growth of the total mass, active vertices, their edges.
+template <typename T, int B>
+__global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, int32_t nN, T *h, T *w, double *pibar,
+                                                      const int32_t *deg, const uint32_t *rp_nn, double c, T xi,
+                                                      double *part) {
+    if (t > ctl->stop_after) return;
+    const int j = threadIdx.x % B;  // the grid stride is a multiple of B: a thread keeps its column
+    const bool live = t <= ctl->col_stop[j];
+    double inact = 0.0, pred = 0.0, cnt = 0.0, edges = 0.0;
+    const int64_t total = (int64_t)nN * B;
+    for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = idx / B;
+        const T hv = h[idx];
+        if (live && hv > xi) {
+            const int32_t dg = deg[v];
+            const uint32_t dnn = rp_nn[v + 1] - rp_nn[v];
+            const double val = (double)hv;
+            pibar[idx] += val;
+            h[idx] = (T)0;
+            w[idx] = (T)(c * val / (double)dg);
+            pred += val * ((double)dnn / (double)dg);
+            cnt += 1.0;
+            edges += (double)dnn;
+        } else {
+            w[idx] = (T)0;
+            inact += (double)hv;
+        }
+    }
+    __shared__ double sd[kBlock / W * B];
+    const double r0 = block_sum_cols<B>(inact, sd);
+    const double r1 = block_sum_cols<B>(pred, sd);
+    const double r3 = block_sum_cols<B>(cnt, sd);
+    const double r4 = block_sum_cols<B>(edges, sd);
+    if (threadIdx.x < B) {
+        const int nb = gridDim.x, b = blockIdx.x, jj = threadIdx.x;
+        part[(0 * B + jj) * nb + b] = r0;
+        part[(1 * B + jj) * nb + b] = r1;
+        part[(2 * B + jj) * nb + b] = r3;
+        part[(3 * B + jj) * nb + b] = r4;
+    }
+}
+
+// Management step for B columns (one workgroup).  Column j stops after the
+// sweep whose scatter certifies its L1 bound (or before a sweep that moves
+// nothing); the batch stops when every column has.
+template <int B>
+__global__ __launch_bounds__(1024) void k_decide_b(int t, CtlB *ctl, int nb, const double *part, double c,
+                                                     int stop_l1, double tol, double pull_thr, int force,
+                                                     unsigned long long pull_edges) {
+    if (t > ctl->stop_after) return;
+    __shared__ double s_sum[4 * B];
+    // one wave per partial row (4B rows of nb entries)
+    const int wv = threadIdx.x / W;
+    for (int r = wv; r < 4 * B; r += blockDim.x / W) {
+        double s = 0.0;
+        for (int b = lane_id(); b < nb; b += W) s += part[(int64_t)r * nb + b];
+        s = wave_sum(s);
+        if (lane_id() == 0) s_sum[r] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double k = 2.0 * c / (1.0 - c);
+    bool any_moved = false, any_next = false;
+    double total_edges = 0.0;
+    for (int j = 0; j < B; ++j) {
+        if (t > ctl->col_stop[j]) continue;  // frozen column
+        const double a_in = s_sum[0 * B + j], a_pr = s_sum[1 * B + j];
+        const double a_c = s_sum[2 * B + j], a_e = s_sum[3 * B + j];
+        if (a_c == 0.0) {
+            ctl->col_stop[j] = t - 1;
+            ctl->last_bound[j] = k * a_in / ctl->sx[j];
+            continue;
+        }
+        any_moved = true;
+        total_edges += a_e;
+        const double sn = a_in + c * a_pr;
+        const double sx = ctl->sx[j] + c * a_pr;  // IFP2: the mass that stays on non-dangling vertices
+        ctl->sx[j] = sx;
+        const double bound = k * sn / sx;
+        ctl->last_bound[j] = bound;
+        ctl->col_sweeps[j] = t + 1;
+        ctl->tot_pushes[j] += (unsigned long long)a_c;
+        ctl->tot_edges[j] += (unsigned long long)a_e;
+        if (stop_l1 && bound <= tol) ctl->col_stop[j] = t;
+        else any_next = true;
+    }
+    const int pull = force == 1 ? 0 : (force == 2 ? 1 : (total_edges >= pull_thr ? 1 : 0));
+    ctl->use_pull = pull;
+    if (any_moved) {
+        ctl->pull_sweeps += pull;
+        ctl->tot_traversed += pull ? pull_edges : (unsigned long long)total_edges;
+    }
+    if (!any_next) ctl->stop_after = any_moved ? t : t - 1;
+}
+
+// Scatter for B columns: a group of B lanes walks the merge-path items, lane j
+// adds column j of the source's weight to column j of each target.
+template <typename T, int B, int K>
+__global__ __launch_bounds__(kBlock) void k_push_b(int t, const CtlB *ctl, int check_mode, const uint32_t *rp,
+                                                   int32_t R, const int32_t *col, const uint2 *plan, uint32_t items,
+                                                   int32_t ntiles, const T *w, T *h) {
+    constexpr int G = kBlock / B;  // groups per workgroup
+    constexpr int IPB = G * K;     // items per tile
+    if (t > ctl->stop_after || (check_mode && ctl->use_pull)) return;
+    __shared__ uint32_t s_end[IPB + 1];
+    __shared__ int32_t s_col[IPB];
+    __shared__ T s_w[(IPB + 1) * B];
+    const uint32_t rp0 = rp[0];
+    const int g = threadIdx.x / B, j = threadIdx.x % B;
+    for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint2 a = plan[tile], b = plan[tile + 1];
+        const int32_t i0 = (int32_t)a.x;
+        const int32_t i1 = min((int32_t)b.x, R - 1);
+        const uint32_t e0 = a.y, e1 = b.y;
+        const int32_t nr = i1 - i0 + 1;
+        int any = 0;
+        for (int32_t kk = threadIdx.x; kk < nr; kk += kBlock) s_end[kk] = rp[i0 + 1 + kk] - rp0 + (uint32_t)(i0 + kk);
+        for (int32_t q = threadIdx.x; q < nr * B; q += kBlock) {
+            const T wv = w[(int64_t)i0 * B + q];
+            s_w[q] = wv;
+            any |= wv != (T)0;
+        }
+        any = __syncthreads_or(any);
+        if (!any) continue;
+        const int32_t ne = (int32_t)(e1 - e0);
+        for (int32_t e = threadIdx.x; e < ne; e += kBlock) s_col[e] = col[e0 + e];
+        __syncthreads();
+        uint32_t d = min((uint32_t)(tile * IPB + g * K), items);
+        const uint32_t dend = min(d + (uint32_t)K, items);
+        if (d < dend) {
+            int32_t lo = 0, hi = nr;
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (s_end[mid] < d) lo = mid + 1;
+                else hi = mid;
+            }
+            int32_t k = lo;
+            uint32_t et = rp0 + d - (uint32_t)(i0 + k);
+            T wr = k < nr ? s_w[k * B + j] : (T)0;
+            for (; d < dend; ++d) {
+                if (d == s_end[k]) {
+                    ++k;
+                    wr = k < nr ? s_w[k * B + j] : (T)0;
+                } else {
+                    if (wr != (T)0) atomicAdd(h + (int64_t)s_col[et - e0] * B + j, wr);
+                    ++et;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Gather for B columns: out[j of row r] += sum of w[j of source] over the row's
+// in-edges.  The tile's B-wide weight segments are first gathered into LDS
+// (consecutive lanes read consecutive columns of one source), then a group of
+// B lanes walks the tile's items, lane j summing column j in FP64; rows shared
+// by groups meet in an LDS FP64 accumulator, rows shared by tiles through one
+// global atomic per column and tile.
+template <typename WT, typename OT, int B, int K>
+__global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int check_mode, const uint32_t *rp,
+                                                   int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
+                                                   int32_t ntiles, const WT *w, OT *out) {
+    constexpr int G = kBlock / B;
+    constexpr int IPB = G * K;
+    if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
+    __shared__ uint32_t s_end[IPB + 1];
+    __shared__ WT s_val[IPB * B];
+    __shared__ double s_acc[(IPB + 1) * B];
+    const uint32_t rp0 = rp[0];
+    const int g = threadIdx.x / B, j = threadIdx.x % B;
+    for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const uint2 a = plan[tile], b = plan[tile + 1];
+        const int32_t i0 = (int32_t)a.x;
+        const int32_t i1 = min((int32_t)b.x, R - 1);
+        const uint32_t e0 = a.y, e1 = b.y;
+        const int32_t nr = i1 - i0 + 1;
+        const uint32_t first = rp[i0];
+        for (int32_t kk = threadIdx.x; kk < nr; kk += kBlock) s_end[kk] = rp[i0 + 1 + kk] - rp0 + (uint32_t)(i0 + kk);
+        for (int32_t q = threadIdx.x; q < nr * B; q += kBlock) s_acc[q] = 0.0;
+        const int32_t ne = (int32_t)(e1 - e0);
+        if (ne > 0) {
+            // element q = e * B + column; K per thread, loads issued back to back
+            int32_t sidx[K];
+            WT v[K];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const int32_t q = threadIdx.x + r * kBlock;
+                sidx[r] = src[e0 + min(q / B, ne - 1)];
+            }
+#pragma unroll
+            for (int r = 0; r < K; ++r) v[r] = w[(int64_t)sidx[r] * B + j];
+#pragma unroll
+            for (int r = 0; r < K; ++r) {
+                const int32_t q = threadIdx.x + r * kBlock;
+                if (q / B < ne) s_val[q] = v[r];
+            }
+        }
+        __syncthreads();
+        uint32_t d = min((uint32_t)(tile * IPB + g * K), items);
+        const uint32_t dend = min(d + (uint32_t)K, items);
+        if (d < dend) {
+            int32_t lo = 0, hi = nr;
+            while (lo < hi) {
+                int32_t mid = (lo + hi) >> 1;
+                if (s_end[mid] < d) lo = mid + 1;
+                else hi = mid;
+            }
+            int32_t k = lo;
+            uint32_t et = rp0 + d - (uint32_t)(i0 + k);
+            const uint32_t row_first = k == 0 ? first : s_end[k - 1] + rp0 + 1u - (uint32_t)(i0 + k);
+            bool owned = et == row_first;
+            bool touched = false;
+            double acc = 0.0;
+            for (; d < dend; ++d) {
+                if (d == s_end[k]) {
+                    if (touched) {
+                        if (owned) {
+                            OT *o = out + (int64_t)(i0 + k) * B + j;
+                            *o = (OT)((double)*o + acc);
+                        } else {
+                            atomicAdd(s_acc + k * B + j, acc);
+                        }
+                    }
+                    acc = 0.0;
+                    touched = false;
+                    owned = true;
+                    ++k;
+                } else {
+                    acc += (double)s_val[(et - e0) * B + j];
+                    touched = true;
+                    ++et;
+                }
+            }
+            if (touched) atomicAdd(s_acc + k * B + j, acc);
+        }
+        __syncthreads();
+        for (int32_t q = threadIdx.x; q < nr * B; q += kBlock) {
+            const double v = s_acc[q];
+            if (v == 0.0) continue;
+            const int32_t k = q / B;
+            OT *o = out + (int64_t)i0 * B + q;
+            if (k == 0 || k == nr - 1) atomicAdd(o, (OT)v);
+            else *o = (OT)((double)*o + v);
+        }
+        __syncthreads();
+    }
+}
+
+template <typename T, int B>
+__global__ void k_phase2_prep_b(int64_t n, int32_t nN, const int32_t *perm, SrcSet src, const T *h,
+                                const double *pibar, const int32_t *deg, double c, double *w2, double *xD) {
+    const int64_t total = n * B;
+    for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
+        const int64_t v = idx / B;
+        if (v < nN) {
+            w2[idx] = c * (pibar[idx] + (double)h[idx]) / (double)deg[v];
+        } else {
+            const int32_t s = src.s[idx % B];
+            xD[idx - (int64_t)nN * B] = (s >= 0 && perm[v] == s) ? (double)n : 0.0;
+        }
+    }
+}
+
+template <typename T, int B>
+__device__ __forceinline__ double x_b(int64_t idx, int64_t nN, const T *h, const double *pibar, const double *xD) {
+    const int64_t v = idx / B;
+    return v < nN ? pibar[idx] + (double)h[idx] : xD[idx - nN * B];
+}
+
+template <typename T, int B>
+__global__ __launch_bounds__(kBlock) void k_final_sum_b(int64_t n, int32_t nN, const T *h, const double *pibar,
+                                                        const double *xD, double *part) {
+    double s = 0.0, sn = 0.0;
+    const int64_t total = n * B;
+    for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
+        s += x_b<T, B>(idx, nN, h, pibar, xD);
+        if (idx / B < nN) sn += (double)h[idx];
+    }
+    __shared__ double sd[kBlock / W * B];
+    const double rs = block_sum_cols<B>(s, sd);
+    const double rn = block_sum_cols<B>(sn, sd);
+    if (threadIdx.x < B) {
+        part[threadIdx.x * gridDim.x + blockIdx.x] = rs;
+        part[(B + threadIdx.x) * gridDim.x + blockIdx.x] = rn;
+    }
+}
+
+template <int B>
+__global__ __launch_bounds__(1024) void k_final_decide_b(CtlB *ctl, int nb, const double *part) {
+    const int wv = threadIdx.x / W;
+    for (int r = wv; r < 2 * B; r += blockDim.x / W) {
+        double s = 0.0;
+        for (int b = lane_id(); b < nb; b += W) s += part[(int64_t)r * nb + b];
+        s = wave_sum(s);
+        if (lane_id() == 0) {
+            if (r < B) ctl->fin_sum[r] = s;
+            else ctl->fin_sn[r - B] = s;
+        }
+    }
+}
+
+// pi[j * n + original id] = x / sum_j for the k_real leading columns
+template <typename T, int B>
+__global__ void k_final_write_b(const CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, int k_real,
+                                const T *h, const double *pibar, const double *xD, double *out) {
+    const int64_t total = n * B;
+    for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
+        const int jj = (int)(idx % B);
+        if (jj >= k_real) continue;
+        const int64_t v = idx / B;
+        out[(int64_t)jj * n + perm[v]] = x_b<T, B>(idx, nN, h, pibar, xD) / ctl->fin_sum[jj];
+    }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <typename T, int B>
+hipError_t launch_init_b(int64_t n, int32_t nN, const int32_t *perm, const SrcSet &src, T *h, double *pibar,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_init_b<T, B>), dim3(grid_for(n * B, 4, 16384)), dim3(kBlock), 0, s, n, nN,
+                       perm, src, h, pibar);
+    return hipGetLastError();
+}
+
+template <typename T, int B>
+hipError_t launch_reserve_b(int t, CtlB *ctl, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
+                            const uint32_t *rp_nn, double c, double xi, int stop_l1, double tol, double pull_thr,
+                            int force, unsigned long long pull_edges, double *part, hipStream_t s) {
+    const int nb = grid_for((int64_t)nN * B, 4, kRedBlocks);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reserve_b<T, B>), dim3(nb), dim3(kBlock), 0, s, t, (const CtlB *)ctl, nN, h,
+                       w, pibar, deg, rp_nn, c, (T)xi, part);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_decide_b<B>), dim3(1), dim3(1024), 0, s, t, ctl, nb, (const double *)part,
+                       c, stop_l1, tol, pull_thr, force, pull_edges);
+    return hipGetLastError();
+}
+
+template <typename T, int B>
+hipError_t launch_push_b(int t, const CtlB *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s) {
+    if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
+    auto kern = &k_push_b<T, B, kMPK>;
+    static const int grid = resident_grid(kern);
+    hipLaunchKernelGGL(kern, dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R, p.idx,
+                       (const uint2 *)p.plan, p.items, p.blocks, w, h);
+    return hipGetLastError();
+}
+
+template <typename WT, typename OT, int B>
+hipError_t launch_pull_b(int t, const CtlB *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
+                         hipStream_t s) {
+    if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
+    auto kern = &k_pull_b<WT, OT, B, kMPK>;
+    static const int grid = resident_grid(kern);
+    hipLaunchKernelGGL(kern, dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R, p.idx,
+                       (const uint2 *)p.plan, p.items, p.blocks, w, out);
+    return hipGetLastError();
+}
+
+template <typename T, int B>
+hipError_t launch_phase2_b(int64_t n, int32_t nN, const int32_t *perm, const SrcSet &src, const T *h,
+                           const double *pibar, const int32_t *deg, double c, double *w2, double *xD,
+                           const MPPlan &pull_nd, hipStream_t s) {
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_phase2_prep_b<T, B>), dim3(grid_for(n * B, 4, 16384)), dim3(kBlock), 0, s, n,
+                       nN, perm, src, h, pibar, deg, c, w2, xD);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return launch_pull_b<double, double, B>(-1, nullptr, pull_nd, w2, xD, 0, s);
+}
+
+template <typename T, int B>
+hipError_t launch_final_b(CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, int k_real, const T *h,
+                          const double *pibar, const double *xD, double *out, double *part, hipStream_t s) {
+    const int nb = grid_for(n * B, 4, kRedBlocks);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_final_sum_b<T, B>), dim3(nb), dim3(kBlock), 0, s, n, nN, h, pibar, xD, part);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_final_decide_b<B>), dim3(1), dim3(1024), 0, s, ctl, nb,
+                       (const double *)part);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_final_write_b<T, B>), dim3(grid_for(n * B, 4, 16384)), dim3(kBlock), 0, s,
+                       (const CtlB *)ctl, n, nN, perm, k_real, h, pibar, xD, out);
+    return hipGetLastError();
+}
+
+#define PRK_BATCH_INST(T, B)                                                                                         \
+    template hipError_t launch_init_b<T, B>(int64_t, int32_t, const int32_t *, const SrcSet &, T *, double *,       \
+                                            hipStream_t);                                                            \
+    template hipError_t launch_reserve_b<T, B>(int, CtlB *, int32_t, T *, T *, double *, const int32_t *,           \
+                                               const uint32_t *, double, double, int, double, double, int,          \
+                                               unsigned long long, double *, hipStream_t);                          \
+    template hipError_t launch_push_b<T, B>(int, const CtlB *, const MPPlan &, const T *, T *, int, hipStream_t);   \
+    template hipError_t launch_pull_b<T, T, B>(int, const CtlB *, const MPPlan &, const T *, T *, int, hipStream_t); \
+    template hipError_t launch_phase2_b<T, B>(int64_t, int32_t, const int32_t *, const SrcSet &, const T *,         \
+                                              const double *, const int32_t *, double, double *, double *,          \
+                                              const MPPlan &, hipStream_t);                                          \
+    template hipError_t launch_final_b<T, B>(CtlB *, int64_t, int32_t, const int32_t *, int, const T *,             \
+                                             const double *, const double *, double *, double *, hipStream_t);
+
+PRK_BATCH_INST(float, 8)
+PRK_BATCH_INST(double, 8)
+
+}  // namespace prk

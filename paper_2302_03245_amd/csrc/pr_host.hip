@@ -838,6 +838,162 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     return stopped ? PR_OK : PR_ENOCONV;
 }
 
+// Plans for the batched kernels (tiles of (kBlock / kBatch) * kMPK items), built
+// once per graph on the first batched solve.
+pr_status ensure_batch_plans(Graph &G, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(G.bp_mu);
+    if (G.bp_ready) return PR_OK;
+    auto mk = [&](MPPlan &p, const uint32_t *rpp, const int32_t *idx, int32_t R, int64_t edges) -> hipError_t {
+        p.rp = rpp;
+        p.idx = idx;
+        p.R = R;
+        p.items = (uint32_t)(R + edges);
+        p.ipb = (kBlock / kBatch) * kMPK;
+        p.blocks = 0;
+        const int32_t blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
+        void *mem = nullptr;
+        hipError_t e = hipMalloc(&mem, sizeof(uint2) * ((size_t)blocks + 1));
+        if (e != hipSuccess) return e;
+        G.allocs.push_back(mem);
+        G.device_bytes += (int64_t)(sizeof(uint2) * ((size_t)blocks + 1));
+        p.plan = (uint2 *)mem;
+        if (R == 0) return hipSuccess;
+        return launch_plan(p, s);
+    };
+    G.bp_pull_nn.clear();
+    for (const Epoch &e : G.epochs) {
+        MPPlan p;
+        HIPCHK(mk(p, e.in_ptr, e.in_src, G.nN, e.edges_nn));
+        G.bp_pull_nn.push_back(p);
+    }
+    HIPCHK(mk(G.bp_pull_nd, G.in_ptr + G.nN, G.in_src, G.nD, G.mND));
+    HIPCHK(mk(G.bp_push_nn, G.rp_nn, G.col_nn, G.nN, G.mNN));
+    HIPCHK(hipStreamSynchronize(s));
+    G.bp_ready = true;
+    return PR_OK;
+}
+
+// IFP2 for kb <= kBatch single-source PPR queries at once (pr_batch.hip):
+// column-interleaved residuals, per-column management, one gather serving all
+// columns.  pi_rows[r * n ...] receives the vector of srcs[r].
+template <typename T>
+pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const pr_opts &o, double *pi_rows,
+                            pr_stats *st) {
+    constexpr int B = kBatch;
+    Graph &G = const_cast<Graph &>(Gc);
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
+    pr_status ps = ensure_batch_plans(G, s);
+    if (ps != PR_OK) return ps;
+    const int64_t n = G.n;
+    const int32_t nN = G.nN, nD = G.nD;
+    const bool out_dev = o.flags & PR_OUT_DEVICE;
+    const double c = o.c;
+    const bool l1 = o.stop == PR_STOP_L1;
+    double xi = o.xi;
+    if (l1) xi = o.l1_tol * (1.0 - c) / (2.0 * c) * (double)n / (double)std::max<int32_t>(nN, 1) * (1.0 - 1e-9);
+    const double tol = l1 ? o.l1_tol * (1.0 - 1e-6) : 0.0;
+    const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
+
+    size_t bytes = carve_size<T>((size_t)n * B) + carve_size<T>((size_t)nN * B) + carve_size<double>((size_t)nN * B) +
+                   carve_size<double>((size_t)nD * B) + carve_size<double>((size_t)nN * B) +
+                   carve_size<double>(out_dev ? 0 : (size_t)kb * n) + carve_size<CtlB>(1) +
+                   carve_size<double>((size_t)4 * B * kRedBlocks);
+    Workspace ws;
+    ps = acquire_ws(G, bytes, ws);
+    if (ps != PR_OK) return ps;
+    Carve cv{ws.base};
+    T *h = cv.take<T>((size_t)n * B);
+    T *w = cv.take<T>((size_t)nN * B);
+    double *pibar = cv.take<double>((size_t)nN * B);
+    double *xD = cv.take<double>((size_t)nD * B);
+    double *w2 = cv.take<double>((size_t)nN * B);
+    double *outbuf = cv.take<double>(out_dev ? 0 : (size_t)kb * n);
+    CtlB *ctl = cv.take<CtlB>(1);
+    double *part = cv.take<double>((size_t)4 * B * kRedBlocks);
+    CtlB *hc = nullptr;
+    HIPCHK(hipHostMalloc((void **)&hc, sizeof(CtlB), hipHostMallocDefault));
+    std::unique_ptr<CtlB, void (*)(CtlB *)> hc_guard(hc, [](CtlB *p) { (void)hipHostFree(p); });
+
+    SrcSet ss;
+    for (int j = 0; j < kMaxBatch; ++j) ss.s[j] = j < kb ? srcs[j] : -1;
+    memset(hc, 0, sizeof(CtlB));
+    hc->stop_after = INT_MAX;
+    for (int j = 0; j < B; ++j) {
+        hc->col_stop[j] = j < kb ? INT_MAX : -1;
+        hc->sx[j] = (double)n;
+    }
+    EventPair ev_solve;
+    HIPCHK(hipEventRecord(ev_solve.a, s));
+    HIPCHK(hipMemcpyAsync(ctl, hc, sizeof(CtlB), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_init_b<T, B>(n, nN, G.perm, ss, h, pibar, s));
+
+    const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
+    const int check_mode = force == 0;
+    auto pull_plan = [&](int t) -> const MPPlan & {
+        size_t e = 0;
+        while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
+        return G.bp_pull_nn[e];
+    };
+    int t = 0;
+    bool stopped = false;
+    if (nN > 0) {
+        int batch = l1 ? 8 : 16;
+        double bound_prev = -1.0;
+        int t_prev = 0;
+        while (t < max_sweeps) {
+            const int nbt = std::min(batch, max_sweeps - t);
+            for (int k = 0; k < nbt; ++k, ++t) {
+                const MPPlan &pullp = pull_plan(t);
+                // a gather serves every column; scatter when the active (vertex, column) edges are few
+                const double pull_thr = 0.25 * (double)pullp.edges();
+                HIPCHK(launch_reserve_b<T, B>(t, ctl, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, l1 ? 1 : 0, tol,
+                                              pull_thr, force, (unsigned long long)pullp.edges(), part, s));
+                if (force != 2) HIPCHK(launch_push_b<T, B>(t, ctl, G.bp_push_nn, w, h, check_mode, s));
+                if (force != 1) HIPCHK((launch_pull_b<T, T, B>(t, ctl, pullp, w, h, check_mode, s)));
+            }
+            HIPCHK(hipMemcpyAsync(hc, ctl, sizeof(CtlB), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (hc->stop_after < t) {
+                stopped = true;
+                break;
+            }
+            double worst = 0.0;
+            for (int j = 0; j < kb; ++j)
+                if (hc->col_stop[j] >= t) worst = std::max(worst, hc->last_bound[j]);
+            batch = next_batch(batch, bound_prev, worst, t - t_prev, tol, l1);
+            bound_prev = worst;
+            t_prev = t;
+        }
+    } else {
+        stopped = true;
+    }
+    if (nD > 0) HIPCHK(launch_phase2_b<T, B>(n, nN, G.perm, ss, h, pibar, G.deg, c, w2, xD, G.bp_pull_nd, s));
+    double *dst = out_dev ? pi_rows : outbuf;
+    HIPCHK(launch_final_b<T, B>(ctl, n, nN, G.perm, kb, h, pibar, xD, dst, part, s));
+    HIPCHK(hipEventRecord(ev_solve.b, s));
+    HIPCHK(hipMemcpyAsync(hc, ctl, sizeof(CtlB), hipMemcpyDeviceToHost, s));
+    if (!out_dev) HIPCHK(hipMemcpyAsync(pi_rows, outbuf, sizeof(double) * (size_t)kb * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) {
+        const double secs = elapsed_s(ev_solve.a, ev_solve.b);
+        for (int j = 0; j < kb; ++j) {
+            pr_stats z;
+            memset(&z, 0, sizeof(z));
+            z.sweeps = hc->col_sweeps[j];
+            z.pull_sweeps = hc->pull_sweeps;
+            z.edges_processed = (int64_t)hc->tot_edges[j] + G.mND;
+            z.edges_traversed = (int64_t)hc->tot_traversed + G.mND;
+            z.vertex_pushes = (int64_t)hc->tot_pushes[j];
+            z.residual_l1 = hc->fin_sum[j] > 0 ? hc->fin_sn[j] / hc->fin_sum[j] : 0.0;
+            z.l1_bound = hc->fin_sum[j] > 0 ? 2.0 * c / (1.0 - c) * hc->fin_sn[j] / hc->fin_sum[j] : 0.0;
+            z.seconds_solve = secs;
+            z.seconds_preprocess = G.seconds_split;
+            st[j] = z;
+        }
+    }
+    return stopped ? PR_OK : PR_ENOCONV;
+}
+
 pr_status opts_or_default(const pr_opts *o, pr_opts *out) {
     if (o) *out = *o;
     else pr_opts_default(out);
@@ -977,11 +1133,19 @@ pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_
     if (ps != PR_OK) return ps;
     pr_status worst = PR_OK;
     try {
-        for (int32_t r = 0; r < k; ++r) {
-            double *row = pi + (size_t)r * (size_t)G.n;
+        // groups of kBatch sources share one batched solve; a lone source runs alone
+        for (int32_t r = 0; r < k; r += kBatch) {
+            const int kb = (int)std::min<int32_t>(kBatch, k - r);
+            double *rows = pi + (size_t)r * (size_t)G.n;
             pr_stats *sr = st ? st + r : nullptr;
-            pr_status rs = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, sources[r], op, row, sr)
-                                                      : solve_ifp_t<double>(G, true, nullptr, sources[r], op, row, sr);
+            pr_status rs;
+            if (kb == 1) {
+                rs = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, sources[r], op, rows, sr)
+                                                : solve_ifp_t<double>(G, true, nullptr, sources[r], op, rows, sr);
+            } else {
+                rs = op.residual == PR_RES_FP32 ? solve_ppr_batch_t<float>(G, sources + r, kb, op, rows, sr)
+                                                : solve_ppr_batch_t<double>(G, sources + r, kb, op, rows, sr);
+            }
             if (rs < 0) return rs;
             if (rs > worst) worst = rs;
         }

@@ -17,6 +17,7 @@ constexpr int kRedBlocks = 1024;  // max workgroups of a streaming kernel that f
 constexpr int32_t kDepthInf = 0x7fffffff;  // unreferenced depth of vertices on or below a cycle
 constexpr int kMaxEpochs = 8;     // compacted in-edge lists kept per graph
 constexpr int kMPK = 8;           // default merge-path items (rows + edges) per thread (4, 8 or 16)
+constexpr int kBatch = 8;         // vectors per batched launch
 
 // Merge-path work split over a CSR-like segment: rows r in [0, R) with edges
 // [rp[r], rp[r+1]).  The item sequence lists the edges of a row followed by an
@@ -56,6 +57,27 @@ struct alignas(128) Ctl {
     double pad1[4];
 };
 
+// Control block of a batch of B <= kMaxBatch vectors (see Ctl).
+constexpr int kMaxBatch = 16;
+struct alignas(128) CtlB {
+    int32_t stop_after;             // sweeps with index > stop_after do nothing
+    int32_t use_pull;
+    int32_t pull_sweeps;
+    int32_t pad0;
+    int32_t col_stop[kMaxBatch];    // column j reserves only in sweeps <= col_stop[j]
+    int32_t col_sweeps[kMaxBatch];
+    double sx[kMaxBatch];
+    double last_bound[kMaxBatch];
+    unsigned long long tot_pushes[kMaxBatch], tot_edges[kMaxBatch];
+    unsigned long long tot_traversed;
+    double fin_sum[kMaxBatch], fin_sn[kMaxBatch];
+};
+
+// sources of a batch (original ids; -1 = unused column), passed by value
+struct SrcSet {
+    int32_t s[kMaxBatch];
+};
+
 struct Trace {
     unsigned long long cnt[kMaxTrace];
     unsigned long long edges[kMaxTrace];
@@ -89,6 +111,12 @@ struct Graph {
     uint32_t *in_ptr = nullptr;   // in-edges of every target (N targets first), [n + 1]
     int32_t *in_src = nullptr;    // [m]
     MPPlan push_nn, push_nd, pull_all, pull_nn, pull_nd;
+    // merge-path plans with tiles of (kBlock / kBatch) * kMPK items for the batched
+    // kernels, built on the first batched solve
+    std::mutex bp_mu;
+    bool bp_ready = false;
+    std::vector<MPPlan> bp_pull_nn;  // per epoch
+    MPPlan bp_pull_nd, bp_push_nn;
     int32_t *depth = nullptr;     // unreferenced depth of non-dangling vertices, [nN]
     int32_t max_depth = -1;       // largest finite depth
     std::vector<Epoch> epochs;    // epochs[0] aliases the full in-edge lists
@@ -169,5 +197,26 @@ hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, 
 hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStream_t s);
 hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, double *part, hipStream_t s);
 hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s);
+
+// batched IFP2 (pr_batch.hip)
+template <typename T, int B>
+hipError_t launch_init_b(int64_t n, int32_t nN, const int32_t *perm, const SrcSet &src, T *h, double *pibar,
+                         hipStream_t s);
+template <typename T, int B>
+hipError_t launch_reserve_b(int t, CtlB *ctl, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
+                            const uint32_t *rp_nn, double c, double xi, int stop_l1, double tol, double pull_thr,
+                            int force, unsigned long long pull_edges, double *part, hipStream_t s);
+template <typename T, int B>
+hipError_t launch_push_b(int t, const CtlB *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s);
+template <typename WT, typename OT, int B>
+hipError_t launch_pull_b(int t, const CtlB *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
+                         hipStream_t s);
+template <typename T, int B>
+hipError_t launch_phase2_b(int64_t n, int32_t nN, const int32_t *perm, const SrcSet &src, const T *h,
+                           const double *pibar, const int32_t *deg, double c, double *w2, double *xD,
+                           const MPPlan &pull_nd, hipStream_t s);
+template <typename T, int B>
+hipError_t launch_final_b(CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, int k_real, const T *h,
+                          const double *pibar, const double *xD, double *out, double *part, hipStream_t s);
 
 }  // namespace prk

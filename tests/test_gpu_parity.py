@@ -246,6 +246,27 @@ def test_ppr_sources(pr):
     assert l1(out32[0], oracle.power(g, C, p, tol=1e-13)[0]) <= 1e-6
 
 
+@pytest.mark.parametrize("mode", [None, "push", "pull"])
+def test_ppr_batches(pr, mode):
+    """Eleven sources: one batch of eight column-interleaved vectors and one of three,
+    each column against the oracle with p = e_s, FP64 and FP32 residuals."""
+    g = prgen.workload_rmat_small(seed=5)
+    dg = pr.upload(g.row_ptr, g.col)
+    deg = np.diff(g.row_ptr)
+    rng = np.random.default_rng(11)
+    srcs = [int(np.argmax(deg)), int(np.where(deg == 0)[0][3])] + [int(x) for x in rng.choice(g.n, 9, replace=False)]
+    out, stats = pr.ppr(dg, srcs, c=C, xi=1e-12, mode=mode)
+    out32, stats32 = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32", mode=mode)
+    for r, s in enumerate(srcs):
+        p = np.zeros(g.n)
+        p[s] = 1.0
+        ref, _, _ = oracle.power(g, C, p, tol=1e-13)
+        assert stats[r]["status"] == 0
+        assert l1(out[r], ref) <= 1e-9, (r, s)
+        assert stats32[r]["l1_bound"] <= 1e-6
+        assert l1(out32[r], ref) <= 1e-6, (r, s)
+
+
 def test_literal_ifp2_matches_oracle_literal(pr):
     g = prgen.random_digraph(4000, 30000, seed=9, dangling_frac=0.25)
     dg = pr.upload(g.row_ptr, g.col)
