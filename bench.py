@@ -191,7 +191,7 @@ def main():
 
 def run_ppr(pr, dg, g, c, args):
     """Aggregate throughput of single-source PPR (IFP2, FP32 residuals, certified L1 <= tol):
-    the same queries one call per source, and in one call (batched eight per launch)."""
+    the same queries one call per source, and in one call (batched sixteen per launch)."""
     import numpy as np
     import torch
     rng = np.random.default_rng(7)
@@ -215,7 +215,7 @@ def run_ppr(pr, dg, g, c, args):
     log(f"[bench] PPR x{k}: one at a time {t_single * 1e3:.1f} ms, batched {t_batch * 1e3:.1f} ms")
     return {"queries": k, "one_at_a_time_ms": t_single * 1e3, "batched_ms": t_batch * 1e3,
             "one_at_a_time_gteps": k * g.m / t_single / 1e9, "batched_gteps": k * g.m / t_batch / 1e9,
-            "speedup": t_single / t_batch, "batch_width": 8,
+            "speedup": t_single / t_batch, "batch_width": 16,
             "mean_sweeps_single": float(np.mean([s["sweeps"] for s in single])),
             "mean_sweeps_batched": float(np.mean([s["sweeps"] for s in batched]))}
 

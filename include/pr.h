@@ -188,11 +188,15 @@ pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, d
 /*
  * Single-source personalized PageRank (section 2.1: p = e_s; the mass of
  * dangling vertices jumps back to s because P' = P + p d^T), solved by IFP2
- * for each of the k sources.
+ * for each of the k sources.  Up to 16 sources share one batched solve: their
+ * residual vectors are interleaved so that every gathered in-edge serves all of
+ * them, and each keeps its own stop decision (same result as one call per
+ * source, within the tolerances).  With PR_OUT_DEVICE, pi is a device pointer.
  *   sources  int32[k] host array, each in [0, n); k >= 1
  *   pi       double[k * n], row r is the PPR vector of sources[r]
  *   st       optional, k entries
- * Returns the worst status over the k solves.
+ * Returns the worst status over the k solves; on a negative status the rows of
+ * sources already solved may have been written.
  */
 pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_opts *o, double *pi,
                  pr_stats *st);

@@ -293,7 +293,7 @@ def last_trace() -> dict:
 
 def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, stream=None,
         mode=None, out=None):
-    """Single-source PPR for each source (IFP2, sources batched eight at a time);
+    """Single-source PPR for each source (IFP2, sources batched sixteen at a time);
     returns (float64[k, n], list of stats dicts).  `out` may be a (k, n) float64 numpy
     array or torch CUDA tensor."""
     src = np.ascontiguousarray(sources, dtype=np.int32)

@@ -438,5 +438,7 @@ hipError_t launch_final_b(CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm,
 
 PRK_BATCH_INST(float, 8)
 PRK_BATCH_INST(double, 8)
+PRK_BATCH_INST(float, 16)
+PRK_BATCH_INST(double, 16)
 
 }  // namespace prk

@@ -838,17 +838,19 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     return stopped ? PR_OK : PR_ENOCONV;
 }
 
-// Plans for the batched kernels (tiles of (kBlock / kBatch) * kMPK items), built
-// once per graph on the first batched solve.
+// Plans for the batched kernels of width B (tiles of (kBlock / B) * kMPK items),
+// built once per graph and width on the first batched solve.
+template <int B>
 pr_status ensure_batch_plans(Graph &G, hipStream_t s) {
+    constexpr int slot = B == 8 ? 0 : 1;
     std::lock_guard<std::mutex> lk(G.bp_mu);
-    if (G.bp_ready) return PR_OK;
+    if (G.bp_ready[slot]) return PR_OK;
     auto mk = [&](MPPlan &p, const uint32_t *rpp, const int32_t *idx, int32_t R, int64_t edges) -> hipError_t {
         p.rp = rpp;
         p.idx = idx;
         p.R = R;
         p.items = (uint32_t)(R + edges);
-        p.ipb = (kBlock / kBatch) * kMPK;
+        p.ipb = (kBlock / B) * kMPK;
         p.blocks = 0;
         const int32_t blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
         void *mem = nullptr;
@@ -860,29 +862,29 @@ pr_status ensure_batch_plans(Graph &G, hipStream_t s) {
         if (R == 0) return hipSuccess;
         return launch_plan(p, s);
     };
-    G.bp_pull_nn.clear();
+    G.bp_pull_nn[slot].clear();
     for (const Epoch &e : G.epochs) {
         MPPlan p;
         HIPCHK(mk(p, e.in_ptr, e.in_src, G.nN, e.edges_nn));
-        G.bp_pull_nn.push_back(p);
+        G.bp_pull_nn[slot].push_back(p);
     }
-    HIPCHK(mk(G.bp_pull_nd, G.in_ptr + G.nN, G.in_src, G.nD, G.mND));
-    HIPCHK(mk(G.bp_push_nn, G.rp_nn, G.col_nn, G.nN, G.mNN));
+    HIPCHK(mk(G.bp_pull_nd[slot], G.in_ptr + G.nN, G.in_src, G.nD, G.mND));
+    HIPCHK(mk(G.bp_push_nn[slot], G.rp_nn, G.col_nn, G.nN, G.mNN));
     HIPCHK(hipStreamSynchronize(s));
-    G.bp_ready = true;
+    G.bp_ready[slot] = true;
     return PR_OK;
 }
 
 // IFP2 for kb <= kBatch single-source PPR queries at once (pr_batch.hip):
 // column-interleaved residuals, per-column management, one gather serving all
 // columns.  pi_rows[r * n ...] receives the vector of srcs[r].
-template <typename T>
+template <typename T, int B>
 pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const pr_opts &o, double *pi_rows,
                             pr_stats *st) {
-    constexpr int B = kBatch;
+    constexpr int slot = B == 8 ? 0 : 1;
     Graph &G = const_cast<Graph &>(Gc);
     hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
-    pr_status ps = ensure_batch_plans(G, s);
+    pr_status ps = ensure_batch_plans<B>(G, s);
     if (ps != PR_OK) return ps;
     const int64_t n = G.n;
     const int32_t nN = G.nN, nD = G.nD;
@@ -932,7 +934,7 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     auto pull_plan = [&](int t) -> const MPPlan & {
         size_t e = 0;
         while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
-        return G.bp_pull_nn[e];
+        return G.bp_pull_nn[slot][e];
     };
     int t = 0;
     bool stopped = false;
@@ -948,7 +950,7 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
                 const double pull_thr = 0.25 * (double)pullp.edges();
                 HIPCHK(launch_reserve_b<T, B>(t, ctl, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, l1 ? 1 : 0, tol,
                                               pull_thr, force, (unsigned long long)pullp.edges(), part, s));
-                if (force != 2) HIPCHK(launch_push_b<T, B>(t, ctl, G.bp_push_nn, w, h, check_mode, s));
+                if (force != 2) HIPCHK(launch_push_b<T, B>(t, ctl, G.bp_push_nn[slot], w, h, check_mode, s));
                 if (force != 1) HIPCHK((launch_pull_b<T, T, B>(t, ctl, pullp, w, h, check_mode, s)));
             }
             HIPCHK(hipMemcpyAsync(hc, ctl, sizeof(CtlB), hipMemcpyDeviceToHost, s));
@@ -967,7 +969,7 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     } else {
         stopped = true;
     }
-    if (nD > 0) HIPCHK(launch_phase2_b<T, B>(n, nN, G.perm, ss, h, pibar, G.deg, c, w2, xD, G.bp_pull_nd, s));
+    if (nD > 0) HIPCHK(launch_phase2_b<T, B>(n, nN, G.perm, ss, h, pibar, G.deg, c, w2, xD, G.bp_pull_nd[slot], s));
     double *dst = out_dev ? pi_rows : outbuf;
     HIPCHK(launch_final_b<T, B>(ctl, n, nN, G.perm, kb, h, pibar, xD, dst, part, s));
     HIPCHK(hipEventRecord(ev_solve.b, s));
@@ -1142,9 +1144,12 @@ pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_
             if (kb == 1) {
                 rs = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, sources[r], op, rows, sr)
                                                 : solve_ifp_t<double>(G, true, nullptr, sources[r], op, rows, sr);
+            } else if (kb <= 8) {
+                rs = op.residual == PR_RES_FP32 ? solve_ppr_batch_t<float, 8>(G, sources + r, kb, op, rows, sr)
+                                                : solve_ppr_batch_t<double, 8>(G, sources + r, kb, op, rows, sr);
             } else {
-                rs = op.residual == PR_RES_FP32 ? solve_ppr_batch_t<float>(G, sources + r, kb, op, rows, sr)
-                                                : solve_ppr_batch_t<double>(G, sources + r, kb, op, rows, sr);
+                rs = op.residual == PR_RES_FP32 ? solve_ppr_batch_t<float, 16>(G, sources + r, kb, op, rows, sr)
+                                                : solve_ppr_batch_t<double, 16>(G, sources + r, kb, op, rows, sr);
             }
             if (rs < 0) return rs;
             if (rs > worst) worst = rs;

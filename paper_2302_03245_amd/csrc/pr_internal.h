@@ -17,7 +17,7 @@ constexpr int kRedBlocks = 1024;  // max workgroups of a streaming kernel that f
 constexpr int32_t kDepthInf = 0x7fffffff;  // unreferenced depth of vertices on or below a cycle
 constexpr int kMaxEpochs = 8;     // compacted in-edge lists kept per graph
 constexpr int kMPK = 8;           // default merge-path items (rows + edges) per thread (4, 8 or 16)
-constexpr int kBatch = 8;         // vectors per batched launch
+constexpr int kBatch = 16;        // vectors per batched launch (a batch of <= 8 uses width 8)
 
 // Merge-path work split over a CSR-like segment: rows r in [0, R) with edges
 // [rp[r], rp[r+1]).  The item sequence lists the edges of a row followed by an
@@ -111,12 +111,12 @@ struct Graph {
     uint32_t *in_ptr = nullptr;   // in-edges of every target (N targets first), [n + 1]
     int32_t *in_src = nullptr;    // [m]
     MPPlan push_nn, push_nd, pull_all, pull_nn, pull_nd;
-    // merge-path plans with tiles of (kBlock / kBatch) * kMPK items for the batched
-    // kernels, built on the first batched solve
+    // merge-path plans with tiles of (kBlock / B) * kMPK items for the batched kernels
+    // of width B = 8 (index 0) and 16 (index 1), built on the first batched solve
     std::mutex bp_mu;
-    bool bp_ready = false;
-    std::vector<MPPlan> bp_pull_nn;  // per epoch
-    MPPlan bp_pull_nd, bp_push_nn;
+    bool bp_ready[2] = {false, false};
+    std::vector<MPPlan> bp_pull_nn[2];  // per epoch
+    MPPlan bp_pull_nd[2], bp_push_nn[2];
     int32_t *depth = nullptr;     // unreferenced depth of non-dangling vertices, [nN]
     int32_t max_depth = -1;       // largest finite depth
     std::vector<Epoch> epochs;    // epochs[0] aliases the full in-edge lists

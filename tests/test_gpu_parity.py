@@ -248,13 +248,13 @@ def test_ppr_sources(pr):
 
 @pytest.mark.parametrize("mode", [None, "push", "pull"])
 def test_ppr_batches(pr, mode):
-    """Eleven sources: one batch of eight column-interleaved vectors and one of three,
-    each column against the oracle with p = e_s, FP64 and FP32 residuals."""
+    """Twenty-one sources: one batch of sixteen column-interleaved vectors and one of
+    five (width 8), each column against the oracle with p = e_s, FP64 and FP32 residuals."""
     g = prgen.workload_rmat_small(seed=5)
     dg = pr.upload(g.row_ptr, g.col)
     deg = np.diff(g.row_ptr)
     rng = np.random.default_rng(11)
-    srcs = [int(np.argmax(deg)), int(np.where(deg == 0)[0][3])] + [int(x) for x in rng.choice(g.n, 9, replace=False)]
+    srcs = [int(np.argmax(deg)), int(np.where(deg == 0)[0][3])] + [int(x) for x in rng.choice(g.n, 19, replace=False)]
     out, stats = pr.ppr(dg, srcs, c=C, xi=1e-12, mode=mode)
     out32, stats32 = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32", mode=mode)
     for r, s in enumerate(srcs):
