@@ -1,0 +1,88 @@
+/*
+ * pr_serve.h -- a PageRank / PPR query server over graphs resident in device
+ * memory (part of libpr.so).
+ *
+ * Queries are global PageRank (p = e/n) or single-source PPR (p = e_s), both
+ * solved by IFP2 (Algorithm 3 of Zhang, Tang, Yao, Liang, arXiv 2302.03245)
+ * with the certified L1 stop.  Each registered graph gets an engine: a host
+ * thread with its own HIP stream running a batched IFP2 solve whose columns
+ * are query slots.  Between rounds of sweeps an engine finishes the columns
+ * that met their bound (dangling phase + normalisation for those columns only)
+ * and admits waiting queries into free columns while the other columns keep
+ * iterating (continuous batching).  Engines of different graphs run
+ * concurrently on the device.  Admission by memory: a graph is accepted only
+ * if its engine's workspace fits in the server's device-memory budget; a query
+ * is admitted when its graph's engine has a free slot.
+ *
+ * Results equal those of pr_ppr / pr_solve_ifp2 on the same graph within the
+ * certified tolerance (the rounding order differs).
+ */
+#ifndef PR_SERVE_H
+#define PR_SERVE_H
+
+#include <stdint.h>
+
+#include "pr.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pr_server pr_server;
+
+typedef struct {
+    double c;                 /* damping factor, 0 < c < 1 */
+    double l1_tol;            /* certified L1 bound per query, > 0 */
+    int32_t residual;         /* PR_RES_FP32 or PR_RES_FP64 */
+    int32_t slots;            /* query columns per graph engine: 8 or 16 */
+    int32_t sweeps_per_round; /* sweeps between two admission / retirement points, >= 1 */
+    int32_t max_sweeps;       /* per query; 0 -> 100000 (a query reaching it ends with PR_ENOCONV) */
+    int64_t memory_budget;    /* device bytes the engines' workspaces may use; 0 -> 90 % of free memory */
+} pr_server_opts;
+
+typedef struct {
+    int64_t submitted, completed;
+    double p50_ms, p99_ms, mean_ms, max_ms; /* submit-to-completion latency of completed queries */
+    double edges_per_second;                /* sum of m over completed queries / (last completion - first submit) */
+    int64_t device_bytes;                   /* engine workspaces */
+} pr_server_stats;
+
+/* defaults: c 0.85, l1_tol 1e-6, FP32 residuals, 16 slots, 4 sweeps per round, budget 0 */
+void pr_server_opts_default(pr_server_opts *o);
+
+/* PR_EINVAL on invalid options. */
+pr_status pr_server_create(const pr_server_opts *o, pr_server **out);
+
+/*
+ * Register an uploaded graph; its engine starts immediately.  The graph stays
+ * owned by the caller and must outlive the server.  PR_ENOMEM if the engine's
+ * workspace does not fit in the remaining budget.
+ */
+pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id);
+
+/*
+ * Queue a query.  source = -1: global PageRank; else single-source PPR from that
+ * vertex (original id).  pi_device: device buffer of n doubles receiving the
+ * result, owned by the caller, untouched until the query completes.
+ */
+pr_status pr_server_submit(pr_server *s, int32_t graph_id, int32_t source, double *pi_device, int64_t *request_id);
+
+/*
+ * Wait for a query (timeout_seconds < 0: no limit).  Returns the query's status
+ * (PR_OK, PR_ENOCONV, or a negative error); PR_EDEVICE with "timeout" when the
+ * limit expires first (the query stays queued).  st (optional) receives its
+ * statistics; seconds_solve is its submit-to-completion latency.  A completed
+ * query can be waited for once.
+ */
+pr_status pr_server_wait(pr_server *s, int64_t request_id, double timeout_seconds, pr_stats *st);
+
+pr_status pr_server_get_stats(pr_server *s, pr_server_stats *out);
+
+/* Stop the engines (queued queries complete with PR_EINVAL) and free the server. */
+pr_status pr_server_destroy(pr_server *s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PR_SERVE_H */

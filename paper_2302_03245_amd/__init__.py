@@ -26,10 +26,12 @@ PR_INPUT_DEVICE, PR_DEDUPE = 0x1, 0x2
 PR_P_DEVICE, PR_OUT_DEVICE, PR_IFP2_LITERAL = 0x1, 0x2, 0x4
 PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE = 0x8, 0x10, 0x20
 
-# every symbol the two public headers declare
+# every symbol the public headers declare
 EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_info", "pr_solve_ifp1",
             "pr_solve_ifp2", "pr_solve_power", "pr_ppr", "pr_last_error", "pr_last_trace",
-            "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len"]
+            "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len",
+            "pr_server_opts_default", "pr_server_create", "pr_server_add_graph", "pr_server_submit",
+            "pr_server_wait", "pr_server_get_stats", "pr_server_destroy"]
 
 
 class PRError(RuntimeError):
@@ -57,6 +59,18 @@ class Stats(ctypes.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("c", ctypes.c_double), ("l1_tol", ctypes.c_double), ("residual", ctypes.c_int32),
+                ("slots", ctypes.c_int32), ("sweeps_per_round", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
+                ("memory_budget", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("edges_per_second", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -111,6 +125,20 @@ def lib():
     L.pr_probe_scatter.restype = ctypes.c_int
     L.pr_probe_gather_out_len.argtypes = [i64]
     L.pr_probe_gather_out_len.restype = i64
+    L.pr_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
+    L.pr_server_opts_default.restype = None
+    L.pr_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
+    L.pr_server_create.restype = ctypes.c_int
+    L.pr_server_add_graph.argtypes = [vp, vp, ctypes.POINTER(i32)]
+    L.pr_server_add_graph.restype = ctypes.c_int
+    L.pr_server_submit.argtypes = [vp, i32, i32, vp, ctypes.POINTER(i64)]
+    L.pr_server_submit.restype = ctypes.c_int
+    L.pr_server_wait.argtypes = [vp, i64, ctypes.c_double, ctypes.POINTER(Stats)]
+    L.pr_server_wait.restype = ctypes.c_int
+    L.pr_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
+    L.pr_server_get_stats.restype = ctypes.c_int
+    L.pr_server_destroy.argtypes = [vp]
+    L.pr_server_destroy.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -312,3 +340,72 @@ def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_s
     if status < 0:
         raise _err(status)
     return out, [dict(st[i].as_dict(), status=status) for i in range(k)]
+
+
+class Server:
+    """Query server over resident graphs (include/pr_serve.h): global PageRank and
+    single-source PPR queries, continuously batched per graph, engines overlapping
+    on the device.  Results are written into caller-owned torch CUDA float64 tensors."""
+
+    def __init__(self, c=0.85, l1_tol=1e-6, residual="fp32", slots=16, sweeps_per_round=4, max_sweeps=0,
+                 memory_budget=0):
+        L = lib()
+        o = ServerOpts()
+        L.pr_server_opts_default(ctypes.byref(o))
+        o.c, o.l1_tol = c, l1_tol
+        o.residual = {"fp64": PR_RES_FP64, "fp32": PR_RES_FP32}[residual]
+        o.slots, o.sweeps_per_round, o.max_sweeps, o.memory_budget = slots, sweeps_per_round, max_sweeps, memory_budget
+        h = ctypes.c_void_p()
+        st = L.pr_server_create(ctypes.byref(o), ctypes.byref(h))
+        if st != PR_OK:
+            raise _err(st)
+        self._h = h.value
+        self._graphs = []   # keep the graphs alive while the server runs
+        self._outs = {}
+
+    def add_graph(self, g: Graph) -> int:
+        gid = ctypes.c_int32()
+        st = lib().pr_server_add_graph(self._h, g.handle, ctypes.byref(gid))
+        if st != PR_OK:
+            raise _err(st)
+        self._graphs.append(g)
+        return gid.value
+
+    def submit(self, graph_id: int, source: int, out) -> int:
+        """source = -1: global PageRank; out: contiguous torch CUDA float64 tensor of n entries."""
+        if not (_is_torch(out) and out.is_cuda and str(out.dtype) == "torch.float64" and out.is_contiguous()):
+            raise TypeError("out must be a contiguous CUDA float64 tensor")
+        rid = ctypes.c_int64()
+        st = lib().pr_server_submit(self._h, graph_id, source, out.data_ptr(), ctypes.byref(rid))
+        if st != PR_OK:
+            raise _err(st)
+        self._outs[rid.value] = out
+        return rid.value
+
+    def wait(self, request_id: int, timeout: float = -1.0) -> dict:
+        s = Stats()
+        st = lib().pr_server_wait(self._h, request_id, timeout, ctypes.byref(s))
+        self._outs.pop(request_id, None)
+        if st < 0:
+            raise _err(st)
+        d = s.as_dict()
+        d["status"] = st
+        return d
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        st = lib().pr_server_get_stats(self._h, ctypes.byref(s))
+        if st != PR_OK:
+            raise _err(st)
+        return {k: getattr(s, k) for k, _ in s._fields_}
+
+    def close(self):
+        if self._h is not None:
+            lib().pr_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -25,13 +25,24 @@ __device__ __forceinline__ double block_sum_cols(double v, double *sbuf /* [kBlo
     return r;
 }
 
+// initial residual of column j at vertex v: n at the source (p = e_s), 1 everywhere
+// for a global PageRank column (p = e / n), 0 for an unused column
+template <typename T>
+__device__ __forceinline__ double h0_col(int32_t s, int32_t orig, int64_t n) {
+    if (s == kSrcUniform) return 1.0;
+    return (s >= 0 && orig == s) ? (double)n : 0.0;
+}
+
+// (re)initialise the columns in `mask`; the others are left untouched
 template <typename T, int B>
-__global__ void k_init_b(int64_t n, int32_t nN, const int32_t *perm, SrcSet src, T *h, double *pibar) {
+__global__ void k_init_b(int64_t n, int32_t nN, const int32_t *perm, SrcSet src, uint32_t mask, T *h,
+                         double *pibar) {
     const int64_t total = n * B;
     for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
+        const int j = (int)(idx % B);
+        if (!((mask >> j) & 1u)) continue;
         const int64_t v = idx / B;
-        const int32_t s = src.s[idx % B];
-        h[idx] = (s >= 0 && perm[v] == s) ? (T)n : (T)0;
+        h[idx] = (T)h0_col<T>(src.s[j], perm[v], n);
         if (v < nN) pibar[idx] = 0.0;
     }
 }
@@ -296,8 +307,7 @@ __global__ void k_phase2_prep_b(int64_t n, int32_t nN, const int32_t *perm, SrcS
         if (v < nN) {
             w2[idx] = c * (pibar[idx] + (double)h[idx]) / (double)deg[v];
         } else {
-            const int32_t s = src.s[idx % B];
-            xD[idx - (int64_t)nN * B] = (s >= 0 && perm[v] == s) ? (double)n : 0.0;
+            xD[idx - (int64_t)nN * B] = h0_col<T>(src.s[idx % B], perm[v], n);
         }
     }
 }
@@ -340,16 +350,16 @@ __global__ __launch_bounds__(1024) void k_final_decide_b(CtlB *ctl, int nb, cons
     }
 }
 
-// pi[j * n + original id] = x / sum_j for the k_real leading columns
+// out.p[j][original id] = x / sum_j for the columns in `mask`
 template <typename T, int B>
-__global__ void k_final_write_b(const CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, int k_real,
-                                const T *h, const double *pibar, const double *xD, double *out) {
+__global__ void k_final_write_b(const CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, uint32_t mask,
+                                OutSet out, const T *h, const double *pibar, const double *xD) {
     const int64_t total = n * B;
     for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
         const int jj = (int)(idx % B);
-        if (jj >= k_real) continue;
+        if (!((mask >> jj) & 1u)) continue;
         const int64_t v = idx / B;
-        out[(int64_t)jj * n + perm[v]] = x_b<T, B>(idx, nN, h, pibar, xD) / ctl->fin_sum[jj];
+        out.p[jj][perm[v]] = x_b<T, B>(idx, nN, h, pibar, xD) / ctl->fin_sum[jj];
     }
 }
 
@@ -359,10 +369,10 @@ __global__ void k_final_write_b(const CtlB *ctl, int64_t n, int32_t nN, const in
 // launchers
 // ---------------------------------------------------------------------------
 template <typename T, int B>
-hipError_t launch_init_b(int64_t n, int32_t nN, const int32_t *perm, const SrcSet &src, T *h, double *pibar,
-                         hipStream_t s) {
+hipError_t launch_init_b(int64_t n, int32_t nN, const int32_t *perm, const SrcSet &src, uint32_t mask, T *h,
+                         double *pibar, hipStream_t s) {
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_init_b<T, B>), dim3(grid_for(n * B, 4, 16384)), dim3(kBlock), 0, s, n, nN,
-                       perm, src, h, pibar);
+                       perm, src, mask, h, pibar);
     return hipGetLastError();
 }
 
@@ -411,20 +421,20 @@ hipError_t launch_phase2_b(int64_t n, int32_t nN, const int32_t *perm, const Src
 }
 
 template <typename T, int B>
-hipError_t launch_final_b(CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, int k_real, const T *h,
-                          const double *pibar, const double *xD, double *out, double *part, hipStream_t s) {
+hipError_t launch_final_b(CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, uint32_t mask, const OutSet &out,
+                          const T *h, const double *pibar, const double *xD, double *part, hipStream_t s) {
     const int nb = grid_for(n * B, 4, kRedBlocks);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_final_sum_b<T, B>), dim3(nb), dim3(kBlock), 0, s, n, nN, h, pibar, xD, part);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_final_decide_b<B>), dim3(1), dim3(1024), 0, s, ctl, nb,
                        (const double *)part);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_final_write_b<T, B>), dim3(grid_for(n * B, 4, 16384)), dim3(kBlock), 0, s,
-                       (const CtlB *)ctl, n, nN, perm, k_real, h, pibar, xD, out);
+                       (const CtlB *)ctl, n, nN, perm, mask, out, h, pibar, xD);
     return hipGetLastError();
 }
 
 #define PRK_BATCH_INST(T, B)                                                                                         \
-    template hipError_t launch_init_b<T, B>(int64_t, int32_t, const int32_t *, const SrcSet &, T *, double *,       \
-                                            hipStream_t);                                                            \
+    template hipError_t launch_init_b<T, B>(int64_t, int32_t, const int32_t *, const SrcSet &, uint32_t, T *,       \
+                                            double *, hipStream_t);                                                  \
     template hipError_t launch_reserve_b<T, B>(int, CtlB *, int32_t, T *, T *, double *, const int32_t *,           \
                                                const uint32_t *, double, double, int, double, double, int,          \
                                                unsigned long long, double *, hipStream_t);                          \
@@ -433,8 +443,8 @@ hipError_t launch_final_b(CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm,
     template hipError_t launch_phase2_b<T, B>(int64_t, int32_t, const int32_t *, const SrcSet &, const T *,         \
                                               const double *, const int32_t *, double, double *, double *,          \
                                               const MPPlan &, hipStream_t);                                          \
-    template hipError_t launch_final_b<T, B>(CtlB *, int64_t, int32_t, const int32_t *, int, const T *,             \
-                                             const double *, const double *, double *, double *, hipStream_t);
+    template hipError_t launch_final_b<T, B>(CtlB *, int64_t, int32_t, const int32_t *, uint32_t, const OutSet &,  \
+                                             const T *, const double *, const double *, double *, hipStream_t);
 
 PRK_BATCH_INST(float, 8)
 PRK_BATCH_INST(double, 8)

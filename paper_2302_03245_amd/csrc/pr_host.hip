@@ -18,9 +18,6 @@
 
 using namespace prk;
 
-struct pr_graph {
-    Graph g;
-};
 
 namespace {
 
@@ -841,7 +838,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
 // Plans for the batched kernels of width B (tiles of (kBlock / B) * kMPK items),
 // built once per graph and width on the first batched solve.
 template <int B>
-pr_status ensure_batch_plans(Graph &G, hipStream_t s) {
+pr_status ensure_batch_plans_impl(Graph &G, hipStream_t s) {
     constexpr int slot = B == 8 ? 0 : 1;
     std::lock_guard<std::mutex> lk(G.bp_mu);
     if (G.bp_ready[slot]) return PR_OK;
@@ -884,7 +881,7 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     constexpr int slot = B == 8 ? 0 : 1;
     Graph &G = const_cast<Graph &>(Gc);
     hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
-    pr_status ps = ensure_batch_plans<B>(G, s);
+    pr_status ps = ensure_batch_plans_impl<B>(G, s);
     if (ps != PR_OK) return ps;
     const int64_t n = G.n;
     const int32_t nN = G.nN, nD = G.nD;
@@ -927,7 +924,8 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     EventPair ev_solve;
     HIPCHK(hipEventRecord(ev_solve.a, s));
     HIPCHK(hipMemcpyAsync(ctl, hc, sizeof(CtlB), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_init_b<T, B>(n, nN, G.perm, ss, h, pibar, s));
+    const uint32_t kmask = (uint32_t)((1ull << kb) - 1ull);
+    HIPCHK(launch_init_b<T, B>(n, nN, G.perm, ss, kmask, h, pibar, s));
 
     const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
     const int check_mode = force == 0;
@@ -971,7 +969,9 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     }
     if (nD > 0) HIPCHK(launch_phase2_b<T, B>(n, nN, G.perm, ss, h, pibar, G.deg, c, w2, xD, G.bp_pull_nd[slot], s));
     double *dst = out_dev ? pi_rows : outbuf;
-    HIPCHK(launch_final_b<T, B>(ctl, n, nN, G.perm, kb, h, pibar, xD, dst, part, s));
+    OutSet os;
+    for (int j = 0; j < kMaxBatch; ++j) os.p[j] = j < kb ? dst + (size_t)j * n : nullptr;
+    HIPCHK(launch_final_b<T, B>(ctl, n, nN, G.perm, kmask, os, h, pibar, xD, part, s));
     HIPCHK(hipEventRecord(ev_solve.b, s));
     HIPCHK(hipMemcpyAsync(hc, ctl, sizeof(CtlB), hipMemcpyDeviceToHost, s));
     if (!out_dev) HIPCHK(hipMemcpyAsync(pi_rows, outbuf, sizeof(double) * (size_t)kb * n, hipMemcpyDeviceToHost, s));
@@ -1009,6 +1009,14 @@ pr_status enter(const pr_graph *g) {
 }
 
 }  // namespace
+
+namespace prk {
+pr_status set_error(pr_status st, const std::string &msg) { return fail(st, msg); }
+pr_status batch_plans(Graph &G, int B, hipStream_t s) {
+    return B == 8 ? ensure_batch_plans_impl<8>(G, s) : ensure_batch_plans_impl<16>(G, s);
+}
+void clear_error() { g_err.clear(); }
+}  // namespace prk
 
 // ---------------------------------------------------------------------------
 // C ABI

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "../../include/pr.h"
+
 #include <mutex>
 #include <string>
 #include <vector>
@@ -73,9 +75,15 @@ struct alignas(128) CtlB {
     double fin_sum[kMaxBatch], fin_sn[kMaxBatch];
 };
 
-// sources of a batch (original ids; -1 = unused column), passed by value
+// sources of a batch (original ids; kSrcUnused = unused column, kSrcUniform =
+// global PageRank column), passed by value
+constexpr int32_t kSrcUnused = -1, kSrcUniform = -2;
 struct SrcSet {
     int32_t s[kMaxBatch];
+};
+// output vector of each column (device pointers), passed by value
+struct OutSet {
+    double *p[kMaxBatch];
 };
 
 struct Trace {
@@ -132,6 +140,11 @@ struct Graph {
     void *ws_mem = nullptr;
     size_t ws_bytes = 0;
 };
+
+// host helpers shared by the host translation units (pr_host.hip)
+pr_status set_error(pr_status st, const std::string &msg);
+void clear_error();
+pr_status batch_plans(Graph &G, int B, hipStream_t s);  // B = 8 or 16
 
 // ---- kernel launchers (pr_kernels.hip) ----
 hipError_t launch_check_cols(const int32_t *col, int64_t m, int64_t n, unsigned int *bad, hipStream_t s);
@@ -200,8 +213,8 @@ hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStr
 
 // batched IFP2 (pr_batch.hip)
 template <typename T, int B>
-hipError_t launch_init_b(int64_t n, int32_t nN, const int32_t *perm, const SrcSet &src, T *h, double *pibar,
-                         hipStream_t s);
+hipError_t launch_init_b(int64_t n, int32_t nN, const int32_t *perm, const SrcSet &src, uint32_t mask, T *h,
+                         double *pibar, hipStream_t s);
 template <typename T, int B>
 hipError_t launch_reserve_b(int t, CtlB *ctl, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
                             const uint32_t *rp_nn, double c, double xi, int stop_l1, double tol, double pull_thr,
@@ -216,7 +229,11 @@ hipError_t launch_phase2_b(int64_t n, int32_t nN, const int32_t *perm, const Src
                            const double *pibar, const int32_t *deg, double c, double *w2, double *xD,
                            const MPPlan &pull_nd, hipStream_t s);
 template <typename T, int B>
-hipError_t launch_final_b(CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, int k_real, const T *h,
-                          const double *pibar, const double *xD, double *out, double *part, hipStream_t s);
+hipError_t launch_final_b(CtlB *ctl, int64_t n, int32_t nN, const int32_t *perm, uint32_t mask, const OutSet &out,
+                          const T *h, const double *pibar, const double *xD, double *part, hipStream_t s);
 
 }  // namespace prk
+
+struct pr_graph {
+    prk::Graph g;
+};

@@ -1,0 +1,442 @@
+// pr_serve.hip -- query server of include/pr_serve.h: one engine (host thread +
+// HIP stream + batched IFP2 workspace) per resident graph, query slots = columns
+// of the batched solve, continuous admission and retirement between rounds.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <climits>
+#include <condition_variable>
+#include <deque>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/pr_serve.h"
+#include "pr_internal.h"
+
+using namespace prk;
+
+namespace {
+
+double now_s() {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align256(size_t v) { return (v + 255) / 256 * 256; }
+
+struct Request {
+    int64_t id = 0;
+    int32_t gid = 0;
+    int32_t source = -1;
+    double *out = nullptr;
+    double t_submit = 0, t_done = 0;
+    bool done = false;
+    pr_status status = PR_OK;
+    pr_stats st{};
+    std::string err;
+};
+
+struct Engine;
+
+}  // namespace
+
+struct pr_server {
+    pr_server_opts o{};
+    std::mutex mu;
+    std::condition_variable cv_done;
+    std::vector<std::unique_ptr<Engine>> engines;
+    std::unordered_map<int64_t, std::shared_ptr<Request>> reqs;
+    int64_t next_id = 1;
+    int64_t submitted = 0;
+    std::vector<double> lat_ms;
+    double edges_done = 0, t_first = -1, t_last = 0;
+    int64_t budget = 0, used = 0;
+    std::atomic<bool> stop{false};
+};
+
+namespace {
+
+struct Engine {
+    pr_server *srv = nullptr;
+    const Graph *G = nullptr;
+    int32_t gid = 0;
+    int B = 16;
+    bool fp32 = true;
+    hipStream_t stream = nullptr;
+    char *ws = nullptr;
+    size_t ws_bytes = 0;
+    CtlB *hctl = nullptr;  // pinned
+    std::deque<std::shared_ptr<Request>> queue;  // guarded by srv->mu
+    std::condition_variable cv_work;
+    std::thread th;
+
+    ~Engine() {
+        if (th.joinable()) th.join();
+        if (ws) (void)hipFree(ws);
+        if (hctl) (void)hipHostFree(hctl);
+        if (stream) (void)hipStreamDestroy(stream);
+    }
+
+    // workspace of the batched solve (same carving for both residual types)
+    static size_t footprint(const Graph &G, int B, bool fp32) {
+        const size_t sT = fp32 ? 4 : 8;
+        size_t b = 0;
+        b += align256((size_t)G.n * B * sT);
+        b += align256((size_t)G.nN * B * sT);
+        b += align256((size_t)G.nN * B * 8);
+        b += align256((size_t)std::max<int32_t>(G.nD, 1) * B * 8);
+        b += align256((size_t)G.nN * B * 8);
+        b += align256(sizeof(CtlB));
+        b += align256((size_t)4 * B * kRedBlocks * 8);
+        return b;
+    }
+
+    template <typename T, int Bw>
+    void run();
+};
+
+// Engine loop for residual type T and width Bw.
+template <typename T, int Bw>
+void Engine::run() {
+    const Graph &g = *G;
+    (void)hipSetDevice(g.device);
+    hipStream_t s = stream;
+    const int64_t n = g.n;
+    const int32_t nN = g.nN, nD = g.nD;
+    const double c = srv->o.c;
+    const double tol = srv->o.l1_tol * (1.0 - 1e-6);
+    const double xi = srv->o.l1_tol * (1.0 - c) / (2.0 * c) * (double)n / (double)std::max<int32_t>(nN, 1) *
+                      (1.0 - 1e-9);
+    const int S = srv->o.sweeps_per_round;
+    const int max_sweeps = srv->o.max_sweeps > 0 ? srv->o.max_sweeps : 100000;
+    const int slot = Bw == 8 ? 0 : 1;
+
+    char *p = ws;
+    auto take = [&](size_t bytes) {
+        char *r = p;
+        p += align256(bytes);
+        return r;
+    };
+    T *h = (T *)take((size_t)n * Bw * sizeof(T));
+    T *w = (T *)take((size_t)nN * Bw * sizeof(T));
+    double *pibar = (double *)take((size_t)nN * Bw * 8);
+    double *xD = (double *)take((size_t)std::max<int32_t>(nD, 1) * Bw * 8);
+    double *w2 = (double *)take((size_t)nN * Bw * 8);
+    CtlB *dctl = (CtlB *)take(sizeof(CtlB));
+    double *part = (double *)take((size_t)4 * Bw * kRedBlocks * 8);
+
+    std::shared_ptr<Request> slots[kMaxBatch];
+    int t0[kMaxBatch] = {0};
+    SrcSet ss;
+    for (int j = 0; j < kMaxBatch; ++j) ss.s[j] = kSrcUnused;
+    memset(hctl, 0, sizeof(CtlB));
+    hctl->stop_after = INT_MAX;
+    for (int j = 0; j < kMaxBatch; ++j) hctl->col_stop[j] = -1;
+    int t = 0;
+    bool ok = true;
+    std::string err;
+    auto chk = [&](hipError_t e, const char *what) {
+        if (e != hipSuccess && ok) {
+            ok = false;
+            err = std::string(what) + ": " + hipGetErrorString(e);
+        }
+        return e == hipSuccess;
+    };
+
+    while (!srv->stop.load()) {
+        // ---- admission
+        uint32_t admit = 0;
+        int live = 0;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            for (int j = 0; j < Bw; ++j) {
+                if (!slots[j] && !queue.empty()) {
+                    slots[j] = queue.front();
+                    queue.pop_front();
+                    admit |= 1u << j;
+                    t0[j] = t;
+                }
+                live += slots[j] ? 1 : 0;
+            }
+            if (live == 0) {
+                cv_work.wait_for(lk, std::chrono::milliseconds(50),
+                                 [&] { return srv->stop.load() || !queue.empty(); });
+                continue;
+            }
+        }
+        if (admit) {
+            for (int j = 0; j < Bw; ++j) {
+                if (!((admit >> j) & 1u)) continue;
+                ss.s[j] = slots[j]->source >= 0 ? slots[j]->source : kSrcUniform;
+                hctl->col_stop[j] = INT_MAX;
+                hctl->col_sweeps[j] = 0;
+                hctl->sx[j] = (double)n;
+                hctl->last_bound[j] = INFINITY;
+                hctl->tot_pushes[j] = 0;
+                hctl->tot_edges[j] = 0;
+            }
+            hctl->stop_after = INT_MAX;
+            chk(hipMemcpyAsync(dctl, hctl, sizeof(CtlB), hipMemcpyHostToDevice, s), "control block");
+            chk(launch_init_b<T, Bw>(n, nN, g.perm, ss, admit, h, pibar, s), "init");
+        }
+        // ---- a round of sweeps; the gather uses the epoch of the youngest live column
+        int youngest = INT_MAX;
+        for (int j = 0; j < Bw; ++j)
+            if (slots[j]) youngest = std::min(youngest, t - t0[j]);
+        for (int k = 0; k < S && ok && nN > 0; ++k, ++t, ++youngest) {
+            size_t e = 0;
+            while (e + 1 < g.epochs.size() && g.epochs[e + 1].t_start <= youngest) ++e;
+            const MPPlan &pullp = g.bp_pull_nn[slot][e];
+            chk(launch_reserve_b<T, Bw>(t, dctl, nN, h, w, pibar, g.deg, g.rp_nn, c, xi, 1, tol,
+                                        0.25 * (double)pullp.edges(), 0, (unsigned long long)pullp.edges(), part, s),
+                "reserve");
+            chk(launch_push_b<T, Bw>(t, dctl, g.bp_push_nn[slot], w, h, 1, s), "push");
+            chk(launch_pull_b<T, T, Bw>(t, dctl, pullp, w, h, 1, s), "pull");
+        }
+        chk(hipMemcpyAsync(hctl, dctl, sizeof(CtlB), hipMemcpyDeviceToHost, s), "control block");
+        chk(hipStreamSynchronize(s), "sweeps");
+        // ---- retirement of the columns that met their bound (or ran out of sweeps)
+        uint32_t fin = 0;
+        OutSet os;
+        for (int j = 0; j < kMaxBatch; ++j) os.p[j] = nullptr;
+        for (int j = 0; j < Bw; ++j) {
+            if (!slots[j]) continue;
+            if (!ok || nN == 0 || hctl->col_stop[j] < t || t - t0[j] >= max_sweeps) {
+                fin |= 1u << j;
+                os.p[j] = slots[j]->out;
+            }
+        }
+        if (!fin) continue;
+        if (ok && nD > 0) chk(launch_phase2_b<T, Bw>(n, nN, g.perm, ss, h, pibar, g.deg, c, w2, xD, g.bp_pull_nd[slot], s),
+                              "dangling phase");
+        if (ok) chk(launch_final_b<T, Bw>(dctl, n, nN, g.perm, fin, os, h, pibar, xD, part, s), "normalisation");
+        if (ok) chk(hipMemcpyAsync(hctl, dctl, sizeof(CtlB), hipMemcpyDeviceToHost, s), "control block");
+        if (ok) chk(hipStreamSynchronize(s), "normalisation");
+        const double tnow = now_s();
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            for (int j = 0; j < Bw; ++j) {
+                if (!((fin >> j) & 1u)) continue;
+                Request &r = *slots[j];
+                r.t_done = tnow;
+                r.done = true;
+                memset(&r.st, 0, sizeof(r.st));
+                if (!ok) {
+                    r.status = PR_EDEVICE;
+                    r.err = err;
+                } else {
+                    const bool conv = hctl->col_stop[j] < t || nN == 0;
+                    r.status = conv ? PR_OK : PR_ENOCONV;
+                    r.st.sweeps = hctl->col_sweeps[j];
+                    r.st.edges_processed = (int64_t)hctl->tot_edges[j] + g.mND;
+                    r.st.vertex_pushes = (int64_t)hctl->tot_pushes[j];
+                    const double fs = hctl->fin_sum[j];
+                    r.st.residual_l1 = fs > 0 ? hctl->fin_sn[j] / fs : 0.0;
+                    r.st.l1_bound = fs > 0 ? 2.0 * c / (1.0 - c) * hctl->fin_sn[j] / fs : 0.0;
+                    r.st.seconds_solve = r.t_done - r.t_submit;
+                    r.st.seconds_preprocess = g.seconds_split;
+                }
+                srv->lat_ms.push_back((r.t_done - r.t_submit) * 1e3);
+                srv->edges_done += (double)g.m;
+                srv->t_last = std::max(srv->t_last, tnow);
+                slots[j].reset();
+                ss.s[j] = kSrcUnused;
+                hctl->col_stop[j] = -1;
+            }
+        }
+        // the host copy of the control block stays authoritative for the next admission
+        srv->cv_done.notify_all();
+        if (!ok) break;
+    }
+    // fail whatever is left
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (int j = 0; j < Bw; ++j) {
+        if (!slots[j]) continue;
+        slots[j]->done = true;
+        slots[j]->status = ok ? PR_EINVAL : PR_EDEVICE;
+        slots[j]->err = ok ? "server destroyed" : err;
+    }
+    for (auto &r : queue) {
+        r->done = true;
+        r->status = ok ? PR_EINVAL : PR_EDEVICE;
+        r->err = ok ? "server destroyed" : err;
+    }
+    queue.clear();
+    srv->cv_done.notify_all();
+}
+
+}  // namespace
+
+extern "C" {
+
+void pr_server_opts_default(pr_server_opts *o) {
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->c = 0.85;
+    o->l1_tol = 1e-6;
+    o->residual = PR_RES_FP32;
+    o->slots = 16;
+    o->sweeps_per_round = 4;
+}
+
+pr_status pr_server_create(const pr_server_opts *o, pr_server **out) {
+    clear_error();
+    if (!out) return set_error(PR_EINVAL, "out is NULL");
+    pr_server_opts op;
+    if (o) op = *o;
+    else pr_server_opts_default(&op);
+    if (!(op.c > 0.0 && op.c < 1.0)) return set_error(PR_EINVAL, "c must be in (0, 1)");
+    if (!(op.l1_tol > 0.0) || !isfinite(op.l1_tol)) return set_error(PR_EINVAL, "l1_tol must be > 0 and finite");
+    if (op.residual != PR_RES_FP32 && op.residual != PR_RES_FP64) return set_error(PR_EINVAL, "unknown residual type");
+    if (op.slots != 8 && op.slots != 16) return set_error(PR_EINVAL, "slots must be 8 or 16");
+    if (op.sweeps_per_round < 1) return set_error(PR_EINVAL, "sweeps_per_round must be >= 1");
+    if (op.max_sweeps < 0 || op.memory_budget < 0) return set_error(PR_EINVAL, "negative limit");
+    std::unique_ptr<pr_server> sv(new (std::nothrow) pr_server());
+    if (!sv) return set_error(PR_ENOMEM, "host allocation");
+    sv->o = op;
+    if (op.memory_budget > 0) {
+        sv->budget = op.memory_budget;
+    } else {
+        size_t fr = 0, tot = 0;
+        hipError_t e = hipMemGetInfo(&fr, &tot);
+        if (e != hipSuccess) return set_error(PR_EDEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
+        sv->budget = (int64_t)(0.9 * (double)fr);
+    }
+    *out = sv.release();
+    return PR_OK;
+}
+
+pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id) {
+    clear_error();
+    if (!s || !g || !graph_id) return set_error(PR_EINVAL, "NULL argument");
+    const Graph &G = g->g;
+    const bool fp32 = s->o.residual == PR_RES_FP32;
+    const size_t fp = Engine::footprint(G, s->o.slots, fp32);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->used + (int64_t)fp > s->budget)
+            return set_error(PR_ENOMEM, "graph engine workspace exceeds the server's memory budget");
+        s->used += (int64_t)fp;
+    }
+    std::unique_ptr<Engine> eng(new (std::nothrow) Engine());
+    auto undo = [&](pr_status st, const std::string &m) {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->used -= (int64_t)fp;
+        return set_error(st, m);
+    };
+    if (!eng) return undo(PR_ENOMEM, "host allocation");
+    eng->srv = s;
+    eng->G = &G;
+    eng->B = s->o.slots;
+    eng->fp32 = fp32;
+    hipError_t e = hipSetDevice(G.device);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&eng->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return undo(PR_EDEVICE, std::string("stream: ") + hipGetErrorString(e));
+    pr_status ps = batch_plans(const_cast<Graph &>(G), eng->B, eng->stream);
+    if (ps != PR_OK) return undo(ps, "batch plans");
+    e = hipMalloc((void **)&eng->ws, fp);
+    if (e != hipSuccess) return undo(PR_ENOMEM, std::string("engine workspace: ") + hipGetErrorString(e));
+    eng->ws_bytes = fp;
+    e = hipHostMalloc((void **)&eng->hctl, sizeof(CtlB), hipHostMallocDefault);
+    if (e != hipSuccess) return undo(PR_ENOMEM, "pinned control block");
+    Engine *ep = eng.get();
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        ep->gid = (int32_t)s->engines.size();
+        s->engines.push_back(std::move(eng));
+    }
+    if (ep->fp32) ep->th = std::thread(ep->B == 8 ? &Engine::run<float, 8> : &Engine::run<float, 16>, ep);
+    else ep->th = std::thread(ep->B == 8 ? &Engine::run<double, 8> : &Engine::run<double, 16>, ep);
+    *graph_id = ep->gid;
+    return PR_OK;
+}
+
+pr_status pr_server_submit(pr_server *s, int32_t graph_id, int32_t source, double *pi_device, int64_t *request_id) {
+    clear_error();
+    if (!s || !pi_device || !request_id) return set_error(PR_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (graph_id < 0 || graph_id >= (int32_t)s->engines.size()) return set_error(PR_EINVAL, "unknown graph id");
+    Engine &eng = *s->engines[(size_t)graph_id];
+    if (source < -1 || source >= eng.G->n) return set_error(PR_EINVAL, "source out of [-1, n)");
+    auto r = std::make_shared<Request>();
+    r->id = s->next_id++;
+    r->gid = graph_id;
+    r->source = source;
+    r->out = pi_device;
+    r->t_submit = now_s();
+    if (s->t_first < 0) s->t_first = r->t_submit;
+    s->reqs[r->id] = r;
+    s->submitted += 1;
+    eng.queue.push_back(r);
+    eng.cv_work.notify_one();
+    *request_id = r->id;
+    return PR_OK;
+}
+
+pr_status pr_server_wait(pr_server *s, int64_t request_id, double timeout_seconds, pr_stats *st) {
+    clear_error();
+    if (!s) return set_error(PR_EINVAL, "server is NULL");
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->reqs.find(request_id);
+    if (it == s->reqs.end()) return set_error(PR_EINVAL, "unknown or already collected request");
+    std::shared_ptr<Request> r = it->second;
+    auto pred = [&] { return r->done; };
+    if (timeout_seconds < 0) {
+        s->cv_done.wait(lk, pred);
+    } else if (!s->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_seconds), pred)) {
+        return set_error(PR_EDEVICE, "timeout");
+    }
+    s->reqs.erase(it);
+    if (st) *st = r->st;
+    if (r->status < 0) return set_error(r->status, r->err);
+    return r->status;
+}
+
+pr_status pr_server_get_stats(pr_server *s, pr_server_stats *out) {
+    clear_error();
+    if (!s || !out) return set_error(PR_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    memset(out, 0, sizeof(*out));
+    out->submitted = s->submitted;
+    out->completed = (int64_t)s->lat_ms.size();
+    out->device_bytes = s->used;
+    if (!s->lat_ms.empty()) {
+        std::vector<double> v = s->lat_ms;
+        std::sort(v.begin(), v.end());
+        auto q = [&](double f) { return v[(size_t)std::min<double>((double)v.size() - 1, floor(f * (double)v.size()))]; };
+        out->p50_ms = q(0.50);
+        out->p99_ms = q(0.99);
+        out->max_ms = v.back();
+        double sum = 0;
+        for (double x : v) sum += x;
+        out->mean_ms = sum / (double)v.size();
+        const double span = s->t_last - s->t_first;
+        out->edges_per_second = span > 0 ? s->edges_done / span : 0.0;
+    }
+    return PR_OK;
+}
+
+pr_status pr_server_destroy(pr_server *s) {
+    clear_error();
+    if (!s) return PR_OK;
+    s->stop.store(true);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        for (auto &e : s->engines) e->cv_work.notify_all();
+    }
+    for (auto &e : s->engines)
+        if (e->th.joinable()) e->th.join();
+    s->engines.clear();
+    delete s;
+    return PR_OK;
+}
+
+}  // extern "C"

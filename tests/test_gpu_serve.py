@@ -1,0 +1,98 @@
+"""The query server (include/pr_serve.h): every result is the same alone and in the mix.
+
+Queries (global PageRank and single-source PPR) on two resident graphs arrive in
+waves while earlier ones are still on the device; each result is compared with
+the same query solved alone through pr_ppr / pr_solve_ifp2 and with the FP64
+oracle, within the certified tolerance.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import prgen
+from conftest import l1
+
+pytestmark = pytest.mark.gpu
+C = 0.85
+
+
+@pytest.fixture(scope="module")
+def pr():
+    import paper_2302_03245_amd as pr
+    pr.lib()
+    return pr
+
+
+@pytest.mark.parametrize("residual,tol,slots", [("fp32", 1e-6, 16), ("fp64", 1e-9, 8)])
+def test_mix_equals_alone(pr, residual, tol, slots):
+    import torch
+    graphs = [prgen.workload_rmat_small(seed=0), prgen.random_digraph(20011, 150000, seed=3, dangling_frac=0.2,
+                                                                      unref_frac=0.1)]
+    dgs = [pr.upload(g.row_ptr, g.col) for g in graphs]
+    srv = pr.Server(c=C, l1_tol=tol, residual=residual, slots=slots, sweeps_per_round=3)
+    gids = [srv.add_graph(d) for d in dgs]
+    rng = np.random.default_rng(5)
+    queries = []
+    for q in range(40):
+        gi = int(rng.integers(0, 2))
+        src = -1 if rng.random() < 0.35 else int(rng.integers(0, graphs[gi].n))
+        queries.append((gi, src))
+    outs, rids = [], []
+    for q, (gi, src) in enumerate(queries):
+        out = torch.empty(graphs[gi].n, dtype=torch.float64, device="cuda")
+        outs.append(out)
+        rids.append(srv.submit(gids[gi], src, out))
+        if q % 7 == 6:
+            time.sleep(0.003)  # later waves arrive while earlier queries are in flight
+    stats = [srv.wait(r, timeout=120.0) for r in rids]
+    s = srv.stats()
+    print(f"server: {s}", flush=True)
+    assert s["completed"] == len(queries)
+    ref_cache = {}
+    for q, ((gi, src), st) in enumerate(zip(queries, stats)):
+        assert st["status"] == 0 and st["l1_bound"] <= tol
+        got = outs[q].cpu().numpy()
+        g = graphs[gi]
+        key = (gi, src)
+        if key not in ref_cache:
+            p = None
+            if src >= 0:
+                p = np.zeros(g.n)
+                p[src] = 1.0
+            ref_cache[key] = oracle.power(g, C, p, tol=1e-13)[0]
+        ref = ref_cache[key]
+        assert l1(got, ref) <= tol, (q, gi, src, l1(got, ref))
+        # the same query alone
+        if src >= 0:
+            alone = pr.ppr(dgs[gi], [src], c=C, l1_tol=tol, residual=residual)[0][0]
+        else:
+            alone = pr.ifp2(dgs[gi], c=C, l1_tol=tol, residual=residual)[0]
+        assert l1(got, alone) <= 2 * tol
+    srv.close()
+
+
+def test_server_rejections(pr):
+    import torch
+    g = prgen.random_digraph(1000, 6000, seed=1, dangling_frac=0.2)
+    dg = pr.upload(g.row_ptr, g.col)
+    with pytest.raises(pr.PRError, match="slots"):
+        pr.Server(slots=12)
+    small = pr.Server(memory_budget=1024)
+    with pytest.raises(pr.PRError, match="budget"):
+        small.add_graph(dg)
+    small.close()
+    srv = pr.Server()
+    gid = srv.add_graph(dg)
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(pr.PRError, match="graph id"):
+        srv.submit(gid + 5, 0, out)
+    with pytest.raises(pr.PRError, match="source"):
+        srv.submit(gid, g.n, out)
+    rid = srv.submit(gid, 3, out)
+    st = srv.wait(rid, timeout=60.0)
+    assert st["status"] == 0
+    with pytest.raises(pr.PRError, match="collected"):
+        srv.wait(rid)
+    srv.close()
