@@ -77,6 +77,13 @@ def main():
     ap.add_argument("--probes", action="store_true", help="also run the copy / gather / scatter probes")
     ap.add_argument("--ppr", type=int, default=16,
                     help="single-source PPR queries timed one at a time and batched (0 = skip)")
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="served scenario: seconds of Poisson arrivals (0 = skip)")
+    ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-compare", type=int, default=160,
+                    help="queries of the served stream also run one at a time and all at once")
+    ap.add_argument("--serve-ppr-scale", type=int, default=24,
+                    help="R-MAT scale of the resident PPR graph of the served scenario")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU layout is design-only.",
@@ -181,6 +188,8 @@ def main():
     }
     if args.ppr > 0:
         res["ppr"] = run_ppr(pr, dg, g, c, args)
+    if args.serve_seconds > 0:
+        res["served"] = run_serve(pr, prgen, c, args)
     if args.probes:
         res["probes"] = run_probes(pr, torch, g)
     if not args.no_cpu_baseline:
@@ -218,6 +227,145 @@ def run_ppr(pr, dg, g, c, args):
             "speedup": t_single / t_batch, "batch_width": 16,
             "mean_sweeps_single": float(np.mean([s["sweeps"] for s in single])),
             "mean_sweeps_batched": float(np.mean([s["sweeps"] for s in batched]))}
+
+
+def run_serve(pr, prgen, c, args):
+    """Served queries: Poisson arrivals at --serve-qps for --serve-seconds; 30 % are
+    single-source PPR (uniformly random source) on a resident R-MAT graph of scale
+    --serve-ppr-scale (2**28 draws at scale 24), 70 % global PageRank on one of 32
+    resident R-MAT graphs (n log-uniform in [10k, 4M], average degree 16, 15 %
+    dangling), picked uniformly.  IFP2 with FP32 residuals, certified L1 <= tol per
+    query; one server (continuous batching, 16 slots per graph); results stay in HBM.
+
+    Beside the open-loop run, the first --serve-compare queries of the same stream are
+    solved one at a time (pr_ppr / pr_solve_ifp2, back to back) and, separately, all
+    submitted to the server at once: aggregate GTEPS of both at equal accuracy."""
+    import threading
+
+    import numpy as np
+    import torch
+    log(f"[bench] serve: generating the PPR graph (scale {args.serve_ppr_scale}) and the 32-graph pool")
+    t0 = time.perf_counter()
+    gp = prgen.workload_rmat(scale=args.serve_ppr_scale, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=1)
+    pool = prgen.workload_serve_pool(count=32, seed=0)
+    graphs = [gp] + pool
+    log(f"[bench] serve: graphs ready in {time.perf_counter() - t0:.1f}s (PPR graph n={gp.n} m={gp.m}; pool "
+        f"n {sum(x.n for x in pool)} m {sum(x.m for x in pool)})")
+    dgs = [pr.upload(x.row_ptr, x.col) for x in graphs]
+    rng = np.random.default_rng(11)
+    n_q = int(args.serve_qps * args.serve_seconds)
+    gaps = rng.exponential(1.0 / args.serve_qps, n_q)
+    is_ppr = rng.random(n_q) < 0.30
+    pool_pick = rng.integers(1, len(graphs), n_q)
+    srcs = rng.integers(0, gp.n, n_q)
+    queries = [(0, int(srcs[q])) if is_ppr[q] else (int(pool_pick[q]), -1) for q in range(n_q)]
+    free = [[torch.empty(x.n, dtype=torch.float64, device="cuda") for _ in range(24 if i == 0 else 8)]
+            for i, x in enumerate(graphs)]
+
+    def make_server():
+        srv = pr.Server(c=c, l1_tol=args.tol, residual="fp32", slots=16, sweeps_per_round=4)
+        gids = [srv.add_graph(d) for d in dgs]
+        for gi in range(len(graphs)):  # one query per graph first: workspaces and plans
+            buf = free[gi][0]
+            srv.wait(srv.submit(gids[gi], -1, buf), timeout=300.0)
+        return srv, gids
+
+    def serve(qs, gaps_s):
+        """Submit qs at the given inter-arrival gaps (None: all at once); returns
+        per-query (graph index, stats) in completion order and the span."""
+        srv, gids = make_server()
+        lock = threading.Condition()
+        pending, done = [], []
+
+        def collector():
+            while True:
+                with lock:
+                    while not pending:
+                        lock.wait()
+                    item = pending.pop(0)
+                if item is None:
+                    return
+                rid, gi, buf = item
+                st = srv.wait(rid, timeout=300.0)
+                with lock:
+                    done.append((gi, st))
+                    free[gi].append(buf)
+                    lock.notify_all()
+
+        th = threading.Thread(target=collector)
+        th.start()
+        t_start = time.perf_counter()
+        t_next = t_start
+        for q, (gi, src) in enumerate(qs):
+            if gaps_s is not None:
+                t_next += gaps_s[q]
+                delay = t_next - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            with lock:
+                while not free[gi]:
+                    lock.wait()
+                buf = free[gi].pop()
+            rid = srv.submit(gids[gi], src, buf)
+            with lock:
+                pending.append((rid, gi, buf))
+                lock.notify_all()
+        with lock:
+            pending.append(None)
+            lock.notify_all()
+        th.join()
+        span = time.perf_counter() - t_start
+        srv.close()
+        return done, span
+
+    def summary(done, span):
+        ok = all(st["status"] == 0 and st["l1_bound"] <= args.tol for _, st in done)
+        lat = np.array([st["seconds_solve"] for _, st in done]) * 1e3
+        kind = np.array([gi == 0 for gi, _ in done])
+        edges = sum(graphs[gi].m for gi, _ in done)
+        out = {"completed": len(done), "all_certified": ok, "seconds": span, "qps": len(done) / span,
+               "gteps_aggregate": edges / span / 1e9,
+               "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "mean_ms": float(lat.mean()), "max_ms": float(lat.max())}
+        for name, sel in (("ppr", kind), ("pagerank", ~kind)):
+            if sel.any():
+                out[name] = {"count": int(sel.sum()), "p50_ms": float(np.percentile(lat[sel], 50)),
+                             "p99_ms": float(np.percentile(lat[sel], 99))}
+        return out
+
+    done, span = serve(queries, gaps)
+    open_loop = summary(done, span)
+    open_loop.update({"qps_target": args.serve_qps, "queries": n_q})
+    log(f"[bench] served open loop: {open_loop}")
+
+    k = min(args.serve_compare, n_q)
+    done, span = serve(queries[:k], None)
+    saturated = summary(done, span)
+    log(f"[bench] served, {k} queries submitted at once: {saturated}")
+
+    # the same queries one at a time, back to back, same accuracy
+    for gi in range(len(graphs)):
+        pr.ifp2(dgs[gi], c=c, l1_tol=args.tol, residual="fp32", out=free[gi][0])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    edges, ok = 0, True
+    for gi, src in queries[:k]:
+        if src >= 0:
+            _, sts = pr.ppr(dgs[gi], [src], c=c, l1_tol=args.tol, residual="fp32", out=free[gi][0].view(1, -1))
+            st = sts[0]
+        else:
+            _, st = pr.ifp2(dgs[gi], c=c, l1_tol=args.tol, residual="fp32", out=free[gi][0])
+        ok = ok and st["l1_bound"] <= args.tol
+        edges += graphs[gi].m
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    one = {"queries": k, "seconds": t_one, "gteps_aggregate": edges / t_one / 1e9, "all_certified": ok}
+    log(f"[bench] the same {k} queries one at a time: {one}")
+    return {"open_loop": open_loop, "saturated": saturated, "one_at_a_time": one,
+            "served_over_one_at_a_time": saturated["gteps_aggregate"] / one["gteps_aggregate"],
+            "ppr_graph": {"n": gp.n, "m": gp.m},
+            "pool": {"graphs": len(pool), "n": sum(x.n for x in pool), "m": sum(x.m for x in pool)},
+            "ppr_share": float(is_ppr.mean()), "slots_per_graph": 16}
 
 
 def run_probes(pr, torch, g):

@@ -5,14 +5,18 @@
  * Queries are global PageRank (p = e/n) or single-source PPR (p = e_s), both
  * solved by IFP2 (Algorithm 3 of Zhang, Tang, Yao, Liang, arXiv 2302.03245)
  * with the certified L1 stop.  Each registered graph gets an engine: a host
- * thread with its own HIP stream running a batched IFP2 solve whose columns
- * are query slots.  Between rounds of sweeps an engine finishes the columns
- * that met their bound (dangling phase + normalisation for those columns only)
- * and admits waiting queries into free columns while the other columns keep
- * iterating (continuous batching).  Engines of different graphs run
- * concurrently on the device.  Admission by memory: a graph is accepted only
- * if its engine's workspace fits in the server's device-memory budget; a query
- * is admitted when its graph's engine has a free slot.
+ * thread with its own HIP stream.  An idle engine looks at its queue: with
+ * fewer than batch_min waiting queries it solves the oldest one alone (the
+ * pr_ppr / pr_solve_ifp2 path); otherwise it starts a batched IFP2 run whose
+ * columns are query slots, 8 wide, or 16 wide when more than 8 queries wait
+ * and slots is 16.  Between rounds of sweeps a run finishes the columns that
+ * met their bound (dangling phase + normalisation for those columns only) and
+ * admits waiting queries into free columns while the other columns keep
+ * iterating (continuous batching).  A run ends when its last column retires;
+ * an 8-wide run whose queue outgrows its free slots stops admitting so that
+ * the next run can be 16 wide.  Engines of different graphs run concurrently
+ * on the device.  Admission by memory: a graph is accepted only if its
+ * engine's workspaces fit in the server's device-memory budget.
  *
  * Results equal those of pr_ppr / pr_solve_ifp2 on the same graph within the
  * certified tolerance (the rounding order differs).
@@ -34,7 +38,8 @@ typedef struct {
     double c;                 /* damping factor, 0 < c < 1 */
     double l1_tol;            /* certified L1 bound per query, > 0 */
     int32_t residual;         /* PR_RES_FP32 or PR_RES_FP64 */
-    int32_t slots;            /* query columns per graph engine: 8 or 16 */
+    int32_t slots;            /* widest batched run per graph engine: 8 or 16 */
+    int32_t batch_min;        /* queue length at which an idle engine batches; >= 1 (1: always batch) */
     int32_t sweeps_per_round; /* sweeps between two admission / retirement points, >= 1 */
     int32_t max_sweeps;       /* per query; 0 -> 100000 (a query reaching it ends with PR_ENOCONV) */
     int64_t memory_budget;    /* device bytes the engines' workspaces may use; 0 -> 90 % of free memory */
@@ -47,7 +52,7 @@ typedef struct {
     int64_t device_bytes;                   /* engine workspaces */
 } pr_server_stats;
 
-/* defaults: c 0.85, l1_tol 1e-6, FP32 residuals, 16 slots, 4 sweeps per round, budget 0 */
+/* defaults: c 0.85, l1_tol 1e-6, FP32 residuals, 16 slots, batch_min 2, 4 sweeps per round, budget 0 */
 void pr_server_opts_default(pr_server_opts *o);
 
 /* PR_EINVAL on invalid options. */

@@ -63,8 +63,8 @@ class Stats(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("c", ctypes.c_double), ("l1_tol", ctypes.c_double), ("residual", ctypes.c_int32),
-                ("slots", ctypes.c_int32), ("sweeps_per_round", ctypes.c_int32), ("max_sweeps", ctypes.c_int32),
-                ("memory_budget", ctypes.c_int64)]
+                ("slots", ctypes.c_int32), ("batch_min", ctypes.c_int32), ("sweeps_per_round", ctypes.c_int32),
+                ("max_sweeps", ctypes.c_int32), ("memory_budget", ctypes.c_int64)]
 
 
 class ServerStats(ctypes.Structure):
@@ -344,17 +344,19 @@ def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_s
 
 class Server:
     """Query server over resident graphs (include/pr_serve.h): global PageRank and
-    single-source PPR queries, continuously batched per graph, engines overlapping
-    on the device.  Results are written into caller-owned torch CUDA float64 tensors."""
+    single-source PPR queries, solved alone when an engine's queue is short and
+    continuously batched otherwise, engines overlapping on the device.  Results are
+    written into caller-owned torch CUDA float64 tensors."""
 
     def __init__(self, c=0.85, l1_tol=1e-6, residual="fp32", slots=16, sweeps_per_round=4, max_sweeps=0,
-                 memory_budget=0):
+                 memory_budget=0, batch_min=2):
         L = lib()
         o = ServerOpts()
         L.pr_server_opts_default(ctypes.byref(o))
         o.c, o.l1_tol = c, l1_tol
         o.residual = {"fp64": PR_RES_FP64, "fp32": PR_RES_FP32}[residual]
         o.slots, o.sweeps_per_round, o.max_sweeps, o.memory_budget = slots, sweeps_per_round, max_sweeps, memory_budget
+        o.batch_min = batch_min
         h = ctypes.c_void_p()
         st = L.pr_server_create(ctypes.byref(o), ctypes.byref(h))
         if st != PR_OK:

@@ -246,6 +246,9 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
     std::vector<int32_t> h_perm, h_newid;
     G.nN = degree_order(n, rp, h_perm, h_newid);
     G.nD = (int32_t)(n - G.nN);
+    G.dangling_bits.assign((size_t)(n + 63) / 64, 0);
+    for (int64_t i = 0; i < n; ++i)
+        if (rp[i + 1] == rp[i]) G.dangling_bits[(size_t)i >> 6] |= 1ull << (i & 63);
     HIPCHK(galloc(&G.perm, (size_t)n));
     HIPCHK(galloc(&G.newid, (size_t)n));
     HIPCHK(hipMemcpyAsync(G.perm, h_perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
@@ -437,7 +440,7 @@ struct Workspace {
     bool cached = false;
     Ctl *hctl = nullptr;  // pinned
     ~Workspace() {
-        if (hctl) (void)hipHostFree(hctl);
+        if (hctl && !cached) (void)hipHostFree(hctl);
         if (!base) return;
         if (cached) {
             std::lock_guard<std::mutex> lk(g->ws_mu);
@@ -462,16 +465,20 @@ pr_status acquire_ws(Graph &G, size_t bytes, Workspace &ws) {
                 if (e != hipSuccess) return hip_fail(e, "workspace");
                 G.ws_bytes = bytes;
             }
+            if (!G.ws_hctl) {
+                hipError_t e = hipHostMalloc(&G.ws_hctl, sizeof(Ctl), hipHostMallocDefault);
+                if (e != hipSuccess) return hip_fail(e, "pinned control block");
+            }
             G.ws_busy = true;
             ws.base = (char *)G.ws_mem;
+            ws.hctl = (Ctl *)G.ws_hctl;
             ws.cached = true;
+            return PR_OK;
         }
     }
-    if (!ws.base) {
-        hipError_t e = hipMalloc((void **)&ws.base, bytes);
-        if (e != hipSuccess) return hip_fail(e, "workspace");
-    }
-    hipError_t e = hipHostMalloc((void **)&ws.hctl, sizeof(Ctl), hipHostMallocDefault);
+    hipError_t e = hipMalloc((void **)&ws.base, bytes);
+    if (e != hipSuccess) return hip_fail(e, "workspace");
+    e = hipHostMalloc((void **)&ws.hctl, sizeof(Ctl), hipHostMallocDefault);
     if (e != hipSuccess) return hip_fail(e, "pinned control block");
     return PR_OK;
 }
@@ -1066,6 +1073,7 @@ pr_status pr_graph_free(pr_graph *g) {
     if (g->g.stream) (void)hipStreamSynchronize(g->g.stream);
     for (void *p : g->g.allocs) (void)hipFree(p);
     if (g->g.ws_mem) (void)hipFree(g->g.ws_mem);
+    if (g->g.ws_hctl) (void)hipHostFree(g->g.ws_hctl);
     if (g->g.stream) (void)hipStreamDestroy(g->g.stream);
     delete g;
     return PR_OK;

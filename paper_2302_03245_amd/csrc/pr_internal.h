@@ -139,6 +139,9 @@ struct Graph {
     bool ws_busy = false;
     void *ws_mem = nullptr;
     size_t ws_bytes = 0;
+    void *ws_hctl = nullptr;  // pinned host control block that goes with ws_mem
+    std::vector<uint64_t> dangling_bits;  // host bitmap over original ids: no out-edges
+    bool dangling(int64_t v) const { return (dangling_bits[(size_t)v >> 6] >> (v & 63)) & 1u; }
 };
 
 // host helpers shared by the host translation units (pr_host.hip)
@@ -210,6 +213,7 @@ hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, 
 hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStream_t s);
 hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, double *part, hipStream_t s);
 hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s);
+hipError_t launch_unit_vector(double *out, int64_t n, int64_t src, hipStream_t s);
 
 // batched IFP2 (pr_batch.hip)
 template <typename T, int B>

@@ -940,6 +940,16 @@ hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *
     return hipGetLastError();
 }
 
+// out = e_src: the PageRank of a single-source query whose source has no out-edges
+__global__ __launch_bounds__(kBlock) void k_unit_vector(double *out, int64_t n, int64_t src) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        out[i] = i == src ? 1.0 : 0.0;
+}
+
+hipError_t launch_unit_vector(double *out, int64_t n, int64_t src, hipStream_t s) {
+    PRK_LAUNCH(k_unit_vector, grid_for(n, 4, 4096), out, n, src);
+}
+
 hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s) {
     PRK_LAUNCH(k_validate_p, grid_for(n, 4, 2048), p, n, sum_bad);
 }

@@ -66,9 +66,10 @@ namespace {
 
 struct Engine {
     pr_server *srv = nullptr;
+    const pr_graph *hg = nullptr;
     const Graph *G = nullptr;
     int32_t gid = 0;
-    int B = 16;
+    int B = 16;  // widest batched run
     bool fp32 = true;
     hipStream_t stream = nullptr;
     char *ws = nullptr;
@@ -85,7 +86,7 @@ struct Engine {
         if (stream) (void)hipStreamDestroy(stream);
     }
 
-    // workspace of the batched solve (same carving for both residual types)
+    // workspace of the batched runs (same carving for both residual types)
     static size_t footprint(const Graph &G, int B, bool fp32) {
         const size_t sT = fp32 ? 4 : 8;
         size_t b = 0;
@@ -99,15 +100,134 @@ struct Engine {
         return b;
     }
 
+    // workspace of a single-vector solve (cached on the graph by the solve itself)
+    static size_t footprint_single(const Graph &G, bool fp32) {
+        const size_t sT = fp32 ? 4 : 8;
+        return align256((size_t)G.n * sT) + align256((size_t)G.nN * sT) + 3 * align256((size_t)G.nN * 8) +
+               align256((size_t)std::max<int32_t>(G.nD, 1) * 8) + 64 * 1024 + 5 * kRedBlocks * 8;
+    }
+
+    template <typename T>
+    void serve();
     template <typename T, int Bw>
-    void run();
+    bool run();
+    bool run_single();
+    bool trivial(const Request &r) const { return r.source >= 0 && G->dangling(r.source); }
+    void take_trivial(std::vector<std::shared_ptr<Request>> &out);
+    bool answer_trivial(std::vector<std::shared_ptr<Request>> &rs, bool sync);
+    void finish(const std::shared_ptr<Request> &r, pr_status status, const pr_stats *st, const std::string &err);
 };
 
-// Engine loop for residual type T and width Bw.
+void Engine::finish(const std::shared_ptr<Request> &r, pr_status status, const pr_stats *st,
+                    const std::string &err) {
+    const double tnow = now_s();
+    std::lock_guard<std::mutex> lk(srv->mu);
+    r->t_done = tnow;
+    r->done = true;
+    r->status = status;
+    r->err = err;
+    if (st) r->st = *st;
+    else memset(&r->st, 0, sizeof(r->st));
+    r->st.seconds_solve = tnow - r->t_submit;
+    if (status >= 0) {
+        srv->lat_ms.push_back((tnow - r->t_submit) * 1e3);
+        srv->edges_done += (double)G->m;
+        srv->t_last = std::max(srv->t_last, tnow);
+    }
+}
+
+// A single-source query whose source has no out-edges needs no sweep: its
+// PageRank is e_s exactly (no mass ever leaves s; the normalisation is 1).
+// Such queries are taken out of the queue (caller holds srv->mu) ...
+void Engine::take_trivial(std::vector<std::shared_ptr<Request>> &out) {
+    for (auto it = queue.begin(); it != queue.end();) {
+        if (trivial(**it)) {
+            out.push_back(*it);
+            it = queue.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
+// ... and answered with one fill each on the engine's stream (completed after
+// the stream has been synchronised: here if sync, else by the caller).
+bool Engine::answer_trivial(std::vector<std::shared_ptr<Request>> &rs, bool sync) {
+    hipError_t e = hipSuccess;
+    for (auto &r : rs)
+        if (e == hipSuccess) e = launch_unit_vector(r->out, G->n, r->source, stream);
+    if (sync && e == hipSuccess) e = hipStreamSynchronize(stream);
+    if (!sync) return e == hipSuccess;
+    pr_stats st{};
+    for (auto &r : rs)
+        finish(r, e == hipSuccess ? PR_OK : PR_EDEVICE, e == hipSuccess ? &st : nullptr,
+               e == hipSuccess ? std::string() : std::string("fill: ") + hipGetErrorString(e));
+    rs.clear();
+    srv->cv_done.notify_all();
+    return e == hipSuccess;
+}
+
+// Dispatcher of one engine: single-vector solves or batched runs, by queue length.
+template <typename T>
+void Engine::serve() {
+    (void)hipSetDevice(G->device);
+    bool ok = true;
+    while (ok && !srv->stop.load()) {
+        size_t q = 0;
+        std::vector<std::shared_ptr<Request>> triv;
+        {
+            std::unique_lock<std::mutex> lk(srv->mu);
+            cv_work.wait_for(lk, std::chrono::milliseconds(50), [&] { return srv->stop.load() || !queue.empty(); });
+            take_trivial(triv);
+            q = queue.size();
+        }
+        if (!triv.empty()) ok = answer_trivial(triv, true);
+        if (!ok || q == 0 || srv->stop.load()) continue;
+        if ((int64_t)q < (int64_t)srv->o.batch_min) ok = run_single();
+        else if (B == 16 && q > 8) ok = run<T, 16>();
+        else ok = run<T, 8>();
+        srv->cv_done.notify_all();
+    }
+    std::lock_guard<std::mutex> lk(srv->mu);
+    for (auto &r : queue) {
+        r->done = true;
+        r->status = ok ? PR_EINVAL : PR_EDEVICE;
+        r->err = ok ? "server destroyed" : "device error in this graph's engine";
+    }
+    queue.clear();
+    srv->cv_done.notify_all();
+}
+
+// The oldest waiting query solved alone on the engine's stream.
+bool Engine::run_single() {
+    std::shared_ptr<Request> r;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        if (queue.empty()) return true;
+        r = queue.front();
+        queue.pop_front();
+    }
+    pr_opts o;
+    pr_opts_default(&o);
+    o.c = srv->o.c;
+    o.l1_tol = srv->o.l1_tol;
+    o.stop = PR_STOP_L1;
+    o.residual = srv->o.residual;
+    o.max_sweeps = srv->o.max_sweeps;
+    o.flags = PR_OUT_DEVICE;
+    o.stream = (void *)stream;
+    pr_stats st{};
+    const int32_t src = r->source;
+    const pr_status ps = src >= 0 ? pr_ppr(hg, &src, 1, &o, r->out, &st) : pr_solve_ifp2(hg, nullptr, &o, r->out, &st);
+    finish(r, ps, ps >= 0 ? &st : nullptr, ps < 0 ? std::string(pr_last_error()) : std::string());
+    srv->cv_done.notify_all();
+    return ps != PR_EDEVICE;
+}
+
+// One batched run of residual type T and width Bw: lasts until its last column retires.
 template <typename T, int Bw>
-void Engine::run() {
+bool Engine::run() {
     const Graph &g = *G;
-    (void)hipSetDevice(g.device);
     hipStream_t s = stream;
     const int64_t n = g.n;
     const int32_t nN = g.nN, nD = g.nD;
@@ -142,6 +262,7 @@ void Engine::run() {
     for (int j = 0; j < kMaxBatch; ++j) hctl->col_stop[j] = -1;
     int t = 0;
     bool ok = true;
+    bool draining = false;
     std::string err;
     auto chk = [&](hipError_t e, const char *what) {
         if (e != hipSuccess && ok) {
@@ -155,10 +276,15 @@ void Engine::run() {
         // ---- admission
         uint32_t admit = 0;
         int live = 0;
+        std::vector<std::shared_ptr<Request>> triv;
         {
             std::unique_lock<std::mutex> lk(srv->mu);
+            take_trivial(triv);
+            int free_slots = 0;
+            for (int j = 0; j < Bw; ++j) free_slots += slots[j] ? 0 : 1;
+            if (Bw < B && (int)queue.size() > free_slots) draining = true;
             for (int j = 0; j < Bw; ++j) {
-                if (!slots[j] && !queue.empty()) {
+                if (!draining && !slots[j] && !queue.empty()) {
                     slots[j] = queue.front();
                     queue.pop_front();
                     admit |= 1u << j;
@@ -166,11 +292,19 @@ void Engine::run() {
                 }
                 live += slots[j] ? 1 : 0;
             }
-            if (live == 0) {
-                cv_work.wait_for(lk, std::chrono::milliseconds(50),
-                                 [&] { return srv->stop.load() || !queue.empty(); });
-                continue;
+            if (live == 0 && triv.empty()) break;  // back to the dispatcher
+        }
+        if (live == 0) {
+            if (!answer_trivial(triv, true)) {
+                ok = false;
+                err = "fill of single-source answers";
+                break;
             }
+            continue;
+        }
+        if (!triv.empty() && !answer_trivial(triv, false)) {
+            ok = false;
+            err = "fill of single-source answers";
         }
         if (admit) {
             for (int j = 0; j < Bw; ++j) {
@@ -203,6 +337,12 @@ void Engine::run() {
         }
         chk(hipMemcpyAsync(hctl, dctl, sizeof(CtlB), hipMemcpyDeviceToHost, s), "control block");
         chk(hipStreamSynchronize(s), "sweeps");
+        if (!triv.empty()) {  // filled before this round's sweeps, on the same stream
+            pr_stats st0{};
+            for (auto &r : triv) finish(r, ok ? PR_OK : PR_EDEVICE, ok ? &st0 : nullptr, ok ? std::string() : err);
+            triv.clear();
+            srv->cv_done.notify_all();
+        }
         // ---- retirement of the columns that met their bound (or ran out of sweeps)
         uint32_t fin = 0;
         OutSet os;
@@ -220,43 +360,31 @@ void Engine::run() {
         if (ok) chk(launch_final_b<T, Bw>(dctl, n, nN, g.perm, fin, os, h, pibar, xD, part, s), "normalisation");
         if (ok) chk(hipMemcpyAsync(hctl, dctl, sizeof(CtlB), hipMemcpyDeviceToHost, s), "control block");
         if (ok) chk(hipStreamSynchronize(s), "normalisation");
-        const double tnow = now_s();
-        {
-            std::lock_guard<std::mutex> lk(srv->mu);
-            for (int j = 0; j < Bw; ++j) {
-                if (!((fin >> j) & 1u)) continue;
-                Request &r = *slots[j];
-                r.t_done = tnow;
-                r.done = true;
-                memset(&r.st, 0, sizeof(r.st));
-                if (!ok) {
-                    r.status = PR_EDEVICE;
-                    r.err = err;
-                } else {
-                    const bool conv = hctl->col_stop[j] < t || nN == 0;
-                    r.status = conv ? PR_OK : PR_ENOCONV;
-                    r.st.sweeps = hctl->col_sweeps[j];
-                    r.st.edges_processed = (int64_t)hctl->tot_edges[j] + g.mND;
-                    r.st.vertex_pushes = (int64_t)hctl->tot_pushes[j];
-                    const double fs = hctl->fin_sum[j];
-                    r.st.residual_l1 = fs > 0 ? hctl->fin_sn[j] / fs : 0.0;
-                    r.st.l1_bound = fs > 0 ? 2.0 * c / (1.0 - c) * hctl->fin_sn[j] / fs : 0.0;
-                    r.st.seconds_solve = r.t_done - r.t_submit;
-                    r.st.seconds_preprocess = g.seconds_split;
-                }
-                srv->lat_ms.push_back((r.t_done - r.t_submit) * 1e3);
-                srv->edges_done += (double)g.m;
-                srv->t_last = std::max(srv->t_last, tnow);
-                slots[j].reset();
-                ss.s[j] = kSrcUnused;
-                hctl->col_stop[j] = -1;
+        for (int j = 0; j < Bw; ++j) {
+            if (!((fin >> j) & 1u)) continue;
+            if (!ok) {
+                finish(slots[j], PR_EDEVICE, nullptr, err);
+            } else {
+                pr_stats st{};
+                const bool conv = hctl->col_stop[j] < t || nN == 0;
+                st.sweeps = hctl->col_sweeps[j];
+                st.edges_processed = (int64_t)hctl->tot_edges[j] + g.mND;
+                st.vertex_pushes = (int64_t)hctl->tot_pushes[j];
+                const double fs = hctl->fin_sum[j];
+                st.residual_l1 = fs > 0 ? hctl->fin_sn[j] / fs : 0.0;
+                st.l1_bound = fs > 0 ? 2.0 * c / (1.0 - c) * hctl->fin_sn[j] / fs : 0.0;
+                st.seconds_preprocess = g.seconds_split;
+                finish(slots[j], conv ? PR_OK : PR_ENOCONV, &st, std::string());
             }
+            slots[j].reset();
+            ss.s[j] = kSrcUnused;
+            hctl->col_stop[j] = -1;
         }
         // the host copy of the control block stays authoritative for the next admission
         srv->cv_done.notify_all();
         if (!ok) break;
     }
-    // fail whatever is left
+    // columns still live here: the server is being destroyed, or the device failed
     std::lock_guard<std::mutex> lk(srv->mu);
     for (int j = 0; j < Bw; ++j) {
         if (!slots[j]) continue;
@@ -264,13 +392,7 @@ void Engine::run() {
         slots[j]->status = ok ? PR_EINVAL : PR_EDEVICE;
         slots[j]->err = ok ? "server destroyed" : err;
     }
-    for (auto &r : queue) {
-        r->done = true;
-        r->status = ok ? PR_EINVAL : PR_EDEVICE;
-        r->err = ok ? "server destroyed" : err;
-    }
-    queue.clear();
-    srv->cv_done.notify_all();
+    return ok;
 }
 
 }  // namespace
@@ -284,6 +406,7 @@ void pr_server_opts_default(pr_server_opts *o) {
     o->l1_tol = 1e-6;
     o->residual = PR_RES_FP32;
     o->slots = 16;
+    o->batch_min = 2;
     o->sweeps_per_round = 4;
 }
 
@@ -298,6 +421,7 @@ pr_status pr_server_create(const pr_server_opts *o, pr_server **out) {
     if (op.residual != PR_RES_FP32 && op.residual != PR_RES_FP64) return set_error(PR_EINVAL, "unknown residual type");
     if (op.slots != 8 && op.slots != 16) return set_error(PR_EINVAL, "slots must be 8 or 16");
     if (op.sweeps_per_round < 1) return set_error(PR_EINVAL, "sweeps_per_round must be >= 1");
+    if (op.batch_min < 1) return set_error(PR_EINVAL, "batch_min must be >= 1");
     if (op.max_sweeps < 0 || op.memory_budget < 0) return set_error(PR_EINVAL, "negative limit");
     std::unique_ptr<pr_server> sv(new (std::nothrow) pr_server());
     if (!sv) return set_error(PR_ENOMEM, "host allocation");
@@ -319,7 +443,7 @@ pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id
     if (!s || !g || !graph_id) return set_error(PR_EINVAL, "NULL argument");
     const Graph &G = g->g;
     const bool fp32 = s->o.residual == PR_RES_FP32;
-    const size_t fp = Engine::footprint(G, s->o.slots, fp32);
+    const size_t fp = Engine::footprint(G, s->o.slots, fp32) + Engine::footprint_single(G, fp32);
     {
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->used + (int64_t)fp > s->budget)
@@ -334,15 +458,18 @@ pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id
     };
     if (!eng) return undo(PR_ENOMEM, "host allocation");
     eng->srv = s;
+    eng->hg = g;
     eng->G = &G;
     eng->B = s->o.slots;
     eng->fp32 = fp32;
     hipError_t e = hipSetDevice(G.device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&eng->stream, hipStreamNonBlocking);
     if (e != hipSuccess) return undo(PR_EDEVICE, std::string("stream: ") + hipGetErrorString(e));
-    pr_status ps = batch_plans(const_cast<Graph &>(G), eng->B, eng->stream);
-    if (ps != PR_OK) return undo(ps, "batch plans");
-    e = hipMalloc((void **)&eng->ws, fp);
+    for (int bw = 8; bw <= eng->B; bw *= 2) {
+        pr_status ps = batch_plans(const_cast<Graph &>(G), bw, eng->stream);
+        if (ps != PR_OK) return undo(ps, "batch plans");
+    }
+    e = hipMalloc((void **)&eng->ws, Engine::footprint(G, eng->B, fp32));
     if (e != hipSuccess) return undo(PR_ENOMEM, std::string("engine workspace: ") + hipGetErrorString(e));
     eng->ws_bytes = fp;
     e = hipHostMalloc((void **)&eng->hctl, sizeof(CtlB), hipHostMallocDefault);
@@ -353,8 +480,7 @@ pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id
         ep->gid = (int32_t)s->engines.size();
         s->engines.push_back(std::move(eng));
     }
-    if (ep->fp32) ep->th = std::thread(ep->B == 8 ? &Engine::run<float, 8> : &Engine::run<float, 16>, ep);
-    else ep->th = std::thread(ep->B == 8 ? &Engine::run<double, 8> : &Engine::run<double, 16>, ep);
+    ep->th = std::thread(ep->fp32 ? &Engine::serve<float> : &Engine::serve<double>, ep);
     *graph_id = ep->gid;
     return PR_OK;
 }

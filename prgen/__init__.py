@@ -20,6 +20,14 @@ for them with the same kinds of structure, see the experiment section of the pap
   random 10 % redirected to uniform vertices outside that set.
 * ``workload_dag``: 2**23 vertices in 64 random layers, Zipf(2.0) out-degrees
   capped at 10,000 and scaled to 80M forward edges, plus 2 % back edges.
+* ``workload_rmat_n``: R-MAT at any n (drawn at scale ceil(log2 n), endpoints
+  >= n rejected) with an exact number of distinct edges avg_degree * n, then
+  the out-edges of a random dangling_frac of the vertices dropped.
+* ``workload_batch``: many independent ``workload_rmat_n`` graphs, n
+  log-uniform in [1k, 500k], average degree uniform in [4, 32], 5-20 % dangling,
+  damping factor drawn from {0.85, 0.9} per graph.
+* ``workload_serve_pool``: a resident pool of ``workload_rmat_n`` graphs with n
+  log-uniform in [10k, 4M], average degree 16, 15 % dangling.
 """
 from __future__ import annotations
 
@@ -122,7 +130,7 @@ def _cached(key: str, make):
 
 
 # workload ids keep the random streams of different recipes independent
-WL_RMAT_SMALL, WL_RMAT, WL_DAG = 1, 2, 3
+WL_RMAT_SMALL, WL_RMAT, WL_DAG, WL_RMAT_N = 1, 2, 3, 4
 
 
 def workload_rmat_small(seed: int = 0, n: int = 10_000, scale: int = 14, m: int = 100_000,
@@ -154,6 +162,54 @@ def workload_dag(n_layers: int = 64, layer_size: int = 131_072, zipf_s: float = 
         res = _load().prgen_dag(n_layers, layer_size, zipf_s, zmax, target_edges, back_frac, seed, WL_DAG)
         return _take(res, f"dag_L{n_layers}_w{layer_size}_s{seed}", {"seed": seed})
     return _cached(key, make)
+
+
+def workload_rmat_n(n: int, avg_degree: float, dangling_frac: float, seed: int,
+                    a=0.57, b=0.19, c=0.19) -> Graph:
+    """R-MAT with any n: drawn at scale ceil(log2 n), endpoints >= n, self-loops and
+    repeats rejected until round(avg_degree * n) distinct edges exist; then all
+    out-edges of round(dangling_frac * n) uniformly chosen vertices are dropped."""
+    scale = max(1, int(np.ceil(np.log2(max(n, 2)))))
+    m = int(round(avg_degree * n))
+    nd = int(round(dangling_frac * n))
+    key = f"rmatn:{n}:{m}:{nd}:{seed}:{a}:{b}:{c}"
+
+    def make():
+        res = _load().prgen_rmat_exact(n, scale, m, nd, a, b, c, seed, WL_RMAT_N)
+        return _take(res, f"rmatn_n{n}_m{m}_s{seed}", {"seed": seed})
+    return _cached(key, make)
+
+
+def _many(params, workers):
+    """Generate several workload_rmat_n graphs on a thread pool (the C calls run
+    without the GIL); the result does not depend on the worker count."""
+    from concurrent.futures import ThreadPoolExecutor
+    if workers is None:
+        workers = min(8, os.cpu_count() or 1)
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        return list(ex.map(lambda q: workload_rmat_n(*q), params))
+
+
+def workload_batch(count: int = 256, n_lo: int = 1_000, n_hi: int = 500_000, deg_lo: float = 4.0,
+                   deg_hi: float = 32.0, dangling_lo: float = 0.05, dangling_hi: float = 0.20,
+                   c_choices=(0.85, 0.9), seed: int = 0, workers=None):
+    """Independent graphs for batched solves: returns (graphs, c per graph)."""
+    rng = np.random.default_rng([seed, WL_RMAT_N, 100])
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).round().astype(np.int64)
+    degs = rng.uniform(deg_lo, deg_hi, count)
+    dfr = rng.uniform(dangling_lo, dangling_hi, count)
+    cs = rng.choice(np.asarray(c_choices, dtype=np.float64), count)
+    params = [(int(ns[i]), float(degs[i]), float(dfr[i]), seed * 100_003 + i) for i in range(count)]
+    return _many(params, workers), [float(x) for x in cs]
+
+
+def workload_serve_pool(count: int = 32, n_lo: int = 10_000, n_hi: int = 4_000_000,
+                        avg_degree: float = 16.0, dangling_frac: float = 0.15, seed: int = 0, workers=None):
+    """Resident graphs answering global PageRank queries in the served scenario."""
+    rng = np.random.default_rng([seed, WL_RMAT_N, 200])
+    ns = np.exp(rng.uniform(np.log(n_lo), np.log(n_hi), count)).round().astype(np.int64)
+    params = [(int(ns[i]), avg_degree, dangling_frac, seed * 100_003 + 50_000 + i) for i in range(count)]
+    return _many(params, workers)
 
 
 def from_edges(n: int, src, dst, name: str = "") -> Graph:

@@ -181,34 +181,107 @@ static inline uint64_t rmat_draw(uint64_t key, uint64_t k, int scale, double a, 
 /* and repeats, until `target_m` distinct edges exist (draw order), then     */
 /* drop all out-edges of `n_dangling` uniformly chosen vertices, relabel.    */
 /* ------------------------------------------------------------------------ */
+/* stable LSD radix sort of 64-bit keys carrying 32-bit payloads */
+static void radix_sort_kv(uint64_t *k, uint32_t *v, int64_t n, int key_bits) {
+    const int RB = 11, R = 1 << RB;
+    int nthreads = 1;
+#ifdef _OPENMP
+    nthreads = omp_get_max_threads();
+#endif
+    int64_t *hist = (int64_t *)malloc(sizeof(int64_t) * (size_t)nthreads * R);
+    uint64_t *tk = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n > 0 ? n : 1));
+    uint32_t *tv = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(n > 0 ? n : 1));
+    uint64_t *sk = k, *dk = tk;
+    uint32_t *sv = v, *dv = tv;
+    int passes = (key_bits + RB - 1) / RB;
+    for (int pass = 0; pass < passes; ++pass) {
+        int shift = pass * RB;
+        memset(hist, 0, sizeof(int64_t) * (size_t)nthreads * R);
+#pragma omp parallel num_threads(nthreads)
+        {
+            int t = 0;
+#ifdef _OPENMP
+            t = omp_get_thread_num();
+#endif
+            int64_t lo = n * t / nthreads, hi = n * (t + 1) / nthreads;
+            int64_t *h = hist + (size_t)t * R;
+            for (int64_t i = lo; i < hi; ++i) h[(sk[i] >> shift) & (R - 1)]++;
+#pragma omp barrier
+#pragma omp single
+            {
+                int64_t run = 0;
+                for (int d = 0; d < R; ++d)
+                    for (int tt = 0; tt < nthreads; ++tt) {
+                        int64_t c = hist[(size_t)tt * R + d];
+                        hist[(size_t)tt * R + d] = run;
+                        run += c;
+                    }
+            }
+            for (int64_t i = lo; i < hi; ++i) {
+                int64_t o = h[(sk[i] >> shift) & (R - 1)]++;
+                dk[o] = sk[i];
+                dv[o] = sv[i];
+            }
+        }
+        uint64_t *s = sk; sk = dk; dk = s;
+        uint32_t *s2 = sv; sv = dv; dv = s2;
+    }
+    if (sk != k) {
+        memcpy(k, sk, sizeof(uint64_t) * (size_t)n);
+        memcpy(v, sv, sizeof(uint32_t) * (size_t)n);
+    }
+    free(tk);
+    free(tv);
+    free(hist);
+}
+
+/* ------------------------------------------------------------------------ */
+/* Small R-MAT workload: draw at `scale`, reject endpoints >= n, self-loops  */
+/* and repeats, until `target_m` distinct edges exist (draw order), then     */
+/* drop all out-edges of `n_dangling` uniformly chosen vertices, relabel.    */
+/* The first target_m distinct valid draws are found in parallel: draws     */
+/* 0..K-1 are sorted stably by edge, which leaves each edge's first draw at  */
+/* the head of its run; a scan in draw order then takes the first target_m   */
+/* such heads (K grows until enough exist).                                  */
+/* ------------------------------------------------------------------------ */
 prgen_graph *prgen_rmat_exact(int64_t n, int scale, int64_t target_m, int64_t n_dangling,
                               double a, double b, double c, uint64_t seed, uint32_t wl) {
     if (n < 1 || n > ((int64_t)1 << scale) || scale > 31 || target_m < 0 ||
         target_m > n * (n - 1) || n_dangling < 0 || n_dangling > n)
         return NULL;
     uint64_t ke = stream_key(seed, wl, 0), kd = stream_key(seed, wl, 1), kr = stream_key(seed, wl, 3);
-    int64_t cap = 1;
-    while (cap < 2 * target_m + 16) cap <<= 1;
-    uint64_t *table = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)cap);
-    memset(table, 0xff, sizeof(uint64_t) * (size_t)cap);
-    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(target_m > 0 ? target_m : 1));
-    int64_t have = 0, k = 0;
     const double ab = a + b, abc = a + b + c;
+    const uint64_t INVALID = (uint64_t)1 << (32 + scale); /* above every valid key */
+    uint64_t *keys = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(target_m > 0 ? target_m : 1));
+    int64_t have = 0, k_used = 0;
+    int64_t K = target_m + target_m / 4 + 1024;
     while (have < target_m) {
-        uint64_t e = rmat_draw(ke, (uint64_t)k++, scale, a, ab, abc);
-        uint64_t s = e >> 32, t = e & 0xffffffffULL;
-        if ((int64_t)s >= n || (int64_t)t >= n || s == t) continue;
-        uint64_t h = mix64(e) & (uint64_t)(cap - 1);
-        int dup = 0;
-        while (table[h] != ~0ULL) {
-            if (table[h] == e) { dup = 1; break; }
-            h = (h + 1) & (uint64_t)(cap - 1);
+        if (K > ((int64_t)1 << 32) - 1) { free(keys); return NULL; }
+        uint64_t *e = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)K);
+        uint32_t *idx = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)K);
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < K; ++k) {
+            uint64_t d = rmat_draw(ke, (uint64_t)k, scale, a, ab, abc);
+            uint64_t s = d >> 32, t = d & 0xffffffffULL;
+            e[k] = ((int64_t)s >= n || (int64_t)t >= n || s == t) ? INVALID : d;
+            idx[k] = (uint32_t)k;
         }
-        if (dup) continue;
-        table[h] = e;
-        keys[have++] = e;
+        radix_sort_kv(e, idx, K, 33 + scale);
+        /* head[k] = edge of draw k if draw k is its edge's first valid draw */
+        uint64_t *head = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)K);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < K; ++i)
+            head[idx[i]] = (e[i] != INVALID && (i == 0 || e[i] != e[i - 1])) ? e[i] : INVALID;
+        free(idx);
+        free(e);
+        have = 0;
+        int64_t k = 0;
+        for (; k < K && have < target_m; ++k)
+            if (head[k] != INVALID) keys[have++] = head[k];
+        k_used = k;
+        free(head);
+        K += K / 2;
     }
-    free(table);
     /* dangling set: first n_dangling entries of a permutation of V */
     int32_t *pd = permutation(n, kd);
     uint8_t *isd = (uint8_t *)calloc((size_t)n, 1);
@@ -220,7 +293,7 @@ prgen_graph *prgen_rmat_exact(int64_t n, int scale, int64_t target_m, int64_t n_
     free(isd);
     int32_t *pr = permutation(n, kr);
     prgen_graph *g = to_csr(keys, w, n, pr);
-    g->draws = k;
+    g->draws = k_used;
     free(pr);
     free(keys);
     return g;

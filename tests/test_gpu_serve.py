@@ -25,13 +25,14 @@ def pr():
     return pr
 
 
-@pytest.mark.parametrize("residual,tol,slots", [("fp32", 1e-6, 16), ("fp64", 1e-9, 8)])
-def test_mix_equals_alone(pr, residual, tol, slots):
+@pytest.mark.parametrize("residual,tol,slots,batch_min", [("fp32", 1e-6, 16, 1), ("fp64", 1e-9, 8, 1),
+                                                          ("fp32", 1e-6, 16, 2), ("fp64", 1e-9, 16, 3)])
+def test_mix_equals_alone(pr, residual, tol, slots, batch_min):
     import torch
     graphs = [prgen.workload_rmat_small(seed=0), prgen.random_digraph(20011, 150000, seed=3, dangling_frac=0.2,
                                                                       unref_frac=0.1)]
     dgs = [pr.upload(g.row_ptr, g.col) for g in graphs]
-    srv = pr.Server(c=C, l1_tol=tol, residual=residual, slots=slots, sweeps_per_round=3)
+    srv = pr.Server(c=C, l1_tol=tol, residual=residual, slots=slots, sweeps_per_round=3, batch_min=batch_min)
     gids = [srv.add_graph(d) for d in dgs]
     rng = np.random.default_rng(5)
     queries = []
@@ -46,6 +47,8 @@ def test_mix_equals_alone(pr, residual, tol, slots):
         rids.append(srv.submit(gids[gi], src, out))
         if q % 7 == 6:
             time.sleep(0.003)  # later waves arrive while earlier queries are in flight
+        if q >= 30:
+            time.sleep(0.002)  # a trickle at the end: short queues, solved alone unless batch_min is 1
     stats = [srv.wait(r, timeout=120.0) for r in rids]
     s = srv.stats()
     print(f"server: {s}", flush=True)
@@ -79,6 +82,8 @@ def test_server_rejections(pr):
     dg = pr.upload(g.row_ptr, g.col)
     with pytest.raises(pr.PRError, match="slots"):
         pr.Server(slots=12)
+    with pytest.raises(pr.PRError, match="batch_min"):
+        pr.Server(batch_min=0)
     small = pr.Server(memory_budget=1024)
     with pytest.raises(pr.PRError, match="budget"):
         small.add_graph(dg)
