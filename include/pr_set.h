@@ -1,0 +1,72 @@
+/*
+ * pr_set.h -- many independent graphs solved together (part of libpr.so).
+ *
+ * A graph set holds k directed graphs uploaded as one block-diagonal union in
+ * device memory.  pr_set_solve_ifp2 runs IFP2 (Algorithm 3 of Zhang, Tang,
+ * Yao, Liang, arXiv 2302.03245) on all of them at once: every sweep is one
+ * launch sequence over the union (reserve, management, push or pull), with the
+ * damping factor, the push threshold, the stop rule and the final
+ * normalisation (Eq. 4) kept per graph.  Each graph's result is its global
+ * PageRank (uniform p) with its own certified L1 bound; a graph that meets its
+ * bound stops moving mass while the others continue.
+ *
+ * Graph g's vertices are 0 .. n[g]-1 in its own CSR; in the solution array they
+ * sit at offset off[g] = n[0] + ... + n[g-1].
+ */
+#ifndef PR_SET_H
+#define PR_SET_H
+
+#include <stdint.h>
+
+#include "pr.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pr_graph_set pr_graph_set;
+
+typedef struct {
+    int64_t k;                  /* graphs in the set */
+    int64_t n, m;               /* totals over the set */
+    int64_t n_dangling, m_dangling;
+    int64_t device_bytes;
+    double seconds_upload;
+} pr_set_info_t;
+
+/*
+ * Upload k >= 1 graphs.  n[g] >= 1 vertices; row_ptr[g] (host, n[g] + 1 int64,
+ * non-decreasing, row_ptr[g][0] = 0) and col[g] (host, row_ptr[g][n[g]] int32,
+ * each in [0, n[g])) give graph g in CSR with out-edges per row.  Duplicate
+ * edges count with multiplicity.  Totals must stay below 2^31 vertices and 2^31
+ * edges.  flags: PR_TILE_SHIFT only.  The inputs are copied.  PR_EINVAL on a
+ * malformed graph (nothing is uploaded), PR_ENOMEM / PR_EDEVICE on allocation
+ * or device failure.
+ */
+pr_status pr_set_upload(int32_t k, const int64_t *n, const int64_t *const *row_ptr, const int32_t *const *col,
+                        uint32_t flags, pr_graph_set **out);
+pr_status pr_set_free(pr_graph_set *s);
+pr_status pr_set_info(const pr_graph_set *s, pr_set_info_t *out);
+
+/*
+ * IFP2 on every graph of the set, uniform personalisation.
+ *   c    k damping factors in (0, 1), or NULL for o->c on every graph.
+ *   o    o->stop PR_STOP_L1: graph g stops once its certified L1 bound is
+ *        <= o->l1_tol (thresholds xi_g derived per graph); PR_STOP_XI: every
+ *        graph uses threshold o->xi and stops when no vertex exceeds it.
+ *        o->residual, o->max_sweeps (for the whole set), o->stream; flags
+ *        PR_OUT_DEVICE, PR_FORCE_PUSH, PR_FORCE_PULL.
+ *   pi   sum of n[g] doubles (host, or device with PR_OUT_DEVICE), graph g at
+ *        offset off[g]; written only when the status is not negative.
+ *   st   k entries or NULL: per-graph sweeps, pushes, edges, residual and bound;
+ *        seconds_solve is the time of the whole set solve.
+ * Returns PR_OK when every graph converged, PR_ENOCONV when some graph reached
+ * max_sweeps first (its entry of st says how far it got).
+ */
+pr_status pr_set_solve_ifp2(const pr_graph_set *s, const double *c, const pr_opts *o, double *pi, pr_stats *st);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PR_SET_H */

@@ -31,7 +31,8 @@ EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_inf
             "pr_solve_ifp2", "pr_solve_power", "pr_ppr", "pr_last_error", "pr_last_trace",
             "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len",
             "pr_server_opts_default", "pr_server_create", "pr_server_add_graph", "pr_server_submit",
-            "pr_server_wait", "pr_server_get_stats", "pr_server_destroy"]
+            "pr_server_wait", "pr_server_get_stats", "pr_server_destroy",
+            "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2"]
 
 
 class PRError(RuntimeError):
@@ -71,6 +72,12 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
                 ("edges_per_second", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+
+
+class SetInfo(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int64), ("n", ctypes.c_int64), ("m", ctypes.c_int64),
+                ("n_dangling", ctypes.c_int64), ("m_dangling", ctypes.c_int64),
+                ("device_bytes", ctypes.c_int64), ("seconds_upload", ctypes.c_double)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -125,6 +132,14 @@ def lib():
     L.pr_probe_scatter.restype = ctypes.c_int
     L.pr_probe_gather_out_len.argtypes = [i64]
     L.pr_probe_gather_out_len.restype = i64
+    L.pr_set_upload.argtypes = [i32, vp, vp, vp, u32, ctypes.POINTER(vp)]
+    L.pr_set_upload.restype = ctypes.c_int
+    L.pr_set_free.argtypes = [vp]
+    L.pr_set_free.restype = ctypes.c_int
+    L.pr_set_info.argtypes = [vp, ctypes.POINTER(SetInfo)]
+    L.pr_set_info.restype = ctypes.c_int
+    L.pr_set_solve_ifp2.argtypes = [vp, vp, ctypes.POINTER(Opts), dp, ctypes.POINTER(Stats)]
+    L.pr_set_solve_ifp2.restype = ctypes.c_int
     L.pr_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
     L.pr_server_opts_default.restype = None
     L.pr_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
@@ -229,6 +244,90 @@ def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0) -> Graph:
     if dedupe:
         g.m = g.info()["m"]
     return g
+
+
+class GraphSet:
+    """k graphs resident in device memory as one union (handle of pr_set_upload)."""
+
+    def __init__(self, handle, sizes):
+        self._h = handle
+        self.sizes = [int(x) for x in sizes]
+        self.k = len(self.sizes)
+        self.offsets = np.concatenate([[0], np.cumsum(self.sizes)]).astype(np.int64)
+        self.n = int(self.offsets[-1])
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("graph set was freed")
+        return self._h
+
+    def info(self) -> dict:
+        si = SetInfo()
+        st = lib().pr_set_info(self.handle, ctypes.byref(si))
+        if st != PR_OK:
+            raise _err(st)
+        return {k: getattr(si, k) for k, _ in si._fields_}
+
+    def split(self, pi):
+        """Per-graph views of a solution over the whole set."""
+        return [pi[int(self.offsets[g]):int(self.offsets[g + 1])] for g in range(self.k)]
+
+    def free(self):
+        if self._h is not None:
+            lib().pr_set_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def upload_set(graphs, tile_shift: int = 0) -> GraphSet:
+    """Upload host CSR graphs [(row_ptr int64[n+1], col int32[m]), ...] as one graph set."""
+    k = len(graphs)
+    rps = [np.ascontiguousarray(rp, dtype=np.int64) for rp, _ in graphs]
+    cols = [np.ascontiguousarray(c, dtype=np.int32) for _, c in graphs]
+    ns = np.array([r.shape[0] - 1 for r in rps], dtype=np.int64)
+    rp_ptrs = (ctypes.c_void_p * max(k, 1))(*[r.ctypes.data for r in rps])
+    col_ptrs = (ctypes.c_void_p * max(k, 1))(*[c.ctypes.data if c.size else None for c in cols])
+    h = ctypes.c_void_p()
+    st = lib().pr_set_upload(k, ns.ctypes.data if k else None, rp_ptrs, col_ptrs, (tile_shift & 7) << 8,
+                             ctypes.byref(h))
+    if st != PR_OK:
+        raise _err(st)
+    return GraphSet(h.value, ns)
+
+
+def set_ifp2(gs: GraphSet, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None, stream=None,
+             mode=None):
+    """IFP2 on every graph of a set: c is one factor or one per graph.  Returns
+    (solution over the whole set, list of per-graph stats dicts)."""
+    o = _opts(0.85, xi, l1_tol, residual, max_sweeps, stream, False, mode, False)
+    cs = None
+    if np.ndim(c) == 0:
+        o.c = float(c)
+    else:
+        cs = np.ascontiguousarray(c, dtype=np.float64)
+        if cs.shape != (gs.k,):
+            raise ValueError("c must be a scalar or have one entry per graph")
+    if out is None:
+        out = np.empty(gs.n, dtype=np.float64)
+    out_keep, out_ptr, out_dev = _ptr_any(out, np.float64, "float64")
+    if (out_keep.numel() if _is_torch(out_keep) else out_keep.shape[0]) != gs.n:
+        raise ValueError("out must have one entry per vertex of the set")
+    if not _is_torch(out) and out_keep is not out:
+        raise ValueError("out must be a contiguous float64 numpy array")
+    if out_dev:
+        o.flags |= PR_OUT_DEVICE
+    st = (Stats * gs.k)()
+    status = lib().pr_set_solve_ifp2(gs.handle, cs.ctypes.data if cs is not None else None, ctypes.byref(o),
+                                     out_ptr, st)
+    if status < 0:
+        raise _err(status)
+    return out, [dict(st[i].as_dict(), status=status) for i in range(gs.k)]
 
 
 def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, power=False):

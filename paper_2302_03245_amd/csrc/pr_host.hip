@@ -14,6 +14,7 @@
 #include <vector>
 
 #include "../../include/pr.h"
+#include "../../include/pr_set.h"
 #include "pr_internal.h"
 
 using namespace prk;
@@ -92,8 +93,12 @@ struct EventPair {
 // out-degree is how often its weight is gathered by a pull sweep (and, on
 // these graphs, tracks how often it is a scatter target), so the most-read
 // entries of the residual-sized vectors share cache lines and stay resident in
-// the per-XCD L2.  Stable LSD radix sort on the complemented degree.
-int32_t degree_order(int64_t n, const int64_t *rp, std::vector<int32_t> &perm, std::vector<int32_t> &newid) {
+// the per-XCD L2.  Stable LSD radix sort on the complemented degree.  With a
+// segment index per vertex (a graph set: segments are contiguous id ranges)
+// the order is by segment first, so every segment's non-dangling vertices,
+// and its dangling ones, stay contiguous.
+int32_t degree_order(int64_t n, const int64_t *rp, const int32_t *seg_of, std::vector<int32_t> &perm,
+                     std::vector<int32_t> &newid) {
     std::vector<int32_t> nd;
     std::vector<uint32_t> key;
     nd.reserve((size_t)n);
@@ -102,10 +107,13 @@ int32_t degree_order(int64_t n, const int64_t *rp, std::vector<int32_t> &perm, s
     const size_t nN = nd.size();
     std::vector<int32_t> tmp(nN);
     std::vector<uint32_t> cnt(1u << 16);
-    for (int pass = 0; pass < 2; ++pass) {
-        const int sh = 16 * pass;
+    for (int pass = 0; pass < (seg_of ? 4 : 2); ++pass) {
+        const int sh = 16 * (pass & 1);
         std::fill(cnt.begin(), cnt.end(), 0u);
-        auto kf = [&](int32_t v) { return ((~(uint32_t)(rp[v + 1] - rp[v])) >> sh) & 0xffffu; };
+        auto kf = [&](int32_t v) {
+            const uint32_t key = pass < 2 ? ~(uint32_t)(rp[v + 1] - rp[v]) : (uint32_t)seg_of[v];
+            return (key >> sh) & 0xffffu;
+        };
         for (int32_t v : nd) cnt[kf(v)]++;
         uint32_t run = 0;
         for (auto &c : cnt) {
@@ -127,7 +135,7 @@ int32_t degree_order(int64_t n, const int64_t *rp, std::vector<int32_t> &perm, s
 }
 
 pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
-                      pr_graph **out) {
+                      const int32_t *seg_of, pr_graph **out) {
     if (!out) return fail(PR_EINVAL, "out is NULL");
     if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE | PR_TILE_MASK)) return fail(PR_EINVAL, "unknown upload flag");
     const uint32_t tile_shift = (flags & PR_TILE_MASK) >> 8;
@@ -244,7 +252,7 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
 
     // vertex order on the device (see degree_order)
     std::vector<int32_t> h_perm, h_newid;
-    G.nN = degree_order(n, rp, h_perm, h_newid);
+    G.nN = degree_order(n, rp, seg_of, h_perm, h_newid);
     G.nD = (int32_t)(n - G.nN);
     G.dangling_bits.assign((size_t)(n + 63) / 64, 0);
     for (int64_t i = 0; i < n; ++i)
@@ -1003,6 +1011,231 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     return stopped ? PR_OK : PR_ENOCONV;
 }
 
+// ---------------------------------------------------------------------------
+// graph sets (include/pr_set.h)
+// ---------------------------------------------------------------------------
+}  // namespace
+
+struct pr_graph_set {
+    pr_graph *u = nullptr;                 // the block-diagonal union
+    int32_t k = 0;
+    std::vector<int64_t> n_g, off;         // vertices per graph; offsets in original ids (k + 1)
+    std::vector<int32_t> offN, offD;       // segment offsets in the two regions of the union (k + 1)
+    std::vector<int64_t> m_g, mND_g;       // edges, and edges into dangling vertices, per graph
+    int32_t *d_offN = nullptr, *d_offD = nullptr;
+    uint2 *d_tg_push = nullptr;            // graph range of every tile of the push plan
+    std::vector<uint2 *> d_tg_pull;        // ... and of every epoch's gather plan
+    ~pr_graph_set() {
+        if (d_offN) (void)hipFree(d_offN);
+        if (d_offD) (void)hipFree(d_offD);
+        if (d_tg_push) (void)hipFree(d_tg_push);
+        for (uint2 *p : d_tg_pull)
+            if (p) (void)hipFree(p);
+        if (u) (void)pr_graph_free(u);
+    }
+};
+
+namespace {
+
+pr_status set_upload_impl(int32_t k, const int64_t *n, const int64_t *const *row_ptr, const int32_t *const *col,
+                          uint32_t flags, pr_graph_set **out) {
+    if (!out) return fail(PR_EINVAL, "out is NULL");
+    if (k < 1) return fail(PR_EINVAL, "k must be >= 1");
+    if (!n || !row_ptr || !col) return fail(PR_EINVAL, "NULL array");
+    if (flags & ~PR_TILE_MASK) return fail(PR_EINVAL, "unknown upload flag for a graph set");
+    std::unique_ptr<pr_graph_set> S(new pr_graph_set());
+    S->k = k;
+    S->n_g.assign(n, n + k);
+    S->off.assign((size_t)k + 1, 0);
+    int64_t mt = 0;
+    for (int32_t g = 0; g < k; ++g) {
+        if (n[g] < 1) return fail(PR_EINVAL, "every graph needs n >= 1");
+        const int64_t *rp = row_ptr[g];
+        if (!rp) return fail(PR_EINVAL, "row_ptr entry is NULL");
+        if (rp[0] != 0) return fail(PR_EINVAL, "row_ptr[0] != 0");
+        for (int64_t i = 0; i < n[g]; ++i)
+            if (rp[i + 1] < rp[i]) return fail(PR_EINVAL, "row_ptr is not non-decreasing");
+        const int64_t mg = rp[n[g]];
+        if (mg > 0 && !col[g]) return fail(PR_EINVAL, "col entry is NULL");
+        for (int64_t e = 0; e < mg; ++e)
+            if (col[g][e] < 0 || col[g][e] >= n[g]) return fail(PR_EINVAL, "col entry out of [0, n)");
+        S->off[(size_t)g + 1] = S->off[(size_t)g] + n[g];
+        mt += mg;
+        if (S->off[(size_t)g + 1] >= ((int64_t)1 << 31) || mt >= ((int64_t)1 << 31))
+            return fail(PR_EINVAL, "set exceeds 2^31 vertices or edges");
+    }
+    const int64_t nt = S->off[(size_t)k];
+    std::vector<int64_t> urp((size_t)nt + 1);
+    std::vector<int32_t> ucol((size_t)std::max<int64_t>(mt, 1));
+    std::vector<int32_t> seg((size_t)nt);
+    S->offN.assign((size_t)k + 1, 0);
+    S->offD.assign((size_t)k + 1, 0);
+    S->mND_g.assign((size_t)k, 0);
+    S->m_g.assign((size_t)k, 0);
+    int64_t e_at = 0;
+    for (int32_t g = 0; g < k; ++g) {
+        const int64_t *rp = row_ptr[g];
+        const int64_t o = S->off[(size_t)g];
+        int32_t nd = 0;
+        for (int64_t i = 0; i < n[g]; ++i) {
+            urp[(size_t)(o + i)] = e_at + rp[i];
+            seg[(size_t)(o + i)] = g;
+            nd += rp[i + 1] == rp[i];
+        }
+        int64_t mnd = 0;
+        for (int64_t e = 0; e < rp[n[g]]; ++e) {
+            const int32_t v = col[g][e];
+            ucol[(size_t)(e_at + e)] = (int32_t)(o + v);
+            mnd += rp[v + 1] == rp[v];
+        }
+        S->mND_g[(size_t)g] = mnd;
+        S->m_g[(size_t)g] = rp[n[g]];
+        S->offN[(size_t)g + 1] = S->offN[(size_t)g] + (int32_t)(n[g] - nd);
+        S->offD[(size_t)g + 1] = S->offD[(size_t)g] + nd;
+        e_at += rp[n[g]];
+    }
+    urp[(size_t)nt] = e_at;
+    pr_status ps = upload_impl(nt, mt, urp.data(), ucol.data(), flags, seg.data(), &S->u);
+    if (ps != PR_OK) return ps;
+    const Graph &G = S->u->g;
+    if (G.nN != S->offN[(size_t)k]) return fail(PR_EDEVICE, "internal: region sizes of the set disagree");
+    HIPCHK(hipMalloc((void **)&S->d_offN, sizeof(int32_t) * ((size_t)k + 1)));
+    HIPCHK(hipMalloc((void **)&S->d_offD, sizeof(int32_t) * ((size_t)k + 1)));
+    HIPCHK(hipMemcpy(S->d_offN, S->offN.data(), sizeof(int32_t) * ((size_t)k + 1), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(S->d_offD, S->offD.data(), sizeof(int32_t) * ((size_t)k + 1), hipMemcpyHostToDevice));
+    auto tile_graphs = [&](const MPPlan &p, uint2 **dst) -> hipError_t {
+        hipError_t e = hipMalloc((void **)dst, sizeof(uint2) * (size_t)std::max<int32_t>(p.blocks, 1));
+        if (e != hipSuccess) return e;
+        return launch_set_tile_graphs(p, S->d_offN, k, *dst, G.stream);
+    };
+    HIPCHK(tile_graphs(G.push_nn, &S->d_tg_push));
+    S->d_tg_pull.assign(G.epochs.size(), nullptr);
+    for (size_t e = 0; e < G.epochs.size(); ++e) HIPCHK(tile_graphs(G.epochs[e].pull_nn, &S->d_tg_pull[e]));
+    HIPCHK(hipStreamSynchronize(G.stream));
+    *out = S.release();
+    return PR_OK;
+}
+
+template <typename T>
+pr_status solve_set_t(const pr_graph_set &S, const double *cg, const pr_opts &o, double *pi, pr_stats *st) {
+    const Graph &G = S.u->g;
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
+    const int64_t n = G.n;
+    const int32_t nN = G.nN, nD = G.nD, k = S.k;
+    const bool out_dev = o.flags & PR_OUT_DEVICE;
+    const bool l1 = o.stop == PR_STOP_L1;
+    const double tol = l1 ? o.l1_tol * (1.0 - 1e-6) : 0.0;
+    const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
+    const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
+
+    std::vector<SetG> hs((size_t)k);
+    for (int32_t g = 0; g < k; ++g) {
+        SetG &x = hs[(size_t)g];
+        memset(&x, 0, sizeof(x));
+        const double c = cg ? cg[g] : o.c;
+        if (!(c > 0.0 && c < 1.0)) return fail(PR_EINVAL, "every c must be in (0, 1)");
+        const int32_t nNg = S.offN[(size_t)g + 1] - S.offN[(size_t)g];
+        x.c = c;
+        // as for one graph: the threshold at which an empty frontier certifies the bound
+        x.xi = l1 ? o.l1_tol * (1.0 - c) / (2.0 * c) * (double)S.n_g[(size_t)g] / (double)std::max<int32_t>(nNg, 1) *
+                        (1.0 - 1e-9)
+                  : o.xi;
+        x.sx = (double)S.n_g[(size_t)g];
+        x.m_nn = (double)(S.m_g[(size_t)g] - S.mND_g[(size_t)g]);
+        x.last_bound = INFINITY;
+        x.stop_after = nNg > 0 ? INT_MAX : -1;
+    }
+
+    size_t bytes = carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
+                   carve_size<double>(nN) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
+                   carve_size<SetG>((size_t)k);
+    Workspace ws;
+    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
+    if (ps != PR_OK) return ps;
+    Carve cv{ws.base};
+    T *h = cv.take<T>(n);
+    T *w = cv.take<T>(nN);
+    double *pibar = cv.take<double>(nN);
+    double *xD = cv.take<double>(nD);
+    double *w2 = cv.take<double>(nN);
+    double *outbuf = cv.take<double>(out_dev ? 0 : n);
+    Ctl *ctl = cv.take<Ctl>(1);
+    SetG *gs = cv.take<SetG>((size_t)k);
+
+    EventPair ev_solve;
+    HIPCHK(hipEventRecord(ev_solve.a, s));
+    Ctl hc;
+    memset(&hc, 0, sizeof(hc));
+    hc.stop_after = INT_MAX;
+    HIPCHK(hipMemcpyAsync(ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(gs, hs.data(), sizeof(SetG) * (size_t)k, hipMemcpyHostToDevice, s));
+    HIPCHK(launch_set_init<T>(n, nN, h, pibar, s));
+
+    int t = 0;
+    bool stopped = nN == 0;
+    if (nN > 0) {
+        int batch = l1 ? 8 : 16;
+        double bound_prev = -1.0;
+        int t_prev = 0;
+        while (t < max_sweeps) {
+            const int nb = std::min(batch, max_sweeps - t);
+            for (int q = 0; q < nb; ++q, ++t) {
+                size_t e = 0;
+                while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
+                const MPPlan &pullp = G.epochs[e].pull_nn;
+                // share of the N -> N edges still in this epoch's gather lists
+                const double live_frac = G.mNN > 0 ? (double)pullp.edges() / (double)G.mNN : 0.0;
+                HIPCHK(launch_set_reserve<T>(t, ctl, gs, S.d_offN, k, nN, h, w, pibar, G.deg, G.rp_nn, s));
+                HIPCHK(launch_set_decide(t, ctl, gs, k, l1 ? 1 : 0, tol, live_frac, force, s));
+                if (force != 2) HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, force == 0, s, TileSkip{S.d_tg_push, gs}));
+                if (force != 1)
+                    HIPCHK(launch_pull<T, T>(t, ctl, pullp, w, h, force == 0, s, TileSkip{S.d_tg_pull[e], gs}));
+            }
+            HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (ws.hctl->stop_after < t) {
+                stopped = true;
+                break;
+            }
+            batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, l1);
+            bound_prev = ws.hctl->last_bound;
+            t_prev = t;
+        }
+    }
+    if (nD > 0) {
+        HIPCHK(launch_set_phase2_prep<T>(n, nN, gs, S.d_offN, k, h, pibar, G.deg, w2, xD, s));
+        HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
+    }
+    double *dst = out_dev ? pi : outbuf;
+    HIPCHK(launch_set_final<T>(n, nN, gs, S.d_offN, S.d_offD, k, G.perm, h, pibar, xD, dst, s));
+    HIPCHK(hipEventRecord(ev_solve.b, s));
+    HIPCHK(hipMemcpyAsync(hs.data(), gs, sizeof(SetG) * (size_t)k, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const double secs = elapsed_s(ev_solve.a, ev_solve.b);
+    bool all = true;
+    for (int32_t g = 0; g < k; ++g) {
+        const SetG &x = hs[(size_t)g];
+        const bool conv = x.stop_after < INT_MAX || stopped;
+        all = all && conv;
+        if (!st) continue;
+        pr_stats z;
+        memset(&z, 0, sizeof(z));
+        z.sweeps = x.sweeps;
+        z.pull_sweeps = ws.hctl->pull_sweeps;
+        z.edges_processed = (int64_t)x.tot_edges + S.mND_g[(size_t)g];
+        z.edges_traversed = z.edges_processed;
+        z.vertex_pushes = (int64_t)x.tot_pushes;
+        z.residual_l1 = x.fin_sum > 0 ? x.fin_sn / x.fin_sum : 0.0;
+        z.l1_bound = x.fin_sum > 0 ? 2.0 * x.c / (1.0 - x.c) * x.fin_sn / x.fin_sum : 0.0;
+        z.seconds_solve = secs;
+        z.seconds_preprocess = G.seconds_split;
+        st[g] = z;
+    }
+    return all ? PR_OK : PR_ENOCONV;
+}
+
 pr_status opts_or_default(const pr_opts *o, pr_opts *out) {
     if (o) *out = *o;
     else pr_opts_default(out);
@@ -1060,7 +1293,7 @@ pr_status pr_graph_upload(int64_t n, int64_t m, const int64_t *row_ptr, const in
                           pr_graph **out) {
     g_err.clear();
     try {
-        return upload_impl(n, m, row_ptr, col, flags, out);
+        return upload_impl(n, m, row_ptr, col, flags, nullptr, out);
     } catch (const std::bad_alloc &) {
         return fail(PR_ENOMEM, "host allocation");
     }
@@ -1116,6 +1349,59 @@ static pr_status solve_common(const pr_graph *g, int method, const double *p, co
         const bool ifp2 = method == 2;
         return op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, ifp2, p, -1, op, pi, st)
                                           : solve_ifp_t<double>(G, ifp2, p, -1, op, pi, st);
+    } catch (const std::bad_alloc &) {
+        return fail(PR_ENOMEM, "host allocation");
+    }
+}
+
+pr_status pr_set_upload(int32_t k, const int64_t *n, const int64_t *const *row_ptr, const int32_t *const *col,
+                        uint32_t flags, pr_graph_set **out) {
+    g_err.clear();
+    try {
+        return set_upload_impl(k, n, row_ptr, col, flags, out);
+    } catch (const std::bad_alloc &) {
+        return fail(PR_ENOMEM, "host allocation");
+    }
+}
+
+pr_status pr_set_free(pr_graph_set *s) {
+    g_err.clear();
+    if (!s) return PR_OK;
+    (void)hipSetDevice(s->u->g.device);
+    delete s;
+    return PR_OK;
+}
+
+pr_status pr_set_info(const pr_graph_set *s, pr_set_info_t *out) {
+    g_err.clear();
+    if (!s || !out) return fail(PR_EINVAL, "NULL argument");
+    const Graph &G = s->u->g;
+    out->k = s->k;
+    out->n = G.n;
+    out->m = G.m;
+    out->n_dangling = G.nD;
+    out->m_dangling = G.mND;
+    out->device_bytes = G.device_bytes + (int64_t)(2 * sizeof(int32_t) * ((size_t)s->k + 1));
+    out->seconds_upload = G.seconds_upload;
+    return PR_OK;
+}
+
+pr_status pr_set_solve_ifp2(const pr_graph_set *s, const double *c, const pr_opts *o, double *pi, pr_stats *st) {
+    g_err.clear();
+    if (!s) return fail(PR_EINVAL, "graph set is NULL");
+    if (!pi) return fail(PR_EINVAL, "pi is NULL");
+    pr_opts op;
+    opts_or_default(o, &op);
+    if (c) op.c = 0.5;  // per-graph factors are checked by the solve
+    pr_status ps = check_opts(op, false);
+    if (ps != PR_OK) return ps;
+    if (op.flags & (PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE))
+        return fail(PR_EINVAL, "option flag not supported for graph sets");
+    ps = enter(s->u);
+    if (ps != PR_OK) return ps;
+    try {
+        return op.residual == PR_RES_FP32 ? solve_set_t<float>(*s, c, op, pi, st)
+                                          : solve_set_t<double>(*s, c, op, pi, st);
     } catch (const std::bad_alloc &) {
         return fail(PR_ENOMEM, "host allocation");
     }

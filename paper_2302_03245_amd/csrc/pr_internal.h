@@ -86,6 +86,29 @@ struct OutSet {
     double *p[kMaxBatch];
 };
 
+// Per-graph state of a multi-graph solve (device memory, one entry per graph).
+// fin_sum and fin_sn are adjacent, and so are the five acc entries: the
+// kernels accumulate into them as runs of doubles.
+struct alignas(8) SetG {
+    double c;             // damping factor of this graph
+    double xi;            // push threshold (units where h0 = 1 per vertex)
+    double sx;            // total mass sum(pibar + h) + untouched dangling mass
+    double last_bound;    // bound certified at the last reserve
+    double fin_sum, fin_sn;
+    double acc[5];        // this sweep: inactive residual, mass to N, sx growth, pushes, pushed edges
+    double m_nn;          // edges between non-dangling vertices (what a gather of this graph reads)
+    unsigned long long tot_pushes, tot_edges;
+    int32_t stop_after;   // last sweep whose scatter counts (INT_MAX while running)
+    int32_t sweeps;
+};
+
+// Graph-set sweeps: per merge-path tile the first and last graph of its rows,
+// so that tiles of graphs that stopped are skipped (all null for one graph).
+struct TileSkip {
+    const uint2 *tgr = nullptr;  // [tiles]
+    const SetG *gs = nullptr;
+};
+
 struct Trace {
     unsigned long long cnt[kMaxTrace];
     unsigned long long edges[kMaxTrace];
@@ -196,10 +219,11 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
                           unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
                           double *part, hipStream_t s);
 template <typename T>
-hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s);
+hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
+                       TileSkip skip = TileSkip());
 template <typename WT, typename OT>
 hipError_t launch_pull(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
-                       hipStream_t s);
+                       hipStream_t s, TileSkip skip = TileSkip());
 template <typename T>
 hipError_t launch_phase2_prep(const InitArgs &a, const T *h, const double *pibar, const int32_t *deg, double c,
                               int literal, double *w2, double *xD, hipStream_t s);
@@ -214,6 +238,25 @@ hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStrea
 hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, double *part, hipStream_t s);
 hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s);
 hipError_t launch_unit_vector(double *out, int64_t n, int64_t src, hipStream_t s);
+
+// multi-graph solve (pr_set.hip); offN / offD: k + 1 segment offsets of the
+// graphs in the non-dangling and dangling regions of the union
+template <typename T>
+hipError_t launch_set_init(int64_t n, int32_t nN, T *h, double *pibar, hipStream_t s);
+template <typename T>
+hipError_t launch_set_reserve(int t, const Ctl *ctl, SetG *gs, const int32_t *offN, int32_t k, int32_t nN, T *h,
+                              T *w, double *pibar, const int32_t *deg, const uint32_t *rp_nn, hipStream_t s);
+hipError_t launch_set_tile_graphs(const MPPlan &p, const int32_t *offN, int32_t k, uint2 *out, hipStream_t s);
+hipError_t launch_set_decide(int t, Ctl *ctl, SetG *gs, int32_t k, int stop_l1, double tol, double live_frac,
+                             int force, hipStream_t s);
+template <typename T>
+hipError_t launch_set_phase2_prep(int64_t n, int32_t nN, const SetG *gs, const int32_t *offN, int32_t k,
+                                  const T *h, const double *pibar, const int32_t *deg, double *w2, double *xD,
+                                  hipStream_t s);
+template <typename T>
+hipError_t launch_set_final(int64_t n, int32_t nN, SetG *gs, const int32_t *offN, const int32_t *offD, int32_t k,
+                            const int32_t *perm, const T *h, const double *pibar, const double *xD, double *out,
+                            hipStream_t s);
 
 // batched IFP2 (pr_batch.hip)
 template <typename T, int B>

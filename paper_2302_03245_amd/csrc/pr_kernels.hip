@@ -404,6 +404,15 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
     }
 }
 
+// graph-set sweeps: a tile whose rows all belong to graphs that stopped before
+// sweep t has nothing to move (their weights are zero)
+__device__ __forceinline__ bool tile_frozen(const TileSkip &sk, int32_t tile, int t) {
+    const uint2 r = sk.tgr[tile];
+    for (uint32_t g = r.x; g <= r.y; ++g)
+        if (sk.gs[g].stop_after >= t) return false;
+    return true;
+}
+
 // Scatter step (push): every edge i -> j of a row with w_i != 0 adds w_i to h_j
 // with a hardware FP atomic.  Merge-path tiles give every tile the same number
 // of rows + edges, so a hub row is spread over many tiles and a run of short
@@ -413,7 +422,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
 template <typename T, int K>
 __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
                                                  int32_t R, const int32_t *col, const uint2 *plan, uint32_t items,
-                                                 int32_t ntiles, const T *w, T *h) {
+                                                 int32_t ntiles, const T *w, T *h, TileSkip skip) {
     constexpr int IPB = K * kBlock;
     if (t >= 0 && (t > ctl->stop_after || (check_mode && ctl->use_pull))) return;
     __shared__ uint32_t s_end[IPB + 1];
@@ -421,6 +430,7 @@ __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int chec
     __shared__ T s_w[IPB + 1];
     const uint32_t rp0 = rp[0];
     for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (skip.tgr && tile_frozen(skip, tile, t)) continue;  // uniform over the workgroup
         const uint2 a = plan[tile], b = plan[tile + 1];
         const int32_t i0 = (int32_t)a.x;
         const int32_t i1 = min((int32_t)b.x, R - 1);
@@ -497,7 +507,7 @@ __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int chec
 template <typename WT, typename OT, int K>
 __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
                                                  int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
-                                                 int32_t ntiles, const WT *w, OT *out) {
+                                                 int32_t ntiles, const WT *w, OT *out, TileSkip skip) {
     constexpr int IPB = K * kBlock;
     if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
     __shared__ uint32_t s_end[IPB + 1];
@@ -505,6 +515,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
     __shared__ double s_acc[IPB + 1];
     const uint32_t rp0 = rp[0];
     for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        if (skip.tgr && tile_frozen(skip, tile, t)) continue;  // uniform over the workgroup
         const uint2 a = plan[tile], b = plan[tile + 1];
         const int32_t i0 = (int32_t)a.x;
         const int32_t i1 = min((int32_t)b.x, R - 1);
@@ -862,41 +873,43 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
 }
 
 template <typename T, int K>
-hipError_t launch_push_k(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s) {
+hipError_t launch_push_k(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
+                         TileSkip skip) {
     static const int grid = resident_grid(k_push<T, K>);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_push<T, K>), dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl,
-                       check_mode, p.rp, p.R, p.idx, (const uint2 *)p.plan, p.items, p.blocks, w, h);
+                       check_mode, p.rp, p.R, p.idx, (const uint2 *)p.plan, p.items, p.blocks, w, h, skip);
     return hipGetLastError();
 }
 
 template <typename T>
-hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s) {
+hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
+                       TileSkip skip) {
     if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
     switch (p.ipb / kBlock) {
-        case 4: return launch_push_k<T, 4>(t, ctl, p, w, h, check_mode, s);
-        case 16: return launch_push_k<T, 16>(t, ctl, p, w, h, check_mode, s);
-        default: return launch_push_k<T, 8>(t, ctl, p, w, h, check_mode, s);
+        case 4: return launch_push_k<T, 4>(t, ctl, p, w, h, check_mode, s, skip);
+        case 16: return launch_push_k<T, 16>(t, ctl, p, w, h, check_mode, s, skip);
+        default: return launch_push_k<T, 8>(t, ctl, p, w, h, check_mode, s, skip);
     }
 }
 
 template <typename WT, typename OT, int K>
 hipError_t launch_pull_k(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
-                         hipStream_t s) {
+                         hipStream_t s, TileSkip skip) {
     auto kern = &k_pull<WT, OT, K>;
     static const int grid = resident_grid(kern);
     hipLaunchKernelGGL(kern, dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R,
-                       p.idx, (const uint2 *)p.plan, p.items, p.blocks, w, out);
+                       p.idx, (const uint2 *)p.plan, p.items, p.blocks, w, out, skip);
     return hipGetLastError();
 }
 
 template <typename WT, typename OT>
 hipError_t launch_pull(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
-                       hipStream_t s) {
+                       hipStream_t s, TileSkip skip) {
     if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
     switch (p.ipb / kBlock) {
-        case 4: return launch_pull_k<WT, OT, 4>(t, ctl, p, w, out, check_mode, s);
-        case 16: return launch_pull_k<WT, OT, 16>(t, ctl, p, w, out, check_mode, s);
-        default: return launch_pull_k<WT, OT, 8>(t, ctl, p, w, out, check_mode, s);
+        case 4: return launch_pull_k<WT, OT, 4>(t, ctl, p, w, out, check_mode, s, skip);
+        case 16: return launch_pull_k<WT, OT, 16>(t, ctl, p, w, out, check_mode, s, skip);
+        default: return launch_pull_k<WT, OT, 8>(t, ctl, p, w, out, check_mode, s, skip);
     }
 }
 
@@ -963,15 +976,16 @@ template hipError_t launch_reserve<float>(int, Ctl *, Trace *, int32_t, float *,
 template hipError_t launch_reserve<double>(int, Ctl *, Trace *, int32_t, double *, double *, double *,
                                            const int32_t *, const uint32_t *, double, double, int, int, double,
                                            unsigned long long, int, unsigned long long, double *, hipStream_t);
-template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t);
+template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t,
+                                       TileSkip);
 template hipError_t launch_push<double>(int, const Ctl *, const MPPlan &, const double *, double *, int,
-                                        hipStream_t);
+                                        hipStream_t, TileSkip);
 template hipError_t launch_pull<float, float>(int, const Ctl *, const MPPlan &, const float *, float *, int,
-                                              hipStream_t);
+                                              hipStream_t, TileSkip);
 template hipError_t launch_pull<double, double>(int, const Ctl *, const MPPlan &, const double *, double *, int,
-                                                hipStream_t);
+                                                hipStream_t, TileSkip);
 template hipError_t launch_pull<float, double>(int, const Ctl *, const MPPlan &, const float *, double *, int,
-                                               hipStream_t);
+                                               hipStream_t, TileSkip);
 template hipError_t launch_phase2_prep<float>(const InitArgs &, const float *, const double *, const int32_t *,
                                               double, int, double *, double *, hipStream_t);
 template hipError_t launch_phase2_prep<double>(const InitArgs &, const double *, const double *, const int32_t *,

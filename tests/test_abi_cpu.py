@@ -15,7 +15,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libpr.so not bu
 
 def _declared():
     names = set()
-    for h in ("pr.h", "pr_probe.h", "pr_serve.h"):
+    for h in ("pr.h", "pr_probe.h", "pr_serve.h", "pr_set.h"):
         txt = open(os.path.join(ROOT, "include", h)).read()
         txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
         for m in re.finditer(r"^\s*[A-Za-z_][\w \*]*?\b(pr_\w+)\s*\(", txt, flags=re.M):
@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported():
     import paper_2302_03245_amd as pr
 
     names = _declared()
-    assert len(names) >= 21
+    assert len(names) >= 25
     lib = ctypes.CDLL(LIB)
     for name in names:
         assert hasattr(lib, name), name
@@ -63,6 +63,46 @@ def test_upload_rejects_invalid_host_input(n, m, rp, col, flags, msg):
     assert st == pr.PR_EINVAL
     assert msg in L.pr_last_error().decode()
     assert h.value is None
+
+
+def _set_args(graphs):
+    rps = [np.asarray(rp, np.int64) for rp, _ in graphs]
+    cols = [np.asarray(c if c else [0], np.int32) for _, c in graphs]
+    ns = np.array([len(r) - 1 for r in rps], np.int64)
+    return (rps, cols, ns, (ctypes.c_void_p * len(rps))(*[r.ctypes.data for r in rps]),
+            (ctypes.c_void_p * len(cols))(*[c.ctypes.data for c in cols]))
+
+
+@pytest.mark.parametrize("graphs,flags,msg", [
+    ([([0, 1, 1], [1]), ([0], [])], 0, "n >= 1"),
+    ([([0, 1, 1], [1]), ([0, 2, 1], [0, 1])], 0, "non-decreasing"),
+    ([([0, 1, 1], [1]), ([1, 1], [0])], 0, "row_ptr[0]"),
+    ([([0, 1, 1], [1]), ([0, 1, 1], [2])], 0, "out of [0, n)"),   # an edge into another graph
+    ([([0, 1, 1], [1])], 0x2, "unknown upload flag"),
+    ([([0, 1, 1], [1])], 0x1, "unknown upload flag"),
+])
+def test_set_upload_rejects_invalid_host_input(graphs, flags, msg):
+    import paper_2302_03245_amd as pr
+
+    L = pr.lib()
+    rps, cols, ns, rp_ptrs, col_ptrs = _set_args(graphs)
+    h = ctypes.c_void_p()
+    st = L.pr_set_upload(len(graphs), ns.ctypes.data, rp_ptrs, col_ptrs, flags, ctypes.byref(h))
+    assert st == pr.PR_EINVAL
+    assert msg in L.pr_last_error().decode()
+    assert h.value is None
+    st = L.pr_set_upload(0, ns.ctypes.data, rp_ptrs, col_ptrs, 0, ctypes.byref(h))
+    assert st == pr.PR_EINVAL and "k must be" in L.pr_last_error().decode()
+
+
+def test_set_solve_rejects_null_set():
+    import paper_2302_03245_amd as pr
+
+    L = pr.lib()
+    out = np.zeros(4)
+    assert L.pr_set_solve_ifp2(None, None, None, out.ctypes.data, None) == pr.PR_EINVAL
+    assert "graph set is NULL" in L.pr_last_error().decode()
+    assert L.pr_set_free(None) == pr.PR_OK
 
 
 def test_solve_rejects_null_graph_and_bad_options():

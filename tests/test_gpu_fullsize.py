@@ -76,3 +76,44 @@ def pr_lib():
     import paper_2302_03245_amd as pr
     pr.lib()
     return pr
+
+
+def _eq_residual_c(g, pi, c):
+    deg = np.diff(g.row_ptr)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    inv = np.zeros(g.n)
+    inv[deg > 0] = 1.0 / deg[deg > 0]
+    P = sp.csr_matrix((inv[src], (g.col, src)), shape=(g.n, g.n))
+    gamma = 1 - c + c * pi[deg == 0].sum()
+    return float(np.abs(pi - c * (P @ pi) - gamma / g.n).sum())
+
+
+@pytest.mark.timeout(900)
+def test_graph_set_256(pr_lib):
+    """The batched workload: 256 R-MAT graphs (n log-uniform in [1k, 500k], average
+    degree in [4, 32], 5-20 % dangling, c in {0.85, 0.9}) solved as one set with
+    FP32 residuals at L1 <= 1e-6, as bench.py times it.  Every graph: certified
+    bound, unit sum, and the PageRank-equation residual within (1 + c) * 1e-6 (it
+    holds for any vector within 1e-6 of the solution); the eight smallest graphs
+    and two larger ones also against the FP64 oracle element by element."""
+    pr = pr_lib
+    graphs, cs = prgen.workload_batch(count=256, seed=0)
+    print(f"set: n {sum(g.n for g in graphs)} m {sum(g.m for g in graphs)}", flush=True)
+    gs = pr.upload_set([(g.row_ptr, g.col) for g in graphs])
+    pi, sts = pr.set_ifp2(gs, c=cs, l1_tol=1e-6, residual="fp32")
+    parts = gs.split(pi)
+    for i, (g, c, x, st) in enumerate(zip(graphs, cs, parts, sts)):
+        assert st["status"] == 0 and st["l1_bound"] <= 1e-6, (i, st)
+        assert abs(x.sum() - 1.0) <= 1e-12, i
+        r = _eq_residual_c(g, x, c)
+        assert r <= (1 + c) * 1e-6, (i, g.n, r)
+    order = np.argsort([g.n for g in graphs])
+    sample = list(order[:8]) + [int(order[100]), int(order[140])]
+    for i in sample:
+        ref = oracle.power(graphs[i], cs[i], tol=1e-13)[0]
+        d = l1(parts[i], ref)
+        print(f"graph {i}: n {graphs[i].n} c {cs[i]} L1 vs oracle {d:.3e}", flush=True)
+        assert d <= 1e-6, (i, d)
+        ok, swaps, eps = topk_agree(ref, parts[i], min(1000, graphs[i].n))
+        assert ok, (i, swaps, eps)
+    gs.free()
