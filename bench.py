@@ -28,9 +28,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha():
-    with open(os.path.join(ROOT, "paper_2302_03245_amd", "csrc", "pr_kernels.hip"), "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()[:12]
+def kernel_source_sha(kernel: str = "pull"):
+    """Hash of the source the counters depend on: the kernel's own text in
+    pr_kernels.hip (template line through its closing brace) and the device helpers."""
+    csrc = os.path.join(ROOT, "paper_2302_03245_amd", "csrc")
+    src = open(os.path.join(csrc, "pr_kernels.hip")).read()
+    start = src.index(f"void k_{kernel}(")
+    start = src.rindex("template", 0, start)
+    end = src.index("\n}\n", start) + 3
+    body = src[start:end] + open(os.path.join(csrc, "pr_device.h")).read()
+    return hashlib.sha1(body.encode()).hexdigest()[:12]
 
 
 def traffic_from_profiles(kernel: str, workload: str):
@@ -40,7 +47,7 @@ def traffic_from_profiles(kernel: str, workload: str):
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_source_sha") != kernel_source_sha():
+    if d.get("kernel_source_sha") != kernel_source_sha(kernel):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -148,8 +155,11 @@ def main():
     kbytes = sum(s[f"{kern}_bytes"] for s in st_ifp2)
     achieved = kbytes / secs / 1e9 if secs > 0 else 0.0
     traffic = traffic_from_profiles(kern, wl_key)
+    avg_s = secs / max(launches, 1)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic, "kernel": f"k_{kern}<float>",
+                "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
+                "traffic_gbs": traffic / avg_s / 1e9 if traffic and avg_s > 0 else None,
+                "kernel": f"k_{kern}<float>",
                 "launches": launches, "avg_launch_us": secs / max(launches, 1) * 1e6,
                 "algorithmic_bytes_per_launch": kbytes / max(launches, 1)}
 
