@@ -40,14 +40,18 @@ def kernel_source_sha(kernel: str = "pull"):
     return hashlib.sha1(body.encode()).hexdigest()[:12]
 
 
-def traffic_from_profiles(kernel: str, workload: str):
+def traffic_from_profiles(kernel: str, workload: str, alg_bytes_per_launch: float):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source; else None."""
+    on the current kernel source and on launches of the same size (algorithmic bytes per
+    launch within 1 %); else None."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
     if d.get("kernel_source_sha") != kernel_source_sha(kernel):
+        return None
+    ref = d.get("algorithmic_bytes_per_launch") or 0.0
+    if abs(ref - alg_bytes_per_launch) > 0.01 * alg_bytes_per_launch:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -84,6 +88,7 @@ def main():
     ap.add_argument("--probes", action="store_true", help="also run the copy / gather / scatter probes")
     ap.add_argument("--ppr", type=int, default=16,
                     help="single-source PPR queries timed one at a time and batched (0 = skip)")
+    ap.add_argument("--no-tune", action="store_true", help="skip the per-graph schedule autotuner")
     ap.add_argument("--set-count", type=int, default=256,
                     help="batched solves: independent graphs solved as one set (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -119,8 +124,13 @@ def main():
         wl_key = "dag23"
     log(f"[bench] n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f}s")
     dg = pr.upload(g.row_ptr, g.col, tile_shift=args.tile_shift)
+    log(f"[bench] uploaded: {dg.info()}")
+    tuning = None
+    if not args.no_tune and args.mode is None and args.tile_shift == 0:
+        # one-time per graph, like the upload: pick the sweep schedule of global solves
+        tuning = pr.tune(dg, c=c, l1_tol=args.tol, residual="fp32", reps=2)
+        log(f"[bench] tuned in {tuning['seconds']:.2f}s: chosen {tuning['chosen']}; candidates {tuning['candidates']}")
     info = dg.info()
-    log(f"[bench] uploaded: {info}")
     out = torch.empty(g.n, dtype=torch.float64, device="cuda")
 
     def run_ifp2(profile=False):
@@ -134,7 +144,9 @@ def main():
             fn()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        stats = [fn(True)[1] for _ in range(args.steps)]
+        # HIP events around every sweep kernel of the last timed step only (the roofline
+        # figures); the other steps run without them
+        stats = [fn(i == args.steps - 1)[1] for i in range(args.steps)]
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / args.steps, stats
 
@@ -147,14 +159,15 @@ def main():
     assert all(s["status"] == 0 and s["l1_bound"] <= args.tol for s in st_ifp2 + st_pow)
 
     # dominant kernel of the IFP2 step: the scatter (push) or gather (pull) kernel
-    push_s = sum(s["push_seconds"] for s in st_ifp2)
-    pull_s = sum(s["pull_seconds"] for s in st_ifp2)
+    prof = st_ifp2[-1:]
+    push_s = sum(s["push_seconds"] for s in prof)
+    pull_s = sum(s["pull_seconds"] for s in prof)
     kern = "push" if push_s >= pull_s else "pull"
     secs = push_s if kern == "push" else pull_s
-    launches = sum(s[f"{kern}_launches"] for s in st_ifp2)
-    kbytes = sum(s[f"{kern}_bytes"] for s in st_ifp2)
+    launches = sum(s[f"{kern}_launches"] for s in prof)
+    kbytes = sum(s[f"{kern}_bytes"] for s in prof)
     achieved = kbytes / secs / 1e9 if secs > 0 else 0.0
-    traffic = traffic_from_profiles(kern, wl_key)
+    traffic = traffic_from_profiles(kern, wl_key, kbytes / max(launches, 1))
     avg_s = secs / max(launches, 1)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
@@ -196,6 +209,9 @@ def main():
                   "l1_bound": st_pow[-1]["l1_bound"]},
         "ifp2_over_power": t_pow / t_ifp2,
         "upload_s": info["seconds_upload"],
+        "tuning": tuning,
+        "schedule": {"tile_items": info["tile_items"], "ordered_sweeps": bool(info["ordered"]),
+                     "groups": info["groups"]},
         "depth_epochs": info["epochs"], "max_depth": info["max_depth"],
     }
     if args.ppr > 0:

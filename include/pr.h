@@ -61,6 +61,10 @@ typedef enum {
    s in {2, 3, 4}; 0 selects the default (s = 3) */
 #define PR_TILE_SHIFT(s) (((uint32_t)(s) & 0x7u) << 8)
 #define PR_TILE_MASK 0x700u
+/* ordered sweeps of global IFP2 solves: the non-dangling vertices are split into k
+   groups of equal out-edge counts (k in 1..15; 1 = no ordered sweeps; 0 selects 4) */
+#define PR_GROUPS(k) (((uint32_t)(k) & 0xFu) << 12)
+#define PR_GROUPS_MASK 0xF000u
 
 /* pr_opts.flags */
 #define PR_P_DEVICE 0x1u     /* p is a device pointer (double[n]) */
@@ -69,6 +73,7 @@ typedef enum {
 #define PR_FORCE_PUSH 0x8u   /* every sweep scatters along out-edges with atomic adds */
 #define PR_FORCE_PULL 0x10u  /* every sweep gathers along in-edges (no atomics) */
 #define PR_PROFILE 0x20u     /* time each sweep kernel with HIP events (stats->kernel_*) */
+#define PR_JACOBI 0x40u      /* IFP2 global solves: synchronous sweeps even where ordered sweeps apply */
 
 typedef struct {
     double c;           /* damping factor, 0 < c < 1 (section 2.1) */
@@ -78,7 +83,8 @@ typedef struct {
     int32_t stop;       /* pr_stop */
     int32_t residual;   /* pr_residual */
     int32_t max_sweeps; /* 0 -> 100000 */
-    uint32_t flags;     /* PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE */
+    uint32_t flags;     /* PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE
+                           | PR_JACOBI */
     void *stream;       /* hipStream_t to run on; NULL -> the graph's own stream */
 } pr_opts;
 
@@ -114,6 +120,9 @@ typedef struct {
     int64_t max_depth;      /* largest finite unreferenced depth of a non-dangling vertex (0: a
                                vertex without non-dangling in-neighbours; -1: none), see below */
     int64_t epochs;         /* in-edge lists kept for the gather sweeps (1 + compacted copies) */
+    int64_t groups;         /* vertex groups of ordered sweeps (1: none) */
+    int64_t tile_items;     /* rows + edges per sweep tile (256 << tile shift) */
+    int64_t ordered;        /* 1 if global IFP2 solves use ordered sweeps */
 } pr_graph_info_t;
 
 /*
@@ -150,6 +159,31 @@ pr_status pr_graph_free(pr_graph *g);
  */
 pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out);
 
+/* Outcome of pr_graph_tune: every candidate schedule that was timed. */
+#define PR_TUNE_MAX 8
+typedef struct {
+    int32_t candidates;               /* entries filled below */
+    int32_t tile_shift[PR_TUNE_MAX];  /* sweep tiles of 256 << s rows + edges per workgroup */
+    int32_t ordered[PR_TUNE_MAX];     /* 1: ordered sweeps over the vertex groups; 0: synchronous */
+    double ms[PR_TUNE_MAX];           /* fastest of the timed solves, device milliseconds */
+    int32_t sweeps[PR_TUNE_MAX];
+    int32_t chosen;                   /* index of the candidate the graph keeps */
+    double seconds;                   /* wall time spent tuning */
+} pr_tune_report;
+
+/*
+ * Autotuner of the sweep schedule for global solves on this graph: times IFP2 with
+ * the options o (c, stop rule, tolerance, residual type; p uniform) for every tile
+ * size s in {2, 3, 4} with synchronous sweeps and, when the graph has vertex groups,
+ * with ordered sweeps (the split of a sweep's work between per-vertex reserve
+ * passes and per-edge gathers), `reps` solves each after one warm-up (reps <= 0:
+ * 2), and keeps the fastest: later solves of every kind use its tile size, and
+ * global IFP2 solves use ordered sweeps only if it chose them.  Results do not
+ * change beyond rounding order.  No other call may use the graph meanwhile.
+ * rep may be NULL.  PR_EINVAL on bad options or forced scatter modes.
+ */
+pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_report *rep);
+
 /*
  * IFP1 (section 3.2, Algorithm 2): every non-dangling vertex whose residual
  * exceeds the threshold reserves 100 % of it and pushes c * r / deg(i) to each
@@ -174,6 +208,14 @@ pr_status pr_solve_ifp1(const pr_graph *g, const double *p, const pr_opts *o, do
  * deg being the original out-degree.  z = pibar + h by default;
  * PR_IFP2_LITERAL uses z = pibar and drops the leftover residual as the
  * algorithm is written.  Arguments and errors as pr_solve_ifp1.
+ *
+ * Global solves (p = NULL) of a graph uploaded with more than one vertex group
+ * (PR_GROUPS, default 4) use ordered sweeps: within a sweep the groups, in
+ * order of decreasing out-degree, each take their residuals and gather their
+ * pushes before the next group takes its own, so later groups already see this
+ * sweep's pushes -- the effect of the paper's calculation threads pushing as
+ * they go -- and fewer sweeps reach the bound.  Unless the options force a
+ * scatter mode or set PR_JACOBI; the stop rule and its certificate are the same.
  */
 pr_status pr_solve_ifp2(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st);
 

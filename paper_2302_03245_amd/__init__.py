@@ -24,7 +24,7 @@ PR_RES_FP64, PR_RES_FP32 = 0, 1
 PR_STOP_XI, PR_STOP_L1 = 0, 1
 PR_INPUT_DEVICE, PR_DEDUPE = 0x1, 0x2
 PR_P_DEVICE, PR_OUT_DEVICE, PR_IFP2_LITERAL = 0x1, 0x2, 0x4
-PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE = 0x8, 0x10, 0x20
+PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE, PR_JACOBI = 0x8, 0x10, 0x20, 0x40
 
 # every symbol the public headers declare
 EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_info", "pr_solve_ifp1",
@@ -32,7 +32,7 @@ EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_inf
             "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len",
             "pr_server_opts_default", "pr_server_create", "pr_server_add_graph", "pr_server_submit",
             "pr_server_wait", "pr_server_get_stats", "pr_server_destroy",
-            "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2"]
+            "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2", "pr_graph_tune"]
 
 
 class PRError(RuntimeError):
@@ -84,7 +84,14 @@ class GraphInfo(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("m", ctypes.c_int64), ("n_dangling", ctypes.c_int64),
                 ("m_dangling", ctypes.c_int64), ("n_unreferenced", ctypes.c_int64),
                 ("device_bytes", ctypes.c_int64), ("seconds_upload", ctypes.c_double),
-                ("seconds_split", ctypes.c_double), ("max_depth", ctypes.c_int64), ("epochs", ctypes.c_int64)]
+                ("seconds_split", ctypes.c_double), ("max_depth", ctypes.c_int64), ("epochs", ctypes.c_int64),
+                ("groups", ctypes.c_int64), ("tile_items", ctypes.c_int64), ("ordered", ctypes.c_int64)]
+
+
+class TuneReport(ctypes.Structure):
+    _fields_ = [("candidates", ctypes.c_int32), ("tile_shift", ctypes.c_int32 * 8), ("ordered", ctypes.c_int32 * 8),
+                ("ms", ctypes.c_double * 8), ("sweeps", ctypes.c_int32 * 8), ("chosen", ctypes.c_int32),
+                ("seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -132,6 +139,8 @@ def lib():
     L.pr_probe_scatter.restype = ctypes.c_int
     L.pr_probe_gather_out_len.argtypes = [i64]
     L.pr_probe_gather_out_len.restype = i64
+    L.pr_graph_tune.argtypes = [vp, ctypes.POINTER(Opts), i32, ctypes.POINTER(TuneReport)]
+    L.pr_graph_tune.restype = ctypes.c_int
     L.pr_set_upload.argtypes = [i32, vp, vp, vp, u32, ctypes.POINTER(vp)]
     L.pr_set_upload.restype = ctypes.c_int
     L.pr_set_free.argtypes = [vp]
@@ -225,17 +234,19 @@ class Graph:
             pass
 
 
-def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0) -> Graph:
+def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0, groups: int = 0) -> Graph:
     """Copy a CSR graph (host numpy or device torch tensors) to the device.
 
-    `tile_shift` s in {2, 3, 4} sets 256 << s rows + edges per sweep tile (0: default)."""
+    `tile_shift` s in {2, 3, 4} sets 256 << s rows + edges per sweep tile (0: default);
+    `groups` k in 1..15 sets the vertex groups of ordered sweeps (0: default 4, 1: none)."""
     rp_keep, rp_ptr, rp_dev = _ptr_any(row_ptr, np.int64, "int64")
     col_keep, col_ptr, col_dev = _ptr_any(col, np.int32, "int32")
     if rp_dev != col_dev:
         raise ValueError("row_ptr and col must both be host or both be device buffers")
     n = (rp_keep.shape[0] if not _is_torch(rp_keep) else rp_keep.numel()) - 1
     m = col_keep.shape[0] if not _is_torch(col_keep) else col_keep.numel()
-    flags = (PR_INPUT_DEVICE if rp_dev else 0) | (PR_DEDUPE if dedupe else 0) | ((tile_shift & 7) << 8)
+    flags = (PR_INPUT_DEVICE if rp_dev else 0) | (PR_DEDUPE if dedupe else 0) | ((tile_shift & 7) << 8) | \
+        ((groups & 15) << 12)
     h = ctypes.c_void_p()
     st = lib().pr_graph_upload(int(n), int(m), rp_ptr, col_ptr if m else None, flags, ctypes.byref(h))
     if st != PR_OK:
@@ -244,6 +255,19 @@ def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0) -> Graph:
     if dedupe:
         g.m = g.info()["m"]
     return g
+
+
+def tune(g: Graph, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", reps=2) -> dict:
+    """Autotune the sweep schedule of global solves on g (pr_graph_tune); returns the report."""
+    o = _opts(c, xi, l1_tol, residual, 0, None, False, None, False)
+    r = TuneReport()
+    st = lib().pr_graph_tune(g.handle, ctypes.byref(o), int(reps), ctypes.byref(r))
+    if st != PR_OK:
+        raise _err(st)
+    k = r.candidates
+    cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "ms": r.ms[i], "sweeps": r.sweeps[i]}
+             for i in range(k)]
+    return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds}
 
 
 class GraphSet:
@@ -330,7 +354,7 @@ def set_ifp2(gs: GraphSet, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_s
     return out, [dict(st[i].as_dict(), status=status) for i in range(gs.k)]
 
 
-def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, power=False):
+def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, power=False, jacobi=False):
     o = Opts()
     lib().pr_opts_default(ctypes.byref(o))
     o.c = c
@@ -354,6 +378,8 @@ def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, p
         raise ValueError("mode must be None, 'push' or 'pull'")
     if profile:
         flags |= PR_PROFILE
+    if jacobi:
+        flags |= PR_JACOBI
     o.flags = flags
     return o
 
@@ -392,9 +418,10 @@ def ifp1(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_s
 
 
 def ifp2(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
-         stream=None, literal=False, mode=None, profile=False):
-    """IFP2 (Algorithm 3).  `literal` drops the leftover residual at normalisation."""
-    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile)
+         stream=None, literal=False, mode=None, profile=False, jacobi=False):
+    """IFP2 (Algorithm 3).  `literal` drops the leftover residual at normalisation;
+    `jacobi` keeps global solves on synchronous sweeps (no ordered groups)."""
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, jacobi=jacobi)
     return _solve(lib().pr_solve_ifp2, g, p, o, out)
 
 

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <climits>
 #include <memory>
 #include <new>
@@ -65,6 +66,11 @@ struct DevBufs {
 };
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+int64_t clock_now_ns() {
+    return std::chrono::duration_cast<std::chrono::nanoseconds>(std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
 
 double elapsed_s(hipEvent_t a, hipEvent_t b) {
     float ms = 0.f;
@@ -137,7 +143,8 @@ int32_t degree_order(int64_t n, const int64_t *rp, const int32_t *seg_of, std::v
 pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
                       const int32_t *seg_of, pr_graph **out) {
     if (!out) return fail(PR_EINVAL, "out is NULL");
-    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE | PR_TILE_MASK)) return fail(PR_EINVAL, "unknown upload flag");
+    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE | PR_TILE_MASK | PR_GROUPS_MASK))
+        return fail(PR_EINVAL, "unknown upload flag");
     const uint32_t tile_shift = (flags & PR_TILE_MASK) >> 8;
     if (tile_shift != 0 && (tile_shift < 2 || tile_shift > 4)) return fail(PR_EINVAL, "tile shift must be 2, 3 or 4");
     if (n < 1 || n >= ((int64_t)1 << 31)) return fail(PR_EINVAL, "n must be in [1, 2^31)");
@@ -390,7 +397,7 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
             Epoch ep;
             ep.t_start = t0;
             HIPCHK(galloc(&ep.in_ptr, (size_t)n + 1));
-            HIPCHK(launch_live_count((int32_t)n, G.in_ptr, G.in_src, G.depth, t0, d_cnt, s));
+            HIPCHK(launch_live_count((int32_t)n, G.in_ptr, G.in_src, G.depth, t0, 0, INT_MAX, d_cnt, s));
             HIPCHK(launch_scan_u32(d_cnt, ep.in_ptr, n, d_scan, s));
             uint32_t h_e[2] = {0, 0};
             HIPCHK(hipMemcpyAsync(&h_e[0], ep.in_ptr + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
@@ -399,10 +406,54 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
             ep.edges_all = h_e[0];
             ep.edges_nn = h_e[1];
             HIPCHK(galloc(&ep.in_src, (size_t)ep.edges_all));
-            HIPCHK(launch_live_fill((int32_t)n, G.in_ptr, G.in_src, G.depth, t0, ep.in_ptr, ep.in_src, s));
+            HIPCHK(launch_live_fill((int32_t)n, G.in_ptr, G.in_src, G.depth, t0, 0, INT_MAX, ep.in_ptr, ep.in_src,
+                                    s));
             HIPCHK(make_plan(ep.pull_all, ep.in_ptr, ep.in_src, (int32_t)n, ep.edges_all));
             HIPCHK(make_plan(ep.pull_nn, ep.in_ptr, ep.in_src, G.nN, ep.edges_nn));
             G.epochs.push_back(ep);
+        }
+    }
+
+    // Ordered sweeps (not for graph sets): source groups of equal N -> N out-edges in
+    // the degree order, and for every epoch the in-lists of the N targets split by group.
+    const int32_t ngroups_req = (flags & PR_GROUPS_MASK) ? (int32_t)((flags & PR_GROUPS_MASK) >> 12) : 4;
+    if (!seg_of && G.nN > 0 && G.mNN > 0 && ngroups_req > 1) {
+        std::vector<uint32_t> h_rpnn((size_t)G.nN + 1);
+        HIPCHK(hipMemcpyAsync(h_rpnn.data(), G.rp_nn, sizeof(uint32_t) * ((size_t)G.nN + 1), hipMemcpyDeviceToHost,
+                              s));
+        HIPCHK(hipStreamSynchronize(s));
+        G.grp.push_back(0);
+        for (int32_t q = 1; q < ngroups_req; ++q) {
+            const uint32_t target = (uint32_t)((double)G.mNN * q / ngroups_req);
+            const int32_t b = (int32_t)(std::lower_bound(h_rpnn.begin(), h_rpnn.end(), target) - h_rpnn.begin());
+            if (b > G.grp.back() && b < G.nN) G.grp.push_back(b);
+        }
+        G.grp.push_back(G.nN);
+        uint32_t *d_gc;
+        HIPCHK(tmp.alloc(&d_gc, (size_t)G.nN + 1));
+        for (size_t e = 0; e < G.epochs.size(); ++e) {
+            std::vector<MPPlan> plans;
+            std::vector<int64_t> edges;
+            for (size_t q = 0; q + 1 < G.grp.size(); ++q) {
+                uint32_t *gp;
+                int32_t *gs;
+                HIPCHK(galloc(&gp, (size_t)G.nN + 1));
+                HIPCHK(launch_live_count(G.nN, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
+                                         G.grp[q + 1], d_gc, s));
+                HIPCHK(launch_scan_u32(d_gc, gp, G.nN, d_scan, s));
+                uint32_t ge = 0;
+                HIPCHK(hipMemcpyAsync(&ge, gp + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipStreamSynchronize(s));
+                HIPCHK(galloc(&gs, (size_t)ge));
+                HIPCHK(launch_live_fill(G.nN, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
+                                        G.grp[q + 1], gp, gs, s));
+                MPPlan pl;
+                HIPCHK(make_plan(pl, gp, gs, G.nN, ge));
+                plans.push_back(pl);
+                edges.push_back(ge);
+            }
+            G.grp_pull.push_back(plans);
+            G.grp_edges.push_back(edges);
         }
     }
 
@@ -426,7 +477,8 @@ pr_status check_opts(const pr_opts &o, bool power) {
     if (o.stop != PR_STOP_XI && o.stop != PR_STOP_L1) return fail(PR_EINVAL, "unknown stop rule");
     if (o.residual != PR_RES_FP64 && o.residual != PR_RES_FP32) return fail(PR_EINVAL, "unknown residual type");
     if (o.max_sweeps < 0) return fail(PR_EINVAL, "max_sweeps < 0");
-    const uint32_t known = PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE;
+    const uint32_t known =
+        PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE | PR_JACOBI;
     if (o.flags & ~known) return fail(PR_EINVAL, "unknown option flag");
     if ((o.flags & PR_FORCE_PUSH) && (o.flags & PR_FORCE_PULL))
         return fail(PR_EINVAL, "PR_FORCE_PUSH and PR_FORCE_PULL together");
@@ -557,19 +609,23 @@ struct SweepTimer {
     std::vector<int> sweep_of;                   // sweep index of each launch
     std::vector<int> is_pull;                    // 1 = gather kernel, 0 = scatter kernel
     std::vector<double> bytes;                   // algorithmic bytes of a gather launch
-    hipEvent_t begin(hipStream_t s, int t, int pull, double b) {
-        if (!on) return nullptr;
+    // events for the next timed launch (taken by the launch itself)
+    KernelEvents next(int t, int pull, double b) {
+        if (!on) return KernelEvents();
         ev.emplace_back(new EventPair());
         sweep_of.push_back(t);
         is_pull.push_back(pull);
         bytes.push_back(b);
-        (void)hipEventRecord(ev.back()->a, s);
-        return ev.back()->b;
-    }
-    void end(hipEvent_t b, hipStream_t s) {
-        if (b) (void)hipEventRecord(b, s);
+        return KernelEvents{ev.back()->a, ev.back()->b};
     }
 };
+
+// partials of one solve: the synchronous sweep's 5 x kRedBlocks, or the ordered
+// sweep's 5 x kGroupBlocks per group plus kRedBlocks for the residual sum
+constexpr int kGroupBlocks = 256;
+constexpr int kMaxGroups = 15;
+constexpr size_t kPartDoubles = (size_t)5 * kGroupBlocks * kMaxGroups + kRedBlocks;
+static_assert(kPartDoubles >= (size_t)5 * kRedBlocks, "partials");
 
 template <typename T>
 pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
@@ -594,7 +650,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     size_t bytes = carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
                    carve_size<double>(nN) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
                    carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
-                   carve_size<double>(2) + carve_size<double>(5 * kRedBlocks);
+                   carve_size<double>(2) + carve_size<double>(kPartDoubles);
     Workspace ws;
     pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
     if (ps != PR_OK) return ps;
@@ -609,7 +665,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     Trace *tr = cv.take<Trace>(1);
     double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
     double *sumbad = cv.take<double>(2);
-    double *part = cv.take<double>(5 * kRedBlocks);
+    double *part = cv.take<double>(kPartDoubles);
 
     InitArgs a{};
     a.n = n;
@@ -639,9 +695,47 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     };
     const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
     const int check_mode = force == 0;
+    // ordered sweeps: global IFP2 (every vertex starts active), groups built at upload
+    const int ngr = (int)G.grp.size() - 1;
+    const bool ordered = ifp2 && ngr > 1 && ngr <= kMaxGroups && a.uniform && force == 0 &&
+                         !(o.flags & PR_JACOBI) && !G.grp_pull.empty() && G.prefer_ordered;
     int t = 0;
     bool stopped = false;
-    if (nN > 0) {
+    if (nN > 0 && ordered) {
+        int batch = l1 ? 8 : 16;
+        double bound_prev = -1.0;
+        int t_prev = 0;
+        const double sT = (double)sizeof(T);
+        double *part_s = part + (size_t)5 * kGroupBlocks * ngr;
+        while (t < max_sweeps) {
+            const int nb = std::min(batch, max_sweeps - t);
+            for (int k = 0; k < nb; ++k, ++t) {
+                size_t e = 0;
+                while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
+                unsigned long long sweep_edges = 0;
+                for (int q = 0; q < ngr; ++q) {
+                    HIPCHK(launch_reserve_range<T>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg, G.rp_nn, c, xi,
+                                                   kGroupBlocks, part + (size_t)5 * kGroupBlocks * q, s));
+                    const MPPlan &pl = G.grp_pull[e][q];
+                    sweep_edges += (unsigned long long)pl.edges();
+                    const KernelEvents ev =
+                        timer.next(t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT));
+                    HIPCHK(launch_pull<T, T>(t, ctl, pl, w, h, 0, s, TileSkip(), ev));
+                }
+                HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, kGroupBlocks, part, part_s, c, l1 ? 1 : 0, tol,
+                                           sweep_edges, s));
+            }
+            HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (ws.hctl->stop_after < t) {
+                stopped = true;
+                break;
+            }
+            batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, l1);
+            bound_prev = ws.hctl->last_bound;
+            t_prev = t;
+        }
+    } else if (nN > 0) {
         int batch = l1 ? 8 : 16;
         double bound_prev = -1.0;
         int t_prev = 0;
@@ -657,18 +751,20 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                 if (force != 2) {
                     // the scatter is timed when it is forced; in the automatic mode only the
                     // gather (the dense sweeps' kernel) carries events, to keep their overhead low
-                    hipEvent_t e = force == 1 ? timer.begin(s, t, 0, 0.0) : nullptr;
-                    HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, check_mode, s));
-                    if (!ifp2) HIPCHK(launch_push<T>(t, ctl, G.push_nd, w, h, check_mode, s));
-                    timer.end(e, s);
+                    const KernelEvents e = force == 1 ? timer.next(t, 0, 0.0) : KernelEvents();
+                    if (ifp2) {
+                        HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, check_mode, s, TileSkip(), e));
+                    } else {  // one interval over both scatter launches
+                        HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, check_mode, s, TileSkip(), {e.a, nullptr}));
+                        HIPCHK(launch_push<T>(t, ctl, G.push_nd, w, h, check_mode, s, TileSkip(), {nullptr, e.b}));
+                    }
                 }
                 if (force != 1) {
                     // every live in-edge: source id + gathered weight; every target row: offset + residual update
                     const double sT = (double)sizeof(T);
-                    hipEvent_t e = timer.begin(s, t, 1,
-                                               (double)pullp.edges() * (4.0 + sT) + (double)pullp.R * (4.0 + 2.0 * sT));
-                    HIPCHK(launch_pull<T, T>(t, ctl, pullp, w, h, check_mode, s));
-                    timer.end(e, s);
+                    const KernelEvents e =
+                        timer.next(t, 1, (double)pullp.edges() * (4.0 + sT) + (double)pullp.R * (4.0 + 2.0 * sT));
+                    HIPCHK(launch_pull<T, T>(t, ctl, pullp, w, h, check_mode, s, TileSkip(), e));
                 }
             }
             HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -733,6 +829,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                 bool pulled = (trc[ts] >> 63) != 0;
                 if ((int)pulled != timer.is_pull[i]) continue;
                 double sec = elapsed_s(timer.ev[i]->a, timer.ev[i]->b);
+                if (sec <= 0.0) continue;  // nothing was launched (empty plan)
                 if (pulled) {
                     z.pull_seconds += sec;
                     z.pull_launches += 1;
@@ -803,9 +900,8 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
         for (int k = 0; k < nb; ++k, ++t) {
             HIPCHK(launch_power_prescale<WT>(t, ctl, a, x, acc, y, G.deg, c, tol, part, s));
             if (t < max_it) {
-                hipEvent_t e = timer.begin(s, t, 1, 0.0);
-                HIPCHK(launch_pull<WT, double>(t, ctl, G.pull_all, y, acc, 0, s));
-                timer.end(e, s);
+                const KernelEvents e = timer.next(t, 1, 0.0);
+                HIPCHK(launch_pull<WT, double>(t, ctl, G.pull_all, y, acc, 0, s, TileSkip(), e));
             }
         }
         HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
@@ -1236,6 +1332,109 @@ pr_status solve_set_t(const pr_graph_set &S, const double *cg, const pr_opts &o,
     return all ? PR_OK : PR_ENOCONV;
 }
 
+// Rebuild every single-vector merge-path plan of the graph for tiles of kBlock * tile_k
+// items (the batched kernels keep their own plans).
+pr_status replan(Graph &G, int32_t tile_k, hipStream_t s) {
+    auto one = [&](MPPlan &p) -> hipError_t {
+        const int32_t ipb = kBlock * tile_k;
+        if (p.ipb == ipb) return hipSuccess;
+        const int32_t blocks = (int32_t)(((int64_t)p.items + ipb - 1) / ipb);
+        uint2 *np = nullptr;
+        hipError_t e = hipMalloc((void **)&np, sizeof(uint2) * ((size_t)std::max(blocks, 0) + 1));
+        if (e != hipSuccess) return e;
+        auto it = std::find(G.allocs.begin(), G.allocs.end(), (void *)p.plan);
+        if (it != G.allocs.end()) {
+            G.allocs.erase(it);
+            G.device_bytes -= (int64_t)sizeof(uint2) * ((int64_t)p.blocks + 1);
+        }
+        (void)hipFree(p.plan);
+        G.allocs.push_back((void *)np);
+        G.device_bytes += (int64_t)sizeof(uint2) * ((int64_t)blocks + 1);
+        p.plan = np;
+        p.ipb = ipb;
+        if (p.R == 0) {
+            p.blocks = 0;
+            return hipSuccess;
+        }
+        return launch_plan(p, s);
+    };
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(one(G.push_nn));
+    HIPCHK(one(G.push_nd));
+    HIPCHK(one(G.pull_all));
+    HIPCHK(one(G.pull_nn));
+    HIPCHK(one(G.pull_nd));
+    for (size_t e = 0; e < G.epochs.size(); ++e) {
+        if (e == 0) {  // epoch 0 aliases the full lists
+            G.epochs[0].pull_all = G.pull_all;
+            G.epochs[0].pull_nn = G.pull_nn;
+        } else {
+            HIPCHK(one(G.epochs[e].pull_all));
+            HIPCHK(one(G.epochs[e].pull_nn));
+        }
+    }
+    for (auto &v : G.grp_pull)
+        for (auto &p : v) HIPCHK(one(p));
+    HIPCHK(hipStreamSynchronize(s));
+    G.tile_k = tile_k;
+    return PR_OK;
+}
+
+template <typename T>
+pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
+                      pr_stats *st);
+
+pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *rep) {
+    const double t_start = (double)clock_now_ns() * 1e-9;
+    if (reps <= 0) reps = 2;
+    pr_tune_report r;
+    memset(&r, 0, sizeof(r));
+    double *out = nullptr;
+    HIPCHK(hipMalloc((void **)&out, sizeof(double) * (size_t)G.n));
+    struct Free {
+        double *p;
+        ~Free() { (void)hipFree(p); }
+    } fr{out};
+    pr_opts op = o;
+    op.flags = (o.flags & ~(PR_OUT_DEVICE | PR_PROFILE | PR_JACOBI)) | PR_OUT_DEVICE;
+    const bool can_order = G.grp.size() > 2 && !G.grp_pull.empty();
+    double best = INFINITY;
+    int best_i = 0;
+    for (int32_t shift = 2; shift <= 4; ++shift) {
+        pr_status ps = replan(G, 1 << shift, G.stream);
+        if (ps != PR_OK) return ps;
+        for (int ord = 0; ord <= (can_order ? 1 : 0); ++ord) {
+            G.prefer_ordered = ord == 1;
+            double ms = INFINITY;
+            int32_t sweeps = 0;
+            for (int32_t q = 0; q <= reps; ++q) {
+                pr_stats st;
+                ps = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, -1, op, out, &st)
+                                                : solve_ifp_t<double>(G, true, nullptr, -1, op, out, &st);
+                if (ps < 0) return ps;
+                if (q > 0) ms = std::min(ms, st.seconds_solve * 1e3);
+                sweeps = st.sweeps;
+            }
+            const int i = r.candidates++;
+            r.tile_shift[i] = shift;
+            r.ordered[i] = ord;
+            r.ms[i] = ms;
+            r.sweeps[i] = sweeps;
+            if (ms < best) {
+                best = ms;
+                best_i = i;
+            }
+        }
+    }
+    r.chosen = best_i;
+    pr_status ps = replan(G, 1 << r.tile_shift[best_i], G.stream);
+    if (ps != PR_OK) return ps;
+    G.prefer_ordered = r.ordered[best_i] == 1;
+    r.seconds = (double)clock_now_ns() * 1e-9 - t_start;
+    if (rep) *rep = r;
+    return PR_OK;
+}
+
 pr_status opts_or_default(const pr_opts *o, pr_opts *out) {
     if (o) *out = *o;
     else pr_opts_default(out);
@@ -1326,6 +1525,9 @@ pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out) {
     out->seconds_split = G.seconds_split;
     out->max_depth = G.max_depth;
     out->epochs = (int64_t)G.epochs.size();
+    out->groups = G.grp.size() > 1 ? (int64_t)G.grp.size() - 1 : 1;
+    out->tile_items = (int64_t)kBlock * G.tile_k;
+    out->ordered = G.grp.size() > 2 && !G.grp_pull.empty() && G.prefer_ordered ? 1 : 0;
     return PR_OK;
 }
 
@@ -1349,6 +1551,24 @@ static pr_status solve_common(const pr_graph *g, int method, const double *p, co
         const bool ifp2 = method == 2;
         return op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, ifp2, p, -1, op, pi, st)
                                           : solve_ifp_t<double>(G, ifp2, p, -1, op, pi, st);
+    } catch (const std::bad_alloc &) {
+        return fail(PR_ENOMEM, "host allocation");
+    }
+}
+
+pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_report *rep) {
+    g_err.clear();
+    if (!g) return fail(PR_EINVAL, "graph is NULL");
+    pr_opts op;
+    opts_or_default(o, &op);
+    pr_status ps = check_opts(op, false);
+    if (ps != PR_OK) return ps;
+    if (op.flags & (PR_FORCE_PUSH | PR_FORCE_PULL | PR_P_DEVICE))
+        return fail(PR_EINVAL, "tuning times the automatic schedule of global solves");
+    ps = enter(g);
+    if (ps != PR_OK) return ps;
+    try {
+        return tune_impl(g->g, op, reps, rep);
     } catch (const std::bad_alloc &) {
         return fail(PR_ENOMEM, "host allocation");
     }

@@ -109,6 +109,12 @@ struct TileSkip {
     const SetG *gs = nullptr;
 };
 
+// Optional timing of one sweep-kernel launch: the start / stop events are taken
+// by the launch itself (no separate event records around it).
+struct KernelEvents {
+    hipEvent_t a = nullptr, b = nullptr;
+};
+
 struct Trace {
     unsigned long long cnt[kMaxTrace];
     unsigned long long edges[kMaxTrace];
@@ -152,6 +158,12 @@ struct Graph {
     int32_t max_depth = -1;       // largest finite depth
     std::vector<Epoch> epochs;    // epochs[0] aliases the full in-edge lists
     int32_t tile_k = kMPK;        // merge-path items per thread of the sweep tiles
+    // ordered sweeps: non-dangling sources split into groups of equal N -> N out-edges
+    // (group g = [grp[g], grp[g + 1])), and per epoch the gather plan of each group's in-edges
+    std::vector<int32_t> grp;
+    bool prefer_ordered = true;                 // set by the autotuner
+    std::vector<std::vector<MPPlan>> grp_pull;  // [epoch][group]
+    std::vector<std::vector<int64_t>> grp_edges;
     int64_t device_bytes = 0;
     double seconds_upload = 0, seconds_split = 0;
     hipStream_t stream = nullptr;
@@ -196,10 +208,12 @@ hipError_t launch_depth_init(int32_t nN, const uint32_t *in_ptr, uint32_t *rem, 
 hipError_t launch_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *rp_nn, const int32_t *col_nn,
                              uint32_t *rem, int32_t *depth, int32_t round, int32_t *next, uint32_t *ncount,
                              hipStream_t s);
+// in-edges whose source has depth >= t0 and lies in [slo, shi)
 hipError_t launch_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                             int32_t t0, uint32_t *cnt, hipStream_t s);
+                             int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt, hipStream_t s);
 hipError_t launch_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                            int32_t t0, const uint32_t *out_ptr, int32_t *out_src, hipStream_t s);
+                            int32_t t0, int32_t slo, int32_t shi, const uint32_t *out_ptr, int32_t *out_src,
+                            hipStream_t s);
 
 // solve kernels
 struct InitArgs {
@@ -218,12 +232,22 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
                           const uint32_t *rp_nn, double c, double xi, int ifp2, int stop_l1, double tol,
                           unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
                           double *part, hipStream_t s);
+// ordered sweeps: reserve of the non-dangling range [lo, hi) into nbg workgroup
+// partials (5 * nbg doubles at part); after all groups, k_sum_h + k_decide_gs
+template <typename T>
+hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
+                                const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int nbg,
+                                double *part, hipStream_t s);
+template <typename T>
+hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, int nbg,
+                            const double *part, double *part_s, double c, int stop_l1, double tol,
+                            unsigned long long pull_edges, hipStream_t s);
 template <typename T>
 hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
-                       TileSkip skip = TileSkip());
+                       TileSkip skip = TileSkip(), KernelEvents ev = KernelEvents());
 template <typename WT, typename OT>
 hipError_t launch_pull(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
-                       hipStream_t s, TileSkip skip = TileSkip());
+                       hipStream_t s, TileSkip skip = TileSkip(), KernelEvents ev = KernelEvents());
 template <typename T>
 hipError_t launch_phase2_prep(const InitArgs &a, const T *h, const double *pibar, const int32_t *deg, double c,
                               int literal, double *w2, double *xD, hipStream_t s);

@@ -5,6 +5,8 @@
 // 64-wide waves: wave ballots for compaction and row splitting, LDS-staged
 // merge-path tiles for edge streaming, FP64 block reductions finished by the
 // last workgroup of a launch.
+#include <hip/hip_ext.h>
+
 #include "pr_device.h"
 
 #include <limits.h>
@@ -237,15 +239,17 @@ __global__ void k_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *r
 }
 
 // one wave per target row: number of in-edges whose source depth is >= t0
+// (also restricted to sources in [slo, shi): the in-lists of one source group)
 __global__ void k_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                             int32_t t0, uint32_t *cnt) {
+                             int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt) {
     const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
     const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
     for (int64_t r = wave; r < R; r += nwaves) {
         const uint32_t lo = in_ptr[r], hi = in_ptr[r + 1];
         uint32_t c = 0;
         for (uint32_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
-            bool live = e < hi && depth[in_src[e]] >= t0;
+            const int32_t u = e < hi ? in_src[e] : 0;
+            const bool live = e < hi && u >= slo && u < shi && depth[u] >= t0;
             c += (uint32_t)__popcll(__ballot(live));
         }
         if (lane_id() == 0) cnt[r] = c;
@@ -254,7 +258,7 @@ __global__ void k_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *i
 
 // one wave per target row: copy the live in-edges, order kept
 __global__ void k_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                            int32_t t0, const uint32_t *out_ptr, int32_t *out_src) {
+                            int32_t t0, int32_t slo, int32_t shi, const uint32_t *out_ptr, int32_t *out_src) {
     const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
     const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
     const unsigned long long lt = (1ull << lane_id()) - 1ull;
@@ -263,7 +267,7 @@ __global__ void k_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in
         uint32_t o = out_ptr[r];
         for (uint32_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
             const int32_t u = e < hi ? in_src[e] : 0;
-            const bool live = e < hi && depth[u] >= t0;
+            const bool live = e < hi && u >= slo && u < shi && depth[u] >= t0;
             const unsigned long long mk = __ballot(live);
             if (live) out_src[o + __popcll(mk & lt)] = u;
             o += (uint32_t)__popcll(mk);
@@ -313,13 +317,13 @@ __global__ void k_init_ifp(InitArgs a, T *h, double *pibar) {
 // sweep sends to non-dangling vertices, growth of the total mass, active
 // vertices and their valid edges.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32_t nN, T *h, T *w, double *pibar,
-                                                    const int32_t *deg, const uint32_t *rp_nn, double c, T xi,
-                                                    int ifp2, double *part) {
+__global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w,
+                                                    double *pibar, const int32_t *deg, const uint32_t *rp_nn,
+                                                    double c, T xi, int ifp2, double *part) {
     if (t > ctl->stop_after) return;
     double inact = 0.0, pred = 0.0, sxinc = 0.0;
     unsigned long long cnt = 0, edges = 0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock) {
+    for (int64_t i = lo + blockIdx.x * (int64_t)kBlock + threadIdx.x; i < hi; i += (int64_t)gridDim.x * kBlock) {
         T hv = h[i];
         if (hv > xi) {
             int32_t dg = deg[i];
@@ -351,6 +355,64 @@ __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32
         part[2 * nb + b] = sxinc;
         part[3 * nb + b] = dc;
         part[4 * nb + b] = de;
+    }
+}
+
+// Residual left on the non-dangling vertices after an ordered sweep (per
+// workgroup partials): S_N of the stop rule, summed directly because mass a
+// group pushes may already have been taken by a later group of the same sweep.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t nN, const T *h, double *part) {
+    if (t > ctl->stop_after) return;
+    double s = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock)
+        s += (double)h[i];
+    __shared__ double sd[kBlock / W];
+    s = block_sum(s, sd);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+// Management step of an ordered sweep (one workgroup), after all groups have
+// reserved and gathered: the growth of the total mass and the work from the
+// groups' reserve partials (ng groups of nbg workgroups, 5 sums each), S_N
+// from k_sum_h; stop when nothing was above the threshold or the certified
+// bound is met.
+__global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr, int ng, int nbg,
+                                                      const double *part, int nbs, const double *part_s, double c,
+                                                      int stop_l1, double tol, unsigned long long pull_edges) {
+    if (t > ctl->stop_after) return;
+    __shared__ double sd[kBlock / W];
+    double a_sx = 0.0, a_cd = 0.0, a_ed = 0.0;
+    for (int g = 0; g < ng; ++g) {
+        const double *pg = part + (size_t)g * 5 * nbg;
+        a_sx += reduce_partials(pg + 2 * nbg, nbg, sd);
+        a_cd += reduce_partials(pg + 3 * nbg, nbg, sd);
+        a_ed += reduce_partials(pg + 4 * nbg, nbg, sd);
+    }
+    const double sn = reduce_partials(part_s, nbs, sd);
+    if (threadIdx.x != 0) return;
+    const unsigned long long a_c = (unsigned long long)a_cd, a_e = (unsigned long long)a_ed;
+    const double k = 2.0 * c / (1.0 - c);
+    const double sx = ctl->sx + c * a_sx;
+    const double bound = k * sn / sx;
+    ctl->sx = sx;
+    ctl->last_bound = bound;
+    if (a_c == 0) {
+        ctl->stop_after = t - 1;  // nothing moved in this sweep
+    } else {
+        ctl->sweeps = t + 1;
+        ctl->tot_pushes += a_c;
+        ctl->tot_edges += a_e;
+        ctl->use_pull = 1;
+        ctl->pull_sweeps += 1;
+        ctl->tot_traversed += pull_edges;
+        if (stop_l1 && bound <= tol) ctl->stop_after = t;
+    }
+    if (t < kMaxTrace) {
+        tr->cnt[t] = a_c | (a_c ? (1ull << 63) : 0ull);
+        tr->edges[t] = a_e;
+        tr->sn[t] = sn;
+        tr->bound[t] = bound;
     }
 }
 
@@ -840,14 +902,16 @@ hipError_t launch_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *r
                ncount);
 }
 hipError_t launch_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                             int32_t t0, uint32_t *cnt, hipStream_t s) {
+                             int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt, hipStream_t s) {
     if (R == 0) return hipSuccess;
-    PRK_LAUNCH(k_live_count, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, cnt);
+    PRK_LAUNCH(k_live_count, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, slo, shi, cnt);
 }
 hipError_t launch_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                            int32_t t0, const uint32_t *out_ptr, int32_t *out_src, hipStream_t s) {
+                            int32_t t0, int32_t slo, int32_t shi, const uint32_t *out_ptr, int32_t *out_src,
+                            hipStream_t s) {
     if (R == 0) return hipSuccess;
-    PRK_LAUNCH(k_live_fill, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, out_ptr, out_src);
+    PRK_LAUNCH(k_live_fill, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, slo, shi, out_ptr,
+               out_src);
 }
 hipError_t launch_plan(MPPlan &p, hipStream_t s) {
     p.blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
@@ -865,51 +929,78 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
                           unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
                           double *part, hipStream_t s) {
     const int nb = grid_for(nN, 4, kRedBlocks);
-    hipLaunchKernelGGL(k_reserve<T>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, w, pibar, deg, rp_nn,
-                       c, (T)xi, ifp2, part);
+    hipLaunchKernelGGL(k_reserve<T>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, 0, nN, h, w, pibar, deg,
+                       rp_nn, c, (T)xi, ifp2, part);
     hipLaunchKernelGGL(k_decide_ifp, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, nb, (const double *)part, c, stop_l1,
                        tol, pull_edges_thr, force, pull_edges);
     return hipGetLastError();
 }
 
-template <typename T, int K>
-hipError_t launch_push_k(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
-                         TileSkip skip) {
-    static const int grid = resident_grid(k_push<T, K>);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_push<T, K>), dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl,
-                       check_mode, p.rp, p.R, p.idx, (const uint2 *)p.plan, p.items, p.blocks, w, h, skip);
+template <typename T>
+hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
+                                const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int nbg,
+                                double *part, hipStream_t s) {
+    hipLaunchKernelGGL(k_reserve<T>, dim3(nbg), dim3(kBlock), 0, s, t, (const Ctl *)ctl, lo, hi, h, w, pibar, deg,
+                       rp_nn, c, (T)xi, 1, part);
     return hipGetLastError();
 }
 
 template <typename T>
+hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, int nbg,
+                            const double *part, double *part_s, double c, int stop_l1, double tol,
+                            unsigned long long pull_edges, hipStream_t s) {
+    const int nbs = grid_for(nN, 8, kRedBlocks);
+    hipLaunchKernelGGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, part_s);
+    hipLaunchKernelGGL(k_decide_gs, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, ng, nbg, part, nbs,
+                       (const double *)part_s, c, stop_l1, tol, pull_edges);
+    return hipGetLastError();
+}
+
+// a launch that is timed takes its start / stop timestamps itself
+template <typename F, typename... Args>
+hipError_t launch_timed(F kern, int grid, hipStream_t s, KernelEvents ev, Args... args) {
+    if (ev.a || ev.b) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, ev.a, ev.b, 0, args...);
+    else hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, args...);
+    return hipGetLastError();
+}
+
+template <typename T, int K>
+hipError_t launch_push_k(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
+                         TileSkip skip, KernelEvents ev) {
+    auto kern = &k_push<T, K>;
+    static const int grid = resident_grid(kern);
+    return launch_timed(kern, std::min(p.blocks, grid), s, ev, t, ctl, check_mode, p.rp, p.R, p.idx,
+                        (const uint2 *)p.plan, p.items, p.blocks, w, h, skip);
+}
+
+template <typename T>
 hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
-                       TileSkip skip) {
+                       TileSkip skip, KernelEvents ev) {
     if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
     switch (p.ipb / kBlock) {
-        case 4: return launch_push_k<T, 4>(t, ctl, p, w, h, check_mode, s, skip);
-        case 16: return launch_push_k<T, 16>(t, ctl, p, w, h, check_mode, s, skip);
-        default: return launch_push_k<T, 8>(t, ctl, p, w, h, check_mode, s, skip);
+        case 4: return launch_push_k<T, 4>(t, ctl, p, w, h, check_mode, s, skip, ev);
+        case 16: return launch_push_k<T, 16>(t, ctl, p, w, h, check_mode, s, skip, ev);
+        default: return launch_push_k<T, 8>(t, ctl, p, w, h, check_mode, s, skip, ev);
     }
 }
 
 template <typename WT, typename OT, int K>
 hipError_t launch_pull_k(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
-                         hipStream_t s, TileSkip skip) {
+                         hipStream_t s, TileSkip skip, KernelEvents ev) {
     auto kern = &k_pull<WT, OT, K>;
     static const int grid = resident_grid(kern);
-    hipLaunchKernelGGL(kern, dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R,
-                       p.idx, (const uint2 *)p.plan, p.items, p.blocks, w, out, skip);
-    return hipGetLastError();
+    return launch_timed(kern, std::min(p.blocks, grid), s, ev, t, ctl, check_mode, p.rp, p.R, p.idx,
+                        (const uint2 *)p.plan, p.items, p.blocks, w, out, skip);
 }
 
 template <typename WT, typename OT>
 hipError_t launch_pull(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
-                       hipStream_t s, TileSkip skip) {
+                       hipStream_t s, TileSkip skip, KernelEvents ev) {
     if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
     switch (p.ipb / kBlock) {
-        case 4: return launch_pull_k<WT, OT, 4>(t, ctl, p, w, out, check_mode, s, skip);
-        case 16: return launch_pull_k<WT, OT, 16>(t, ctl, p, w, out, check_mode, s, skip);
-        default: return launch_pull_k<WT, OT, 8>(t, ctl, p, w, out, check_mode, s, skip);
+        case 4: return launch_pull_k<WT, OT, 4>(t, ctl, p, w, out, check_mode, s, skip, ev);
+        case 16: return launch_pull_k<WT, OT, 16>(t, ctl, p, w, out, check_mode, s, skip, ev);
+        default: return launch_pull_k<WT, OT, 8>(t, ctl, p, w, out, check_mode, s, skip, ev);
     }
 }
 
@@ -976,16 +1067,27 @@ template hipError_t launch_reserve<float>(int, Ctl *, Trace *, int32_t, float *,
 template hipError_t launch_reserve<double>(int, Ctl *, Trace *, int32_t, double *, double *, double *,
                                            const int32_t *, const uint32_t *, double, double, int, int, double,
                                            unsigned long long, int, unsigned long long, double *, hipStream_t);
+template hipError_t launch_reserve_range<float>(int, Ctl *, int32_t, int32_t, float *, float *, double *,
+                                                const int32_t *, const uint32_t *, double, double, int, double *,
+                                                hipStream_t);
+template hipError_t launch_reserve_range<double>(int, Ctl *, int32_t, int32_t, double *, double *, double *,
+                                                 const int32_t *, const uint32_t *, double, double, int, double *,
+                                                 hipStream_t);
+template hipError_t launch_decide_gs<float>(int, Ctl *, Trace *, int32_t, const float *, int, int, const double *,
+                                            double *, double, int, double, unsigned long long, hipStream_t);
+template hipError_t launch_decide_gs<double>(int, Ctl *, Trace *, int32_t, const double *, int, int,
+                                             const double *, double *, double, int, double, unsigned long long,
+                                             hipStream_t);
 template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t,
-                                       TileSkip);
+                                       TileSkip, KernelEvents);
 template hipError_t launch_push<double>(int, const Ctl *, const MPPlan &, const double *, double *, int,
-                                        hipStream_t, TileSkip);
+                                        hipStream_t, TileSkip, KernelEvents);
 template hipError_t launch_pull<float, float>(int, const Ctl *, const MPPlan &, const float *, float *, int,
-                                              hipStream_t, TileSkip);
+                                              hipStream_t, TileSkip, KernelEvents);
 template hipError_t launch_pull<double, double>(int, const Ctl *, const MPPlan &, const double *, double *, int,
-                                                hipStream_t, TileSkip);
+                                                hipStream_t, TileSkip, KernelEvents);
 template hipError_t launch_pull<float, double>(int, const Ctl *, const MPPlan &, const float *, double *, int,
-                                               hipStream_t, TileSkip);
+                                               hipStream_t, TileSkip, KernelEvents);
 template hipError_t launch_phase2_prep<float>(const InitArgs &, const float *, const double *, const int32_t *,
                                               double, int, double *, double *, hipStream_t);
 template hipError_t launch_phase2_prep<double>(const InitArgs &, const double *, const double *, const int32_t *,

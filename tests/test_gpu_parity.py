@@ -358,3 +358,72 @@ def test_equation_residual_and_bounds(pr):
     assert res <= 2 * st["l1_bound"]
     assert abs(pi.sum() - 1) < 1e-12
     assert np.all(pi >= (1 - C) / g.n * (1 - 1e-6))
+
+
+@pytest.mark.parametrize("groups", [1, 2, 4, 8, 15])
+def test_ordered_sweeps(pr, groups):
+    """Global IFP2 with ordered sweeps (the vertex groups take their residuals one after
+    another within a sweep) reaches the oracle's answer with the same certificate as
+    synchronous sweeps, and in no more sweeps."""
+    for g in (prgen.workload_rmat_small(seed=0), prgen.random_digraph(70001, 420000, seed=3, dangling_frac=0.15,
+                                                                        unref_frac=0.1),
+              prgen.workload_dag(n_layers=12, layer_size=3000, zmax=200, target_edges=300_000, back_frac=0.005,
+                                 seed=2)):
+        _say(f"ordered sweeps: groups {groups}, n {g.n}")
+        ref, _, _ = oracle.power(g, C, tol=1e-13)
+        dg = pr.upload(g.row_ptr, g.col, groups=groups)
+        pi, st = pr.ifp2(dg, c=C, xi=1e-13)
+        assert st["status"] == 0
+        assert l1(pi, ref) <= 1e-9
+        ok, swaps, eps = topk_agree(ref, pi, 1000)
+        assert ok
+        for residual, tol in (("fp32", 1e-6), ("fp64", 1e-10)):
+            po, so = pr.ifp2(dg, c=C, l1_tol=tol, residual=residual)
+            pj, sj = pr.ifp2(dg, c=C, l1_tol=tol, residual=residual, jacobi=True)
+            assert so["status"] == 0 and so["l1_bound"] <= tol and sj["l1_bound"] <= tol
+            assert l1(po, ref) <= tol and l1(pj, ref) <= tol
+            assert l1(po, pj) <= 2 * tol
+            assert abs(po.sum() - 1) < 1e-12
+            if groups == 1:
+                assert so["sweeps"] == sj["sweeps"]
+            else:
+                assert so["sweeps"] <= sj["sweeps"], (so["sweeps"], sj["sweeps"])
+        pl, sl = pr.ifp2(dg, c=C, xi=1e-13, literal=True)
+        assert l1(pl, ref) <= 1e-9 and sl["l1_bound"] >= l1(pl, ref)
+
+
+def test_autotune_keeps_results(pr):
+    """The autotuner times every tile size with synchronous and ordered sweeps, keeps the
+    fastest, and every solve afterwards still gives the oracle's answer."""
+    for g, groups in ((prgen.workload_rmat_small(seed=0), 0),
+                      (prgen.workload_dag(n_layers=12, layer_size=3000, zmax=200, target_edges=300_000,
+                                          back_frac=0.005, seed=2), 0),
+                      (prgen.random_digraph(20011, 150000, seed=2, dangling_frac=0.3), 1)):
+        ref, _, _ = oracle.power(g, C, tol=1e-13)
+        dg = pr.upload(g.row_ptr, g.col, groups=groups)
+        rep = pr.tune(dg, c=C, l1_tol=1e-6, residual="fp32", reps=1)
+        _say(f"tune n={g.n}: {rep}")
+        cands = rep["candidates"]
+        assert len(cands) == (3 if groups == 1 else 6)
+        assert sorted({x["tile_shift"] for x in cands}) == [2, 3, 4]
+        assert rep["chosen"]["ms"] == min(x["ms"] for x in cands)
+        info = dg.info()
+        assert info["tile_items"] == 256 << rep["chosen"]["tile_shift"]
+        assert info["ordered"] == int(rep["chosen"]["ordered"])
+        for method in ("ifp1", "ifp2"):
+            for mode in (None, "push", "pull"):
+                pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
+                assert l1(pi, ref) <= 1e-9, (method, mode)
+        pi, st = pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32")
+        assert st["l1_bound"] <= 1e-6 and l1(pi, ref) <= 1e-6
+        pw, _ = pr.power(dg, c=C, l1_tol=1e-11)
+        assert l1(pw, ref) <= 1e-9
+        srcs = [0, g.n // 2, g.n - 1]
+        out, sts = pr.ppr(dg, srcs, c=C, xi=1e-13)
+        for r, s in enumerate(srcs):
+            p = np.zeros(g.n)
+            p[s] = 1.0
+            assert l1(out[r], oracle.power(g, C, p, tol=1e-13)[0]) <= 1e-9
+    o = pr._opts(C, 1e-12, 1e-6, "fp32", 0, None, False, "push", False)
+    assert pr.lib().pr_graph_tune(dg.handle, o, 1, None) == pr.PR_EINVAL
+    assert "automatic" in pr.lib().pr_last_error().decode()

@@ -72,7 +72,7 @@ def test_set_matches_oracle_and_alone(pr, residual, tol, mode):
         ref = _oracle(g, c, (i, c))
         assert l1(x, ref) <= tol, (i, g.n, c, l1(x, ref))
         dg = pr.upload(g.row_ptr, g.col)
-        alone, sa = pr.ifp2(dg, c=c, l1_tol=tol, residual=residual, mode=mode)
+        alone, sa = pr.ifp2(dg, c=c, l1_tol=tol, residual=residual, mode=mode, jacobi=True)
         assert l1(x, alone) <= 2 * tol, (i, l1(x, alone))
         # same Jacobi trajectory per graph: only the rounding order differs
         assert abs(st["sweeps"] - sa["sweeps"]) <= 1, (i, st["sweeps"], sa["sweeps"])
@@ -124,7 +124,7 @@ def test_set_xi_rule_and_device_output(pr):
     got = gs.split(out.cpu().numpy())
     for g, x, st in zip(graphs, got, sts):
         dg = pr.upload(g.row_ptr, g.col)
-        alone, sa = pr.ifp2(dg, c=0.85, xi=1e-11, residual="fp64")
+        alone, sa = pr.ifp2(dg, c=0.85, xi=1e-11, residual="fp64", jacobi=True)
         assert l1(x, alone) <= 1e-12
         assert abs(st["sweeps"] - sa["sweeps"]) <= 1
 
