@@ -89,6 +89,7 @@ def main():
     ap.add_argument("--ppr", type=int, default=16,
                     help="single-source PPR queries timed one at a time and batched (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="skip the per-graph schedule autotuner")
+    ap.add_argument("--no-warm", action="store_true", help="skip the dynamic-graph warm-start leg")
     ap.add_argument("--set-count", type=int, default=256,
                     help="batched solves: independent graphs solved as one set (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -216,6 +217,8 @@ def main():
     }
     if args.ppr > 0:
         res["ppr"] = run_ppr(pr, dg, g, c, args)
+    if not args.no_warm:
+        res["warm_start"] = run_warm(pr, prgen, dg, g, c, args)
     if args.set_count > 0:
         res["batched_graphs"] = run_set(pr, prgen, args)
     if args.serve_seconds > 0:
@@ -257,6 +260,53 @@ def run_ppr(pr, dg, g, c, args):
             "speedup": t_single / t_batch, "batch_width": 16,
             "mean_sweeps_single": float(np.mean([s["sweeps"] for s in single])),
             "mean_sweeps_batched": float(np.mean([s["sweeps"] for s in batched]))}
+
+
+def run_warm(pr, prgen, dg, g, c, args):
+    """Dynamic graph: after a solve, the out-edge lists of a random 0.1 % of the
+    non-dangling vertices are replaced (random targets, the same number of edges); the
+    state is carried to the new graph (pr_state_update over the changed sources) and
+    IFP2 resumes from it, against a cold solve of the changed graph; FP32 residuals,
+    certified L1 <= tol."""
+    import numpy as np
+    import torch
+    rng = np.random.default_rng(17)
+    deg = np.diff(g.row_ptr)
+    nz = np.flatnonzero(deg > 0)
+    changed = np.sort(rng.choice(nz, max(1, len(nz) // 1000), replace=False)).astype(np.int32)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    keep = ~np.isin(src, changed)
+    new_dst = rng.integers(0, g.n, int(deg[changed].sum()))
+    new_src = np.repeat(changed.astype(np.int64), deg[changed])
+    g2 = prgen.from_edges(g.n, np.concatenate([src[keep], new_src]), np.concatenate([g.col[keep], new_dst]))
+    d2 = pr.upload(g2.row_ptr, g2.col)
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    st = pr.State(g.n)
+    pr.ifp2_warm(dg, st, c=c, l1_tol=args.tol, residual="fp32", out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st.update(dg, d2, changed)
+    t_upd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    _, sw = pr.ifp2_warm(d2, st, c=c, l1_tol=args.tol, residual="fp32", out=out)
+    torch.cuda.synchronize()
+    t_warm = time.perf_counter() - t0
+    pr.ifp2(d2, c=c, l1_tol=args.tol, residual="fp32", out=out, jacobi=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, sc = pr.ifp2(d2, c=c, l1_tol=args.tol, residual="fp32", out=out, jacobi=True)
+    torch.cuda.synchronize()
+    t_cold = time.perf_counter() - t0
+    res = {"changed_sources": int(len(changed)), "changed_edges": int(deg[changed].sum()),
+           "update_ms": t_upd * 1e3, "warm_ms": t_warm * 1e3, "cold_ms": t_cold * 1e3,
+           "warm_sweeps": sw["sweeps"], "cold_sweeps": sc["sweeps"],
+           "warm_edges_processed": sw["edges_processed"], "cold_edges_processed": sc["edges_processed"],
+           "warm_l1_bound": sw["l1_bound"], "cold_l1_bound": sc["l1_bound"],
+           "speedup_incl_update": t_cold / (t_warm + t_upd)}
+    log(f"[bench] warm start: {res}")
+    st.free()
+    d2.free()
+    return res
 
 
 def run_set(pr, prgen, args):

@@ -32,7 +32,8 @@ EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_inf
             "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len",
             "pr_server_opts_default", "pr_server_create", "pr_server_add_graph", "pr_server_submit",
             "pr_server_wait", "pr_server_get_stats", "pr_server_destroy",
-            "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2", "pr_graph_tune"]
+            "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2", "pr_graph_tune",
+            "pr_state_create", "pr_state_free", "pr_state_read", "pr_solve_ifp2_warm", "pr_state_update"]
 
 
 class PRError(RuntimeError):
@@ -139,6 +140,16 @@ def lib():
     L.pr_probe_scatter.restype = ctypes.c_int
     L.pr_probe_gather_out_len.argtypes = [i64]
     L.pr_probe_gather_out_len.restype = i64
+    L.pr_state_create.argtypes = [i64, vp, ctypes.POINTER(vp)]
+    L.pr_state_create.restype = ctypes.c_int
+    L.pr_state_free.argtypes = [vp]
+    L.pr_state_free.restype = ctypes.c_int
+    L.pr_state_read.argtypes = [vp, vp, vp]
+    L.pr_state_read.restype = ctypes.c_int
+    L.pr_solve_ifp2_warm.argtypes = [vp, ctypes.POINTER(Opts), vp, dp, ctypes.POINTER(Stats)]
+    L.pr_solve_ifp2_warm.restype = ctypes.c_int
+    L.pr_state_update.argtypes = [vp, vp, vp, vp, i32]
+    L.pr_state_update.restype = ctypes.c_int
     L.pr_graph_tune.argtypes = [vp, ctypes.POINTER(Opts), i32, ctypes.POINTER(TuneReport)]
     L.pr_graph_tune.restype = ctypes.c_int
     L.pr_set_upload.argtypes = [i32, vp, vp, vp, u32, ctypes.POINTER(vp)]
@@ -268,6 +279,75 @@ def tune(g: Graph, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", reps=2) -> di
     cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "ms": r.ms[i], "sweeps": r.sweeps[i]}
              for i in range(k)]
     return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds}
+
+
+class State:
+    """Reserve and residual of a forward-push solve, carried across graph changes
+    (include/pr_warm.h).  p: host personalisation (None: uniform), used for the cold start."""
+
+    def __init__(self, n: int, p=None):
+        self.n = int(n)
+        pk = None if p is None else np.ascontiguousarray(p, dtype=np.float64)
+        if pk is not None and pk.shape != (self.n,):
+            raise ValueError("p must have n entries")
+        h = ctypes.c_void_p()
+        st = lib().pr_state_create(self.n, pk.ctypes.data if pk is not None else None, ctypes.byref(h))
+        if st != PR_OK:
+            raise _err(st)
+        self._h = h.value
+
+    @property
+    def handle(self):
+        if self._h is None:
+            raise ValueError("state was freed")
+        return self._h
+
+    def read(self):
+        pb, h = np.empty(self.n), np.empty(self.n)
+        st = lib().pr_state_read(self.handle, pb.ctypes.data, h.ctypes.data)
+        if st != PR_OK:
+            raise _err(st)
+        return pb, h
+
+    def update(self, g_old: Graph, g_new: Graph, changed=None):
+        """h += c (P_new - P_old) pibar over the changed sources (all when None)."""
+        ch = None if changed is None else np.ascontiguousarray(changed, dtype=np.int32)
+        st = lib().pr_state_update(self.handle, g_old.handle, g_new.handle,
+                                   ch.ctypes.data if ch is not None and ch.size else None,
+                                   0 if ch is None else int(ch.size))
+        if st != PR_OK:
+            raise _err(st)
+
+    def free(self):
+        if self._h is not None:
+            lib().pr_state_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def ifp2_warm(g: Graph, state: State, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
+              stream=None, mode=None, profile=False):
+    """IFP2 resumed from `state` (and leaving its end state there)."""
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, profile)
+    if out is None:
+        out = np.empty(g.n, dtype=np.float64)
+    out_keep, out_ptr, out_dev = _ptr_any(out, np.float64, "float64")
+    if (out_keep.numel() if _is_torch(out_keep) else out_keep.shape[0]) != g.n:
+        raise ValueError("out must have n entries")
+    if not _is_torch(out) and out_keep is not out:
+        raise ValueError("out must be a contiguous float64 numpy array")
+    if out_dev:
+        o.flags |= PR_OUT_DEVICE
+    st = Stats()
+    status = lib().pr_solve_ifp2_warm(g.handle, ctypes.byref(o), state.handle, out_ptr, ctypes.byref(st))
+    if status < 0:
+        raise _err(status)
+    return out, dict(st.as_dict(), status=status)
 
 
 class GraphSet:

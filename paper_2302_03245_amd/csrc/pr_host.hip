@@ -16,6 +16,7 @@
 
 #include "../../include/pr.h"
 #include "../../include/pr_set.h"
+#include "../../include/pr_warm.h"
 #include "pr_internal.h"
 
 using namespace prk;
@@ -627,9 +628,15 @@ constexpr int kMaxGroups = 15;
 constexpr size_t kPartDoubles = (size_t)5 * kGroupBlocks * kMaxGroups + kRedBlocks;
 static_assert(kPartDoubles >= (size_t)5 * kRedBlocks, "partials");
 
+// state of a warm start (device, original ids): read at the start, written at the end
+struct WarmArgs {
+    double *pibar;
+    double *h;
+};
+
 template <typename T>
 pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
-                      pr_stats *st) {
+                      pr_stats *st, const WarmArgs *warm = nullptr) {
     hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
     const int64_t n = G.n;
     const int32_t nN = G.nN, nD = G.nD;
@@ -650,7 +657,8 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     size_t bytes = carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
                    carve_size<double>(nN) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
                    carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
-                   carve_size<double>(2) + carve_size<double>(kPartDoubles);
+                   carve_size<double>(2) + carve_size<double>(kPartDoubles) +
+                   (warm ? 2 * carve_size<double>(nN) + 3 * carve_size<double>(nD) : 0);
     Workspace ws;
     pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
     if (ps != PR_OK) return ps;
@@ -666,6 +674,12 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
     double *sumbad = cv.take<double>(2);
     double *part = cv.take<double>(kPartDoubles);
+    // warm start: reserve at the start, mass taken this solve pushed to dangling vertices
+    double *pibar0 = warm ? cv.take<double>(nN) : nullptr;
+    double *w3 = warm ? cv.take<double>(nN) : nullptr;
+    double *xD0 = warm ? cv.take<double>(nD) : nullptr;
+    double *hD0 = warm ? cv.take<double>(nD) : nullptr;
+    double *hDn = warm ? cv.take<double>(nD) : nullptr;
 
     InitArgs a{};
     a.n = n;
@@ -685,7 +699,10 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     hc.stop_after = INT_MAX;
     hc.sx = (double)n;
     HIPCHK(hipMemcpyAsync(ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
-    HIPCHK(launch_init_ifp<T>(a, h, pibar, s));
+    if (warm)
+        HIPCHK(launch_warm_import<T>(ctl, n, nN, G.perm, warm->pibar, warm->h, h, pibar, pibar0, xD0, hD0, part, s));
+    else
+        HIPCHK(launch_init_ifp<T>(a, h, pibar, s));
 
     // the gather of sweep t uses the in-edge lists of the last epoch starting at or before t
     auto pull_plan = [&](int t) -> const MPPlan & {
@@ -698,7 +715,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     // ordered sweeps: global IFP2 (every vertex starts active), groups built at upload
     const int ngr = (int)G.grp.size() - 1;
     const bool ordered = ifp2 && ngr > 1 && ngr <= kMaxGroups && a.uniform && force == 0 &&
-                         !(o.flags & PR_JACOBI) && !G.grp_pull.empty() && G.prefer_ordered;
+                         !(o.flags & PR_JACOBI) && !G.grp_pull.empty() && G.prefer_ordered && !warm;
     int t = 0;
     bool stopped = false;
     if (nN > 0 && ordered) {
@@ -780,12 +797,17 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     } else {
         stopped = true;
     }
-    if (ifp2 && nD > 0) {
+    if (ifp2 && nD > 0 && warm) {
+        HIPCHK(launch_warm_phase2_prep<T>(nN, nD, h, pibar, pibar0, G.deg, c, xD0, hD0, w2, w3, xD, hDn, s));
+        HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
+        HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w3, hDn, 0, s));
+    } else if (ifp2 && nD > 0) {
         HIPCHK(launch_phase2_prep<T>(a, h, pibar, G.deg, c, literal ? 1 : 0, w2, xD, s));
         HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
     }
     double *dst = out_dev ? pi : outbuf;
     HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, dst, part, s));
+    if (warm) HIPCHK(launch_warm_export<T>(n, nN, G.perm, h, pibar, hDn, warm->pibar, warm->h, s));
     HIPCHK(hipEventRecord(ev_solve.b, s));
     HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
@@ -802,6 +824,13 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         z.residual_l1 = r.fin_sum > 0 ? r.fin_sn / r.fin_sum : 0.0;
         const double k = literal ? 2.0 / (1.0 - c) : 2.0 * c / (1.0 - c);
         z.l1_bound = r.fin_sum > 0 ? k * r.fin_sn / r.fin_sum : 0.0;
+        if (warm) {
+            // signed residuals: unnormalised error E <= c / (1 - c) sum|h_N|, the exact mass is at
+            // least fin_sum - E, and normalising costs (1 + sum|x| / sum x) E / (that mass)
+            const double E = c / (1.0 - c) * r.fin_sn;
+            const double den = r.fin_sum - E;
+            z.l1_bound = den > 0 ? (1.0 + r.fin_abs / r.fin_sum) * E / den : INFINITY;
+        }
         z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
         z.seconds_preprocess = ifp2 ? G.seconds_split : 0.0;
         if (timer.on) {
@@ -1380,10 +1409,6 @@ pr_status replan(Graph &G, int32_t tile_k, hipStream_t s) {
     return PR_OK;
 }
 
-template <typename T>
-pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
-                      pr_stats *st);
-
 pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *rep) {
     const double t_start = (double)clock_now_ns() * 1e-9;
     if (reps <= 0) reps = 2;
@@ -1448,6 +1473,17 @@ pr_status enter(const pr_graph *g) {
 }
 
 }  // namespace
+
+struct pr_state {
+    int64_t n = 0;
+    double c = 0.0;  // fixed by the first solve
+    int device = 0;
+    double *pibar = nullptr, *h = nullptr;  // device, original ids
+    ~pr_state() {
+        if (pibar) (void)hipFree(pibar);
+        if (h) (void)hipFree(h);
+    }
+};
 
 namespace prk {
 pr_status set_error(pr_status st, const std::string &msg) { return fail(st, msg); }
@@ -1554,6 +1590,104 @@ static pr_status solve_common(const pr_graph *g, int method, const double *p, co
     } catch (const std::bad_alloc &) {
         return fail(PR_ENOMEM, "host allocation");
     }
+}
+
+pr_status pr_state_create(int64_t n, const double *p, pr_state **out) {
+    g_err.clear();
+    if (!out) return fail(PR_EINVAL, "out is NULL");
+    if (n < 1 || n >= ((int64_t)1 << 31)) return fail(PR_EINVAL, "n must be in [1, 2^31)");
+    std::vector<double> h((size_t)n, 1.0);
+    if (p) {
+        double sum = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            if (!(p[i] >= 0.0) || !std::isfinite(p[i])) return fail(PR_EINVAL, "p has a negative or non-finite entry");
+            sum += p[i];
+        }
+        if (!(sum > 0.0)) return fail(PR_EINVAL, "p must have a positive sum");
+        for (int64_t i = 0; i < n; ++i) h[(size_t)i] = (double)n * p[i] / sum;
+    }
+    std::unique_ptr<pr_state> S(new (std::nothrow) pr_state());
+    if (!S) return fail(PR_ENOMEM, "host allocation");
+    S->n = n;
+    HIPCHK(hipGetDevice(&S->device));
+    HIPCHK(hipMalloc((void **)&S->pibar, sizeof(double) * (size_t)n));
+    HIPCHK(hipMalloc((void **)&S->h, sizeof(double) * (size_t)n));
+    HIPCHK(hipMemset(S->pibar, 0, sizeof(double) * (size_t)n));
+    HIPCHK(hipMemcpy(S->h, h.data(), sizeof(double) * (size_t)n, hipMemcpyHostToDevice));
+    *out = S.release();
+    return PR_OK;
+}
+
+pr_status pr_state_free(pr_state *s) {
+    g_err.clear();
+    if (!s) return PR_OK;
+    (void)hipSetDevice(s->device);
+    delete s;
+    return PR_OK;
+}
+
+pr_status pr_state_read(const pr_state *s, double *pibar, double *h) {
+    g_err.clear();
+    if (!s) return fail(PR_EINVAL, "state is NULL");
+    HIPCHK(hipSetDevice(s->device));
+    if (pibar) HIPCHK(hipMemcpy(pibar, s->pibar, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost));
+    if (h) HIPCHK(hipMemcpy(h, s->h, sizeof(double) * (size_t)s->n, hipMemcpyDeviceToHost));
+    return PR_OK;
+}
+
+pr_status pr_solve_ifp2_warm(const pr_graph *g, const pr_opts *o, pr_state *s, double *pi, pr_stats *st) {
+    g_err.clear();
+    if (!g) return fail(PR_EINVAL, "graph is NULL");
+    if (!s) return fail(PR_EINVAL, "state is NULL");
+    if (!pi) return fail(PR_EINVAL, "pi is NULL");
+    pr_opts op;
+    opts_or_default(o, &op);
+    pr_status ps = check_opts(op, false);
+    if (ps != PR_OK) return ps;
+    if (op.flags & (PR_IFP2_LITERAL | PR_P_DEVICE)) return fail(PR_EINVAL, "option flag not supported for warm solves");
+    if (g->g.n != s->n) return fail(PR_EINVAL, "graph and state differ in n");
+    if (s->c != 0.0 && s->c != op.c) return fail(PR_EINVAL, "c differs from the state's damping factor");
+    ps = enter(g);
+    if (ps != PR_OK) return ps;
+    try {
+        WarmArgs wa{s->pibar, s->h};
+        ps = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(g->g, true, nullptr, -1, op, pi, st, &wa)
+                                        : solve_ifp_t<double>(g->g, true, nullptr, -1, op, pi, st, &wa);
+        if (ps >= 0) s->c = op.c;
+        return ps;
+    } catch (const std::bad_alloc &) {
+        return fail(PR_ENOMEM, "host allocation");
+    }
+}
+
+pr_status pr_state_update(pr_state *s, const pr_graph *g_old, const pr_graph *g_new, const int32_t *changed,
+                          int32_t k) {
+    g_err.clear();
+    if (!s || !g_old || !g_new) return fail(PR_EINVAL, "NULL argument");
+    if (s->c == 0.0) return fail(PR_EINVAL, "the state has not been solved yet (no damping factor)");
+    if (g_old->g.n != s->n || g_new->g.n != s->n) return fail(PR_EINVAL, "graphs and state differ in n");
+    if (changed && k < 0) return fail(PR_EINVAL, "k < 0");
+    if (changed)
+        for (int32_t q = 0; q < k; ++q)
+            if (changed[q] < 0 || changed[q] >= s->n) return fail(PR_EINVAL, "changed source out of [0, n)");
+    HIPCHK(hipSetDevice(s->device));
+    hipStream_t st = g_new->g.stream;
+    int32_t *d_src = nullptr;
+    if (changed && k > 0) {
+        HIPCHK(hipMalloc((void **)&d_src, sizeof(int32_t) * (size_t)k));
+        HIPCHK(hipMemcpyAsync(d_src, changed, sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice, st));
+    }
+    struct Free {
+        int32_t *p;
+        ~Free() {
+            if (p) (void)hipFree(p);
+        }
+    } fr{d_src};
+    // both graphs' streams may still hold work that reads them
+    HIPCHK(hipStreamSynchronize(g_old->g.stream));
+    HIPCHK(launch_state_update(d_src, changed ? (int64_t)k : s->n, g_old->g, g_new->g, s->c, s->pibar, s->h, st));
+    HIPCHK(hipStreamSynchronize(st));
+    return PR_OK;
 }
 
 pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_report *rep) {

@@ -45,7 +45,8 @@ struct alignas(128) Ctl {
     int32_t pull_sweeps;
     uint32_t bdone;       // last-block counters
     uint32_t fdone;
-    uint32_t pad0[2];
+    int32_t signed_res;   // residuals may be negative (a warm start): the bound uses the signed form
+    uint32_t pad0;
     double acc[4];        // per-sweep FP64 accumulators
     unsigned long long acc_cnt, acc_edges;
     double sx;            // running total mass sum(pibar + h) (+ untouched dangling mass for IFP2)
@@ -56,7 +57,8 @@ struct alignas(128) Ctl {
     double pw_diff;       // ||x_t - x_{t-1}||_1 of the last iterate
     // finalisation
     double fin_sum, fin_sn;
-    double pad1[4];
+    double fin_abs;       // sum |x| (equals fin_sum unless residuals went negative)
+    double pad1[3];
 };
 
 // Control block of a batch of B <= kMaxBatch vectors (see Ctl).
@@ -281,6 +283,22 @@ template <typename T>
 hipError_t launch_set_final(int64_t n, int32_t nN, SetG *gs, const int32_t *offN, const int32_t *offD, int32_t k,
                             const int32_t *perm, const T *h, const double *pibar, const double *xD, double *out,
                             hipStream_t s);
+
+// warm start (pr_warm.hip): state arrays in original ids
+template <typename T>
+hipError_t launch_warm_import(Ctl *ctl, int64_t n, int32_t nN, const int32_t *perm, const double *st_pibar,
+                              const double *st_h, T *h, double *pibar, double *pibar0, double *xD0, double *hD0,
+                              double *part, hipStream_t s);
+template <typename T>
+hipError_t launch_warm_phase2_prep(int32_t nN, int32_t nD, const T *h, const double *pibar, const double *pibar0,
+                                   const int32_t *deg, double c, const double *xD0, const double *hD0, double *w2,
+                                   double *w3, double *xD, double *hDn, hipStream_t s);
+template <typename T>
+hipError_t launch_warm_export(int64_t n, int32_t nN, const int32_t *perm, const T *h, const double *pibar,
+                              const double *hDn, double *st_pibar, double *st_h, hipStream_t s);
+struct Graph;
+hipError_t launch_state_update(const int32_t *src, int64_t count, const Graph &g_old, const Graph &g_new, double c,
+                               const double *st_pibar, double *st_h, hipStream_t s);
 
 // batched IFP2 (pr_batch.hip)
 template <typename T, int B>

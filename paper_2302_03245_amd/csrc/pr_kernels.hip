@@ -325,7 +325,8 @@ __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32
     unsigned long long cnt = 0, edges = 0;
     for (int64_t i = lo + blockIdx.x * (int64_t)kBlock + threadIdx.x; i < hi; i += (int64_t)gridDim.x * kBlock) {
         T hv = h[i];
-        if (hv > xi) {
+        // |h_i| > xi: residuals are non-negative except after a warm start
+        if (hv > xi || hv < -xi) {
             int32_t dg = deg[i];
             uint32_t dnn = rp_nn[i + 1] - rp_nn[i];
             double v = (double)hv;
@@ -333,13 +334,13 @@ __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32
             h[i] = (T)0;
             w[i] = (T)(c * v / (double)dg);
             double fN = (double)dnn / (double)dg;
-            pred += v * fN;
+            pred += fabs(v) * fN;
             sxinc += ifp2 ? v * fN : v;
             cnt += 1;
             edges += ifp2 ? dnn : (uint32_t)dg;
         } else {
             w[i] = (T)0;
-            inact += (double)hv;
+            inact += fabs((double)hv);
         }
     }
     __shared__ double sd[kBlock / W];
@@ -358,6 +359,18 @@ __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32
     }
 }
 
+// Certified L1 bound on the normalised result from the residual sum sn (of |h| over
+// the non-dangling vertices) and the total mass sx, k = 2c / (1 - c).  Non-negative
+// residuals: the exact unnormalised vector is at least the estimate, so k sn / sx.
+// Signed residuals (warm start): the estimate may exceed it, and its mass is only
+// known within E = (k / 2) sn, so k sn / (sx - E) (the final figure of the solve also
+// carries the estimate's negative part).
+__device__ __forceinline__ double l1_bound_of(double k, double sn, double sx, int signed_res) {
+    if (!signed_res) return k * sn / sx;
+    const double den = sx - 0.5 * k * sn;
+    return den > 0.0 ? k * sn / den : INFINITY;
+}
+
 // Residual left on the non-dangling vertices after an ordered sweep (per
 // workgroup partials): S_N of the stop rule, summed directly because mass a
 // group pushes may already have been taken by a later group of the same sweep.
@@ -366,7 +379,7 @@ __global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t
     if (t > ctl->stop_after) return;
     double s = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock)
-        s += (double)h[i];
+        s += fabs((double)h[i]);
     __shared__ double sd[kBlock / W];
     s = block_sum(s, sd);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -394,7 +407,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr
     const unsigned long long a_c = (unsigned long long)a_cd, a_e = (unsigned long long)a_ed;
     const double k = 2.0 * c / (1.0 - c);
     const double sx = ctl->sx + c * a_sx;
-    const double bound = k * sn / sx;
+    const double bound = l1_bound_of(k, sn, sx, ctl->signed_res);
     ctl->sx = sx;
     ctl->last_bound = bound;
     if (a_c == 0) {
@@ -436,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
     if (a_c == 0) {
         // nothing above the threshold: the state is unchanged, stop before this sweep's scatter
         ctl->stop_after = t - 1;
-        ctl->last_bound = k * a_in / ctl->sx;
+        ctl->last_bound = l1_bound_of(k, a_in, ctl->sx, ctl->signed_res);
         if (t < kMaxTrace) {
             tr->cnt[t] = 0;
             tr->edges[t] = 0;
@@ -447,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
     }
     const double sn = a_in + c * a_pr;
     const double sx = ctl->sx + c * a_sx;
-    const double bound = k * sn / sx;
+    const double bound = l1_bound_of(k, sn, sx, ctl->signed_res);
     ctl->sx = sx;
     ctl->sweeps = t + 1;
     ctl->tot_pushes += a_c;
@@ -692,28 +705,34 @@ __device__ __forceinline__ double x_ifp(const InitArgs &a, const T *h, const dou
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_final_sum(InitArgs a, const T *h, const double *pibar,
                                                       const double *xD, int ifp2, int literal, double *part) {
-    double s = 0.0, sn = 0.0;
+    double s = 0.0, sn = 0.0, sa = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
-        s += x_ifp(a, h, pibar, xD, ifp2, literal, i);
-        if (i < a.nN) sn += (double)h[i];
+        const double x = x_ifp(a, h, pibar, xD, ifp2, literal, i);
+        s += x;
+        sa += fabs(x);
+        if (i < a.nN) sn += fabs((double)h[i]);
     }
     __shared__ double sd[kBlock / W];
     s = block_sum(s, sd);
     sn = block_sum(sn, sd);
+    sa = block_sum(sa, sd);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = s;
         part[gridDim.x + blockIdx.x] = sn;
+        part[2 * gridDim.x + blockIdx.x] = sa;
     }
 }
 
-// fin_sum = part[0..nb), fin_sn = part[nb..2nb)
+// fin_sum = part[0..nb), fin_sn = part[nb..2nb), fin_abs = part[2nb..3nb)
 __global__ __launch_bounds__(kBlock) void k_final_decide(Ctl *ctl, int nb, const double *part) {
     __shared__ double sd[kBlock / W];
     const double s = reduce_partials(part, nb, sd);
     const double sn = reduce_partials(part + nb, nb, sd);
+    const double sa = reduce_partials(part + 2 * nb, nb, sd);
     if (threadIdx.x == 0) {
         ctl->fin_sum = s;
         ctl->fin_sn = sn;
+        ctl->fin_abs = sa;
     }
 }
 
@@ -801,6 +820,7 @@ __global__ __launch_bounds__(kBlock) void k_final_x_sum(int64_t n, const double 
     if (threadIdx.x == 0) {
         part[blockIdx.x] = s;
         part[gridDim.x + blockIdx.x] = 0.0;
+        part[2 * gridDim.x + blockIdx.x] = s;  // the iterates are non-negative
     }
 }
 

@@ -15,7 +15,7 @@ pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libpr.so not bu
 
 def _declared():
     names = set()
-    for h in ("pr.h", "pr_probe.h", "pr_serve.h", "pr_set.h"):
+    for h in ("pr.h", "pr_probe.h", "pr_serve.h", "pr_set.h", "pr_warm.h"):
         txt = open(os.path.join(ROOT, "include", h)).read()
         txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
         for m in re.finditer(r"^\s*[A-Za-z_][\w \*]*?\b(pr_\w+)\s*\(", txt, flags=re.M):
@@ -27,7 +27,7 @@ def test_every_declared_symbol_is_exported():
     import paper_2302_03245_amd as pr
 
     names = _declared()
-    assert len(names) >= 26
+    assert len(names) >= 31
     lib = ctypes.CDLL(LIB)
     for name in names:
         assert hasattr(lib, name), name
@@ -93,6 +93,26 @@ def test_set_upload_rejects_invalid_host_input(graphs, flags, msg):
     assert h.value is None
     st = L.pr_set_upload(0, ns.ctypes.data, rp_ptrs, col_ptrs, 0, ctypes.byref(h))
     assert st == pr.PR_EINVAL and "k must be" in L.pr_last_error().decode()
+
+
+def test_state_rejects_invalid_host_input():
+    import paper_2302_03245_amd as pr
+
+    L = pr.lib()
+    h = ctypes.c_void_p()
+    assert L.pr_state_create(0, None, ctypes.byref(h)) == pr.PR_EINVAL
+    assert "n must be" in L.pr_last_error().decode()
+    p = np.array([1.0, -1.0, 2.0])
+    assert L.pr_state_create(3, p.ctypes.data, ctypes.byref(h)) == pr.PR_EINVAL
+    assert "negative" in L.pr_last_error().decode()
+    p = np.zeros(3)
+    assert L.pr_state_create(3, p.ctypes.data, ctypes.byref(h)) == pr.PR_EINVAL
+    assert "positive sum" in L.pr_last_error().decode()
+    assert h.value is None
+    out = np.zeros(3)
+    assert L.pr_solve_ifp2_warm(None, None, None, out.ctypes.data, None) == pr.PR_EINVAL
+    assert L.pr_state_update(None, None, None, None, 0) == pr.PR_EINVAL
+    assert L.pr_state_free(None) == pr.PR_OK
 
 
 def test_set_solve_rejects_null_set():
