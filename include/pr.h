@@ -62,7 +62,9 @@ typedef enum {
 #define PR_TILE_SHIFT(s) (((uint32_t)(s) & 0x7u) << 8)
 #define PR_TILE_MASK 0x700u
 /* ordered sweeps of global IFP2 solves: the non-dangling vertices are split into k
-   groups of equal out-edge counts (k in 1..15; 1 = no ordered sweeps; 0 selects 4) */
+   groups of equal out-edge counts (k in 1..15; 1 = no ordered sweeps; 0 selects 4 when
+   at least 2^24 edges join non-dangling vertices, else 1: on smaller graphs the extra
+   launches of an ordered sweep cost more than the sweeps it saves) */
 #define PR_GROUPS(k) (((uint32_t)(k) & 0xFu) << 12)
 #define PR_GROUPS_MASK 0xF000u
 

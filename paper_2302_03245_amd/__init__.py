@@ -249,7 +249,8 @@ def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0, groups: int 
     """Copy a CSR graph (host numpy or device torch tensors) to the device.
 
     `tile_shift` s in {2, 3, 4} sets 256 << s rows + edges per sweep tile (0: default);
-    `groups` k in 1..15 sets the vertex groups of ordered sweeps (0: default 4, 1: none)."""
+    `groups` k in 1..15 sets the vertex groups of ordered sweeps (0: 4 on graphs with at least
+    2^24 edges between non-dangling vertices, else none; 1: none)."""
     rp_keep, rp_ptr, rp_dev = _ptr_any(row_ptr, np.int64, "int64")
     col_keep, col_ptr, col_dev = _ptr_any(col, np.int32, "int32")
     if rp_dev != col_dev:

@@ -417,7 +417,8 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
 
     // Ordered sweeps (not for graph sets): source groups of equal N -> N out-edges in
     // the degree order, and for every epoch the in-lists of the N targets split by group.
-    const int32_t ngroups_req = (flags & PR_GROUPS_MASK) ? (int32_t)((flags & PR_GROUPS_MASK) >> 12) : 4;
+    const int32_t ngroups_req = (flags & PR_GROUPS_MASK) ? (int32_t)((flags & PR_GROUPS_MASK) >> 12)
+                                                         : (G.mNN >= ((int64_t)1 << 24) ? 4 : 1);
     if (!seg_of && G.nN > 0 && G.mNN > 0 && ngroups_req > 1) {
         std::vector<uint32_t> h_rpnn((size_t)G.nN + 1);
         HIPCHK(hipMemcpyAsync(h_rpnn.data(), G.rp_nn, sizeof(uint32_t) * ((size_t)G.nN + 1), hipMemcpyDeviceToHost,
