@@ -67,6 +67,9 @@ typedef enum {
    launches of an ordered sweep cost more than the sweeps it saves) */
 #define PR_GROUPS(k) (((uint32_t)(k) & 0xFu) << 12)
 #define PR_GROUPS_MASK 0xF000u
+/* keep every in-edge list in fill order instead of sorting it by source (sorted lists
+   make gathers touch fewer cache lines and their rounding order deterministic) */
+#define PR_UNSORTED_IN 0x10000u
 
 /* pr_opts.flags */
 #define PR_P_DEVICE 0x1u     /* p is a device pointer (double[n]) */

@@ -245,7 +245,7 @@ class Graph:
             pass
 
 
-def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0, groups: int = 0) -> Graph:
+def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0, groups: int = 0, sort_in: bool = True) -> Graph:
     """Copy a CSR graph (host numpy or device torch tensors) to the device.
 
     `tile_shift` s in {2, 3, 4} sets 256 << s rows + edges per sweep tile (0: default);
@@ -258,7 +258,7 @@ def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0, groups: int 
     n = (rp_keep.shape[0] if not _is_torch(rp_keep) else rp_keep.numel()) - 1
     m = col_keep.shape[0] if not _is_torch(col_keep) else col_keep.numel()
     flags = (PR_INPUT_DEVICE if rp_dev else 0) | (PR_DEDUPE if dedupe else 0) | ((tile_shift & 7) << 8) | \
-        ((groups & 15) << 12)
+        ((groups & 15) << 12) | (0 if sort_in else 0x10000)
     h = ctypes.c_void_p()
     st = lib().pr_graph_upload(int(n), int(m), rp_ptr, col_ptr if m else None, flags, ctypes.byref(h))
     if st != PR_OK:

@@ -144,7 +144,7 @@ int32_t degree_order(int64_t n, const int64_t *rp, const int32_t *seg_of, std::v
 pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
                       const int32_t *seg_of, pr_graph **out) {
     if (!out) return fail(PR_EINVAL, "out is NULL");
-    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE | PR_TILE_MASK | PR_GROUPS_MASK))
+    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE | PR_TILE_MASK | PR_GROUPS_MASK | PR_UNSORTED_IN))
         return fail(PR_EINVAL, "unknown upload flag");
     const uint32_t tile_shift = (flags & PR_TILE_MASK) >> 8;
     if (tile_shift != 0 && (tile_shift < 2 || tile_shift > 4)) return fail(PR_EINVAL, "tile shift must be 2, 3 or 4");
@@ -306,6 +306,7 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
     HIPCHK(hipMemcpyAsync(d_cursor, G.in_ptr, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_fill_csc(G.rp_nn, G.col_nn, G.nN, d_cursor, G.in_src, s));
     HIPCHK(launch_fill_csc(G.rp_nd, G.col_nd, G.nN, d_cursor, G.in_src, s));
+    if (!(flags & PR_UNSORTED_IN)) HIPCHK(sort_in_lists(n, m, G.in_ptr, G.in_src, s));
     unsigned long long *d_zero;
     HIPCHK(tmp.alloc(&d_zero, 1));
     HIPCHK(hipMemsetAsync(d_zero, 0, sizeof(unsigned long long), s));

@@ -210,6 +210,8 @@ hipError_t launch_depth_init(int32_t nN, const uint32_t *in_ptr, uint32_t *rem, 
 hipError_t launch_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *rp_nn, const int32_t *col_nn,
                              uint32_t *rem, int32_t *depth, int32_t round, int32_t *next, uint32_t *ncount,
                              hipStream_t s);
+// every in-edge list sorted by source id (pr_sort.hip); synchronises the stream
+hipError_t sort_in_lists(int64_t n, int64_t m, const uint32_t *in_ptr, int32_t *in_src, hipStream_t s);
 // in-edges whose source has depth >= t0 and lies in [slo, shi)
 hipError_t launch_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
                              int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt, hipStream_t s);
