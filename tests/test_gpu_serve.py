@@ -25,13 +25,15 @@ def pr():
     return pr
 
 
-@pytest.mark.parametrize("residual,tol,slots,batch_min", [("fp32", 1e-6, 16, 1), ("fp64", 1e-9, 8, 1),
-                                                          ("fp32", 1e-6, 16, 2), ("fp64", 1e-9, 16, 3)])
-def test_mix_equals_alone(pr, residual, tol, slots, batch_min):
+@pytest.mark.parametrize("residual,tol,slots,batch_min,groups", [("fp32", 1e-6, 16, 1, 0), ("fp64", 1e-9, 8, 1, 0),
+                                                                 ("fp32", 1e-6, 16, 2, 0), ("fp64", 1e-9, 16, 3, 0),
+                                                                 ("fp32", 1e-6, 16, 1, 4), ("fp64", 1e-9, 8, 2, 4)])
+def test_mix_equals_alone(pr, residual, tol, slots, batch_min, groups):
     import torch
     graphs = [prgen.workload_rmat_small(seed=0), prgen.random_digraph(20011, 150000, seed=3, dangling_frac=0.2,
                                                                       unref_frac=0.1)]
-    dgs = [pr.upload(g.row_ptr, g.col) for g in graphs]
+    # groups: vertex groups for ordered sweeps (batched rounds turn ordered once they gather)
+    dgs = [pr.upload(g.row_ptr, g.col, groups=groups) for g in graphs]
     srv = pr.Server(c=C, l1_tol=tol, residual=residual, slots=slots, sweeps_per_round=3, batch_min=batch_min)
     gids = [srv.add_graph(d) for d in dgs]
     rng = np.random.default_rng(5)
