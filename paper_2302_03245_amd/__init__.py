@@ -527,13 +527,13 @@ def last_trace() -> dict:
 
 
 def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, stream=None,
-        mode=None, out=None):
+        mode=None, out=None, jacobi=False):
     """Single-source PPR for each source (IFP2, sources batched sixteen at a time);
     returns (float64[k, n], list of stats dicts).  `out` may be a (k, n) float64 numpy
     array or torch CUDA tensor."""
     src = np.ascontiguousarray(sources, dtype=np.int32)
     k = int(src.shape[0])
-    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, False)
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, False, jacobi=jacobi)
     if out is None:
         out = np.empty((k, g.n), dtype=np.float64)
     out_keep, out_ptr, out_dev = _ptr_any(out, np.float64, "float64")

@@ -714,47 +714,16 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     };
     const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
     const int check_mode = force == 0;
-    // ordered sweeps: global IFP2 (every vertex starts active), groups built at upload
+    // ordered sweeps (groups built at upload): from the start for global IFP2, where every
+    // vertex starts active; otherwise from the first batch after a sweep that gathered
     const int ngr = (int)G.grp.size() - 1;
-    const bool ordered = ifp2 && ngr > 1 && ngr <= kMaxGroups && a.uniform && force == 0 &&
-                         !(o.flags & PR_JACOBI) && !G.grp_pull.empty() && G.prefer_ordered && !warm;
+    const bool ordered_ok = ifp2 && ngr > 1 && ngr <= kMaxGroups && force == 0 && !(o.flags & PR_JACOBI) &&
+                            !G.grp_pull.empty() && G.prefer_ordered;
+    bool ordered = ordered_ok && a.uniform && !warm;
+    const double sT = (double)sizeof(T);
     int t = 0;
     bool stopped = false;
-    if (nN > 0 && ordered) {
-        int batch = l1 ? 8 : 16;
-        double bound_prev = -1.0;
-        int t_prev = 0;
-        const double sT = (double)sizeof(T);
-        double *part_s = part + (size_t)5 * kGroupBlocks * ngr;
-        while (t < max_sweeps) {
-            const int nb = std::min(batch, max_sweeps - t);
-            for (int k = 0; k < nb; ++k, ++t) {
-                size_t e = 0;
-                while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
-                unsigned long long sweep_edges = 0;
-                for (int q = 0; q < ngr; ++q) {
-                    HIPCHK(launch_reserve_range<T>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg, G.rp_nn, c, xi,
-                                                   kGroupBlocks, part + (size_t)5 * kGroupBlocks * q, s));
-                    const MPPlan &pl = G.grp_pull[e][q];
-                    sweep_edges += (unsigned long long)pl.edges();
-                    const KernelEvents ev =
-                        timer.next(t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT));
-                    HIPCHK(launch_pull<T, T>(t, ctl, pl, w, h, 0, s, TileSkip(), ev));
-                }
-                HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, kGroupBlocks, part, part_s, c, l1 ? 1 : 0, tol,
-                                           sweep_edges, s));
-            }
-            HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-            HIPCHK(hipStreamSynchronize(s));
-            if (ws.hctl->stop_after < t) {
-                stopped = true;
-                break;
-            }
-            batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, l1);
-            bound_prev = ws.hctl->last_bound;
-            t_prev = t;
-        }
-    } else if (nN > 0) {
+    if (nN > 0) {
         int batch = l1 ? 8 : 16;
         double bound_prev = -1.0;
         int t_prev = 0;
@@ -765,6 +734,24 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                 // a gather reads every live in-edge; scatter when the active edges are fewer than half of them
                 const unsigned long long pull_edges = (unsigned long long)pullp.edges();
                 const unsigned long long pull_thr = (unsigned long long)(0.5 * (double)pull_edges) + 1;
+                if (ordered) {
+                    size_t e = 0;
+                    while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
+                    unsigned long long sweep_edges = 0;
+                    for (int q = 0; q < ngr; ++q) {
+                        HIPCHK(launch_reserve_range<T>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg, G.rp_nn, c,
+                                                       xi, kGroupBlocks, part + (size_t)5 * kGroupBlocks * q, s));
+                        const MPPlan &pl = G.grp_pull[e][q];
+                        sweep_edges += (unsigned long long)pl.edges();
+                        const KernelEvents ev =
+                            timer.next(t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT));
+                        HIPCHK(launch_pull<T, T>(t, ctl, pl, w, h, 0, s, TileSkip(), ev));
+                    }
+                    HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, kGroupBlocks, part,
+                                               part + (size_t)5 * kGroupBlocks * ngr, c, l1 ? 1 : 0, tol, pull_thr,
+                                               sweep_edges, s));
+                    continue;
+                }
                 HIPCHK(launch_reserve<T>(t, ctl, tr, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, l1 ? 1 : 0,
                                          tol, pull_thr, force, pull_edges, part, s));
                 if (force != 2) {
@@ -780,7 +767,6 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                 }
                 if (force != 1) {
                     // every live in-edge: source id + gathered weight; every target row: offset + residual update
-                    const double sT = (double)sizeof(T);
                     const KernelEvents e =
                         timer.next(t, 1, (double)pullp.edges() * (4.0 + sT) + (double)pullp.R * (4.0 + 2.0 * sT));
                     HIPCHK(launch_pull<T, T>(t, ctl, pullp, w, h, check_mode, s, TileSkip(), e));
@@ -792,6 +778,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                 stopped = true;
                 break;
             }
+            ordered = ordered_ok && ws.hctl->use_pull;  // dense frontier: ordered sweeps from here
             batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, l1);
             bound_prev = ws.hctl->last_bound;
             t_prev = t;

@@ -245,7 +245,7 @@ hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T
 template <typename T>
 hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, int nbg,
                             const double *part, double *part_s, double c, int stop_l1, double tol,
-                            unsigned long long pull_edges, hipStream_t s);
+                            unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s);
 template <typename T>
 hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
                        TileSkip skip = TileSkip(), KernelEvents ev = KernelEvents());

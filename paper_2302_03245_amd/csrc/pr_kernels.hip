@@ -392,7 +392,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t
 // bound is met.
 __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr, int ng, int nbg,
                                                       const double *part, int nbs, const double *part_s, double c,
-                                                      int stop_l1, double tol, unsigned long long pull_edges) {
+                                                      int stop_l1, double tol, unsigned long long pull_thr,
+                                                      unsigned long long pull_edges) {
     if (t > ctl->stop_after) return;
     __shared__ double sd[kBlock / W];
     double a_sx = 0.0, a_cd = 0.0, a_ed = 0.0;
@@ -416,7 +417,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr
         ctl->sweeps = t + 1;
         ctl->tot_pushes += a_c;
         ctl->tot_edges += a_e;
-        ctl->use_pull = 1;
+        ctl->use_pull = a_e >= pull_thr ? 1 : 0;  // would a synchronous sweep gather (is the frontier dense)
         ctl->pull_sweeps += 1;
         ctl->tot_traversed += pull_edges;
         if (stop_l1 && bound <= tol) ctl->stop_after = t;
@@ -968,11 +969,11 @@ hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T
 template <typename T>
 hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, int nbg,
                             const double *part, double *part_s, double c, int stop_l1, double tol,
-                            unsigned long long pull_edges, hipStream_t s) {
+                            unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s) {
     const int nbs = grid_for(nN, 8, kRedBlocks);
     hipLaunchKernelGGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, part_s);
     hipLaunchKernelGGL(k_decide_gs, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, ng, nbg, part, nbs,
-                       (const double *)part_s, c, stop_l1, tol, pull_edges);
+                       (const double *)part_s, c, stop_l1, tol, pull_thr, pull_edges);
     return hipGetLastError();
 }
 
@@ -1094,10 +1095,11 @@ template hipError_t launch_reserve_range<double>(int, Ctl *, int32_t, int32_t, d
                                                  const int32_t *, const uint32_t *, double, double, int, double *,
                                                  hipStream_t);
 template hipError_t launch_decide_gs<float>(int, Ctl *, Trace *, int32_t, const float *, int, int, const double *,
-                                            double *, double, int, double, unsigned long long, hipStream_t);
+                                            double *, double, int, double, unsigned long long, unsigned long long,
+                                            hipStream_t);
 template hipError_t launch_decide_gs<double>(int, Ctl *, Trace *, int32_t, const double *, int, int,
                                              const double *, double *, double, int, double, unsigned long long,
-                                             hipStream_t);
+                                             unsigned long long, hipStream_t);
 template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t,
                                        TileSkip, KernelEvents);
 template hipError_t launch_push<double>(int, const Ctl *, const MPPlan &, const double *, double *, int,

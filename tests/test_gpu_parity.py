@@ -427,3 +427,28 @@ def test_autotune_keeps_results(pr):
     o = pr._opts(C, 1e-12, 1e-6, "fp32", 0, None, False, "push", False)
     assert pr.lib().pr_graph_tune(dg.handle, o, 1, None) == pr.PR_EINVAL
     assert "automatic" in pr.lib().pr_last_error().decode()
+
+
+def test_ordered_sweeps_after_a_sparse_start(pr):
+    """Single-source PPR and personalised p on a graph with vertex groups: the solve starts
+    with synchronous sweeps and turns to ordered sweeps once a sweep gathers; the result
+    matches the oracle and takes no more sweeps than synchronous sweeps alone."""
+    g = prgen.random_digraph(70001, 420000, seed=3, dangling_frac=0.15, unref_frac=0.1)
+    dg = pr.upload(g.row_ptr, g.col, groups=4)
+    deg = np.diff(g.row_ptr)
+    for s in np.flatnonzero(deg > 0)[[0, 500, 20000]]:
+        p = np.zeros(g.n)
+        p[s] = 1.0
+        ref = oracle.power(g, C, p, tol=1e-13)[0]
+        out, st = pr.ppr(dg, [int(s)], c=C, xi=1e-13)
+        outj, stj = pr.ppr(dg, [int(s)], c=C, xi=1e-13, jacobi=True)
+        assert l1(out[0], ref) <= 1e-9 and l1(outj[0], ref) <= 1e-9
+        assert st[0]["sweeps"] <= stj[0]["sweeps"] + 1, (st[0]["sweeps"], stj[0]["sweeps"])
+        o32, s32 = pr.ppr(dg, [int(s)], c=C, l1_tol=1e-6, residual="fp32")
+        assert s32[0]["l1_bound"] <= 1e-6 and l1(o32[0], ref) <= 1e-6
+    p = prgen.random_p(g.n, seed=4, zero_frac=0.3)
+    ref = oracle.power(g, C, p, tol=1e-13)[0]
+    pi, st = pr.ifp2(dg, p=p, c=C, l1_tol=1e-10)
+    pj, sj = pr.ifp2(dg, p=p, c=C, l1_tol=1e-10, jacobi=True)
+    assert st["l1_bound"] <= 1e-10 and l1(pi, ref) <= 1e-10 and l1(pj, ref) <= 1e-10
+    assert st["sweeps"] < sj["sweeps"], (st["sweeps"], sj["sweeps"])

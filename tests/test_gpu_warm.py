@@ -77,11 +77,12 @@ def test_cold_state_identity_and_result(pr):
     assert s["sweeps"] == sj["sweeps"] and l1(pi, pj) <= 1e-12
 
 
-@pytest.mark.parametrize("changed_all", [False, True])
-def test_update_then_warm_solve(pr, changed_all):
+@pytest.mark.parametrize("changed_all,groups", [(False, 0), (True, 0), (False, 4)])
+def test_update_then_warm_solve(pr, changed_all, groups):
+    """groups = 4: the resumed solve turns to ordered sweeps once a sweep gathers."""
     g1 = prgen.random_digraph(5000, 40000, seed=22, dangling_frac=0.2, unref_frac=0.1)
     g2, changed = _perturb(g1, 0.02, seed=5)
-    d1, d2 = pr.upload(g1.row_ptr, g1.col), pr.upload(g2.row_ptr, g2.col)
+    d1, d2 = pr.upload(g1.row_ptr, g1.col, groups=groups), pr.upload(g2.row_ptr, g2.col, groups=groups)
     st = pr.State(g1.n)
     pr.ifp2_warm(d1, st, c=C, xi=1e-13)
     st.update(d1, d2, None if changed_all else changed)
