@@ -90,6 +90,7 @@ def main():
                     help="single-source PPR queries timed one at a time and batched (0 = skip)")
     ap.add_argument("--no-tune", action="store_true", help="skip the per-graph schedule autotuner")
     ap.add_argument("--no-warm", action="store_true", help="skip the dynamic-graph warm-start leg")
+    ap.add_argument("--no-peel", action="store_true", help="skip the weak-dangling peeling leg")
     ap.add_argument("--set-count", type=int, default=256,
                     help="batched solves: independent graphs solved as one set (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -215,6 +216,8 @@ def main():
                      "groups": info["groups"]},
         "depth_epochs": info["epochs"], "max_depth": info["max_depth"],
     }
+    if not args.no_peel and args.mode is None:
+        res["peeled"] = run_peel(pr, g, c, args, t_ifp2, last)
     if args.ppr > 0:
         res["ppr"] = run_ppr(pr, dg, g, c, args)
     if not args.no_warm:
@@ -229,6 +232,37 @@ def main():
         log("[bench] CPU baseline (serial oracle IFP2)")
         res["cpu_baseline"] = cpu_baseline(g, c, args.tol)
     print(json.dumps(res), flush=True)
+
+
+def run_peel(pr, g, c, args, t_plain, st_plain):
+    """IFP2 on the same graph uploaded with its weakly dangling vertices peeled (PR_PEEL:
+    phase 1 sweeps the core only, phase 2 gathers the peeled levels from the highest
+    down); same options, tuning and step count as the main IFP2 line."""
+    import torch
+    t0 = time.perf_counter()
+    dp = pr.upload(g.row_ptr, g.col, tile_shift=args.tile_shift, peel=True)
+    t_up = time.perf_counter() - t0
+    if not args.no_tune and args.tile_shift == 0:
+        pr.tune(dp, c=c, l1_tol=args.tol, residual="fp32", reps=2)
+    info = dp.info()
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        pr.ifp2(dp, c=c, l1_tol=args.tol, residual="fp32", out=out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = [pr.ifp2(dp, c=c, l1_tol=args.tol, residual="fp32", out=out)[1] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    assert all(s["status"] == 0 and s["l1_bound"] <= args.tol for s in sts)
+    st = sts[-1]
+    res = {"ms": t * 1e3, "gteps": g.m / t / 1e9, "speedup_vs_unpeeled": t_plain / t,
+           "n_peeled": info["n_peeled"], "levels": info["peel_levels"],
+           "edges_processed": st["edges_processed"], "edges_processed_unpeeled": st_plain["edges_processed"],
+           "sweeps": st["sweeps"], "l1_bound": st["l1_bound"], "upload_s": t_up,
+           "ordered_sweeps": bool(info["ordered"]), "tile_items": info["tile_items"]}
+    log(f"[bench] peeled: {res}")
+    dp.free()
+    return res
 
 
 def run_ppr(pr, dg, g, c, args):

@@ -70,6 +70,19 @@ typedef enum {
 /* keep every in-edge list in fill order instead of sorting it by source (sorted lists
    make gathers touch fewer cache lines and their rounding order deterministic) */
 #define PR_UNSORTED_IN 0x10000u
+/* weak-dangling peeling for IFP2 (section 2: deleting the dangling vertices leaves new
+   dangling vertices, the weakly dangling ones; repeated, this ranks vertices in levels).
+   Level 1: every out-edge leads to a dangling vertex; level L: every out-edge leads to a
+   vertex of a level below L (up to PR_PEEL_MAX_LEVELS; a vertex that reaches a cycle, a
+   self-loop included, never peels).  Peeled vertices leave IFP2's phase 1 like dangling vertices:
+   the sweeps run over the remaining core, with the edges into peeled vertices
+   invalidated, and phase 2 gathers the levels from the highest down, each from the
+   finished values of its in-neighbours, then the dangling vertices.  The certified bound
+   is unchanged (c / (1-c) of the core's residual bounds the unnormalised error).  Such a
+   graph serves pr_solve_ifp2, pr_ppr (sources solved one at a time) and pr_graph_tune;
+   IFP1, the power method, warm starts and the server reject it. */
+#define PR_PEEL 0x20000u
+#define PR_PEEL_MAX_LEVELS 64
 
 /* pr_opts.flags */
 #define PR_P_DEVICE 0x1u     /* p is a device pointer (double[n]) */
@@ -116,7 +129,8 @@ typedef struct {
 typedef struct {
     int64_t n, m;
     int64_t n_dangling;     /* out-degree 0 */
-    int64_t m_dangling;     /* edges whose target is dangling (invalidated by IFP2) */
+    int64_t m_dangling;     /* edges whose target is dangling, or peeled (PR_PEEL): invalidated
+                               in IFP2's phase 1 and gathered once in its phase 2 */
     int64_t n_unreferenced; /* in-degree 0 */
     int64_t device_bytes;   /* device memory held by the graph */
     double seconds_upload;  /* whole upload: copies, classification, relabelling, plans */
@@ -128,6 +142,8 @@ typedef struct {
     int64_t groups;         /* vertex groups of ordered sweeps (1: none) */
     int64_t tile_items;     /* rows + edges per sweep tile (256 << tile shift) */
     int64_t ordered;        /* 1 if global IFP2 solves use ordered sweeps */
+    int64_t n_peeled;       /* weakly dangling vertices taken out of the sweeps (PR_PEEL; else 0) */
+    int64_t peel_levels;    /* their levels (0 without PR_PEEL) */
 } pr_graph_info_t;
 
 /*
@@ -143,7 +159,8 @@ void pr_opts_default(pr_opts *o);
  *   m        number of edges, 0 <= m < 2^31
  *   row_ptr  int64[n+1], row_ptr[0] == 0, non-decreasing, row_ptr[n] == m
  *   col      int32[m], every entry in [0, n)   (may be NULL when m == 0)
- *   flags    PR_INPUT_DEVICE: row_ptr / col are device pointers; PR_DEDUPE
+ *   flags    PR_INPUT_DEVICE: row_ptr / col are device pointers; PR_DEDUPE; PR_TILE_SHIFT;
+ *            PR_GROUPS; PR_UNSORTED_IN; PR_PEEL
  *   out      receives the handle
  * The inputs are copied; the caller keeps ownership of them.  The handle is
  * owned by the library until pr_graph_free.  Errors: PR_EINVAL for any
@@ -201,7 +218,8 @@ pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_rep
  *   st   optional statistics
  * One GPU sweep processes every vertex above the threshold once (a
  * synchronous version of one scan of all calculation threads, section 3.3.1).
- * Errors: PR_EINVAL (bad graph handle, options, p), PR_ENOMEM, PR_EDEVICE;
+ * Errors: PR_EINVAL (bad graph handle, options, p, a graph uploaded with PR_PEEL
+ * for IFP1), PR_ENOMEM, PR_EDEVICE;
  * PR_ENOCONV when max_sweeps ends the iteration.
  */
 pr_status pr_solve_ifp1(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st);
@@ -228,7 +246,7 @@ pr_status pr_solve_ifp2(const pr_graph *g, const double *p, const pr_opts *o, do
  * Power method on P'' = c P' + (1-c) p e^T (Eq. 1), the baseline the paper
  * compares against (section 4.3): x <- c P x + (c d^T x + (1-c) e^T x) p from
  * x = p until c / (1-c) * ||x' - x||_1 <= l1_tol; xi and stop are ignored.
- * Arguments and errors as pr_solve_ifp1; l1_tol must be > 0.
+ * Arguments and errors as pr_solve_ifp1 (PR_PEEL graphs rejected); l1_tol must be > 0.
  */
 pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st);
 
@@ -238,7 +256,8 @@ pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, d
  * for each of the k sources.  Up to 16 sources share one batched solve: their
  * residual vectors are interleaved so that every gathered in-edge serves all of
  * them, and each keeps its own stop decision (same result as one call per
- * source, within the tolerances).  With PR_OUT_DEVICE, pi is a device pointer.
+ * source, within the tolerances).  On a graph uploaded with PR_PEEL every
+ * source is solved alone.  With PR_OUT_DEVICE, pi is a device pointer.
  *   sources  int32[k] host array, each in [0, n); k >= 1
  *   pi       double[k * n], row r is the PPR vector of sources[r]
  *   st       optional, k entries

@@ -61,7 +61,8 @@ pr_status pr_server_create(const pr_server_opts *o, pr_server **out);
 /*
  * Register an uploaded graph; its engine starts immediately.  The graph stays
  * owned by the caller and must outlive the server.  PR_ENOMEM if the engine's
- * workspace does not fit in the remaining budget.
+ * workspace does not fit in the remaining budget; PR_EINVAL for a graph uploaded
+ * with PR_PEEL.
  */
 pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id);
 

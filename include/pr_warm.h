@@ -41,7 +41,7 @@ pr_status pr_state_free(pr_state *s);
  * reserve and residual in it.  g must have the state's n; the first solve fixes
  * the damping factor o->c of the state, later solves and updates must use the
  * same one.  Options as pr_solve_ifp2 except p (taken from the state) and
- * PR_IFP2_LITERAL (rejected).  The stop rule and pi / st as pr_solve_ifp2; the
+ * PR_IFP2_LITERAL (rejected); graphs uploaded with PR_PEEL are rejected.  The stop rule and pi / st as pr_solve_ifp2; the
  * bound covers negative residuals.
  */
 pr_status pr_solve_ifp2_warm(const pr_graph *g, const pr_opts *o, pr_state *s, double *pi, pr_stats *st);
@@ -51,7 +51,8 @@ pr_status pr_solve_ifp2_warm(const pr_graph *g, const pr_opts *o, pr_state *s, d
  * h += c (P_new - P_old) pibar over the k sources in `changed` (host array of
  * original ids whose out-edge lists differ), or over every vertex when changed is
  * NULL.  A source left out although its edges changed leaves the state wrong for
- * g_new.  PR_EINVAL if no solve has fixed c yet, on size mismatch or bad ids.
+ * g_new.  PR_EINVAL if no solve has fixed c yet, on size mismatch, bad ids or
+ * a graph uploaded with PR_PEEL.
  */
 pr_status pr_state_update(pr_state *s, const pr_graph *g_old, const pr_graph *g_new, const int32_t *changed,
                           int32_t k);

@@ -9,6 +9,8 @@ the GPU library (``paper_2302_03245_amd``) and never imports it.
   and a dense Gaussian-elimination solve of Eq. 2 / Eq. 4 for small graphs.
 * ``exact`` (pure Python, ``fractions.Fraction``): exact rational solves of Eq. 2
   and Eq. 4 for graphs of a handful of vertices.
+* ``weak_dangling_levels`` (numpy): the dangling and weakly dangling vertices of
+  section 2, found by deleting dangling vertices round after round.
 
 Every graph argument is any object with ``n``, ``row_ptr`` (int64[n+1]) and
 ``col`` (int32[m]) attributes, or an ``(n, row_ptr, col)`` tuple.
@@ -147,3 +149,31 @@ def xi_for_l1(tol: float, c: float, n: int, n_nondangling: int) -> float:
     doubles the error.
     """
     return tol * (1.0 - c) / (2.0 * c) * n / max(1, n_nondangling)
+
+
+def weak_dangling_levels(g, max_levels=None):
+    """Deletion round in which each vertex becomes dangling (section 2, graph definitions).
+
+    Round 0 deletes the dangling vertices (no out-edge); round L >= 1 deletes the
+    vertices that the earlier deletions left without an out-edge -- the weakly
+    dangling vertices.  Returns int64[n]: the round of each vertex, -1 for vertices
+    never deleted (they reach a cycle), and for those of rounds above max_levels
+    when it is given.  Each round recounts every vertex's out-edges into vertices
+    not yet deleted (O(m) per round).
+    """
+    n, rp, col = _graph(g)
+    m = int(rp[n])
+    src = np.repeat(np.arange(n, dtype=np.int64), np.diff(rp))
+    dst = col[:m].astype(np.int64)
+    level = np.full(n, -1, dtype=np.int64)
+    deleted = np.zeros(n, dtype=bool)
+    rnd = 0
+    while max_levels is None or rnd <= max_levels:
+        live_out = np.bincount(src[~deleted[dst]], minlength=n)
+        new = ~deleted & (live_out == 0)
+        if not new.any():
+            break
+        level[new] = rnd
+        deleted |= new
+        rnd += 1
+    return level

@@ -95,6 +95,48 @@ struct EventPair {
 // graph upload
 // ---------------------------------------------------------------------------
 
+// Levels of weakly dangling vertices (PR_PEEL): lev = 0 for a dangling vertex, L >= 1 for
+// one whose out-edges all lead to vertices of levels below L, -1 for the core.  Rounds of
+// deletion from the dangling vertices along reversed edges: each vertex counts down its
+// out-edges into vertices not yet peeled and peels in the round that takes the last one.
+// Returns the number of levels.
+int32_t peel_levels(int64_t n, const int64_t *rp, const int32_t *col, std::vector<int32_t> &lev) {
+    const int64_t m = rp[n];
+    std::vector<int64_t> ip((size_t)n + 1, 0);
+    for (int64_t e = 0; e < m; ++e) ip[(size_t)col[e] + 1]++;
+    for (int64_t i = 0; i < n; ++i) ip[(size_t)i + 1] += ip[(size_t)i];
+    std::vector<int32_t> isrc((size_t)std::max<int64_t>(m, 1));
+    {
+        std::vector<int64_t> cur(ip.begin(), ip.end() - 1);
+        for (int64_t v = 0; v < n; ++v)
+            for (int64_t e = rp[v]; e < rp[v + 1]; ++e) isrc[(size_t)cur[(size_t)col[e]]++] = (int32_t)v;
+    }
+    std::vector<int32_t> rem((size_t)n), front, next;
+    lev.assign((size_t)n, -1);
+    for (int64_t v = 0; v < n; ++v) {
+        rem[(size_t)v] = (int32_t)(rp[v + 1] - rp[v]);
+        if (rem[(size_t)v] == 0) {
+            lev[(size_t)v] = 0;
+            front.push_back((int32_t)v);
+        }
+    }
+    int32_t levels = 0;
+    for (int32_t L = 1; L <= PR_PEEL_MAX_LEVELS && !front.empty(); ++L) {
+        next.clear();
+        for (int32_t v : front)
+            for (int64_t e = ip[(size_t)v]; e < ip[(size_t)v + 1]; ++e) {
+                const int32_t u = isrc[(size_t)e];
+                if (--rem[(size_t)u] == 0) {
+                    lev[(size_t)u] = L;
+                    next.push_back(u);
+                }
+            }
+        if (!next.empty()) levels = L;
+        front.swap(next);
+    }
+    return levels;
+}
+
 // Device vertex order: non-dangling vertices first, by decreasing out-degree
 // (ties by original id), then dangling vertices in original order.  A vertex's
 // out-degree is how often its weight is gathered by a pull sweep (and, on
@@ -103,14 +145,17 @@ struct EventPair {
 // the per-XCD L2.  Stable LSD radix sort on the complemented degree.  With a
 // segment index per vertex (a graph set: segments are contiguous id ranges)
 // the order is by segment first, so every segment's non-dangling vertices,
-// and its dangling ones, stay contiguous.
-int32_t degree_order(int64_t n, const int64_t *rp, const int32_t *seg_of, std::vector<int32_t> &perm,
-                     std::vector<int32_t> &newid) {
+// and its dangling ones, stay contiguous.  With peel levels (lev, see peel_levels) the
+// sorted prefix is the core, followed by the peeled vertices by level from the highest
+// down (original order within a level); lvl_lo receives the first new id of each level,
+// then of the dangling vertices, then n.
+int32_t degree_order(int64_t n, const int64_t *rp, const int32_t *seg_of, const int32_t *lev, int32_t levels,
+                     std::vector<int32_t> &perm, std::vector<int32_t> &newid, std::vector<int32_t> &lvl_lo) {
     std::vector<int32_t> nd;
     std::vector<uint32_t> key;
     nd.reserve((size_t)n);
     for (int64_t i = 0; i < n; ++i)
-        if (rp[i + 1] > rp[i]) nd.push_back((int32_t)i);
+        if (lev ? lev[i] < 0 : rp[i + 1] > rp[i]) nd.push_back((int32_t)i);
     const size_t nN = nd.size();
     std::vector<int32_t> tmp(nN);
     std::vector<uint32_t> cnt(1u << 16);
@@ -135,6 +180,22 @@ int32_t degree_order(int64_t n, const int64_t *rp, const int32_t *seg_of, std::v
     newid.resize((size_t)n);
     size_t k = 0;
     for (int32_t v : nd) perm[k++] = v;
+    lvl_lo.clear();
+    if (lev) {
+        std::vector<size_t> pos((size_t)levels + 1, 0);
+        for (int64_t i = 0; i < n; ++i)
+            if (lev[i] > 0) pos[(size_t)lev[i]]++;
+        for (int32_t L = levels; L >= 1; --L) {  // highest level first
+            const size_t c = pos[(size_t)L];
+            pos[(size_t)L] = k;
+            lvl_lo.push_back((int32_t)k);
+            k += c;
+        }
+        for (int64_t i = 0; i < n; ++i)
+            if (lev[i] > 0) perm[pos[(size_t)lev[i]]++] = (int32_t)i;
+        lvl_lo.push_back((int32_t)k);
+        lvl_lo.push_back((int32_t)n);
+    }
     for (int64_t i = 0; i < n; ++i)
         if (rp[i + 1] == rp[i]) perm[k++] = (int32_t)i;
     for (int64_t j = 0; j < n; ++j) newid[perm[j]] = (int32_t)j;
@@ -144,8 +205,9 @@ int32_t degree_order(int64_t n, const int64_t *rp, const int32_t *seg_of, std::v
 pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
                       const int32_t *seg_of, pr_graph **out) {
     if (!out) return fail(PR_EINVAL, "out is NULL");
-    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE | PR_TILE_MASK | PR_GROUPS_MASK | PR_UNSORTED_IN))
+    if (flags & ~(PR_INPUT_DEVICE | PR_DEDUPE | PR_TILE_MASK | PR_GROUPS_MASK | PR_UNSORTED_IN | PR_PEEL))
         return fail(PR_EINVAL, "unknown upload flag");
+    if ((flags & PR_PEEL) && seg_of) return fail(PR_EINVAL, "graph sets are not peeled");
     const uint32_t tile_shift = (flags & PR_TILE_MASK) >> 8;
     if (tile_shift != 0 && (tile_shift < 2 || tile_shift > 4)) return fail(PR_EINVAL, "tile shift must be 2, 3 or 4");
     if (n < 1 || n >= ((int64_t)1 << 31)) return fail(PR_EINVAL, "n must be in [1, 2^31)");
@@ -253,15 +315,41 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
         return e;
     };
 
+    // weakly dangling levels (PR_PEEL) need the columns on the host
+    std::vector<int32_t> lev, ccol;
+    int32_t levels = 0;
+    if (flags & PR_PEEL) {
+        const int32_t *pc = hcol;
+        if (!pc) {
+            ccol.resize((size_t)std::max<int64_t>(m, 1));
+            if (m) HIPCHK(hipMemcpyAsync(ccol.data(), d_col, sizeof(int32_t) * m, hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            pc = ccol.data();
+        }
+        levels = peel_levels(n, rp, pc, lev);
+        std::vector<int32_t>().swap(ccol);
+    }
+
+    // class of every vertex: swept (non-dangling; with PR_PEEL the core) or deferred
     uint32_t *d_isN, *d_scan;
     HIPCHK(tmp.alloc(&d_isN, (size_t)n));
     HIPCHK(tmp.alloc(&d_scan, scan_tmp_elems(std::max<int64_t>(n, m) + 1)));
-    HIPCHK(launch_degree_class(d_rp64, n, d_isN, s));
+    if (flags & PR_PEEL) {
+        std::vector<uint32_t> is_core((size_t)n);
+        for (int64_t i = 0; i < n; ++i) is_core[(size_t)i] = lev[(size_t)i] < 0 ? 1u : 0u;
+        HIPCHK(hipMemcpyAsync(d_isN, is_core.data(), sizeof(uint32_t) * n, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    } else {
+        HIPCHK(launch_degree_class(d_rp64, n, d_isN, s));
+    }
 
     // vertex order on the device (see degree_order)
     std::vector<int32_t> h_perm, h_newid;
-    G.nN = degree_order(n, rp, seg_of, h_perm, h_newid);
+    G.nN = degree_order(n, rp, seg_of, lev.empty() ? nullptr : lev.data(), levels, h_perm, h_newid, G.lvl_lo);
     G.nD = (int32_t)(n - G.nN);
+    G.nP = lev.empty() ? 0 : G.lvl_lo[(size_t)levels] - G.nN;
+    const int32_t nNP = G.nN + G.nP;  // rows with out-edges
+    std::vector<int32_t>().swap(lev);
     G.dangling_bits.assign((size_t)(n + 63) / 64, 0);
     for (int64_t i = 0; i < n; ++i)
         if (rp[i + 1] == rp[i]) G.dangling_bits[(size_t)i >> 6] |= 1ull << (i & 63);
@@ -276,25 +364,30 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
     HIPCHK(hipMemsetAsync(d_indeg_old, 0, sizeof(uint32_t) * n, s));
     HIPCHK(launch_indegree(d_col, m, d_indeg_old, s));
 
-    HIPCHK(tmp.alloc(&d_cnn, (size_t)G.nN + 1));
-    HIPCHK(tmp.alloc(&d_cnd, (size_t)G.nN + 1));
-    HIPCHK(galloc(&G.deg, (size_t)G.nN));
-    HIPCHK(galloc(&G.rp_nn, (size_t)G.nN + 1));
-    HIPCHK(galloc(&G.rp_nd, (size_t)G.nN + 1));
+    HIPCHK(tmp.alloc(&d_cnn, (size_t)nNP + 1));
+    HIPCHK(tmp.alloc(&d_cnd, (size_t)nNP + 1));
+    HIPCHK(galloc(&G.deg, (size_t)nNP));
+    HIPCHK(galloc(&G.rp_nn, (size_t)nNP + 1));
+    HIPCHK(galloc(&G.rp_nd, (size_t)nNP + 1));
     HIPCHK(hipEventRecord(ev_split.a, s));
-    HIPCHK(launch_count_nn(d_rp64, d_col, d_isN, G.perm, G.nN, d_cnn, d_cnd, G.deg, s));
-    HIPCHK(launch_scan_u32(d_cnn, G.rp_nn, G.nN, d_scan, s));
-    HIPCHK(launch_scan_u32(d_cnd, G.rp_nd, G.nN, d_scan, s));
-    uint32_t h_mm[2] = {0, 0};
+    HIPCHK(launch_count_nn(d_rp64, d_col, d_isN, G.perm, nNP, d_cnn, d_cnd, G.deg, s));
+    HIPCHK(launch_scan_u32(d_cnn, G.rp_nn, nNP, d_scan, s));
+    HIPCHK(launch_scan_u32(d_cnd, G.rp_nd, nNP, d_scan, s));
+    // edges of the swept rows into swept / deferred targets, and of all rows
+    uint32_t h_mm[4] = {0, 0, 0, 0};
     HIPCHK(hipMemcpyAsync(&h_mm[0], G.rp_nn + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipMemcpyAsync(&h_mm[1], G.rp_nd + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&h_mm[2], G.rp_nn + nNP, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&h_mm[3], G.rp_nd + nNP, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    G.mNN = h_mm[0];
-    G.mND = h_mm[1];
-    if (G.mNN + G.mND != m) return fail(PR_EDEVICE, "internal: split edge count mismatch");
+    G.mNN = h_mm[2];
+    G.mND = h_mm[3];
+    const int64_t mND_swept = h_mm[1];
+    // a peeled vertex has no edge into the core
+    if (h_mm[0] != h_mm[2] || G.mNN + G.mND != m) return fail(PR_EDEVICE, "internal: split edge count mismatch");
     HIPCHK(galloc(&G.col_nn, (size_t)G.mNN));
     HIPCHK(galloc(&G.col_nd, (size_t)G.mND));
-    HIPCHK(launch_split_rows(d_rp64, d_col, d_isN, G.newid, G.perm, G.nN, G.rp_nn, G.col_nn, G.rp_nd, G.col_nd, s));
+    HIPCHK(launch_split_rows(d_rp64, d_col, d_isN, G.newid, G.perm, nNP, G.rp_nn, G.col_nn, G.rp_nd, G.col_nd, s));
     HIPCHK(hipEventRecord(ev_split.b, s));
 
     // in-edge lists (N targets first, then D targets)
@@ -304,8 +397,8 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
     HIPCHK(launch_scan_u32(d_indeg, G.in_ptr, n, d_scan, s));
     HIPCHK(tmp.alloc(&d_cursor, (size_t)n));
     HIPCHK(hipMemcpyAsync(d_cursor, G.in_ptr, sizeof(uint32_t) * n, hipMemcpyDeviceToDevice, s));
-    HIPCHK(launch_fill_csc(G.rp_nn, G.col_nn, G.nN, d_cursor, G.in_src, s));
-    HIPCHK(launch_fill_csc(G.rp_nd, G.col_nd, G.nN, d_cursor, G.in_src, s));
+    HIPCHK(launch_fill_csc(G.rp_nn, G.col_nn, nNP, d_cursor, G.in_src, s));
+    HIPCHK(launch_fill_csc(G.rp_nd, G.col_nd, nNP, d_cursor, G.in_src, s));
     if (!(flags & PR_UNSORTED_IN)) HIPCHK(sort_in_lists(n, m, G.in_ptr, G.in_src, s));
     unsigned long long *d_zero;
     HIPCHK(tmp.alloc(&d_zero, 1));
@@ -329,10 +422,20 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
         return launch_plan(p, s);
     };
     HIPCHK(make_plan(G.push_nn, G.rp_nn, G.col_nn, G.nN, G.mNN));
-    HIPCHK(make_plan(G.push_nd, G.rp_nd, G.col_nd, G.nN, G.mND));
+    HIPCHK(make_plan(G.push_nd, G.rp_nd, G.col_nd, G.nN, mND_swept));
     HIPCHK(make_plan(G.pull_all, G.in_ptr, G.in_src, (int32_t)n, m));
     HIPCHK(make_plan(G.pull_nn, G.in_ptr, G.in_src, G.nN, G.mNN));
     HIPCHK(make_plan(G.pull_nd, G.in_ptr + G.nN, G.in_src, G.nD, G.mND));
+    if (!G.lvl_lo.empty()) {  // PR_PEEL: one gather per deferred block
+        std::vector<uint32_t> ip_lo(G.lvl_lo.size());
+        for (size_t b = 0; b < G.lvl_lo.size(); ++b)
+            HIPCHK(hipMemcpyAsync(&ip_lo[b], G.in_ptr + G.lvl_lo[b], sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        G.lvl_pull.resize(G.lvl_lo.size() - 1);
+        for (size_t b = 0; b + 1 < G.lvl_lo.size(); ++b)
+            HIPCHK(make_plan(G.lvl_pull[b], G.in_ptr + G.lvl_lo[b], G.in_src, G.lvl_lo[b + 1] - G.lvl_lo[b],
+                             (int64_t)ip_lo[b + 1] - ip_lo[b]));
+    }
     {
         Epoch e0;
         e0.t_start = 0;
@@ -349,7 +452,12 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
     // edges), then compacted in-edge lists for the sweeps after which whole depth
     // classes of sources can no longer push (section 3.3.3: unreferenced and weakly
     // unreferenced vertices leave the computation).
-    HIPCHK(galloc(&G.depth, (size_t)G.nN));
+    HIPCHK(galloc(&G.depth, (size_t)nNP));
+    if (G.nP > 0) {  // peeled sources never lose their in-edges from the compacted lists
+        std::vector<int32_t> inf((size_t)G.nP, kDepthInf);
+        HIPCHK(hipMemcpyAsync(G.depth + G.nN, inf.data(), sizeof(int32_t) * G.nP, hipMemcpyHostToDevice, s));
+        HIPCHK(hipStreamSynchronize(s));
+    }
     if (G.nN > 0) {
         uint32_t *d_rem, *d_qc;
         int32_t *d_q0, *d_q1;
@@ -657,7 +765,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
 
     size_t bytes = carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
-                   carve_size<double>(nN) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
+                   carve_size<double>(nN + G.nP) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
                    carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
                    carve_size<double>(2) + carve_size<double>(kPartDoubles) +
                    (warm ? 2 * carve_size<double>(nN) + 3 * carve_size<double>(nD) : 0);
@@ -669,7 +777,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     T *w = cv.take<T>(nN);
     double *pibar = cv.take<double>(nN);
     double *xD = cv.take<double>(nD);
-    double *w2 = cv.take<double>(nN);
+    double *w2 = cv.take<double>(nN + G.nP);  // phase-2 weights of every source of a deferred vertex
     double *outbuf = cv.take<double>(out_dev ? 0 : n);
     Ctl *ctl = cv.take<Ctl>(1);
     Trace *tr = cv.take<Trace>(1);
@@ -790,6 +898,15 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         HIPCHK(launch_warm_phase2_prep<T>(nN, nD, h, pibar, pibar0, G.deg, c, xD0, hD0, w2, w3, xD, hDn, s));
         HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
         HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w3, hDn, 0, s));
+    } else if (ifp2 && G.nP > 0) {
+        // peeled levels from the highest down: each gathers from the core and the levels
+        // above it, then hands its own weights to the levels below; the dangling block last
+        HIPCHK(launch_phase2_prep<T>(a, h, pibar, G.deg, c, literal ? 1 : 0, w2, xD, s));
+        for (size_t b = 0; b < G.lvl_pull.size(); ++b) {
+            const int32_t lo = G.lvl_lo[b], hi = G.lvl_lo[b + 1];
+            HIPCHK(launch_pull<double, double>(-1, ctl, G.lvl_pull[b], w2, xD + (lo - nN), 0, s));
+            if (lo < nN + G.nP) HIPCHK(launch_peel_w2(lo, hi, nN, xD, G.deg, c, w2, s));
+        }
     } else if (ifp2 && nD > 0) {
         HIPCHK(launch_phase2_prep<T>(a, h, pibar, G.deg, c, literal ? 1 : 0, w2, xD, s));
         HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
@@ -1393,6 +1510,7 @@ pr_status replan(Graph &G, int32_t tile_k, hipStream_t s) {
     }
     for (auto &v : G.grp_pull)
         for (auto &p : v) HIPCHK(one(p));
+    for (auto &p : G.lvl_pull) HIPCHK(one(p));
     HIPCHK(hipStreamSynchronize(s));
     G.tile_k = tile_k;
     return PR_OK;
@@ -1542,7 +1660,7 @@ pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out) {
     const Graph &G = g->g;
     out->n = G.n;
     out->m = G.m;
-    out->n_dangling = G.nD;
+    out->n_dangling = G.nD - G.nP;
     out->m_dangling = G.mND;
     out->n_unreferenced = G.n_unref;
     out->device_bytes = G.device_bytes;
@@ -1553,6 +1671,8 @@ pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out) {
     out->groups = G.grp.size() > 1 ? (int64_t)G.grp.size() - 1 : 1;
     out->tile_items = (int64_t)kBlock * G.tile_k;
     out->ordered = G.grp.size() > 2 && !G.grp_pull.empty() && G.prefer_ordered ? 1 : 0;
+    out->n_peeled = G.nP;
+    out->peel_levels = G.nP > 0 ? (int64_t)G.lvl_pull.size() - 1 : 0;
     return PR_OK;
 }
 
@@ -1567,6 +1687,8 @@ static pr_status solve_common(const pr_graph *g, int method, const double *p, co
     if (ps != PR_OK) return ps;
     ps = enter(g);
     if (ps != PR_OK) return ps;
+    if (method != 2 && g->g.nP > 0)
+        return fail(PR_EINVAL, "a graph uploaded with PR_PEEL serves IFP2 solves only");
     try {
         const Graph &G = g->g;
         if (method == 3) {
@@ -1635,6 +1757,7 @@ pr_status pr_solve_ifp2_warm(const pr_graph *g, const pr_opts *o, pr_state *s, d
     if (ps != PR_OK) return ps;
     if (op.flags & (PR_IFP2_LITERAL | PR_P_DEVICE)) return fail(PR_EINVAL, "option flag not supported for warm solves");
     if (g->g.n != s->n) return fail(PR_EINVAL, "graph and state differ in n");
+    if (g->g.nP > 0) return fail(PR_EINVAL, "warm starts need a graph uploaded without PR_PEEL");
     if (s->c != 0.0 && s->c != op.c) return fail(PR_EINVAL, "c differs from the state's damping factor");
     ps = enter(g);
     if (ps != PR_OK) return ps;
@@ -1655,6 +1778,8 @@ pr_status pr_state_update(pr_state *s, const pr_graph *g_old, const pr_graph *g_
     if (!s || !g_old || !g_new) return fail(PR_EINVAL, "NULL argument");
     if (s->c == 0.0) return fail(PR_EINVAL, "the state has not been solved yet (no damping factor)");
     if (g_old->g.n != s->n || g_new->g.n != s->n) return fail(PR_EINVAL, "graphs and state differ in n");
+    if (g_old->g.nP > 0 || g_new->g.nP > 0)
+        return fail(PR_EINVAL, "warm starts need graphs uploaded without PR_PEEL");
     if (changed && k < 0) return fail(PR_EINVAL, "k < 0");
     if (changed)
         for (int32_t q = 0; q < k; ++q)
@@ -1780,9 +1905,11 @@ pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_
     if (ps != PR_OK) return ps;
     pr_status worst = PR_OK;
     try {
-        // groups of kBatch sources share one batched solve; a lone source runs alone
-        for (int32_t r = 0; r < k; r += kBatch) {
-            const int kb = (int)std::min<int32_t>(kBatch, k - r);
+        // groups of kBatch sources share one batched solve; a lone source runs alone, as
+        // does every source on a peeled graph (the batched sweeps cover every non-dangling row)
+        const int32_t width = G.nP > 0 ? 1 : kBatch;
+        for (int32_t r = 0; r < k; r += width) {
+            const int kb = (int)std::min<int32_t>(width, k - r);
             double *rows = pi + (size_t)r * (size_t)G.n;
             pr_stats *sr = st ? st + r : nullptr;
             pr_status rs;

@@ -138,14 +138,19 @@ struct Epoch {
 // vertices come first ([0, n_N), original order kept), dangling after.
 struct Graph {
     int64_t n = 0, m = 0;
-    int32_t nN = 0, nD = 0;
+    int32_t nN = 0, nD = 0;       // swept prefix [0, nN); deferred vertices [nN, n), nD = n - nN
+    // PR_PEEL: weakly dangling vertices [nN, nN + nP) of the deferred region, by level from
+    // the highest down; the rows of deg, rp_nn and rp_nd cover them too (nN + nP rows)
+    int32_t nP = 0;
+    std::vector<int32_t> lvl_lo;   // first new id of each deferred block (levels, then dangling), then n
+    std::vector<MPPlan> lvl_pull;  // gather plan of each block's in-edges
     int64_t mNN = 0, mND = 0, n_unref = 0;
     int32_t *perm = nullptr;      // new id -> original id, [n]
     int32_t *newid = nullptr;     // original id -> new id, [n]
-    int32_t *deg = nullptr;       // out-degree of non-dangling vertices, [nN]
-    uint32_t *rp_nn = nullptr;    // CSR of edges N -> N, [nN + 1]
+    int32_t *deg = nullptr;       // out-degree of non-dangling vertices, [nN + nP]
+    uint32_t *rp_nn = nullptr;    // CSR of edges N -> N, [nN + nP + 1]
     int32_t *col_nn = nullptr;    // [mNN]
-    uint32_t *rp_nd = nullptr;    // CSR of edges N -> D, [nN + 1]
+    uint32_t *rp_nd = nullptr;    // CSR of edges into the deferred region, [nN + nP + 1]
     int32_t *col_nd = nullptr;    // [mND]
     uint32_t *in_ptr = nullptr;   // in-edges of every target (N targets first), [n + 1]
     int32_t *in_src = nullptr;    // [m]
@@ -156,7 +161,7 @@ struct Graph {
     bool bp_ready[2] = {false, false};
     std::vector<MPPlan> bp_pull_nn[2];  // per epoch
     MPPlan bp_pull_nd[2], bp_push_nn[2];
-    int32_t *depth = nullptr;     // unreferenced depth of non-dangling vertices, [nN]
+    int32_t *depth = nullptr;     // unreferenced depth of non-dangling vertices, [nN + nP] (peeled: infinite)
     int32_t max_depth = -1;       // largest finite depth
     std::vector<Epoch> epochs;    // epochs[0] aliases the full in-edge lists
     int32_t tile_k = kMPK;        // merge-path items per thread of the sweep tiles
@@ -203,6 +208,9 @@ hipError_t launch_permute_u32(const uint32_t *in_old, const int32_t *perm, int64
                               hipStream_t s);
 hipError_t launch_fill_csc(const uint32_t *rp, const int32_t *col, int32_t R, uint32_t *cursor, int32_t *in_src,
                            hipStream_t s);
+// PR_PEEL phase 2: w2[v] = c xD[v - nN] / deg[v] for the peeled block [lo, hi)
+hipError_t launch_peel_w2(int32_t lo, int32_t hi, int32_t nN, const double *xD, const int32_t *deg, double c,
+                          double *w2, hipStream_t s);
 hipError_t launch_count_zero(const uint32_t *a, int64_t n, unsigned long long *out, hipStream_t s);
 hipError_t launch_plan(MPPlan &p, hipStream_t s);
 hipError_t launch_depth_init(int32_t nN, const uint32_t *in_ptr, uint32_t *rem, int32_t *depth, int32_t *q,

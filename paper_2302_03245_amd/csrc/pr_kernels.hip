@@ -696,6 +696,13 @@ __global__ void k_phase2_prep(InitArgs a, const T *h, const double *pibar, const
     }
 }
 
+// a finished level of peeled vertices passes its values on to the levels below
+__global__ void k_peel_w2(int32_t lo, int32_t hi, int32_t nN, const double *xD, const int32_t *deg, double c,
+                          double *w2) {
+    for (int64_t v = lo + blockIdx.x * (int64_t)kBlock + threadIdx.x; v < hi; v += (int64_t)gridDim.x * kBlock)
+        w2[v] = c * xD[v - nN] / (double)deg[v];
+}
+
 template <typename T>
 __device__ __forceinline__ double x_ifp(const InitArgs &a, const T *h, const double *pibar, const double *xD,
                                         int ifp2, int literal, int64_t i) {
@@ -1029,6 +1036,12 @@ template <typename T>
 hipError_t launch_phase2_prep(const InitArgs &a, const T *h, const double *pibar, const int32_t *deg, double c,
                               int literal, double *w2, double *xD, hipStream_t s) {
     PRK_LAUNCH(k_phase2_prep<T>, grid_for(a.n, 4, 8192), a, h, pibar, deg, c, literal, w2, xD);
+}
+
+hipError_t launch_peel_w2(int32_t lo, int32_t hi, int32_t nN, const double *xD, const int32_t *deg, double c,
+                          double *w2, hipStream_t s) {
+    if (hi <= lo) return hipSuccess;
+    PRK_LAUNCH(k_peel_w2, grid_for((int64_t)hi - lo, 4, 8192), lo, hi, nN, xD, deg, c, w2);
 }
 
 template <typename T>

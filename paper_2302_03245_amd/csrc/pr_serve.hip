@@ -442,6 +442,7 @@ pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id
     clear_error();
     if (!s || !g || !graph_id) return set_error(PR_EINVAL, "NULL argument");
     const Graph &G = g->g;
+    if (G.nP > 0) return set_error(PR_EINVAL, "the server needs graphs uploaded without PR_PEEL");
     const bool fp32 = s->o.residual == PR_RES_FP32;
     const size_t fp = Engine::footprint(G, s->o.slots, fp32) + Engine::footprint_single(G, fp32);
     {

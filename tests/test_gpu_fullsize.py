@@ -4,7 +4,8 @@
   unreferenced): IFP1 / IFP2 / power with FP32 residuals and the certified
   L1 <= 1e-6 stop, and IFP2 with FP64 residuals at L1 <= 1e-9.
 * Layered DAG (2^23 vertices, 64 layers, 80M Zipf edges + 2 % back edges):
-  the same FP32 configuration.
+  the same FP32 configuration, and IFP2 on the graph uploaded with its weakly
+  dangling vertices peeled (counts pinned to oracle.weak_dangling_levels).
 Reference: the FP64 power-method oracle over the whole graph (tens of seconds
 of one host core).  Every GPU result is compared element by element (L1), by
 its top-1000 ranking (tie rule of conftest.topk_agree), and by the
@@ -32,13 +33,20 @@ def _eq_residual(g, pi):
     return float(np.abs(pi - C * (P @ pi) - gamma / g.n).sum())
 
 
-def _check(pr, g, ref, fp64_too):
+def _check(pr, g, ref, fp64_too, peel=False):
     dg = pr.upload(g.row_ptr, g.col)
     runs = [("ifp2", lambda: pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6),
             ("ifp1", lambda: pr.ifp1(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6),
             ("power", lambda: pr.power(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6)]
     if fp64_too:
         runs.append(("ifp2_fp64", lambda: pr.ifp2(dg, c=C, l1_tol=1e-9), 1e-9))
+    if peel:  # weakly dangling vertices out of the sweeps, as the DAG bench line runs it
+        dp = pr.upload(g.row_ptr, g.col, peel=True)
+        lev = oracle.weak_dangling_levels(g, max_levels=64)
+        info = dp.info()
+        print(f"{g.name} peeled {info['n_peeled']} in {info['peel_levels']} levels", flush=True)
+        assert info["n_peeled"] == int((lev >= 1).sum()) and info["m_dangling"] == int((lev[g.col] >= 0).sum())
+        runs.append(("ifp2_peel", lambda: pr.ifp2(dp, c=C, l1_tol=1e-6, residual="fp32"), 1e-6))
     for name, run, tol in runs:
         pi, st = run()
         err = l1(pi, ref)
@@ -51,6 +59,8 @@ def _check(pr, g, ref, fp64_too):
         assert abs(pi.sum() - 1.0) < 1e-10
         assert _eq_residual(g, pi) <= 2 * tol
     dg.free()
+    if peel:
+        dp.free()
 
 
 @pytest.mark.timeout(300)
@@ -68,7 +78,7 @@ def test_layered_dag(pr_lib):
     print(f"layered DAG: n={g.n} m={g.m} lambda={g.meta['lambda']:.4f}", flush=True)
     ref, it, delta = oracle.power(g, C, tol=1e-11)
     print(f"oracle power: {it} iterations, delta {delta:.2e}", flush=True)
-    _check(pr_lib, g, ref, fp64_too=False)
+    _check(pr_lib, g, ref, fp64_too=False, peel=True)
 
 
 @pytest.fixture(scope="module")
