@@ -732,9 +732,9 @@ struct SweepTimer {
 };
 
 // partials of one solve: the synchronous sweep's 5 x kRedBlocks, or the ordered
-// sweep's 5 x kGroupBlocks per group plus kRedBlocks for the residual sum
-constexpr int kGroupBlocks = 256;
-constexpr int kMaxGroups = 15;
+// sweep's 5 x kGroupBlocks per group plus kRedBlocks for the residual sum; a
+// group's reserve takes one workgroup per 1024 vertices, up to kGroupBlocks
+constexpr int kGroupBlocks = 1024;
 constexpr size_t kPartDoubles = (size_t)5 * kGroupBlocks * kMaxGroups + kRedBlocks;
 static_assert(kPartDoubles >= (size_t)5 * kRedBlocks, "partials");
 
@@ -828,6 +828,11 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     const bool ordered_ok = ifp2 && ngr > 1 && ngr <= kMaxGroups && force == 0 && !(o.flags & PR_JACOBI) &&
                             !G.grp_pull.empty() && G.prefer_ordered;
     bool ordered = ordered_ok && a.uniform && !warm;
+    GroupBlocks gb{};
+    gb.stride = kGroupBlocks;
+    for (int q = 0; q < ngr && q < kMaxGroups; ++q)
+        gb.nb[q] = (int32_t)std::min<int64_t>(
+            kGroupBlocks, std::max<int64_t>(1, ((int64_t)G.grp[q + 1] - G.grp[q] + 1023) / 1024));
     const double sT = (double)sizeof(T);
     int t = 0;
     bool stopped = false;
@@ -848,14 +853,14 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                     unsigned long long sweep_edges = 0;
                     for (int q = 0; q < ngr; ++q) {
                         HIPCHK(launch_reserve_range<T>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg, G.rp_nn, c,
-                                                       xi, kGroupBlocks, part + (size_t)5 * kGroupBlocks * q, s));
+                                                       xi, gb.nb[q], part + (size_t)5 * kGroupBlocks * q, s));
                         const MPPlan &pl = G.grp_pull[e][q];
                         sweep_edges += (unsigned long long)pl.edges();
                         const KernelEvents ev =
                             timer.next(t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT));
                         HIPCHK(launch_pull<T, T>(t, ctl, pl, w, h, 0, s, TileSkip(), ev));
                     }
-                    HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, kGroupBlocks, part,
+                    HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, gb, part,
                                                part + (size_t)5 * kGroupBlocks * ngr, c, l1 ? 1 : 0, tol, pull_thr,
                                                sweep_edges, s));
                     continue;

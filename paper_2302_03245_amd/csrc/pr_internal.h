@@ -16,6 +16,14 @@ namespace prk {
 constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kMaxTrace = 4096;   // per-sweep trace entries kept on the device
 constexpr int kRedBlocks = 1024;  // max workgroups of a streaming kernel that feeds a reduction
+constexpr int kMaxGroups = 15;    // vertex groups of ordered sweeps
+
+// workgroups of each group's reserve in an ordered sweep; group g's five partial
+// arrays (nb[g] entries each) start at part + 5 * stride * g
+struct GroupBlocks {
+    int32_t stride;
+    int32_t nb[kMaxGroups];
+};
 constexpr int32_t kDepthInf = 0x7fffffff;  // unreferenced depth of vertices on or below a cycle
 constexpr int kMaxEpochs = 8;     // compacted in-edge lists kept per graph
 constexpr int kMPK = 8;           // default merge-path items (rows + edges) per thread (4, 8 or 16)
@@ -251,7 +259,7 @@ hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T
                                 const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int nbg,
                                 double *part, hipStream_t s);
 template <typename T>
-hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, int nbg,
+hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, const GroupBlocks &gb,
                             const double *part, double *part_s, double c, int stop_l1, double tol,
                             unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s);
 template <typename T>

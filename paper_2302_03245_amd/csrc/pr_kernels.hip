@@ -387,23 +387,30 @@ __global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t
 
 // Management step of an ordered sweep (one workgroup), after all groups have
 // reserved and gathered: the growth of the total mass and the work from the
-// groups' reserve partials (ng groups of nbg workgroups, 5 sums each), S_N
+// groups' reserve partials (group g: gb.nb[g] workgroups, 5 sums each), S_N
 // from k_sum_h; stop when nothing was above the threshold or the certified
-// bound is met.
-__global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr, int ng, int nbg,
+// bound is met.  One pass over all partials, then one block sum per quantity.
+__global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr, int ng, GroupBlocks gb,
                                                       const double *part, int nbs, const double *part_s, double c,
                                                       int stop_l1, double tol, unsigned long long pull_thr,
                                                       unsigned long long pull_edges) {
     if (t > ctl->stop_after) return;
     __shared__ double sd[kBlock / W];
-    double a_sx = 0.0, a_cd = 0.0, a_ed = 0.0;
+    double a_sx = 0.0, a_cd = 0.0, a_ed = 0.0, sn = 0.0;
     for (int g = 0; g < ng; ++g) {
-        const double *pg = part + (size_t)g * 5 * nbg;
-        a_sx += reduce_partials(pg + 2 * nbg, nbg, sd);
-        a_cd += reduce_partials(pg + 3 * nbg, nbg, sd);
-        a_ed += reduce_partials(pg + 4 * nbg, nbg, sd);
+        const double *pg = part + (size_t)g * 5 * gb.stride;
+        const int nb = gb.nb[g];
+        for (int b = threadIdx.x; b < nb; b += kBlock) {
+            a_sx += pg[2 * nb + b];
+            a_cd += pg[3 * nb + b];
+            a_ed += pg[4 * nb + b];
+        }
     }
-    const double sn = reduce_partials(part_s, nbs, sd);
+    for (int b = threadIdx.x; b < nbs; b += kBlock) sn += part_s[b];
+    a_sx = block_sum(a_sx, sd);
+    a_cd = block_sum(a_cd, sd);
+    a_ed = block_sum(a_ed, sd);
+    sn = block_sum(sn, sd);
     if (threadIdx.x != 0) return;
     const unsigned long long a_c = (unsigned long long)a_cd, a_e = (unsigned long long)a_ed;
     const double k = 2.0 * c / (1.0 - c);
@@ -585,13 +592,19 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
                                                  int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
                                                  int32_t ntiles, const WT *w, OT *out, TileSkip skip) {
     constexpr int IPB = K * kBlock;
+    static_assert(IPB < 65536, "row ends are kept as 16-bit offsets within the tile");
+    // pieces of rows shared by threads meet in FP64, or in FP32 when the output is FP32
+    // (the sum is rounded to FP32 when it is added to the output anyway); smaller LDS
+    // footprints let more workgroups share a CU
+    using AccT = typename std::conditional<sizeof(OT) == 4, float, double>::type;
     if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
-    __shared__ uint32_t s_end[IPB + 1];
+    __shared__ uint16_t s_end[IPB + 1];  // row ends in tile items, clamped to IPB
     __shared__ WT s_val[IPB];
-    __shared__ double s_acc[IPB + 1];
+    __shared__ AccT s_acc[IPB + 1];
     const uint32_t rp0 = rp[0];
     for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         if (skip.tgr && tile_frozen(skip, tile, t)) continue;  // uniform over the workgroup
+        const uint32_t base = (uint32_t)tile * IPB;  // first item of the tile
         const uint2 a = plan[tile], b = plan[tile + 1];
         const int32_t i0 = (int32_t)a.x;
         const int32_t i1 = min((int32_t)b.x, R - 1);
@@ -607,8 +620,9 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
             for (int j = 0; j <= K; ++j) {
                 const int32_t kk = threadIdx.x + j * kBlock;
                 if (kk < nr) {
-                    s_end[kk] = rv[j] - rp0 + (uint32_t)(i0 + kk);
-                    s_acc[kk] = 0.0;
+                    // the row of the tile's first item ends at or after it
+                    s_end[kk] = (uint16_t)min(rv[j] - rp0 + (uint32_t)(i0 + kk) - base, (uint32_t)IPB);
+                    s_acc[kk] = (AccT)0;
                 }
             }
         }
@@ -630,9 +644,12 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
             }
         }
         __syncthreads();
-        uint32_t d = min((uint32_t)(tile * IPB + threadIdx.x * K), items);
-        const uint32_t dend = min(d + (uint32_t)K, items);
-        if (d < dend) {
+        const uint32_t d0 = min(base + threadIdx.x * (uint32_t)K, items);
+        const uint32_t dend = min(d0 + (uint32_t)K, items);
+        if (d0 < dend) {
+            // items of this thread, as offsets within the tile (< IPB)
+            uint32_t d = d0 - base;
+            const uint32_t dr_end = dend - base;
             int32_t lo = 0, hi = nr;
             while (lo < hi) {
                 int32_t mid = (lo + hi) >> 1;
@@ -640,20 +657,20 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
                 else hi = mid;
             }
             int32_t k = lo;
-            uint32_t et = rp0 + d - (uint32_t)(i0 + k);
-            // first edge of row i0 + k
-            uint32_t row_first = k == 0 ? first : s_end[k - 1] + rp0 + 1u - (uint32_t)(i0 + k);
+            uint32_t et = rp0 + d0 - (uint32_t)(i0 + k);
+            // first edge of row i0 + k (row k - 1 ends inside the tile)
+            uint32_t row_first = k == 0 ? first : (uint32_t)s_end[k - 1] + base + rp0 + 1u - (uint32_t)(i0 + k);
             bool owned = et == row_first;
             bool touched = false;
             double acc = 0.0;
-            for (; d < dend; ++d) {
+            for (; d < dr_end; ++d) {
                 if (d == s_end[k]) {
                     if (touched) {
                         if (owned) {
                             OT *o = out + (i0 + k);
                             *o = (OT)((double)*o + acc);
                         } else {
-                            atomicAdd(s_acc + k, acc);
+                            atomicAdd(s_acc + k, (AccT)acc);
                         }
                     }
                     acc = 0.0;
@@ -666,12 +683,12 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
                     ++et;
                 }
             }
-            if (touched) atomicAdd(s_acc + k, acc);
+            if (touched) atomicAdd(s_acc + k, (AccT)acc);
         }
         __syncthreads();
         // rows strictly inside the tile belong to this workgroup alone
         for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
-            double v = s_acc[k];
+            double v = (double)s_acc[k];
             if (v == 0.0) continue;
             OT *o = out + (i0 + k);
             if (k == 0 || k == nr - 1) atomicAdd(o, (OT)v);
@@ -974,12 +991,12 @@ hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T
 }
 
 template <typename T>
-hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, int nbg,
+hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, const GroupBlocks &gb,
                             const double *part, double *part_s, double c, int stop_l1, double tol,
                             unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s) {
     const int nbs = grid_for(nN, 8, kRedBlocks);
     hipLaunchKernelGGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, part_s);
-    hipLaunchKernelGGL(k_decide_gs, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, ng, nbg, part, nbs,
+    hipLaunchKernelGGL(k_decide_gs, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, ng, gb, part, nbs,
                        (const double *)part_s, c, stop_l1, tol, pull_thr, pull_edges);
     return hipGetLastError();
 }
@@ -1107,10 +1124,10 @@ template hipError_t launch_reserve_range<float>(int, Ctl *, int32_t, int32_t, fl
 template hipError_t launch_reserve_range<double>(int, Ctl *, int32_t, int32_t, double *, double *, double *,
                                                  const int32_t *, const uint32_t *, double, double, int, double *,
                                                  hipStream_t);
-template hipError_t launch_decide_gs<float>(int, Ctl *, Trace *, int32_t, const float *, int, int, const double *,
-                                            double *, double, int, double, unsigned long long, unsigned long long,
-                                            hipStream_t);
-template hipError_t launch_decide_gs<double>(int, Ctl *, Trace *, int32_t, const double *, int, int,
+template hipError_t launch_decide_gs<float>(int, Ctl *, Trace *, int32_t, const float *, int, const GroupBlocks &,
+                                            const double *, double *, double, int, double, unsigned long long,
+                                            unsigned long long, hipStream_t);
+template hipError_t launch_decide_gs<double>(int, Ctl *, Trace *, int32_t, const double *, int, const GroupBlocks &,
                                              const double *, double *, double, int, double, unsigned long long,
                                              unsigned long long, hipStream_t);
 template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t,
