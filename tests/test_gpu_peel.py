@@ -168,3 +168,24 @@ def test_max_sweeps_and_rejections(pr):
     # still usable afterwards
     pi, st = pr.ifp2(dg, c=C, xi=1e-13)
     assert l1(pi, ref) <= 1e-9
+
+
+def test_device_input_and_dedupe(pr):
+    """Peeling from device buffers (the columns come back to the host for the levels) and
+    after collapsing repeated edges; levels against the oracle on the graph the library keeps."""
+    import torch
+    g = prgen.random_digraph(6000, 15000, seed=31, multi=True, self_loops=True, dangling_frac=0.3)
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    dg = pr.upload(torch.tensor(g.row_ptr, device="cuda"), torch.tensor(g.col, device="cuda"), peel=True)
+    exp = _expected_info(g)
+    info = dg.info()
+    assert info["n_peeled"] == exp["n_peeled"] > 0 and info["m_dangling"] == exp["m_dangling"]
+    pi, st = pr.ifp2(dg, c=C, xi=1e-13)
+    assert st["status"] == 0 and l1(pi, ref) <= 1e-9
+    deg = np.diff(g.row_ptr)
+    key = np.unique(np.repeat(np.arange(g.n), deg).astype(np.int64) * g.n + g.col)
+    gu = prgen.from_edges(g.n, key // g.n, key % g.n)
+    dd = pr.upload(g.row_ptr, g.col, dedupe=True, peel=True)
+    assert dd.m == gu.m and dd.info()["n_peeled"] == _expected_info(gu)["n_peeled"]
+    pi, st = pr.ifp2(dd, c=C, xi=1e-13)
+    assert l1(pi, oracle.power(gu, C, tol=1e-13)[0]) <= 1e-9
