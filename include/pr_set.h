@@ -32,6 +32,7 @@ typedef struct {
     int64_t n_dangling, m_dangling;
     int64_t device_bytes;
     double seconds_upload;
+    int64_t groups;             /* vertex groups of ordered sweeps per graph (1: none) */
 } pr_set_info_t;
 
 /*
@@ -39,9 +40,10 @@ typedef struct {
  * non-decreasing, row_ptr[g][0] = 0) and col[g] (host, row_ptr[g][n[g]] int32,
  * each in [0, n[g])) give graph g in CSR with out-edges per row.  Duplicate
  * edges count with multiplicity.  Totals must stay below 2^31 vertices and 2^31
- * edges.  flags: PR_TILE_SHIFT only.  The inputs are copied.  PR_EINVAL on a
- * malformed graph (nothing is uploaded), PR_ENOMEM / PR_EDEVICE on allocation
- * or device failure.
+ * edges.  flags: PR_TILE_SHIFT, PR_GROUPS(q) (vertex groups per graph for ordered
+ * sweeps, as for one graph: 1 = none; 0 selects 4).  The inputs are copied.
+ * PR_EINVAL on a malformed graph (nothing is uploaded), PR_ENOMEM / PR_EDEVICE
+ * on allocation or device failure.
  */
 pr_status pr_set_upload(int32_t k, const int64_t *n, const int64_t *const *row_ptr, const int32_t *const *col,
                         uint32_t flags, pr_graph_set **out);
@@ -55,7 +57,12 @@ pr_status pr_set_info(const pr_graph_set *s, pr_set_info_t *out);
  *        <= o->l1_tol (thresholds xi_g derived per graph); PR_STOP_XI: every
  *        graph uses threshold o->xi and stops when no vertex exceeds it.
  *        o->residual, o->max_sweeps (for the whole set), o->stream; flags
- *        PR_OUT_DEVICE, PR_FORCE_PUSH, PR_FORCE_PULL.
+ *        PR_OUT_DEVICE, PR_FORCE_PUSH, PR_FORCE_PULL, PR_JACOBI.
+ *        With vertex groups, sweeps over a dense frontier are ordered: group
+ *        by group (in every graph at once), each takes its residuals and
+ *        gathers its pushes before the next group takes its own, as in
+ *        pr_solve_ifp2; a forced scatter mode or PR_JACOBI keeps synchronous
+ *        sweeps.
  *   pi   sum of n[g] doubles (host, or device with PR_OUT_DEVICE), graph g at
  *        offset off[g]; written only when the status is not negative.
  *   st   k entries or NULL: per-graph sweeps, pushes, edges, residual and bound;

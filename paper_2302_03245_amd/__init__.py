@@ -78,7 +78,7 @@ class ServerStats(ctypes.Structure):
 class SetInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("n", ctypes.c_int64), ("m", ctypes.c_int64),
                 ("n_dangling", ctypes.c_int64), ("m_dangling", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("seconds_upload", ctypes.c_double)]
+                ("device_bytes", ctypes.c_int64), ("seconds_upload", ctypes.c_double), ("groups", ctypes.c_int64)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -393,8 +393,9 @@ class GraphSet:
             pass
 
 
-def upload_set(graphs, tile_shift: int = 0) -> GraphSet:
-    """Upload host CSR graphs [(row_ptr int64[n+1], col int32[m]), ...] as one graph set."""
+def upload_set(graphs, tile_shift: int = 0, groups: int = 0) -> GraphSet:
+    """Upload host CSR graphs [(row_ptr int64[n+1], col int32[m]), ...] as one graph set.
+    `groups` q in 1..15: vertex groups per graph for ordered sweeps (0: 4; 1: none)."""
     k = len(graphs)
     rps = [np.ascontiguousarray(rp, dtype=np.int64) for rp, _ in graphs]
     cols = [np.ascontiguousarray(c, dtype=np.int32) for _, c in graphs]
@@ -402,18 +403,19 @@ def upload_set(graphs, tile_shift: int = 0) -> GraphSet:
     rp_ptrs = (ctypes.c_void_p * max(k, 1))(*[r.ctypes.data for r in rps])
     col_ptrs = (ctypes.c_void_p * max(k, 1))(*[c.ctypes.data if c.size else None for c in cols])
     h = ctypes.c_void_p()
-    st = lib().pr_set_upload(k, ns.ctypes.data if k else None, rp_ptrs, col_ptrs, (tile_shift & 7) << 8,
-                             ctypes.byref(h))
+    st = lib().pr_set_upload(k, ns.ctypes.data if k else None, rp_ptrs, col_ptrs,
+                             ((tile_shift & 7) << 8) | ((groups & 15) << 12), ctypes.byref(h))
     if st != PR_OK:
         raise _err(st)
     return GraphSet(h.value, ns)
 
 
 def set_ifp2(gs: GraphSet, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None, stream=None,
-             mode=None):
-    """IFP2 on every graph of a set: c is one factor or one per graph.  Returns
-    (solution over the whole set, list of per-graph stats dicts)."""
-    o = _opts(0.85, xi, l1_tol, residual, max_sweeps, stream, False, mode, False)
+             mode=None, jacobi=False):
+    """IFP2 on every graph of a set: c is one factor or one per graph; `jacobi` keeps
+    synchronous sweeps on a set with vertex groups.  Returns (solution over the whole
+    set, list of per-graph stats dicts)."""
+    o = _opts(0.85, xi, l1_tol, residual, max_sweeps, stream, False, mode, False, jacobi=jacobi)
     cs = None
     if np.ndim(c) == 0:
         o.c = float(c)

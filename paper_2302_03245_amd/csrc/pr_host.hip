@@ -1261,11 +1261,25 @@ struct pr_graph_set {
     int32_t *d_offN = nullptr, *d_offD = nullptr;
     uint2 *d_tg_push = nullptr;            // graph range of every tile of the push plan
     std::vector<uint2 *> d_tg_pull;        // ... and of every epoch's gather plan
+    // ordered sweeps: every graph's non-dangling vertices split into ngr groups of equal
+    // N -> N out-edges (as for one graph); group q of all graphs is a position range
+    // [0, glen[q]) cut by d_goff[q] (k + 1) with vertex = position + d_gbase[q][graph]
+    int32_t ngr = 1;
+    std::vector<int32_t> glen;
+    std::vector<int32_t *> d_goff, d_gbase;
+    std::vector<MPPlan> grp_pull;          // gather plan of each group's in-edges (owned by the union)
+    std::vector<uint2 *> d_tg_grp;         // graph range of every tile of those plans
     ~pr_graph_set() {
         if (d_offN) (void)hipFree(d_offN);
         if (d_offD) (void)hipFree(d_offD);
         if (d_tg_push) (void)hipFree(d_tg_push);
         for (uint2 *p : d_tg_pull)
+            if (p) (void)hipFree(p);
+        for (int32_t *p : d_goff)
+            if (p) (void)hipFree(p);
+        for (int32_t *p : d_gbase)
+            if (p) (void)hipFree(p);
+        for (uint2 *p : d_tg_grp)
             if (p) (void)hipFree(p);
         if (u) (void)pr_graph_free(u);
     }
@@ -1273,12 +1287,100 @@ struct pr_graph_set {
 
 namespace {
 
+// Vertex groups of ordered sweeps for a graph set: within every graph the rule of one
+// graph (boundaries at equal shares of its N -> N out-edges in the degree order; a
+// boundary that does not advance leaves an empty group), and per group the in-edges of
+// all non-dangling rows whose source is in the group, with their gather plan.
+pr_status set_groups(pr_graph_set &S, int32_t ngr) {
+    Graph &G = S.u->g;
+    hipStream_t s = G.stream;
+    const int32_t nN = G.nN, k = S.k;
+    std::vector<uint32_t> rp((size_t)nN + 1);
+    HIPCHK(hipMemcpy(rp.data(), G.rp_nn, sizeof(uint32_t) * ((size_t)nN + 1), hipMemcpyDeviceToHost));
+    std::vector<uint8_t> gid((size_t)nN);
+    std::vector<std::vector<int32_t>> goff((size_t)ngr, std::vector<int32_t>((size_t)k + 1, 0));
+    std::vector<std::vector<int32_t>> gbase((size_t)ngr, std::vector<int32_t>((size_t)k, 0));
+    std::vector<int32_t> b((size_t)ngr + 1);
+    for (int32_t g = 0; g < k; ++g) {
+        const int32_t a = S.offN[(size_t)g], nNg = S.offN[(size_t)g + 1] - a;
+        const uint32_t e0 = rp[(size_t)a], mg = rp[(size_t)(a + nNg)] - e0;
+        b[0] = 0;
+        for (int32_t q = 1; q < ngr; ++q) {
+            const uint32_t target = e0 + (uint32_t)((double)mg * q / ngr);
+            const int32_t x = (int32_t)(std::lower_bound(rp.begin() + a, rp.begin() + a + nNg + 1, target) -
+                                        (rp.begin() + a));
+            b[(size_t)q] = std::min(std::max(x, b[(size_t)q - 1]), nNg);
+        }
+        b[(size_t)ngr] = nNg;
+        for (int32_t q = 0; q < ngr; ++q) {
+            const int32_t len = b[(size_t)q + 1] - b[(size_t)q];
+            for (int32_t j = b[(size_t)q]; j < b[(size_t)q + 1]; ++j) gid[(size_t)(a + j)] = (uint8_t)q;
+            gbase[(size_t)q][(size_t)g] = a + b[(size_t)q] - goff[(size_t)q][(size_t)g];
+            goff[(size_t)q][(size_t)g + 1] = goff[(size_t)q][(size_t)g] + len;
+        }
+    }
+    DevBufs tmp;
+    uint8_t *d_gid;
+    uint32_t *d_cnt, *d_scan;
+    HIPCHK(tmp.alloc(&d_gid, (size_t)nN));
+    HIPCHK(tmp.alloc(&d_cnt, (size_t)nN + 1));
+    HIPCHK(tmp.alloc(&d_scan, scan_tmp_elems((int64_t)nN + 1)));
+    HIPCHK(hipMemcpy(d_gid, gid.data(), (size_t)nN, hipMemcpyHostToDevice));
+    auto galloc = [&](auto **p, size_t count) -> hipError_t {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc((void **)p, bytes);
+        if (e == hipSuccess) {
+            G.allocs.push_back((void *)*p);
+            G.device_bytes += (int64_t)bytes;
+        }
+        return e;
+    };
+    S.ngr = ngr;
+    for (int32_t q = 0; q < ngr; ++q) {
+        int32_t *d_off = nullptr, *d_base = nullptr;
+        HIPCHK(hipMalloc((void **)&d_off, sizeof(int32_t) * ((size_t)k + 1)));
+        S.d_goff.push_back(d_off);
+        HIPCHK(hipMalloc((void **)&d_base, sizeof(int32_t) * (size_t)k));
+        S.d_gbase.push_back(d_base);
+        HIPCHK(hipMemcpy(d_off, goff[(size_t)q].data(), sizeof(int32_t) * ((size_t)k + 1), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(d_base, gbase[(size_t)q].data(), sizeof(int32_t) * (size_t)k, hipMemcpyHostToDevice));
+        S.glen.push_back(goff[(size_t)q][(size_t)k]);
+        // the group's in-edges of every non-dangling row (full lists: no depth epochs)
+        uint32_t *gp;
+        int32_t *gsrc;
+        HIPCHK(galloc(&gp, (size_t)nN + 1));
+        HIPCHK(launch_live_count(nN, G.in_ptr, G.in_src, G.depth, 0, 0, INT_MAX, d_cnt, s, d_gid, q));
+        HIPCHK(launch_scan_u32(d_cnt, gp, nN, d_scan, s));
+        uint32_t ge = 0;
+        HIPCHK(hipMemcpyAsync(&ge, gp + nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        HIPCHK(galloc(&gsrc, (size_t)ge));
+        HIPCHK(launch_live_fill(nN, G.in_ptr, G.in_src, G.depth, 0, 0, INT_MAX, gp, gsrc, s, d_gid, q));
+        MPPlan pl;
+        pl.rp = gp;
+        pl.idx = gsrc;
+        pl.R = nN;
+        pl.items = (uint32_t)((int64_t)nN + ge);
+        pl.ipb = kBlock * G.tile_k;
+        HIPCHK(galloc(&pl.plan, (size_t)(((int64_t)pl.items + pl.ipb - 1) / pl.ipb) + 1));
+        HIPCHK(launch_plan(pl, s));
+        S.grp_pull.push_back(pl);
+        uint2 *tg = nullptr;
+        HIPCHK(hipMalloc((void **)&tg, sizeof(uint2) * (size_t)std::max<int32_t>(pl.blocks, 1)));
+        S.d_tg_grp.push_back(tg);
+        HIPCHK(launch_set_tile_graphs(pl, S.d_offN, k, tg, s));
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    return PR_OK;
+}
+
 pr_status set_upload_impl(int32_t k, const int64_t *n, const int64_t *const *row_ptr, const int32_t *const *col,
                           uint32_t flags, pr_graph_set **out) {
     if (!out) return fail(PR_EINVAL, "out is NULL");
     if (k < 1) return fail(PR_EINVAL, "k must be >= 1");
     if (!n || !row_ptr || !col) return fail(PR_EINVAL, "NULL array");
-    if (flags & ~PR_TILE_MASK) return fail(PR_EINVAL, "unknown upload flag for a graph set");
+    if (flags & ~(PR_TILE_MASK | PR_GROUPS_MASK)) return fail(PR_EINVAL, "unknown upload flag for a graph set");
     std::unique_ptr<pr_graph_set> S(new pr_graph_set());
     S->k = k;
     S->n_g.assign(n, n + k);
@@ -1331,7 +1433,7 @@ pr_status set_upload_impl(int32_t k, const int64_t *n, const int64_t *const *row
         e_at += rp[n[g]];
     }
     urp[(size_t)nt] = e_at;
-    pr_status ps = upload_impl(nt, mt, urp.data(), ucol.data(), flags, seg.data(), &S->u);
+    pr_status ps = upload_impl(nt, mt, urp.data(), ucol.data(), flags & PR_TILE_MASK, seg.data(), &S->u);
     if (ps != PR_OK) return ps;
     const Graph &G = S->u->g;
     if (G.nN != S->offN[(size_t)k]) return fail(PR_EDEVICE, "internal: region sizes of the set disagree");
@@ -1348,6 +1450,11 @@ pr_status set_upload_impl(int32_t k, const int64_t *n, const int64_t *const *row
     S->d_tg_pull.assign(G.epochs.size(), nullptr);
     for (size_t e = 0; e < G.epochs.size(); ++e) HIPCHK(tile_graphs(G.epochs[e].pull_nn, &S->d_tg_pull[e]));
     HIPCHK(hipStreamSynchronize(G.stream));
+    const int32_t ngr = (flags & PR_GROUPS_MASK) ? (int32_t)((flags & PR_GROUPS_MASK) >> 12) : 4;
+    if (ngr > 1 && G.nN > 0 && G.mNN > 0) {
+        ps = set_groups(*S, ngr);
+        if (ps != PR_OK) return ps;
+    }
     *out = S.release();
     return PR_OK;
 }
@@ -1409,6 +1516,10 @@ pr_status solve_set_t(const pr_graph_set &S, const double *cg, const pr_opts &o,
 
     int t = 0;
     bool stopped = nN == 0;
+    // ordered sweeps over the vertex groups while the frontier is dense (every vertex
+    // starts active), as for one graph
+    const bool ordered_ok = S.ngr > 1 && force == 0 && !(o.flags & PR_JACOBI);
+    bool ordered = ordered_ok;
     if (nN > 0) {
         int batch = l1 ? 8 : 16;
         double bound_prev = -1.0;
@@ -1416,13 +1527,24 @@ pr_status solve_set_t(const pr_graph_set &S, const double *cg, const pr_opts &o,
         while (t < max_sweeps) {
             const int nb = std::min(batch, max_sweeps - t);
             for (int q = 0; q < nb; ++q, ++t) {
+                if (ordered) {
+                    for (int32_t r = 0; r < S.ngr; ++r) {
+                        HIPCHK(launch_set_reserve<T>(t, ctl, gs, S.d_goff[(size_t)r], S.d_gbase[(size_t)r], k,
+                                                     S.glen[(size_t)r], h, w, pibar, G.deg, G.rp_nn, s));
+                        HIPCHK(launch_pull<T, T>(t, ctl, S.grp_pull[(size_t)r], w, h, 0, s,
+                                                 TileSkip{S.d_tg_grp[(size_t)r], gs}));
+                    }
+                    HIPCHK(launch_set_sum_h<T>(t, ctl, gs, S.d_offN, k, nN, h, s));
+                    HIPCHK(launch_set_decide(t, ctl, gs, k, l1 ? 1 : 0, tol, 1.0, force, 1, s));
+                    continue;
+                }
                 size_t e = 0;
                 while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
                 const MPPlan &pullp = G.epochs[e].pull_nn;
                 // share of the N -> N edges still in this epoch's gather lists
                 const double live_frac = G.mNN > 0 ? (double)pullp.edges() / (double)G.mNN : 0.0;
-                HIPCHK(launch_set_reserve<T>(t, ctl, gs, S.d_offN, k, nN, h, w, pibar, G.deg, G.rp_nn, s));
-                HIPCHK(launch_set_decide(t, ctl, gs, k, l1 ? 1 : 0, tol, live_frac, force, s));
+                HIPCHK(launch_set_reserve<T>(t, ctl, gs, S.d_offN, nullptr, k, nN, h, w, pibar, G.deg, G.rp_nn, s));
+                HIPCHK(launch_set_decide(t, ctl, gs, k, l1 ? 1 : 0, tol, live_frac, force, 0, s));
                 if (force != 2) HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, force == 0, s, TileSkip{S.d_tg_push, gs}));
                 if (force != 1)
                     HIPCHK(launch_pull<T, T>(t, ctl, pullp, w, h, force == 0, s, TileSkip{S.d_tg_pull[e], gs}));
@@ -1433,6 +1555,7 @@ pr_status solve_set_t(const pr_graph_set &S, const double *cg, const pr_opts &o,
                 stopped = true;
                 break;
             }
+            ordered = ordered_ok && ws.hctl->use_pull;  // a thin frontier scatters instead
             batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, l1);
             bound_prev = ws.hctl->last_bound;
             t_prev = t;
@@ -1856,6 +1979,7 @@ pr_status pr_set_info(const pr_graph_set *s, pr_set_info_t *out) {
     out->m_dangling = G.mND;
     out->device_bytes = G.device_bytes + (int64_t)(2 * sizeof(int32_t) * ((size_t)s->k + 1));
     out->seconds_upload = G.seconds_upload;
+    out->groups = s->ngr;
     return PR_OK;
 }
 

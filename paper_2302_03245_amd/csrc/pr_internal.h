@@ -106,6 +106,7 @@ struct alignas(8) SetG {
     double last_bound;    // bound certified at the last reserve
     double fin_sum, fin_sn;
     double acc[5];        // this sweep: inactive residual, mass to N, sx growth, pushes, pushed edges
+    double sn;            // ordered sweeps: residual left on the non-dangling vertices, summed directly
     double m_nn;          // edges between non-dangling vertices (what a gather of this graph reads)
     unsigned long long tot_pushes, tot_edges;
     int32_t stop_after;   // last sweep whose scatter counts (INT_MAX while running)
@@ -228,12 +229,14 @@ hipError_t launch_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *r
                              hipStream_t s);
 // every in-edge list sorted by source id (pr_sort.hip); synchronises the stream
 hipError_t sort_in_lists(int64_t n, int64_t m, const uint32_t *in_ptr, int32_t *in_src, hipStream_t s);
-// in-edges whose source has depth >= t0 and lies in [slo, shi)
+// in-edges whose source has depth >= t0, lies in [slo, shi) and, when grp is given,
+// belongs to vertex group q (grp[u] == q)
 hipError_t launch_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                             int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt, hipStream_t s);
+                             int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt, hipStream_t s,
+                             const uint8_t *grp = nullptr, int32_t q = 0);
 hipError_t launch_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
                             int32_t t0, int32_t slo, int32_t shi, const uint32_t *out_ptr, int32_t *out_src,
-                            hipStream_t s);
+                            hipStream_t s, const uint8_t *grp = nullptr, int32_t q = 0);
 
 // solve kernels
 struct InitArgs {
@@ -287,12 +290,19 @@ hipError_t launch_unit_vector(double *out, int64_t n, int64_t src, hipStream_t s
 // graphs in the non-dangling and dangling regions of the union
 template <typename T>
 hipError_t launch_set_init(int64_t n, int32_t nN, T *h, double *pibar, hipStream_t s);
+// reserve over `len` positions: position p of graph g (pos_off[g] <= p < pos_off[g + 1])
+// is vertex p + base[g] (base NULL: 0, positions are the non-dangling vertices)
 template <typename T>
-hipError_t launch_set_reserve(int t, const Ctl *ctl, SetG *gs, const int32_t *offN, int32_t k, int32_t nN, T *h,
-                              T *w, double *pibar, const int32_t *deg, const uint32_t *rp_nn, hipStream_t s);
+hipError_t launch_set_reserve(int t, const Ctl *ctl, SetG *gs, const int32_t *pos_off, const int32_t *base,
+                              int32_t k, int32_t len, T *h, T *w, double *pibar, const int32_t *deg,
+                              const uint32_t *rp_nn, hipStream_t s);
+// ordered sweeps: per running graph, sum |h| over its non-dangling vertices into SetG::sn
+template <typename T>
+hipError_t launch_set_sum_h(int t, const Ctl *ctl, SetG *gs, const int32_t *offN, int32_t k, int32_t nN,
+                            const T *h, hipStream_t s);
 hipError_t launch_set_tile_graphs(const MPPlan &p, const int32_t *offN, int32_t k, uint2 *out, hipStream_t s);
 hipError_t launch_set_decide(int t, Ctl *ctl, SetG *gs, int32_t k, int stop_l1, double tol, double live_frac,
-                             int force, hipStream_t s);
+                             int force, int ordered, hipStream_t s);
 template <typename T>
 hipError_t launch_set_phase2_prep(int64_t n, int32_t nN, const SetG *gs, const int32_t *offN, int32_t k,
                                   const T *h, const double *pibar, const int32_t *deg, double *w2, double *xD,

@@ -241,7 +241,7 @@ __global__ void k_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *r
 // one wave per target row: number of in-edges whose source depth is >= t0
 // (also restricted to sources in [slo, shi): the in-lists of one source group)
 __global__ void k_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                             int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt) {
+                             int32_t t0, int32_t slo, int32_t shi, const uint8_t *grp, int32_t q, uint32_t *cnt) {
     const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
     const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
     for (int64_t r = wave; r < R; r += nwaves) {
@@ -249,7 +249,7 @@ __global__ void k_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *i
         uint32_t c = 0;
         for (uint32_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
             const int32_t u = e < hi ? in_src[e] : 0;
-            const bool live = e < hi && u >= slo && u < shi && depth[u] >= t0;
+            const bool live = e < hi && u >= slo && u < shi && depth[u] >= t0 && (!grp || grp[u] == q);
             c += (uint32_t)__popcll(__ballot(live));
         }
         if (lane_id() == 0) cnt[r] = c;
@@ -258,7 +258,8 @@ __global__ void k_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *i
 
 // one wave per target row: copy the live in-edges, order kept
 __global__ void k_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                            int32_t t0, int32_t slo, int32_t shi, const uint32_t *out_ptr, int32_t *out_src) {
+                            int32_t t0, int32_t slo, int32_t shi, const uint8_t *grp, int32_t q,
+                            const uint32_t *out_ptr, int32_t *out_src) {
     const int64_t wave = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W;
     const int64_t nwaves = (int64_t)gridDim.x * kBlock / W;
     const unsigned long long lt = (1ull << lane_id()) - 1ull;
@@ -267,7 +268,7 @@ __global__ void k_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in
         uint32_t o = out_ptr[r];
         for (uint32_t e = lo + lane_id(); e - lane_id() < hi; e += W) {
             const int32_t u = e < hi ? in_src[e] : 0;
-            const bool live = e < hi && u >= slo && u < shi && depth[u] >= t0;
+            const bool live = e < hi && u >= slo && u < shi && depth[u] >= t0 && (!grp || grp[u] == q);
             const unsigned long long mk = __ballot(live);
             if (live) out_src[o + __popcll(mk & lt)] = u;
             o += (uint32_t)__popcll(mk);
@@ -947,16 +948,18 @@ hipError_t launch_depth_step(const int32_t *q, uint32_t qsize, const uint32_t *r
                ncount);
 }
 hipError_t launch_live_count(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
-                             int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt, hipStream_t s) {
+                             int32_t t0, int32_t slo, int32_t shi, uint32_t *cnt, hipStream_t s, const uint8_t *grp,
+                             int32_t q) {
     if (R == 0) return hipSuccess;
-    PRK_LAUNCH(k_live_count, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, slo, shi, cnt);
+    PRK_LAUNCH(k_live_count, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, slo, shi, grp, q,
+               cnt);
 }
 hipError_t launch_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in_src, const int32_t *depth,
                             int32_t t0, int32_t slo, int32_t shi, const uint32_t *out_ptr, int32_t *out_src,
-                            hipStream_t s) {
+                            hipStream_t s, const uint8_t *grp, int32_t q) {
     if (R == 0) return hipSuccess;
-    PRK_LAUNCH(k_live_fill, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, slo, shi, out_ptr,
-               out_src);
+    PRK_LAUNCH(k_live_fill, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, slo, shi, grp, q,
+               out_ptr, out_src);
 }
 hipError_t launch_plan(MPPlan &p, hipStream_t s) {
     p.blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);

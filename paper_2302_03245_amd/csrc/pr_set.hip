@@ -112,17 +112,20 @@ __global__ void k_set_init(int64_t n, int32_t nN, T *h, double *pibar) {
 // w_i = c_g v / deg(i); graphs that stopped publish zeros (their scatter adds
 // nothing).  Per-graph sums (inactive residual, mass sent to non-dangling
 // vertices, growth of the total mass, pushes, pushed edges) go to acc of SetG.
+// The positions [0, len) are cut into per-graph segments by pos_off; position p
+// of graph g is vertex p + base[g]: all non-dangling vertices (base NULL), or
+// one vertex group of every graph (an ordered sweep).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_set_reserve(int t, const Ctl *ctl, SetG *gs, const int32_t *offN,
-                                                        int32_t k, int32_t nN, T *h, T *w, double *pibar,
-                                                        const int32_t *deg, const uint32_t *rp_nn) {
+__global__ __launch_bounds__(kBlock) void k_set_reserve(int t, const Ctl *ctl, SetG *gs, const int32_t *pos_off,
+                                                        const int32_t *base, int32_t k, int32_t len, T *h, T *w,
+                                                        double *pibar, const int32_t *deg, const uint32_t *rp_nn) {
     if (t > ctl->stop_after) return;
     int64_t lo, hi;
-    block_range(nN, lo, hi);
+    block_range(len, lo, hi);
     if (lo >= hi) return;  // whole workgroup
     {
         // graphs that stopped before sweep t - 1 already publish zero weights
-        const int32_t g0 = graph_of(offN, k, lo), g1 = graph_of(offN, k, hi - 1);
+        const int32_t g0 = graph_of(pos_off, k, lo), g1 = graph_of(pos_off, k, hi - 1);
         bool idle = true;
         for (int32_t g = g0; g <= g1 && idle; ++g) idle = gs[g].stop_after < t - 1;
         if (idle) return;  // same answer for every thread of the workgroup
@@ -130,24 +133,27 @@ __global__ __launch_bounds__(kBlock) void k_set_reserve(int t, const Ctl *ctl, S
     __shared__ double s_acc[kLG * 5];
     for (int j = threadIdx.x; j < kLG * 5; j += kBlock) s_acc[j] = 0.0;
     __syncthreads();
-    SegAcc<5> sa{s_acc, gs, (int)(offsetof(SetG, acc) / sizeof(double)), graph_of(offN, k, lo)};
-    GraphCursor cur{offN, k};
+    SegAcc<5> sa{s_acc, gs, (int)(offsetof(SetG, acc) / sizeof(double)), graph_of(pos_off, k, lo)};
+    GraphCursor cur{pos_off, k};
     T xi = (T)0;
     double c = 0.0;
     bool live = false;
+    int64_t shift = 0;
     double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
-        if (cur.g >= 0 && i >= cur.end) {
+    for (int64_t p = lo + threadIdx.x; p < hi; p += kBlock) {
+        if (cur.g >= 0 && p >= cur.end) {
             sa.add(cur.g, a);
 #pragma unroll
             for (int j = 0; j < 5; ++j) a[j] = 0.0;
         }
-        if (cur.advance(i)) {
+        if (cur.advance(p)) {
             const SetG &G = gs[cur.g];
             xi = (T)G.xi;
             c = G.c;
             live = G.stop_after >= t;
+            shift = base ? base[cur.g] : 0;
         }
+        const int64_t i = p + shift;
         const T hv = h[i];
         if (live && hv > xi) {
             const int32_t dg = deg[i];
@@ -168,6 +174,42 @@ __global__ __launch_bounds__(kBlock) void k_set_reserve(int t, const Ctl *ctl, S
     }
     if (cur.g >= 0) sa.add(cur.g, a);
     __syncthreads();
+    sa.flush(graph_of(pos_off, k, hi - 1));
+}
+
+// Residual left on each running graph's non-dangling vertices after an ordered
+// sweep, summed directly (mass one group pushes may already have been taken by
+// a later group of the same sweep): SetG::sn, cleared again by the decision.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_set_sum_h(int t, const Ctl *ctl, SetG *gs, const int32_t *offN,
+                                                      int32_t k, int32_t nN, const T *h) {
+    if (t > ctl->stop_after) return;
+    int64_t lo, hi;
+    block_range(nN, lo, hi);
+    if (lo >= hi) return;
+    {
+        const int32_t g0 = graph_of(offN, k, lo), g1 = graph_of(offN, k, hi - 1);
+        bool idle = true;
+        for (int32_t g = g0; g <= g1 && idle; ++g) idle = gs[g].stop_after < t;
+        if (idle) return;
+    }
+    __shared__ double s_acc[kLG];
+    for (int j = threadIdx.x; j < kLG; j += kBlock) s_acc[j] = 0.0;
+    __syncthreads();
+    SegAcc<1> sa{s_acc, gs, (int)(offsetof(SetG, sn) / sizeof(double)), graph_of(offN, k, lo)};
+    GraphCursor cur{offN, k};
+    bool live = false;
+    double a = 0.0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += kBlock) {
+        if (cur.g >= 0 && i >= cur.end) {
+            sa.add(cur.g, &a);
+            a = 0.0;
+        }
+        if (cur.advance(i)) live = gs[cur.g].stop_after >= t;
+        if (live) a += fabs((double)h[i]);
+    }
+    if (cur.g >= 0) sa.add(cur.g, &a);
+    __syncthreads();
     sa.flush(graph_of(offN, k, hi - 1));
 }
 
@@ -176,26 +218,30 @@ __global__ __launch_bounds__(kBlock) void k_set_reserve(int t, const Ctl *ctl, S
 // union's push/pull mode: gather when the pushed edges reach half of what a
 // gather reads, i.e. of the live edges of the graphs whose scatter this sweep
 // still counts (tiles of the others are skipped).  Accumulators are cleared
-// for the next sweep.
+// for the next sweep.  After an ordered sweep the residual on the non-dangling
+// vertices is the directly summed SetG::sn.
 constexpr int kDecideThreads = 1024;
 __global__ __launch_bounds__(kDecideThreads) void k_set_decide(int t, Ctl *ctl, SetG *gs, int32_t k, int stop_l1,
-                                                               double tol, double live_frac, int force) {
+                                                               double tol, double live_frac, int force,
+                                                               int ordered) {
     if (t > ctl->stop_after) return;
     double edges = 0.0, running = 0.0, bmax = 0.0, live = 0.0;
     for (int32_t g = threadIdx.x; g < k; g += kDecideThreads) {
         SetG &S = gs[g];
         if (S.stop_after < t) continue;
         const double a_in = S.acc[0], a_pr = S.acc[1], a_sx = S.acc[2], a_c = S.acc[3], a_e = S.acc[4];
+        const double sn_direct = S.sn;
 #pragma unroll
         for (int j = 0; j < 5; ++j) S.acc[j] = 0.0;
+        S.sn = 0.0;
         const double kk = 2.0 * S.c / (1.0 - S.c);
         if (a_c == 0.0) {
             // nothing above the threshold: the state is final before this sweep
             S.stop_after = t - 1;
-            S.last_bound = kk * a_in / S.sx;
+            S.last_bound = kk * (ordered ? sn_direct : a_in) / S.sx;
             continue;
         }
-        const double sn = a_in + S.c * a_pr;
+        const double sn = ordered ? sn_direct : a_in + S.c * a_pr;
         const double sx = S.sx + S.c * a_sx;
         const double bound = kk * sn / sx;
         S.sx = sx;
@@ -332,9 +378,18 @@ hipError_t launch_set_init(int64_t n, int32_t nN, T *h, double *pibar, hipStream
 }
 
 template <typename T>
-hipError_t launch_set_reserve(int t, const Ctl *ctl, SetG *gs, const int32_t *offN, int32_t k, int32_t nN, T *h,
-                              T *w, double *pibar, const int32_t *deg, const uint32_t *rp_nn, hipStream_t s) {
-    PRK_LAUNCH(k_set_reserve<T>, grid_for(nN, 4, 2048), t, ctl, gs, offN, k, nN, h, w, pibar, deg, rp_nn);
+hipError_t launch_set_reserve(int t, const Ctl *ctl, SetG *gs, const int32_t *pos_off, const int32_t *base,
+                              int32_t k, int32_t len, T *h, T *w, double *pibar, const int32_t *deg,
+                              const uint32_t *rp_nn, hipStream_t s) {
+    if (len <= 0) return hipSuccess;
+    PRK_LAUNCH(k_set_reserve<T>, grid_for(len, 4, 2048), t, ctl, gs, pos_off, base, k, len, h, w, pibar, deg, rp_nn);
+}
+
+template <typename T>
+hipError_t launch_set_sum_h(int t, const Ctl *ctl, SetG *gs, const int32_t *offN, int32_t k, int32_t nN,
+                            const T *h, hipStream_t s) {
+    if (nN <= 0) return hipSuccess;
+    PRK_LAUNCH(k_set_sum_h<T>, grid_for(nN, 8, 2048), t, ctl, gs, offN, k, nN, h);
 }
 
 hipError_t launch_set_tile_graphs(const MPPlan &p, const int32_t *offN, int32_t k, uint2 *out, hipStream_t s) {
@@ -343,9 +398,9 @@ hipError_t launch_set_tile_graphs(const MPPlan &p, const int32_t *offN, int32_t 
 }
 
 hipError_t launch_set_decide(int t, Ctl *ctl, SetG *gs, int32_t k, int stop_l1, double tol, double live_frac,
-                             int force, hipStream_t s) {
+                             int force, int ordered, hipStream_t s) {
     hipLaunchKernelGGL(k_set_decide, dim3(1), dim3(kDecideThreads), 0, s, t, ctl, gs, k, stop_l1, tol, live_frac,
-                       force);
+                       force, ordered);
     return hipGetLastError();
 }
 
@@ -376,15 +431,18 @@ hipError_t launch_set_final(int64_t n, int32_t nN, SetG *gs, const int32_t *offN
     PRK_LAUNCH(k_set_final_write<T>, grid_for(n, 4, 4096), n, nN, gs, offN, offD, k, perm, h, pibar, xD, out);
 }
 
-#define PRK_SET_INST(T)                                                                                          \
-    template hipError_t launch_set_init<T>(int64_t, int32_t, T *, double *, hipStream_t);                        \
-    template hipError_t launch_set_reserve<T>(int, const Ctl *, SetG *, const int32_t *, int32_t, int32_t, T *, \
-                                              T *, double *, const int32_t *, const uint32_t *, hipStream_t);    \
-    template hipError_t launch_set_phase2_prep<T>(int64_t, int32_t, const SetG *, const int32_t *, int32_t,     \
-                                                  const T *, const double *, const int32_t *, double *, double *, \
-                                                  hipStream_t);                                                  \
-    template hipError_t launch_set_final<T>(int64_t, int32_t, SetG *, const int32_t *, const int32_t *, int32_t, \
-                                            const int32_t *, const T *, const double *, const double *, double *, \
+#define PRK_SET_INST(T)                                                                                              \
+    template hipError_t launch_set_init<T>(int64_t, int32_t, T *, double *, hipStream_t);                            \
+    template hipError_t launch_set_reserve<T>(int, const Ctl *, SetG *, const int32_t *, const int32_t *,            \
+                                              int32_t, int32_t, T *, T *, double *, const int32_t *,                 \
+                                              const uint32_t *, hipStream_t);                                        \
+    template hipError_t launch_set_sum_h<T>(int, const Ctl *, SetG *, const int32_t *, int32_t, int32_t,             \
+                                            const T *, hipStream_t);                                                 \
+    template hipError_t launch_set_phase2_prep<T>(int64_t, int32_t, const SetG *, const int32_t *, int32_t,          \
+                                                  const T *, const double *, const int32_t *, double *, double *,    \
+                                                  hipStream_t);                                                      \
+    template hipError_t launch_set_final<T>(int64_t, int32_t, SetG *, const int32_t *, const int32_t *, int32_t,     \
+                                            const int32_t *, const T *, const double *, const double *, double *,    \
                                             hipStream_t);
 PRK_SET_INST(float)
 PRK_SET_INST(double)

@@ -80,6 +80,7 @@ def _set_args(graphs):
     ([([0, 1, 1], [1]), ([0, 1, 1], [2])], 0, "out of [0, n)"),   # an edge into another graph
     ([([0, 1, 1], [1])], 0x2, "unknown upload flag"),
     ([([0, 1, 1], [1])], 0x1, "unknown upload flag"),
+    ([([0, 1, 1], [1])], 0x20000, "unknown upload flag"),    # PR_PEEL is not for sets
 ])
 def test_set_upload_rejects_invalid_host_input(graphs, flags, msg):
     import paper_2302_03245_amd as pr

@@ -3,6 +3,9 @@
 Every graph's result is checked against the FP64 oracle (power method to
 1e-13) within the certified tolerance, against the same graph solved alone
 through pr_solve_ifp2, and for the closed forms against the exact vector.
+Synchronous set sweeps follow each graph's solo synchronous trajectory (same
+sweep count up to one); ordered set sweeps (vertex groups per graph, the
+default) are checked against the oracle and need no more sweeps in total.
 Tolerances: L1 <= 1e-9 with FP64 residuals, L1 <= 1e-6 with FP32 residuals.
 """
 import numpy as np
@@ -63,7 +66,8 @@ def _oracle(g, c, key):
 def test_set_matches_oracle_and_alone(pr, residual, tol, mode):
     graphs, cs = _mixed_graphs()
     _say(f"set of {len(graphs)} graphs, n = {sum(g.n for g in graphs)}, residual {residual}, mode {mode}")
-    gs = pr.upload_set([(g.row_ptr, g.col) for g in graphs])
+    gs = pr.upload_set([(g.row_ptr, g.col) for g in graphs], groups=1)
+    assert gs.info()["groups"] == 1
     pi, sts = pr.set_ifp2(gs, c=cs, l1_tol=tol, residual=residual, mode=mode)
     for i, (g, c, x, st) in enumerate(zip(graphs, cs, gs.split(pi), sts)):
         assert st["status"] == 0, (i, st)
@@ -76,6 +80,30 @@ def test_set_matches_oracle_and_alone(pr, residual, tol, mode):
         assert l1(x, alone) <= 2 * tol, (i, l1(x, alone))
         # same Jacobi trajectory per graph: only the rounding order differs
         assert abs(st["sweeps"] - sa["sweeps"]) <= 1, (i, st["sweeps"], sa["sweeps"])
+
+
+@pytest.mark.parametrize("residual,tol,groups", [("fp64", 1e-9, 0), ("fp32", 1e-6, 0), ("fp64", 1e-9, 3),
+                                                 ("fp32", 1e-6, 15)])
+def test_ordered_set_sweeps(pr, residual, tol, groups):
+    """Ordered sweeps over per-graph vertex groups: every graph against the oracle and
+    against its solo solve; no more sweeps in total than synchronous set sweeps."""
+    graphs, cs = _mixed_graphs()
+    gs = pr.upload_set([(g.row_ptr, g.col) for g in graphs], groups=groups)
+    assert gs.info()["groups"] == (groups or 4)
+    pi, sts = pr.set_ifp2(gs, c=cs, l1_tol=tol, residual=residual)
+    _, sync = pr.set_ifp2(gs, c=cs, l1_tol=tol, residual=residual, jacobi=True)
+    tot_o, tot_s = sum(st["sweeps"] for st in sts), sum(st["sweeps"] for st in sync)
+    _say(f"groups {groups or 4}: sweeps ordered {tot_o} synchronous {tot_s}")
+    assert tot_o <= tot_s
+    for i, (g, c, x, st) in enumerate(zip(graphs, cs, gs.split(pi), sts)):
+        assert st["status"] == 0 and st["l1_bound"] <= tol, (i, st)
+        assert abs(x.sum() - 1.0) <= 1e-12, i
+        ref = _oracle(g, c, (i, c))
+        assert l1(x, ref) <= tol, (i, g.n, c, l1(x, ref))
+        if residual == "fp64":  # the bound holds in exact arithmetic; FP32 weights round at ~1e-8
+            assert st["l1_bound"] >= l1(x, ref) - 1e-12, i
+        alone, _ = pr.ifp2(pr.upload(g.row_ptr, g.col, groups=groups or 4), c=c, l1_tol=tol, residual=residual)
+        assert l1(x, alone) <= 2 * tol, (i, l1(x, alone))
 
 
 def test_set_closed_forms_exact(pr):
@@ -120,7 +148,7 @@ def test_set_xi_rule_and_device_output(pr):
     graphs = graphs[4:12]
     gs = pr.upload_set([(g.row_ptr, g.col) for g in graphs])
     out = torch.empty(gs.n, dtype=torch.float64, device="cuda")
-    pi, sts = pr.set_ifp2(gs, c=0.85, xi=1e-11, residual="fp64", out=out)
+    pi, sts = pr.set_ifp2(gs, c=0.85, xi=1e-11, residual="fp64", out=out, jacobi=True)
     got = gs.split(out.cpu().numpy())
     for g, x, st in zip(graphs, got, sts):
         dg = pr.upload(g.row_ptr, g.col)
