@@ -355,6 +355,11 @@ def run_set(pr, prgen, args):
     n_tot, m_tot = sum(g.n for g in graphs), sum(g.m for g in graphs)
     log(f"[bench] set: {len(graphs)} graphs, n {n_tot}, m {m_tot}, generated in {time.perf_counter() - t0:.1f}s")
     gs = pr.upload_set([(g.row_ptr, g.col) for g in graphs])
+    tuning = None
+    if not args.no_tune:
+        # one-time per set, like the upload: tile size and ordered / synchronous sweeps
+        tuning = pr.set_tune(gs, c=cs, l1_tol=args.tol, residual="fp32", reps=2)
+        log(f"[bench] set tuned in {tuning['seconds']:.2f}s: chosen {tuning['chosen']}")
     info = gs.info()
     out = torch.empty(gs.n, dtype=torch.float64, device="cuda")
     pr.set_ifp2(gs, c=cs, l1_tol=args.tol, residual="fp32", out=out)
@@ -367,8 +372,11 @@ def run_set(pr, prgen, args):
     t_set = (time.perf_counter() - t0) / reps
     ok_set = all(st["l1_bound"] <= args.tol and st["status"] == 0 for st in sts)
     sums = torch.stack([x.sum() for x in gs.split(out)]).cpu().numpy()
-    # one at a time: each graph resident on its own, solved back to back
+    # one at a time: each graph resident on its own (tuned on its own too), solved back to back
     dgs = [pr.upload(g.row_ptr, g.col) for g in graphs]
+    if not args.no_tune:
+        for dg, c in zip(dgs, cs):
+            pr.tune(dg, c=c, l1_tol=args.tol, residual="fp32", reps=1)
     outs = gs.split(out)
     for dg, c, o in zip(dgs[:4], cs, outs):
         pr.ifp2(dg, c=c, l1_tol=args.tol, residual="fp32", out=o)
@@ -387,7 +395,10 @@ def run_set(pr, prgen, args):
            "set_over_one_at_a_time": t_one / t_set, "all_certified": bool(ok_set and ok_one),
            "max_sum_error": float(np.abs(sums - 1.0).max()),
            "sweeps_max": max(st["sweeps"] for st in sts), "sweeps_min": min(st["sweeps"] for st in sts),
-           "upload_s": info["seconds_upload"], "device_bytes": info["device_bytes"]}
+           "upload_s": info["seconds_upload"], "device_bytes": info["device_bytes"],
+           "schedule": {"groups": info["groups"], "ordered_sweeps": bool(info["ordered"]),
+                        "tile_items": info["tile_items"]},
+           "tuning": tuning}
     log(f"[bench] set: {res}")
     gs.free()
     return res

@@ -33,6 +33,8 @@ typedef struct {
     int64_t device_bytes;
     double seconds_upload;
     int64_t groups;             /* vertex groups of ordered sweeps per graph (1: none) */
+    int64_t tile_items;         /* rows + edges per sweep tile */
+    int64_t ordered;            /* 1 if set solves use ordered sweeps */
 } pr_set_info_t;
 
 /*
@@ -71,6 +73,17 @@ pr_status pr_set_info(const pr_graph_set *s, pr_set_info_t *out);
  * max_sweeps first (its entry of st says how far it got).
  */
 pr_status pr_set_solve_ifp2(const pr_graph_set *s, const double *c, const pr_opts *o, double *pi, pr_stats *st);
+
+/*
+ * Autotuner of the set's sweep schedule, as pr_graph_tune for one graph: times
+ * pr_set_solve_ifp2 with the damping factors c (or NULL) and options o for every
+ * tile size s in {2, 3, 4} with synchronous and, when the set has vertex groups,
+ * ordered sweeps, `reps` solves each after one warm-up (reps <= 0: 2), and keeps
+ * the fastest.  rep->sweeps holds the largest per-graph sweep count of each
+ * candidate.  Results do not change beyond rounding order.  No other call may use
+ * the set meanwhile.  rep may be NULL.  PR_EINVAL on bad options or forced modes.
+ */
+pr_status pr_set_tune(pr_graph_set *s, const double *c, const pr_opts *o, int32_t reps, pr_tune_report *rep);
 
 #ifdef __cplusplus
 }

@@ -32,7 +32,7 @@ EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_inf
             "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len",
             "pr_server_opts_default", "pr_server_create", "pr_server_add_graph", "pr_server_submit",
             "pr_server_wait", "pr_server_get_stats", "pr_server_destroy",
-            "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2", "pr_graph_tune",
+            "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2", "pr_set_tune", "pr_graph_tune",
             "pr_state_create", "pr_state_free", "pr_state_read", "pr_solve_ifp2_warm", "pr_state_update"]
 
 
@@ -78,7 +78,8 @@ class ServerStats(ctypes.Structure):
 class SetInfo(ctypes.Structure):
     _fields_ = [("k", ctypes.c_int64), ("n", ctypes.c_int64), ("m", ctypes.c_int64),
                 ("n_dangling", ctypes.c_int64), ("m_dangling", ctypes.c_int64),
-                ("device_bytes", ctypes.c_int64), ("seconds_upload", ctypes.c_double), ("groups", ctypes.c_int64)]
+                ("device_bytes", ctypes.c_int64), ("seconds_upload", ctypes.c_double), ("groups", ctypes.c_int64),
+                ("tile_items", ctypes.c_int64), ("ordered", ctypes.c_int64)]
 
 
 class GraphInfo(ctypes.Structure):
@@ -161,6 +162,8 @@ def lib():
     L.pr_set_info.restype = ctypes.c_int
     L.pr_set_solve_ifp2.argtypes = [vp, vp, ctypes.POINTER(Opts), dp, ctypes.POINTER(Stats)]
     L.pr_set_solve_ifp2.restype = ctypes.c_int
+    L.pr_set_tune.argtypes = [vp, vp, ctypes.POINTER(Opts), i32, ctypes.POINTER(TuneReport)]
+    L.pr_set_tune.restype = ctypes.c_int
     L.pr_server_opts_default.argtypes = [ctypes.POINTER(ServerOpts)]
     L.pr_server_opts_default.restype = None
     L.pr_server_create.argtypes = [ctypes.POINTER(ServerOpts), ctypes.POINTER(vp)]
@@ -438,6 +441,26 @@ def set_ifp2(gs: GraphSet, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_s
     if status < 0:
         raise _err(status)
     return out, [dict(st[i].as_dict(), status=status) for i in range(gs.k)]
+
+
+def set_tune(gs: GraphSet, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", reps=2) -> dict:
+    """Autotune the sweep schedule of set solves (pr_set_tune); returns the report."""
+    o = _opts(0.85, xi, l1_tol, residual, 0, None, False, None, False)
+    cs = None
+    if np.ndim(c) == 0:
+        o.c = float(c)
+    else:
+        cs = np.ascontiguousarray(c, dtype=np.float64)
+        if cs.shape != (gs.k,):
+            raise ValueError("c must be a scalar or have one entry per graph")
+    r = TuneReport()
+    st = lib().pr_set_tune(gs.handle, cs.ctypes.data if cs is not None else None, ctypes.byref(o), int(reps),
+                           ctypes.byref(r))
+    if st != PR_OK:
+        raise _err(st)
+    cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "ms": r.ms[i], "sweeps": r.sweeps[i]}
+             for i in range(r.candidates)]
+    return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds}
 
 
 def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, power=False, jacobi=False):

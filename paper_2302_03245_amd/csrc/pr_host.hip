@@ -1265,6 +1265,7 @@ struct pr_graph_set {
     // N -> N out-edges (as for one graph); group q of all graphs is a position range
     // [0, glen[q]) cut by d_goff[q] (k + 1) with vertex = position + d_gbase[q][graph]
     int32_t ngr = 1;
+    bool prefer_ordered = true;            // set by the autotuner
     std::vector<int32_t> glen;
     std::vector<int32_t *> d_goff, d_gbase;
     std::vector<MPPlan> grp_pull;          // gather plan of each group's in-edges (owned by the union)
@@ -1518,7 +1519,7 @@ pr_status solve_set_t(const pr_graph_set &S, const double *cg, const pr_opts &o,
     bool stopped = nN == 0;
     // ordered sweeps over the vertex groups while the frontier is dense (every vertex
     // starts active), as for one graph
-    const bool ordered_ok = S.ngr > 1 && force == 0 && !(o.flags & PR_JACOBI);
+    const bool ordered_ok = S.ngr > 1 && S.prefer_ordered && force == 0 && !(o.flags & PR_JACOBI);
     bool ordered = ordered_ok;
     if (nN > 0) {
         int batch = l1 ? 8 : 16;
@@ -1597,30 +1598,112 @@ pr_status solve_set_t(const pr_graph_set &S, const double *cg, const pr_opts &o,
 
 // Rebuild every single-vector merge-path plan of the graph for tiles of kBlock * tile_k
 // items (the batched kernels keep their own plans).
-pr_status replan(Graph &G, int32_t tile_k, hipStream_t s) {
-    auto one = [&](MPPlan &p) -> hipError_t {
-        const int32_t ipb = kBlock * tile_k;
-        if (p.ipb == ipb) return hipSuccess;
-        const int32_t blocks = (int32_t)(((int64_t)p.items + ipb - 1) / ipb);
-        uint2 *np = nullptr;
-        hipError_t e = hipMalloc((void **)&np, sizeof(uint2) * ((size_t)std::max(blocks, 0) + 1));
+pr_status replan(Graph &G, int32_t tile_k, hipStream_t s);
+hipError_t replan_plan(Graph &G, MPPlan &p, int32_t tile_k, hipStream_t s);
+
+// A graph set's plans for a new tile size, with the tile-to-graph tables that follow them.
+pr_status set_replan(pr_graph_set &S, int32_t tile_k) {
+    Graph &G = S.u->g;
+    hipStream_t s = G.stream;
+    pr_status ps = replan(G, tile_k, s);
+    if (ps != PR_OK) return ps;
+    for (MPPlan &p : S.grp_pull) HIPCHK(replan_plan(G, p, tile_k, s));
+    auto retable = [&](const MPPlan &p, uint2 *&dst) -> hipError_t {
+        if (dst) (void)hipFree(dst);
+        dst = nullptr;
+        hipError_t e = hipMalloc((void **)&dst, sizeof(uint2) * (size_t)std::max<int32_t>(p.blocks, 1));
         if (e != hipSuccess) return e;
-        auto it = std::find(G.allocs.begin(), G.allocs.end(), (void *)p.plan);
-        if (it != G.allocs.end()) {
-            G.allocs.erase(it);
-            G.device_bytes -= (int64_t)sizeof(uint2) * ((int64_t)p.blocks + 1);
-        }
-        (void)hipFree(p.plan);
-        G.allocs.push_back((void *)np);
-        G.device_bytes += (int64_t)sizeof(uint2) * ((int64_t)blocks + 1);
-        p.plan = np;
-        p.ipb = ipb;
-        if (p.R == 0) {
-            p.blocks = 0;
-            return hipSuccess;
-        }
-        return launch_plan(p, s);
+        return launch_set_tile_graphs(p, S.d_offN, S.k, dst, s);
     };
+    HIPCHK(retable(G.push_nn, S.d_tg_push));
+    for (size_t e = 0; e < G.epochs.size(); ++e) HIPCHK(retable(G.epochs[e].pull_nn, S.d_tg_pull[e]));
+    for (size_t q = 0; q < S.grp_pull.size(); ++q) HIPCHK(retable(S.grp_pull[q], S.d_tg_grp[q]));
+    HIPCHK(hipStreamSynchronize(s));
+    return PR_OK;
+}
+
+// The autotuner of one graph (tune_impl) for a graph set: every tile size with
+// synchronous and, when the set has vertex groups, ordered sweeps; the set keeps the
+// fastest schedule.
+pr_status set_tune_impl(pr_graph_set &S, const double *cg, const pr_opts &o, int32_t reps, pr_tune_report *rep) {
+    Graph &G = S.u->g;
+    const double t_start = (double)clock_now_ns() * 1e-9;
+    if (reps <= 0) reps = 2;
+    pr_tune_report r;
+    memset(&r, 0, sizeof(r));
+    double *out = nullptr;
+    HIPCHK(hipMalloc((void **)&out, sizeof(double) * (size_t)G.n));
+    struct Free {
+        double *p;
+        ~Free() { (void)hipFree(p); }
+    } fr{out};
+    pr_opts op = o;
+    op.flags = (o.flags & ~(PR_OUT_DEVICE | PR_JACOBI)) | PR_OUT_DEVICE;
+    std::vector<pr_stats> st((size_t)S.k);
+    const bool can_order = S.ngr > 1;
+    double best = INFINITY;
+    int best_i = 0;
+    for (int32_t shift = 2; shift <= 4; ++shift) {
+        pr_status ps = set_replan(S, 1 << shift);
+        if (ps != PR_OK) return ps;
+        for (int ord = 0; ord <= (can_order ? 1 : 0); ++ord) {
+            S.prefer_ordered = ord == 1;
+            double ms = INFINITY;
+            int32_t sweeps = 0;
+            for (int32_t q = 0; q <= reps; ++q) {
+                ps = op.residual == PR_RES_FP32 ? solve_set_t<float>(S, cg, op, out, st.data())
+                                                : solve_set_t<double>(S, cg, op, out, st.data());
+                if (ps < 0) return ps;
+                if (q > 0) ms = std::min(ms, st[0].seconds_solve * 1e3);
+                sweeps = 0;
+                for (const pr_stats &x : st) sweeps = std::max(sweeps, x.sweeps);
+            }
+            const int i = r.candidates++;
+            r.tile_shift[i] = shift;
+            r.ordered[i] = ord;
+            r.ms[i] = ms;
+            r.sweeps[i] = sweeps;
+            if (ms < best) {
+                best = ms;
+                best_i = i;
+            }
+        }
+    }
+    r.chosen = best_i;
+    pr_status ps = set_replan(S, 1 << r.tile_shift[best_i]);
+    if (ps != PR_OK) return ps;
+    S.prefer_ordered = r.ordered[best_i] == 1;
+    r.seconds = (double)clock_now_ns() * 1e-9 - t_start;
+    if (rep) *rep = r;
+    return PR_OK;
+}
+// One plan of G (its split-point array owned by G) rebuilt for tiles of kBlock * tile_k items.
+hipError_t replan_plan(Graph &G, MPPlan &p, int32_t tile_k, hipStream_t s) {
+    const int32_t ipb = kBlock * tile_k;
+    if (p.ipb == ipb) return hipSuccess;
+    const int32_t blocks = (int32_t)(((int64_t)p.items + ipb - 1) / ipb);
+    uint2 *np = nullptr;
+    hipError_t e = hipMalloc((void **)&np, sizeof(uint2) * ((size_t)std::max(blocks, 0) + 1));
+    if (e != hipSuccess) return e;
+    auto it = std::find(G.allocs.begin(), G.allocs.end(), (void *)p.plan);
+    if (it != G.allocs.end()) {
+        G.allocs.erase(it);
+        G.device_bytes -= (int64_t)sizeof(uint2) * ((int64_t)p.blocks + 1);
+    }
+    (void)hipFree(p.plan);
+    G.allocs.push_back((void *)np);
+    G.device_bytes += (int64_t)sizeof(uint2) * ((int64_t)blocks + 1);
+    p.plan = np;
+    p.ipb = ipb;
+    if (p.R == 0) {
+        p.blocks = 0;
+        return hipSuccess;
+    }
+    return launch_plan(p, s);
+}
+
+pr_status replan(Graph &G, int32_t tile_k, hipStream_t s) {
+    auto one = [&](MPPlan &p) -> hipError_t { return replan_plan(G, p, tile_k, s); };
     HIPCHK(hipStreamSynchronize(s));
     HIPCHK(one(G.push_nn));
     HIPCHK(one(G.push_nd));
@@ -1980,7 +2063,28 @@ pr_status pr_set_info(const pr_graph_set *s, pr_set_info_t *out) {
     out->device_bytes = G.device_bytes + (int64_t)(2 * sizeof(int32_t) * ((size_t)s->k + 1));
     out->seconds_upload = G.seconds_upload;
     out->groups = s->ngr;
+    out->tile_items = (int64_t)kBlock * G.tile_k;
+    out->ordered = s->ngr > 1 && s->prefer_ordered ? 1 : 0;
     return PR_OK;
+}
+
+pr_status pr_set_tune(pr_graph_set *s, const double *c, const pr_opts *o, int32_t reps, pr_tune_report *rep) {
+    g_err.clear();
+    if (!s) return fail(PR_EINVAL, "graph set is NULL");
+    pr_opts op;
+    opts_or_default(o, &op);
+    if (c) op.c = 0.5;  // per-graph factors are checked by the solve
+    pr_status ps = check_opts(op, false);
+    if (ps != PR_OK) return ps;
+    if (op.flags & (PR_FORCE_PUSH | PR_FORCE_PULL | PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE))
+        return fail(PR_EINVAL, "tuning times the automatic schedule of set solves");
+    ps = enter(s->u);
+    if (ps != PR_OK) return ps;
+    try {
+        return set_tune_impl(*s, c, op, reps, rep);
+    } catch (const std::bad_alloc &) {
+        return fail(PR_ENOMEM, "host allocation");
+    }
 }
 
 pr_status pr_set_solve_ifp2(const pr_graph_set *s, const double *c, const pr_opts *o, double *pi, pr_stats *st) {

@@ -169,3 +169,28 @@ def test_set_max_sweeps_and_rejections(pr):
         pr.set_ifp2(gs, c=[1.5] * gs.k, l1_tol=1e-6)
     with pytest.raises(ValueError):
         pr.set_ifp2(gs, c=[0.85] * (gs.k + 1), l1_tol=1e-6)
+
+
+def test_set_tune_keeps_results(pr):
+    """The set autotuner times every tile size with synchronous and ordered sweeps and
+    keeps the fastest; results stay within the tolerance afterwards."""
+    graphs, cs = _mixed_graphs()
+    gs = pr.upload_set([(g.row_ptr, g.col) for g in graphs])
+    rep = pr.set_tune(gs, c=cs, l1_tol=1e-6, residual="fp32", reps=1)
+    _say(f"set tune: {rep}")
+    assert len(rep["candidates"]) == 6
+    assert {(x["tile_shift"], x["ordered"]) for x in rep["candidates"]} == {(s, o) for s in (2, 3, 4)
+                                                                           for o in (False, True)}
+    info = gs.info()
+    assert info["tile_items"] == 256 << rep["chosen"]["tile_shift"]
+    assert bool(info["ordered"]) == rep["chosen"]["ordered"]
+    for residual, tol in (("fp32", 1e-6), ("fp64", 1e-9)):
+        pi, sts = pr.set_ifp2(gs, c=cs, l1_tol=tol, residual=residual)
+        for i, (g, c, x, st) in enumerate(zip(graphs, cs, gs.split(pi), sts)):
+            assert st["status"] == 0 and st["l1_bound"] <= tol
+            assert l1(x, _oracle(g, c, (i, c))) <= tol, i
+    with pytest.raises(pr.PRError, match="automatic schedule"):
+        o = pr._opts(0.85, 1e-12, 1e-6, "fp32", 0, None, False, "push", False)
+        r = pr.TuneReport()
+        st = pr.lib().pr_set_tune(gs.handle, None, o, 1, r)
+        raise pr._err(st)
