@@ -138,6 +138,9 @@ def main():
     def run_ifp2(profile=False):
         return pr.ifp2(dg, c=c, l1_tol=args.tol, residual="fp32", out=out, mode=args.mode, profile=profile)
 
+    def run_ifp1(profile=False):
+        return pr.ifp1(dg, c=c, l1_tol=args.tol, residual="fp32", out=out, mode=args.mode, profile=profile)
+
     def run_power(profile=False):
         return pr.power(dg, c=c, l1_tol=args.tol, residual="fp32", out=out, profile=profile)
 
@@ -155,10 +158,13 @@ def main():
     log("[bench] IFP2 timed steps")
     t_ifp2, st_ifp2 = timed(run_ifp2)
     log(f"[bench] IFP2 {t_ifp2 * 1e3:.3f} ms/step, sweeps {st_ifp2[-1]['sweeps']}, bound {st_ifp2[-1]['l1_bound']:.3e}")
+    log("[bench] IFP1 timed steps")
+    t_ifp1, st_ifp1 = timed(run_ifp1)
+    log(f"[bench] IFP1 {t_ifp1 * 1e3:.3f} ms/step, sweeps {st_ifp1[-1]['sweeps']}, bound {st_ifp1[-1]['l1_bound']:.3e}")
     log("[bench] power method timed steps")
     t_pow, st_pow = timed(run_power)
     log(f"[bench] power {t_pow * 1e3:.3f} ms/step, iterations {st_pow[-1]['sweeps']}")
-    assert all(s["status"] == 0 and s["l1_bound"] <= args.tol for s in st_ifp2 + st_pow)
+    assert all(s["status"] == 0 and s["l1_bound"] <= args.tol for s in st_ifp2 + st_ifp1 + st_pow)
 
     # dominant kernel of the IFP2 step: the scatter (push) or gather (pull) kernel
     prof = st_ifp2[-1:]
@@ -206,6 +212,10 @@ def main():
                  "edges_processed": last["edges_processed"], "edges_traversed": last["edges_traversed"],
                  "gteps_processed": last["edges_processed"] / t_ifp2 / 1e9, "l1_bound": last["l1_bound"],
                  "preprocess_ms": info["seconds_split"] * 1e3},
+        "ifp1": {"ms": t_ifp1 * 1e3, "sweeps": st_ifp1[-1]["sweeps"], "pull_sweeps": st_ifp1[-1]["pull_sweeps"],
+                 "edges_processed": st_ifp1[-1]["edges_processed"], "gteps_normalised": g.m / t_ifp1 / 1e9,
+                 "gteps_processed": st_ifp1[-1]["edges_processed"] / t_ifp1 / 1e9,
+                 "l1_bound": st_ifp1[-1]["l1_bound"]},
         "power": {"ms": t_pow * 1e3, "iterations": st_pow[-1]["sweeps"], "gteps_normalised": g.m / t_pow / 1e9,
                   "gteps_processed": st_pow[-1]["edges_processed"] / t_pow / 1e9,
                   "l1_bound": st_pow[-1]["l1_bound"]},
