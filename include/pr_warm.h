@@ -41,8 +41,8 @@ pr_status pr_state_free(pr_state *s);
  * reserve and residual in it.  g must have the state's n; the first solve fixes
  * the damping factor o->c of the state, later solves and updates must use the
  * same one.  Options as pr_solve_ifp2 except p (taken from the state) and
- * PR_IFP2_LITERAL (rejected); graphs uploaded with PR_PEEL are rejected.  The stop rule and pi / st as pr_solve_ifp2; the
- * bound covers negative residuals.
+ * PR_IFP2_LITERAL (rejected); graphs uploaded with PR_PEEL are rejected.  The
+ * stop rule and pi / st as pr_solve_ifp2; the bound covers negative residuals.
  */
 pr_status pr_solve_ifp2_warm(const pr_graph *g, const pr_opts *o, pr_state *s, double *pi, pr_stats *st);
 
