@@ -91,7 +91,7 @@ typedef enum {
 #define PR_FORCE_PUSH 0x8u   /* every sweep scatters along out-edges with atomic adds */
 #define PR_FORCE_PULL 0x10u  /* every sweep gathers along in-edges (no atomics) */
 #define PR_PROFILE 0x20u     /* time each sweep kernel with HIP events (stats->kernel_*) */
-#define PR_JACOBI 0x40u      /* IFP2 global solves: synchronous sweeps even where ordered sweeps apply */
+#define PR_JACOBI 0x40u      /* IFP1 / IFP2: synchronous sweeps even where ordered sweeps apply */
 
 typedef struct {
     double c;           /* damping factor, 0 < c < 1 (section 2.1) */
@@ -217,7 +217,9 @@ pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_rep
  *   pi   double[n] output (host, or device with PR_OUT_DEVICE)
  *   st   optional statistics
  * One GPU sweep processes every vertex above the threshold once (a
- * synchronous version of one scan of all calculation threads, section 3.3.1).
+ * synchronous version of one scan of all calculation threads, section 3.3.1);
+ * on a graph with vertex groups, sweeps over a dense frontier are ordered as
+ * pr_solve_ifp2 describes, each group's pushes gathered into every vertex.
  * Errors: PR_EINVAL (bad graph handle, options, p, a graph uploaded with PR_PEEL
  * for IFP1), PR_ENOMEM, PR_EDEVICE;
  * PR_ENOCONV when max_sweeps ends the iteration.

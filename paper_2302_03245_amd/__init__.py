@@ -520,9 +520,10 @@ def _solve(fn, g, p, o, out):
 
 
 def ifp1(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
-         stream=None, mode=None, profile=False):
-    """IFP1 (Algorithm 2).  `l1_tol` switches to the certified-L1 stop rule."""
-    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, profile)
+         stream=None, mode=None, profile=False, jacobi=False):
+    """IFP1 (Algorithm 2).  `l1_tol` switches to the certified-L1 stop rule; `jacobi`
+    keeps synchronous sweeps on a graph with vertex groups."""
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, profile, jacobi=jacobi)
     return _solve(lib().pr_solve_ifp1, g, p, o, out)
 
 

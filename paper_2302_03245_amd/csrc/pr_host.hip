@@ -541,30 +541,31 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
         }
         G.grp.push_back(G.nN);
         uint32_t *d_gc;
-        HIPCHK(tmp.alloc(&d_gc, (size_t)G.nN + 1));
+        HIPCHK(tmp.alloc(&d_gc, (size_t)n + 1));
         for (size_t e = 0; e < G.epochs.size(); ++e) {
-            std::vector<MPPlan> plans;
-            std::vector<int64_t> edges;
+            std::vector<MPPlan> plans, plans_all;
             for (size_t q = 0; q + 1 < G.grp.size(); ++q) {
                 uint32_t *gp;
                 int32_t *gs;
-                HIPCHK(galloc(&gp, (size_t)G.nN + 1));
-                HIPCHK(launch_live_count(G.nN, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
+                HIPCHK(galloc(&gp, (size_t)n + 1));
+                HIPCHK(launch_live_count((int32_t)n, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
                                          G.grp[q + 1], d_gc, s));
-                HIPCHK(launch_scan_u32(d_gc, gp, G.nN, d_scan, s));
-                uint32_t ge = 0;
-                HIPCHK(hipMemcpyAsync(&ge, gp + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+                HIPCHK(launch_scan_u32(d_gc, gp, n, d_scan, s));
+                uint32_t ge[2] = {0, 0};  // edges into the non-dangling rows, into all rows
+                HIPCHK(hipMemcpyAsync(&ge[0], gp + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+                HIPCHK(hipMemcpyAsync(&ge[1], gp + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
                 HIPCHK(hipStreamSynchronize(s));
-                HIPCHK(galloc(&gs, (size_t)ge));
-                HIPCHK(launch_live_fill(G.nN, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
+                HIPCHK(galloc(&gs, (size_t)ge[1]));
+                HIPCHK(launch_live_fill((int32_t)n, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
                                         G.grp[q + 1], gp, gs, s));
-                MPPlan pl;
-                HIPCHK(make_plan(pl, gp, gs, G.nN, ge));
+                MPPlan pl, pla;
+                HIPCHK(make_plan(pl, gp, gs, G.nN, ge[0]));
+                HIPCHK(make_plan(pla, gp, gs, (int32_t)n, ge[1]));
                 plans.push_back(pl);
-                edges.push_back(ge);
+                plans_all.push_back(pla);
             }
             G.grp_pull.push_back(plans);
-            G.grp_edges.push_back(edges);
+            G.grp_pull_all.push_back(plans_all);
         }
     }
 
@@ -822,10 +823,11 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     };
     const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
     const int check_mode = force == 0;
-    // ordered sweeps (groups built at upload): from the start for global IFP2, where every
-    // vertex starts active; otherwise from the first batch after a sweep that gathered
+    // ordered sweeps (groups built at upload): from the start for global solves, where every
+    // vertex starts active; otherwise from the first batch after a sweep that gathered.  IFP2
+    // gathers into the non-dangling rows, IFP1 into all rows (its pushes reach dangling vertices)
     const int ngr = (int)G.grp.size() - 1;
-    const bool ordered_ok = ifp2 && ngr > 1 && ngr <= kMaxGroups && force == 0 && !(o.flags & PR_JACOBI) &&
+    const bool ordered_ok = ngr > 1 && ngr <= kMaxGroups && force == 0 && !(o.flags & PR_JACOBI) &&
                             !G.grp_pull.empty() && G.prefer_ordered;
     bool ordered = ordered_ok && a.uniform && !warm;
     GroupBlocks gb{};
@@ -853,8 +855,9 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                     unsigned long long sweep_edges = 0;
                     for (int q = 0; q < ngr; ++q) {
                         HIPCHK(launch_reserve_range<T>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg, G.rp_nn, c,
-                                                       xi, gb.nb[q], part + (size_t)5 * kGroupBlocks * q, s));
-                        const MPPlan &pl = G.grp_pull[e][q];
+                                                       xi, ifp2 ? 1 : 0, gb.nb[q],
+                                                       part + (size_t)5 * kGroupBlocks * q, s));
+                        const MPPlan &pl = ifp2 ? G.grp_pull[e][q] : G.grp_pull_all[e][q];
                         sweep_edges += (unsigned long long)pl.edges();
                         const KernelEvents ev =
                             timer.next(t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT));
@@ -1720,6 +1723,8 @@ pr_status replan(Graph &G, int32_t tile_k, hipStream_t s) {
         }
     }
     for (auto &v : G.grp_pull)
+        for (auto &p : v) HIPCHK(one(p));
+    for (auto &v : G.grp_pull_all)
         for (auto &p : v) HIPCHK(one(p));
     for (auto &p : G.lvl_pull) HIPCHK(one(p));
     HIPCHK(hipStreamSynchronize(s));

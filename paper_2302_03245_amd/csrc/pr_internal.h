@@ -175,11 +175,13 @@ struct Graph {
     std::vector<Epoch> epochs;    // epochs[0] aliases the full in-edge lists
     int32_t tile_k = kMPK;        // merge-path items per thread of the sweep tiles
     // ordered sweeps: non-dangling sources split into groups of equal N -> N out-edges
-    // (group g = [grp[g], grp[g + 1])), and per epoch the gather plan of each group's in-edges
+    // (group g = [grp[g], grp[g + 1])), and per epoch the gather plans of each group's
+    // in-edges: over the non-dangling rows (IFP2) and over all rows (IFP1), one list
+    // serving both since the non-dangling rows come first
     std::vector<int32_t> grp;
-    bool prefer_ordered = true;                 // set by the autotuner
-    std::vector<std::vector<MPPlan>> grp_pull;  // [epoch][group]
-    std::vector<std::vector<int64_t>> grp_edges;
+    bool prefer_ordered = true;                     // set by the autotuner
+    std::vector<std::vector<MPPlan>> grp_pull;      // [epoch][group], rows [0, nN)
+    std::vector<std::vector<MPPlan>> grp_pull_all;  // [epoch][group], rows [0, n)
     int64_t device_bytes = 0;
     double seconds_upload = 0, seconds_split = 0;
     hipStream_t stream = nullptr;
@@ -259,7 +261,7 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
 // partials (5 * nbg doubles at part); after all groups, k_sum_h + k_decide_gs
 template <typename T>
 hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
-                                const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int nbg,
+                                const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2, int nbg,
                                 double *part, hipStream_t s);
 template <typename T>
 hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, const GroupBlocks &gb,

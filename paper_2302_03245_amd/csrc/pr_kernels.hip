@@ -986,10 +986,10 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
 
 template <typename T>
 hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
-                                const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int nbg,
+                                const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2, int nbg,
                                 double *part, hipStream_t s) {
     hipLaunchKernelGGL(k_reserve<T>, dim3(nbg), dim3(kBlock), 0, s, t, (const Ctl *)ctl, lo, hi, h, w, pibar, deg,
-                       rp_nn, c, (T)xi, 1, part);
+                       rp_nn, c, (T)xi, ifp2, part);
     return hipGetLastError();
 }
 
@@ -1122,11 +1122,11 @@ template hipError_t launch_reserve<double>(int, Ctl *, Trace *, int32_t, double 
                                            const int32_t *, const uint32_t *, double, double, int, int, double,
                                            unsigned long long, int, unsigned long long, double *, hipStream_t);
 template hipError_t launch_reserve_range<float>(int, Ctl *, int32_t, int32_t, float *, float *, double *,
-                                                const int32_t *, const uint32_t *, double, double, int, double *,
-                                                hipStream_t);
+                                                const int32_t *, const uint32_t *, double, double, int, int,
+                                                double *, hipStream_t);
 template hipError_t launch_reserve_range<double>(int, Ctl *, int32_t, int32_t, double *, double *, double *,
-                                                 const int32_t *, const uint32_t *, double, double, int, double *,
-                                                 hipStream_t);
+                                                 const int32_t *, const uint32_t *, double, double, int, int,
+                                                 double *, hipStream_t);
 template hipError_t launch_decide_gs<float>(int, Ctl *, Trace *, int32_t, const float *, int, const GroupBlocks &,
                                             const double *, double *, double, int, double, unsigned long long,
                                             unsigned long long, hipStream_t);

@@ -390,6 +390,18 @@ def test_ordered_sweeps(pr, groups):
                 assert so["sweeps"] <= sj["sweeps"], (so["sweeps"], sj["sweeps"])
         pl, sl = pr.ifp2(dg, c=C, xi=1e-13, literal=True)
         assert l1(pl, ref) <= 1e-9 and sl["l1_bound"] >= l1(pl, ref)
+        # IFP1 orders its sweeps the same way, gathering into every vertex
+        p1, s1 = pr.ifp1(dg, c=C, xi=1e-13)
+        assert s1["status"] == 0 and l1(p1, ref) <= 1e-9
+        for residual, tol in (("fp32", 1e-6), ("fp64", 1e-10)):
+            po, so = pr.ifp1(dg, c=C, l1_tol=tol, residual=residual)
+            pj, sj = pr.ifp1(dg, c=C, l1_tol=tol, residual=residual, jacobi=True)
+            assert so["status"] == 0 and so["l1_bound"] <= tol and sj["l1_bound"] <= tol
+            assert l1(po, ref) <= tol and l1(pj, ref) <= tol
+            if groups == 1:
+                assert so["sweeps"] == sj["sweeps"]
+            else:
+                assert so["sweeps"] <= sj["sweeps"], (so["sweeps"], sj["sweeps"])
 
 
 def test_autotune_keeps_results(pr):
