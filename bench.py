@@ -15,6 +15,7 @@ import argparse
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -28,15 +29,22 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_sha(kernel: str = "pull"):
-    """Hash of the source the counters depend on: the kernel's own text in
-    pr_kernels.hip (template line through its closing brace) and the device helpers."""
+def kernel_source_sha(kernel: str = "pull", kernels_src=None, device_src=None):
+    """Hash of the code the counters depend on: the kernel's own text in
+    pr_kernels.hip (template line through its closing brace) and the device helpers,
+    with comments and blank lines removed (a comment edit keeps the counters valid)."""
     csrc = os.path.join(ROOT, "paper_2302_03245_amd", "csrc")
-    src = open(os.path.join(csrc, "pr_kernels.hip")).read()
+    src = kernels_src if kernels_src is not None else open(os.path.join(csrc, "pr_kernels.hip")).read()
+    dev = device_src if device_src is not None else open(os.path.join(csrc, "pr_device.h")).read()
     start = src.index(f"void k_{kernel}(")
     start = src.rindex("template", 0, start)
     end = src.index("\n}\n", start) + 3
-    body = src[start:end] + open(os.path.join(csrc, "pr_device.h")).read()
+
+    def code(text):
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        lines = [re.sub(r"//.*$", "", ln).rstrip() for ln in text.split("\n")]
+        return "\n".join(ln for ln in lines if ln.strip())
+    body = code(src[start:end]) + "\n" + code(dev)
     return hashlib.sha1(body.encode()).hexdigest()[:12]
 
 

@@ -460,7 +460,14 @@ def test_ordered_sweeps_after_a_sparse_start(pr):
         assert s32[0]["l1_bound"] <= 1e-6 and l1(o32[0], ref) <= 1e-6
     p = prgen.random_p(g.n, seed=4, zero_frac=0.3)
     ref = oracle.power(g, C, p, tol=1e-13)[0]
-    pi, st = pr.ifp2(dg, p=p, c=C, l1_tol=1e-10)
-    pj, sj = pr.ifp2(dg, p=p, c=C, l1_tol=1e-10, jacobi=True)
-    assert st["l1_bound"] <= 1e-10 and l1(pi, ref) <= 1e-10 and l1(pj, ref) <= 1e-10
-    assert st["sweeps"] < sj["sweeps"], (st["sweeps"], sj["sweeps"])
+    for method in (pr.ifp2, pr.ifp1):
+        pi, st = method(dg, p=p, c=C, l1_tol=1e-10)
+        pj, sj = method(dg, p=p, c=C, l1_tol=1e-10, jacobi=True)
+        assert st["l1_bound"] <= 1e-10 and l1(pi, ref) <= 1e-10 and l1(pj, ref) <= 1e-10
+        assert st["sweeps"] < sj["sweeps"], (method.__name__, st["sweeps"], sj["sweeps"])
+    # IFP1 from a single source: the frontier starts with one vertex
+    e = np.zeros(g.n)
+    e[int(np.flatnonzero(deg > 0)[7])] = 1.0
+    ref = oracle.power(g, C, e, tol=1e-13)[0]
+    pi, st = pr.ifp1(dg, p=e, c=C, xi=1e-13)
+    assert st["status"] == 0 and l1(pi, ref) <= 1e-9
