@@ -99,6 +99,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true", help="skip the per-graph schedule autotuner")
     ap.add_argument("--no-warm", action="store_true", help="skip the dynamic-graph warm-start leg")
     ap.add_argument("--no-peel", action="store_true", help="skip the weak-dangling peeling leg")
+    ap.add_argument("--no-ifp1", action="store_true", help="skip the IFP1 leg")
     ap.add_argument("--set-count", type=int, default=256,
                     help="batched solves: independent graphs solved as one set (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -166,9 +167,12 @@ def main():
     log("[bench] IFP2 timed steps")
     t_ifp2, st_ifp2 = timed(run_ifp2)
     log(f"[bench] IFP2 {t_ifp2 * 1e3:.3f} ms/step, sweeps {st_ifp2[-1]['sweeps']}, bound {st_ifp2[-1]['l1_bound']:.3e}")
-    log("[bench] IFP1 timed steps")
-    t_ifp1, st_ifp1 = timed(run_ifp1)
-    log(f"[bench] IFP1 {t_ifp1 * 1e3:.3f} ms/step, sweeps {st_ifp1[-1]['sweeps']}, bound {st_ifp1[-1]['l1_bound']:.3e}")
+    t_ifp1, st_ifp1 = None, []
+    if not args.no_ifp1:
+        log("[bench] IFP1 timed steps")
+        t_ifp1, st_ifp1 = timed(run_ifp1)
+        log(f"[bench] IFP1 {t_ifp1 * 1e3:.3f} ms/step, sweeps {st_ifp1[-1]['sweeps']}, "
+            f"bound {st_ifp1[-1]['l1_bound']:.3e}")
     log("[bench] power method timed steps")
     t_pow, st_pow = timed(run_power)
     log(f"[bench] power {t_pow * 1e3:.3f} ms/step, iterations {st_pow[-1]['sweeps']}")
@@ -220,10 +224,10 @@ def main():
                  "edges_processed": last["edges_processed"], "edges_traversed": last["edges_traversed"],
                  "gteps_processed": last["edges_processed"] / t_ifp2 / 1e9, "l1_bound": last["l1_bound"],
                  "preprocess_ms": info["seconds_split"] * 1e3},
-        "ifp1": {"ms": t_ifp1 * 1e3, "sweeps": st_ifp1[-1]["sweeps"], "pull_sweeps": st_ifp1[-1]["pull_sweeps"],
-                 "edges_processed": st_ifp1[-1]["edges_processed"], "gteps_normalised": g.m / t_ifp1 / 1e9,
-                 "gteps_processed": st_ifp1[-1]["edges_processed"] / t_ifp1 / 1e9,
-                 "l1_bound": st_ifp1[-1]["l1_bound"]},
+        "ifp1": None if t_ifp1 is None else {
+            "ms": t_ifp1 * 1e3, "sweeps": st_ifp1[-1]["sweeps"], "pull_sweeps": st_ifp1[-1]["pull_sweeps"],
+            "edges_processed": st_ifp1[-1]["edges_processed"], "gteps_normalised": g.m / t_ifp1 / 1e9,
+            "gteps_processed": st_ifp1[-1]["edges_processed"] / t_ifp1 / 1e9, "l1_bound": st_ifp1[-1]["l1_bound"]},
         "power": {"ms": t_pow * 1e3, "iterations": st_pow[-1]["sweeps"], "gteps_normalised": g.m / t_pow / 1e9,
                   "gteps_processed": st_pow[-1]["edges_processed"] / t_pow / 1e9,
                   "l1_bound": st_pow[-1]["l1_bound"]},
