@@ -6,6 +6,10 @@
 * Layered DAG (2^23 vertices, 64 layers, 80M Zipf edges + 2 % back edges):
   the same FP32 configuration, and IFP2 on the graph uploaded with its weakly
   dangling vertices peeled (counts pinned to oracle.weak_dangling_levels).
+* The widening legs as bench.py runs them: the 256-graph set, 16 PPR columns and
+  the warm start on R-MAT scale 22, and the served workload's resident graphs
+  (R-MAT scale 24 and the 32-graph pool) behind one server; results checked by
+  the oracle where it finishes in seconds, else by the PageRank equation.
 Reference: the FP64 power-method oracle over the whole graph (tens of seconds
 of one host core).  Every GPU result is compared element by element (L1), by
 its top-1000 ranking (tie rule of conftest.topk_agree), and by the
@@ -127,3 +131,128 @@ def test_graph_set_256(pr_lib):
         ok, swaps, eps = topk_agree(ref, parts[i], min(1000, graphs[i].n))
         assert ok, (i, swaps, eps)
     gs.free()
+
+
+def _transition(g):
+    """P[j, u] = 1 / deg(u) for every edge u -> j (CSR), and the out-degrees."""
+    deg = np.diff(g.row_ptr)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    inv = np.zeros(g.n)
+    inv[deg > 0] = 1.0 / deg[deg > 0]
+    return sp.csr_matrix((inv[src], (g.col, src)), shape=(g.n, g.n)), deg
+
+
+def _ppr_residual(g, pi, c, s, Pd=None):
+    """||pi - c P pi - gamma e_s||_1, gamma = 1 - c + c d^T pi (single-source PPR, Eq. 1 with p = e_s);
+    s < 0: global PageRank, gamma e / n."""
+    P, deg = Pd if Pd is not None else _transition(g)
+    r = pi - c * (P @ pi)
+    gamma = 1 - c + c * pi[deg == 0].sum()
+    if s >= 0:
+        r[s] -= gamma
+    else:
+        r -= gamma / g.n
+    return float(np.abs(r).sum())
+
+
+@pytest.mark.timeout(600)
+def test_ppr_batch_scale22(pr_lib):
+    """The bench's PPR leg: 16 non-dangling sources of R-MAT scale 22 in one call (one
+    16-column batched solve, FP32, L1 <= 1e-6 per column).  Every column: certified bound,
+    unit sum and the PPR-equation residual; two columns against the FP64 oracle."""
+    pr = pr_lib
+    g = prgen.workload_rmat(scale=22, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=0)
+    deg = np.diff(g.row_ptr)
+    srcs = np.random.default_rng(7).choice(np.where(deg > 0)[0], 16, replace=False).astype(np.int32)
+    dg = pr.upload(g.row_ptr, g.col)
+    out, sts = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32")
+    Pd = _transition(g)
+    for r, s in enumerate(srcs):
+        assert sts[r]["status"] == 0 and sts[r]["l1_bound"] <= 1e-6, (r, sts[r])
+        assert abs(out[r].sum() - 1.0) <= 1e-10
+        res = _ppr_residual(g, out[r], C, int(s), Pd)
+        assert res <= (1 + C) * 1e-6, (r, res)
+    for r in (0, 9):
+        p = np.zeros(g.n)
+        p[srcs[r]] = 1.0
+        ref = oracle.power(g, C, p, tol=1e-12)[0]
+        d = l1(out[r], ref)
+        print(f"ppr column {r} (source {srcs[r]}): sweeps {sts[r]['sweeps']} L1 vs oracle {d:.3e}", flush=True)
+        assert d <= 1e-6
+    dg.free()
+
+
+@pytest.mark.timeout(600)
+def test_warm_start_scale22(pr_lib):
+    """The bench's warm-start leg: 0.1 % of the non-dangling vertices of R-MAT scale 22 get
+    new out-edge lists; the state carried over and resumed (FP32, L1 <= 1e-6) against a
+    cold solve of the changed graph and the PageRank-equation residual there."""
+    pr = pr_lib
+    g = prgen.workload_rmat(scale=22, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=0)
+    rng = np.random.default_rng(17)
+    deg = np.diff(g.row_ptr)
+    changed = np.sort(rng.choice(np.flatnonzero(deg > 0), len(np.flatnonzero(deg > 0)) // 1000,
+                                 replace=False)).astype(np.int32)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    keep = ~np.isin(src, changed)
+    new_dst = rng.integers(0, g.n, int(deg[changed].sum()))
+    new_src = np.repeat(changed.astype(np.int64), deg[changed])
+    g2 = prgen.from_edges(g.n, np.concatenate([src[keep], new_src]), np.concatenate([g.col[keep], new_dst]))
+    d1, d2 = pr.upload(g.row_ptr, g.col), pr.upload(g2.row_ptr, g2.col)
+    st = pr.State(g.n)
+    pr.ifp2_warm(d1, st, c=C, l1_tol=1e-6, residual="fp32")
+    st.update(d1, d2, changed)
+    pi, sw = pr.ifp2_warm(d2, st, c=C, l1_tol=1e-6, residual="fp32")
+    cold, sc = pr.ifp2(d2, c=C, l1_tol=1e-6, residual="fp32")
+    print(f"warm: {sw['sweeps']} sweeps, cold {sc['sweeps']}; L1 warm-cold {l1(pi, cold):.3e}", flush=True)
+    assert sw["status"] == 0 and sw["l1_bound"] <= 1e-6
+    assert l1(pi, cold) <= 2e-6
+    assert _eq_residual(g2, pi) <= 2e-6
+    assert sw["edges_processed"] < sc["edges_processed"]
+    st.free()
+    d1.free()
+    d2.free()
+
+
+@pytest.mark.timeout(900)
+def test_served_full_size(pr_lib):
+    """The served workload's resident graphs (R-MAT scale 24 for PPR, the 32-graph pool for
+    global PageRank) behind one server: 12 PPR queries (dangling and non-dangling sources)
+    and 12 global queries submitted at once, every result certified at L1 <= 1e-6 and
+    checked by its PageRank-equation residual."""
+    import torch
+    pr = pr_lib
+    gp = prgen.workload_rmat(scale=24, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=1)
+    pool = prgen.workload_serve_pool(count=32, seed=0)
+    print(f"PPR graph n={gp.n} m={gp.m}; pool n={sum(x.n for x in pool)}", flush=True)
+    graphs = [gp] + pool
+    dgs = [pr.upload(x.row_ptr, x.col) for x in graphs]
+    srv = pr.Server(c=C, l1_tol=1e-6, residual="fp32", slots=16, sweeps_per_round=4)
+    try:
+        gids = [srv.add_graph(d) for d in dgs]
+        rng = np.random.default_rng(5)
+        deg = np.diff(gp.row_ptr)
+        srcs = list(rng.choice(np.flatnonzero(deg > 0), 9, replace=False)) + \
+            list(rng.choice(np.flatnonzero(deg == 0), 3, replace=False))
+        picks = [int(x) for x in rng.integers(1, len(graphs), 12)]
+        reqs = []
+        for s in srcs:
+            out = torch.empty(gp.n, dtype=torch.float64, device="cuda")
+            reqs.append((0, int(s), out, srv.submit(gids[0], int(s), out)))
+        for gi in picks:
+            out = torch.empty(graphs[gi].n, dtype=torch.float64, device="cuda")
+            reqs.append((gi, -1, out, srv.submit(gids[gi], -1, out)))
+        Ps = {}
+        for gi, s, out, rid in reqs:
+            st = srv.wait(rid, timeout=600.0)
+            assert st["status"] == 0 and st["l1_bound"] <= 1e-6, (gi, s, st)
+            pi = out.cpu().numpy()
+            assert abs(pi.sum() - 1.0) <= 1e-10
+            if gi not in Ps:
+                Ps[gi] = _transition(graphs[gi])
+            res = _ppr_residual(graphs[gi], pi, C, s, Ps[gi])
+            assert res <= (1 + C) * 1e-6, (gi, s, res)
+    finally:
+        srv.close()
+    for d in dgs:
+        d.free()
