@@ -839,7 +839,8 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     int t = 0;
     bool stopped = false;
     if (nN > 0) {
-        int batch = l1 ? 8 : 16;
+        // a solve that may turn to ordered sweeps checks its frontier after two sweeps
+        int batch = (ordered_ok && !ordered) ? 2 : (l1 ? 8 : 16);
         double bound_prev = -1.0;
         int t_prev = 0;
         while (t < max_sweeps) {
