@@ -105,6 +105,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="served scenario: seconds of Poisson arrivals (0 = skip)")
     ap.add_argument("--serve-qps", type=float, default=200.0)
+    ap.add_argument("--serve-slots", type=int, default=16, help="served scenario: batch columns per graph (8 or 16)")
     ap.add_argument("--serve-compare", type=int, default=160,
                     help="queries of the served stream also run one at a time and all at once")
     ap.add_argument("--serve-ppr-scale", type=int, default=24,
@@ -465,7 +466,7 @@ def run_serve(pr, prgen, c, args):
             for i, x in enumerate(graphs)]
 
     def make_server():
-        srv = pr.Server(c=c, l1_tol=args.tol, residual="fp32", slots=16, sweeps_per_round=4)
+        srv = pr.Server(c=c, l1_tol=args.tol, residual="fp32", slots=args.serve_slots, sweeps_per_round=4)
         gids = [srv.add_graph(d) for d in dgs]
         for gi in range(len(graphs)):  # one query per graph first: workspaces and plans
             buf = free[gi][0]
@@ -567,7 +568,7 @@ def run_serve(pr, prgen, c, args):
             "served_over_one_at_a_time": saturated["gteps_aggregate"] / one["gteps_aggregate"],
             "ppr_graph": {"n": gp.n, "m": gp.m},
             "pool": {"graphs": len(pool), "n": sum(x.n for x in pool), "m": sum(x.m for x in pool)},
-            "ppr_share": float(is_ppr.mean()), "slots_per_graph": 16}
+            "ppr_share": float(is_ppr.mean()), "slots_per_graph": args.serve_slots}
 
 
 def run_probes(pr, torch, g):
