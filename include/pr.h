@@ -79,8 +79,8 @@ typedef enum {
    invalidated, and phase 2 gathers the levels from the highest down, each from the
    finished values of its in-neighbours, then the dangling vertices.  The certified bound
    is unchanged (c / (1-c) of the core's residual bounds the unnormalised error).  Such a
-   graph serves pr_solve_ifp2, pr_ppr (sources solved one at a time) and pr_graph_tune;
-   IFP1, the power method, warm starts and the server reject it. */
+   graph serves pr_solve_ifp2, pr_ppr (sources solved one at a time), pr_solve_power and
+   pr_graph_tune; IFP1, warm starts and the server reject it. */
 #define PR_PEEL 0x20000u
 #define PR_PEEL_MAX_LEVELS 64
 
@@ -248,7 +248,7 @@ pr_status pr_solve_ifp2(const pr_graph *g, const double *p, const pr_opts *o, do
  * Power method on P'' = c P' + (1-c) p e^T (Eq. 1), the baseline the paper
  * compares against (section 4.3): x <- c P x + (c d^T x + (1-c) e^T x) p from
  * x = p until c / (1-c) * ||x' - x||_1 <= l1_tol; xi and stop are ignored.
- * Arguments and errors as pr_solve_ifp1 (PR_PEEL graphs rejected); l1_tol must be > 0.
+ * Arguments and errors as pr_solve_ifp1; l1_tol must be > 0.
  */
 pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st);
 

@@ -996,7 +996,7 @@ template <typename WT>
 pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, double *pi, pr_stats *st) {
     hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
     const int64_t n = G.n;
-    const int32_t nN = G.nN;
+    const int32_t nN = G.nN + G.nP;  // vertices with out-edges (on a peeled graph, the core and the peeled ones)
     const bool out_dev = o.flags & PR_OUT_DEVICE;
     const double c = o.c;
     const double tol = o.l1_tol * (1.0 - 1e-6);
@@ -1904,8 +1904,8 @@ static pr_status solve_common(const pr_graph *g, int method, const double *p, co
     if (ps != PR_OK) return ps;
     ps = enter(g);
     if (ps != PR_OK) return ps;
-    if (method != 2 && g->g.nP > 0)
-        return fail(PR_EINVAL, "a graph uploaded with PR_PEEL serves IFP2 solves only");
+    if (method == 1 && g->g.nP > 0)
+        return fail(PR_EINVAL, "a graph uploaded with PR_PEEL serves IFP2 and power solves, not IFP1");
     try {
         const Graph &G = g->g;
         if (method == 3) {

@@ -154,8 +154,11 @@ def test_max_sweeps_and_rejections(pr):
     assert st["l1_bound"] >= l1(pi, ref)
     with pytest.raises(pr.PRError, match="PR_PEEL"):
         pr.ifp1(dg, c=C)
-    with pytest.raises(pr.PRError, match="PR_PEEL"):
-        pr.power(dg, c=C)
+    # the power method runs on the peeled layout (every vertex with out-edges gathers)
+    pp, sp_ = pr.power(dg, c=C, l1_tol=1e-11)
+    assert sp_["status"] == 0 and l1(pp, ref) <= 1e-9
+    pp32, _ = pr.power(dg, c=C, l1_tol=1e-6, residual="fp32")
+    assert l1(pp32, ref) <= 1e-6
     st_ = pr.State(g.n)
     with pytest.raises(pr.PRError, match="PR_PEEL"):
         pr.ifp2_warm(dg, st_, c=C)
