@@ -471,3 +471,46 @@ def test_ordered_sweeps_after_a_sparse_start(pr):
     ref = oracle.power(g, C, e, tol=1e-13)[0]
     pi, st = pr.ifp1(dg, p=e, c=C, xi=1e-13)
     assert st["status"] == 0 and l1(pi, ref) <= 1e-9
+
+
+def test_concurrent_solves_on_one_graph(pr):
+    """The graph is read-only after upload: solves from several host threads, each on its
+    own stream, share one handle (the second takes a workspace of its own) and give the
+    answers of the same solves run one after another."""
+    import threading
+
+    import torch
+    g = prgen.random_digraph(70001, 420000, seed=3, dangling_frac=0.15, unref_frac=0.1)
+    dg = pr.upload(g.row_ptr, g.col, groups=4)
+    deg = np.diff(g.row_ptr)
+    srcs = [int(x) for x in np.flatnonzero(deg > 0)[[3, 300, 3000]]]
+    ref_glob, _ = pr.ifp2(dg, c=C, l1_tol=1e-9)
+    ref_ppr, _ = pr.ppr(dg, srcs, c=C, l1_tol=1e-9)
+    ref_pow, _ = pr.power(dg, c=C, l1_tol=1e-9)
+    results, errors = {}, []
+
+    def work(name, fn):
+        try:
+            s = torch.cuda.Stream()
+            with torch.cuda.stream(s):
+                for _ in range(3):
+                    results[name] = fn(s)
+        except Exception as e:  # reported below, on the main thread
+            errors.append((name, repr(e)))
+
+    jobs = {
+        "ifp2": lambda s: pr.ifp2(dg, c=C, l1_tol=1e-9, stream=s.cuda_stream)[0],
+        "ppr": lambda s: pr.ppr(dg, srcs, c=C, l1_tol=1e-9, stream=s.cuda_stream)[0],
+        "power": lambda s: pr.power(dg, c=C, l1_tol=1e-9, stream=s.cuda_stream)[0],
+        "ifp2_b": lambda s: pr.ifp2(dg, c=C, l1_tol=1e-9, stream=s.cuda_stream)[0],
+    }
+    threads = [threading.Thread(target=work, args=(k, f)) for k, f in jobs.items()]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join(timeout=120)
+    assert not errors, errors
+    assert l1(results["ifp2"], ref_glob) <= 1e-12 and l1(results["ifp2_b"], ref_glob) <= 1e-12
+    assert l1(results["power"], ref_pow) <= 1e-12
+    for r in range(len(srcs)):
+        assert l1(results["ppr"][r], ref_ppr[r]) <= 1e-12
