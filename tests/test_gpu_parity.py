@@ -338,6 +338,18 @@ def test_invalid_arguments_on_gpu(pr):
         pr.ifp2(dg, p=np.zeros(100))
     with pytest.raises(pr.PRError, match="source"):
         pr.ppr(dg, [100])
+    # outputs stay untouched on a negative status
+    import torch
+    out = torch.full((100,), 7.0, dtype=torch.float64, device="cuda")
+    with pytest.raises(pr.PRError, match="negative"):
+        pr.ifp2(dg, p=p, out=out)
+    with pytest.raises(pr.PRError, match="c must"):
+        pr.power(dg, c=0.0, out=out)
+    assert bool((out == 7.0).all())
+    host = np.full(100, 7.0)
+    with pytest.raises(pr.PRError, match="l1_tol"):
+        pr.ifp1(dg, l1_tol=-1.0, out=host)
+    assert (host == 7.0).all()
     # the graph still works after the rejected calls
     pi, _ = pr.ifp2(dg, c=C, xi=1e-13)
     assert l1(pi, oracle.power(g, C, tol=1e-13)[0]) <= 1e-9
