@@ -197,7 +197,7 @@ struct Graph {
     bool dangling(int64_t v) const { return (dangling_bits[(size_t)v >> 6] >> (v & 63)) & 1u; }
 };
 
-// host helpers shared by the host translation units (pr_host.hip)
+// host helpers for the query server (pr_host.hip: errors; pr_solve.hip: batched plans)
 pr_status set_error(pr_status st, const std::string &msg);
 void clear_error();
 pr_status batch_plans(Graph &G, int B, hipStream_t s);  // B = 8 or 16

@@ -1,0 +1,665 @@
+// pr_solve.hip -- the sweep loops of libpr.so's solvers (IFP1, IFP2, the power
+// method, batched PPR columns), their workspaces, and the per-graph autotuner.
+#include "pr_host.h"
+
+namespace prk {
+namespace host {
+
+pr_status acquire_ws(Graph &G, size_t bytes, Workspace &ws) {
+    ws.g = &G;
+    ws.bytes = bytes;
+    {
+        std::lock_guard<std::mutex> lk(G.ws_mu);
+        if (!G.ws_busy) {
+            if (G.ws_bytes < bytes) {
+                if (G.ws_mem) (void)hipFree(G.ws_mem);
+                G.ws_mem = nullptr;
+                G.ws_bytes = 0;
+                hipError_t e = hipMalloc(&G.ws_mem, bytes);
+                if (e != hipSuccess) return hip_fail(e, "workspace");
+                G.ws_bytes = bytes;
+            }
+            if (!G.ws_hctl) {
+                hipError_t e = hipHostMalloc(&G.ws_hctl, sizeof(Ctl), hipHostMallocDefault);
+                if (e != hipSuccess) return hip_fail(e, "pinned control block");
+            }
+            G.ws_busy = true;
+            ws.base = (char *)G.ws_mem;
+            ws.hctl = (Ctl *)G.ws_hctl;
+            ws.cached = true;
+            return PR_OK;
+        }
+    }
+    hipError_t e = hipMalloc((void **)&ws.base, bytes);
+    if (e != hipSuccess) return hip_fail(e, "workspace");
+    e = hipHostMalloc((void **)&ws.hctl, sizeof(Ctl), hipHostMallocDefault);
+    if (e != hipSuccess) return hip_fail(e, "pinned control block");
+    return PR_OK;
+}
+
+
+// Validate p (host or device) and place it on the device; returns 1/sum(p).
+pr_status prepare_p(const Graph &G, const double *p, const pr_opts &o, double *pdev, double *sumbad,
+                    const double **p_used, double *pscale, hipStream_t s) {
+    *p_used = nullptr;
+    *pscale = 1.0;
+    if (!p) return PR_OK;
+    double sum = 0.0;
+    if (o.flags & PR_P_DEVICE) {
+        HIPCHK(hipMemsetAsync(sumbad, 0, 2 * sizeof(double), s));
+        HIPCHK(launch_validate_p(p, G.n, sumbad, s));
+        double h[2];
+        HIPCHK(hipMemcpyAsync(h, sumbad, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (h[1] != 0.0) return fail(PR_EINVAL, "p has a negative or non-finite entry");
+        sum = h[0];
+        *p_used = p;
+    } else {
+        for (int64_t i = 0; i < G.n; ++i) {
+            if (!(p[i] >= 0.0) || !isfinite(p[i])) return fail(PR_EINVAL, "p has a negative or non-finite entry");
+            sum += p[i];
+        }
+        HIPCHK(hipMemcpyAsync(pdev, p, sizeof(double) * G.n, hipMemcpyHostToDevice, s));
+        *p_used = pdev;
+    }
+    if (!(sum > 0.0) || !isfinite(sum)) return fail(PR_EINVAL, "sum(p) must be > 0");
+    *pscale = 1.0 / sum;
+    return PR_OK;
+}
+
+// Sweep batches: the kernels of sweeps past the stop decision return at once,
+// so the host enqueues a batch, reads the control block, and sizes the next
+// batch from the observed decay of the certified bound.
+int next_batch(int prev_batch, double bound_prev, double bound_now, int swept, double tol, bool l1) {
+    if (l1 && bound_prev > 0 && bound_now > 0 && bound_now < bound_prev && swept > 0) {
+        double rate = pow(bound_now / bound_prev, 1.0 / swept);
+        if (rate > 0 && rate < 1) {
+            double need = log(tol / bound_now) / log(rate);
+            int k = (int)ceil(need) + 1;
+            return std::min(64, std::max(2, k));
+        }
+    }
+    return std::min(64, prev_batch * 2);
+}
+
+template <typename T>
+pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
+                      pr_stats *st, const WarmArgs *warm) {
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
+    const int64_t n = G.n;
+    const int32_t nN = G.nN, nD = G.nD;
+    const bool literal = ifp2 && (o.flags & PR_IFP2_LITERAL);
+    const bool out_dev = o.flags & PR_OUT_DEVICE;
+    const double c = o.c;
+    const bool l1 = o.stop == PR_STOP_L1;
+    // threshold: under the L1 rule, the xi at which an empty frontier already
+    // certifies the bound (residual on N <= nN * xi, total mass >= n)
+    double xi = o.xi;
+    if (l1) {
+        xi = o.l1_tol * (1.0 - c) / (2.0 * c) * (double)n / (double)std::max<int32_t>(nN, 1);
+        xi *= 1.0 - 1e-9;
+    }
+    const double tol = l1 ? o.l1_tol * (1.0 - 1e-6) : 0.0;
+    const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
+
+    size_t bytes = carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
+                   carve_size<double>(nN + G.nP) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
+                   carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
+                   carve_size<double>(2) + carve_size<double>(kPartDoubles) +
+                   (warm ? 2 * carve_size<double>(nN) + 3 * carve_size<double>(nD) : 0);
+    Workspace ws;
+    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
+    if (ps != PR_OK) return ps;
+    Carve cv{ws.base};
+    T *h = cv.take<T>(n);
+    T *w = cv.take<T>(nN);
+    double *pibar = cv.take<double>(nN);
+    double *xD = cv.take<double>(nD);
+    double *w2 = cv.take<double>(nN + G.nP);  // phase-2 weights of every source of a deferred vertex
+    double *outbuf = cv.take<double>(out_dev ? 0 : n);
+    Ctl *ctl = cv.take<Ctl>(1);
+    Trace *tr = cv.take<Trace>(1);
+    double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
+    double *sumbad = cv.take<double>(2);
+    double *part = cv.take<double>(kPartDoubles);
+    // warm start: reserve at the start, mass taken this solve pushed to dangling vertices
+    double *pibar0 = warm ? cv.take<double>(nN) : nullptr;
+    double *w3 = warm ? cv.take<double>(nN) : nullptr;
+    double *xD0 = warm ? cv.take<double>(nD) : nullptr;
+    double *hD0 = warm ? cv.take<double>(nD) : nullptr;
+    double *hDn = warm ? cv.take<double>(nD) : nullptr;
+
+    InitArgs a{};
+    a.n = n;
+    a.nN = nN;
+    a.perm = G.perm;
+    a.source = source;
+    a.uniform = (p == nullptr && source < 0);
+    ps = prepare_p(G, p, o, pdev, sumbad, &a.p, &a.pscale, s);
+    if (ps != PR_OK) return ps;
+
+    EventPair ev_solve;
+    SweepTimer timer;
+    timer.on = o.flags & PR_PROFILE;
+    HIPCHK(hipEventRecord(ev_solve.a, s));
+    Ctl hc;
+    memset(&hc, 0, sizeof(hc));
+    hc.stop_after = INT_MAX;
+    hc.sx = (double)n;
+    HIPCHK(hipMemcpyAsync(ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    if (warm)
+        HIPCHK(launch_warm_import<T>(ctl, n, nN, G.perm, warm->pibar, warm->h, h, pibar, pibar0, xD0, hD0, part, s));
+    else
+        HIPCHK(launch_init_ifp<T>(a, h, pibar, s));
+
+    // the gather of sweep t uses the in-edge lists of the last epoch starting at or before t
+    auto pull_plan = [&](int t) -> const MPPlan & {
+        size_t e = 0;
+        while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
+        return ifp2 ? G.epochs[e].pull_nn : G.epochs[e].pull_all;
+    };
+    const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
+    const int check_mode = force == 0;
+    // ordered sweeps (groups built at upload): from the start for global solves, where every
+    // vertex starts active; otherwise from the first batch after a sweep that gathered.  IFP2
+    // gathers into the non-dangling rows, IFP1 into all rows (its pushes reach dangling vertices)
+    const int ngr = (int)G.grp.size() - 1;
+    const bool ordered_ok = ngr > 1 && ngr <= kMaxGroups && force == 0 && !(o.flags & PR_JACOBI) &&
+                            !G.grp_pull.empty() && G.prefer_ordered;
+    bool ordered = ordered_ok && a.uniform && !warm;
+    GroupBlocks gb{};
+    gb.stride = kGroupBlocks;
+    for (int q = 0; q < ngr && q < kMaxGroups; ++q)
+        gb.nb[q] = (int32_t)std::min<int64_t>(
+            kGroupBlocks, std::max<int64_t>(1, ((int64_t)G.grp[q + 1] - G.grp[q] + 1023) / 1024));
+    const double sT = (double)sizeof(T);
+    int t = 0;
+    bool stopped = false;
+    if (nN > 0) {
+        // a solve that may turn to ordered sweeps checks its frontier after two sweeps
+        int batch = (ordered_ok && !ordered) ? 2 : (l1 ? 8 : 16);
+        double bound_prev = -1.0;
+        int t_prev = 0;
+        while (t < max_sweeps) {
+            int nb = std::min(batch, max_sweeps - t);
+            for (int k = 0; k < nb; ++k, ++t) {
+                const MPPlan &pullp = pull_plan(t);
+                // a gather reads every live in-edge; scatter when the active edges are fewer than half of them
+                const unsigned long long pull_edges = (unsigned long long)pullp.edges();
+                const unsigned long long pull_thr = (unsigned long long)(0.5 * (double)pull_edges) + 1;
+                if (ordered) {
+                    size_t e = 0;
+                    while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
+                    unsigned long long sweep_edges = 0;
+                    for (int q = 0; q < ngr; ++q) {
+                        HIPCHK(launch_reserve_range<T>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg, G.rp_nn, c,
+                                                       xi, ifp2 ? 1 : 0, gb.nb[q],
+                                                       part + (size_t)5 * kGroupBlocks * q, s));
+                        const MPPlan &pl = ifp2 ? G.grp_pull[e][q] : G.grp_pull_all[e][q];
+                        sweep_edges += (unsigned long long)pl.edges();
+                        const KernelEvents ev =
+                            timer.next(t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT));
+                        HIPCHK(launch_pull<T, T>(t, ctl, pl, w, h, 0, s, TileSkip(), ev));
+                    }
+                    HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, gb, part,
+                                               part + (size_t)5 * kGroupBlocks * ngr, c, l1 ? 1 : 0, tol, pull_thr,
+                                               sweep_edges, s));
+                    continue;
+                }
+                HIPCHK(launch_reserve<T>(t, ctl, tr, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, l1 ? 1 : 0,
+                                         tol, pull_thr, force, pull_edges, part, s));
+                if (force != 2) {
+                    // the scatter is timed when it is forced; in the automatic mode only the
+                    // gather (the dense sweeps' kernel) carries events, to keep their overhead low
+                    const KernelEvents e = force == 1 ? timer.next(t, 0, 0.0) : KernelEvents();
+                    if (ifp2) {
+                        HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, check_mode, s, TileSkip(), e));
+                    } else {  // one interval over both scatter launches
+                        HIPCHK(launch_push<T>(t, ctl, G.push_nn, w, h, check_mode, s, TileSkip(), {e.a, nullptr}));
+                        HIPCHK(launch_push<T>(t, ctl, G.push_nd, w, h, check_mode, s, TileSkip(), {nullptr, e.b}));
+                    }
+                }
+                if (force != 1) {
+                    // every live in-edge: source id + gathered weight; every target row: offset + residual update
+                    const KernelEvents e =
+                        timer.next(t, 1, (double)pullp.edges() * (4.0 + sT) + (double)pullp.R * (4.0 + 2.0 * sT));
+                    HIPCHK(launch_pull<T, T>(t, ctl, pullp, w, h, check_mode, s, TileSkip(), e));
+                }
+            }
+            HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (ws.hctl->stop_after < t) {
+                stopped = true;
+                break;
+            }
+            ordered = ordered_ok && ws.hctl->use_pull;  // dense frontier: ordered sweeps from here
+            batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, l1);
+            bound_prev = ws.hctl->last_bound;
+            t_prev = t;
+        }
+    } else {
+        stopped = true;
+    }
+    if (ifp2 && nD > 0 && warm) {
+        HIPCHK(launch_warm_phase2_prep<T>(nN, nD, h, pibar, pibar0, G.deg, c, xD0, hD0, w2, w3, xD, hDn, s));
+        HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
+        HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w3, hDn, 0, s));
+    } else if (ifp2 && G.nP > 0) {
+        // peeled levels from the highest down: each gathers from the core and the levels
+        // above it, then hands its own weights to the levels below; the dangling block last
+        HIPCHK(launch_phase2_prep<T>(a, h, pibar, G.deg, c, literal ? 1 : 0, w2, xD, s));
+        for (size_t b = 0; b < G.lvl_pull.size(); ++b) {
+            const int32_t lo = G.lvl_lo[b], hi = G.lvl_lo[b + 1];
+            HIPCHK(launch_pull<double, double>(-1, ctl, G.lvl_pull[b], w2, xD + (lo - nN), 0, s));
+            if (lo < nN + G.nP) HIPCHK(launch_peel_w2(lo, hi, nN, xD, G.deg, c, w2, s));
+        }
+    } else if (ifp2 && nD > 0) {
+        HIPCHK(launch_phase2_prep<T>(a, h, pibar, G.deg, c, literal ? 1 : 0, w2, xD, s));
+        HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
+    }
+    double *dst = out_dev ? pi : outbuf;
+    HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, dst, part, s));
+    if (warm) HIPCHK(launch_warm_export<T>(n, nN, G.perm, h, pibar, hDn, warm->pibar, warm->h, s));
+    HIPCHK(hipEventRecord(ev_solve.b, s));
+    HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Ctl &r = *ws.hctl;
+    if (st) {
+        pr_stats z;
+        memset(&z, 0, sizeof(z));
+        z.sweeps = r.sweeps;
+        z.pull_sweeps = r.pull_sweeps;
+        z.edges_processed = (int64_t)r.tot_edges + (ifp2 ? G.mND : 0);
+        z.edges_traversed = (int64_t)r.tot_traversed + (ifp2 ? G.mND : 0);
+        z.vertex_pushes = (int64_t)r.tot_pushes;
+        z.residual_l1 = r.fin_sum > 0 ? r.fin_sn / r.fin_sum : 0.0;
+        const double k = literal ? 2.0 / (1.0 - c) : 2.0 * c / (1.0 - c);
+        z.l1_bound = r.fin_sum > 0 ? k * r.fin_sn / r.fin_sum : 0.0;
+        if (warm) {
+            // signed residuals: unnormalised error E <= c / (1 - c) sum|h_N|, the exact mass is at
+            // least fin_sum - E, and normalising costs (1 + sum|x| / sum x) E / (that mass)
+            const double E = c / (1.0 - c) * r.fin_sn;
+            const double den = r.fin_sum - E;
+            z.l1_bound = den > 0 ? (1.0 + r.fin_abs / r.fin_sum) * E / den : INFINITY;
+        }
+        z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
+        z.seconds_preprocess = ifp2 ? G.seconds_split : 0.0;
+        if (timer.on) {
+            std::vector<unsigned long long> trc((size_t)std::min(r.sweeps + 1, kMaxTrace));
+            std::vector<unsigned long long> tre(trc.size());
+            std::vector<double> trs(trc.size()), trb(trc.size());
+            if (!trc.empty()) {
+                HIPCHK(hipMemcpy(trc.data(), tr->cnt, sizeof(unsigned long long) * trc.size(), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(tre.data(), tr->edges, sizeof(unsigned long long) * tre.size(),
+                                 hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(trs.data(), tr->sn, sizeof(double) * trs.size(), hipMemcpyDeviceToHost));
+                HIPCHK(hipMemcpy(trb.data(), tr->bound, sizeof(double) * trb.size(), hipMemcpyDeviceToHost));
+            }
+            g_trace = TraceRec();
+            for (size_t i = 0; i < trc.size() && (int)i < r.sweeps; ++i) {
+                g_trace.active.push_back((int64_t)(trc[i] & ~(1ull << 63)));
+                g_trace.pulled.push_back((int32_t)(trc[i] >> 63));
+                g_trace.edges.push_back((int64_t)tre[i]);
+                g_trace.residual.push_back(trs[i]);
+                g_trace.bound.push_back(trb[i]);
+            }
+            const double sT = (double)sizeof(T);
+            for (size_t i = 0; i < timer.ev.size(); ++i) {
+                int ts = timer.sweep_of[i];
+                if (ts >= r.sweeps || ts >= (int)trc.size()) continue;
+                bool pulled = (trc[ts] >> 63) != 0;
+                if ((int)pulled != timer.is_pull[i]) continue;
+                double sec = elapsed_s(timer.ev[i]->a, timer.ev[i]->b);
+                if (sec <= 0.0) continue;  // nothing was launched (empty plan)
+                if (pulled) {
+                    z.pull_seconds += sec;
+                    z.pull_launches += 1;
+                    z.pull_bytes += timer.bytes[i];
+                } else {
+                    // every pushed edge: target id + residual read-modify-write; every row: offset + weight
+                    int rows = ifp2 ? nN : 2 * nN;
+                    z.push_seconds += sec;
+                    z.push_launches += ifp2 ? 1 : 2;
+                    z.push_bytes += (double)tre[ts] * (4.0 + 2.0 * sT) + (double)rows * (4.0 + sT);
+                }
+            }
+        }
+        *st = z;
+    }
+    return stopped ? PR_OK : PR_ENOCONV;
+}
+
+template <typename WT>
+pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, double *pi, pr_stats *st) {
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
+    const int64_t n = G.n;
+    const int32_t nN = G.nN + G.nP;  // vertices with out-edges (on a peeled graph, the core and the peeled ones)
+    const bool out_dev = o.flags & PR_OUT_DEVICE;
+    const double c = o.c;
+    const double tol = o.l1_tol * (1.0 - 1e-6);
+    const int max_it = o.max_sweeps > 0 ? o.max_sweeps : 100000;
+    size_t bytes = carve_size<double>(n) * 2 + carve_size<WT>(nN) + carve_size<double>(out_dev ? 0 : n) +
+                   carve_size<Ctl>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
+                   carve_size<double>(2) + carve_size<double>(5 * kRedBlocks);
+    Workspace ws;
+    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
+    if (ps != PR_OK) return ps;
+    Carve cv{ws.base};
+    double *x = cv.take<double>(n);
+    double *acc = cv.take<double>(n);
+    WT *y = cv.take<WT>(nN);
+    double *outbuf = cv.take<double>(out_dev ? 0 : n);
+    Ctl *ctl = cv.take<Ctl>(1);
+    double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
+    double *sumbad = cv.take<double>(2);
+    double *part = cv.take<double>(5 * kRedBlocks);
+    InitArgs a{};
+    a.n = n;
+    a.nN = nN;
+    a.perm = G.perm;
+    a.source = -1;
+    a.uniform = p == nullptr;
+    ps = prepare_p(G, p, o, pdev, sumbad, &a.p, &a.pscale, s);
+    if (ps != PR_OK) return ps;
+
+    EventPair ev_solve;
+    SweepTimer timer;
+    timer.on = o.flags & PR_PROFILE;
+    HIPCHK(hipEventRecord(ev_solve.a, s));
+    Ctl hc;
+    memset(&hc, 0, sizeof(hc));
+    hc.stop_after = INT_MAX;
+    HIPCHK(hipMemcpyAsync(ctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, s));
+    HIPCHK(launch_power_init(a, x, acc, s));
+    int t = 0;
+    bool stopped = false;
+    int batch = 8;
+    double bound_prev = -1.0;
+    int t_prev = 0;
+    while (t <= max_it) {
+        int nb = std::min(batch, max_it + 1 - t);
+        for (int k = 0; k < nb; ++k, ++t) {
+            HIPCHK(launch_power_prescale<WT>(t, ctl, a, x, acc, y, G.deg, c, tol, part, s));
+            if (t < max_it) {
+                const KernelEvents e = timer.next(t, 1, 0.0);
+                HIPCHK(launch_pull<WT, double>(t, ctl, G.pull_all, y, acc, 0, s, TileSkip(), e));
+            }
+        }
+        HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (ws.hctl->stop_after < t) {
+            stopped = true;
+            break;
+        }
+        batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, true);
+        bound_prev = ws.hctl->last_bound;
+        t_prev = t;
+    }
+    double *dst = out_dev ? pi : outbuf;
+    HIPCHK(launch_final_x(ctl, a, x, dst, part, s));
+    HIPCHK(hipEventRecord(ev_solve.b, s));
+    HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+    if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    const Ctl &r = *ws.hctl;
+    if (st) {
+        pr_stats z;
+        memset(&z, 0, sizeof(z));
+        z.sweeps = r.sweeps;
+        z.pull_sweeps = r.sweeps;
+        z.edges_processed = (int64_t)r.sweeps * G.m;
+        z.edges_traversed = z.edges_processed;
+        z.vertex_pushes = (int64_t)r.sweeps * nN;
+        z.residual_l1 = r.pw_diff;
+        z.l1_bound = c / (1.0 - c) * r.pw_diff;
+        z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
+        if (timer.on) {
+            const double sW = (double)sizeof(WT);
+            for (size_t i = 0; i < timer.ev.size(); ++i) {
+                if (timer.sweep_of[i] >= r.sweeps) continue;
+                z.pull_seconds += elapsed_s(timer.ev[i]->a, timer.ev[i]->b);
+                z.pull_launches += 1;
+                z.pull_bytes += (double)G.m * (4.0 + sW) + (double)n * (4.0 + 16.0);
+            }
+        }
+        *st = z;
+    }
+    return stopped ? PR_OK : PR_ENOCONV;
+}
+
+// Plans for the batched kernels of width B (tiles of (kBlock / B) * kMPK items),
+// built once per graph and width on the first batched solve.
+template <int B>
+pr_status ensure_batch_plans_impl(Graph &G, hipStream_t s) {
+    constexpr int slot = B == 8 ? 0 : 1;
+    std::lock_guard<std::mutex> lk(G.bp_mu);
+    if (G.bp_ready[slot]) return PR_OK;
+    auto mk = [&](MPPlan &p, const uint32_t *rpp, const int32_t *idx, int32_t R, int64_t edges) -> hipError_t {
+        p.rp = rpp;
+        p.idx = idx;
+        p.R = R;
+        p.items = (uint32_t)(R + edges);
+        p.ipb = (kBlock / B) * kMPK;
+        p.blocks = 0;
+        const int32_t blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
+        void *mem = nullptr;
+        hipError_t e = hipMalloc(&mem, sizeof(uint2) * ((size_t)blocks + 1));
+        if (e != hipSuccess) return e;
+        G.allocs.push_back(mem);
+        G.device_bytes += (int64_t)(sizeof(uint2) * ((size_t)blocks + 1));
+        p.plan = (uint2 *)mem;
+        if (R == 0) return hipSuccess;
+        return launch_plan(p, s);
+    };
+    G.bp_pull_nn[slot].clear();
+    for (const Epoch &e : G.epochs) {
+        MPPlan p;
+        HIPCHK(mk(p, e.in_ptr, e.in_src, G.nN, e.edges_nn));
+        G.bp_pull_nn[slot].push_back(p);
+    }
+    HIPCHK(mk(G.bp_pull_nd[slot], G.in_ptr + G.nN, G.in_src, G.nD, G.mND));
+    HIPCHK(mk(G.bp_push_nn[slot], G.rp_nn, G.col_nn, G.nN, G.mNN));
+    HIPCHK(hipStreamSynchronize(s));
+    G.bp_ready[slot] = true;
+    return PR_OK;
+}
+
+// IFP2 for kb <= kBatch single-source PPR queries at once (pr_batch.hip):
+// column-interleaved residuals, per-column management, one gather serving all
+// columns.  pi_rows[r * n ...] receives the vector of srcs[r].
+template <typename T, int B>
+pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const pr_opts &o, double *pi_rows,
+                            pr_stats *st) {
+    constexpr int slot = B == 8 ? 0 : 1;
+    Graph &G = const_cast<Graph &>(Gc);
+    hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
+    pr_status ps = ensure_batch_plans_impl<B>(G, s);
+    if (ps != PR_OK) return ps;
+    const int64_t n = G.n;
+    const int32_t nN = G.nN, nD = G.nD;
+    const bool out_dev = o.flags & PR_OUT_DEVICE;
+    const double c = o.c;
+    const bool l1 = o.stop == PR_STOP_L1;
+    double xi = o.xi;
+    if (l1) xi = o.l1_tol * (1.0 - c) / (2.0 * c) * (double)n / (double)std::max<int32_t>(nN, 1) * (1.0 - 1e-9);
+    const double tol = l1 ? o.l1_tol * (1.0 - 1e-6) : 0.0;
+    const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
+
+    size_t bytes = carve_size<T>((size_t)n * B) + carve_size<T>((size_t)nN * B) + carve_size<double>((size_t)nN * B) +
+                   carve_size<double>((size_t)nD * B) + carve_size<double>((size_t)nN * B) +
+                   carve_size<double>(out_dev ? 0 : (size_t)kb * n) + carve_size<CtlB>(1) +
+                   carve_size<double>((size_t)4 * B * kRedBlocks);
+    Workspace ws;
+    ps = acquire_ws(G, bytes, ws);
+    if (ps != PR_OK) return ps;
+    Carve cv{ws.base};
+    T *h = cv.take<T>((size_t)n * B);
+    T *w = cv.take<T>((size_t)nN * B);
+    double *pibar = cv.take<double>((size_t)nN * B);
+    double *xD = cv.take<double>((size_t)nD * B);
+    double *w2 = cv.take<double>((size_t)nN * B);
+    double *outbuf = cv.take<double>(out_dev ? 0 : (size_t)kb * n);
+    CtlB *ctl = cv.take<CtlB>(1);
+    double *part = cv.take<double>((size_t)4 * B * kRedBlocks);
+    CtlB *hc = nullptr;
+    HIPCHK(hipHostMalloc((void **)&hc, sizeof(CtlB), hipHostMallocDefault));
+    std::unique_ptr<CtlB, void (*)(CtlB *)> hc_guard(hc, [](CtlB *p) { (void)hipHostFree(p); });
+
+    SrcSet ss;
+    for (int j = 0; j < kMaxBatch; ++j) ss.s[j] = j < kb ? srcs[j] : -1;
+    memset(hc, 0, sizeof(CtlB));
+    hc->stop_after = INT_MAX;
+    for (int j = 0; j < B; ++j) {
+        hc->col_stop[j] = j < kb ? INT_MAX : -1;
+        hc->sx[j] = (double)n;
+    }
+    EventPair ev_solve;
+    HIPCHK(hipEventRecord(ev_solve.a, s));
+    HIPCHK(hipMemcpyAsync(ctl, hc, sizeof(CtlB), hipMemcpyHostToDevice, s));
+    const uint32_t kmask = (uint32_t)((1ull << kb) - 1ull);
+    HIPCHK(launch_init_b<T, B>(n, nN, G.perm, ss, kmask, h, pibar, s));
+
+    const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
+    const int check_mode = force == 0;
+    auto pull_plan = [&](int t) -> const MPPlan & {
+        size_t e = 0;
+        while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
+        return G.bp_pull_nn[slot][e];
+    };
+    int t = 0;
+    bool stopped = false;
+    if (nN > 0) {
+        int batch = l1 ? 8 : 16;
+        double bound_prev = -1.0;
+        int t_prev = 0;
+        while (t < max_sweeps) {
+            const int nbt = std::min(batch, max_sweeps - t);
+            for (int k = 0; k < nbt; ++k, ++t) {
+                const MPPlan &pullp = pull_plan(t);
+                // a gather serves every column; scatter when the active (vertex, column) edges are few
+                const double pull_thr = 0.25 * (double)pullp.edges();
+                HIPCHK(launch_reserve_b<T, B>(t, ctl, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, l1 ? 1 : 0, tol,
+                                              pull_thr, force, (unsigned long long)pullp.edges(), part, s));
+                if (force != 2) HIPCHK(launch_push_b<T, B>(t, ctl, G.bp_push_nn[slot], w, h, check_mode, s));
+                if (force != 1) HIPCHK((launch_pull_b<T, T, B>(t, ctl, pullp, w, h, check_mode, s)));
+            }
+            HIPCHK(hipMemcpyAsync(hc, ctl, sizeof(CtlB), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            if (hc->stop_after < t) {
+                stopped = true;
+                break;
+            }
+            double worst = 0.0;
+            for (int j = 0; j < kb; ++j)
+                if (hc->col_stop[j] >= t) worst = std::max(worst, hc->last_bound[j]);
+            batch = next_batch(batch, bound_prev, worst, t - t_prev, tol, l1);
+            bound_prev = worst;
+            t_prev = t;
+        }
+    } else {
+        stopped = true;
+    }
+    if (nD > 0) HIPCHK(launch_phase2_b<T, B>(n, nN, G.perm, ss, h, pibar, G.deg, c, w2, xD, G.bp_pull_nd[slot], s));
+    double *dst = out_dev ? pi_rows : outbuf;
+    OutSet os;
+    for (int j = 0; j < kMaxBatch; ++j) os.p[j] = j < kb ? dst + (size_t)j * n : nullptr;
+    HIPCHK(launch_final_b<T, B>(ctl, n, nN, G.perm, kmask, os, h, pibar, xD, part, s));
+    HIPCHK(hipEventRecord(ev_solve.b, s));
+    HIPCHK(hipMemcpyAsync(hc, ctl, sizeof(CtlB), hipMemcpyDeviceToHost, s));
+    if (!out_dev) HIPCHK(hipMemcpyAsync(pi_rows, outbuf, sizeof(double) * (size_t)kb * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) {
+        const double secs = elapsed_s(ev_solve.a, ev_solve.b);
+        for (int j = 0; j < kb; ++j) {
+            pr_stats z;
+            memset(&z, 0, sizeof(z));
+            z.sweeps = hc->col_sweeps[j];
+            z.pull_sweeps = hc->pull_sweeps;
+            z.edges_processed = (int64_t)hc->tot_edges[j] + G.mND;
+            z.edges_traversed = (int64_t)hc->tot_traversed + G.mND;
+            z.vertex_pushes = (int64_t)hc->tot_pushes[j];
+            z.residual_l1 = hc->fin_sum[j] > 0 ? hc->fin_sn[j] / hc->fin_sum[j] : 0.0;
+            z.l1_bound = hc->fin_sum[j] > 0 ? 2.0 * c / (1.0 - c) * hc->fin_sn[j] / hc->fin_sum[j] : 0.0;
+            z.seconds_solve = secs;
+            z.seconds_preprocess = G.seconds_split;
+            st[j] = z;
+        }
+    }
+    return stopped ? PR_OK : PR_ENOCONV;
+}
+
+
+pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *rep) {
+    const double t_start = (double)clock_now_ns() * 1e-9;
+    if (reps <= 0) reps = 2;
+    pr_tune_report r;
+    memset(&r, 0, sizeof(r));
+    double *out = nullptr;
+    HIPCHK(hipMalloc((void **)&out, sizeof(double) * (size_t)G.n));
+    struct Free {
+        double *p;
+        ~Free() { (void)hipFree(p); }
+    } fr{out};
+    pr_opts op = o;
+    op.flags = (o.flags & ~(PR_OUT_DEVICE | PR_PROFILE | PR_JACOBI)) | PR_OUT_DEVICE;
+    const bool can_order = G.grp.size() > 2 && !G.grp_pull.empty();
+    double best = INFINITY;
+    int best_i = 0;
+    for (int32_t shift = 2; shift <= 4; ++shift) {
+        pr_status ps = replan(G, 1 << shift, G.stream);
+        if (ps != PR_OK) return ps;
+        for (int ord = 0; ord <= (can_order ? 1 : 0); ++ord) {
+            G.prefer_ordered = ord == 1;
+            double ms = INFINITY;
+            int32_t sweeps = 0;
+            for (int32_t q = 0; q <= reps; ++q) {
+                pr_stats st;
+                ps = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, -1, op, out, &st)
+                                                : solve_ifp_t<double>(G, true, nullptr, -1, op, out, &st);
+                if (ps < 0) return ps;
+                if (q > 0) ms = std::min(ms, st.seconds_solve * 1e3);
+                sweeps = st.sweeps;
+            }
+            const int i = r.candidates++;
+            r.tile_shift[i] = shift;
+            r.ordered[i] = ord;
+            r.ms[i] = ms;
+            r.sweeps[i] = sweeps;
+            if (ms < best) {
+                best = ms;
+                best_i = i;
+            }
+        }
+    }
+    r.chosen = best_i;
+    pr_status ps = replan(G, 1 << r.tile_shift[best_i], G.stream);
+    if (ps != PR_OK) return ps;
+    G.prefer_ordered = r.ordered[best_i] == 1;
+    r.seconds = (double)clock_now_ns() * 1e-9 - t_start;
+    if (rep) *rep = r;
+    return PR_OK;
+}
+
+template pr_status solve_ifp_t<float>(const Graph &, bool, const double *, int32_t, const pr_opts &, double *,
+                                      pr_stats *, const WarmArgs *);
+template pr_status solve_ifp_t<double>(const Graph &, bool, const double *, int32_t, const pr_opts &, double *,
+                                       pr_stats *, const WarmArgs *);
+template pr_status solve_power_t<float>(const Graph &, const double *, const pr_opts &, double *, pr_stats *);
+template pr_status solve_power_t<double>(const Graph &, const double *, const pr_opts &, double *, pr_stats *);
+template pr_status solve_ppr_batch_t<float, 8>(const Graph &, const int32_t *, int, const pr_opts &, double *,
+                                               pr_stats *);
+template pr_status solve_ppr_batch_t<float, 16>(const Graph &, const int32_t *, int, const pr_opts &, double *,
+                                                pr_stats *);
+template pr_status solve_ppr_batch_t<double, 8>(const Graph &, const int32_t *, int, const pr_opts &, double *,
+                                                pr_stats *);
+template pr_status solve_ppr_batch_t<double, 16>(const Graph &, const int32_t *, int, const pr_opts &, double *,
+                                                 pr_stats *);
+
+}  // namespace host
+
+pr_status batch_plans(Graph &G, int B, hipStream_t s) {
+    return B == 8 ? host::ensure_batch_plans_impl<8>(G, s) : host::ensure_batch_plans_impl<16>(G, s);
+}
+
+}  // namespace prk
