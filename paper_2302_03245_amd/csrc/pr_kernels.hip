@@ -584,10 +584,10 @@ __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int chec
 // atomics except for the first and last row of a tile.  Same merge-path tiling
 // as the push; all w_u of a tile's in-edges are first gathered into LDS in one
 // batched pass, then each thread walks its rows + edges from LDS, with sums
-// carried in FP64.  A row finished by one thread is written directly; pieces
-// of rows shared by several threads meet in an LDS accumulator (hardware LDS
-// FP64 add), so a hub row costs one global atomic per tile instead of one per
-// thread.
+// carried in FP64.  Every row's sum meets in an LDS accumulator (a plain store
+// for a row one thread holds whole, a hardware LDS add for pieces of rows
+// shared by threads), and the tile writes its rows out together at the end, so
+// a hub row costs one global atomic per tile instead of one per thread.
 template <typename WT, typename OT, int K>
 __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
                                                  int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
@@ -612,32 +612,31 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
         const uint32_t e0 = a.y, e1 = b.y;
         const int32_t nr = i1 - i0 + 1;
         const uint32_t first = rp[i0];  // first edge of row i0
-        {
-            // nr <= IPB + 1 rows: K + 1 unconditional (clamped) loads per thread
-            uint32_t rv[K + 1];
-#pragma unroll
-            for (int j = 0; j <= K; ++j) rv[j] = ld_stream(rp + i0 + 1 + min((int32_t)threadIdx.x + j * kBlock, nr - 1));
-#pragma unroll
-            for (int j = 0; j <= K; ++j) {
-                const int32_t kk = threadIdx.x + j * kBlock;
-                if (kk < nr) {
-                    // the row of the tile's first item ends at or after it
-                    s_end[kk] = (uint16_t)min(rv[j] - rp0 + (uint32_t)(i0 + kk) - base, (uint32_t)IPB);
-                    s_acc[kk] = (AccT)0;
-                }
-            }
-        }
-        // gather phase: every in-edge of the tile at once.  Indices are clamped so
-        // that all loads are unconditional and issue back to back: K coalesced
-        // source-id loads, then K independent weight loads in flight per thread.
         const int32_t ne = (int32_t)(e1 - e0);
-        if (ne > 0) {
-            int32_t sidx[K];
-            WT v[K];
+        // Every load of the tile issues before the first LDS store, indices clamped so
+        // that the loads are unconditional and back to back: K + 1 row ends (nr <= IPB + 1
+        // rows), K coalesced source ids, then K independent weights in flight per thread.
+        uint32_t rv[K + 1];
+        int32_t sidx[K];
+        WT v[K];
+#pragma unroll
+        for (int j = 0; j <= K; ++j) rv[j] = ld_stream(rp + i0 + 1 + min((int32_t)threadIdx.x + j * kBlock, nr - 1));
+        if (ne > 0) {  // uniform over the workgroup
 #pragma unroll
             for (int j = 0; j < K; ++j) sidx[j] = ld_stream(src + e0 + min((int32_t)threadIdx.x + j * kBlock, ne - 1));
 #pragma unroll
             for (int j = 0; j < K; ++j) v[j] = w[sidx[j]];
+        }
+#pragma unroll
+        for (int j = 0; j <= K; ++j) {
+            const int32_t kk = threadIdx.x + j * kBlock;
+            if (kk < nr) {
+                // the row of the tile's first item ends at or after it
+                s_end[kk] = (uint16_t)min(rv[j] - rp0 + (uint32_t)(i0 + kk) - base, (uint32_t)IPB);
+                s_acc[kk] = (AccT)0;
+            }
+        }
+        if (ne > 0) {
 #pragma unroll
             for (int j = 0; j < K; ++j) {
                 const int32_t e = threadIdx.x + j * kBlock;
@@ -667,12 +666,9 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
             for (; d < dr_end; ++d) {
                 if (d == s_end[k]) {
                     if (touched) {
-                        if (owned) {
-                            OT *o = out + (i0 + k);
-                            *o = (OT)((double)*o + acc);
-                        } else {
-                            atomicAdd(s_acc + k, (AccT)acc);
-                        }
+                        // a row this thread holds whole has no other writer in the tile
+                        if (owned) s_acc[k] = (AccT)acc;
+                        else atomicAdd(s_acc + k, (AccT)acc);
                     }
                     acc = 0.0;
                     touched = false;
@@ -687,7 +683,9 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
             if (touched) atomicAdd(s_acc + k, (AccT)acc);
         }
         __syncthreads();
-        // rows strictly inside the tile belong to this workgroup alone
+        // every row's sum goes out here, one coalesced read-modify-write per row (no
+        // dependent global loads inside the walk above); rows strictly inside the
+        // tile belong to this workgroup alone
         for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
             double v = (double)s_acc[k];
             if (v == 0.0) continue;
