@@ -154,7 +154,6 @@ struct SweepTimer {
 // partials of one solve: the synchronous sweep's 5 x kRedBlocks, or the ordered
 // sweep's 5 x kGroupBlocks per group plus kRedBlocks for the residual sum; a
 // group's reserve takes one workgroup per 1024 vertices, up to kGroupBlocks
-constexpr int kGroupBlocks = 1024;
 constexpr size_t kPartDoubles = (size_t)5 * kGroupBlocks * kMaxGroups + kRedBlocks;
 static_assert(kPartDoubles >= (size_t)5 * kRedBlocks, "partials");
 

@@ -17,6 +17,7 @@ constexpr int kBlock = 256;       // threads per workgroup (4 wave64)
 constexpr int kMaxTrace = 4096;   // per-sweep trace entries kept on the device
 constexpr int kRedBlocks = 1024;  // max workgroups of a streaming kernel that feeds a reduction
 constexpr int kMaxGroups = 15;    // vertex groups of ordered sweeps
+constexpr int kGroupBlocks = 1024;  // max workgroups of one group's reserve in an ordered sweep
 
 // workgroups of each group's reserve in an ordered sweep; group g's five partial
 // arrays (nb[g] entries each) start at part + 5 * stride * g

@@ -311,27 +311,68 @@ __global__ void k_init_ifp(InitArgs a, T *h, double *pibar) {
     }
 }
 
+// Sums of N values over the workgroup in one pass (results in thread 0, each
+// summed in the same order as block_sum); sbuf holds N * kBlock / W entries.
+template <int N>
+__device__ __forceinline__ void block_sum_n(double (&v)[N], double *sbuf) {
+    constexpr int NW = kBlock / W;
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] = wave_sum(v[q]);
+    if (lane_id() == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) sbuf[q * NW + threadIdx.x / W] = v[q];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double r = 0.0;
+#pragma unroll
+            for (int k = 0; k < NW; ++k) r += sbuf[q * NW + k];
+            v[q] = r;
+        }
+    }
+}
+
 // Reserve step of one sweep (the body of the calculation threads' loop):
 // every non-dangling i with h_i > xi moves its residual v into pibar_i and
 // publishes its push weight w_i = c v / deg(i); others publish 0.  Per
 // workgroup partial sums: residual left on inactive vertices, mass this
 // sweep sends to non-dangling vertices, growth of the total mass, active
-// vertices and their valid edges.
+// vertices and their valid edges.  When the grid holds one vertex per thread
+// (the small vertex groups of ordered sweeps) the kernel is bound by the
+// latency of its loads, and a vertex's degree, row offsets and pibar are
+// loaded together with its residual instead of after the test.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w,
                                                     double *pibar, const int32_t *deg, const uint32_t *rp_nn,
                                                     double c, T xi, int ifp2, double *part) {
     if (t > ctl->stop_after) return;
+    const bool one_each = (int64_t)(hi - lo) <= (int64_t)gridDim.x * kBlock;  // uniform over the grid
     double inact = 0.0, pred = 0.0, sxinc = 0.0;
     unsigned long long cnt = 0, edges = 0;
     for (int64_t i = lo + blockIdx.x * (int64_t)kBlock + threadIdx.x; i < hi; i += (int64_t)gridDim.x * kBlock) {
         T hv = h[i];
+        int32_t dg = 0;
+        uint32_t r0 = 0, r1 = 0;
+        double pb = 0.0;
+        if (one_each) {
+            dg = deg[i];
+            r0 = rp_nn[i];
+            r1 = rp_nn[i + 1];
+            pb = pibar[i];
+        }
         // |h_i| > xi: residuals are non-negative except after a warm start
         if (hv > xi || hv < -xi) {
-            int32_t dg = deg[i];
-            uint32_t dnn = rp_nn[i + 1] - rp_nn[i];
+            if (!one_each) {
+                dg = deg[i];
+                r0 = rp_nn[i];
+                r1 = rp_nn[i + 1];
+                pb = pibar[i];
+            }
+            const uint32_t dnn = r1 - r0;
             double v = (double)hv;
-            pibar[i] += v;
+            pibar[i] = pb + v;
             h[i] = (T)0;
             w[i] = (T)(c * v / (double)dg);
             double fN = (double)dnn / (double)dg;
@@ -344,19 +385,13 @@ __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32
             inact += fabs((double)hv);
         }
     }
-    __shared__ double sd[kBlock / W];
-    inact = block_sum(inact, sd);
-    pred = block_sum(pred, sd);
-    sxinc = block_sum(sxinc, sd);
-    double dc = block_sum((double)cnt, sd);
-    double de = block_sum((double)edges, sd);
+    __shared__ double sd[5 * (kBlock / W)];
+    double v[5] = {inact, pred, sxinc, (double)cnt, (double)edges};
+    block_sum_n(v, sd);
     if (threadIdx.x == 0) {
         const int nb = gridDim.x, b = blockIdx.x;
-        part[b] = inact;
-        part[nb + b] = pred;
-        part[2 * nb + b] = sxinc;
-        part[3 * nb + b] = dc;
-        part[4 * nb + b] = de;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) part[q * nb + b] = v[q];
     }
 }
 
@@ -378,9 +413,20 @@ __device__ __forceinline__ double l1_bound_of(double k, double sn, double sx, in
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t nN, const T *h, double *part) {
     if (t > ctl->stop_after) return;
+    // eight loads in flight per thread, added in index order
+    constexpr int U = 8;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
     double s = 0.0;
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock)
-        s += fabs((double)h[i]);
+    for (int64_t i0 = blockIdx.x * (int64_t)kBlock + threadIdx.x; i0 < nN; i0 += U * stride) {
+        T x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * stride;
+            x[u] = i < nN ? h[i] : (T)0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += fabs((double)x[u]);
+    }
     __shared__ double sd[kBlock / W];
     s = block_sum(s, sd);
     if (threadIdx.x == 0) part[blockIdx.x] = s;
@@ -396,23 +442,51 @@ __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr
                                                       int stop_l1, double tol, unsigned long long pull_thr,
                                                       unsigned long long pull_edges) {
     if (t > ctl->stop_after) return;
-    __shared__ double sd[kBlock / W];
+    // a group has at most kGroupRounds * kBlock reserve workgroups (and k_sum_h at
+    // most as many): every partial of a group, or of S_N, is loaded before any is added
+    constexpr int kGroupRounds = 4;
+    static_assert(kGroupBlocks <= kGroupRounds * kBlock && kRedBlocks <= kGroupRounds * kBlock, "partials");
+    __shared__ double sd[4 * (kBlock / W)];
     double a_sx = 0.0, a_cd = 0.0, a_ed = 0.0, sn = 0.0;
     for (int g = 0; g < ng; ++g) {
         const double *pg = part + (size_t)g * 5 * gb.stride;
         const int nb = gb.nb[g];
-        for (int b = threadIdx.x; b < nb; b += kBlock) {
-            a_sx += pg[2 * nb + b];
-            a_cd += pg[3 * nb + b];
-            a_ed += pg[4 * nb + b];
+        double x[kGroupRounds][3];
+#pragma unroll
+        for (int r = 0; r < kGroupRounds; ++r) {
+            const int b = threadIdx.x + r * kBlock;
+            const bool in = b < nb;
+            x[r][0] = in ? pg[2 * nb + b] : 0.0;
+            x[r][1] = in ? pg[3 * nb + b] : 0.0;
+            x[r][2] = in ? pg[4 * nb + b] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kGroupRounds; ++r) {
+            if (threadIdx.x + r * kBlock < nb) {
+                a_sx += x[r][0];
+                a_cd += x[r][1];
+                a_ed += x[r][2];
+            }
         }
     }
-    for (int b = threadIdx.x; b < nbs; b += kBlock) sn += part_s[b];
-    a_sx = block_sum(a_sx, sd);
-    a_cd = block_sum(a_cd, sd);
-    a_ed = block_sum(a_ed, sd);
-    sn = block_sum(sn, sd);
+    {
+        double x[kGroupRounds];
+#pragma unroll
+        for (int r = 0; r < kGroupRounds; ++r) {
+            const int b = threadIdx.x + r * kBlock;
+            x[r] = b < nbs ? part_s[b] : 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kGroupRounds; ++r)
+            if (threadIdx.x + r * kBlock < nbs) sn += x[r];
+    }
+    double v[4] = {a_sx, a_cd, a_ed, sn};
+    block_sum_n(v, sd);
     if (threadIdx.x != 0) return;
+    a_sx = v[0];
+    a_cd = v[1];
+    a_ed = v[2];
+    sn = v[3];
     const unsigned long long a_c = (unsigned long long)a_cd, a_e = (unsigned long long)a_ed;
     const double k = 2.0 * c / (1.0 - c);
     const double sx = ctl->sx + c * a_sx;
