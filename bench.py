@@ -48,15 +48,16 @@ def kernel_source_sha(kernel: str = "pull", kernels_src=None, device_src=None):
     return hashlib.sha1(body.encode()).hexdigest()[:12]
 
 
-def traffic_from_profiles(kernel: str, workload: str, alg_bytes_per_launch: float):
+def traffic_from_profiles(kernel: str, workload: str, alg_bytes_per_launch: float, tile_items: int):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if it was taken
-    on the current kernel source and on launches of the same size (algorithmic bytes per
-    launch within 1 %); else None."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    on the current kernel source, with the same workgroup tile and on launches of the
+    same size (algorithmic bytes per launch within 1 %: one group's gather of an ordered
+    sweep, or a synchronous sweep's whole gather); else None."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}_t{tile_items}.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
-    if d.get("kernel_source_sha") != kernel_source_sha(kernel):
+    if d.get("kernel_source_sha") != kernel_source_sha(kernel) or d.get("tile_items") != tile_items:
         return None
     ref = d.get("algorithmic_bytes_per_launch") or 0.0
     if abs(ref - alg_bytes_per_launch) > 0.01 * alg_bytes_per_launch:
@@ -188,7 +189,7 @@ def main():
     launches = sum(s[f"{kern}_launches"] for s in prof)
     kbytes = sum(s[f"{kern}_bytes"] for s in prof)
     achieved = kbytes / secs / 1e9 if secs > 0 else 0.0
-    traffic = traffic_from_profiles(kern, wl_key, kbytes / max(launches, 1))
+    traffic = traffic_from_profiles(kern, wl_key, kbytes / max(launches, 1), int(info["tile_items"]))
     avg_s = secs / max(launches, 1)
     roofline = {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": achieved / PEAK_HBM_GBS, "traffic": traffic,
