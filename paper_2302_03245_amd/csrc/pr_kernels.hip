@@ -339,43 +339,32 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N], double *sbuf) {
 // publishes its push weight w_i = c v / deg(i); others publish 0.  Per
 // workgroup partial sums: residual left on inactive vertices, mass this
 // sweep sends to non-dangling vertices, growth of the total mass, active
-// vertices and their valid edges.  When the grid holds one vertex per thread
-// (the small vertex groups of ordered sweeps) the kernel is bound by the
-// latency of its loads, and a vertex's degree, row offsets and pibar are
-// loaded together with its residual instead of after the test.
+// vertices and their valid edges.  The kernel is bound by the latency of its
+// loads when the grid holds about one vertex per thread (the small vertex
+// groups of ordered sweeps) and when most vertices are active (a dense
+// frontier: ctl->use_pull, set by the last decision): then a vertex's degree,
+// row offsets and pibar are loaded together with its residual, two vertices
+// per iteration, instead of after the test.  Sums run in the same order either way.
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w,
                                                     double *pibar, const int32_t *deg, const uint32_t *rp_nn,
                                                     double c, T xi, int ifp2, double *part) {
     if (t > ctl->stop_after) return;
-    const bool one_each = (int64_t)(hi - lo) <= (int64_t)gridDim.x * kBlock;  // uniform over the grid
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    // uniform over the grid
+    const bool eager = (int64_t)(hi - lo) <= stride || ctl->use_pull != 0;
     double inact = 0.0, pred = 0.0, sxinc = 0.0;
     unsigned long long cnt = 0, edges = 0;
-    for (int64_t i = lo + blockIdx.x * (int64_t)kBlock + threadIdx.x; i < hi; i += (int64_t)gridDim.x * kBlock) {
-        T hv = h[i];
-        int32_t dg = 0;
-        uint32_t r0 = 0, r1 = 0;
-        double pb = 0.0;
-        if (one_each) {
-            dg = deg[i];
-            r0 = rp_nn[i];
-            r1 = rp_nn[i + 1];
-            pb = pibar[i];
-        }
+    // one vertex whose inputs are loaded (dg, r0, r1, pb are read only when active)
+    auto take = [&](int64_t i, T hv, int32_t dg, uint32_t r0, uint32_t r1, double pb) {
         // |h_i| > xi: residuals are non-negative except after a warm start
         if (hv > xi || hv < -xi) {
-            if (!one_each) {
-                dg = deg[i];
-                r0 = rp_nn[i];
-                r1 = rp_nn[i + 1];
-                pb = pibar[i];
-            }
             const uint32_t dnn = r1 - r0;
-            double v = (double)hv;
+            const double v = (double)hv;
             pibar[i] = pb + v;
             h[i] = (T)0;
             w[i] = (T)(c * v / (double)dg);
-            double fN = (double)dnn / (double)dg;
+            const double fN = (double)dnn / (double)dg;
             pred += fabs(v) * fN;
             sxinc += ifp2 ? v * fN : v;
             cnt += 1;
@@ -383,6 +372,36 @@ __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32
         } else {
             w[i] = (T)0;
             inact += fabs((double)hv);
+        }
+    };
+    int64_t i = lo + blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (eager) {
+        for (; i < hi; i += 2 * stride) {
+            const int64_t i2 = i + stride;
+            const bool two = i2 < hi;
+            const T hv = h[i];
+            const int32_t dg = deg[i];
+            const uint32_t r0 = rp_nn[i], r1 = rp_nn[i + 1];
+            const double pb = pibar[i];
+            T hv2 = (T)0;
+            int32_t dg2 = 1;
+            uint32_t s0 = 0, s1 = 0;
+            double pb2 = 0.0;
+            if (two) {
+                hv2 = h[i2];
+                dg2 = deg[i2];
+                s0 = rp_nn[i2];
+                s1 = rp_nn[i2 + 1];
+                pb2 = pibar[i2];
+            }
+            take(i, hv, dg, r0, r1, pb);
+            if (two) take(i2, hv2, dg2, s0, s1, pb2);
+        }
+    } else {
+        for (; i < hi; i += stride) {
+            const T hv = h[i];
+            if (hv > xi || hv < -xi) take(i, hv, deg[i], rp_nn[i], rp_nn[i + 1], pibar[i]);
+            else take(i, hv, 0, 0, 0, 0.0);
         }
     }
     __shared__ double sd[5 * (kBlock / W)];
