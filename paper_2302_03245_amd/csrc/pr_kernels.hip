@@ -692,9 +692,11 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
     // footprints let more workgroups share a CU
     using AccT = typename std::conditional<sizeof(OT) == 4, float, double>::type;
     if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
-    __shared__ uint16_t s_end[IPB + 1];  // row ends in tile items, clamped to IPB
+    // exactly 2 IPB + 4 IPB + 4 IPB bytes (FP32), so that 4 (IPB = 4096) or 8 (2048)
+    // workgroups fill the 160 KB of LDS of a CU
+    __shared__ uint16_t s_end[IPB];  // row ends in tile items, clamped to IPB
     __shared__ WT s_val[IPB];
-    __shared__ AccT s_acc[IPB + 1];
+    __shared__ AccT s_acc[IPB];
     const uint32_t rp0 = rp[0];
     for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
         if (skip.tgr && tile_frozen(skip, tile, t)) continue;  // uniform over the workgroup
@@ -703,17 +705,20 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
         const int32_t i0 = (int32_t)a.x;
         const int32_t i1 = min((int32_t)b.x, R - 1);
         const uint32_t e0 = a.y, e1 = b.y;
-        const int32_t nr = i1 - i0 + 1;
+        // A tile of IPB items touches IPB + 1 rows only when all its items end rows
+        // i0 .. i0 + IPB - 1 (it holds no edge): row i0 + IPB then has no item here and
+        // is left out, so at most IPB rows are kept.
+        const int32_t nr = min(i1 - i0 + 1, IPB);
         const uint32_t first = rp[i0];  // first edge of row i0
         const int32_t ne = (int32_t)(e1 - e0);
         // Every load of the tile issues before the first LDS store, indices clamped so
-        // that the loads are unconditional and back to back: K + 1 row ends (nr <= IPB + 1
-        // rows), K coalesced source ids, then K independent weights in flight per thread.
-        uint32_t rv[K + 1];
+        // that the loads are unconditional and back to back: K row ends (nr <= IPB rows),
+        // K coalesced source ids, then K independent weights in flight per thread.
+        uint32_t rv[K];
         int32_t sidx[K];
         WT v[K];
 #pragma unroll
-        for (int j = 0; j <= K; ++j) rv[j] = ld_stream(rp + i0 + 1 + min((int32_t)threadIdx.x + j * kBlock, nr - 1));
+        for (int j = 0; j < K; ++j) rv[j] = ld_stream(rp + i0 + 1 + min((int32_t)threadIdx.x + j * kBlock, nr - 1));
         if (ne > 0) {  // uniform over the workgroup
 #pragma unroll
             for (int j = 0; j < K; ++j) sidx[j] = ld_stream(src + e0 + min((int32_t)threadIdx.x + j * kBlock, ne - 1));
@@ -721,7 +726,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
             for (int j = 0; j < K; ++j) v[j] = w[sidx[j]];
         }
 #pragma unroll
-        for (int j = 0; j <= K; ++j) {
+        for (int j = 0; j < K; ++j) {
             const int32_t kk = threadIdx.x + j * kBlock;
             if (kk < nr) {
                 // the row of the tile's first item ends at or after it
