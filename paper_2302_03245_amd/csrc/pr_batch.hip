@@ -206,18 +206,20 @@ __global__ __launch_bounds__(kBlock) void k_push_b(int t, const CtlB *ctl, int c
 // in-edges.  The tile's B-wide weight segments are first gathered into LDS
 // (consecutive lanes read consecutive columns of one source), then a group of
 // B lanes walks the tile's items, lane j summing column j in FP64; rows shared
-// by groups meet in an LDS FP64 accumulator, rows shared by tiles through one
-// global atomic per column and tile.
+// by groups meet in an LDS accumulator (FP64, FP32 when the output is FP32: the
+// sum is rounded to FP32 when it reaches the output anyway), rows shared by tiles
+// through one global atomic per column and tile.
 template <typename WT, typename OT, int B, int K>
 __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int check_mode, const uint32_t *rp,
                                                    int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
                                                    int32_t ntiles, const WT *w, OT *out) {
     constexpr int G = kBlock / B;
     constexpr int IPB = G * K;
+    using AccT = typename std::conditional<sizeof(OT) == 4, float, double>::type;
     if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
-    __shared__ uint32_t s_end[IPB + 1];
+    __shared__ uint32_t s_end[IPB];
     __shared__ WT s_val[IPB * B];
-    __shared__ double s_acc[(IPB + 1) * B];
+    __shared__ AccT s_acc[IPB * B];
     const uint32_t rp0 = rp[0];
     const int g = threadIdx.x / B, j = threadIdx.x % B;
     for (int32_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
@@ -225,10 +227,12 @@ __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int c
         const int32_t i0 = (int32_t)a.x;
         const int32_t i1 = min((int32_t)b.x, R - 1);
         const uint32_t e0 = a.y, e1 = b.y;
-        const int32_t nr = i1 - i0 + 1;
+        // a tile of IPB items touches IPB + 1 rows only when all its items end rows (it
+        // holds no edge): the last of them then has no item here and is left out
+        const int32_t nr = min(i1 - i0 + 1, IPB);
         const uint32_t first = rp[i0];
         for (int32_t kk = threadIdx.x; kk < nr; kk += kBlock) s_end[kk] = rp[i0 + 1 + kk] - rp0 + (uint32_t)(i0 + kk);
-        for (int32_t q = threadIdx.x; q < nr * B; q += kBlock) s_acc[q] = 0.0;
+        for (int32_t q = threadIdx.x; q < nr * B; q += kBlock) s_acc[q] = (AccT)0;
         const int32_t ne = (int32_t)(e1 - e0);
         if (ne > 0) {
             // element q = e * B + column; K per thread, loads issued back to back
@@ -270,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int c
                             OT *o = out + (int64_t)(i0 + k) * B + j;
                             *o = (OT)((double)*o + acc);
                         } else {
-                            atomicAdd(s_acc + k * B + j, acc);
+                            atomicAdd(s_acc + k * B + j, (AccT)acc);
                         }
                     }
                     acc = 0.0;
@@ -283,11 +287,11 @@ __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int c
                     ++et;
                 }
             }
-            if (touched) atomicAdd(s_acc + k * B + j, acc);
+            if (touched) atomicAdd(s_acc + k * B + j, (AccT)acc);
         }
         __syncthreads();
         for (int32_t q = threadIdx.x; q < nr * B; q += kBlock) {
-            const double v = s_acc[q];
+            const double v = (double)s_acc[q];
             if (v == 0.0) continue;
             const int32_t k = q / B;
             OT *o = out + (int64_t)i0 * B + q;
