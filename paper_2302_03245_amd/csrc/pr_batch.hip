@@ -207,8 +207,9 @@ __global__ __launch_bounds__(kBlock) void k_push_b(int t, const CtlB *ctl, int c
 // (consecutive lanes read consecutive columns of one source), then a group of
 // B lanes walks the tile's items, lane j summing column j in FP64; rows shared
 // by groups meet in an LDS accumulator (FP64, FP32 when the output is FP32: the
-// sum is rounded to FP32 when it reaches the output anyway), rows shared by tiles
-// through one global atomic per column and tile.
+// sum is rounded to FP32 when it reaches the output anyway), and so do rows one
+// group holds whole; the tile then writes all its rows out in one coalesced pass,
+// rows shared by tiles through one global atomic per column and tile.
 template <typename WT, typename OT, int B, int K>
 __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int check_mode, const uint32_t *rp,
                                                    int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
@@ -270,12 +271,9 @@ __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int c
             for (; d < dend; ++d) {
                 if (d == s_end[k]) {
                     if (touched) {
-                        if (owned) {
-                            OT *o = out + (int64_t)(i0 + k) * B + j;
-                            *o = (OT)((double)*o + acc);
-                        } else {
-                            atomicAdd(s_acc + k * B + j, (AccT)acc);
-                        }
+                        // a row this lane group holds whole has no other writer in the tile
+                        if (owned) s_acc[k * B + j] = (AccT)acc;
+                        else atomicAdd(s_acc + k * B + j, (AccT)acc);
                     }
                     acc = 0.0;
                     touched = false;
