@@ -216,6 +216,7 @@ __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int c
                                                    int32_t ntiles, const WT *w, OT *out) {
     constexpr int G = kBlock / B;
     constexpr int IPB = G * K;
+    static_assert(IPB <= kBlock, "one row end per thread");
     using AccT = typename std::conditional<sizeof(OT) == 4, float, double>::type;
     if (t >= 0 && (t > ctl->stop_after || (check_mode && !ctl->use_pull))) return;
     __shared__ uint32_t s_end[IPB];
@@ -232,13 +233,14 @@ __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int c
         // holds no edge): the last of them then has no item here and is left out
         const int32_t nr = min(i1 - i0 + 1, IPB);
         const uint32_t first = rp[i0];
-        for (int32_t kk = threadIdx.x; kk < nr; kk += kBlock) s_end[kk] = rp[i0 + 1 + kk] - rp0 + (uint32_t)(i0 + kk);
-        for (int32_t q = threadIdx.x; q < nr * B; q += kBlock) s_acc[q] = (AccT)0;
         const int32_t ne = (int32_t)(e1 - e0);
-        if (ne > 0) {
-            // element q = e * B + column; K per thread, loads issued back to back
-            int32_t sidx[K];
-            WT v[K];
+        // Every load of the tile issues before the first LDS store: one row end per
+        // thread (nr <= IPB <= kBlock), then K source ids (element q = e * B + column)
+        // and K weights, indices clamped so that the loads are unconditional.
+        const uint32_t rv = rp[i0 + 1 + min((int32_t)threadIdx.x, nr - 1)];
+        int32_t sidx[K];
+        WT v[K];
+        if (ne > 0) {  // uniform over the workgroup
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 const int32_t q = threadIdx.x + r * kBlock;
@@ -246,6 +248,10 @@ __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int c
             }
 #pragma unroll
             for (int r = 0; r < K; ++r) v[r] = w[(int64_t)sidx[r] * B + j];
+        }
+        if ((int32_t)threadIdx.x < nr) s_end[threadIdx.x] = rv - rp0 + (uint32_t)(i0 + threadIdx.x);
+        for (int32_t q = threadIdx.x; q < nr * B; q += kBlock) s_acc[q] = (AccT)0;
+        if (ne > 0) {
 #pragma unroll
             for (int r = 0; r < K; ++r) {
                 const int32_t q = threadIdx.x + r * kBlock;
