@@ -184,9 +184,10 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
             int nb = std::min(batch, max_sweeps - t);
             for (int k = 0; k < nb; ++k, ++t) {
                 const MPPlan &pullp = pull_plan(t);
-                // a gather reads every live in-edge; scatter when the active edges are fewer than half of them
+                // a gather reads every live in-edge; scatter while the active edges are a
+                // smaller share of them than kScatterShare
                 const unsigned long long pull_edges = (unsigned long long)pullp.edges();
-                const unsigned long long pull_thr = (unsigned long long)(0.5 * (double)pull_edges) + 1;
+                const unsigned long long pull_thr = (unsigned long long)(kScatterShare * (double)pull_edges) + 1;
                 if (ordered) {
                     size_t e = 0;
                     while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
