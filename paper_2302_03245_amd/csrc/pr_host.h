@@ -157,11 +157,6 @@ struct SweepTimer {
 constexpr size_t kPartDoubles = (size_t)5 * kGroupBlocks * kMaxGroups + kRedBlocks;
 static_assert(kPartDoubles >= (size_t)5 * kRedBlocks, "partials");
 
-// A single-vector sweep scatters (one FP32 / FP64 atomic per active edge, about
-// 21 G/s for random targets) while its active edges are below this share of the
-// edges a gather would read (a gather reads all of them at about 200 G/s).
-constexpr double kScatterShare = 0.1;
-
 // state of a warm start (device, original ids): read at the start, written at the end
 struct WarmArgs {
     double *pibar;

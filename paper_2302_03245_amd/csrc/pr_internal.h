@@ -18,6 +18,10 @@ constexpr int kMaxTrace = 4096;   // per-sweep trace entries kept on the device
 constexpr int kRedBlocks = 1024;  // max workgroups of a streaming kernel that feeds a reduction
 constexpr int kMaxGroups = 15;    // vertex groups of ordered sweeps
 constexpr int kGroupBlocks = 1024;  // max workgroups of one group's reserve in an ordered sweep
+// A single-vector or graph-set sweep scatters (one FP32 / FP64 atomic per active
+// edge, about 21 G/s for random targets) while its active edges are below this
+// share of the edges a gather would read (a gather reads all of them at about 200 G/s).
+constexpr double kScatterShare = 0.1;
 
 // workgroups of each group's reserve in an ordered sweep; group g's five partial
 // arrays (nb[g] entries each) start at part + 5 * stride * g

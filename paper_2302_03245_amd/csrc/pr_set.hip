@@ -282,7 +282,7 @@ __global__ __launch_bounds__(kDecideThreads) void k_set_decide(int t, Ctl *ctl, 
     }
     const unsigned long long ae = (unsigned long long)e;
     const double gather = lv * live_frac;  // in-edges a gather of the live graphs reads this sweep
-    const int pull = force == 1 ? 0 : (force == 2 ? 1 : (e >= 0.5 * gather + 1.0 ? 1 : 0));
+    const int pull = force == 1 ? 0 : (force == 2 ? 1 : (e >= kScatterShare * gather + 1.0 ? 1 : 0));
     ctl->use_pull = pull;
     ctl->sweeps = t + 1;
     ctl->pull_sweeps += pull;
