@@ -22,6 +22,10 @@ constexpr int kGroupBlocks = 1024;  // max workgroups of one group's reserve in 
 // edge, about 21 G/s for random targets) while its active edges are below this
 // share of the edges a gather would read (a gather reads all of them at about 200 G/s).
 constexpr double kScatterShare = 0.1;
+// A batched sweep scatters while its active (vertex, column) edges summed over the
+// columns are below this share of the edges its gather would read (the gather
+// serves all columns at once; the scatter's atomics of one edge hit adjacent columns).
+constexpr double kScatterShareBatch = 0.25;
 
 // workgroups of each group's reserve in an ordered sweep; group g's five partial
 // arrays (nb[g] entries each) start at part + 5 * stride * g

@@ -330,7 +330,7 @@ bool Engine::run() {
             while (e + 1 < g.epochs.size() && g.epochs[e + 1].t_start <= youngest) ++e;
             const MPPlan &pullp = g.bp_pull_nn[slot][e];
             chk(launch_reserve_b<T, Bw>(t, dctl, nN, h, w, pibar, g.deg, g.rp_nn, c, xi, 1, tol,
-                                        0.25 * (double)pullp.edges(), 0, (unsigned long long)pullp.edges(), part, s),
+                                        kScatterShareBatch * (double)pullp.edges(), 0, (unsigned long long)pullp.edges(), part, s),
                 "reserve");
             chk(launch_push_b<T, Bw>(t, dctl, g.bp_push_nn[slot], w, h, 1, s), "push");
             chk(launch_pull_b<T, T, Bw>(t, dctl, pullp, w, h, 1, s), "pull");

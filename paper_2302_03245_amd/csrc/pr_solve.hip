@@ -539,7 +539,7 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
             for (int k = 0; k < nbt; ++k, ++t) {
                 const MPPlan &pullp = pull_plan(t);
                 // a gather serves every column; scatter when the active (vertex, column) edges are few
-                const double pull_thr = 0.25 * (double)pullp.edges();
+                const double pull_thr = kScatterShareBatch * (double)pullp.edges();
                 HIPCHK(launch_reserve_b<T, B>(t, ctl, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, l1 ? 1 : 0, tol,
                                               pull_thr, force, (unsigned long long)pullp.edges(), part, s));
                 if (force != 2) HIPCHK(launch_push_b<T, B>(t, ctl, G.bp_push_nn[slot], w, h, check_mode, s));
