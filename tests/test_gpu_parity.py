@@ -267,6 +267,48 @@ def test_ppr_batches(pr, mode):
         assert l1(out32[r], ref) <= 1e-6, (r, s)
 
 
+def _edge_free_run(n_leaves=20000):
+    """Vertex 0 -> 1 and every leaf v >= 1 -> 0: all vertices have out-edges, and rows
+    2 .. n_leaves have no in-edge, so most gather tiles hold only row ends (a tile of
+    IPB items then spans IPB + 1 rows, of which the last has no item in it)."""
+    src = np.concatenate([[0], np.arange(1, n_leaves + 1)])
+    dst = np.concatenate([[1], np.zeros(n_leaves, int)])
+    return prgen.from_edges(n_leaves + 1, src, dst)
+
+
+@pytest.mark.parametrize("shift", [2, 3, 4])
+def test_tiles_of_row_ends_only(pr, shift):
+    g = _edge_free_run()
+    ref, _, _ = oracle.power(g, C, tol=1e-13)
+    dg = pr.upload(g.row_ptr, g.col, tile_shift=shift)
+    for method in ("ifp1", "ifp2"):
+        pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode="pull")
+        _say(f"shift {shift} {method}: sweeps {st['sweeps']} L1 {l1(pi, ref):.2e}")
+        assert st["status"] == 0 and l1(pi, ref) <= 1e-9
+        pi32, st32 = getattr(pr, method)(dg, c=C, l1_tol=1e-6, residual="fp32", mode="pull")
+        assert st32["l1_bound"] <= 1e-6 and l1(pi32, ref) <= 1e-6
+    pw, _ = pr.power(dg, c=C, l1_tol=1e-12)
+    assert l1(pw, ref) <= 1e-11
+    dg.free()
+
+
+def test_batched_tiles_of_row_ends_only(pr):
+    """The batched gather (128- and 256-item tiles for 16 and 8 columns) over the same
+    runs of rows without in-edges: every column against the oracle's PPR."""
+    g = _edge_free_run()
+    dg = pr.upload(g.row_ptr, g.col)
+    for srcs in ([0, 1, 2, 7, 19999, 20000] + list(range(100, 110)), [0, 5, 20000]):
+        out, stats = pr.ppr(dg, srcs, c=C, xi=1e-12, mode="pull")
+        out32, stats32 = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32", mode="pull")
+        for r, s in enumerate(srcs):
+            p = np.zeros(g.n)
+            p[s] = 1.0
+            ref, _, _ = oracle.power(g, C, p, tol=1e-13)
+            assert stats[r]["status"] == 0 and l1(out[r], ref) <= 1e-9, (len(srcs), s)
+            assert stats32[r]["l1_bound"] <= 1e-6 and l1(out32[r], ref) <= 1e-6, (len(srcs), s)
+    dg.free()
+
+
 def test_literal_ifp2_matches_oracle_literal(pr):
     g = prgen.random_digraph(4000, 30000, seed=9, dangling_frac=0.25)
     dg = pr.upload(g.row_ptr, g.col)
