@@ -455,7 +455,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t
 // reserved and gathered: the growth of the total mass and the work from the
 // groups' reserve partials (group g: gb.nb[g] workgroups, 5 sums each), S_N
 // from k_sum_h; stop when nothing was above the threshold or the certified
-// bound is met.  One pass over all partials, then one block sum per quantity.
+// bound is met.  One pass over all partials, then one workgroup reduction of
+// the four sums.
 __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr, int ng, GroupBlocks gb,
                                                       const double *part, int nbs, const double *part_s, double c,
                                                       int stop_l1, double tol, unsigned long long pull_thr,
