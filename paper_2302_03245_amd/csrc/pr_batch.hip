@@ -59,14 +59,13 @@ __global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, in
     const bool live = t <= ctl->col_stop[j];
     double inact = 0.0, pred = 0.0, cnt = 0.0, edges = 0.0;
     const int64_t total = (int64_t)nN * B;
-    for (int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * kBlock) {
-        const int64_t v = idx / B;
-        const T hv = h[idx];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    // one (vertex, column) entry whose inputs are loaded (dg, r0, r1, pb read only when active)
+    auto take = [&](int64_t idx, T hv, int32_t dg, uint32_t r0, uint32_t r1, double pb) {
         if (live && hv > xi) {
-            const int32_t dg = deg[v];
-            const uint32_t dnn = rp_nn[v + 1] - rp_nn[v];
+            const uint32_t dnn = r1 - r0;
             const double val = (double)hv;
-            pibar[idx] += val;
+            pibar[idx] = pb + val;
             h[idx] = (T)0;
             w[idx] = (T)(c * val / (double)dg);
             pred += val * ((double)dnn / (double)dg);
@@ -75,6 +74,42 @@ __global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, in
         } else {
             w[idx] = (T)0;
             inact += (double)hv;
+        }
+    };
+    int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (ctl->use_pull) {
+        // dense frontier (uniform over the grid): most entries are taken, so an entry's
+        // degree, row offsets and pibar are loaded with its residual, two entries per
+        // iteration, instead of after the test; sums run in the same order
+        for (; idx < total; idx += 2 * stride) {
+            const int64_t i2 = idx + stride;
+            const bool two = i2 < total;
+            const int64_t v = idx / B;
+            const T hv = h[idx];
+            const int32_t dg = deg[v];
+            const uint32_t r0 = rp_nn[v], r1 = rp_nn[v + 1];
+            const double pb = pibar[idx];
+            T hv2 = (T)0;
+            int32_t dg2 = 1;
+            uint32_t s0 = 0, s1 = 0;
+            double pb2 = 0.0;
+            if (two) {
+                const int64_t v2 = i2 / B;
+                hv2 = h[i2];
+                dg2 = deg[v2];
+                s0 = rp_nn[v2];
+                s1 = rp_nn[v2 + 1];
+                pb2 = pibar[i2];
+            }
+            take(idx, hv, dg, r0, r1, pb);
+            if (two) take(i2, hv2, dg2, s0, s1, pb2);
+        }
+    } else {
+        for (; idx < total; idx += stride) {
+            const int64_t v = idx / B;
+            const T hv = h[idx];
+            if (live && hv > xi) take(idx, hv, deg[v], rp_nn[v], rp_nn[v + 1], pibar[idx]);
+            else take(idx, hv, 0, 0, 0, 0.0);
         }
     }
     __shared__ double sd[kBlock / W * B];
