@@ -135,11 +135,21 @@ __global__ __launch_bounds__(1024) void k_decide_b(int t, CtlB *ctl, int nb, con
                                                      unsigned long long pull_edges) {
     if (t > ctl->stop_after) return;
     __shared__ double s_sum[4 * B];
-    // one wave per partial row (4B rows of nb entries)
+    // one wave per partial row (4B rows of nb <= kRedBlocks entries); a lane loads
+    // all its entries of a row before adding them, in index order
+    constexpr int kRounds = kRedBlocks / W;
     const int wv = threadIdx.x / W;
     for (int r = wv; r < 4 * B; r += blockDim.x / W) {
+        const double *row = part + (int64_t)r * nb;
+        double x[kRounds];
+#pragma unroll
+        for (int q = 0; q < kRounds; ++q) {
+            const int b = lane_id() + q * W;
+            x[q] = b < nb ? row[b] : 0.0;
+        }
         double s = 0.0;
-        for (int b = lane_id(); b < nb; b += W) s += part[(int64_t)r * nb + b];
+#pragma unroll
+        for (int q = 0; q < kRounds; ++q) s += x[q];
         s = wave_sum(s);
         if (lane_id() == 0) s_sum[r] = s;
     }
