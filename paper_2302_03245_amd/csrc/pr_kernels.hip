@@ -334,6 +334,33 @@ __device__ __forceinline__ void block_sum_n(double (&v)[N], double *sbuf) {
     }
 }
 
+// Sums of N partial arrays of nb <= kRedBlocks entries each (array q at part + q nb)
+// in one pass: every load issues before any add, each thread adds its entries in
+// index order, then one workgroup reduction -- the same sums, in the same order, as
+// N calls of reduce_partials.  Results in thread 0; sbuf holds N * kBlock / W entries.
+template <int N>
+__device__ __forceinline__ void reduce_partials_n(const double *part, int nb, double (&v)[N], double *sbuf) {
+    constexpr int R = kRedBlocks / kBlock;
+    static_assert(kRedBlocks % kBlock == 0, "partials");
+    double x[N][R];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const int b = threadIdx.x + r * kBlock;
+            x[q][r] = b < nb ? part[(size_t)q * nb + b] : 0.0;
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double acc = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) acc += x[q][r];
+        v[q] = acc;
+    }
+    block_sum_n(v, sbuf);
+}
+
 // Reserve step of one sweep (the body of the calculation threads' loop):
 // every non-dangling i with h_i > xi moves its residual v into pibar_i and
 // publishes its push weight w_i = c v / deg(i); others publish 0.  Per
@@ -540,13 +567,11 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
                                                        unsigned long long pull_thr, int force,
                                                        unsigned long long pull_edges) {
     if (t > ctl->stop_after) return;
-    __shared__ double sd[kBlock / W];
-    const double a_in = reduce_partials(part, nb, sd);
-    const double a_pr = reduce_partials(part + nb, nb, sd);
-    const double a_sx = reduce_partials(part + 2 * nb, nb, sd);
-    const double a_cd = reduce_partials(part + 3 * nb, nb, sd);
-    const double a_ed = reduce_partials(part + 4 * nb, nb, sd);
+    __shared__ double sd[5 * (kBlock / W)];
+    double v[5];
+    reduce_partials_n(part, nb, v, sd);
     if (threadIdx.x != 0) return;
+    const double a_in = v[0], a_pr = v[1], a_sx = v[2], a_cd = v[3], a_ed = v[4];
     const unsigned long long a_c = (unsigned long long)a_cd, a_e = (unsigned long long)a_ed;
     const double k = 2.0 * c / (1.0 - c);
     if (a_c == 0) {
@@ -848,10 +873,10 @@ __global__ __launch_bounds__(kBlock) void k_final_sum(InitArgs a, const T *h, co
 
 // fin_sum = part[0..nb), fin_sn = part[nb..2nb), fin_abs = part[2nb..3nb)
 __global__ __launch_bounds__(kBlock) void k_final_decide(Ctl *ctl, int nb, const double *part) {
-    __shared__ double sd[kBlock / W];
-    const double s = reduce_partials(part, nb, sd);
-    const double sn = reduce_partials(part + nb, nb, sd);
-    const double sa = reduce_partials(part + 2 * nb, nb, sd);
+    __shared__ double sd[3 * (kBlock / W)];
+    double v[3];
+    reduce_partials_n(part, nb, v, sd);
+    const double s = v[0], sn = v[1], sa = v[2];
     if (threadIdx.x == 0) {
         ctl->fin_sum = s;
         ctl->fin_sn = sn;
@@ -921,11 +946,11 @@ __global__ __launch_bounds__(kBlock) void k_power_prescale(int t, const Ctl *ctl
 __global__ __launch_bounds__(kBlock) void k_decide_power(int t, Ctl *ctl, int nb, const double *part, double c,
                                                          double tol) {
     if (t > ctl->stop_after) return;
-    __shared__ double sd[kBlock / W];
-    const double df = reduce_partials(part, nb, sd);
-    const double ds = reduce_partials(part + nb, nb, sd);
-    const double xs = reduce_partials(part + 2 * nb, nb, sd);
+    __shared__ double sd[3 * (kBlock / W)];
+    double v[3];
+    reduce_partials_n(part, nb, v, sd);
     if (threadIdx.x != 0) return;
+    const double df = v[0], ds = v[1], xs = v[2];
     ctl->pw_b = c * ds + (1.0 - c) * xs;
     if (t > 0) {
         ctl->pw_diff = df;
