@@ -140,6 +140,9 @@ __global__ __launch_bounds__(kBlock) void k_set_reserve(int t, const Ctl *ctl, S
     bool live = false;
     int64_t shift = 0;
     double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    // dense set frontier (the last decision gathered): most vertices are taken, so a
+    // vertex's degree, row offsets and pibar are loaded with its residual
+    const bool eager = ctl->use_pull != 0;
     for (int64_t p = lo + threadIdx.x; p < hi; p += kBlock) {
         if (cur.g >= 0 && p >= cur.end) {
             sa.add(cur.g, a);
@@ -155,11 +158,25 @@ __global__ __launch_bounds__(kBlock) void k_set_reserve(int t, const Ctl *ctl, S
         }
         const int64_t i = p + shift;
         const T hv = h[i];
+        int32_t dg = 0;
+        uint32_t r0 = 0, r1 = 0;
+        double pb = 0.0;
+        if (eager) {
+            dg = deg[i];
+            r0 = rp_nn[i];
+            r1 = rp_nn[i + 1];
+            pb = pibar[i];
+        }
         if (live && hv > xi) {
-            const int32_t dg = deg[i];
-            const uint32_t dnn = rp_nn[i + 1] - rp_nn[i];
+            if (!eager) {
+                dg = deg[i];
+                r0 = rp_nn[i];
+                r1 = rp_nn[i + 1];
+                pb = pibar[i];
+            }
+            const uint32_t dnn = r1 - r0;
             const double v = (double)hv;
-            pibar[i] += v;
+            pibar[i] = pb + v;
             h[i] = (T)0;
             w[i] = (T)(c * v / (double)dg);
             const double fN = (double)dnn / (double)dg;
