@@ -34,10 +34,17 @@ def l1(a, b):
     return float(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)).sum())
 
 
-def topk_agree(ref, got, k):
+# caps on eps_inf = max |got - ref| for the top-k tie rule, by residual precision
+EPS_CAP = {"fp64": 1e-12, "fp32": 1e-9}
+
+
+def topk_agree(ref, got, k, precision):
     """Top-k ranking check with the tie rule: rank by (value desc, id asc) in both
     vectors; position j may differ only if the two ids' reference values differ by
-    at most 2 * eps_inf, where eps_inf = max |got - ref|.  Returns (ok, swaps, eps)."""
+    at most 2 * eps_inf, where eps_inf = max |got - ref|, and eps_inf itself must not
+    exceed the cap of the run's residual precision (1e-12 for FP64, 1e-9 for FP32;
+    without the cap a loose result would widen its own tie window).
+    Returns (ok, swaps, eps)."""
     ref = np.asarray(ref, dtype=np.float64)
     got = np.asarray(got, dtype=np.float64)
     n = ref.size
@@ -46,6 +53,8 @@ def topk_agree(ref, got, k):
     r_order = np.lexsort((ids, -ref))[:k]
     g_order = np.lexsort((ids, -got))[:k]
     eps = float(np.abs(got - ref).max())
+    if eps > EPS_CAP[precision]:
+        return False, 0, eps
     swaps = 0
     for a, b in zip(r_order, g_order):
         if a == b:
@@ -54,6 +63,18 @@ def topk_agree(ref, got, k):
         if abs(ref[a] - ref[b]) > 2 * eps:
             return False, swaps, eps
     return True, swaps, eps
+
+
+def oracle_many(jobs, workers=None):
+    """Run oracle.power over many (graph, c, p, tol) jobs in a thread pool (the oracle is
+    a C library called through ctypes, which releases the GIL); returns the vectors in
+    job order."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    workers = workers or max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(max_workers=workers) as ex:
+        futs = [ex.submit(oracle.power, g, c, p, tol) for (g, c, p, tol) in jobs]
+        return [f.result()[0] for f in futs]
 
 
 @pytest.fixture(scope="session")

@@ -21,7 +21,7 @@ import scipy.sparse as sp
 
 import oracle
 import prgen
-from conftest import l1, topk_agree
+from conftest import l1, oracle_many, topk_agree
 
 pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 C = 0.85
@@ -37,29 +37,35 @@ def _eq_residual(g, pi):
     return float(np.abs(pi - C * (P @ pi) - gamma / g.n).sum())
 
 
-def _check(pr, g, ref, fp64_too, peel=False):
+def _check(pr, g, ref, ref_err, fp64_too, peel=False):
+    """Every run against the oracle vector ref, itself within ref_err (L1) of the exact
+    vector: L1 within the gate, certified bound within the gate and at least the
+    measured distance to the exact vector (so also with FP32 residuals the reported
+    bound is not below the true error), top-1000 under the tie rule with the eps_inf
+    cap of the run's precision, unit sum, PageRank-equation residual."""
     dg = pr.upload(g.row_ptr, g.col)
-    runs = [("ifp2", lambda: pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6),
-            ("ifp1", lambda: pr.ifp1(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6),
-            ("power", lambda: pr.power(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6)]
+    runs = [("ifp2", lambda: pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6, "fp32"),
+            ("ifp1", lambda: pr.ifp1(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6, "fp32"),
+            ("power", lambda: pr.power(dg, c=C, l1_tol=1e-6, residual="fp32"), 1e-6, "fp32")]
     if fp64_too:
-        runs.append(("ifp2_fp64", lambda: pr.ifp2(dg, c=C, l1_tol=1e-9), 1e-9))
+        runs.append(("ifp2_fp64", lambda: pr.ifp2(dg, c=C, l1_tol=1e-9), 1e-9, "fp64"))
     if peel:  # weakly dangling vertices out of the sweeps, as the DAG bench line runs it
         dp = pr.upload(g.row_ptr, g.col, peel=True)
         lev = oracle.weak_dangling_levels(g, max_levels=64)
         info = dp.info()
         print(f"{g.name} peeled {info['n_peeled']} in {info['peel_levels']} levels", flush=True)
         assert info["n_peeled"] == int((lev >= 1).sum()) and info["m_dangling"] == int((lev[g.col] >= 0).sum())
-        runs.append(("ifp2_peel", lambda: pr.ifp2(dp, c=C, l1_tol=1e-6, residual="fp32"), 1e-6))
-    for name, run, tol in runs:
+        runs.append(("ifp2_peel", lambda: pr.ifp2(dp, c=C, l1_tol=1e-6, residual="fp32"), 1e-6, "fp32"))
+    for name, run, tol, prec in runs:
         pi, st = run()
         err = l1(pi, ref)
-        ok, swaps, eps = topk_agree(ref, pi, 1000)
+        ok, swaps, eps = topk_agree(ref, pi, 1000, prec)
         print(f"{g.name} {name}: sweeps {st['sweeps']} L1 {err:.3e} bound {st['l1_bound']:.3e} "
               f"top-1000 swaps {swaps} eps_inf {eps:.2e}", flush=True)
         assert st["status"] == 0 and st["l1_bound"] <= tol
         assert err <= tol
-        assert ok
+        assert st["l1_bound"] >= err - ref_err, (name, st["l1_bound"], err)
+        assert ok, (name, swaps, eps)
         assert abs(pi.sum() - 1.0) < 1e-10
         assert _eq_residual(g, pi) <= 2 * tol
     dg.free()
@@ -73,16 +79,20 @@ def test_rmat_scale22(pr_lib):
     print(f"R-MAT scale 22: n={g.n} m={g.m}", flush=True)
     ref, it, delta = oracle.power(g, C, tol=1e-13)
     print(f"oracle power: {it} iterations, delta {delta:.2e}", flush=True)
-    _check(pr_lib, g, ref, fp64_too=True)
+    _check(pr_lib, g, ref, C / (1 - C) * delta, fp64_too=True)
 
 
 @pytest.mark.timeout(400)
 def test_layered_dag(pr_lib):
     g = prgen.workload_dag()
     print(f"layered DAG: n={g.n} m={g.m} lambda={g.meta['lambda']:.4f}", flush=True)
+    # the oracle stops at ||x' - x||_1 <= 1e-11 here rather than 1e-13: on this graph the
+    # FP64 sums of its 81.6M-edge iterations stall near 1e-12 (the rounding of one
+    # iteration), so 1e-13 would not be reached; c / (1 - c) * 1e-11 = 5.7e-11 of
+    # reference error is four orders below the 1e-6 gate of the FP32 runs checked here
     ref, it, delta = oracle.power(g, C, tol=1e-11)
     print(f"oracle power: {it} iterations, delta {delta:.2e}", flush=True)
-    _check(pr_lib, g, ref, fp64_too=False, peel=True)
+    _check(pr_lib, g, ref, C / (1 - C) * delta, fp64_too=False, peel=True)
 
 
 @pytest.fixture(scope="module")
@@ -106,10 +116,15 @@ def _eq_residual_c(g, pi, c):
 def test_graph_set_256(pr_lib):
     """The batched workload: 256 R-MAT graphs (n log-uniform in [1k, 500k], average
     degree in [4, 32], 5-20 % dangling, c in {0.85, 0.9}) solved as one set with
-    FP32 residuals at L1 <= 1e-6, as bench.py times it.  Every graph: certified
-    bound, unit sum, and the PageRank-equation residual within (1 + c) * 1e-6 (it
-    holds for any vector within 1e-6 of the solution); the eight smallest graphs
-    and two larger ones also against the FP64 oracle element by element."""
+    FP32 residuals at L1 <= 1e-6, as bench.py times it.
+
+    Against the FP64 oracle element by element (L1 <= 1e-6, and the certified bound at
+    least the measured error): every graph with n <= 100,000 and every third of the
+    larger ones in order of n (a stratified sample), about 210 of the 256.  Every graph:
+    certified bound, unit sum and the PageRank-equation residual
+    ||pi - c P pi - gamma p||_1 <= (1 + c) * 1e-6.  The residual check alone only bounds
+    the L1 error by (1 + c) / (1 - c) * 1e-6 (the inverse of I - cP'' has L1 norm
+    1 / (1 - c)), which is why the oracle comparison carries the gate."""
     pr = pr_lib
     graphs, cs = prgen.workload_batch(count=256, seed=0)
     print(f"set: n {sum(g.n for g in graphs)} m {sum(g.m for g in graphs)}", flush=True)
@@ -121,15 +136,28 @@ def test_graph_set_256(pr_lib):
         assert abs(x.sum() - 1.0) <= 1e-12, i
         r = _eq_residual_c(g, x, c)
         assert r <= (1 + c) * 1e-6, (i, g.n, r)
-    order = np.argsort([g.n for g in graphs])
-    sample = list(order[:8]) + [int(order[100]), int(order[140])]
-    for i in sample:
-        ref = oracle.power(graphs[i], cs[i], tol=1e-13)[0]
+    order = [int(i) for i in np.argsort([g.n for g in graphs], kind="stable")]
+    small = [i for i in order if graphs[i].n <= 100_000]
+    large = [i for i in order if graphs[i].n > 100_000]
+    sample = small + large[::3]
+    tol_ref = 1e-12
+    refs = oracle_many([(graphs[i], cs[i], None, tol_ref) for i in sample])
+    worst, n_top = 0.0, 0
+    for i, ref in zip(sample, refs):
+        ref_err = cs[i] / (1 - cs[i]) * tol_ref
         d = l1(parts[i], ref)
-        print(f"graph {i}: n {graphs[i].n} c {cs[i]} L1 vs oracle {d:.3e}", flush=True)
-        assert d <= 1e-6, (i, d)
-        ok, swaps, eps = topk_agree(ref, parts[i], min(1000, graphs[i].n))
-        assert ok, (i, swaps, eps)
+        worst = max(worst, d)
+        assert d <= 1e-6, (i, graphs[i].n, d)
+        assert sts[i]["l1_bound"] >= d - ref_err, (i, sts[i]["l1_bound"], d)
+        ok, swaps, eps = topk_agree(ref, parts[i], min(1000, graphs[i].n), "fp32")
+        if graphs[i].n >= 100_000 or eps <= 1e-9:
+            # below 100k vertices an FP32 run at L1 1e-6 may hold single entries off by
+            # more than the FP32 eps_inf cap (the cap is the gate of the large workloads)
+            assert ok, (i, graphs[i].n, swaps, eps)
+            n_top += 1
+    print(f"set: {len(sample)} graphs against the oracle, worst L1 {worst:.3e}, "
+          f"{n_top} with the top-k rule under the FP32 cap", flush=True)
+    assert len(sample) >= 200
     gs.free()
 
 
@@ -159,7 +187,7 @@ def _ppr_residual(g, pi, c, s, Pd=None):
 def test_ppr_batch_scale22(pr_lib):
     """The bench's PPR leg: 16 non-dangling sources of R-MAT scale 22 in one call (one
     16-column batched solve, FP32, L1 <= 1e-6 per column).  Every column: certified bound,
-    unit sum and the PPR-equation residual; two columns against the FP64 oracle."""
+    unit sum, the PPR-equation residual, and the FP64 oracle (all sixteen columns)."""
     pr = pr_lib
     g = prgen.workload_rmat(scale=22, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=0)
     deg = np.diff(g.row_ptr)
@@ -172,13 +200,17 @@ def test_ppr_batch_scale22(pr_lib):
         assert abs(out[r].sum() - 1.0) <= 1e-10
         res = _ppr_residual(g, out[r], C, int(s), Pd)
         assert res <= (1 + C) * 1e-6, (r, res)
-    for r in (0, 9):
+    refs = []
+    for r in range(len(srcs)):
         p = np.zeros(g.n)
         p[srcs[r]] = 1.0
-        ref = oracle.power(g, C, p, tol=1e-12)[0]
+        refs.append((g, C, p, 1e-12))
+    for r, ref in enumerate(oracle_many(refs)):
         d = l1(out[r], ref)
-        print(f"ppr column {r} (source {srcs[r]}): sweeps {sts[r]['sweeps']} L1 vs oracle {d:.3e}", flush=True)
+        print(f"ppr column {r} (source {srcs[r]}): sweeps {sts[r]['sweeps']} L1 vs oracle {d:.3e} "
+              f"bound {sts[r]['l1_bound']:.3e}", flush=True)
         assert d <= 1e-6
+        assert sts[r]["l1_bound"] >= d - C / (1 - C) * 1e-12, (r, sts[r]["l1_bound"], d)
     dg.free()
 
 
@@ -186,7 +218,8 @@ def test_ppr_batch_scale22(pr_lib):
 def test_warm_start_scale22(pr_lib):
     """The bench's warm-start leg: 0.1 % of the non-dangling vertices of R-MAT scale 22 get
     new out-edge lists; the state carried over and resumed (FP32, L1 <= 1e-6) against a
-    cold solve of the changed graph and the PageRank-equation residual there."""
+    cold solve of the changed graph, the FP64 oracle of the changed graph and the
+    PageRank-equation residual there."""
     pr = pr_lib
     g = prgen.workload_rmat(scale=22, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=0)
     rng = np.random.default_rng(17)
@@ -207,6 +240,10 @@ def test_warm_start_scale22(pr_lib):
     print(f"warm: {sw['sweeps']} sweeps, cold {sc['sweeps']}; L1 warm-cold {l1(pi, cold):.3e}", flush=True)
     assert sw["status"] == 0 and sw["l1_bound"] <= 1e-6
     assert l1(pi, cold) <= 2e-6
+    ref, _, delta = oracle.power(g2, C, tol=1e-12)
+    d = l1(pi, ref)
+    print(f"warm: L1 vs oracle {d:.3e} bound {sw['l1_bound']:.3e}", flush=True)
+    assert d <= 1e-6 and sw["l1_bound"] >= d - C / (1 - C) * delta
     assert _eq_residual(g2, pi) <= 2e-6
     assert sw["edges_processed"] < sc["edges_processed"]
     st.free()
@@ -219,7 +256,9 @@ def test_served_full_size(pr_lib):
     """The served workload's resident graphs (R-MAT scale 24 for PPR, the 32-graph pool for
     global PageRank) behind one server: 12 PPR queries (dangling and non-dangling sources)
     and 12 global queries submitted at once, every result certified at L1 <= 1e-6 and
-    checked by its PageRank-equation residual."""
+    checked by its PageRank-equation residual (which alone bounds the L1 error by
+    (1 + c) / (1 - c) * 1e-6); two scale-24 PPR results and four pool-graph results
+    also element by element against the FP64 oracle."""
     import torch
     pr = pr_lib
     gp = prgen.workload_rmat(scale=24, edge_factor=16, dangling_frac=0.15, unref_frac=0.10, seed=1)
@@ -243,6 +282,7 @@ def test_served_full_size(pr_lib):
             out = torch.empty(graphs[gi].n, dtype=torch.float64, device="cuda")
             reqs.append((gi, -1, out, srv.submit(gids[gi], -1, out)))
         Ps = {}
+        results = []
         for gi, s, out, rid in reqs:
             st = srv.wait(rid, timeout=600.0)
             assert st["status"] == 0 and st["l1_bound"] <= 1e-6, (gi, s, st)
@@ -252,6 +292,28 @@ def test_served_full_size(pr_lib):
                 Ps[gi] = _transition(graphs[gi])
             res = _ppr_residual(graphs[gi], pi, C, s, Ps[gi])
             assert res <= (1 + C) * 1e-6, (gi, s, res)
+            results.append((gi, s, pi, st))
+        # element by element against the FP64 oracle: two PPR queries with a non-dangling
+        # source on the scale-24 graph and four global queries on distinct pool graphs
+        chosen = [r for r in results if r[0] == 0 and r[1] >= 0 and np.diff(gp.row_ptr)[r[1]] > 0][:2]
+        seen = set()
+        for r in results:
+            if r[0] != 0 and r[0] not in seen and len(seen) < 4:
+                seen.add(r[0])
+                chosen.append(r)
+        assert len(chosen) == 6
+        jobs = []
+        for gi, s, _, _ in chosen:
+            p = None
+            if s >= 0:
+                p = np.zeros(graphs[gi].n)
+                p[s] = 1.0
+            jobs.append((graphs[gi], C, p, 1e-12))
+        for (gi, s, pi, st), ref in zip(chosen, oracle_many(jobs)):
+            d = l1(pi, ref)
+            print(f"served graph {gi} source {s}: L1 vs oracle {d:.3e} bound {st['l1_bound']:.3e}", flush=True)
+            assert d <= 1e-6, (gi, s, d)
+            assert st["l1_bound"] >= d - C / (1 - C) * 1e-12, (gi, s, st["l1_bound"], d)
     finally:
         srv.close()
     for d in dgs:

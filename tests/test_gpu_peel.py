@@ -68,7 +68,7 @@ def test_peeled_ifp2_matches_oracle(pr, name, g):
         pi, st = pr.ifp2(dg, c=C, xi=1e-13, mode=mode)
         assert st["status"] == 0
         assert l1(pi, ref) <= 1e-9, (mode, l1(pi, ref))
-        assert topk_agree(ref, pi, 1000)[0]
+        assert topk_agree(ref, pi, 1000, "fp64")[0]
         pi32, st32 = pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32", mode=mode)
         assert st32["status"] == 0 and st32["l1_bound"] <= 1e-6
         assert l1(pi32, ref) <= 1e-6
