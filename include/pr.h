@@ -25,6 +25,9 @@
  *  - Thread safety: distinct graphs may be used concurrently.  Solves on one
  *    graph from several host threads or streams are allowed (the graph is
  *    read-only after upload); freeing a graph while a solve runs is undefined.
+ *    pr_graph_tune rebuilds the graph's plans: it returns PR_EBUSY while solves
+ *    (or a query server) use the graph, and solves that start while it runs
+ *    return PR_EBUSY.
  */
 #ifndef PR_H
 #define PR_H
@@ -40,7 +43,9 @@ typedef enum {
     PR_ENOCONV = 1,  /* max_sweeps reached: pi holds the normalised best estimate, stats->l1_bound its quality */
     PR_EINVAL = -1,  /* invalid argument (see each function) */
     PR_ENOMEM = -2,  /* device or host allocation failed */
-    PR_EDEVICE = -3  /* a HIP runtime call failed */
+    PR_EDEVICE = -3, /* a HIP runtime call failed */
+    PR_EBUSY = -4    /* the graph is in use: pr_graph_tune / pr_set_tune while solves or a
+                        server use it, or a solve (or pr_server_add_graph) while it is tuned */
 } pr_status;
 
 typedef struct pr_graph pr_graph; /* opaque, device-resident, owned by the library */
@@ -263,11 +268,23 @@ pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, d
  *   sources  int32[k] host array, each in [0, n); k >= 1
  *   pi       double[k * n], row r is the PPR vector of sources[r]
  *   st       optional, k entries
- * Returns the worst status over the k solves; on a negative status the rows of
- * sources already solved may have been written.
+ * Returns the worst status over the k solves.  On a negative status no row of pi
+ * and no entry of st is written: a call of more than one batch (k > 16, or k > 1
+ * on a peeled graph) solves into a device staging buffer of k * n doubles,
+ * allocated before the first batch (PR_ENOMEM if it cannot be), and copies the
+ * rows out once every batch has succeeded; only a failure of that final copy
+ * (PR_EDEVICE) can leave pi partly written.
  */
 pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_opts *o, double *pi,
                  pr_stats *st);
+
+/*
+ * Testing hook (for callers that check the error contract of pr_ppr): the next
+ * pr_ppr call on this thread fails with PR_ENOMEM when it reaches batch b
+ * (b >= 1, i.e. after b batches have been solved), as if that batch's workspace
+ * could not be allocated.  b <= 0 disables it; the hook is cleared by that call.
+ */
+void pr_debug_fail_ppr_batch(int32_t b);
 
 /* Message describing the last error on this thread ("" if none). */
 const char *pr_last_error(void);

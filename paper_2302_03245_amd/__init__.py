@@ -19,7 +19,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpr.so")
 
-PR_OK, PR_ENOCONV, PR_EINVAL, PR_ENOMEM, PR_EDEVICE = 0, 1, -1, -2, -3
+PR_OK, PR_ENOCONV, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_EBUSY = 0, 1, -1, -2, -3, -4
 PR_RES_FP64, PR_RES_FP32 = 0, 1
 PR_STOP_XI, PR_STOP_L1 = 0, 1
 PR_INPUT_DEVICE, PR_DEDUPE, PR_PEEL = 0x1, 0x2, 0x20000
@@ -33,7 +33,8 @@ EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_inf
             "pr_server_opts_default", "pr_server_create", "pr_server_add_graph", "pr_server_submit",
             "pr_server_wait", "pr_server_get_stats", "pr_server_destroy",
             "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2", "pr_set_tune", "pr_graph_tune",
-            "pr_state_create", "pr_state_free", "pr_state_read", "pr_solve_ifp2_warm", "pr_state_update"]
+            "pr_state_create", "pr_state_free", "pr_state_read", "pr_solve_ifp2_warm", "pr_state_update",
+            "pr_debug_fail_ppr_batch"]
 
 
 class PRError(RuntimeError):
@@ -178,6 +179,8 @@ def lib():
     L.pr_server_get_stats.restype = ctypes.c_int
     L.pr_server_destroy.argtypes = [vp]
     L.pr_server_destroy.restype = ctypes.c_int
+    L.pr_debug_fail_ppr_batch.argtypes = [i32]
+    L.pr_debug_fail_ppr_batch.restype = None
     _lib = L
     return L
 
@@ -576,6 +579,12 @@ def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_s
     if status < 0:
         raise _err(status)
     return out, [dict(st[i].as_dict(), status=status) for i in range(k)]
+
+
+def debug_fail_ppr_batch(b):
+    """Testing hook: the next ppr() call on this thread fails with PR_ENOMEM on reaching
+    batch b (after b batches of sixteen sources were solved); b <= 0 disables it."""
+    lib().pr_debug_fail_ppr_batch(int(b))
 
 
 class Server:

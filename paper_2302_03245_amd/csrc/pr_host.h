@@ -94,7 +94,11 @@ struct Workspace {
     size_t bytes = 0;
     bool cached = false;
     Ctl *hctl = nullptr;  // pinned
+    hipStream_t stream = nullptr;  // the solve's stream
     ~Workspace() {
+        // an error path may leave kernels that use the workspace in flight: wait for them
+        // before another solve can take it (a no-op after a solve that finished)
+        if (base) (void)hipStreamSynchronize(stream);
         if (hctl && !cached) (void)hipHostFree(hctl);
         if (!base) return;
         if (cached) {
@@ -107,7 +111,25 @@ struct Workspace {
 };
 
 
-pr_status acquire_ws(Graph &G, size_t bytes, Workspace &ws);
+pr_status acquire_ws(Graph &G, size_t bytes, Workspace &ws, hipStream_t s);
+
+// A solve (or a server) holds a use of its graph while it runs; the autotuner, which
+// rebuilds the graph's plans, runs only on an unused graph, and solves that start
+// while it runs fail with PR_EBUSY.
+struct GraphUse {
+    Graph *g = nullptr;
+    GraphUse() = default;
+    GraphUse(const GraphUse &) = delete;
+    GraphUse &operator=(const GraphUse &) = delete;
+    ~GraphUse() { release(); }
+    void release();
+};
+pr_status use_graph(const Graph &G, GraphUse &u);
+struct TuneLock {
+    Graph *g = nullptr;
+    ~TuneLock();
+};
+pr_status lock_for_tuning(Graph &G, TuneLock &t);
 
 struct Carve {
     char *base;

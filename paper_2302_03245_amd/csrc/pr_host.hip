@@ -7,6 +7,8 @@ namespace host {
 
 thread_local std::string g_err;
 thread_local TraceRec g_trace;
+// testing hook of pr_ppr: fail on reaching this batch (0: off)
+thread_local int32_t t_fail_ppr_batch = 0;
 
 pr_status fail(pr_status st, const std::string &msg) {
     g_err = msg;
@@ -57,6 +59,37 @@ pr_status opts_or_default(const pr_opts *o, pr_opts *out) {
 pr_status enter(const pr_graph *g) {
     if (!g) return fail(PR_EINVAL, "graph is NULL");
     HIPCHK(hipSetDevice(g->g.device));
+    return PR_OK;
+}
+
+void GraphUse::release() {
+    if (!g) return;
+    std::lock_guard<std::mutex> lk(g->ws_mu);
+    --g->users;
+    g = nullptr;
+}
+
+pr_status use_graph(const Graph &Gc, GraphUse &u) {
+    Graph &G = const_cast<Graph &>(Gc);
+    std::lock_guard<std::mutex> lk(G.ws_mu);
+    if (G.tuning) return fail(PR_EBUSY, "the graph is being tuned (pr_graph_tune / pr_set_tune)");
+    ++G.users;
+    u.g = &G;
+    return PR_OK;
+}
+
+TuneLock::~TuneLock() {
+    if (!g) return;
+    std::lock_guard<std::mutex> lk(g->ws_mu);
+    g->tuning = false;
+}
+
+pr_status lock_for_tuning(Graph &G, TuneLock &t) {
+    std::lock_guard<std::mutex> lk(G.ws_mu);
+    if (G.users > 0) return fail(PR_EBUSY, "solves or a server are using the graph");
+    if (G.tuning) return fail(PR_EBUSY, "the graph is already being tuned");
+    G.tuning = true;
+    t.g = &G;
     return PR_OK;
 }
 
@@ -159,6 +192,9 @@ static pr_status solve_common(const pr_graph *g, int method, const double *p, co
     if (ps != PR_OK) return ps;
     if (method == 1 && g->g.nP > 0)
         return fail(PR_EINVAL, "a graph uploaded with PR_PEEL serves IFP2 and power solves, not IFP1");
+    GraphUse use;
+    ps = use_graph(g->g, use);
+    if (ps != PR_OK) return ps;
     try {
         const Graph &G = g->g;
         if (method == 3) {
@@ -231,6 +267,9 @@ pr_status pr_solve_ifp2_warm(const pr_graph *g, const pr_opts *o, pr_state *s, d
     if (s->c != 0.0 && s->c != op.c) return fail(PR_EINVAL, "c differs from the state's damping factor");
     ps = enter(g);
     if (ps != PR_OK) return ps;
+    GraphUse use;
+    ps = use_graph(g->g, use);
+    if (ps != PR_OK) return ps;
     try {
         WarmArgs wa{s->pibar, s->h};
         ps = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(g->g, true, nullptr, -1, op, pi, st, &wa)
@@ -255,6 +294,10 @@ pr_status pr_state_update(pr_state *s, const pr_graph *g_old, const pr_graph *g_
         for (int32_t q = 0; q < k; ++q)
             if (changed[q] < 0 || changed[q] >= s->n) return fail(PR_EINVAL, "changed source out of [0, n)");
     HIPCHK(hipSetDevice(s->device));
+    GraphUse use_old, use_new;
+    pr_status ps = use_graph(g_old->g, use_old);
+    if (ps == PR_OK) ps = use_graph(g_new->g, use_new);
+    if (ps != PR_OK) return ps;
     hipStream_t st = g_new->g.stream;
     int32_t *d_src = nullptr;
     if (changed && k > 0) {
@@ -284,6 +327,9 @@ pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_rep
     if (op.flags & (PR_FORCE_PUSH | PR_FORCE_PULL | PR_P_DEVICE))
         return fail(PR_EINVAL, "tuning times the automatic schedule of global solves");
     ps = enter(g);
+    if (ps != PR_OK) return ps;
+    TuneLock lock;
+    ps = lock_for_tuning(g->g, lock);
     if (ps != PR_OK) return ps;
     try {
         return tune_impl(g->g, op, reps, rep);
@@ -339,6 +385,9 @@ pr_status pr_set_tune(pr_graph_set *s, const double *c, const pr_opts *o, int32_
         return fail(PR_EINVAL, "tuning times the automatic schedule of set solves");
     ps = enter(s->u);
     if (ps != PR_OK) return ps;
+    TuneLock lock;
+    ps = lock_for_tuning(s->u->g, lock);
+    if (ps != PR_OK) return ps;
     try {
         return set_tune_impl(*s, c, op, reps, rep);
     } catch (const std::bad_alloc &) {
@@ -358,6 +407,9 @@ pr_status pr_set_solve_ifp2(const pr_graph_set *s, const double *c, const pr_opt
     if (op.flags & (PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE))
         return fail(PR_EINVAL, "option flag not supported for graph sets");
     ps = enter(s->u);
+    if (ps != PR_OK) return ps;
+    GraphUse use;
+    ps = use_graph(s->u->g, use);
     if (ps != PR_OK) return ps;
     try {
         return op.residual == PR_RES_FP32 ? solve_set_t<float>(*s, c, op, pi, st)
@@ -382,6 +434,8 @@ pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, d
 pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_opts *o, double *pi,
                  pr_stats *st) {
     g_err.clear();
+    const int32_t fail_at = t_fail_ppr_batch;  // testing hook, one call only
+    t_fail_ppr_batch = 0;
     if (!g) return fail(PR_EINVAL, "graph is NULL");
     if (!pi) return fail(PR_EINVAL, "pi is NULL");
     if (!sources || k < 1) return fail(PR_EINVAL, "need k >= 1 sources");
@@ -395,33 +449,58 @@ pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_
     if (ps != PR_OK) return ps;
     ps = enter(g);
     if (ps != PR_OK) return ps;
+    GraphUse use;
+    ps = use_graph(G, use);
+    if (ps != PR_OK) return ps;
     pr_status worst = PR_OK;
     try {
         // groups of kBatch sources share one batched solve; a lone source runs alone, as
         // does every source on a peeled graph (the batched sweeps cover every non-dangling row)
         const int32_t width = G.nP > 0 ? 1 : kBatch;
-        for (int32_t r = 0; r < k; r += width) {
+        const int32_t nbatch = (k + width - 1) / width;
+        const hipStream_t s = op.stream ? (hipStream_t)op.stream : G.stream;
+        // more than one batch: every row is solved into device staging first and copied
+        // out only once all batches have succeeded, so a failing batch writes no row
+        DevBufs staging;
+        double *stage = nullptr;
+        pr_opts ob = op;
+        if (nbatch > 1) {
+            HIPCHK(staging.alloc(&stage, (size_t)k * (size_t)G.n));
+            ob.flags |= PR_OUT_DEVICE;
+        }
+        std::vector<pr_stats> sts(st ? (size_t)k : 0);
+        for (int32_t r = 0, b = 0; r < k; r += width, ++b) {
+            if (fail_at > 0 && b == fail_at) return fail(PR_ENOMEM, "injected failure of a later batch (testing hook)");
             const int kb = (int)std::min<int32_t>(width, k - r);
-            double *rows = pi + (size_t)r * (size_t)G.n;
-            pr_stats *sr = st ? st + r : nullptr;
+            double *rows = (nbatch > 1 ? stage : pi) + (size_t)r * (size_t)G.n;
+            pr_stats *sr = st ? sts.data() + r : nullptr;
             pr_status rs;
             if (kb == 1) {
-                rs = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, sources[r], op, rows, sr)
-                                                : solve_ifp_t<double>(G, true, nullptr, sources[r], op, rows, sr);
+                rs = ob.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, sources[r], ob, rows, sr)
+                                                : solve_ifp_t<double>(G, true, nullptr, sources[r], ob, rows, sr);
             } else if (kb <= 8) {
-                rs = op.residual == PR_RES_FP32 ? solve_ppr_batch_t<float, 8>(G, sources + r, kb, op, rows, sr)
-                                                : solve_ppr_batch_t<double, 8>(G, sources + r, kb, op, rows, sr);
+                rs = ob.residual == PR_RES_FP32 ? solve_ppr_batch_t<float, 8>(G, sources + r, kb, ob, rows, sr)
+                                                : solve_ppr_batch_t<double, 8>(G, sources + r, kb, ob, rows, sr);
             } else {
-                rs = op.residual == PR_RES_FP32 ? solve_ppr_batch_t<float, 16>(G, sources + r, kb, op, rows, sr)
-                                                : solve_ppr_batch_t<double, 16>(G, sources + r, kb, op, rows, sr);
+                rs = ob.residual == PR_RES_FP32 ? solve_ppr_batch_t<float, 16>(G, sources + r, kb, ob, rows, sr)
+                                                : solve_ppr_batch_t<double, 16>(G, sources + r, kb, ob, rows, sr);
             }
             if (rs < 0) return rs;
             if (rs > worst) worst = rs;
         }
+        if (nbatch > 1) {
+            const bool out_dev = op.flags & PR_OUT_DEVICE;
+            HIPCHK(hipMemcpyAsync(pi, stage, sizeof(double) * (size_t)k * (size_t)G.n,
+                                  out_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+        }
+        if (st) std::copy(sts.begin(), sts.end(), st);
     } catch (const std::bad_alloc &) {
         return fail(PR_ENOMEM, "host allocation");
     }
     return worst;
 }
+
+void pr_debug_fail_ppr_batch(int32_t b) { t_fail_ppr_batch = b > 0 ? b : 0; }
 
 }  // extern "C"

@@ -199,6 +199,8 @@ struct Graph {
     // cached solve workspace
     std::mutex ws_mu;
     bool ws_busy = false;
+    int32_t users = 0;    // solves and servers using the graph (guarded by ws_mu)
+    bool tuning = false;  // the autotuner is rebuilding the plans (guarded by ws_mu)
     void *ws_mem = nullptr;
     size_t ws_bytes = 0;
     void *ws_hctl = nullptr;  // pinned host control block that goes with ws_mem

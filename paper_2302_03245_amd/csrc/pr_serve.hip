@@ -78,9 +78,15 @@ struct Engine {
     std::deque<std::shared_ptr<Request>> queue;  // guarded by srv->mu
     std::condition_variable cv_work;
     std::thread th;
+    bool holds_use = false;  // counted among the graph's users (no tuning while served)
 
     ~Engine() {
         if (th.joinable()) th.join();
+        if (holds_use) {
+            Graph &g = const_cast<Graph &>(*G);
+            std::lock_guard<std::mutex> lk(g.ws_mu);
+            --g.users;
+        }
         if (ws) (void)hipFree(ws);
         if (hctl) (void)hipHostFree(hctl);
         if (stream) (void)hipStreamDestroy(stream);
@@ -461,6 +467,13 @@ pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id
     eng->srv = s;
     eng->hg = g;
     eng->G = &G;
+    {
+        Graph &gm = const_cast<Graph &>(G);
+        std::lock_guard<std::mutex> lk(gm.ws_mu);
+        if (gm.tuning) return undo(PR_EBUSY, "the graph is being tuned");
+        ++gm.users;
+        eng->holds_use = true;
+    }
     eng->B = s->o.slots;
     eng->fp32 = fp32;
     hipError_t e = hipSetDevice(G.device);

@@ -212,7 +212,7 @@ pr_status solve_set_t(const pr_graph_set &S, const double *cg, const pr_opts &o,
                    carve_size<double>(nN) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
                    carve_size<SetG>((size_t)k);
     Workspace ws;
-    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
+    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws, s);
     if (ps != PR_OK) return ps;
     Carve cv{ws.base};
     T *h = cv.take<T>(n);

@@ -5,9 +5,10 @@
 namespace prk {
 namespace host {
 
-pr_status acquire_ws(Graph &G, size_t bytes, Workspace &ws) {
+pr_status acquire_ws(Graph &G, size_t bytes, Workspace &ws, hipStream_t s) {
     ws.g = &G;
     ws.bytes = bytes;
+    ws.stream = s;
     {
         std::lock_guard<std::mutex> lk(G.ws_mu);
         if (!G.ws_busy) {
@@ -108,7 +109,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                    carve_size<double>(2) + carve_size<double>(kPartDoubles) +
                    (warm ? 2 * carve_size<double>(nN) + 3 * carve_size<double>(nD) : 0);
     Workspace ws;
-    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
+    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws, s);
     if (ps != PR_OK) return ps;
     Carve cv{ws.base};
     T *h = cv.take<T>(n);
@@ -344,7 +345,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
                    carve_size<Ctl>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
                    carve_size<double>(2) + carve_size<double>(5 * kRedBlocks);
     Workspace ws;
-    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws);
+    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws, s);
     if (ps != PR_OK) return ps;
     Carve cv{ws.base};
     double *x = cv.take<double>(n);
@@ -492,7 +493,7 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
                    carve_size<double>(out_dev ? 0 : (size_t)kb * n) + carve_size<CtlB>(1) +
                    carve_size<double>((size_t)4 * B * kRedBlocks);
     Workspace ws;
-    ps = acquire_ws(G, bytes, ws);
+    ps = acquire_ws(G, bytes, ws, s);
     if (ps != PR_OK) return ps;
     Carve cv{ws.base};
     T *h = cv.take<T>((size_t)n * B);

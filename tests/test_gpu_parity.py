@@ -268,6 +268,61 @@ def test_ppr_batches(pr, mode):
         assert l1(out32[r], ref) <= 1e-6, (r, s)
 
 
+def test_ppr_failing_later_batch_writes_nothing(pr):
+    """A pr_ppr call whose second batch fails (testing hook: as if that batch's workspace
+    could not be allocated) returns the negative status and leaves every output row and
+    stats entry untouched, for host and device outputs; the same call without the hook
+    then writes every row, each equal to the oracle's."""
+    import torch
+    g = prgen.workload_rmat_small(seed=5)
+    dg = pr.upload(g.row_ptr, g.col)
+    rng = np.random.default_rng(3)
+    srcs = [int(x) for x in rng.choice(g.n, 20, replace=False)]  # a batch of 16, then one of 4
+    sentinel = -7.25
+    host = np.full((len(srcs), g.n), sentinel)
+    dev = torch.full((len(srcs), g.n), sentinel, dtype=torch.float64, device="cuda")
+    for out in (host, dev):
+        pr.debug_fail_ppr_batch(1)
+        with pytest.raises(pr.PRError) as ei:
+            pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32", out=out)
+        assert ei.value.status == pr.PR_ENOMEM
+        vals = out.cpu().numpy() if hasattr(out, "cpu") else out
+        assert np.all(vals == sentinel)
+    # the hook is cleared by the failing call: the next call succeeds
+    out, sts = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32", out=dev)
+    got = dev.cpu().numpy()
+    refs = []
+    for s in srcs:
+        p = np.zeros(g.n)
+        p[s] = 1.0
+        refs.append((g, C, p, 1e-13))
+    from conftest import oracle_many
+    for r, ref in enumerate(oracle_many(refs)):
+        assert sts[r]["status"] == 0
+        assert l1(got[r], ref) <= 1e-6, r
+    dg.free()
+
+
+def test_tune_busy_while_served(pr):
+    """pr_graph_tune rebuilds the graph's plans, so it refuses (PR_EBUSY) while a query
+    server holds the graph, and works again once the server is gone."""
+    g = prgen.workload_rmat_small(seed=6)
+    dg = pr.upload(g.row_ptr, g.col)
+    srv = pr.Server(c=C, l1_tol=1e-6, residual="fp32", slots=8)
+    try:
+        srv.add_graph(dg)
+        with pytest.raises(pr.PRError) as ei:
+            pr.tune(dg, c=C, l1_tol=1e-6, residual="fp32", reps=1)
+        assert ei.value.status == pr.PR_EBUSY
+    finally:
+        srv.close()
+    rep = pr.tune(dg, c=C, l1_tol=1e-6, residual="fp32", reps=1)
+    assert rep["candidates"]
+    pi, st = pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32")
+    assert st["status"] == 0
+    dg.free()
+
+
 def _edge_free_run(n_leaves=20000):
     """Vertex 0 -> 1 and every leaf v >= 1 -> 0: all vertices have out-edges, and rows
     2 .. n_leaves have no in-edge, so most gather tiles hold only row ends (a tile of
