@@ -65,12 +65,40 @@ def traffic_from_profiles(kernel: str, workload: str, alg_bytes_per_launch: floa
     return d.get("hbm_bytes_per_launch")
 
 
+def host_cpu():
+    """Model name and usable core count of the host running the bench."""
+    model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"model": model, "nproc": usable, "cpu_count": os.cpu_count()}
+
+
 def cpu_baseline(g, c, tol):
     """The serial oracle's IFP2 on the same graph, with the threshold at which an
-    empty frontier certifies the same L1 bound (one host core)."""
+    empty frontier certifies the same L1 bound (one host core), compiled for this host
+    with -O3 -march=native."""
+    import tempfile
+
     import numpy as np
 
     import oracle
+    from oracle.build import build_native
+    flags = "-O3 -march=native -ffp-contract=off"
+    try:
+        d = tempfile.mkdtemp(prefix="oracle_native_")
+        oracle.use_library(build_native(os.path.join(d, "liboracle_native.so")))
+    except Exception as e:  # keep the portable build if gcc cannot target this host
+        log(f"[bench] native oracle build failed ({e}); timing the portable -O2 build")
+        flags = "-O2"
     deg = np.diff(g.row_ptr)
     n_nd = int((deg > 0).sum())
     xi = oracle.xi_for_l1(tol, c, g.n, n_nd)
@@ -79,7 +107,7 @@ def cpu_baseline(g, c, tol):
     dt = time.perf_counter() - t0
     return {"value": g.m / dt / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
             "sample": f"one full serial IFP2 solve (oracle, xi={xi:.3e}) on the whole workload graph",
-            "seconds": dt, "passes": r["passes"]}
+            "seconds": dt, "passes": r["passes"], "build": f"gcc {flags}", "host": host_cpu()}
 
 
 def main():
@@ -101,6 +129,9 @@ def main():
     ap.add_argument("--no-warm", action="store_true", help="skip the dynamic-graph warm-start leg")
     ap.add_argument("--no-peel", action="store_true", help="skip the weak-dangling peeling leg")
     ap.add_argument("--no-ifp1", action="store_true", help="skip the IFP1 leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the n = 10,000 FP64 launch-bound leg")
+    ap.add_argument("--no-dag", action="store_true", help="skip the layered-DAG leg (IFP2 / IFP1 / power / peeled)")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the FP64-residual leg on the main graph")
     ap.add_argument("--set-count", type=int, default=256,
                     help="batched solves: independent graphs solved as one set (0 = skip)")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
@@ -240,6 +271,15 @@ def main():
                      "groups": info["groups"]},
         "depth_epochs": info["epochs"], "max_depth": info["max_depth"],
     }
+    # one verified solve of the timed configuration: the a-posteriori bound of the result
+    _, stv = pr.ifp2(dg, c=c, l1_tol=args.tol, residual="fp32", out=out, mode=args.mode, verify=True)
+    res["ifp2"]["l1_verified"] = stv["l1_verified"]
+    res["ifp2"]["launches"] = last["launches"]
+    _, stv = pr.power(dg, c=c, l1_tol=args.tol, residual="fp32", out=out, verify=True)
+    res["power"]["l1_verified"] = stv["l1_verified"]
+    log(f"[bench] verified bounds: IFP2 {res['ifp2']['l1_verified']:.3e}, power {res['power']['l1_verified']:.3e}")
+    if not args.no_fp64 and args.mode is None:
+        res["fp64"] = run_fp64(pr, dg, g, c, args, out)
     if not args.no_peel and args.mode is None:
         res["peeled"] = run_peel(pr, g, c, args, t_ifp2, last)
     if args.ppr > 0:
@@ -252,10 +292,116 @@ def main():
         res["served"] = run_serve(pr, prgen, c, args)
     if args.probes:
         res["probes"] = run_probes(pr, torch, g)
+    if not args.no_small:
+        res["small_fp64"] = run_small(pr, prgen, args)
+    if not args.no_dag and args.workload == "rmat":
+        dg.free()
+        res["dag"] = run_dag(pr, prgen, c, args)
     if not args.no_cpu_baseline:
         log("[bench] CPU baseline (serial oracle IFP2)")
         res["cpu_baseline"] = cpu_baseline(g, c, args.tol)
     print(json.dumps(res), flush=True)
+
+
+def _timed(fn, steps, warmup):
+    """Mean wall time of `steps` calls after `warmup` (device synchronised around), and
+    the stats of the last call."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, st = fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, st
+
+
+def run_fp64(pr, dg, g, c, args, out):
+    """The main graph with FP64 residuals at L1 <= 1e-9 (the paper computes in FP64), IFP2
+    against the FP64 power method at the same certified accuracy."""
+    tol = 1e-9
+    t2, s2 = _timed(lambda: pr.ifp2(dg, c=c, l1_tol=tol, out=out), args.steps, args.warmup)
+    tp, sp = _timed(lambda: pr.power(dg, c=c, l1_tol=tol, out=out), args.steps, args.warmup)
+    _, v2 = pr.ifp2(dg, c=c, l1_tol=tol, out=out, verify=True)
+    assert s2["status"] == 0 and s2["l1_bound"] <= tol and sp["status"] == 0
+    res = {"l1_tol": tol, "ifp2_ms": t2 * 1e3, "ifp2_sweeps": s2["sweeps"], "ifp2_gteps": g.m / t2 / 1e9,
+           "ifp2_l1_bound": s2["l1_bound"], "ifp2_l1_verified": v2["l1_verified"],
+           "power_ms": tp * 1e3, "power_iterations": sp["sweeps"], "power_gteps": g.m / tp / 1e9,
+           "ifp2_over_power": tp / t2}
+    log(f"[bench] fp64: {res}")
+    return res
+
+
+def run_small(pr, prgen, args):
+    """The correctness-sized workload: R-MAT n = 10,000, 100,000 distinct edges drawn, 10 %
+    forced dangling, c = 0.85, uniform p, FP64 residuals, xi = 1e-12 (Algorithms 2 and 3's
+    threshold rule), against the FP64 power method run to the bound IFP2 certified.
+    Launch-bound: every array is L2-resident."""
+    c = 0.85
+    g = prgen.workload_rmat_small(seed=0)
+    dg = pr.upload(g.row_ptr, g.col)
+    steps = max(args.steps, 20)
+    t2, s2 = _timed(lambda: pr.ifp2(dg, c=c, xi=1e-12), steps, args.warmup)
+    t1, s1 = _timed(lambda: pr.ifp1(dg, c=c, xi=1e-12), steps, args.warmup)
+    tol = s2["l1_bound"]
+    tp, sp = _timed(lambda: pr.power(dg, c=c, l1_tol=tol), steps, args.warmup)
+    _, v2 = pr.ifp2(dg, c=c, xi=1e-12, verify=True)
+    assert s2["status"] == 0 and sp["status"] == 0
+    res = {"workload": "R-MAT n=10,000, 100,000 distinct edges drawn, 10% forced dangling, seed 0",
+           "n": g.n, "m": g.m, "xi": 1e-12,
+           "ifp2_ms": t2 * 1e3, "ifp2_sweeps": s2["sweeps"], "ifp2_launches": s2["launches"],
+           "ifp2_us_per_launch": t2 * 1e6 / max(1, s2["launches"]), "ifp2_device_ms": s2["seconds_solve"] * 1e3,
+           "ifp2_l1_bound": s2["l1_bound"], "ifp2_l1_verified": v2["l1_verified"],
+           "ifp1_ms": t1 * 1e3, "ifp1_sweeps": s1["sweeps"], "ifp1_launches": s1["launches"],
+           "power_ms": tp * 1e3, "power_iterations": sp["sweeps"], "power_launches": sp["launches"],
+           "power_l1_tol": tol, "ifp2_over_power": tp / t2}
+    log(f"[bench] small FP64: {res}")
+    dg.free()
+    return res
+
+
+def run_dag(pr, prgen, c, args):
+    """The layered-DAG workload (2^23 vertices in 64 layers, Zipf(2.0) out-degrees capped at
+    10^4 scaled to 80M forward edges, 2 % back edges): IFP2, IFP1 and the power method with
+    FP32 residuals at certified L1 <= tol, and IFP2 on the graph uploaded with its weakly
+    dangling vertices peeled; each tuned once like the main graph."""
+    import torch
+    t0 = time.perf_counter()
+    g = prgen.workload_dag()
+    log(f"[bench] dag: n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f}s")
+    out = torch.empty(g.n, dtype=torch.float64, device="cuda")
+    dg = pr.upload(g.row_ptr, g.col)
+    if not args.no_tune:
+        pr.tune(dg, c=c, l1_tol=args.tol, residual="fp32", reps=2)
+    info = dg.info()
+    t2, s2 = _timed(lambda: pr.ifp2(dg, c=c, l1_tol=args.tol, residual="fp32", out=out), args.steps, args.warmup)
+    t1, s1 = _timed(lambda: pr.ifp1(dg, c=c, l1_tol=args.tol, residual="fp32", out=out), args.steps, args.warmup)
+    tp, sp = _timed(lambda: pr.power(dg, c=c, l1_tol=args.tol, residual="fp32", out=out), args.steps, args.warmup)
+    _, v2 = pr.ifp2(dg, c=c, l1_tol=args.tol, residual="fp32", out=out, verify=True)
+    dg.free()
+    dp = pr.upload(g.row_ptr, g.col, peel=True)
+    if not args.no_tune:
+        pr.tune(dp, c=c, l1_tol=args.tol, residual="fp32", reps=2)
+    pinfo = dp.info()
+    tq, sq = _timed(lambda: pr.ifp2(dp, c=c, l1_tol=args.tol, residual="fp32", out=out), args.steps, args.warmup)
+    dp.free()
+    for st in (s2, s1, sp, sq):
+        assert st["status"] == 0 and st["l1_bound"] <= args.tol
+    res = {"workload": "layered DAG: 2^23 vertices in 64 layers, Zipf(2.0) out-degrees capped at 10^4, "
+                       "80M forward + 2% back edges, seed 0",
+           "n": g.n, "m": g.m, "lambda": g.meta["lambda"],
+           "ifp2_ms": t2 * 1e3, "ifp2_sweeps": s2["sweeps"], "ifp2_gteps": g.m / t2 / 1e9,
+           "ifp2_l1_verified": v2["l1_verified"],
+           "ifp1_ms": t1 * 1e3, "ifp1_sweeps": s1["sweeps"], "ifp1_gteps": g.m / t1 / 1e9,
+           "power_ms": tp * 1e3, "power_iterations": sp["sweeps"], "power_gteps": g.m / tp / 1e9,
+           "peeled_ms": tq * 1e3, "peeled_sweeps": sq["sweeps"], "peeled_gteps": g.m / tq / 1e9,
+           "n_peeled": pinfo["n_peeled"], "peel_levels": pinfo["peel_levels"],
+           "ifp2_over_power": tp / t2, "peeled_over_power": tp / tq,
+           "schedule": {"tile_items": info["tile_items"], "ordered_sweeps": bool(info["ordered"]),
+                        "groups": info["groups"]}}
+    log(f"[bench] dag: {res}")
+    return res
 
 
 def run_peel(pr, g, c, args, t_plain, st_plain):

@@ -97,6 +97,13 @@ typedef enum {
 #define PR_FORCE_PULL 0x10u  /* every sweep gathers along in-edges (no atomics) */
 #define PR_PROFILE 0x20u     /* time each sweep kernel with HIP events (stats->kernel_*) */
 #define PR_JACOBI 0x40u      /* IFP1 / IFP2: synchronous sweeps even where ordered sweeps apply */
+/* After the solve, check the written result a posteriori in FP64: one application of
+   the power-method matrix P'' (Eq. 1) to pi gives r = P'' pi - pi, and
+   stats->l1_verified = ||r||_1 / (1 - c) + |sum(pi) - 1| plus the rounding of the check
+   bounds ||pi - pi_exact||_1 whatever the residual precision (P'' contracts the
+   difference of two vectors of equal sum by c in L1).  Costs about one power-method
+   iteration; under PR_STOP_L1 a verified bound above l1_tol gives PR_ENOCONV. */
+#define PR_VERIFY 0x80u
 
 typedef struct {
     double c;           /* damping factor, 0 < c < 1 (section 2.1) */
@@ -107,7 +114,7 @@ typedef struct {
     int32_t residual;   /* pr_residual */
     int32_t max_sweeps; /* 0 -> 100000 */
     uint32_t flags;     /* PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE
-                           | PR_JACOBI */
+                           | PR_JACOBI | PR_VERIFY */
     void *stream;       /* hipStream_t to run on; NULL -> the graph's own stream */
 } pr_opts;
 
@@ -119,7 +126,10 @@ typedef struct {
     int64_t edges_traversed;    /* edges the kernels actually read (a pull sweep reads every in-edge) */
     int64_t vertex_pushes;      /* sum over sweeps of the number of vertices that pushed */
     double residual_l1;         /* final non-dangling residual / total mass (power: last ||x' - x||_1) */
-    double l1_bound;            /* certified upper bound on ||pi - pi_exact||_1 */
+    double l1_bound;            /* bound on ||pi - pi_exact||_1 from the stop rule's certificate; it
+                                   assumes exact arithmetic, so with FP32 residuals it is an
+                                   estimate (rounding of the pushes is not included): PR_VERIFY
+                                   gives a bound that holds for the computed result */
     double seconds_solve;       /* device time from initialisation to the written result */
     double seconds_preprocess;  /* one-time per-graph preprocessing charged to this method (seconds) */
     /* PR_PROFILE only (else 0): the scatter (push) and gather (pull) kernels of the sweeps,
@@ -129,6 +139,8 @@ typedef struct {
     int64_t push_launches;
     double pull_seconds, pull_bytes;
     int64_t pull_launches;
+    int64_t launches;           /* kernels the solve enqueued (sweeps past the stop return at once) */
+    double l1_verified;         /* PR_VERIFY: a-posteriori bound on ||pi - pi_exact||_1 (else 0) */
 } pr_stats;
 
 typedef struct {

@@ -55,6 +55,15 @@ def _load():
     return lib
 
 
+def use_library(path: str) -> None:
+    """Load the oracle's functions from another build of oracle.c (the host-tuned build
+    that times the CPU baseline); later calls use it."""
+    global _LIB_PATH, _lib
+    _LIB_PATH = path
+    _lib = None
+    _load()
+
+
 def _graph(g):
     if isinstance(g, tuple):
         n, rp, col = g

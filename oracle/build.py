@@ -18,5 +18,20 @@ def build(verbose: bool = False) -> str:
     return out
 
 
+def build_native(out: str, verbose: bool = False) -> str:
+    """The same oracle compiled for the host it runs on (-O3 -march=native), for timing
+    the CPU baseline; -ffp-contract=off keeps every product and sum separately rounded,
+    as in the portable build."""
+    src = os.path.join(_HERE, "oracle.c")
+    tmp = out + ".tmp"
+    cmd = ["gcc", "-O3", "-march=native", "-ffp-contract=off", "-fPIC", "-shared", "-std=c11", "-o", tmp, src,
+           "-lm"]
+    if verbose:
+        print(" ".join(cmd))
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build(verbose=True))

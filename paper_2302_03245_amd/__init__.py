@@ -24,7 +24,7 @@ PR_RES_FP64, PR_RES_FP32 = 0, 1
 PR_STOP_XI, PR_STOP_L1 = 0, 1
 PR_INPUT_DEVICE, PR_DEDUPE, PR_PEEL = 0x1, 0x2, 0x20000
 PR_P_DEVICE, PR_OUT_DEVICE, PR_IFP2_LITERAL = 0x1, 0x2, 0x4
-PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE, PR_JACOBI = 0x8, 0x10, 0x20, 0x40
+PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE, PR_JACOBI, PR_VERIFY = 0x8, 0x10, 0x20, 0x40, 0x80
 
 # every symbol the public headers declare
 EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_info", "pr_solve_ifp1",
@@ -58,7 +58,8 @@ class Stats(ctypes.Structure):
                 ("push_seconds", ctypes.c_double), ("push_bytes", ctypes.c_double),
                 ("push_launches", ctypes.c_int64),
                 ("pull_seconds", ctypes.c_double), ("pull_bytes", ctypes.c_double),
-                ("pull_launches", ctypes.c_int64)]
+                ("pull_launches", ctypes.c_int64), ("launches", ctypes.c_int64),
+                ("l1_verified", ctypes.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -341,9 +342,9 @@ class State:
 
 
 def ifp2_warm(g: Graph, state: State, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
-              stream=None, mode=None, profile=False):
+              stream=None, mode=None, profile=False, verify=False):
     """IFP2 resumed from `state` (and leaving its end state there)."""
-    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, profile)
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, profile, verify=verify)
     if out is None:
         out = np.empty(g.n, dtype=np.float64)
     out_keep, out_ptr, out_dev = _ptr_any(out, np.float64, "float64")
@@ -466,7 +467,8 @@ def set_tune(gs: GraphSet, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", reps=
     return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds}
 
 
-def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, power=False, jacobi=False):
+def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, power=False, jacobi=False,
+          verify=False):
     o = Opts()
     lib().pr_opts_default(ctypes.byref(o))
     o.c = c
@@ -492,6 +494,8 @@ def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, p
         flags |= PR_PROFILE
     if jacobi:
         flags |= PR_JACOBI
+    if verify:
+        flags |= PR_VERIFY
     o.flags = flags
     return o
 
@@ -523,25 +527,27 @@ def _solve(fn, g, p, o, out):
 
 
 def ifp1(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
-         stream=None, mode=None, profile=False, jacobi=False):
+         stream=None, mode=None, profile=False, jacobi=False, verify=False):
     """IFP1 (Algorithm 2).  `l1_tol` switches to the certified-L1 stop rule; `jacobi`
-    keeps synchronous sweeps on a graph with vertex groups."""
-    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, profile, jacobi=jacobi)
+    keeps synchronous sweeps on a graph with vertex groups; `verify` adds the
+    a-posteriori bound l1_verified (PR_VERIFY)."""
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, profile, jacobi=jacobi, verify=verify)
     return _solve(lib().pr_solve_ifp1, g, p, o, out)
 
 
 def ifp2(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
-         stream=None, literal=False, mode=None, profile=False, jacobi=False):
+         stream=None, literal=False, mode=None, profile=False, jacobi=False, verify=False):
     """IFP2 (Algorithm 3).  `literal` drops the leftover residual at normalisation;
-    `jacobi` keeps global solves on synchronous sweeps (no ordered groups)."""
-    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, jacobi=jacobi)
+    `jacobi` keeps global solves on synchronous sweeps (no ordered groups); `verify`
+    adds the a-posteriori bound l1_verified (PR_VERIFY)."""
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, jacobi=jacobi, verify=verify)
     return _solve(lib().pr_solve_ifp2, g, p, o, out)
 
 
 def power(g: Graph, p=None, c=0.85, l1_tol=1e-9, residual="fp64", max_sweeps=0, out=None, stream=None,
-          profile=False):
+          profile=False, verify=False):
     """Power method on P'' until the certified L1 error is <= l1_tol."""
-    o = _opts(c, None, l1_tol, residual, max_sweeps, stream, False, None, profile, power=True)
+    o = _opts(c, None, l1_tol, residual, max_sweeps, stream, False, None, profile, power=True, verify=verify)
     return _solve(lib().pr_solve_power, g, p, o, out)
 
 
@@ -559,13 +565,13 @@ def last_trace() -> dict:
 
 
 def ppr(g: Graph, sources, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, stream=None,
-        mode=None, out=None, jacobi=False):
+        mode=None, out=None, jacobi=False, verify=False):
     """Single-source PPR for each source (IFP2, sources batched sixteen at a time);
     returns (float64[k, n], list of stats dicts).  `out` may be a (k, n) float64 numpy
     array or torch CUDA tensor."""
     src = np.ascontiguousarray(sources, dtype=np.int32)
     k = int(src.shape[0])
-    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, False, jacobi=jacobi)
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, False, mode, False, jacobi=jacobi, verify=verify)
     if out is None:
         out = np.empty((k, g.n), dtype=np.float64)
     out_keep, out_ptr, out_dev = _ptr_any(out, np.float64, "float64")

@@ -37,7 +37,8 @@ pr_status check_opts(const pr_opts &o, bool power) {
     if (o.residual != PR_RES_FP64 && o.residual != PR_RES_FP32) return fail(PR_EINVAL, "unknown residual type");
     if (o.max_sweeps < 0) return fail(PR_EINVAL, "max_sweeps < 0");
     const uint32_t known =
-        PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE | PR_JACOBI;
+        PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE | PR_JACOBI |
+        PR_VERIFY;
     if (o.flags & ~known) return fail(PR_EINVAL, "unknown option flag");
     if ((o.flags & PR_FORCE_PUSH) && (o.flags & PR_FORCE_PULL))
         return fail(PR_EINVAL, "PR_FORCE_PUSH and PR_FORCE_PULL together");
@@ -404,7 +405,7 @@ pr_status pr_set_solve_ifp2(const pr_graph_set *s, const double *c, const pr_opt
     if (c) op.c = 0.5;  // per-graph factors are checked by the solve
     pr_status ps = check_opts(op, false);
     if (ps != PR_OK) return ps;
-    if (op.flags & (PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE))
+    if (op.flags & (PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE | PR_VERIFY))
         return fail(PR_EINVAL, "option flag not supported for graph sets");
     ps = enter(s->u);
     if (ps != PR_OK) return ps;
@@ -456,7 +457,8 @@ pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_
     try {
         // groups of kBatch sources share one batched solve; a lone source runs alone, as
         // does every source on a peeled graph (the batched sweeps cover every non-dangling row)
-        const int32_t width = G.nP > 0 ? 1 : kBatch;
+        // (and with PR_VERIFY, whose check is part of the single-vector solve)
+        const int32_t width = (G.nP > 0 || (op.flags & PR_VERIFY)) ? 1 : kBatch;
         const int32_t nbatch = (k + width - 1) / width;
         const hipStream_t s = op.stream ? (hipStream_t)op.stream : G.stream;
         // more than one batch: every row is solved into device staging first and copied

@@ -75,7 +75,8 @@ struct alignas(128) Ctl {
     // finalisation
     double fin_sum, fin_sn;
     double fin_abs;       // sum |x| (equals fin_sum unless residuals went negative)
-    double pad1[3];
+    // a-posteriori check (PR_VERIFY): ||P'' pi - pi||_1, its rounding bound, sum(pi)
+    double ver_r, ver_err, ver_sum;
 };
 
 // Control block of a batch of B <= kMaxBatch vectors (see Ctl).
@@ -296,6 +297,14 @@ hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, 
                                  const int32_t *deg, double c, double tol, double *part, hipStream_t s);
 hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStream_t s);
 hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, double *part, hipStream_t s);
+// a-posteriori check of the normalised output `out` (original order, device): fills
+// vctl->ver_r / ver_err / ver_sum; x, acc: n doubles, y: doubles for every vertex with
+// out-edges; *depth receives the reduction depth used for the rounding bound
+hipError_t launch_verify(Ctl *vctl, const InitArgs &a, const double *out, double *x, double *acc, double *y,
+                         const int32_t *deg, const MPPlan &pull_all, const uint32_t *in_ptr, double c, double *part,
+                         double *depth, hipStream_t s);
+// kernel launches of the calling thread so far (counted by the launchers)
+extern thread_local int64_t t_kernel_launches;
 hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s);
 hipError_t launch_unit_vector(double *out, int64_t n, int64_t src, hipStream_t s);
 

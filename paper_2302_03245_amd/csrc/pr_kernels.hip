@@ -978,6 +978,58 @@ __global__ void k_final_x_write(const Ctl *ctl, InitArgs a, const double *x, dou
         out[a.perm[i]] = x[i] * inv;
 }
 
+// ------------------------------------------------------------------------
+// a-posteriori check of a written result (PR_VERIFY): for the normalised output
+// pi, one application of the power-method matrix P'' of Eq. 1 gives the residual
+// r = P'' pi - pi; since P'' contracts differences of equal sum by c in L1,
+// ||pi - pi_exact||_1 <= ||r||_1 / (1 - c) + |sum(pi) - 1|, whatever arithmetic
+// produced pi.  The rounding of the check itself is bounded row by row.
+// ------------------------------------------------------------------------
+__global__ void k_verify_load(int64_t n, const int32_t *perm, const double *out, double *x, double *acc) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
+        x[i] = out[perm[i]];
+        acc[i] = 0.0;
+    }
+}
+
+// per row j: r_j = |acc_j + b p_j - x_j| with acc_j = sum over in-edges of c x_u / deg(u);
+// err_j bounds the FP64 rounding of computing it: the k_j-term sum of acc_j (any order:
+// k_j - 1 additions), the quotients c x_u / deg(u) (2 each), b (depth_b additions of
+// its reduction) and the final add, subtract and absolute value
+__global__ __launch_bounds__(kBlock) void k_verify_residual(const Ctl *ctl, InitArgs a, const uint32_t *in_ptr,
+                                                            const double *x, const double *acc, double depth_b,
+                                                            double *part) {
+    const double b = ctl->pw_b;
+    double r = 0.0, err = 0.0, xs = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        const double k = (double)(in_ptr[i + 1] - in_ptr[i]);
+        const double bp = b * p_of(a, i);
+        const double v = acc[i] + bp;
+        r += fabs(v - x[i]);
+        err += (k + 4.0 + depth_b) * (acc[i] + bp + x[i]);
+        xs += x[i];
+    }
+    __shared__ double sd[kBlock / W];
+    r = block_sum(r, sd);
+    err = block_sum(err, sd);
+    xs = block_sum(xs, sd);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = r;
+        part[gridDim.x + blockIdx.x] = err;
+        part[2 * gridDim.x + blockIdx.x] = xs;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_verify_decide(Ctl *ctl, int nb, const double *part) {
+    __shared__ double sd[3 * (kBlock / W)];
+    double v[3];
+    reduce_partials_n(part, nb, v, sd);
+    if (threadIdx.x != 0) return;
+    ctl->ver_r = v[0];
+    ctl->ver_err = v[1];
+    ctl->ver_sum = v[2];
+}
+
 // p validation: sum_bad[0] += p_i, sum_bad[1] += 1 for every negative or non-finite entry
 __global__ __launch_bounds__(kBlock) void k_validate_p(const double *p, int64_t n, double *sum_bad) {
     double s = 0.0, bad = 0.0;
@@ -1000,10 +1052,17 @@ __global__ __launch_bounds__(kBlock) void k_validate_p(const double *p, int64_t 
 // ------------------------------------------------------------------------
 // launchers
 // ------------------------------------------------------------------------
-#define PRK_LAUNCH(kern, grid, ...)                                                   \
-    do {                                                                              \
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);        \
-        return hipGetLastError();                                                     \
+// every kernel launch of this file is counted (the launches field of a solve's stats)
+thread_local int64_t t_kernel_launches = 0;
+#define PRK_GGL(...)                        \
+    do {                                    \
+        ++t_kernel_launches;                \
+        hipLaunchKernelGGL(__VA_ARGS__);    \
+    } while (0)
+#define PRK_LAUNCH(kern, grid, ...)                                          \
+    do {                                                                     \
+        PRK_GGL(kern, dim3(grid), dim3(kBlock), 0, s, __VA_ARGS__);          \
+        return hipGetLastError();                                            \
     } while (0)
 
 hipError_t launch_check_cols(const int32_t *col, int64_t m, int64_t n, unsigned int *bad, hipStream_t s) {
@@ -1024,9 +1083,9 @@ hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_
         return hipMemsetAsync(out, 0, sizeof(uint32_t), s);
     }
     int64_t nb = (n + kScanTile - 1) / kScanTile;
-    hipLaunchKernelGGL(k_scan_partial, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tmp);
-    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb);
-    hipLaunchKernelGGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, (const uint32_t *)tmp);
+    PRK_GGL(k_scan_partial, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, tmp);
+    PRK_GGL(k_scan_top, dim3(1), dim3(kBlock), 0, s, tmp, nb);
+    PRK_GGL(k_scan_final, dim3((unsigned)nb), dim3(kBlock), 0, s, in, out, n, (const uint32_t *)tmp);
     return hipGetLastError();
 }
 hipError_t launch_relabel(const uint32_t *isN, const uint32_t *rankN, int64_t n, int32_t nN, int32_t *newid,
@@ -1099,9 +1158,9 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
                           unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
                           double *part, hipStream_t s) {
     const int nb = grid_for(nN, 4, kRedBlocks);
-    hipLaunchKernelGGL(k_reserve<T>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, 0, nN, h, w, pibar, deg,
+    PRK_GGL(k_reserve<T>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, 0, nN, h, w, pibar, deg,
                        rp_nn, c, (T)xi, ifp2, part);
-    hipLaunchKernelGGL(k_decide_ifp, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, nb, (const double *)part, c, stop_l1,
+    PRK_GGL(k_decide_ifp, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, nb, (const double *)part, c, stop_l1,
                        tol, pull_edges_thr, force, pull_edges);
     return hipGetLastError();
 }
@@ -1110,7 +1169,7 @@ template <typename T>
 hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
                                 const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2, int nbg,
                                 double *part, hipStream_t s) {
-    hipLaunchKernelGGL(k_reserve<T>, dim3(nbg), dim3(kBlock), 0, s, t, (const Ctl *)ctl, lo, hi, h, w, pibar, deg,
+    PRK_GGL(k_reserve<T>, dim3(nbg), dim3(kBlock), 0, s, t, (const Ctl *)ctl, lo, hi, h, w, pibar, deg,
                        rp_nn, c, (T)xi, ifp2, part);
     return hipGetLastError();
 }
@@ -1120,8 +1179,8 @@ hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, 
                             const double *part, double *part_s, double c, int stop_l1, double tol,
                             unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s) {
     const int nbs = grid_for(nN, 8, kRedBlocks);
-    hipLaunchKernelGGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, part_s);
-    hipLaunchKernelGGL(k_decide_gs, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, ng, gb, part, nbs,
+    PRK_GGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, part_s);
+    PRK_GGL(k_decide_gs, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, ng, gb, part, nbs,
                        (const double *)part_s, c, stop_l1, tol, pull_thr, pull_edges);
     return hipGetLastError();
 }
@@ -1129,8 +1188,12 @@ hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, 
 // a launch that is timed takes its start / stop timestamps itself
 template <typename F, typename... Args>
 hipError_t launch_timed(F kern, int grid, hipStream_t s, KernelEvents ev, Args... args) {
-    if (ev.a || ev.b) hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, ev.a, ev.b, 0, args...);
-    else hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, args...);
+    if (ev.a || ev.b) {
+        ++t_kernel_launches;
+        hipExtLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, ev.a, ev.b, 0, args...);
+    } else {
+        PRK_GGL(kern, dim3(grid), dim3(kBlock), 0, s, args...);
+    }
     return hipGetLastError();
 }
 
@@ -1190,9 +1253,9 @@ template <typename T>
 hipError_t launch_final_ifp(Ctl *ctl, const InitArgs &a, const T *h, const double *pibar, const double *xD,
                             int ifp2, int literal, double *out, double *part, hipStream_t s) {
     const int nb = grid_for(a.n, 4, kRedBlocks);
-    hipLaunchKernelGGL(k_final_sum<T>, dim3(nb), dim3(kBlock), 0, s, a, h, pibar, xD, ifp2, literal, part);
-    hipLaunchKernelGGL(k_final_decide, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
-    hipLaunchKernelGGL(k_final_write<T>, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, h,
+    PRK_GGL(k_final_sum<T>, dim3(nb), dim3(kBlock), 0, s, a, h, pibar, xD, ifp2, literal, part);
+    PRK_GGL(k_final_decide, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
+    PRK_GGL(k_final_write<T>, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, h,
                        pibar, xD, ifp2, literal, out);
     return hipGetLastError();
 }
@@ -1205,17 +1268,36 @@ template <typename WT>
 hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, double *acc, WT *y,
                                  const int32_t *deg, double c, double tol, double *part, hipStream_t s) {
     const int nb = grid_for(a.n, 4, kRedBlocks);
-    hipLaunchKernelGGL(k_power_prescale<WT>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, a, x, acc, y, deg, c,
+    PRK_GGL(k_power_prescale<WT>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, a, x, acc, y, deg, c,
                        part);
-    hipLaunchKernelGGL(k_decide_power, dim3(1), dim3(kBlock), 0, s, t, ctl, nb, (const double *)part, c, tol);
+    PRK_GGL(k_decide_power, dim3(1), dim3(kBlock), 0, s, t, ctl, nb, (const double *)part, c, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_verify(Ctl *vctl, const InitArgs &a, const double *out, double *x, double *acc, double *y,
+                         const int32_t *deg, const MPPlan &pull_all, const uint32_t *in_ptr, double c, double *part,
+                         double *depth, hipStream_t s) {
+    const int nb = grid_for(a.n, 4, kRedBlocks);
+    // depth of a reduction over n entries as the sums below run it: a thread's strided
+    // run, the workgroup tree, and the partials summed by one thread per lane
+    *depth = (double)((a.n + (int64_t)nb * kBlock - 1) / ((int64_t)nb * kBlock)) + 8.0 + (double)nb;
+    PRK_GGL(k_verify_load, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, a.n, a.perm, out, x, acc);
+    PRK_GGL(k_power_prescale<double>, dim3(nb), dim3(kBlock), 0, s, 0, (const Ctl *)vctl, a, x, acc, y, deg, c,
+            part);
+    PRK_GGL(k_decide_power, dim3(1), dim3(kBlock), 0, s, 0, vctl, nb, (const double *)part, c, 0.0);
+    hipError_t e = launch_pull<double, double>(0, vctl, pull_all, y, acc, 0, s);
+    if (e != hipSuccess) return e;
+    PRK_GGL(k_verify_residual, dim3(nb), dim3(kBlock), 0, s, (const Ctl *)vctl, a, in_ptr, (const double *)x,
+            (const double *)acc, *depth, part);
+    PRK_GGL(k_verify_decide, dim3(1), dim3(kBlock), 0, s, vctl, nb, (const double *)part);
     return hipGetLastError();
 }
 
 hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, double *part, hipStream_t s) {
     const int nb = grid_for(a.n, 4, kRedBlocks);
-    hipLaunchKernelGGL(k_final_x_sum, dim3(nb), dim3(kBlock), 0, s, a.n, x, part);
-    hipLaunchKernelGGL(k_final_decide, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
-    hipLaunchKernelGGL(k_final_x_write, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, x,
+    PRK_GGL(k_final_x_sum, dim3(nb), dim3(kBlock), 0, s, a.n, x, part);
+    PRK_GGL(k_final_decide, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
+    PRK_GGL(k_final_x_write, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, x,
                        out);
     return hipGetLastError();
 }

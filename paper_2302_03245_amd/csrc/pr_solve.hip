@@ -83,6 +83,34 @@ int next_batch(int prev_batch, double bound_prev, double bound_now, int swept, d
     return std::min(64, prev_batch * 2);
 }
 
+// A-posteriori check of a written result (PR_VERIFY): one application of P'' (Eq. 1)
+// to the normalised output in FP64 (the vertices with out-edges are [0, nN + nP)).
+// The copy of the control block is read back with the solve's own (same stream).
+static hipError_t run_verify(const Graph &G, const InitArgs &a, double c, const double *out, double *x, double *acc,
+                             double *y, Ctl *vctl, double *part, Ctl *res, double *depth, hipStream_t s) {
+    Ctl hc;
+    memset(&hc, 0, sizeof(hc));
+    hc.stop_after = INT_MAX;
+    hipError_t e = hipMemcpyAsync(vctl, &hc, sizeof(Ctl), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    InitArgs av = a;
+    av.nN = G.nN + G.nP;
+    e = launch_verify(vctl, av, out, x, acc, y, G.deg, G.pull_all, G.in_ptr, c, part, depth, s);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(res, vctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+// ||pi - pi_exact||_1 <= ||P'' pi - pi||_1 / (1 - c) + |sum(pi) - 1| (P'' contracts by c
+// the differences of vectors with equal sums), each FP64 quantity widened by the
+// rounding of its own computation (unit roundoff 2^-53, first order, with 1 % margin)
+static double verified_bound(const Ctl &v, double depth, double c) {
+    const double u = ldexp(1.0, -53) * 1.01;
+    const double r = v.ver_r * (1.0 + depth * u) + v.ver_err * u;
+    return r / (1.0 - c) + fabs(v.ver_sum - 1.0) + depth * u * v.ver_sum;
+}
+
 template <typename T>
 pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
                       pr_stats *st, const WarmArgs *warm) {
@@ -102,8 +130,11 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     }
     const double tol = l1 ? o.l1_tol * (1.0 - 1e-6) : 0.0;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
+    const int64_t launches0 = t_kernel_launches;
+    const bool verify = o.flags & PR_VERIFY;
 
-    size_t bytes = carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
+    size_t bytes = (verify ? 2 * carve_size<double>(n) + carve_size<Ctl>(1) : 0) +
+                   carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
                    carve_size<double>(nN + G.nP) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
                    carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
                    carve_size<double>(2) + carve_size<double>(kPartDoubles) +
@@ -129,6 +160,9 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     double *xD0 = warm ? cv.take<double>(nD) : nullptr;
     double *hD0 = warm ? cv.take<double>(nD) : nullptr;
     double *hDn = warm ? cv.take<double>(nD) : nullptr;
+    double *vx = verify ? cv.take<double>(n) : nullptr;
+    double *vacc = verify ? cv.take<double>(n) : nullptr;
+    Ctl *vctl = verify ? cv.take<Ctl>(1) : nullptr;
 
     InitArgs a{};
     a.n = n;
@@ -263,10 +297,14 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, dst, part, s));
     if (warm) HIPCHK(launch_warm_export<T>(n, nN, G.perm, h, pibar, hDn, warm->pibar, warm->h, s));
     HIPCHK(hipEventRecord(ev_solve.b, s));
+    Ctl vres;
+    double vdepth = 0.0;
+    if (verify) HIPCHK(run_verify(G, a, c, dst, vx, vacc, w2, vctl, part, &vres, &vdepth, s));
     HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const Ctl &r = *ws.hctl;
+    const double l1_verified = verify ? verified_bound(vres, vdepth, c) : 0.0;
     if (st) {
         pr_stats z;
         memset(&z, 0, sizeof(z));
@@ -287,6 +325,8 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         }
         z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
         z.seconds_preprocess = ifp2 ? G.seconds_split : 0.0;
+        z.launches = t_kernel_launches - launches0;
+        z.l1_verified = l1_verified;
         if (timer.on) {
             std::vector<unsigned long long> trc((size_t)std::min(r.sweeps + 1, kMaxTrace));
             std::vector<unsigned long long> tre(trc.size());
@@ -329,6 +369,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         }
         *st = z;
     }
+    if (verify && l1 && l1_verified > o.l1_tol) return PR_ENOCONV;
     return stopped ? PR_OK : PR_ENOCONV;
 }
 
@@ -341,7 +382,10 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     const double c = o.c;
     const double tol = o.l1_tol * (1.0 - 1e-6);
     const int max_it = o.max_sweeps > 0 ? o.max_sweeps : 100000;
-    size_t bytes = carve_size<double>(n) * 2 + carve_size<WT>(nN) + carve_size<double>(out_dev ? 0 : n) +
+    const int64_t launches0 = t_kernel_launches;
+    const bool verify = o.flags & PR_VERIFY;
+    size_t bytes = (verify ? carve_size<double>(nN) + carve_size<Ctl>(1) : 0) +
+                   carve_size<double>(n) * 2 + carve_size<WT>(nN) + carve_size<double>(out_dev ? 0 : n) +
                    carve_size<Ctl>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
                    carve_size<double>(2) + carve_size<double>(5 * kRedBlocks);
     Workspace ws;
@@ -356,6 +400,8 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     double *pdev = cv.take<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0);
     double *sumbad = cv.take<double>(2);
     double *part = cv.take<double>(5 * kRedBlocks);
+    double *vy = verify ? cv.take<double>(nN) : nullptr;
+    Ctl *vctl = verify ? cv.take<Ctl>(1) : nullptr;
     InitArgs a{};
     a.n = n;
     a.nN = nN;
@@ -401,10 +447,15 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     double *dst = out_dev ? pi : outbuf;
     HIPCHK(launch_final_x(ctl, a, x, dst, part, s));
     HIPCHK(hipEventRecord(ev_solve.b, s));
+    Ctl vres;
+    double vdepth = 0.0;
+    // the iterate buffers are free once the answer is written: the check reuses them
+    if (verify) HIPCHK(run_verify(G, a, c, dst, x, acc, vy, vctl, part, &vres, &vdepth, s));
     HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const Ctl &r = *ws.hctl;
+    const double l1_verified = verify ? verified_bound(vres, vdepth, c) : 0.0;
     if (st) {
         pr_stats z;
         memset(&z, 0, sizeof(z));
@@ -416,6 +467,8 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
         z.residual_l1 = r.pw_diff;
         z.l1_bound = c / (1.0 - c) * r.pw_diff;
         z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
+        z.launches = t_kernel_launches - launches0;
+        z.l1_verified = l1_verified;
         if (timer.on) {
             const double sW = (double)sizeof(WT);
             for (size_t i = 0; i < timer.ev.size(); ++i) {
@@ -427,6 +480,7 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
         }
         *st = z;
     }
+    if (verify && l1_verified > o.l1_tol) return PR_ENOCONV;
     return stopped ? PR_OK : PR_ENOCONV;
 }
 

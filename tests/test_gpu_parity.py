@@ -268,6 +268,57 @@ def test_ppr_batches(pr, mode):
         assert l1(out32[r], ref) <= 1e-6, (r, s)
 
 
+def _pagerank_residual(g, pi, c, p):
+    """||P'' pi - pi||_1 in FP64 with P'' = c P' + (1 - c) p e^T (Eq. 1), P' = P + p d^T."""
+    import scipy.sparse as sp
+    deg = np.diff(g.row_ptr)
+    src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
+    inv = np.zeros(g.n)
+    inv[deg > 0] = 1.0 / deg[deg > 0]
+    P = sp.csr_matrix((inv[src], (g.col, src)), shape=(g.n, g.n))
+    b = c * pi[deg == 0].sum() + (1 - c) * pi.sum()
+    return float(np.abs(c * (P @ pi) + b * p - pi).sum())
+
+
+@pytest.mark.parametrize("residual", ["fp64", "fp32"])
+def test_verified_bound(pr, residual):
+    """PR_VERIFY: the a-posteriori bound ||P'' pi - pi||_1 / (1 - c) + |sum(pi) - 1| (plus
+    the rounding of the check) is computed as defined (against the same quantity in
+    numpy from the returned vector) and bounds the distance to the oracle, for IFP1,
+    IFP2 (folded and literal), the power method and single-source PPR."""
+    g = prgen.random_digraph(20011, 150000, seed=2, self_loops=True, multi=True, dangling_frac=0.3)
+    ref, _, delta = oracle.power(g, C, tol=1e-13)
+    ref_err = C / (1 - C) * delta
+    dg = pr.upload(g.row_ptr, g.col)
+    u = np.full(g.n, 1.0 / g.n)
+    tol = 1e-6 if residual == "fp32" else 1e-10
+    runs = [("ifp1", lambda: pr.ifp1(dg, c=C, l1_tol=tol, residual=residual, verify=True)),
+            ("ifp2", lambda: pr.ifp2(dg, c=C, l1_tol=tol, residual=residual, verify=True)),
+            ("ifp2_literal", lambda: pr.ifp2(dg, c=C, l1_tol=tol, residual=residual, literal=True, verify=True)),
+            ("power", lambda: pr.power(dg, c=C, l1_tol=tol, residual=residual, verify=True))]
+    for name, run in runs:
+        pi, st = run()
+        d = l1(pi, ref)
+        r = _pagerank_residual(g, pi, C, u)
+        own = r / (1 - C) + abs(pi.sum() - 1)
+        _say(f"{name} {residual}: L1 {d:.3e} bound {st['l1_bound']:.3e} verified {st['l1_verified']:.3e} "
+             f"(numpy {own:.3e}) launches {st['launches']}")
+        assert st["status"] == 0
+        assert st["l1_verified"] >= d - ref_err, (name, st["l1_verified"], d)
+        assert st["l1_verified"] <= tol
+        assert abs(st["l1_verified"] - own) <= 1e-3 * own + 1e-14, (name, st["l1_verified"], own)
+        assert st["launches"] > 0
+    s = int(np.argmax(np.diff(g.row_ptr)))
+    e = np.zeros(g.n)
+    e[s] = 1.0
+    ref_s, _, delta_s = oracle.power(g, C, e, tol=1e-13)
+    out, sts = pr.ppr(dg, [s], c=C, l1_tol=tol, residual=residual, verify=True)
+    own = _pagerank_residual(g, out[0], C, e) / (1 - C) + abs(out[0].sum() - 1)
+    assert sts[0]["l1_verified"] >= l1(out[0], ref_s) - C / (1 - C) * delta_s
+    assert abs(sts[0]["l1_verified"] - own) <= 1e-3 * own + 1e-14
+    dg.free()
+
+
 def test_ppr_failing_later_batch_writes_nothing(pr):
     """A pr_ppr call whose second batch fails (testing hook: as if that batch's workspace
     could not be allocated) returns the negative status and leaves every output row and
