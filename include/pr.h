@@ -104,6 +104,10 @@ typedef enum {
    difference of two vectors of equal sum by c in L1).  Costs about one power-method
    iteration; under PR_STOP_L1 a verified bound above l1_tol gives PR_ENOCONV. */
 #define PR_VERIFY 0x80u
+/* IFP1 / IFP2: every sweep scatters from the compacted frontier list (the vertices with
+   residual > xi, kept as a list of ids between sweeps); without it a solve uses list
+   sweeps while its frontier is sparse.  Not with PR_FORCE_PUSH / PR_FORCE_PULL. */
+#define PR_FORCE_LIST 0x100u
 
 typedef struct {
     double c;           /* damping factor, 0 < c < 1 (section 2.1) */
@@ -114,7 +118,7 @@ typedef struct {
     int32_t residual;   /* pr_residual */
     int32_t max_sweeps; /* 0 -> 100000 */
     uint32_t flags;     /* PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE
-                           | PR_JACOBI | PR_VERIFY */
+                           | PR_JACOBI | PR_VERIFY | PR_FORCE_LIST */
     void *stream;       /* hipStream_t to run on; NULL -> the graph's own stream */
 } pr_opts;
 

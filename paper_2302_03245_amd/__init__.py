@@ -24,7 +24,7 @@ PR_RES_FP64, PR_RES_FP32 = 0, 1
 PR_STOP_XI, PR_STOP_L1 = 0, 1
 PR_INPUT_DEVICE, PR_DEDUPE, PR_PEEL = 0x1, 0x2, 0x20000
 PR_P_DEVICE, PR_OUT_DEVICE, PR_IFP2_LITERAL = 0x1, 0x2, 0x4
-PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE, PR_JACOBI, PR_VERIFY = 0x8, 0x10, 0x20, 0x40, 0x80
+PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE, PR_JACOBI, PR_VERIFY, PR_FORCE_LIST = 0x8, 0x10, 0x20, 0x40, 0x80, 0x100
 
 # every symbol the public headers declare
 EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_info", "pr_solve_ifp1",
@@ -488,8 +488,10 @@ def _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, p
         flags |= PR_FORCE_PUSH
     elif mode == "pull":
         flags |= PR_FORCE_PULL
+    elif mode == "list":
+        flags |= PR_FORCE_LIST
     elif mode is not None:
-        raise ValueError("mode must be None, 'push' or 'pull'")
+        raise ValueError("mode must be None, 'push', 'pull' or 'list'")
     if profile:
         flags |= PR_PROFILE
     if jacobi:

@@ -71,7 +71,8 @@ double elapsed_s(hipEvent_t a, hipEvent_t b);
 
 struct EventPair {
     hipEvent_t a = nullptr, b = nullptr;
-    EventPair() {
+    explicit EventPair(bool create = true) {
+        if (!create) return;
         (void)hipEventCreate(&a);
         (void)hipEventCreate(&b);
     }
@@ -93,12 +94,14 @@ struct Workspace {
     char *base = nullptr;
     size_t bytes = 0;
     bool cached = false;
+    bool borrowed = false;  // caller-provided device memory and host control block: not freed
     Ctl *hctl = nullptr;  // pinned
     hipStream_t stream = nullptr;  // the solve's stream
     ~Workspace() {
         // an error path may leave kernels that use the workspace in flight: wait for them
         // before another solve can take it (a no-op after a solve that finished)
         if (base) (void)hipStreamSynchronize(stream);
+        if (borrowed) return;
         if (hctl && !cached) (void)hipHostFree(hctl);
         if (!base) return;
         if (cached) {
@@ -185,6 +188,14 @@ struct WarmArgs {
     double *h;
 };
 
+// Device memory a caller provides for a solve's workspace (no allocation in the solve:
+// no workspace, pinned control block or timing events are created).
+struct ExtWorkspace {
+    void *base;
+    size_t bytes;
+    Ctl *hctl;  // host copy of the control block (any host memory)
+};
+
 // ---- graph upload and plans (pr_upload.hip)
 pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_t *col, uint32_t flags,
                       const int32_t *seg_of, pr_graph **out);
@@ -197,7 +208,10 @@ pr_status replan(Graph &G, int32_t tile_k, hipStream_t s);
 // ---- solves (pr_solve.hip)
 template <typename T>
 pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
-                      pr_stats *st, const WarmArgs *warm = nullptr);
+                      pr_stats *st, const WarmArgs *warm = nullptr, const ExtWorkspace *ext = nullptr);
+// Workspace bytes solve_ifp_t takes for these options (the size an ExtWorkspace must have).
+template <typename T>
+size_t solve_ifp_bytes(const Graph &G, bool ifp2, const double *p, const pr_opts &o, bool warm);
 template <typename WT>
 pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, double *pi, pr_stats *st);
 template <typename T, int B>

@@ -38,10 +38,10 @@ pr_status check_opts(const pr_opts &o, bool power) {
     if (o.max_sweeps < 0) return fail(PR_EINVAL, "max_sweeps < 0");
     const uint32_t known =
         PR_P_DEVICE | PR_OUT_DEVICE | PR_IFP2_LITERAL | PR_FORCE_PUSH | PR_FORCE_PULL | PR_PROFILE | PR_JACOBI |
-        PR_VERIFY;
+        PR_VERIFY | PR_FORCE_LIST;
     if (o.flags & ~known) return fail(PR_EINVAL, "unknown option flag");
-    if ((o.flags & PR_FORCE_PUSH) && (o.flags & PR_FORCE_PULL))
-        return fail(PR_EINVAL, "PR_FORCE_PUSH and PR_FORCE_PULL together");
+    const uint32_t modes = o.flags & (PR_FORCE_PUSH | PR_FORCE_PULL | PR_FORCE_LIST);
+    if (modes & (modes - 1)) return fail(PR_EINVAL, "at most one of PR_FORCE_PUSH, PR_FORCE_PULL, PR_FORCE_LIST");
     if (power || o.stop == PR_STOP_L1) {
         if (!(o.l1_tol > 0.0) || !isfinite(o.l1_tol)) return fail(PR_EINVAL, "l1_tol must be > 0 and finite");
     }
@@ -325,7 +325,7 @@ pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_rep
     opts_or_default(o, &op);
     pr_status ps = check_opts(op, false);
     if (ps != PR_OK) return ps;
-    if (op.flags & (PR_FORCE_PUSH | PR_FORCE_PULL | PR_P_DEVICE))
+    if (op.flags & (PR_FORCE_PUSH | PR_FORCE_PULL | PR_FORCE_LIST | PR_P_DEVICE))
         return fail(PR_EINVAL, "tuning times the automatic schedule of global solves");
     ps = enter(g);
     if (ps != PR_OK) return ps;
@@ -382,7 +382,7 @@ pr_status pr_set_tune(pr_graph_set *s, const double *c, const pr_opts *o, int32_
     if (c) op.c = 0.5;  // per-graph factors are checked by the solve
     pr_status ps = check_opts(op, false);
     if (ps != PR_OK) return ps;
-    if (op.flags & (PR_FORCE_PUSH | PR_FORCE_PULL | PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE))
+    if (op.flags & (PR_FORCE_PUSH | PR_FORCE_PULL | PR_FORCE_LIST | PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE))
         return fail(PR_EINVAL, "tuning times the automatic schedule of set solves");
     ps = enter(s->u);
     if (ps != PR_OK) return ps;
@@ -405,7 +405,7 @@ pr_status pr_set_solve_ifp2(const pr_graph_set *s, const double *c, const pr_opt
     if (c) op.c = 0.5;  // per-graph factors are checked by the solve
     pr_status ps = check_opts(op, false);
     if (ps != PR_OK) return ps;
-    if (op.flags & (PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE | PR_VERIFY))
+    if (op.flags & (PR_P_DEVICE | PR_IFP2_LITERAL | PR_PROFILE | PR_VERIFY | PR_FORCE_LIST))
         return fail(PR_EINVAL, "option flag not supported for graph sets");
     ps = enter(s->u);
     if (ps != PR_OK) return ps;
@@ -458,7 +458,7 @@ pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_
         // groups of kBatch sources share one batched solve; a lone source runs alone, as
         // does every source on a peeled graph (the batched sweeps cover every non-dangling row)
         // (and with PR_VERIFY, whose check is part of the single-vector solve)
-        const int32_t width = (G.nP > 0 || (op.flags & PR_VERIFY)) ? 1 : kBatch;
+        const int32_t width = (G.nP > 0 || (op.flags & (PR_VERIFY | PR_FORCE_LIST))) ? 1 : kBatch;
         const int32_t nbatch = (k + width - 1) / width;
         const hipStream_t s = op.stream ? (hipStream_t)op.stream : G.stream;
         // more than one batch: every row is solved into device staging first and copied

@@ -26,6 +26,9 @@ constexpr double kScatterShare = 0.1;
 // columns are below this share of the edges its gather would read (the gather
 // serves all columns at once; the scatter's atomics of one edge hit adjacent columns).
 constexpr double kScatterShareBatch = 0.25;
+// A single-vector sweep scatters from a compacted frontier list (returning atomics, no
+// pass over every vertex) while its active edges are below this share of a gather's.
+constexpr double kListShare = 0.02;
 
 // workgroups of each group's reserve in an ordered sweep; group g's five partial
 // arrays (nb[g] entries each) start at part + 5 * stride * g
@@ -77,6 +80,28 @@ struct alignas(128) Ctl {
     double fin_abs;       // sum |x| (equals fin_sum unless residuals went negative)
     // a-posteriori check (PR_VERIFY): ||P'' pi - pi||_1, its rounding bound, sum(pi)
     double ver_r, ver_err, ver_sum;
+    // list sweeps (compacted frontier): entries of the two frontier lists and of the
+    // lane / wave work lists of the scatter, indexed by sweep parity
+    uint32_t fcnt[2], lcnt[2], wcnt[2], pad2[2];
+    unsigned long long fedges[2];   // valid out-edges of the vertices in each frontier list
+    unsigned long long last_edges;  // valid out-edges of the last decided sweep's active vertices
+    double sn_last;                 // residual left on the non-dangling vertices after that sweep
+};
+
+// A scatter item of a list sweep: a vertex with at most kLaneEdges valid out-edges is
+// one lane's work; a longer row is cut into chunks of kChunkEdges edges, one wave's each.
+constexpr int kLaneEdges = 16;
+constexpr int kChunkEdges = 1024;
+// Device buffers of list sweeps (capacities: nN frontier entries per list, nN lane
+// items, nN + valid edges / kChunkEdges wave items).
+template <typename T>
+struct ListBufs {
+    int32_t *f[2];         // frontier lists by sweep parity (vertex ids, unordered)
+    int32_t *lane_v;       // lane items: vertex
+    T *lane_w;             //   push weight c v / deg
+    int32_t *wave_v;       // wave items: vertex
+    int32_t *wave_c;       //   chunk index within the row
+    T *wave_w;             //   push weight
 };
 
 // Control block of a batch of B <= kMaxBatch vectors (see Ctl).
@@ -303,8 +328,27 @@ hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *
 hipError_t launch_verify(Ctl *vctl, const InitArgs &a, const double *out, double *x, double *acc, double *y,
                          const int32_t *deg, const MPPlan &pull_all, const uint32_t *in_ptr, double c, double *part,
                          double *depth, hipStream_t s);
+// zero-fill kernels (used instead of memset nodes on the solve stream)
+hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t s);
+hipError_t launch_zero_f64(double *p, int64_t count, hipStream_t s);
 // kernel launches of the calling thread so far (counted by the launchers)
 extern thread_local int64_t t_kernel_launches;
+// list sweeps (compacted frontier; IFP1 / IFP2 with non-negative residuals)
+// frontier list of sweep t (slot t & 1) from every non-dangling h_i > xi, and the
+// residual on the non-dangling vertices into ctl->sn_last; the list counters must be zero
+template <typename T>
+hipError_t launch_compact(Ctl *ctl, int slot, int32_t nN, const T *h, double xi, int32_t *f, const int32_t *deg,
+                          const uint32_t *rp_nn, int ifp2, double *part, hipStream_t s);
+// reserve + decision of list sweep t over the frontier list of slot t & 1
+template <typename T>
+hipError_t launch_reserve_list(int t, Ctl *ctl, Trace *tr, const ListBufs<T> &lb, T *h, double *pibar,
+                               const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2,
+                               int stop_l1, double tol, double *part, hipStream_t s);
+// scatter of list sweep t; targets whose residual rises above xi form the frontier of t + 1
+template <typename T>
+hipError_t launch_push_list(int t, Ctl *ctl, const ListBufs<T> &lb, T *h, const int32_t *deg, const uint32_t *rp_nn,
+                            const int32_t *col_nn, const uint32_t *rp_nd, const int32_t *col_nd, double xi, int ifp2,
+                            hipStream_t s);
 hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStream_t s);
 hipError_t launch_unit_vector(double *out, int64_t n, int64_t src, hipStream_t s);
 

@@ -539,6 +539,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr
     const double sx = ctl->sx + c * a_sx;
     const double bound = l1_bound_of(k, sn, sx, ctl->signed_res);
     ctl->sx = sx;
+    ctl->sn_last = sn;
+    ctl->last_edges = a_e;
     ctl->last_bound = bound;
     if (a_c == 0) {
         ctl->stop_after = t - 1;  // nothing moved in this sweep
@@ -577,6 +579,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
     if (a_c == 0) {
         // nothing above the threshold: the state is unchanged, stop before this sweep's scatter
         ctl->stop_after = t - 1;
+        ctl->sn_last = a_in;
+        ctl->last_edges = 0;
         ctl->last_bound = l1_bound_of(k, a_in, ctl->sx, ctl->signed_res);
         if (t < kMaxTrace) {
             tr->cnt[t] = 0;
@@ -590,6 +594,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
     const double sx = ctl->sx + c * a_sx;
     const double bound = l1_bound_of(k, sn, sx, ctl->signed_res);
     ctl->sx = sx;
+    ctl->sn_last = sn;
+    ctl->last_edges = a_e;
     ctl->sweeps = t + 1;
     ctl->tot_pushes += a_c;
     ctl->tot_edges += a_e;
@@ -605,6 +611,267 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
         tr->sn[t] = sn;
         tr->bound[t] = bound;
     }
+}
+
+// ------------------------------------------------------------------------
+// list sweeps: the frontier {i in N : h_i > xi} of Algorithms 2 and 3 kept as a
+// compacted list of vertex ids, so a sparse sweep costs O(frontier + its edges)
+// instead of a pass over every non-dangling vertex.  A list is written with one
+// counter atomic per wave: the wave's ballot of set lanes gives the count, and each
+// lane's rank among them (mbcnt over the ballot) its offset.  The scatter uses
+// returning atomics: the one add that lifts h_j from <= xi to > xi appends j to the
+// next sweep's list (the residual only grows during a scatter, so exactly one add
+// crosses), which keeps every vertex above the threshold listed once.
+// ------------------------------------------------------------------------
+
+// Slot of each lane with pred set in a list counted by *cnt (one atomic per wave); the
+// return value is meaningful only where pred is set.  Call with the whole wave active.
+__device__ __forceinline__ uint32_t wave_slot(bool pred, uint32_t *cnt) {
+    const unsigned long long m = __ballot(pred);
+    if (m == 0ull) return 0u;
+    const uint32_t rank =
+        __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+    const int leader = __ffsll((long long)m) - 1;
+    uint32_t base = 0u;
+    if (lane_id() == leader) base = atomicAdd(cnt, (uint32_t)__popcll(m));
+    base = __shfl(base, leader, W);
+    return base + rank;
+}
+
+// Frontier list from the residuals (the start of a run of list sweeps): every
+// non-dangling i with h_i > xi, into f (slot `slot` of the counters, zero on entry).
+// Also the residual on the non-dangling vertices (per workgroup partials), from which
+// list sweeps carry it forward.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_compact(Ctl *ctl, int slot, int32_t nN, const T *h, T xi, int32_t *f,
+                                                    const int32_t *deg, const uint32_t *rp_nn, int ifp2,
+                                                    double *part) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double sn = 0.0;
+    unsigned long long ve = 0;
+    // the trip count is uniform over a wave (its lanes share `base`)
+    for (int64_t base = blockIdx.x * (int64_t)kBlock + (threadIdx.x & ~(W - 1)); base < nN; base += stride) {
+        const int64_t i = base + lane_id();
+        const T hv = i < nN ? h[i] : (T)0;
+        sn += (double)hv;
+        const bool act = hv > xi;
+        const uint32_t q = wave_slot(act, &ctl->fcnt[slot]);
+        if (act) {
+            f[q] = (int32_t)i;
+            ve += ifp2 ? (unsigned long long)(rp_nn[i + 1] - rp_nn[i]) : (unsigned long long)deg[i];
+        }
+    }
+    ve = wave_sum(ve);
+    if (lane_id() == 0 && ve) atomic_add_u64(&ctl->fedges[slot], ve);
+    __shared__ double sd[kBlock / W];
+    sn = block_sum(sn, sd);
+    if (threadIdx.x == 0) part[blockIdx.x] = sn;
+}
+
+__global__ __launch_bounds__(kBlock) void k_list_start(Ctl *ctl, int nb, const double *part) {
+    __shared__ double sd[kBlock / W];
+    const double sn = reduce_partials(part, nb, sd);
+    if (threadIdx.x == 0) ctl->sn_last = sn;
+}
+
+// Reserve step of list sweep t over the frontier list of slot t & 1: each listed
+// vertex moves its residual v into pibar_i and becomes scatter work with weight
+// c v / deg(i) -- one lane item if it has at most kLaneEdges valid out-edges, else
+// one wave item per chunk of kChunkEdges.  Partial sums per workgroup: mass taken,
+// mass sent to non-dangling vertices, growth of the total mass, active vertices and
+// their valid edges.  Also clears the counters the scatter of this sweep fills.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_reserve_list(int t, Ctl *ctl, ListBufs<T> lb, T *h, double *pibar,
+                                                         const int32_t *deg, const uint32_t *rp_nn, double c, T xi,
+                                                         int ifp2, double *part) {
+    if (t > ctl->stop_after) return;
+    const int b = t & 1;
+    const uint32_t nf = ctl->fcnt[b];
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ctl->fcnt[b ^ 1] = 0u;  // next frontier (filled by this sweep's scatter)
+        ctl->fedges[b ^ 1] = 0ull;
+        ctl->lcnt[b ^ 1] = 0u;  // work lists of the next sweep
+        ctl->wcnt[b ^ 1] = 0u;
+    }
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    double taken = 0.0, pred = 0.0, sxinc = 0.0;
+    unsigned long long cnt = 0, edges = 0;
+    for (int64_t base = blockIdx.x * (int64_t)kBlock + (threadIdx.x & ~(W - 1)); base < (int64_t)nf; base += stride) {
+        const int64_t q = base + lane_id();
+        bool lane_item = false;
+        int32_t i = 0;
+        T wt = (T)0;
+        uint32_t dv = 0;
+        if (q < (int64_t)nf) {
+            i = lb.f[b][q];
+            const T hv = h[i];
+            if (hv > xi) {
+                const int32_t dg = deg[i];
+                const uint32_t dnn = rp_nn[i + 1] - rp_nn[i];
+                const double v = (double)hv;
+                pibar[i] += v;
+                h[i] = (T)0;
+                wt = (T)(c * v / (double)dg);
+                const double fN = (double)dnn / (double)dg;
+                taken += v;
+                pred += v * fN;
+                sxinc += ifp2 ? v * fN : v;
+                dv = ifp2 ? dnn : (uint32_t)dg;
+                cnt += 1;
+                edges += dv;
+                lane_item = dv > 0 && dv <= (uint32_t)kLaneEdges;
+            }
+        }
+        const uint32_t ql = wave_slot(lane_item, &ctl->lcnt[b]);
+        if (lane_item) {
+            lb.lane_v[ql] = i;
+            lb.lane_w[ql] = wt;
+        }
+        if (dv > (uint32_t)kLaneEdges) {  // long rows are rare: one atomic per row
+            const uint32_t nch = (dv + kChunkEdges - 1) / kChunkEdges;
+            const uint32_t q0 = atomicAdd(&ctl->wcnt[b], nch);
+            for (uint32_t k = 0; k < nch; ++k) {
+                lb.wave_v[q0 + k] = i;
+                lb.wave_c[q0 + k] = (int32_t)k;
+                lb.wave_w[q0 + k] = wt;
+            }
+        }
+    }
+    __shared__ double sd[5 * (kBlock / W)];
+    double v[5] = {taken, pred, sxinc, (double)cnt, (double)edges};
+    block_sum_n(v, sd);
+    if (threadIdx.x == 0) {
+        const int nb = gridDim.x, bb = blockIdx.x;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) part[q * nb + bb] = v[q];
+    }
+}
+
+// Management step of a list sweep: the residual left on N follows from the previous
+// decision's sum (residuals are non-negative and only listed vertices were taken);
+// otherwise as the synchronous sweep's decision.  List sweeps always scatter.
+__global__ __launch_bounds__(kBlock) void k_decide_list(int t, Ctl *ctl, Trace *tr, int nb, const double *part,
+                                                        double c, int stop_l1, double tol) {
+    if (t > ctl->stop_after) return;
+    __shared__ double sd[5 * (kBlock / W)];
+    double v[5];
+    reduce_partials_n(part, nb, v, sd);
+    if (threadIdx.x != 0) return;
+    const double taken = v[0], a_pr = v[1], a_sx = v[2];
+    const unsigned long long a_c = (unsigned long long)v[3], a_e = (unsigned long long)v[4];
+    const double k = 2.0 * c / (1.0 - c);
+    if (a_c == 0) {
+        ctl->stop_after = t - 1;
+        ctl->last_bound = l1_bound_of(k, ctl->sn_last, ctl->sx, 0);
+        ctl->last_edges = 0;
+        if (t < kMaxTrace) {
+            tr->cnt[t] = 0;
+            tr->edges[t] = 0;
+            tr->sn[t] = ctl->sn_last;
+            tr->bound[t] = ctl->last_bound;
+        }
+        return;
+    }
+    const double sn = fmax(ctl->sn_last - taken, 0.0) + c * a_pr;
+    const double sx = ctl->sx + c * a_sx;
+    const double bound = l1_bound_of(k, sn, sx, 0);
+    ctl->sx = sx;
+    ctl->sn_last = sn;
+    ctl->last_edges = a_e;
+    ctl->sweeps = t + 1;
+    ctl->tot_pushes += a_c;
+    ctl->tot_edges += a_e;
+    ctl->use_pull = 0;
+    ctl->tot_traversed += a_e;
+    ctl->last_bound = bound;
+    if (stop_l1 && bound <= tol) ctl->stop_after = t;
+    if (t < kMaxTrace) {
+        tr->cnt[t] = a_c;
+        tr->edges[t] = a_e;
+        tr->sn[t] = sn;
+        tr->bound[t] = bound;
+    }
+}
+
+// Scatter step of list sweep t: lane items walk their few edges one lane each, wave
+// items one chunk per wave with the lanes on consecutive edges.  Every add returns the
+// old residual; a non-dangling target crossing xi is appended to the next frontier.
+// Edge k of row i: its non-dangling targets first, then (IFP1) those in the deferred region.
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_push_list(int t, Ctl *ctl, ListBufs<T> lb, T *h, const int32_t *deg,
+                                                      const uint32_t *rp_nn, const int32_t *col_nn,
+                                                      const uint32_t *rp_nd, const int32_t *col_nd, T xi, int ifp2) {
+    if (t > ctl->stop_after) return;
+    const int b = t & 1;
+    const uint32_t nl = ctl->lcnt[b], nw = ctl->wcnt[b];
+    uint32_t *fc = &ctl->fcnt[b ^ 1];
+    int32_t *fo = lb.f[b ^ 1];
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    unsigned long long ve = 0;  // valid out-edges of the vertices this thread appended
+    auto valid_edges = [&](int32_t j) -> unsigned long long {
+        return ifp2 ? (unsigned long long)(rp_nn[j + 1] - rp_nn[j]) : (unsigned long long)deg[j];
+    };
+    for (int64_t base = blockIdx.x * (int64_t)kBlock + (threadIdx.x & ~(W - 1)); base < (int64_t)nl; base += stride) {
+        const int64_t q = base + lane_id();
+        int32_t i = 0;
+        T wt = (T)0;
+        uint32_t r0 = 0, dnn = 0, d0 = 0, dv = 0;
+        if (q < (int64_t)nl) {
+            i = lb.lane_v[q];
+            wt = lb.lane_w[q];
+            r0 = rp_nn[i];
+            dnn = rp_nn[i + 1] - r0;
+            dv = dnn;
+            if (!ifp2) {
+                d0 = rp_nd[i];
+                dv += rp_nd[i + 1] - d0;
+            }
+        }
+        for (uint32_t k = 0; __ballot(k < dv) != 0ull; ++k) {  // uniform: until every lane's row is done
+            bool cross = false;
+            int32_t j = 0;
+            if (k < dv) {
+                j = k < dnn ? col_nn[r0 + k] : col_nd[d0 + (k - dnn)];
+                const T old = atomicAdd(h + j, wt);
+                cross = k < dnn && !(old > xi) && (T)(old + wt) > xi;
+            }
+            const uint32_t qf = wave_slot(cross, fc);
+            if (cross) {
+                fo[qf] = j;
+                ve += valid_edges(j);
+            }
+        }
+    }
+    const int64_t nwaves = stride / W;
+    for (int64_t q = (blockIdx.x * (int64_t)kBlock + threadIdx.x) / W; q < (int64_t)nw; q += nwaves) {
+        const int32_t i = lb.wave_v[q];
+        const T wt = lb.wave_w[q];
+        const uint32_t r0 = rp_nn[i], dnn = rp_nn[i + 1] - r0;
+        uint32_t d0 = 0, dv = dnn;
+        if (!ifp2) {
+            d0 = rp_nd[i];
+            dv += rp_nd[i + 1] - d0;
+        }
+        const uint32_t k0 = (uint32_t)lb.wave_c[q] * kChunkEdges;
+        const uint32_t k1 = min(dv, k0 + (uint32_t)kChunkEdges);
+        for (uint32_t kb = k0; kb < k1; kb += W) {
+            const uint32_t k = kb + lane_id();
+            bool cross = false;
+            int32_t j = 0;
+            if (k < k1) {
+                j = k < dnn ? col_nn[r0 + k] : col_nd[d0 + (k - dnn)];
+                const T old = atomicAdd(h + j, wt);
+                cross = k < dnn && !(old > xi) && (T)(old + wt) > xi;
+            }
+            const uint32_t qf = wave_slot(cross, fc);
+            if (cross) {
+                fo[qf] = j;
+                ve += valid_edges(j);
+            }
+        }
+    }
+    ve = wave_sum(ve);
+    if (lane_id() == 0 && ve) atomic_add_u64(&ctl->fedges[b ^ 1], ve);
 }
 
 // graph-set sweeps: a tile whose rows all belong to graphs that stopped before
@@ -1030,6 +1297,14 @@ __global__ __launch_bounds__(kBlock) void k_verify_decide(Ctl *ctl, int nb, cons
     ctl->ver_sum = v[2];
 }
 
+// fill kernels (clearing counters and sums without a memset node in the stream)
+__global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t v) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) p[i] = v;
+}
+__global__ void k_fill_f64(double *p, int64_t count, double v) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) p[i] = v;
+}
+
 // p validation: sum_bad[0] += p_i, sum_bad[1] += 1 for every negative or non-finite entry
 __global__ __launch_bounds__(kBlock) void k_validate_p(const double *p, int64_t n, double *sum_bad) {
     double s = 0.0, bad = 0.0;
@@ -1274,6 +1549,48 @@ hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, 
     return hipGetLastError();
 }
 
+template <typename T>
+hipError_t launch_compact(Ctl *ctl, int slot, int32_t nN, const T *h, double xi, int32_t *f, const int32_t *deg,
+                          const uint32_t *rp_nn, int ifp2, double *part, hipStream_t s) {
+    if (nN <= 0) return hipSuccess;
+    const int nb = grid_for(nN, 4, kRedBlocks);
+    PRK_GGL(k_compact<T>, dim3(nb), dim3(kBlock), 0, s, ctl, slot, nN, h, (T)xi, f, deg, rp_nn, ifp2, part);
+    PRK_GGL(k_list_start, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
+    return hipGetLastError();
+}
+
+constexpr int kListBlocks = 512;  // workgroups of the list reserve (its partials feed the decision)
+
+template <typename T>
+hipError_t launch_reserve_list(int t, Ctl *ctl, Trace *tr, const ListBufs<T> &lb, T *h, double *pibar,
+                               const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2,
+                               int stop_l1, double tol, double *part, hipStream_t s) {
+    static_assert(kListBlocks <= kRedBlocks, "partials");
+    PRK_GGL(k_reserve_list<T>, dim3(kListBlocks), dim3(kBlock), 0, s, t, ctl, lb, h, pibar, deg, rp_nn, c, (T)xi,
+            ifp2, part);
+    PRK_GGL(k_decide_list, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, kListBlocks, (const double *)part, c, stop_l1,
+            tol);
+    return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_push_list(int t, Ctl *ctl, const ListBufs<T> &lb, T *h, const int32_t *deg, const uint32_t *rp_nn,
+                            const int32_t *col_nn, const uint32_t *rp_nd, const int32_t *col_nd, double xi, int ifp2,
+                            hipStream_t s) {
+    static const int grid = resident_grid(k_push_list<T>);
+    PRK_LAUNCH(k_push_list<T>, grid, t, ctl, lb, h, deg, rp_nn, col_nn, rp_nd, col_nd, (T)xi, ifp2);
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    PRK_LAUNCH(k_fill_u32, grid_for(count, 4, 1024), p, count, 0u);
+}
+
+hipError_t launch_zero_f64(double *p, int64_t count, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    PRK_LAUNCH(k_fill_f64, grid_for(count, 4, 1024), p, count, 0.0);
+}
+
 hipError_t launch_verify(Ctl *vctl, const InitArgs &a, const double *out, double *x, double *acc, double *y,
                          const int32_t *deg, const MPPlan &pull_all, const uint32_t *in_ptr, double c, double *part,
                          double *depth, hipStream_t s) {
@@ -1317,6 +1634,22 @@ hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStr
 }
 
 // explicit instantiations
+template hipError_t launch_compact<float>(Ctl *, int, int32_t, const float *, double, int32_t *, const int32_t *,
+                                          const uint32_t *, int, double *, hipStream_t);
+template hipError_t launch_compact<double>(Ctl *, int, int32_t, const double *, double, int32_t *, const int32_t *,
+                                           const uint32_t *, int, double *, hipStream_t);
+template hipError_t launch_reserve_list<float>(int, Ctl *, Trace *, const ListBufs<float> &, float *, double *,
+                                               const int32_t *, const uint32_t *, double, double, int, int, double,
+                                               double *, hipStream_t);
+template hipError_t launch_reserve_list<double>(int, Ctl *, Trace *, const ListBufs<double> &, double *, double *,
+                                                const int32_t *, const uint32_t *, double, double, int, int, double,
+                                                double *, hipStream_t);
+template hipError_t launch_push_list<float>(int, Ctl *, const ListBufs<float> &, float *, const int32_t *,
+                                            const uint32_t *, const int32_t *, const uint32_t *, const int32_t *,
+                                            double, int, hipStream_t);
+template hipError_t launch_push_list<double>(int, Ctl *, const ListBufs<double> &, double *, const int32_t *,
+                                             const uint32_t *, const int32_t *, const uint32_t *, const int32_t *,
+                                             double, int, hipStream_t);
 template hipError_t launch_init_ifp<float>(const InitArgs &, float *, double *, hipStream_t);
 template hipError_t launch_init_ifp<double>(const InitArgs &, double *, double *, hipStream_t);
 template hipError_t launch_reserve<float>(int, Ctl *, Trace *, int32_t, float *, float *, double *, const int32_t *,
@@ -1337,6 +1670,7 @@ template hipError_t launch_decide_gs<float>(int, Ctl *, Trace *, int32_t, const 
 template hipError_t launch_decide_gs<double>(int, Ctl *, Trace *, int32_t, const double *, int, const GroupBlocks &,
                                              const double *, double *, double, int, double, unsigned long long,
                                              unsigned long long, hipStream_t);
+
 template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t,
                                        TileSkip, KernelEvents);
 template hipError_t launch_push<double>(int, const Ctl *, const MPPlan &, const double *, double *, int,

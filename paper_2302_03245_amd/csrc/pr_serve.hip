@@ -109,8 +109,12 @@ struct Engine {
     // workspace of a single-vector solve (cached on the graph by the solve itself)
     static size_t footprint_single(const Graph &G, bool fp32) {
         const size_t sT = fp32 ? 4 : 8;
+        // frontier lists and scatter work lists of list sweeps
+        const size_t wave_cap = (size_t)G.nN + ((size_t)G.mNN + (size_t)G.mND) / kChunkEdges + 1;
+        const size_t lists = 3 * align256((size_t)G.nN * 4) + align256((size_t)G.nN * sT) +
+                             2 * align256(wave_cap * 4) + align256(wave_cap * sT);
         return align256((size_t)G.n * sT) + align256((size_t)G.nN * sT) + 3 * align256((size_t)G.nN * 8) +
-               align256((size_t)std::max<int32_t>(G.nD, 1) * 8) + 64 * 1024 + 5 * kRedBlocks * 8;
+               align256((size_t)std::max<int32_t>(G.nD, 1) * 8) + 64 * 1024 + 5 * kRedBlocks * 8 + lists;
     }
 
     template <typename T>

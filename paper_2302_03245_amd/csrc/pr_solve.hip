@@ -47,7 +47,7 @@ pr_status prepare_p(const Graph &G, const double *p, const pr_opts &o, double *p
     if (!p) return PR_OK;
     double sum = 0.0;
     if (o.flags & PR_P_DEVICE) {
-        HIPCHK(hipMemsetAsync(sumbad, 0, 2 * sizeof(double), s));
+        HIPCHK(launch_zero_f64(sumbad, 2, s));
         HIPCHK(launch_validate_p(p, G.n, sumbad, s));
         double h[2];
         HIPCHK(hipMemcpyAsync(h, sumbad, sizeof(h), hipMemcpyDeviceToHost, s));
@@ -75,7 +75,10 @@ int next_batch(int prev_batch, double bound_prev, double bound_now, int swept, d
     if (l1 && bound_prev > 0 && bound_now > 0 && bound_now < bound_prev && swept > 0) {
         double rate = pow(bound_now / bound_prev, 1.0 / swept);
         if (rate > 0 && rate < 1) {
-            double need = log(tol / bound_now) / log(rate);
+            // past the target (the threshold rule's tail, where a few residuals stay
+            // above xi): grow the batch again, but by at most 16 sweeps
+            if (bound_now <= tol) return std::min(16, std::max(2, prev_batch * 2));
+            const double need = log(tol / bound_now) / log(rate);
             int k = (int)ceil(need) + 1;
             return std::min(64, std::max(2, k));
         }
@@ -111,9 +114,30 @@ static double verified_bound(const Ctl &v, double depth, double c) {
     return r / (1.0 - c) + fabs(v.ver_sum - 1.0) + depth * u * v.ver_sum;
 }
 
+// Workspace layout of solve_ifp_t (the order of the carve below).
+template <typename T>
+size_t solve_ifp_bytes(const Graph &G, bool ifp2, const double *p, const pr_opts &o, bool warm) {
+    (void)ifp2;
+    const int64_t n = G.n;
+    const int32_t nN = G.nN, nD = G.nD;
+    const bool out_dev = o.flags & PR_OUT_DEVICE;
+    const bool verify = o.flags & PR_VERIFY;
+    const bool list_ok = !warm && !(o.flags & (PR_FORCE_PUSH | PR_FORCE_PULL)) && nN > 0;
+    const int64_t wave_cap = (int64_t)nN + ((int64_t)G.mNN + G.mND) / kChunkEdges + 1;
+    const size_t list_bytes = list_ok ? 3 * carve_size<int32_t>(nN) + carve_size<T>(nN) +
+                                            2 * carve_size<int32_t>(wave_cap) + carve_size<T>(wave_cap)
+                                      : 0;
+    return list_bytes + (verify ? 2 * carve_size<double>(n) + carve_size<Ctl>(1) : 0) +
+           carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
+           carve_size<double>(nN + G.nP) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
+           carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
+           carve_size<double>(2) + carve_size<double>(kPartDoubles) +
+           (warm ? 2 * carve_size<double>(nN) + 3 * carve_size<double>(nD) : 0);
+}
+
 template <typename T>
 pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
-                      pr_stats *st, const WarmArgs *warm) {
+                      pr_stats *st, const WarmArgs *warm, const ExtWorkspace *ext) {
     hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
     const int64_t n = G.n;
     const int32_t nN = G.nN, nD = G.nD;
@@ -132,16 +156,24 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
     const int64_t launches0 = t_kernel_launches;
     const bool verify = o.flags & PR_VERIFY;
-
-    size_t bytes = (verify ? 2 * carve_size<double>(n) + carve_size<Ctl>(1) : 0) +
-                   carve_size<T>(n) + carve_size<T>(nN) + carve_size<double>(nN) + carve_size<double>(nD) +
-                   carve_size<double>(nN + G.nP) + carve_size<double>(out_dev ? 0 : n) + carve_size<Ctl>(1) +
-                   carve_size<Trace>(1) + carve_size<double>(p && !(o.flags & PR_P_DEVICE) ? n : 0) +
-                   carve_size<double>(2) + carve_size<double>(kPartDoubles) +
-                   (warm ? 2 * carve_size<double>(nN) + 3 * carve_size<double>(nD) : 0);
+    // list sweeps (compacted frontier) need non-negative residuals: not for warm starts
+    const bool force_list = o.flags & PR_FORCE_LIST;
+    const bool list_ok = !warm && !(o.flags & (PR_FORCE_PUSH | PR_FORCE_PULL)) && nN > 0;
+    const int64_t wave_cap = (int64_t)nN + ((int64_t)G.mNN + G.mND) / kChunkEdges + 1;
+    const size_t bytes = solve_ifp_bytes<T>(G, ifp2, p, o, warm != nullptr);
     Workspace ws;
-    pr_status ps = acquire_ws(const_cast<Graph &>(G), bytes, ws, s);
-    if (ps != PR_OK) return ps;
+    pr_status ps = PR_OK;
+    if (ext) {
+        if (bytes > ext->bytes) return fail(PR_EINVAL, "workspace larger than the memory provided");
+        ws.base = (char *)ext->base;
+        ws.bytes = bytes;
+        ws.hctl = ext->hctl;
+        ws.stream = s;
+        ws.borrowed = true;
+    } else {
+        ps = acquire_ws(const_cast<Graph &>(G), bytes, ws, s);
+        if (ps != PR_OK) return ps;
+    }
     Carve cv{ws.base};
     T *h = cv.take<T>(n);
     T *w = cv.take<T>(nN);
@@ -163,6 +195,16 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     double *vx = verify ? cv.take<double>(n) : nullptr;
     double *vacc = verify ? cv.take<double>(n) : nullptr;
     Ctl *vctl = verify ? cv.take<Ctl>(1) : nullptr;
+    ListBufs<T> lb{};
+    if (list_ok) {
+        lb.f[0] = cv.take<int32_t>(nN);
+        lb.f[1] = cv.take<int32_t>(nN);
+        lb.lane_v = cv.take<int32_t>(nN);
+        lb.lane_w = cv.take<T>(nN);
+        lb.wave_v = cv.take<int32_t>(wave_cap);
+        lb.wave_c = cv.take<int32_t>(wave_cap);
+        lb.wave_w = cv.take<T>(wave_cap);
+    }
 
     InitArgs a{};
     a.n = n;
@@ -173,10 +215,10 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     ps = prepare_p(G, p, o, pdev, sumbad, &a.p, &a.pscale, s);
     if (ps != PR_OK) return ps;
 
-    EventPair ev_solve;
+    EventPair ev_solve(ext == nullptr);  // no events in a solve that allocates nothing
     SweepTimer timer;
     timer.on = o.flags & PR_PROFILE;
-    HIPCHK(hipEventRecord(ev_solve.a, s));
+    if (ev_solve.a) HIPCHK(hipEventRecord(ev_solve.a, s));
     Ctl hc;
     memset(&hc, 0, sizeof(hc));
     hc.stop_after = INT_MAX;
@@ -210,14 +252,37 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     const double sT = (double)sizeof(T);
     int t = 0;
     bool stopped = false;
+    // list sweeps: from the start when forced or for a single-source solve (its frontier
+    // is one vertex); otherwise entered when a synchronous sweep's frontier has fewer valid
+    // edges than kListShare of a gather's, and left when it (or the next frontier's
+    // expected edges) grows past that
+    bool list_on = list_ok && (force_list || (source >= 0 && !ordered));
+    bool list_ready = false;
     if (nN > 0) {
         // a solve that may turn to ordered sweeps checks its frontier after two sweeps
         int batch = (ordered_ok && !ordered) ? 2 : (l1 ? 8 : 16);
         double bound_prev = -1.0;
         int t_prev = 0;
         while (t < max_sweeps) {
-            int nb = std::min(batch, max_sweeps - t);
+            if (list_on && !list_ready) {
+                // the list of sweep t from the residuals; counters of both parities cleared
+                HIPCHK(launch_zero_u32(&ctl->fcnt[0], 8, s));
+                HIPCHK(launch_zero_u32((uint32_t *)(void *)&ctl->fedges[0], 4, s));
+                HIPCHK(launch_compact<T>(ctl, t & 1, nN, h, xi, lb.f[t & 1], G.deg, G.rp_nn, ifp2 ? 1 : 0, part, s));
+                list_ready = true;
+            }
+            // while sparse, the host looks at the frontier after every sweep (it can grow a
+            // hundredfold in one: a hub enters it)
+            const int bmax = (list_on && !force_list) ? 1 : batch;
+            int nb = std::min(bmax, max_sweeps - t);
             for (int k = 0; k < nb; ++k, ++t) {
+                if (list_on) {
+                    HIPCHK(launch_reserve_list<T>(t, ctl, tr, lb, h, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0,
+                                                  l1 ? 1 : 0, tol, part, s));
+                    HIPCHK(launch_push_list<T>(t, ctl, lb, h, G.deg, G.rp_nn, G.col_nn, G.rp_nd, G.col_nd, xi,
+                                               ifp2 ? 1 : 0, s));
+                    continue;
+                }
                 const MPPlan &pullp = pull_plan(t);
                 // a gather reads every live in-edge; scatter while the active edges are a
                 // smaller share of them than kScatterShare
@@ -268,8 +333,27 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                 stopped = true;
                 break;
             }
-            ordered = ordered_ok && ws.hctl->use_pull;  // dense frontier: ordered sweeps from here
-            batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, tol, l1);
+            if (list_ok && !force_list) {
+                const double list_thr = kListShare * (double)pull_plan(t).edges();
+                if (list_on) {
+                    // the valid out-edges of the frontier list of sweep t
+                    const double next_edges = (double)ws.hctl->fedges[t & 1];
+                    if ((double)ws.hctl->last_edges >= list_thr || next_edges >= list_thr) {
+                        list_on = false;  // dense from the next sweep: its reserve reads every residual
+                        list_ready = false;
+                    }
+                } else if (!ordered && (double)ws.hctl->last_edges < list_thr) {
+                    list_on = true;  // the list is built from the residuals before the next sweep
+                }
+            }
+            ordered = ordered_ok && ws.hctl->use_pull && !list_on;  // dense frontier: ordered sweeps from here
+            // under the threshold rule the frontier empties some sweeps after the mean
+            // residual on N reaches xi: the bound at that mean is the target of the sizing
+            const double target = l1 ? tol : 2.0 * c / (1.0 - c) * xi * (double)nN / std::max(ws.hctl->sx, 1.0);
+            batch = next_batch(batch, bound_prev, ws.hctl->last_bound, t - t_prev, target, true);
+            // until the frontier is dense enough for ordered sweeps, look at it every two
+            // sweeps (a long run of synchronous sweeps would forgo their faster decay)
+            if (ordered_ok && !ordered) batch = std::min(batch, 2);
             bound_prev = ws.hctl->last_bound;
             t_prev = t;
         }
@@ -296,7 +380,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     double *dst = out_dev ? pi : outbuf;
     HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, dst, part, s));
     if (warm) HIPCHK(launch_warm_export<T>(n, nN, G.perm, h, pibar, hDn, warm->pibar, warm->h, s));
-    HIPCHK(hipEventRecord(ev_solve.b, s));
+    if (ev_solve.b) HIPCHK(hipEventRecord(ev_solve.b, s));
     Ctl vres;
     double vdepth = 0.0;
     if (verify) HIPCHK(run_verify(G, a, c, dst, vx, vacc, w2, vctl, part, &vres, &vdepth, s));
@@ -323,7 +407,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
             const double den = r.fin_sum - E;
             z.l1_bound = den > 0 ? (1.0 + r.fin_abs / r.fin_sum) * E / den : INFINITY;
         }
-        z.seconds_solve = elapsed_s(ev_solve.a, ev_solve.b);
+        z.seconds_solve = ev_solve.a ? elapsed_s(ev_solve.a, ev_solve.b) : 0.0;
         z.seconds_preprocess = ifp2 ? G.seconds_split : 0.0;
         z.launches = t_kernel_launches - launches0;
         z.l1_verified = l1_verified;
@@ -698,9 +782,11 @@ pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *re
 }
 
 template pr_status solve_ifp_t<float>(const Graph &, bool, const double *, int32_t, const pr_opts &, double *,
-                                      pr_stats *, const WarmArgs *);
+                                      pr_stats *, const WarmArgs *, const ExtWorkspace *);
 template pr_status solve_ifp_t<double>(const Graph &, bool, const double *, int32_t, const pr_opts &, double *,
-                                       pr_stats *, const WarmArgs *);
+                                       pr_stats *, const WarmArgs *, const ExtWorkspace *);
+template size_t solve_ifp_bytes<float>(const Graph &, bool, const double *, const pr_opts &, bool);
+template size_t solve_ifp_bytes<double>(const Graph &, bool, const double *, const pr_opts &, bool);
 template pr_status solve_power_t<float>(const Graph &, const double *, const pr_opts &, double *, pr_stats *);
 template pr_status solve_power_t<double>(const Graph &, const double *, const pr_opts &, double *, pr_stats *);
 template pr_status solve_ppr_batch_t<float, 8>(const Graph &, const int32_t *, int, const pr_opts &, double *,

@@ -67,7 +67,7 @@ CLOSED = _closed_forms()
 def test_closed_forms(pr, name, g, expect, method):
     _say(f"closed form {name} {method}")
     dg = pr.upload(g.row_ptr, g.col)
-    for mode in ([None, "push", "pull"] if method != "power" else [None]):
+    for mode in ([None, "push", "pull", "list"] if method != "power" else [None]):
         if method == "power":
             # 1e-12: below that the order of the FP64 atomic adds into a hub row is visible in ||x' - x||
             pi, st = pr.power(dg, c=C, l1_tol=1e-12)
@@ -114,7 +114,7 @@ def test_random_graphs(pr, name, kw):
     info = dg.info()
     assert info["n"] == g.n and info["m"] == g.m
     for method in ("ifp1", "ifp2"):
-        for mode in (None, "push", "pull"):
+        for mode in (None, "push", "pull", "list"):
             _say(f"{name} {method} mode={mode}")
             pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
             assert st["status"] == 0
@@ -247,7 +247,7 @@ def test_ppr_sources(pr):
     assert l1(out32[0], oracle.power(g, C, p, tol=1e-13)[0]) <= 1e-6
 
 
-@pytest.mark.parametrize("mode", [None, "push", "pull"])
+@pytest.mark.parametrize("mode", [None, "push", "pull", "list"])
 def test_ppr_batches(pr, mode):
     """Twenty-one sources: one batch of sixteen column-interleaved vectors and one of
     five (width 8), each column against the oracle with p = e_s, FP64 and FP32 residuals."""
@@ -266,6 +266,68 @@ def test_ppr_batches(pr, mode):
         assert l1(out[r], ref) <= 1e-9, (r, s)
         assert stats32[r]["l1_bound"] <= 1e-6
         assert l1(out32[r], ref) <= 1e-6, (r, s)
+
+
+def _dyadic_graph(n, seed):
+    """Random digraph whose out-degrees are powers of two (1, 2, 4, 8): with c = 1/2 every
+    push weight c v / deg(i) is exact in FP64, so two sweeps that take the same vertices
+    differ only in the order of their adds (rounding far below any threshold)."""
+    rng = np.random.default_rng(seed)
+    deg = np.where(rng.random(n) < 0.2, 0, 2 ** rng.integers(0, 4, n))
+    src = np.repeat(np.arange(n), deg)
+    dst = rng.integers(0, n, src.size)
+    return prgen.from_edges(n, src, dst)
+
+
+@pytest.mark.parametrize("method", ["ifp1", "ifp2"])
+def test_list_sweeps_take_the_same_vertices(pr, method):
+    """List sweeps (the frontier compacted into a list of ids between sweeps, scattered
+    with returning atomics that append the targets crossing xi) take exactly the
+    vertices the tile scatter takes, sweep by sweep (c = 1/2, power-of-two degrees, FP64:
+    exact weights): same active vertices and edges in every sweep, and the same result up
+    to the order of the adds."""
+    g = _dyadic_graph(30011, seed=4)
+    dg = pr.upload(g.row_ptr, g.col)
+    fn = getattr(pr, method)
+    pa, sa = fn(dg, c=0.5, xi=2.0 ** -20, mode="push", profile=True)
+    ta = pr.last_trace()
+    pb, sb = fn(dg, c=0.5, xi=2.0 ** -20, mode="list", profile=True)
+    tb = pr.last_trace()
+    _say(f"list vs tile scatter: sweeps {sa['sweeps']} / {sb['sweeps']}, pushes {sa['vertex_pushes']} / "
+         f"{sb['vertex_pushes']}")
+    assert sa["sweeps"] == sb["sweeps"]
+    assert sa["vertex_pushes"] == sb["vertex_pushes"]
+    assert sa["edges_processed"] == sb["edges_processed"]
+    assert np.array_equal(ta["active"], tb["active"]) and np.array_equal(ta["edges"], tb["edges"])
+    assert float(np.abs(pa - pb).max()) <= 1e-15
+    ref = oracle.power(g, 0.5, tol=1e-13)[0]
+    assert l1(pb, ref) <= 4 * sb["l1_bound"] + 1e-12
+    dg.free()
+
+
+def test_list_sweeps_sparse_then_dense(pr):
+    """Single-source solves start with list sweeps and turn to dense sweeps as the
+    frontier grows; a personalised p with a few non-zero entries drops into list sweeps
+    once its synchronous sweeps thin out.  Results against the oracle, FP64 and FP32."""
+    g = prgen.random_digraph(70001, 420000, seed=3, dangling_frac=0.15, unref_frac=0.1)
+    dg = pr.upload(g.row_ptr, g.col)
+    deg = np.diff(g.row_ptr)
+    srcs = [int(np.argmax(deg)), int(np.flatnonzero(deg == 1)[0]), 12345]
+    for s in srcs:
+        e = np.zeros(g.n)
+        e[s] = 1.0
+        ref = oracle.power(g, C, e, tol=1e-13)[0]
+        out, sts = pr.ppr(dg, [s], c=C, xi=1e-13)
+        assert sts[0]["status"] == 0 and l1(out[0], ref) <= 1e-9, s
+        out32, sts32 = pr.ppr(dg, [s], c=C, l1_tol=1e-6, residual="fp32")
+        assert l1(out32[0], ref) <= 1e-6, s
+    p = np.zeros(g.n)
+    p[np.random.default_rng(1).choice(g.n, 5, replace=False)] = 1.0
+    ref = oracle.power(g, C, p, tol=1e-13)[0]
+    for method in ("ifp1", "ifp2"):
+        pi, st = getattr(pr, method)(dg, p=p, c=C, xi=1e-13)
+        assert st["status"] == 0 and l1(pi, ref) <= 1e-9, method
+    dg.free()
 
 
 def _pagerank_residual(g, pi, c, p):
@@ -306,7 +368,9 @@ def test_verified_bound(pr, residual):
         assert st["status"] == 0
         assert st["l1_verified"] >= d - ref_err, (name, st["l1_verified"], d)
         assert st["l1_verified"] <= tol
-        assert abs(st["l1_verified"] - own) <= 1e-3 * own + 1e-14, (name, st["l1_verified"], own)
+        # the library adds the rounding of its own check (about (in-degree + reduction
+        # depth) x 2^-53 of the mass per row, / (1 - c)); numpy's figure has none of it
+        assert own <= st["l1_verified"] <= own * (1 + 1e-3) + 1e-12, (name, st["l1_verified"], own)
         assert st["launches"] > 0
     s = int(np.argmax(np.diff(g.row_ptr)))
     e = np.zeros(g.n)
@@ -315,7 +379,7 @@ def test_verified_bound(pr, residual):
     out, sts = pr.ppr(dg, [s], c=C, l1_tol=tol, residual=residual, verify=True)
     own = _pagerank_residual(g, out[0], C, e) / (1 - C) + abs(out[0].sum() - 1)
     assert sts[0]["l1_verified"] >= l1(out[0], ref_s) - C / (1 - C) * delta_s
-    assert abs(sts[0]["l1_verified"] - own) <= 1e-3 * own + 1e-14
+    assert own <= sts[0]["l1_verified"] <= own * (1 + 1e-3) + 1e-12
     dg.free()
 
 
@@ -584,7 +648,7 @@ def test_autotune_keeps_results(pr):
         assert info["tile_items"] == 256 << rep["chosen"]["tile_shift"]
         assert info["ordered"] == int(rep["chosen"]["ordered"])
         for method in ("ifp1", "ifp2"):
-            for mode in (None, "push", "pull"):
+            for mode in (None, "push", "pull", "list"):
                 pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
                 assert l1(pi, ref) <= 1e-9, (method, mode)
         pi, st = pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32")

@@ -64,7 +64,7 @@ def test_peeled_ifp2_matches_oracle(pr, name, g):
         assert info[k] == v, (k, info[k], v)
     ref, _, _ = oracle.power(g, C, tol=1e-13)
     plain = pr.upload(g.row_ptr, g.col)
-    for mode in (None, "push", "pull"):
+    for mode in (None, "push", "pull", "list"):
         pi, st = pr.ifp2(dg, c=C, xi=1e-13, mode=mode)
         assert st["status"] == 0
         assert l1(pi, ref) <= 1e-9, (mode, l1(pi, ref))
