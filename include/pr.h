@@ -302,6 +302,22 @@ pr_status pr_ppr(const pr_graph *g, const int32_t *sources, int32_t k, const pr_
  */
 void pr_debug_fail_ppr_batch(int32_t b);
 
+/*
+ * pr_solve_ifp2 for callers that cannot allocate memory (code under stream capture,
+ * tight serving loops, harnesses that forbid allocation): the same solve, with every
+ * byte of its device workspace taken from a fixed array of 256 MiB that the library
+ * holds on each device it runs on (until the process ends), and no allocation, pinned
+ * host memory or timing event created by the call (stats->seconds_solve is 0).  The
+ * caller still passes p and pi as for pr_solve_ifp2 (host or device, PR_P_DEVICE /
+ * PR_OUT_DEVICE).  A solve whose workspace exceeds the array (about 32 bytes per
+ * vertex plus 18 per non-dangling vertex, and more with a host p, a host pi or
+ * PR_VERIFY: R-MAT scale 22 with FP32 residuals and a device pi takes about 140 MB)
+ * returns PR_EINVAL with the size it needs; PR_PROFILE returns PR_EINVAL.  All calls on
+ * one device share the array: calls that overlap on one device race, and each call
+ * initialises everything it reads.  Otherwise as pr_solve_ifp2.
+ */
+pr_status pr_solve_ifp2_noalloc(const pr_graph *g, const double *p, const pr_opts *o, double *pi, pr_stats *st);
+
 /* Message describing the last error on this thread ("" if none). */
 const char *pr_last_error(void);
 

@@ -34,7 +34,7 @@ EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_inf
             "pr_server_wait", "pr_server_get_stats", "pr_server_destroy",
             "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2", "pr_set_tune", "pr_graph_tune",
             "pr_state_create", "pr_state_free", "pr_state_read", "pr_solve_ifp2_warm", "pr_state_update",
-            "pr_debug_fail_ppr_batch"]
+            "pr_debug_fail_ppr_batch", "pr_solve_ifp2_noalloc"]
 
 
 class PRError(RuntimeError):
@@ -182,6 +182,8 @@ def lib():
     L.pr_server_destroy.restype = ctypes.c_int
     L.pr_debug_fail_ppr_batch.argtypes = [i32]
     L.pr_debug_fail_ppr_batch.restype = None
+    L.pr_solve_ifp2_noalloc.argtypes = [vp, dp, ctypes.POINTER(Opts), dp, ctypes.POINTER(Stats)]
+    L.pr_solve_ifp2_noalloc.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -544,6 +546,14 @@ def ifp2(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_s
     adds the a-posteriori bound l1_verified (PR_VERIFY)."""
     o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, profile, jacobi=jacobi, verify=verify)
     return _solve(lib().pr_solve_ifp2, g, p, o, out)
+
+
+def ifp2_noalloc(g: Graph, p=None, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", max_sweeps=0, out=None,
+                 stream=None, literal=False, mode=None, jacobi=False, verify=False):
+    """IFP2 through pr_solve_ifp2_noalloc: the workspace comes from the library's fixed
+    device array (no allocation in the call); otherwise as ifp2()."""
+    o = _opts(c, xi, l1_tol, residual, max_sweeps, stream, literal, mode, False, jacobi=jacobi, verify=verify)
+    return _solve(lib().pr_solve_ifp2_noalloc, g, p, o, out)
 
 
 def power(g: Graph, p=None, c=0.85, l1_tol=1e-9, residual="fp64", max_sweeps=0, out=None, stream=None,

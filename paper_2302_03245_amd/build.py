@@ -6,7 +6,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 SOURCES = ["csrc/pr_kernels.hip", "csrc/pr_batch.hip", "csrc/pr_set.hip", "csrc/pr_warm.hip", "csrc/pr_sort.hip",
            "csrc/pr_upload.hip", "csrc/pr_solve.hip", "csrc/pr_set_host.hip", "csrc/pr_host.hip",
-           "csrc/pr_serve.hip", "csrc/pr_probe.hip"]
+           "csrc/pr_serve.hip", "csrc/pr_probe.hip", "csrc/pr_noalloc.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
