@@ -78,14 +78,25 @@ struct alignas(128) Ctl {
     // finalisation
     double fin_sum, fin_sn;
     double fin_abs;       // sum |x| (equals fin_sum unless residuals went negative)
+    double fin_res;       // sum |h| over the non-dangling vertices (fin_sn is weighted when the bound is)
     // a-posteriori check (PR_VERIFY): ||P'' pi - pi||_1, its rounding bound, sum(pi)
     double ver_r, ver_err, ver_sum;
+    double ver_rf;        // sum_j f_j |r_j| with f_j the absorbing mass weight of row j (see launch_verify)
     // list sweeps (compacted frontier): entries of the two frontier lists and of the
     // lane / wave work lists of the scatter, indexed by sweep parity
     uint32_t fcnt[2], lcnt[2], wcnt[2], pad2[2];
     unsigned long long fedges[2];   // valid out-edges of the vertices in each frontier list
     unsigned long long last_edges;  // valid out-edges of the last decided sweep's active vertices
     double sn_last;                 // residual left on the non-dangling vertices after that sweep
+};
+
+// Per-vertex weights of the stop rule's error bound for folded IFP2 (null: the uniform
+// weight c / (1 - c)): g[i] bounds the L1 mass that a unit of residual left at i would
+// still add to the exact vector, q[i] the weight of a unit pushed from i into the
+// non-dangling vertices (the mean of g over i's valid out-neighbours per deg(i)).
+struct ErrWeights {
+    const float *g;
+    const float *q;
 };
 
 // A scatter item of a list sweep: a vertex with at most kLaneEdges valid out-edges is
@@ -230,6 +241,15 @@ struct Graph {
     void *ws_mem = nullptr;
     size_t ws_bytes = 0;
     void *ws_hctl = nullptr;  // pinned host control block that goes with ws_mem
+    // error weights of IFP2's stop rule, per damping factor (built by the first solve with
+    // that factor, device arrays over [0, nN) owned by the graph)
+    struct Amp {
+        double c;
+        float *g, *q;
+        double seconds;  // time taken to build them (charged as preprocessing)
+    };
+    std::mutex amp_mu;
+    std::vector<Amp> amp;
     std::vector<uint64_t> dangling_bits;  // host bitmap over original ids: no out-edges
     bool dangling(int64_t v) const { return (dangling_bits[(size_t)v >> 6] >> (v & 63)) & 1u; }
 };
@@ -291,9 +311,9 @@ template <typename T>
 hipError_t launch_init_ifp(const InitArgs &a, T *h, double *pibar, hipStream_t s);
 template <typename T>
 hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
-                          const uint32_t *rp_nn, double c, double xi, int ifp2, int stop_l1, double tol,
-                          unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
-                          double *part, hipStream_t s);
+                          const uint32_t *rp_nn, double c, double xi, int ifp2, ErrWeights ew, double kb,
+                          int stop_l1, double tol, unsigned long long pull_edges_thr, int force,
+                          unsigned long long pull_edges, double *part, hipStream_t s);
 // ordered sweeps: reserve of the non-dangling range [lo, hi) into nbg workgroup
 // partials (5 * nbg doubles at part); after all groups, k_sum_h + k_decide_gs
 template <typename T>
@@ -302,8 +322,8 @@ hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T
                                 double *part, hipStream_t s);
 template <typename T>
 hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, const GroupBlocks &gb,
-                            const double *part, double *part_s, double c, int stop_l1, double tol,
-                            unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s);
+                            const double *part, double *part_s, double c, const float *g, double kb, int stop_l1,
+                            double tol, unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s);
 template <typename T>
 hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
                        TileSkip skip = TileSkip(), KernelEvents ev = KernelEvents());
@@ -315,7 +335,7 @@ hipError_t launch_phase2_prep(const InitArgs &a, const T *h, const double *pibar
                               int literal, double *w2, double *xD, hipStream_t s);
 template <typename T>
 hipError_t launch_final_ifp(Ctl *ctl, const InitArgs &a, const T *h, const double *pibar, const double *xD,
-                            int ifp2, int literal, double *out, double *part, hipStream_t s);
+                            int ifp2, int literal, const float *g, double *out, double *part, hipStream_t s);
 // power method
 template <typename WT>
 hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, double *acc, WT *y,
@@ -323,14 +343,21 @@ hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, 
 hipError_t launch_power_init(const InitArgs &a, double *x, double *acc, hipStream_t s);
 hipError_t launch_final_x(Ctl *ctl, const InitArgs &a, const double *x, double *out, double *part, hipStream_t s);
 // a-posteriori check of the normalised output `out` (original order, device): fills
-// vctl->ver_r / ver_err / ver_sum; x, acc: n doubles, y: doubles for every vertex with
-// out-edges; *depth receives the reduction depth used for the rounding bound
+// vctl->ver_r / ver_err / ver_sum, and ver_rf when the stop-rule weights g of factor c
+// (ErrWeights::g, over the first nN vertices; rp_nn their non-dangling out-degrees) are
+// given; x, acc: n doubles, y: doubles for every vertex with out-edges; *depth receives
+// the reduction depth used for the rounding bound
 hipError_t launch_verify(Ctl *vctl, const InitArgs &a, const double *out, double *x, double *acc, double *y,
-                         const int32_t *deg, const MPPlan &pull_all, const uint32_t *in_ptr, double c, double *part,
-                         double *depth, hipStream_t s);
+                         const int32_t *deg, const MPPlan &pull_all, const uint32_t *in_ptr, double c, const float *g,
+                         int32_t nN, const uint32_t *rp_nn, double *part, double *depth, hipStream_t s);
 // zero-fill kernels (used instead of memset nodes on the solve stream)
 hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t s);
 hipError_t launch_zero_f64(double *p, int64_t count, hipStream_t s);
+// error weights of IFP2's stop rule (ErrWeights) for damping c: iterations of the
+// future-mass recursion from its upper bound 1 / (1 - c) over the N -> N out-edges
+// (plan push_nn), each an upper bound; f and acc: nN doubles of scratch
+hipError_t launch_amp_weights(int32_t nN, const MPPlan &push_nn, const int32_t *deg, const uint32_t *rp_nn,
+                              double c, int iters, double *f, double *acc, float *g, float *q, hipStream_t s);
 // kernel launches of the calling thread so far (counted by the launchers)
 extern thread_local int64_t t_kernel_launches;
 // list sweeps (compacted frontier; IFP1 / IFP2 with non-negative residuals)
@@ -338,12 +365,12 @@ extern thread_local int64_t t_kernel_launches;
 // residual on the non-dangling vertices into ctl->sn_last; the list counters must be zero
 template <typename T>
 hipError_t launch_compact(Ctl *ctl, int slot, int32_t nN, const T *h, double xi, int32_t *f, const int32_t *deg,
-                          const uint32_t *rp_nn, int ifp2, double *part, hipStream_t s);
+                          const uint32_t *rp_nn, int ifp2, const float *g, double *part, hipStream_t s);
 // reserve + decision of list sweep t over the frontier list of slot t & 1
 template <typename T>
 hipError_t launch_reserve_list(int t, Ctl *ctl, Trace *tr, const ListBufs<T> &lb, T *h, double *pibar,
                                const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2,
-                               int stop_l1, double tol, double *part, hipStream_t s);
+                               ErrWeights ew, double kb, int stop_l1, double tol, double *part, hipStream_t s);
 // scatter of list sweep t; targets whose residual rises above xi form the frontier of t + 1
 template <typename T>
 hipError_t launch_push_list(int t, Ctl *ctl, const ListBufs<T> &lb, T *h, const int32_t *deg, const uint32_t *rp_nn,

@@ -372,10 +372,12 @@ __device__ __forceinline__ void reduce_partials_n(const double *part, int nb, do
 // frontier: ctl->use_pull, set by the last decision): then a vertex's degree,
 // row offsets and pibar are loaded together with its residual, two vertices
 // per iteration, instead of after the test.  Sums run in the same order either way.
+// With error weights (ew.g non-null) the residual left and the mass sent to N are
+// weighted by g and q (the stop rule's weighted bound).
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w,
                                                     double *pibar, const int32_t *deg, const uint32_t *rp_nn,
-                                                    double c, T xi, int ifp2, double *part) {
+                                                    double c, T xi, int ifp2, ErrWeights ew, double *part) {
     if (t > ctl->stop_after) return;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     // uniform over the grid
@@ -392,13 +394,13 @@ __global__ __launch_bounds__(kBlock) void k_reserve(int t, const Ctl *ctl, int32
             h[i] = (T)0;
             w[i] = (T)(c * v / (double)dg);
             const double fN = (double)dnn / (double)dg;
-            pred += fabs(v) * fN;
+            pred += fabs(v) * (ew.q ? (double)ew.q[i] : fN);
             sxinc += ifp2 ? v * fN : v;
             cnt += 1;
             edges += ifp2 ? dnn : (uint32_t)dg;
         } else {
             w[i] = (T)0;
-            inact += fabs((double)hv);
+            inact += fabs((double)hv) * (ew.g ? (double)ew.g[i] : 1.0);
         }
     };
     int64_t i = lo + blockIdx.x * (int64_t)kBlock + threadIdx.x;
@@ -457,21 +459,24 @@ __device__ __forceinline__ double l1_bound_of(double k, double sn, double sx, in
 // workgroup partials): S_N of the stop rule, summed directly because mass a
 // group pushes may already have been taken by a later group of the same sweep.
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t nN, const T *h, double *part) {
+__global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t nN, const T *h, const float *g,
+                                                  double *part) {
     if (t > ctl->stop_after) return;
-    // eight loads in flight per thread, added in index order
+    // eight loads in flight per thread, added in index order (weighted by g when given)
     constexpr int U = 8;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     double s = 0.0;
     for (int64_t i0 = blockIdx.x * (int64_t)kBlock + threadIdx.x; i0 < nN; i0 += U * stride) {
         T x[U];
+        float gv[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = i0 + u * stride;
             x[u] = i < nN ? h[i] : (T)0;
+            gv[u] = (g && i < nN) ? g[i] : 1.0f;
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u) s += fabs((double)x[u]);
+        for (int u = 0; u < U; ++u) s += fabs((double)x[u]) * (double)gv[u];
     }
     __shared__ double sd[kBlock / W];
     s = block_sum(s, sd);
@@ -486,8 +491,8 @@ __global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t
 // the four sums.
 __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr, int ng, GroupBlocks gb,
                                                       const double *part, int nbs, const double *part_s, double c,
-                                                      int stop_l1, double tol, unsigned long long pull_thr,
-                                                      unsigned long long pull_edges) {
+                                                      double kb, int stop_l1, double tol,
+                                                      unsigned long long pull_thr, unsigned long long pull_edges) {
     if (t > ctl->stop_after) return;
     // a group has at most kGroupRounds * kBlock reserve workgroups (and k_sum_h at
     // most as many): every partial of a group, or of S_N, is loaded before any is added
@@ -535,7 +540,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr
     a_ed = v[2];
     sn = v[3];
     const unsigned long long a_c = (unsigned long long)a_cd, a_e = (unsigned long long)a_ed;
-    const double k = 2.0 * c / (1.0 - c);
+    const double k = kb;
     const double sx = ctl->sx + c * a_sx;
     const double bound = l1_bound_of(k, sn, sx, ctl->signed_res);
     ctl->sx = sx;
@@ -565,7 +570,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr
 // decides -- stop (no vertex above the threshold, or the certified L1 bound
 // after this sweep's pushes is met), and push or pull for the scatter.
 __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *tr, int nb, const double *part,
-                                                       double c, int stop_l1, double tol,
+                                                       double c, double kb, int stop_l1, double tol,
                                                        unsigned long long pull_thr, int force,
                                                        unsigned long long pull_edges) {
     if (t > ctl->stop_after) return;
@@ -575,7 +580,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_ifp(int t, Ctl *ctl, Trace *t
     if (threadIdx.x != 0) return;
     const double a_in = v[0], a_pr = v[1], a_sx = v[2], a_cd = v[3], a_ed = v[4];
     const unsigned long long a_c = (unsigned long long)a_cd, a_e = (unsigned long long)a_ed;
-    const double k = 2.0 * c / (1.0 - c);
+    const double k = kb;
     if (a_c == 0) {
         // nothing above the threshold: the state is unchanged, stop before this sweep's scatter
         ctl->stop_after = t - 1;
@@ -645,7 +650,7 @@ __device__ __forceinline__ uint32_t wave_slot(bool pred, uint32_t *cnt) {
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_compact(Ctl *ctl, int slot, int32_t nN, const T *h, T xi, int32_t *f,
                                                     const int32_t *deg, const uint32_t *rp_nn, int ifp2,
-                                                    double *part) {
+                                                    const float *g, double *part) {
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     double sn = 0.0;
     unsigned long long ve = 0;
@@ -653,7 +658,7 @@ __global__ __launch_bounds__(kBlock) void k_compact(Ctl *ctl, int slot, int32_t 
     for (int64_t base = blockIdx.x * (int64_t)kBlock + (threadIdx.x & ~(W - 1)); base < nN; base += stride) {
         const int64_t i = base + lane_id();
         const T hv = i < nN ? h[i] : (T)0;
-        sn += (double)hv;
+        sn += (double)hv * ((g && i < nN) ? (double)g[i] : 1.0);
         const bool act = hv > xi;
         const uint32_t q = wave_slot(act, &ctl->fcnt[slot]);
         if (act) {
@@ -683,7 +688,7 @@ __global__ __launch_bounds__(kBlock) void k_list_start(Ctl *ctl, int nb, const d
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_reserve_list(int t, Ctl *ctl, ListBufs<T> lb, T *h, double *pibar,
                                                          const int32_t *deg, const uint32_t *rp_nn, double c, T xi,
-                                                         int ifp2, double *part) {
+                                                         int ifp2, ErrWeights ew, double *part) {
     if (t > ctl->stop_after) return;
     const int b = t & 1;
     const uint32_t nf = ctl->fcnt[b];
@@ -713,8 +718,8 @@ __global__ __launch_bounds__(kBlock) void k_reserve_list(int t, Ctl *ctl, ListBu
                 h[i] = (T)0;
                 wt = (T)(c * v / (double)dg);
                 const double fN = (double)dnn / (double)dg;
-                taken += v;
-                pred += v * fN;
+                taken += v * (ew.g ? (double)ew.g[i] : 1.0);
+                pred += v * (ew.q ? (double)ew.q[i] : fN);
                 sxinc += ifp2 ? v * fN : v;
                 dv = ifp2 ? dnn : (uint32_t)dg;
                 cnt += 1;
@@ -751,7 +756,7 @@ __global__ __launch_bounds__(kBlock) void k_reserve_list(int t, Ctl *ctl, ListBu
 // decision's sum (residuals are non-negative and only listed vertices were taken);
 // otherwise as the synchronous sweep's decision.  List sweeps always scatter.
 __global__ __launch_bounds__(kBlock) void k_decide_list(int t, Ctl *ctl, Trace *tr, int nb, const double *part,
-                                                        double c, int stop_l1, double tol) {
+                                                        double c, double kb, int stop_l1, double tol) {
     if (t > ctl->stop_after) return;
     __shared__ double sd[5 * (kBlock / W)];
     double v[5];
@@ -759,7 +764,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_list(int t, Ctl *ctl, Trace *
     if (threadIdx.x != 0) return;
     const double taken = v[0], a_pr = v[1], a_sx = v[2];
     const unsigned long long a_c = (unsigned long long)v[3], a_e = (unsigned long long)v[4];
-    const double k = 2.0 * c / (1.0 - c);
+    const double k = kb;
     if (a_c == 0) {
         ctl->stop_after = t - 1;
         ctl->last_bound = l1_bound_of(k, ctl->sn_last, ctl->sx, 0);
@@ -1119,35 +1124,39 @@ __device__ __forceinline__ double x_ifp(const InitArgs &a, const T *h, const dou
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_final_sum(InitArgs a, const T *h, const double *pibar,
-                                                      const double *xD, int ifp2, int literal, double *part) {
-    double s = 0.0, sn = 0.0, sa = 0.0;
+                                                      const double *xD, int ifp2, int literal, const float *g,
+                                                      double *part) {
+    double s = 0.0, sn = 0.0, sa = 0.0, sr = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
         const double x = x_ifp(a, h, pibar, xD, ifp2, literal, i);
         s += x;
         sa += fabs(x);
-        if (i < a.nN) sn += fabs((double)h[i]);
+        if (i < a.nN) {
+            const double r = fabs((double)h[i]);
+            sr += r;
+            sn += g ? r * (double)g[i] : r;
+        }
     }
-    __shared__ double sd[kBlock / W];
-    s = block_sum(s, sd);
-    sn = block_sum(sn, sd);
-    sa = block_sum(sa, sd);
+    __shared__ double sd[4 * (kBlock / W)];
+    double v[4] = {s, sn, sa, sr};
+    block_sum_n(v, sd);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = s;
-        part[gridDim.x + blockIdx.x] = sn;
-        part[2 * gridDim.x + blockIdx.x] = sa;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) part[q * gridDim.x + blockIdx.x] = v[q];
     }
 }
 
-// fin_sum = part[0..nb), fin_sn = part[nb..2nb), fin_abs = part[2nb..3nb)
+// fin_sum = part[0..nb), fin_sn = part[nb..2nb) (weighted residual), fin_abs =
+// part[2nb..3nb), fin_res = part[3nb..4nb) (plain residual)
 __global__ __launch_bounds__(kBlock) void k_final_decide(Ctl *ctl, int nb, const double *part) {
-    __shared__ double sd[3 * (kBlock / W)];
-    double v[3];
+    __shared__ double sd[4 * (kBlock / W)];
+    double v[4];
     reduce_partials_n(part, nb, v, sd);
-    const double s = v[0], sn = v[1], sa = v[2];
     if (threadIdx.x == 0) {
-        ctl->fin_sum = s;
-        ctl->fin_sn = sn;
-        ctl->fin_abs = sa;
+        ctl->fin_sum = v[0];
+        ctl->fin_sn = v[1];
+        ctl->fin_abs = v[2];
+        ctl->fin_res = v[3];
     }
 }
 
@@ -1236,6 +1245,7 @@ __global__ __launch_bounds__(kBlock) void k_final_x_sum(int64_t n, const double 
         part[blockIdx.x] = s;
         part[gridDim.x + blockIdx.x] = 0.0;
         part[2 * gridDim.x + blockIdx.x] = s;  // the iterates are non-negative
+        part[3 * gridDim.x + blockIdx.x] = 0.0;
     }
 }
 
@@ -1250,7 +1260,14 @@ __global__ void k_final_x_write(const Ctl *ctl, InitArgs a, const double *x, dou
 // pi, one application of the power-method matrix P'' of Eq. 1 gives the residual
 // r = P'' pi - pi; since P'' contracts differences of equal sum by c in L1,
 // ||pi - pi_exact||_1 <= ||r||_1 / (1 - c) + |sum(pi) - 1|, whatever arithmetic
-// produced pi.  The rounding of the check itself is bounded row by row.
+// produced pi.  A second bound weighs each row instead: with b = c d^T pi +
+// (1 - c) sum(pi) (the jump weight of r), u = pi / b solves (I - cP) u = p - r / b,
+// so u differs from y = (I - cP)^{-1} p (Eq. 4, dangling vertices absorbing) by
+// (I - cP)^{-1} r / b, whose L1 norm is at most sum_j f_j |r_j| / b with f_j the
+// mass that a unit at j adds to y: 1 at a dangling j, and 1 + c delta_j + g_j at
+// a non-dangling one (the stop rule's weights, upper bounds).  Normalising, pi_exact
+// = y / |y| and |u| = sum(pi) / b give ||pi - pi_exact||_1 <= 2 sum_j f_j |r_j| /
+// sum(pi) + |sum(pi) - 1|.  The rounding of the check itself is bounded row by row.
 // ------------------------------------------------------------------------
 __global__ void k_verify_load(int64_t n, const int32_t *perm, const double *out, double *x, double *acc) {
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
@@ -1262,39 +1279,98 @@ __global__ void k_verify_load(int64_t n, const int32_t *perm, const double *out,
 // per row j: r_j = |acc_j + b p_j - x_j| with acc_j = sum over in-edges of c x_u / deg(u);
 // err_j bounds the FP64 rounding of computing it: the k_j-term sum of acc_j (any order:
 // k_j - 1 additions), the quotients c x_u / deg(u) (2 each), b (depth_b additions of
-// its reduction) and the final add, subtract and absolute value
+// its reduction) and the final add, subtract and absolute value.  With weights g (of
+// the first nN rows), rf accumulates f_j r_j; f_j is widened by 1e-12 relative over
+// the rounding of forming it.
 __global__ __launch_bounds__(kBlock) void k_verify_residual(const Ctl *ctl, InitArgs a, const uint32_t *in_ptr,
                                                             const double *x, const double *acc, double depth_b,
-                                                            double *part) {
+                                                            double c, const float *g, int32_t nN, const int32_t *deg,
+                                                            const uint32_t *rp_nn, double *part) {
     const double b = ctl->pw_b;
-    double r = 0.0, err = 0.0, xs = 0.0;
+    double r = 0.0, err = 0.0, xs = 0.0, rf = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
         const double k = (double)(in_ptr[i + 1] - in_ptr[i]);
         const double bp = b * p_of(a, i);
         const double v = acc[i] + bp;
-        r += fabs(v - x[i]);
+        const double ri = fabs(v - x[i]);
+        r += ri;
         err += (k + 4.0 + depth_b) * (acc[i] + bp + x[i]);
         xs += x[i];
+        if (g) {
+            double f = 1.0;
+            if (i < nN) {
+                const double dg = (double)deg[i];
+                const double delta = 1.0 - (double)(rp_nn[i + 1] - rp_nn[i]) / dg;
+                f = (1.0 + c * delta + (double)g[i]) * (1.0 + 1e-12);
+            }
+            rf += f * ri;
+        }
     }
     __shared__ double sd[kBlock / W];
     r = block_sum(r, sd);
     err = block_sum(err, sd);
     xs = block_sum(xs, sd);
+    rf = block_sum(rf, sd);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = r;
         part[gridDim.x + blockIdx.x] = err;
         part[2 * gridDim.x + blockIdx.x] = xs;
+        part[3 * gridDim.x + blockIdx.x] = rf;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_verify_decide(Ctl *ctl, int nb, const double *part) {
-    __shared__ double sd[3 * (kBlock / W)];
-    double v[3];
+    __shared__ double sd[4 * (kBlock / W)];
+    double v[4];
     reduce_partials_n(part, nb, v, sd);
     if (threadIdx.x != 0) return;
     ctl->ver_r = v[0];
     ctl->ver_err = v[1];
     ctl->ver_sum = v[2];
+    ctl->ver_rf = v[3];
+}
+
+// ------------------------------------------------------------------------
+// error weights of the stop rule (folded IFP2).  A unit of residual left at a
+// non-dangling i would still be pushed: c / deg(i) to each non-dangling out-neighbour
+// j, whose arrival then counts itself, the share c delta_j it sends to dangling
+// vertices (delta_j: the share of j's out-edges that lead there), and its own pushes
+// on.  With f_j the mass a unit arriving at j adds in total,
+//   f_j = 1 + c delta_j + (c / deg(j)) sum_{k in out_N(j)} f_k,
+// and g_i = (c / deg(i)) sum_{j in out_N(i)} f_j is the error a unit at i leaves.
+// f = 1 / (1 - c) satisfies f >= T(f), so the iterates from it decrease to the
+// fixed point and each is an upper bound; the stored weights are rounded up with a
+// relative margin of 1e-6 over the FP64 rounding of the iterations.
+// ------------------------------------------------------------------------
+__global__ void k_amp_init(int32_t nN, double c, double *f, double *acc) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock) {
+        f[i] = 1.0 / (1.0 - c);
+        acc[i] = 0.0;
+    }
+}
+
+// f_i = 1 + c delta_i + c acc_i / deg(i), acc_i = sum of f over i's N out-neighbours
+__global__ void k_amp_step(int32_t nN, double c, const int32_t *deg, const uint32_t *rp_nn, double *f, double *acc) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock) {
+        const double dg = (double)deg[i];
+        const double delta = 1.0 - (double)(rp_nn[i + 1] - rp_nn[i]) / dg;
+        f[i] = 1.0 + c * delta + c * acc[i] / dg;
+        acc[i] = 0.0;
+    }
+}
+
+// g_i = c acc_i / deg(i) (acc = sum of f), rounded up
+__global__ void k_amp_g(int32_t nN, double c, const int32_t *deg, double *acc, float *g) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock) {
+        g[i] = __double2float_ru(c * acc[i] / (double)deg[i] * (1.0 + 1e-6));
+        acc[i] = 0.0;
+    }
+}
+
+// q_i = acc_i / deg(i) (acc = sum of g), rounded up
+__global__ void k_amp_q(int32_t nN, const int32_t *deg, const double *acc, float *q) {
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < nN; i += (int64_t)gridDim.x * kBlock)
+        q[i] = __double2float_ru(acc[i] / (double)deg[i] * (1.0 + 1e-6));
 }
 
 // fill kernels (clearing counters and sums without a memset node in the stream)
@@ -1429,13 +1505,13 @@ hipError_t launch_init_ifp(const InitArgs &a, T *h, double *pibar, hipStream_t s
 
 template <typename T>
 hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
-                          const uint32_t *rp_nn, double c, double xi, int ifp2, int stop_l1, double tol,
-                          unsigned long long pull_edges_thr, int force, unsigned long long pull_edges,
-                          double *part, hipStream_t s) {
+                          const uint32_t *rp_nn, double c, double xi, int ifp2, ErrWeights ew, double kb,
+                          int stop_l1, double tol, unsigned long long pull_edges_thr, int force,
+                          unsigned long long pull_edges, double *part, hipStream_t s) {
     const int nb = grid_for(nN, 4, kRedBlocks);
     PRK_GGL(k_reserve<T>, dim3(nb), dim3(kBlock), 0, s, t, (const Ctl *)ctl, 0, nN, h, w, pibar, deg,
-                       rp_nn, c, (T)xi, ifp2, part);
-    PRK_GGL(k_decide_ifp, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, nb, (const double *)part, c, stop_l1,
+                       rp_nn, c, (T)xi, ifp2, ew, part);
+    PRK_GGL(k_decide_ifp, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, nb, (const double *)part, c, kb, stop_l1,
                        tol, pull_edges_thr, force, pull_edges);
     return hipGetLastError();
 }
@@ -1445,18 +1521,18 @@ hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T
                                 const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2, int nbg,
                                 double *part, hipStream_t s) {
     PRK_GGL(k_reserve<T>, dim3(nbg), dim3(kBlock), 0, s, t, (const Ctl *)ctl, lo, hi, h, w, pibar, deg,
-                       rp_nn, c, (T)xi, ifp2, part);
+                       rp_nn, c, (T)xi, ifp2, ErrWeights{nullptr, nullptr}, part);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, const GroupBlocks &gb,
-                            const double *part, double *part_s, double c, int stop_l1, double tol,
-                            unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s) {
+                            const double *part, double *part_s, double c, const float *g, double kb, int stop_l1,
+                            double tol, unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s) {
     const int nbs = grid_for(nN, 8, kRedBlocks);
-    PRK_GGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, part_s);
+    PRK_GGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, g, part_s);
     PRK_GGL(k_decide_gs, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, ng, gb, part, nbs,
-                       (const double *)part_s, c, stop_l1, tol, pull_thr, pull_edges);
+                       (const double *)part_s, c, kb, stop_l1, tol, pull_thr, pull_edges);
     return hipGetLastError();
 }
 
@@ -1526,9 +1602,9 @@ hipError_t launch_peel_w2(int32_t lo, int32_t hi, int32_t nN, const double *xD, 
 
 template <typename T>
 hipError_t launch_final_ifp(Ctl *ctl, const InitArgs &a, const T *h, const double *pibar, const double *xD,
-                            int ifp2, int literal, double *out, double *part, hipStream_t s) {
+                            int ifp2, int literal, const float *g, double *out, double *part, hipStream_t s) {
     const int nb = grid_for(a.n, 4, kRedBlocks);
-    PRK_GGL(k_final_sum<T>, dim3(nb), dim3(kBlock), 0, s, a, h, pibar, xD, ifp2, literal, part);
+    PRK_GGL(k_final_sum<T>, dim3(nb), dim3(kBlock), 0, s, a, h, pibar, xD, ifp2, literal, g, part);
     PRK_GGL(k_final_decide, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
     PRK_GGL(k_final_write<T>, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, (const Ctl *)ctl, a, h,
                        pibar, xD, ifp2, literal, out);
@@ -1551,10 +1627,10 @@ hipError_t launch_power_prescale(int t, Ctl *ctl, const InitArgs &a, double *x, 
 
 template <typename T>
 hipError_t launch_compact(Ctl *ctl, int slot, int32_t nN, const T *h, double xi, int32_t *f, const int32_t *deg,
-                          const uint32_t *rp_nn, int ifp2, double *part, hipStream_t s) {
+                          const uint32_t *rp_nn, int ifp2, const float *g, double *part, hipStream_t s) {
     if (nN <= 0) return hipSuccess;
     const int nb = grid_for(nN, 4, kRedBlocks);
-    PRK_GGL(k_compact<T>, dim3(nb), dim3(kBlock), 0, s, ctl, slot, nN, h, (T)xi, f, deg, rp_nn, ifp2, part);
+    PRK_GGL(k_compact<T>, dim3(nb), dim3(kBlock), 0, s, ctl, slot, nN, h, (T)xi, f, deg, rp_nn, ifp2, g, part);
     PRK_GGL(k_list_start, dim3(1), dim3(kBlock), 0, s, ctl, nb, (const double *)part);
     return hipGetLastError();
 }
@@ -1564,12 +1640,12 @@ constexpr int kListBlocks = 512;  // workgroups of the list reserve (its partial
 template <typename T>
 hipError_t launch_reserve_list(int t, Ctl *ctl, Trace *tr, const ListBufs<T> &lb, T *h, double *pibar,
                                const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2,
-                               int stop_l1, double tol, double *part, hipStream_t s) {
+                               ErrWeights ew, double kb, int stop_l1, double tol, double *part, hipStream_t s) {
     static_assert(kListBlocks <= kRedBlocks, "partials");
     PRK_GGL(k_reserve_list<T>, dim3(kListBlocks), dim3(kBlock), 0, s, t, ctl, lb, h, pibar, deg, rp_nn, c, (T)xi,
-            ifp2, part);
-    PRK_GGL(k_decide_list, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, kListBlocks, (const double *)part, c, stop_l1,
-            tol);
+            ifp2, ew, part);
+    PRK_GGL(k_decide_list, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, kListBlocks, (const double *)part, c, kb,
+            stop_l1, tol);
     return hipGetLastError();
 }
 
@@ -1579,6 +1655,25 @@ hipError_t launch_push_list(int t, Ctl *ctl, const ListBufs<T> &lb, T *h, const 
                             hipStream_t s) {
     static const int grid = resident_grid(k_push_list<T>);
     PRK_LAUNCH(k_push_list<T>, grid, t, ctl, lb, h, deg, rp_nn, col_nn, rp_nd, col_nd, (T)xi, ifp2);
+}
+
+hipError_t launch_amp_weights(int32_t nN, const MPPlan &push_nn, const int32_t *deg, const uint32_t *rp_nn,
+                              double c, int iters, double *f, double *acc, float *g, float *q, hipStream_t s) {
+    if (nN <= 0) return hipSuccess;
+    const int grid = grid_for(nN, 4, 8192);
+    PRK_GGL(k_amp_init, dim3(grid), dim3(kBlock), 0, s, nN, c, f, acc);
+    for (int k = 0; k < iters; ++k) {
+        hipError_t e = launch_pull<double, double>(-1, nullptr, push_nn, f, acc, 0, s);
+        if (e != hipSuccess) return e;
+        PRK_GGL(k_amp_step, dim3(grid), dim3(kBlock), 0, s, nN, c, deg, rp_nn, f, acc);
+    }
+    hipError_t e = launch_pull<double, double>(-1, nullptr, push_nn, f, acc, 0, s);
+    if (e != hipSuccess) return e;
+    PRK_GGL(k_amp_g, dim3(grid), dim3(kBlock), 0, s, nN, c, deg, acc, g);
+    e = launch_pull<float, double>(-1, nullptr, push_nn, g, acc, 0, s);
+    if (e != hipSuccess) return e;
+    PRK_GGL(k_amp_q, dim3(grid), dim3(kBlock), 0, s, nN, deg, (const double *)acc, q);
+    return hipGetLastError();
 }
 
 hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t s) {
@@ -1592,8 +1687,8 @@ hipError_t launch_zero_f64(double *p, int64_t count, hipStream_t s) {
 }
 
 hipError_t launch_verify(Ctl *vctl, const InitArgs &a, const double *out, double *x, double *acc, double *y,
-                         const int32_t *deg, const MPPlan &pull_all, const uint32_t *in_ptr, double c, double *part,
-                         double *depth, hipStream_t s) {
+                         const int32_t *deg, const MPPlan &pull_all, const uint32_t *in_ptr, double c, const float *g,
+                         int32_t nN, const uint32_t *rp_nn, double *part, double *depth, hipStream_t s) {
     const int nb = grid_for(a.n, 4, kRedBlocks);
     // depth of a reduction over n entries as the sums below run it: a thread's strided
     // run, the workgroup tree, and the partials summed by one thread per lane
@@ -1605,7 +1700,7 @@ hipError_t launch_verify(Ctl *vctl, const InitArgs &a, const double *out, double
     hipError_t e = launch_pull<double, double>(0, vctl, pull_all, y, acc, 0, s);
     if (e != hipSuccess) return e;
     PRK_GGL(k_verify_residual, dim3(nb), dim3(kBlock), 0, s, (const Ctl *)vctl, a, in_ptr, (const double *)x,
-            (const double *)acc, *depth, part);
+            (const double *)acc, *depth, c, g, nN, deg, rp_nn, part);
     PRK_GGL(k_verify_decide, dim3(1), dim3(kBlock), 0, s, vctl, nb, (const double *)part);
     return hipGetLastError();
 }
@@ -1635,15 +1730,15 @@ hipError_t launch_validate_p(const double *p, int64_t n, double *sum_bad, hipStr
 
 // explicit instantiations
 template hipError_t launch_compact<float>(Ctl *, int, int32_t, const float *, double, int32_t *, const int32_t *,
-                                          const uint32_t *, int, double *, hipStream_t);
+                                          const uint32_t *, int, const float *, double *, hipStream_t);
 template hipError_t launch_compact<double>(Ctl *, int, int32_t, const double *, double, int32_t *, const int32_t *,
-                                           const uint32_t *, int, double *, hipStream_t);
+                                           const uint32_t *, int, const float *, double *, hipStream_t);
 template hipError_t launch_reserve_list<float>(int, Ctl *, Trace *, const ListBufs<float> &, float *, double *,
-                                               const int32_t *, const uint32_t *, double, double, int, int, double,
-                                               double *, hipStream_t);
+                                               const int32_t *, const uint32_t *, double, double, int, ErrWeights,
+                                               double, int, double, double *, hipStream_t);
 template hipError_t launch_reserve_list<double>(int, Ctl *, Trace *, const ListBufs<double> &, double *, double *,
-                                                const int32_t *, const uint32_t *, double, double, int, int, double,
-                                                double *, hipStream_t);
+                                                const int32_t *, const uint32_t *, double, double, int, ErrWeights,
+                                                double, int, double, double *, hipStream_t);
 template hipError_t launch_push_list<float>(int, Ctl *, const ListBufs<float> &, float *, const int32_t *,
                                             const uint32_t *, const int32_t *, const uint32_t *, const int32_t *,
                                             double, int, hipStream_t);
@@ -1653,11 +1748,12 @@ template hipError_t launch_push_list<double>(int, Ctl *, const ListBufs<double> 
 template hipError_t launch_init_ifp<float>(const InitArgs &, float *, double *, hipStream_t);
 template hipError_t launch_init_ifp<double>(const InitArgs &, double *, double *, hipStream_t);
 template hipError_t launch_reserve<float>(int, Ctl *, Trace *, int32_t, float *, float *, double *, const int32_t *,
-                                          const uint32_t *, double, double, int, int, double, unsigned long long,
-                                          int, unsigned long long, double *, hipStream_t);
+                                          const uint32_t *, double, double, int, ErrWeights, double, int, double,
+                                          unsigned long long, int, unsigned long long, double *, hipStream_t);
 template hipError_t launch_reserve<double>(int, Ctl *, Trace *, int32_t, double *, double *, double *,
-                                           const int32_t *, const uint32_t *, double, double, int, int, double,
-                                           unsigned long long, int, unsigned long long, double *, hipStream_t);
+                                           const int32_t *, const uint32_t *, double, double, int, ErrWeights, double,
+                                           int, double, unsigned long long, int, unsigned long long, double *,
+                                           hipStream_t);
 template hipError_t launch_reserve_range<float>(int, Ctl *, int32_t, int32_t, float *, float *, double *,
                                                 const int32_t *, const uint32_t *, double, double, int, int,
                                                 double *, hipStream_t);
@@ -1665,11 +1761,11 @@ template hipError_t launch_reserve_range<double>(int, Ctl *, int32_t, int32_t, d
                                                  const int32_t *, const uint32_t *, double, double, int, int,
                                                  double *, hipStream_t);
 template hipError_t launch_decide_gs<float>(int, Ctl *, Trace *, int32_t, const float *, int, const GroupBlocks &,
-                                            const double *, double *, double, int, double, unsigned long long,
-                                            unsigned long long, hipStream_t);
+                                            const double *, double *, double, const float *, double, int, double,
+                                            unsigned long long, unsigned long long, hipStream_t);
 template hipError_t launch_decide_gs<double>(int, Ctl *, Trace *, int32_t, const double *, int, const GroupBlocks &,
-                                             const double *, double *, double, int, double, unsigned long long,
-                                             unsigned long long, hipStream_t);
+                                             const double *, double *, double, const float *, double, int, double,
+                                             unsigned long long, unsigned long long, hipStream_t);
 
 template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t,
                                        TileSkip, KernelEvents);
@@ -1686,9 +1782,9 @@ template hipError_t launch_phase2_prep<float>(const InitArgs &, const float *, c
 template hipError_t launch_phase2_prep<double>(const InitArgs &, const double *, const double *, const int32_t *,
                                                double, int, double *, double *, hipStream_t);
 template hipError_t launch_final_ifp<float>(Ctl *, const InitArgs &, const float *, const double *, const double *,
-                                            int, int, double *, double *, hipStream_t);
+                                            int, int, const float *, double *, double *, hipStream_t);
 template hipError_t launch_final_ifp<double>(Ctl *, const InitArgs &, const double *, const double *,
-                                             const double *, int, int, double *, double *, hipStream_t);
+                                             const double *, int, int, const float *, double *, double *, hipStream_t);
 template hipError_t launch_power_prescale<float>(int, Ctl *, const InitArgs &, double *, double *, float *,
                                                  const int32_t *, double, double, double *, hipStream_t);
 template hipError_t launch_power_prescale<double>(int, Ctl *, const InitArgs &, double *, double *, double *,

@@ -39,6 +39,57 @@ pr_status acquire_ws(Graph &G, size_t bytes, Workspace &ws, hipStream_t s) {
 }
 
 
+// Error weights of IFP2's stop rule for damping factor c (see ErrWeights): built once per
+// graph and factor on the solve's stream and kept on the graph (for up to kMaxAmp
+// factors; a solve that may not allocate, or finds the table full, keeps the uniform
+// weight c / (1 - c)).  kAmpIters iterations of the recursion leave the weights within
+// about c^k of their limit on the graphs measured (the residual decays at the rate of
+// c P restricted to the non-dangling vertices).
+constexpr int kMaxAmp = 4;
+constexpr int kAmpIters = 16;
+
+static pr_status amp_weights(Graph &G, double c, bool may_alloc, hipStream_t s, ErrWeights *out,
+                             double *seconds = nullptr) {
+    *out = ErrWeights{nullptr, nullptr};
+    if (seconds) *seconds = 0.0;
+    std::lock_guard<std::mutex> lk(G.amp_mu);
+    for (const Graph::Amp &a : G.amp)
+        if (a.c == c) {
+            *out = ErrWeights{a.g, a.q};
+            if (seconds) *seconds = a.seconds;
+            return PR_OK;
+        }
+    if (!may_alloc || (int)G.amp.size() >= kMaxAmp || G.nN == 0 || G.mNN == 0) return PR_OK;
+    const auto t0 = std::chrono::steady_clock::now();
+    DevBufs tmp;
+    double *f = nullptr, *acc = nullptr;
+    HIPCHK(tmp.alloc(&f, (size_t)G.nN));
+    HIPCHK(tmp.alloc(&acc, (size_t)G.nN));
+    DevBufs keep;
+    float *g = nullptr, *q = nullptr;
+    HIPCHK(keep.alloc(&g, (size_t)G.nN));
+    HIPCHK(keep.alloc(&q, (size_t)G.nN));
+    HIPCHK(launch_amp_weights(G.nN, G.push_nn, G.deg, G.rp_nn, c, kAmpIters, f, acc, g, q, s));
+    HIPCHK(hipStreamSynchronize(s));  // other streams may take the weights from the table
+    for (void *p : keep.ptrs) {
+        G.allocs.push_back(p);
+        G.device_bytes += (int64_t)sizeof(float) * G.nN;
+    }
+    keep.ptrs.clear();
+    const double sec = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    G.amp.push_back(Graph::Amp{c, g, q, sec});
+    *out = ErrWeights{g, q};
+    if (seconds) *seconds = sec;
+    return PR_OK;
+}
+
+// The stop rule's error weights for factor c built ahead of solves that may not allocate
+// (a server engine's solves run in a workspace of its own).
+pr_status stop_weights(Graph &G, double c, hipStream_t s) {
+    ErrWeights ew;
+    return amp_weights(G, c, true, s, &ew);
+}
+
 // Validate p (host or device) and place it on the device; returns 1/sum(p).
 pr_status prepare_p(const Graph &G, const double *p, const pr_opts &o, double *pdev, double *sumbad,
                     const double **p_used, double *pscale, hipStream_t s) {
@@ -89,8 +140,9 @@ int next_batch(int prev_batch, double bound_prev, double bound_now, int swept, d
 // A-posteriori check of a written result (PR_VERIFY): one application of P'' (Eq. 1)
 // to the normalised output in FP64 (the vertices with out-edges are [0, nN + nP)).
 // The copy of the control block is read back with the solve's own (same stream).
-static hipError_t run_verify(const Graph &G, const InitArgs &a, double c, const double *out, double *x, double *acc,
-                             double *y, Ctl *vctl, double *part, Ctl *res, double *depth, hipStream_t s) {
+// g: the stop rule's weights for factor c (null: the check without row weights)
+static hipError_t run_verify(const Graph &G, const InitArgs &a, double c, const float *g, const double *out, double *x,
+                             double *acc, double *y, Ctl *vctl, double *part, Ctl *res, double *depth, hipStream_t s) {
     Ctl hc;
     memset(&hc, 0, sizeof(hc));
     hc.stop_after = INT_MAX;
@@ -98,7 +150,7 @@ static hipError_t run_verify(const Graph &G, const InitArgs &a, double c, const 
     if (e != hipSuccess) return e;
     InitArgs av = a;
     av.nN = G.nN + G.nP;
-    e = launch_verify(vctl, av, out, x, acc, y, G.deg, G.pull_all, G.in_ptr, c, part, depth, s);
+    e = launch_verify(vctl, av, out, x, acc, y, G.deg, G.pull_all, G.in_ptr, c, g, G.nN, G.rp_nn, part, depth, s);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(res, vctl, sizeof(Ctl), hipMemcpyDeviceToHost, s);
     if (e != hipSuccess) return e;
@@ -106,12 +158,20 @@ static hipError_t run_verify(const Graph &G, const InitArgs &a, double c, const 
 }
 
 // ||pi - pi_exact||_1 <= ||P'' pi - pi||_1 / (1 - c) + |sum(pi) - 1| (P'' contracts by c
-// the differences of vectors with equal sums), each FP64 quantity widened by the
-// rounding of its own computation (unit roundoff 2^-53, first order, with 1 % margin)
-static double verified_bound(const Ctl &v, double depth, double c) {
+// the differences of vectors with equal sums), and with row weights f (weighted)
+// <= 2 sum_j f_j |r_j| / sum(pi) + |sum(pi) - 1| (see launch_verify); the smaller of the
+// two, each FP64 quantity widened by the rounding of its own computation (unit roundoff
+// 2^-53, first order, with 1 % margin; a row's weight is at most 1 / (1 - c))
+static double verified_bound(const Ctl &v, double depth, double c, bool weighted) {
     const double u = ldexp(1.0, -53) * 1.01;
+    const double tail = fabs(v.ver_sum - 1.0) + depth * u * v.ver_sum;
     const double r = v.ver_r * (1.0 + depth * u) + v.ver_err * u;
-    return r / (1.0 - c) + fabs(v.ver_sum - 1.0) + depth * u * v.ver_sum;
+    double best = r / (1.0 - c) + tail;
+    if (weighted && v.ver_sum > 0.0) {
+        const double rf = v.ver_rf * (1.0 + depth * u) + v.ver_err * u / (1.0 - c);
+        best = std::min(best, 2.0 * rf / (v.ver_sum * (1.0 - depth * u)) + tail);
+    }
+    return best;
 }
 
 // Workspace layout of solve_ifp_t (the order of the carve below).
@@ -214,6 +274,19 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     a.uniform = (p == nullptr && source < 0);
     ps = prepare_p(G, p, o, pdev, sumbad, &a.p, &a.pscale, s);
     if (ps != PR_OK) return ps;
+    // the stop rule's error bound: per-vertex weights for folded IFP2 on a graph without
+    // peeled vertices (the weighted sum bounds the unnormalised error itself, so the
+    // factor is 2 for the normalisation), else c / (1 - c) per unit of residual.  A warm
+    // start takes them only when the graph already has them: after a change the graph is
+    // new, and building them (a few gathers over its edges) would cost a large share of
+    // the few sweeps a warm start needs
+    ErrWeights ew{nullptr, nullptr};
+    double seconds_weights = 0.0;
+    if (ifp2 && !literal && G.nP == 0) {
+        ps = amp_weights(const_cast<Graph &>(G), c, ext == nullptr && !warm, s, &ew, &seconds_weights);
+        if (ps != PR_OK) return ps;
+    }
+    const double kb = ew.g ? 2.0 : 2.0 * c / (1.0 - c);
 
     EventPair ev_solve(ext == nullptr);  // no events in a solve that allocates nothing
     SweepTimer timer;
@@ -268,7 +341,8 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                 // the list of sweep t from the residuals; counters of both parities cleared
                 HIPCHK(launch_zero_u32(&ctl->fcnt[0], 8, s));
                 HIPCHK(launch_zero_u32((uint32_t *)(void *)&ctl->fedges[0], 4, s));
-                HIPCHK(launch_compact<T>(ctl, t & 1, nN, h, xi, lb.f[t & 1], G.deg, G.rp_nn, ifp2 ? 1 : 0, part, s));
+                HIPCHK(launch_compact<T>(ctl, t & 1, nN, h, xi, lb.f[t & 1], G.deg, G.rp_nn, ifp2 ? 1 : 0, ew.g, part,
+                                         s));
                 list_ready = true;
             }
             // while sparse, the host looks at the frontier after every sweep (it can grow a
@@ -277,8 +351,8 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
             int nb = std::min(bmax, max_sweeps - t);
             for (int k = 0; k < nb; ++k, ++t) {
                 if (list_on) {
-                    HIPCHK(launch_reserve_list<T>(t, ctl, tr, lb, h, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0,
-                                                  l1 ? 1 : 0, tol, part, s));
+                    HIPCHK(launch_reserve_list<T>(t, ctl, tr, lb, h, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, ew,
+                                                  kb, l1 ? 1 : 0, tol, part, s));
                     HIPCHK(launch_push_list<T>(t, ctl, lb, h, G.deg, G.rp_nn, G.col_nn, G.rp_nd, G.col_nd, xi,
                                                ifp2 ? 1 : 0, s));
                     continue;
@@ -298,17 +372,20 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                                                        part + (size_t)5 * kGroupBlocks * q, s));
                         const MPPlan &pl = ifp2 ? G.grp_pull[e][q] : G.grp_pull_all[e][q];
                         sweep_edges += (unsigned long long)pl.edges();
-                        const KernelEvents ev =
-                            timer.next(t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT));
+                        // the method's own bytes: every gathered in-edge (source id + weight), and
+                        // each target row once per sweep (offset + residual update), shared
+                        // evenly by the group gathers that each walk all the rows
+                        const KernelEvents ev = timer.next(
+                            t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT) / (double)ngr);
                         HIPCHK(launch_pull<T, T>(t, ctl, pl, w, h, 0, s, TileSkip(), ev));
                     }
                     HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, gb, part,
-                                               part + (size_t)5 * kGroupBlocks * ngr, c, l1 ? 1 : 0, tol, pull_thr,
-                                               sweep_edges, s));
+                                               part + (size_t)5 * kGroupBlocks * ngr, c, ew.g, kb, l1 ? 1 : 0, tol,
+                                               pull_thr, sweep_edges, s));
                     continue;
                 }
-                HIPCHK(launch_reserve<T>(t, ctl, tr, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, l1 ? 1 : 0,
-                                         tol, pull_thr, force, pull_edges, part, s));
+                HIPCHK(launch_reserve<T>(t, ctl, tr, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, ew, kb,
+                                         l1 ? 1 : 0, tol, pull_thr, force, pull_edges, part, s));
                 if (force != 2) {
                     // the scatter is timed when it is forced; in the automatic mode only the
                     // gather (the dense sweeps' kernel) carries events, to keep their overhead low
@@ -378,17 +455,24 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         HIPCHK(launch_pull<double, double>(-1, ctl, G.pull_nd, w2, xD, 0, s));
     }
     double *dst = out_dev ? pi : outbuf;
-    HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, dst, part, s));
+    HIPCHK(launch_final_ifp<T>(ctl, a, h, pibar, xD, ifp2 ? 1 : 0, literal ? 1 : 0, ew.g, dst, part, s));
     if (warm) HIPCHK(launch_warm_export<T>(n, nN, G.perm, h, pibar, hDn, warm->pibar, warm->h, s));
     if (ev_solve.b) HIPCHK(hipEventRecord(ev_solve.b, s));
     Ctl vres;
     double vdepth = 0.0;
-    if (verify) HIPCHK(run_verify(G, a, c, dst, vx, vacc, w2, vctl, part, &vres, &vdepth, s));
+    // the check's row weights: those of the stop rule (graphs without peeled vertices,
+    // whose dangling vertices are the only absorbing ones)
+    ErrWeights evw = ew;
+    if (verify && !evw.g && G.nP == 0) {
+        ps = amp_weights(const_cast<Graph &>(G), c, ext == nullptr, s, &evw);
+        if (ps != PR_OK) return ps;
+    }
+    if (verify) HIPCHK(run_verify(G, a, c, evw.g, dst, vx, vacc, w2, vctl, part, &vres, &vdepth, s));
     HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const Ctl &r = *ws.hctl;
-    const double l1_verified = verify ? verified_bound(vres, vdepth, c) : 0.0;
+    const double l1_verified = verify ? verified_bound(vres, vdepth, c, evw.g != nullptr) : 0.0;
     if (st) {
         pr_stats z;
         memset(&z, 0, sizeof(z));
@@ -397,18 +481,19 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
         z.edges_processed = (int64_t)r.tot_edges + (ifp2 ? G.mND : 0);
         z.edges_traversed = (int64_t)r.tot_traversed + (ifp2 ? G.mND : 0);
         z.vertex_pushes = (int64_t)r.tot_pushes;
-        z.residual_l1 = r.fin_sum > 0 ? r.fin_sn / r.fin_sum : 0.0;
-        const double k = literal ? 2.0 / (1.0 - c) : 2.0 * c / (1.0 - c);
+        z.residual_l1 = r.fin_sum > 0 ? r.fin_res / r.fin_sum : 0.0;
+        const double k = literal ? 2.0 / (1.0 - c) : kb;
         z.l1_bound = r.fin_sum > 0 ? k * r.fin_sn / r.fin_sum : 0.0;
         if (warm) {
-            // signed residuals: unnormalised error E <= c / (1 - c) sum|h_N|, the exact mass is at
-            // least fin_sum - E, and normalising costs (1 + sum|x| / sum x) E / (that mass)
-            const double E = c / (1.0 - c) * r.fin_sn;
+            // signed residuals: unnormalised error E <= c / (1 - c) sum|h_N| (or the weighted
+            // sum), the exact mass is at least fin_sum - E, and normalising costs
+            // (1 + sum|x| / sum x) E / (that mass)
+            const double E = 0.5 * kb * r.fin_sn;
             const double den = r.fin_sum - E;
             z.l1_bound = den > 0 ? (1.0 + r.fin_abs / r.fin_sum) * E / den : INFINITY;
         }
         z.seconds_solve = ev_solve.a ? elapsed_s(ev_solve.a, ev_solve.b) : 0.0;
-        z.seconds_preprocess = ifp2 ? G.seconds_split : 0.0;
+        z.seconds_preprocess = ifp2 ? G.seconds_split + seconds_weights : 0.0;
         z.launches = t_kernel_launches - launches0;
         z.l1_verified = l1_verified;
         if (timer.on) {
@@ -534,12 +619,17 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     Ctl vres;
     double vdepth = 0.0;
     // the iterate buffers are free once the answer is written: the check reuses them
-    if (verify) HIPCHK(run_verify(G, a, c, dst, x, acc, vy, vctl, part, &vres, &vdepth, s));
+    ErrWeights evw{nullptr, nullptr};
+    if (verify && G.nP == 0) {
+        ps = amp_weights(const_cast<Graph &>(G), c, true, s, &evw);
+        if (ps != PR_OK) return ps;
+    }
+    if (verify) HIPCHK(run_verify(G, a, c, evw.g, dst, x, acc, vy, vctl, part, &vres, &vdepth, s));
     HIPCHK(hipMemcpyAsync(ws.hctl, ctl, sizeof(Ctl), hipMemcpyDeviceToHost, s));
     if (!out_dev) HIPCHK(hipMemcpyAsync(pi, outbuf, sizeof(double) * n, hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     const Ctl &r = *ws.hctl;
-    const double l1_verified = verify ? verified_bound(vres, vdepth, c) : 0.0;
+    const double l1_verified = verify ? verified_bound(vres, vdepth, c, evw.g != nullptr) : 0.0;
     if (st) {
         pr_stats z;
         memset(&z, 0, sizeof(z));

@@ -78,8 +78,10 @@ def test_set_matches_oracle_and_alone(pr, residual, tol, mode):
         dg = pr.upload(g.row_ptr, g.col)
         alone, sa = pr.ifp2(dg, c=c, l1_tol=tol, residual=residual, mode=mode, jacobi=True)
         assert l1(x, alone) <= 2 * tol, (i, l1(x, alone))
-        # same Jacobi trajectory per graph: only the rounding order differs
-        assert abs(st["sweeps"] - sa["sweeps"]) <= 1, (i, st["sweeps"], sa["sweeps"])
+        # same Jacobi trajectory per graph, only the rounding order differs; the solo
+        # solve's stop rule weighs each vertex's residual by its own error weight, never
+        # above the set's uniform c / (1 - c), so it stops no later
+        assert sa["sweeps"] <= st["sweeps"] + 1, (i, st["sweeps"], sa["sweeps"])
 
 
 @pytest.mark.parametrize("residual,tol,groups", [("fp64", 1e-9, 0), ("fp32", 1e-6, 0), ("fp64", 1e-9, 3),
