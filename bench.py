@@ -611,6 +611,7 @@ def run_serve(pr, prgen, c, args):
     queries = [(0, int(srcs[q])) if is_ppr[q] else (int(pool_pick[q]), -1) for q in range(n_q)]
     free = [[torch.empty(x.n, dtype=torch.float64, device="cuda") for _ in range(24 if i == 0 else 8)]
             for i, x in enumerate(graphs)]
+    big = 1 + int(np.argmax([x.n for x in pool]))
 
     def make_server():
         srv = pr.Server(c=c, l1_tol=args.tol, residual="fp32", slots=args.serve_slots, sweeps_per_round=4)
@@ -665,8 +666,15 @@ def run_serve(pr, prgen, c, args):
             lock.notify_all()
         th.join()
         span = time.perf_counter() - t_start
+        mem = srv.stats()
+        foot = {"ppr_graph": {w: srv.footprint(gids[0], w) for w in (1, 8, 16)},
+                "largest_pool_graph": {w: srv.footprint(gids[big], w) for w in (1, 8, 16)}}
         srv.close()
-        return done, span
+        memory = {"budget_gb": mem["budget"] / 1e9, "graphs_gb": mem["graph_bytes"] / 1e9,
+                  "peak_gb": mem["peak_bytes"] / 1e9, "memory_waits": mem["memory_waits"],
+                  "narrowed_runs": mem["narrowed_runs"], "rejected": mem["rejected"],
+                  "workspace_bytes_by_width": foot}
+        return done, span, memory
 
     def summary(done, span):
         ok = all(st["status"] == 0 and st["l1_bound"] <= args.tol for _, st in done)
@@ -683,13 +691,13 @@ def run_serve(pr, prgen, c, args):
                              "p99_ms": float(np.percentile(lat[sel], 99))}
         return out
 
-    done, span = serve(queries, gaps)
+    done, span, memory = serve(queries, gaps)
     open_loop = summary(done, span)
-    open_loop.update({"qps_target": args.serve_qps, "queries": n_q})
+    open_loop.update({"qps_target": args.serve_qps, "queries": n_q, "memory": memory})
     log(f"[bench] served open loop: {open_loop}")
 
     k = min(args.serve_compare, n_q)
-    done, span = serve(queries[:k], None)
+    done, span, _ = serve(queries[:k], None)
     saturated = summary(done, span)
     log(f"[bench] served, {k} queries submitted at once: {saturated}")
 

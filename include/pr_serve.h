@@ -15,8 +15,22 @@
  * iterating (continuous batching).  A run ends when its last column retires;
  * an 8-wide run whose queue outgrows its free slots stops admitting so that
  * the next run can be 16 wide.  Engines of different graphs run concurrently
- * on the device.  Admission by memory: a graph is accepted only if its
- * engine's workspaces fit in the server's device-memory budget.
+ * on the device.
+ *
+ * Admission by memory footprint.  The budget covers the registered graphs'
+ * device bytes (CSR, plans and the caches the server adds) and the query
+ * workspaces.  A query runs in its engine's workspace: a column of a 16- or
+ * 8-wide batched run (pr_server_footprint(.., 16 or 8, ..) bytes for the run)
+ * or a single-vector solve (width 1).  Before each run an engine takes the
+ * workspace of the width its queue asks for when the budget has room for it
+ * next to the graphs and the other engines' workspaces; else the widest
+ * narrower one that fits (8, then 1); else its queries wait.  Engines that wait
+ * for memory get it in arrival order: while one waits, idle engines and engines
+ * between runs give their workspace back, and running batched runs stop
+ * admitting new columns so that they end.  A graph is registered only if it and
+ * one single-query workspace fit next to the graphs already registered, so every
+ * query can run eventually; a query fails with PR_ENOMEM only when the device
+ * refuses the allocation with no other workspace left to wait for.
  *
  * Results equal those of pr_ppr / pr_solve_ifp2 on the same graph within the
  * certified tolerance (the rounding order differs).
@@ -42,14 +56,21 @@ typedef struct {
     int32_t batch_min;        /* queue length at which an idle engine batches; >= 1 (1: always batch) */
     int32_t sweeps_per_round; /* sweeps between two admission / retirement points, >= 1 */
     int32_t max_sweeps;       /* per query; 0 -> 100000 (a query reaching it ends with PR_ENOCONV) */
-    int64_t memory_budget;    /* device bytes the engines' workspaces may use; 0 -> 90 % of free memory */
+    int64_t memory_budget;    /* device bytes for the registered graphs plus the query workspaces;
+                                 0 -> 90 % of the device's memory */
 } pr_server_opts;
 
 typedef struct {
     int64_t submitted, completed;
     double p50_ms, p99_ms, mean_ms, max_ms; /* submit-to-completion latency of completed queries */
     double edges_per_second;                /* sum of m over completed queries / (last completion - first submit) */
-    int64_t device_bytes;                   /* engine workspaces */
+    int64_t device_bytes;                   /* graphs + query workspaces held now */
+    int64_t graph_bytes;                    /* registered graphs */
+    int64_t peak_bytes;                     /* highest device_bytes so far (<= budget) */
+    int64_t budget;                         /* the memory budget in force */
+    int64_t memory_waits;                   /* times an engine's queries waited for workspace memory */
+    int64_t narrowed_runs;                  /* runs narrower than the queue asked for, for lack of memory */
+    int64_t rejected;                       /* queries failed with PR_ENOMEM */
 } pr_server_stats;
 
 /* defaults: c 0.85, l1_tol 1e-6, FP32 residuals, 16 slots, batch_min 2, 4 sweeps per round, budget 0 */
@@ -60,11 +81,20 @@ pr_status pr_server_create(const pr_server_opts *o, pr_server **out);
 
 /*
  * Register an uploaded graph; its engine starts immediately.  The graph stays
- * owned by the caller and must outlive the server.  PR_ENOMEM if the engine's
- * workspace does not fit in the remaining budget; PR_EINVAL for a graph uploaded
- * with PR_PEEL.
+ * owned by the caller and must outlive the server.  Registration builds the
+ * graph's batch plans and stop-rule weights (kept on the graph).  PR_ENOMEM if
+ * the graphs registered so far, this one and the largest single-query workspace
+ * exceed the budget; PR_EBUSY while the graph is being tuned; PR_EINVAL for a
+ * graph uploaded with PR_PEEL.
  */
 pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id);
+
+/*
+ * Device bytes of one run's workspace on a registered graph: width 1 is a
+ * single-vector solve (one query), 8 and 16 a batched run of that many query
+ * slots.  PR_EINVAL for an unknown graph id or another width.
+ */
+pr_status pr_server_footprint(pr_server *s, int32_t graph_id, int32_t width, int64_t *bytes);
 
 /*
  * Queue a query.  source = -1: global PageRank; else single-source PPR from that

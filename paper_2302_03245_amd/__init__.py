@@ -30,7 +30,7 @@ PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE, PR_JACOBI, PR_VERIFY, PR_FORCE_LIST = 
 EXPORTED = ["pr_opts_default", "pr_graph_upload", "pr_graph_free", "pr_graph_info", "pr_solve_ifp1",
             "pr_solve_ifp2", "pr_solve_power", "pr_ppr", "pr_last_error", "pr_last_trace",
             "pr_probe_copy", "pr_probe_gather", "pr_probe_scatter", "pr_probe_gather_out_len",
-            "pr_server_opts_default", "pr_server_create", "pr_server_add_graph", "pr_server_submit",
+            "pr_server_opts_default", "pr_server_create", "pr_server_add_graph", "pr_server_footprint", "pr_server_submit",
             "pr_server_wait", "pr_server_get_stats", "pr_server_destroy",
             "pr_set_upload", "pr_set_free", "pr_set_info", "pr_set_solve_ifp2", "pr_set_tune", "pr_graph_tune",
             "pr_state_create", "pr_state_free", "pr_state_read", "pr_solve_ifp2_warm", "pr_state_update",
@@ -74,7 +74,9 @@ class ServerOpts(ctypes.Structure):
 class ServerStats(ctypes.Structure):
     _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64), ("p50_ms", ctypes.c_double),
                 ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
-                ("edges_per_second", ctypes.c_double), ("device_bytes", ctypes.c_int64)]
+                ("edges_per_second", ctypes.c_double), ("device_bytes", ctypes.c_int64),
+                ("graph_bytes", ctypes.c_int64), ("peak_bytes", ctypes.c_int64), ("budget", ctypes.c_int64),
+                ("memory_waits", ctypes.c_int64), ("narrowed_runs", ctypes.c_int64), ("rejected", ctypes.c_int64)]
 
 
 class SetInfo(ctypes.Structure):
@@ -176,6 +178,8 @@ def lib():
     L.pr_server_submit.restype = ctypes.c_int
     L.pr_server_wait.argtypes = [vp, i64, ctypes.c_double, ctypes.POINTER(Stats)]
     L.pr_server_wait.restype = ctypes.c_int
+    L.pr_server_footprint.argtypes = [vp, i32, i32, ctypes.POINTER(ctypes.c_int64)]
+    L.pr_server_footprint.restype = ctypes.c_int
     L.pr_server_get_stats.argtypes = [vp, ctypes.POINTER(ServerStats)]
     L.pr_server_get_stats.restype = ctypes.c_int
     L.pr_server_destroy.argtypes = [vp]
@@ -635,6 +639,15 @@ class Server:
             raise _err(st)
         self._graphs.append(g)
         return gid.value
+
+    def footprint(self, graph_id: int, width: int) -> int:
+        """Device bytes of a run's workspace on a registered graph: width 1 (one query
+        solved alone), 8 or 16 (a batched run of that many query slots)."""
+        b = ctypes.c_int64()
+        st = lib().pr_server_footprint(self._h, graph_id, width, ctypes.byref(b))
+        if st != PR_OK:
+            raise _err(st)
+        return b.value
 
     def submit(self, graph_id: int, source: int, out) -> int:
         """source = -1: global PageRank; out: contiguous torch CUDA float64 tensor of n entries."""

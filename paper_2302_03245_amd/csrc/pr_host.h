@@ -209,6 +209,8 @@ pr_status replan(Graph &G, int32_t tile_k, hipStream_t s);
 template <typename T>
 pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source, const pr_opts &o, double *pi,
                       pr_stats *st, const WarmArgs *warm = nullptr, const ExtWorkspace *ext = nullptr);
+// Builds and caches on G the stop rule's per-vertex error weights for factor c.
+pr_status stop_weights(Graph &G, double c, hipStream_t s);
 // Workspace bytes solve_ifp_t takes for these options (the size an ExtWorkspace must have).
 template <typename T>
 size_t solve_ifp_bytes(const Graph &G, bool ifp2, const double *p, const pr_opts &o, bool warm);

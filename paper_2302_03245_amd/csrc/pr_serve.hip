@@ -1,6 +1,7 @@
 // pr_serve.hip -- query server of include/pr_serve.h: one engine (host thread +
-// HIP stream + batched IFP2 workspace) per resident graph, query slots = columns
-// of the batched solve, continuous admission and retirement between rounds.
+// HIP stream + query workspace) per resident graph, query slots = columns of the
+// batched solve, continuous admission and retirement between rounds, and
+// workspaces taken against the server's memory budget per run.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -20,9 +21,10 @@
 #include <vector>
 
 #include "../../include/pr_serve.h"
-#include "pr_internal.h"
+#include "pr_host.h"
 
 using namespace prk;
+using namespace prk::host;
 
 namespace {
 
@@ -58,7 +60,15 @@ struct pr_server {
     int64_t submitted = 0;
     std::vector<double> lat_ms;
     double edges_done = 0, t_first = -1, t_last = 0;
-    int64_t budget = 0, used = 0;
+    // memory admission (guarded by mu)
+    int64_t budget = 0;
+    int64_t graph_bytes = 0;  // device bytes of the registered graphs
+    int64_t ws_used = 0;      // query workspaces the engines hold
+    int64_t max_single = 0;   // largest single-query workspace of a registered graph
+    int64_t peak = 0;
+    int64_t mem_waits = 0, narrowed = 0, rejected = 0;
+    std::deque<Engine *> mem_queue;  // engines waiting for workspace memory, oldest first
+    std::condition_variable cv_mem;
     std::atomic<bool> stop{false};
 };
 
@@ -72,8 +82,9 @@ struct Engine {
     int B = 16;  // widest batched run
     bool fp32 = true;
     hipStream_t stream = nullptr;
-    char *ws = nullptr;
-    size_t ws_bytes = 0;
+    char *ws = nullptr;    // query workspace, held between runs while no engine waits for memory
+    size_t ws_bytes = 0;   // its size, counted in srv->ws_used
+    bool wide_blocked = false;  // the last 16-wide workspace request found no room
     CtlB *hctl = nullptr;  // pinned
     std::deque<std::shared_ptr<Request>> queue;  // guarded by srv->mu
     std::condition_variable cv_work;
@@ -106,21 +117,24 @@ struct Engine {
         return b;
     }
 
-    // workspace of a single-vector solve (cached on the graph by the solve itself)
-    static size_t footprint_single(const Graph &G, bool fp32) {
-        const size_t sT = fp32 ? 4 : 8;
-        // frontier lists and scatter work lists of list sweeps
-        const size_t wave_cap = (size_t)G.nN + ((size_t)G.mNN + (size_t)G.mND) / kChunkEdges + 1;
-        const size_t lists = 3 * align256((size_t)G.nN * 4) + align256((size_t)G.nN * sT) +
-                             2 * align256(wave_cap * 4) + align256(wave_cap * sT);
-        return align256((size_t)G.n * sT) + align256((size_t)G.nN * sT) + 3 * align256((size_t)G.nN * 8) +
-               align256((size_t)std::max<int32_t>(G.nD, 1) * 8) + 64 * 1024 + 5 * kRedBlocks * 8 + lists;
+    // workspace of a single-vector solve in this server's residual type
+    size_t single_bytes() const {
+        pr_opts o = single_opts();
+        return fp32 ? solve_ifp_bytes<float>(*G, true, nullptr, o, false)
+                    : solve_ifp_bytes<double>(*G, true, nullptr, o, false);
     }
+    size_t width_bytes(int w) const { return w == 1 ? single_bytes() : footprint(*G, w, fp32); }
+    pr_opts single_opts() const;
+    enum class Room { held, none, failed };
+    Room hold_ws(size_t need, std::string *err);
+    void release_ws();
+    void leave_mem_queue();  // caller holds srv->mu
 
     template <typename T>
     void serve();
     template <typename T, int Bw>
     bool run();
+    template <typename T>
     bool run_single();
     bool trivial(const Request &r) const { return r.source >= 0 && G->dangling(r.source); }
     void take_trivial(std::vector<std::shared_ptr<Request>> &out);
@@ -144,6 +158,90 @@ void Engine::finish(const std::shared_ptr<Request> &r, pr_status status, const p
         srv->edges_done += (double)G->m;
         srv->t_last = std::max(srv->t_last, tnow);
     }
+}
+
+pr_opts Engine::single_opts() const {
+    pr_opts o;
+    pr_opts_default(&o);
+    o.c = srv->o.c;
+    o.l1_tol = srv->o.l1_tol;
+    o.stop = PR_STOP_L1;
+    o.residual = srv->o.residual;
+    o.max_sweeps = srv->o.max_sweeps;
+    o.flags = PR_OUT_DEVICE;
+    o.stream = (void *)stream;
+    return o;
+}
+
+void Engine::leave_mem_queue() {
+    auto it = std::find(srv->mem_queue.begin(), srv->mem_queue.end(), this);
+    if (it == srv->mem_queue.end()) return;
+    srv->mem_queue.erase(it);
+    srv->cv_mem.notify_all();
+}
+
+// Give the workspace back (its stream idle first): the memory and its share of the budget.
+void Engine::release_ws() {
+    if (!ws) return;
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(ws);
+    ws = nullptr;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->ws_used -= (int64_t)ws_bytes;
+    ws_bytes = 0;
+    srv->cv_mem.notify_all();
+}
+
+// Make the engine hold a workspace of at least `need` bytes: the one it holds if large enough,
+// else a new one when the budget has room for it next to the registered graphs and the
+// other engines' workspaces -- the engine's widest workspace when there is room for that
+// (later runs of any width reuse it), else exactly `need`.  Engines waiting for memory
+// take it in arrival order: one that does not hold enough gets memory only when no engine
+// waits ahead of it.  Room::failed: the allocation itself failed with no other workspace
+// to wait for (*err).
+Engine::Room Engine::hold_ws(size_t need, std::string *err) {
+    if (ws && ws_bytes >= need) return Room::held;
+    const size_t old = ws_bytes;
+    const size_t widest = std::max(need, std::max(width_bytes(B), single_bytes()));
+    size_t bytes = need;
+    {
+        std::lock_guard<std::mutex> lk(srv->mu);
+        const bool first = srv->mem_queue.empty() || srv->mem_queue.front() == this;
+        const int64_t others = srv->graph_bytes + srv->ws_used - (int64_t)old;
+        if (!first || others + (int64_t)need > srv->budget) return Room::none;
+        if (others + (int64_t)widest <= srv->budget) bytes = widest;
+        srv->ws_used += (int64_t)bytes - (int64_t)old;  // reserved before the memory is taken
+        srv->peak = std::max(srv->peak, srv->graph_bytes + srv->ws_used);
+    }
+    if (ws) {
+        (void)hipStreamSynchronize(stream);
+        (void)hipFree(ws);
+        ws = nullptr;
+    }
+    hipError_t e = hipMalloc((void **)&ws, bytes);
+    if (e != hipSuccess && bytes > need) {  // the device refuses the widest: exactly what is needed
+        (void)hipGetLastError();
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            srv->ws_used -= (int64_t)(bytes - need);
+        }
+        bytes = need;
+        e = hipMalloc((void **)&ws, bytes);
+    }
+    if (e == hipSuccess) {
+        ws_bytes = bytes;
+        return Room::held;
+    }
+    (void)hipGetLastError();
+    ws = nullptr;
+    std::lock_guard<std::mutex> lk(srv->mu);
+    srv->ws_used -= (int64_t)bytes;
+    ws_bytes = 0;
+    srv->cv_mem.notify_all();
+    // memory outside the budget is in use: wait while other workspaces may come back
+    if (srv->ws_used > 0) return Room::none;
+    *err = std::string("query workspace of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e);
+    return Room::failed;
 }
 
 // A single-source query whose source has no out-edges needs no sweep: its
@@ -177,28 +275,80 @@ bool Engine::answer_trivial(std::vector<std::shared_ptr<Request>> &rs, bool sync
     return e == hipSuccess;
 }
 
-// Dispatcher of one engine: single-vector solves or batched runs, by queue length.
+// Dispatcher of one engine: single-vector solves or batched runs, by queue length and by
+// the workspace memory the budget allows: the width the queue asks for, else the widest
+// narrower one that fits, else the queries wait until another engine gives memory back.
 template <typename T>
 void Engine::serve() {
     (void)hipSetDevice(G->device);
     bool ok = true;
     while (ok && !srv->stop.load()) {
         size_t q = 0;
+        bool yield = false;  // another engine waits for memory ahead of this one
         std::vector<std::shared_ptr<Request>> triv;
         {
             std::unique_lock<std::mutex> lk(srv->mu);
-            cv_work.wait_for(lk, std::chrono::milliseconds(50), [&] { return srv->stop.load() || !queue.empty(); });
+            auto waits_ahead = [&] { return !srv->mem_queue.empty() && srv->mem_queue.front() != this; };
+            cv_work.wait_for(lk, std::chrono::milliseconds(50),
+                             [&] { return srv->stop.load() || !queue.empty() || (ws && waits_ahead()); });
             take_trivial(triv);
             q = queue.size();
+            if (q == 0) leave_mem_queue();
+            yield = ws && waits_ahead();
         }
         if (!triv.empty()) ok = answer_trivial(triv, true);
+        if (yield) release_ws();
         if (!ok || q == 0 || srv->stop.load()) continue;
-        if ((int64_t)q < (int64_t)srv->o.batch_min) ok = run_single();
-        else if (B == 16 && q > 8) ok = run<T, 16>();
+        const int want = (int64_t)q < (int64_t)srv->o.batch_min ? 1 : (B == 16 && q > 8 ? 16 : 8);
+        int width = 0;
+        Room room = Room::none;
+        std::string err;
+        for (int w = want; w >= 1; w = w == 8 ? 1 : w / 2) {
+            room = hold_ws(width_bytes(w), &err);
+            if (w == 16) wide_blocked = room != Room::held;
+            if (room == Room::held) {
+                width = w;
+                break;
+            }
+        }
+        if (room == Room::failed) {
+            std::shared_ptr<Request> r;
+            {
+                std::lock_guard<std::mutex> lk(srv->mu);
+                leave_mem_queue();
+                if (!queue.empty()) {
+                    r = queue.front();
+                    queue.pop_front();
+                    ++srv->rejected;
+                }
+            }
+            if (r) finish(r, PR_ENOMEM, nullptr, err);
+            srv->cv_done.notify_all();
+            continue;
+        }
+        if (width == 0) {  // wait for memory (engines ahead in the queue go first)
+            std::unique_lock<std::mutex> lk(srv->mu);
+            if (std::find(srv->mem_queue.begin(), srv->mem_queue.end(), this) == srv->mem_queue.end()) {
+                srv->mem_queue.push_back(this);
+                ++srv->mem_waits;
+                for (auto &e : srv->engines) e->cv_work.notify_all();  // idle holders give memory back
+            }
+            srv->cv_mem.wait_for(lk, std::chrono::milliseconds(20));
+            continue;
+        }
+        {
+            std::lock_guard<std::mutex> lk(srv->mu);
+            leave_mem_queue();
+            if (width < want) ++srv->narrowed;
+        }
+        if (width == 1) ok = run_single<T>();
+        else if (width == 16) ok = run<T, 16>();
         else ok = run<T, 8>();
         srv->cv_done.notify_all();
     }
+    release_ws();
     std::lock_guard<std::mutex> lk(srv->mu);
+    leave_mem_queue();
     for (auto &r : queue) {
         r->done = true;
         r->status = ok ? PR_EINVAL : PR_EDEVICE;
@@ -208,7 +358,8 @@ void Engine::serve() {
     srv->cv_done.notify_all();
 }
 
-// The oldest waiting query solved alone on the engine's stream.
+// The oldest waiting query solved alone on the engine's stream, in the engine's workspace.
+template <typename T>
 bool Engine::run_single() {
     std::shared_ptr<Request> r;
     {
@@ -217,18 +368,16 @@ bool Engine::run_single() {
         r = queue.front();
         queue.pop_front();
     }
-    pr_opts o;
-    pr_opts_default(&o);
-    o.c = srv->o.c;
-    o.l1_tol = srv->o.l1_tol;
-    o.stop = PR_STOP_L1;
-    o.residual = srv->o.residual;
-    o.max_sweeps = srv->o.max_sweeps;
-    o.flags = PR_OUT_DEVICE;
-    o.stream = (void *)stream;
+    const pr_opts o = single_opts();
     pr_stats st{};
-    const int32_t src = r->source;
-    const pr_status ps = src >= 0 ? pr_ppr(hg, &src, 1, &o, r->out, &st) : pr_solve_ifp2(hg, nullptr, &o, r->out, &st);
+    Ctl sctl;  // host copy of the control block
+    ExtWorkspace ext{ws, ws_bytes, &sctl};
+    pr_status ps;
+    try {
+        ps = solve_ifp_t<T>(*G, true, nullptr, r->source, o, r->out, &st, nullptr, &ext);
+    } catch (const std::bad_alloc &) {
+        ps = set_error(PR_ENOMEM, "host allocation");
+    }
     finish(r, ps, ps >= 0 ? &st : nullptr, ps < 0 ? std::string(pr_last_error()) : std::string());
     srv->cv_done.notify_all();
     return ps != PR_EDEVICE;
@@ -249,6 +398,7 @@ bool Engine::run() {
     const int max_sweeps = srv->o.max_sweeps > 0 ? srv->o.max_sweeps : 100000;
     const int slot = Bw == 8 ? 0 : 1;
 
+    if (!ws || ws_bytes < footprint(g, Bw, fp32)) return false;  // the dispatcher holds it first
     char *p = ws;
     auto take = [&](size_t bytes) {
         char *r = p;
@@ -292,7 +442,10 @@ bool Engine::run() {
             take_trivial(triv);
             int free_slots = 0;
             for (int j = 0; j < Bw; ++j) free_slots += slots[j] ? 0 : 1;
-            if (Bw < B && (int)queue.size() > free_slots) draining = true;
+            // stop admitting: to restart 16 wide (when memory allows it), or to give the
+            // workspace back to an engine that waits for memory
+            if (Bw < B && !wide_blocked && (int)queue.size() > free_slots) draining = true;
+            if (!srv->mem_queue.empty()) draining = true;
             for (int j = 0; j < Bw; ++j) {
                 if (!draining && !slots[j] && !queue.empty()) {
                     slots[j] = queue.front();
@@ -442,7 +595,7 @@ pr_status pr_server_create(const pr_server_opts *o, pr_server **out) {
         size_t fr = 0, tot = 0;
         hipError_t e = hipMemGetInfo(&fr, &tot);
         if (e != hipSuccess) return set_error(PR_EDEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(e));
-        sv->budget = (int64_t)(0.9 * (double)fr);
+        sv->budget = (int64_t)(0.9 * (double)tot);
     }
     *out = sv.release();
     return PR_OK;
@@ -454,52 +607,70 @@ pr_status pr_server_add_graph(pr_server *s, const pr_graph *g, int32_t *graph_id
     const Graph &G = g->g;
     if (G.nP > 0) return set_error(PR_EINVAL, "the server needs graphs uploaded without PR_PEEL");
     const bool fp32 = s->o.residual == PR_RES_FP32;
-    const size_t fp = Engine::footprint(G, s->o.slots, fp32) + Engine::footprint_single(G, fp32);
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        if (s->used + (int64_t)fp > s->budget)
-            return set_error(PR_ENOMEM, "graph engine workspace exceeds the server's memory budget");
-        s->used += (int64_t)fp;
-    }
     std::unique_ptr<Engine> eng(new (std::nothrow) Engine());
-    auto undo = [&](pr_status st, const std::string &m) {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->used -= (int64_t)fp;
-        return set_error(st, m);
-    };
-    if (!eng) return undo(PR_ENOMEM, "host allocation");
+    if (!eng) return set_error(PR_ENOMEM, "host allocation");
     eng->srv = s;
     eng->hg = g;
     eng->G = &G;
+    eng->B = s->o.slots;
+    eng->fp32 = fp32;
+    // the graph and one query's workspace must fit next to the graphs already registered
+    // (workspaces held by running engines come and go and are not counted here)
+    auto fits = [&](int64_t gbytes, const char *when) {
+        const int64_t one = (int64_t)eng->single_bytes();
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->graph_bytes + gbytes + std::max(s->max_single, one) > s->budget)
+            return set_error(PR_ENOMEM, std::string("the graph and one query's workspace exceed the server's memory budget") +
+                                            when + " (" + std::to_string(s->graph_bytes + gbytes) + " + " +
+                                            std::to_string(std::max(s->max_single, one)) + " > " +
+                                            std::to_string(s->budget) + " bytes)");
+        return PR_OK;
+    };
+    pr_status ps = fits(G.device_bytes, "");
+    if (ps != PR_OK) return ps;
     {
         Graph &gm = const_cast<Graph &>(G);
         std::lock_guard<std::mutex> lk(gm.ws_mu);
-        if (gm.tuning) return undo(PR_EBUSY, "the graph is being tuned");
+        if (gm.tuning) return set_error(PR_EBUSY, "the graph is being tuned");
         ++gm.users;
         eng->holds_use = true;
     }
-    eng->B = s->o.slots;
-    eng->fp32 = fp32;
     hipError_t e = hipSetDevice(G.device);
     if (e == hipSuccess) e = hipStreamCreateWithFlags(&eng->stream, hipStreamNonBlocking);
-    if (e != hipSuccess) return undo(PR_EDEVICE, std::string("stream: ") + hipGetErrorString(e));
+    if (e != hipSuccess) return set_error(PR_EDEVICE, std::string("stream: ") + hipGetErrorString(e));
+    // batch plans and the stop rule's weights stay on the graph
     for (int bw = 8; bw <= eng->B; bw *= 2) {
-        pr_status ps = batch_plans(const_cast<Graph &>(G), bw, eng->stream);
-        if (ps != PR_OK) return undo(ps, "batch plans");
+        ps = batch_plans(const_cast<Graph &>(G), bw, eng->stream);
+        if (ps != PR_OK) return set_error(ps, "batch plans");
     }
-    e = hipMalloc((void **)&eng->ws, Engine::footprint(G, eng->B, fp32));
-    if (e != hipSuccess) return undo(PR_ENOMEM, std::string("engine workspace: ") + hipGetErrorString(e));
-    eng->ws_bytes = fp;
+    ps = host::stop_weights(const_cast<Graph &>(G), s->o.c, eng->stream);
+    if (ps != PR_OK) return ps;
+    const int64_t gbytes = G.device_bytes;
+    ps = fits(gbytes, " with its batch plans");
+    if (ps != PR_OK) return ps;
     e = hipHostMalloc((void **)&eng->hctl, sizeof(CtlB), hipHostMallocDefault);
-    if (e != hipSuccess) return undo(PR_ENOMEM, "pinned control block");
+    if (e != hipSuccess) return set_error(PR_ENOMEM, "pinned control block");
     Engine *ep = eng.get();
     {
         std::lock_guard<std::mutex> lk(s->mu);
+        s->graph_bytes += gbytes;
+        s->max_single = std::max(s->max_single, (int64_t)ep->single_bytes());
+        s->peak = std::max(s->peak, s->graph_bytes + s->ws_used);
         ep->gid = (int32_t)s->engines.size();
         s->engines.push_back(std::move(eng));
     }
     ep->th = std::thread(ep->fp32 ? &Engine::serve<float> : &Engine::serve<double>, ep);
     *graph_id = ep->gid;
+    return PR_OK;
+}
+
+pr_status pr_server_footprint(pr_server *s, int32_t graph_id, int32_t width, int64_t *bytes) {
+    clear_error();
+    if (!s || !bytes) return set_error(PR_EINVAL, "NULL argument");
+    if (width != 1 && width != 8 && width != 16) return set_error(PR_EINVAL, "width must be 1, 8 or 16");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (graph_id < 0 || graph_id >= (int32_t)s->engines.size()) return set_error(PR_EINVAL, "unknown graph id");
+    *bytes = (int64_t)s->engines[(size_t)graph_id]->width_bytes(width);
     return PR_OK;
 }
 
@@ -551,7 +722,13 @@ pr_status pr_server_get_stats(pr_server *s, pr_server_stats *out) {
     memset(out, 0, sizeof(*out));
     out->submitted = s->submitted;
     out->completed = (int64_t)s->lat_ms.size();
-    out->device_bytes = s->used;
+    out->device_bytes = s->graph_bytes + s->ws_used;
+    out->graph_bytes = s->graph_bytes;
+    out->peak_bytes = s->peak;
+    out->budget = s->budget;
+    out->memory_waits = s->mem_waits;
+    out->narrowed_runs = s->narrowed;
+    out->rejected = s->rejected;
     if (!s->lat_ms.empty()) {
         std::vector<double> v = s->lat_ms;
         std::sort(v.begin(), v.end());
@@ -575,6 +752,7 @@ pr_status pr_server_destroy(pr_server *s) {
     {
         std::lock_guard<std::mutex> lk(s->mu);
         for (auto &e : s->engines) e->cv_work.notify_all();
+        s->cv_mem.notify_all();
     }
     for (auto &e : s->engines)
         if (e->th.joinable()) e->th.join();
