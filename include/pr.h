@@ -99,10 +99,15 @@ typedef enum {
 #define PR_JACOBI 0x40u      /* IFP1 / IFP2: synchronous sweeps even where ordered sweeps apply */
 /* After the solve, check the written result a posteriori in FP64: one application of
    the power-method matrix P'' (Eq. 1) to pi gives r = P'' pi - pi, and
-   stats->l1_verified = ||r||_1 / (1 - c) + |sum(pi) - 1| plus the rounding of the check
-   bounds ||pi - pi_exact||_1 whatever the residual precision (P'' contracts the
-   difference of two vectors of equal sum by c in L1).  Costs about one power-method
-   iteration; under PR_STOP_L1 a verified bound above l1_tol gives PR_ENOCONV. */
+   stats->l1_verified bounds ||pi - pi_exact||_1 whatever the residual precision: the
+   smaller of ||r||_1 / (1 - c) (P'' contracts the difference of two vectors of equal sum
+   by c in L1) and 2 sum_j F_j |r_j| / sum(pi) (F_j: the L1 mass a unit at j adds to
+   (I - cP)^{-1}, dangling vertices absorbing; graphs uploaded without PR_PEEL), each
+   + |sum(pi) - 1| and the rounding of the check.  Costs about one power-method
+   iteration.  IFP1 / IFP2 under PR_STOP_L1 (not warm starts): when the check finds the
+   result short of l1_tol, the solve sweeps on to a target tightened by the check's
+   excess over the stop rule's estimate and checks again (at most 3 times); a verified
+   bound still above l1_tol gives PR_ENOCONV. */
 #define PR_VERIFY 0x80u
 /* IFP1 / IFP2: every sweep scatters from the compacted frontier list (the vertices with
    residual > xi, kept as a list of ids between sweeps); without it a solve uses list

@@ -82,6 +82,8 @@ struct alignas(128) Ctl {
     // a-posteriori check (PR_VERIFY): ||P'' pi - pi||_1, its rounding bound, sum(pi)
     double ver_r, ver_err, ver_sum;
     double ver_rf;        // sum_j f_j |r_j| with f_j the absorbing mass weight of row j (see launch_verify)
+    double ver_beta;      // the second scale of the weighted bound (0: none)
+    double ver_rf2;       // sum_j f_j |r_j| at that scale (infinite without one)
     // list sweeps (compacted frontier): entries of the two frontier lists and of the
     // lane / wave work lists of the scatter, indexed by sweep parity
     uint32_t fcnt[2], lcnt[2], wcnt[2], pad2[2];

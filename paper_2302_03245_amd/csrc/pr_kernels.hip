@@ -1260,41 +1260,74 @@ __global__ void k_final_x_write(const Ctl *ctl, InitArgs a, const double *x, dou
 // pi, one application of the power-method matrix P'' of Eq. 1 gives the residual
 // r = P'' pi - pi; since P'' contracts differences of equal sum by c in L1,
 // ||pi - pi_exact||_1 <= ||r||_1 / (1 - c) + |sum(pi) - 1|, whatever arithmetic
-// produced pi.  A second bound weighs each row instead: with b = c d^T pi +
-// (1 - c) sum(pi) (the jump weight of r), u = pi / b solves (I - cP) u = p - r / b,
-// so u differs from y = (I - cP)^{-1} p (Eq. 4, dangling vertices absorbing) by
-// (I - cP)^{-1} r / b, whose L1 norm is at most sum_j f_j |r_j| / b with f_j the
-// mass that a unit at j adds to y: 1 at a dangling j, and 1 + c delta_j + g_j at
-// a non-dangling one (the stop rule's weights, upper bounds).  Normalising, pi_exact
-// = y / |y| and |u| = sum(pi) / b give ||pi - pi_exact||_1 <= 2 sum_j f_j |r_j| /
-// sum(pi) + |sum(pi) - 1|.  The rounding of the check itself is bounded row by row.
+// produced pi.  A second bound weighs each row instead: for any beta > 0,
+// u = pi / beta solves (I - cP) u = p - r_beta / beta with r_beta = beta p -
+// (I - cP) pi, so u differs from y = (I - cP)^{-1} p (Eq. 4, dangling vertices
+// absorbing) by (I - cP)^{-1} r_beta / beta, whose L1 norm is at most
+// sum_j f_j |r_beta,j| / beta with f_j the mass that a unit at j adds to y: 1 at a
+// dangling j, and 1 + c delta_j + g_j at a non-dangling one (the stop rule's
+// weights, upper bounds).  Normalising, pi_exact = y / |y| and |u| = sum(pi) / beta
+// give ||pi - pi_exact||_1 <= 2 sum_j f_j |r_beta,j| / sum(pi) + |sum(pi) - 1|.  Two
+// betas are tried: b = c d^T pi + (1 - c) sum(pi) (then r_beta = r), and the ratio
+// pi_j / p_j over the vertices without in-edges, where the IFP output is exact
+// (their value is the initial mass, which fixes the scale of the unnormalised
+// vector; then r_beta is the residual mass the push has not yet delivered, and the
+// bound equals the stop rule's).  The rounding of the check itself is bounded row by
+// row.
 // ------------------------------------------------------------------------
-__global__ void k_verify_load(int64_t n, const int32_t *perm, const double *out, double *x, double *acc) {
-    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock) {
-        x[i] = out[perm[i]];
+// x = the output in the internal order, acc = 0; partials of sum pi_j and sum p_j over
+// the vertices without in-edges
+__global__ __launch_bounds__(kBlock) void k_verify_load(InitArgs a, const uint32_t *in_ptr, const double *out,
+                                                        double *x, double *acc, double *part) {
+    double xs = 0.0, ps = 0.0;
+    for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
+        const double v = out[a.perm[i]];
+        x[i] = v;
         acc[i] = 0.0;
+        if (in_ptr[i + 1] == in_ptr[i]) {
+            xs += v;
+            ps += p_of(a, i);
+        }
     }
+    __shared__ double sd[kBlock / W];
+    xs = block_sum(xs, sd);
+    ps = block_sum(ps, sd);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = xs;
+        part[gridDim.x + blockIdx.x] = ps;
+    }
+}
+
+// the second beta of the weighted bound (0: none, no vertex without in-edges carries p)
+__global__ __launch_bounds__(kBlock) void k_verify_beta(Ctl *ctl, int nb, const double *part) {
+    __shared__ double sd[2 * (kBlock / W)];
+    double v[2];
+    reduce_partials_n(part, nb, v, sd);
+    if (threadIdx.x != 0) return;
+    ctl->ver_beta = v[1] > 0.0 ? v[0] / v[1] : 0.0;
 }
 
 // per row j: r_j = |acc_j + b p_j - x_j| with acc_j = sum over in-edges of c x_u / deg(u);
 // err_j bounds the FP64 rounding of computing it: the k_j-term sum of acc_j (any order:
 // k_j - 1 additions), the quotients c x_u / deg(u) (2 each), b (depth_b additions of
-// its reduction) and the final add, subtract and absolute value.  With weights g (of
-// the first nN rows), rf accumulates f_j r_j; f_j is widened by 1e-12 relative over
-// the rounding of forming it.
+// its reduction) and the final add, subtract and absolute value (with the larger of the
+// two betas, which covers the second residual too).  With weights g (of the first nN
+// rows), rf and rf2 accumulate f_j r_j for both betas; f_j is widened by 1e-12
+// relative over the rounding of forming it.
 __global__ __launch_bounds__(kBlock) void k_verify_residual(const Ctl *ctl, InitArgs a, const uint32_t *in_ptr,
                                                             const double *x, const double *acc, double depth_b,
                                                             double c, const float *g, int32_t nN, const int32_t *deg,
                                                             const uint32_t *rp_nn, double *part) {
     const double b = ctl->pw_b;
-    double r = 0.0, err = 0.0, xs = 0.0, rf = 0.0;
+    const double b2 = ctl->ver_beta;
+    const double bm = fmax(b, b2);
+    double r = 0.0, err = 0.0, xs = 0.0, rf = 0.0, rf2 = 0.0;
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * kBlock) {
         const double k = (double)(in_ptr[i + 1] - in_ptr[i]);
-        const double bp = b * p_of(a, i);
-        const double v = acc[i] + bp;
-        const double ri = fabs(v - x[i]);
+        const double pv = p_of(a, i);
+        const double ri = fabs(acc[i] + b * pv - x[i]);
         r += ri;
-        err += (k + 4.0 + depth_b) * (acc[i] + bp + x[i]);
+        err += (k + 4.0 + depth_b) * (acc[i] + bm * pv + x[i]);
         xs += x[i];
         if (g) {
             double f = 1.0;
@@ -1304,6 +1337,7 @@ __global__ __launch_bounds__(kBlock) void k_verify_residual(const Ctl *ctl, Init
                 f = (1.0 + c * delta + (double)g[i]) * (1.0 + 1e-12);
             }
             rf += f * ri;
+            rf2 += f * fabs(acc[i] + b2 * pv - x[i]);
         }
     }
     __shared__ double sd[kBlock / W];
@@ -1311,23 +1345,26 @@ __global__ __launch_bounds__(kBlock) void k_verify_residual(const Ctl *ctl, Init
     err = block_sum(err, sd);
     xs = block_sum(xs, sd);
     rf = block_sum(rf, sd);
+    rf2 = block_sum(rf2, sd);
     if (threadIdx.x == 0) {
         part[blockIdx.x] = r;
         part[gridDim.x + blockIdx.x] = err;
         part[2 * gridDim.x + blockIdx.x] = xs;
         part[3 * gridDim.x + blockIdx.x] = rf;
+        part[4 * gridDim.x + blockIdx.x] = rf2;
     }
 }
 
 __global__ __launch_bounds__(kBlock) void k_verify_decide(Ctl *ctl, int nb, const double *part) {
-    __shared__ double sd[4 * (kBlock / W)];
-    double v[4];
+    __shared__ double sd[5 * (kBlock / W)];
+    double v[5];
     reduce_partials_n(part, nb, v, sd);
     if (threadIdx.x != 0) return;
     ctl->ver_r = v[0];
     ctl->ver_err = v[1];
     ctl->ver_sum = v[2];
     ctl->ver_rf = v[3];
+    ctl->ver_rf2 = ctl->ver_beta > 0.0 ? v[4] : INFINITY;
 }
 
 // ------------------------------------------------------------------------
@@ -1693,7 +1730,8 @@ hipError_t launch_verify(Ctl *vctl, const InitArgs &a, const double *out, double
     // depth of a reduction over n entries as the sums below run it: a thread's strided
     // run, the workgroup tree, and the partials summed by one thread per lane
     *depth = (double)((a.n + (int64_t)nb * kBlock - 1) / ((int64_t)nb * kBlock)) + 8.0 + (double)nb;
-    PRK_GGL(k_verify_load, dim3(grid_for(a.n, 4, 8192)), dim3(kBlock), 0, s, a.n, a.perm, out, x, acc);
+    PRK_GGL(k_verify_load, dim3(nb), dim3(kBlock), 0, s, a, in_ptr, out, x, acc, part);
+    PRK_GGL(k_verify_beta, dim3(1), dim3(kBlock), 0, s, vctl, nb, (const double *)part);
     PRK_GGL(k_power_prescale<double>, dim3(nb), dim3(kBlock), 0, s, 0, (const Ctl *)vctl, a, x, acc, y, deg, c,
             part);
     PRK_GGL(k_decide_power, dim3(1), dim3(kBlock), 0, s, 0, vctl, nb, (const double *)part, c, 0.0);

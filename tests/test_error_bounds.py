@@ -8,9 +8,12 @@ from their definitions and compared with dense solves (oracle.dense, numpy.linal
   that decrease to F.
 * Folded IFP2 (Algorithm 3, phase 2 on the final pibar + h): the unnormalised error
   is sum_N g_i h_i exactly, g_i = F_i - 1 - c delta_i.
-* For any pi > 0 with r = c P pi + b p - pi, b = c d^T pi + (1 - c) sum(pi):
-  ||pi - pi*||_1 <= 2 sum_j F_j |r_j| / sum(pi) + |sum(pi) - 1|, and
-  ||pi - pi*||_1 <= ||r||_1 / (1 - c) + |sum(pi) - 1| (P'' contracts by c).
+* For any pi > 0 and any beta > 0, with r_beta = beta p - (I - cP) pi:
+  ||pi - pi*||_1 <= 2 sum_j F_j |r_beta,j| / sum(pi) + |sum(pi) - 1|; the library
+  tries beta = b = c d^T pi + (1 - c) sum(pi) (r_b = P'' pi - pi) and beta = the ratio
+  pi_j / p_j over the vertices without in-edges, for which an IFP output's bound
+  equals the stop rule's 2 sum_N g_i h_i / S_x.  Also
+  ||pi - pi*||_1 <= ||r_b||_1 / (1 - c) + |sum(pi) - 1| (P'' contracts by c).
 """
 import numpy as np
 import pytest
@@ -55,12 +58,21 @@ def _weights_iterated(g, c, iters):
     return out
 
 
-def _bounds(g, c, pi, p, F):
+def _beta2(g, pi, p):
+    """pi_j / p_j summed over the vertices without in-edges (None if they carry no p)."""
+    noin = np.bincount(np.asarray(g.col, dtype=np.int64), minlength=g.n) == 0
+    ps = p[noin].sum()
+    return pi[noin].sum() / ps if ps > 0 else None
+
+
+def _bounds(g, c, pi, p, F, beta=None):
+    """(weighted bound at beta (default b), contraction bound)."""
     P, deg, _, _ = _dense(g)
     b = c * pi[deg == 0].sum() + (1 - c) * pi.sum()
     r = np.abs(c * (P @ pi) + b * p - pi)
+    rb = r if beta is None else np.abs(c * (P @ pi) + beta * p - pi)
     tail = abs(pi.sum() - 1.0)
-    return 2.0 * float((F * r).sum()) / pi.sum() + tail, r.sum() / (1 - c) + tail
+    return 2.0 * float((F * rb).sum()) / pi.sum() + tail, r.sum() / (1 - c) + tail
 
 
 @pytest.mark.parametrize("gi", range(len(GRAPHS)))
@@ -111,6 +123,31 @@ def _perturbations(g, y, rng):
 
 
 @pytest.mark.parametrize("gi", range(len(GRAPHS)))
+@pytest.mark.parametrize("passes", [2, 5])
+def test_second_scale_recovers_the_stop_rule(gi, passes):
+    """On a folded IFP2 output (oracle state after some passes, normalised), the weighted
+    bound at beta = pi_j / p_j over the vertices without in-edges is exactly the stop
+    rule's 2 sum_N g_i h_i / S_x (at beta = b it differs either way, so the check takes
+    the smaller of the two)."""
+    g = GRAPHS[gi]
+    P, deg, nd, delta = _dense(g)
+    F = np.linalg.inv(np.eye(g.n) - C * P).sum(axis=0)
+    if not np.any(np.bincount(g.col, minlength=g.n) == 0):
+        pytest.skip("every vertex has an in-edge")
+    r = oracle.ifp2(g, C, xi=1e-300, max_passes=passes)
+    h0 = np.ones(g.n)
+    z = np.zeros(g.n)
+    z[nd] = r["pibar"][nd] + r["h"][nd]
+    z[~nd] = h0[~nd] + C * (P @ z)[~nd]
+    pi = z / z.sum()
+    p = np.full(g.n, 1.0 / g.n)
+    gw = np.where(nd, F - 1.0 - C * delta, 0.0)
+    stop = 2.0 * float((gw * r["h"]).sum()) / z.sum()
+    w2, _ = _bounds(g, C, pi, p, F, _beta2(g, pi, p))
+    assert abs(w2 - stop) <= 1e-9 * max(stop, 1e-300) + 1e-15, (w2, stop)
+
+
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
 def test_verify_bounds_hold(gi):
     g = GRAPHS[gi]
     _, _, nd, _ = _dense(g)
@@ -127,6 +164,10 @@ def test_verify_bounds_hold(gi):
             d = np.abs(pi - star).sum()
             w, plain = _bounds(g, C, pi, p, F)
             assert d <= w * (1 + 1e-9) and d <= plain * (1 + 1e-9), (ppr, d, w, plain)
+            for beta in (_beta2(g, pi, p), 0.5 * pi.sum(), 3.0):  # any positive scale
+                if beta:
+                    w2, _ = _bounds(g, C, pi, p, F, beta)
+                    assert d <= w2 * (1 + 1e-9), (ppr, beta, d, w2)
 
 
 def test_verify_weighted_bound_needs_its_factor_two():

@@ -349,18 +349,25 @@ def _row_weights(g, c, iters=16):
 
 
 def _verified_numpy(g, pi, c, p, f):
-    """The smaller of the check's two bounds (without its rounding terms):
-    ||r||_1 / (1 - c) and 2 sum_j f_j |r_j| / sum(pi), each + |sum(pi) - 1|."""
+    """The smallest of the check's bounds (without its rounding terms): ||r||_1 / (1 - c)
+    with r = P'' pi - pi, and 2 sum_j f_j |beta p_j - ((I - cP) pi)_j| / sum(pi) at beta =
+    c d^T pi + (1 - c) sum(pi) and at beta = the ratio pi_j / p_j summed over the vertices
+    without in-edges; each + |sum(pi) - 1|."""
     import scipy.sparse as sp
     deg = np.diff(g.row_ptr)
     src = np.repeat(np.arange(g.n, dtype=np.int64), deg)
     inv = np.zeros(g.n)
     inv[deg > 0] = 1.0 / deg[deg > 0]
     P = sp.csr_matrix((inv[src], (g.col, src)), shape=(g.n, g.n))
+    cp = c * (P @ pi)
     b = c * pi[deg == 0].sum() + (1 - c) * pi.sum()
-    r = np.abs(c * (P @ pi) + b * p - pi)
-    tail = abs(pi.sum() - 1)
-    return min(r.sum() / (1 - c), 2 * float((f * r).sum()) / pi.sum()) + tail
+    r = np.abs(cp + b * p - pi)
+    best = min(r.sum() / (1 - c), 2 * float((f * r).sum()) / pi.sum())
+    noin = np.bincount(np.asarray(g.col, dtype=np.int64), minlength=g.n) == 0
+    if p[noin].sum() > 0:
+        beta = pi[noin].sum() / p[noin].sum()
+        best = min(best, 2 * float((f * np.abs(cp + beta * p - pi)).sum()) / pi.sum())
+    return best + abs(pi.sum() - 1)
 
 
 @pytest.mark.parametrize("residual", ["fp64", "fp32"])
