@@ -72,6 +72,9 @@ typedef enum {
    launches of an ordered sweep cost more than the sweeps it saves) */
 #define PR_GROUPS(k) (((uint32_t)(k) & 0xFu) << 12)
 #define PR_GROUPS_MASK 0xF000u
+/* ordered sweeps: each group's gather walks every target row instead of only the rows
+   with an edge from that group (the default; pr_graph_tune times both and keeps one) */
+#define PR_GROUP_ALL_ROWS 0x40000u
 /* keep every in-edge list in fill order instead of sorting it by source (sorted lists
    make gathers touch fewer cache lines and their rounding order deterministic) */
 #define PR_UNSORTED_IN 0x10000u
@@ -213,7 +216,9 @@ pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out);
 typedef struct {
     int32_t candidates;               /* entries filled below */
     int32_t tile_shift[PR_TUNE_MAX];  /* sweep tiles of 256 << s rows + edges per workgroup */
-    int32_t ordered[PR_TUNE_MAX];     /* 1: ordered sweeps over the vertex groups; 0: synchronous */
+    int32_t ordered[PR_TUNE_MAX];     /* 0: synchronous sweeps; ordered sweeps over the vertex groups
+                                         with each group's gather over every row (1) or over only
+                                         the rows that group reaches (2; graph sets: 1 only) */
     double ms[PR_TUNE_MAX];           /* fastest of the timed solves, device milliseconds */
     int32_t sweeps[PR_TUNE_MAX];
     int32_t chosen;                   /* index of the candidate the graph keeps */
@@ -226,8 +231,10 @@ typedef struct {
  * size s in {2, 3, 4} with synchronous sweeps and, when the graph has vertex groups,
  * with ordered sweeps (the split of a sweep's work between per-vertex reserve
  * passes and per-edge gathers), `reps` solves each after one warm-up (reps <= 0:
- * 2), and keeps the fastest: later solves of every kind use its tile size, and
- * global IFP2 solves use ordered sweeps only if it chose them.  Results do not
+ * 2); when ordered sweeps win, the other form of the group gathers (every row, or
+ * only the rows each group reaches) is timed at the same tile size.  It keeps the
+ * fastest: later solves of every kind use its tile size, and global IFP2 solves use
+ * ordered sweeps, with that form of gather, only if it chose them.  Results do not
  * change beyond rounding order.  No other call may use the graph meanwhile.
  * rep may be NULL.  PR_EINVAL on bad options or forced scatter modes.
  */

@@ -22,7 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libpr.so")
 PR_OK, PR_ENOCONV, PR_EINVAL, PR_ENOMEM, PR_EDEVICE, PR_EBUSY = 0, 1, -1, -2, -3, -4
 PR_RES_FP64, PR_RES_FP32 = 0, 1
 PR_STOP_XI, PR_STOP_L1 = 0, 1
-PR_INPUT_DEVICE, PR_DEDUPE, PR_PEEL = 0x1, 0x2, 0x20000
+PR_INPUT_DEVICE, PR_DEDUPE, PR_PEEL, PR_GROUP_ALL_ROWS = 0x1, 0x2, 0x20000, 0x40000
 PR_P_DEVICE, PR_OUT_DEVICE, PR_IFP2_LITERAL = 0x1, 0x2, 0x4
 PR_FORCE_PUSH, PR_FORCE_PULL, PR_PROFILE, PR_JACOBI, PR_VERIFY, PR_FORCE_LIST = 0x8, 0x10, 0x20, 0x40, 0x80, 0x100
 
@@ -260,13 +260,14 @@ class Graph:
 
 
 def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0, groups: int = 0, sort_in: bool = True,
-           peel: bool = False) -> Graph:
+           peel: bool = False, group_rows: bool = True) -> Graph:
     """Copy a CSR graph (host numpy or device torch tensors) to the device.
 
     `tile_shift` s in {2, 3, 4} sets 256 << s rows + edges per sweep tile (0: default);
     `groups` k in 1..15 sets the vertex groups of ordered sweeps (0: 4 on graphs with at least
     2^24 edges between non-dangling vertices, else none; 1: none); `peel` takes weakly
-    dangling vertices out of IFP2's sweeps (PR_PEEL: IFP2 and PPR only)."""
+    dangling vertices out of IFP2's sweeps (PR_PEEL: IFP2 and PPR only); `group_rows`
+    False makes each group's gather walk every row (PR_GROUP_ALL_ROWS)."""
     rp_keep, rp_ptr, rp_dev = _ptr_any(row_ptr, np.int64, "int64")
     col_keep, col_ptr, col_dev = _ptr_any(col, np.int32, "int32")
     if rp_dev != col_dev:
@@ -274,7 +275,8 @@ def upload(row_ptr, col, dedupe: bool = False, tile_shift: int = 0, groups: int 
     n = (rp_keep.shape[0] if not _is_torch(rp_keep) else rp_keep.numel()) - 1
     m = col_keep.shape[0] if not _is_torch(col_keep) else col_keep.numel()
     flags = (PR_INPUT_DEVICE if rp_dev else 0) | (PR_DEDUPE if dedupe else 0) | ((tile_shift & 7) << 8) | \
-        ((groups & 15) << 12) | (0 if sort_in else 0x10000) | (PR_PEEL if peel else 0)
+        ((groups & 15) << 12) | (0 if sort_in else 0x10000) | (PR_PEEL if peel else 0) | \
+        (0 if group_rows else PR_GROUP_ALL_ROWS)
     h = ctypes.c_void_p()
     st = lib().pr_graph_upload(int(n), int(m), rp_ptr, col_ptr if m else None, flags, ctypes.byref(h))
     if st != PR_OK:
@@ -293,8 +295,8 @@ def tune(g: Graph, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", reps=2) -> di
     if st != PR_OK:
         raise _err(st)
     k = r.candidates
-    cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "ms": r.ms[i], "sweeps": r.sweeps[i]}
-             for i in range(k)]
+    cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "group_rows": r.ordered[i] == 2,
+              "ms": r.ms[i], "sweeps": r.sweeps[i]} for i in range(k)]
     return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds}
 
 

@@ -53,6 +53,8 @@ struct MPPlan {
     int32_t blocks = 0;
     int32_t ipb = 0;               // items per tile (kBlock x items per thread)
     uint2 *plan = nullptr;         // device, blocks + 1 entries (owned by the graph)
+    const int32_t *rid = nullptr;  // device, R target-row ids when the plan keeps only the rows
+                                   // with an edge in it (a vertex group's gather); null: rows 0 .. R-1
     int64_t edges() const { return (int64_t)items - R; }
 };
 
@@ -230,6 +232,9 @@ struct Graph {
     bool prefer_ordered = true;                     // set by the autotuner
     std::vector<std::vector<MPPlan>> grp_pull;      // [epoch][group], rows [0, nN)
     std::vector<std::vector<MPPlan>> grp_pull_all;  // [epoch][group], rows [0, n)
+    // the same gathers over only the rows each group reaches (MPPlan::rid)
+    std::vector<std::vector<MPPlan>> grp_pull_rows, grp_pull_all_rows;
+    bool group_rows = true;                         // ordered sweeps use those (set by the autotuner)
     int64_t device_bytes = 0;
     double seconds_upload = 0, seconds_split = 0;
     hipStream_t stream = nullptr;
@@ -266,6 +271,12 @@ hipError_t launch_check_cols(const int32_t *col, int64_t m, int64_t n, unsigned 
 hipError_t launch_degree_class(const int64_t *rp64, int64_t n, uint32_t *isN, hipStream_t s);
 hipError_t launch_indegree(const int32_t *col, int64_t m, uint32_t *indeg, hipStream_t s);
 hipError_t launch_scan_u32(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *tmp, hipStream_t s);
+// the rows r < R of a gather plan that have an edge (cnt[r] > 0): flag[r] = 1 or 0; after an
+// exclusive scan pos of flag, rid[pos[r]] = r and rp[pos[r]] = off[r] for those rows, and
+// rp[pos[R]] = off[R] (off: the plan's R + 1 edge offsets)
+hipError_t launch_row_flags(int32_t R, const uint32_t *cnt, uint32_t *flag, hipStream_t s);
+hipError_t launch_row_fill(int32_t R, const uint32_t *cnt, const uint32_t *pos, const uint32_t *off, int32_t *rid,
+                           uint32_t *rp, hipStream_t s);
 size_t scan_tmp_elems(int64_t n);
 hipError_t launch_relabel(const uint32_t *isN, const uint32_t *rankN, int64_t n, int32_t nN, int32_t *newid,
                           int32_t *perm, hipStream_t s);

@@ -276,6 +276,24 @@ __global__ void k_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in
     }
 }
 
+// rows with an edge in a vertex group's in-lists (see launch_row_flags)
+__global__ void k_row_flags(int32_t R, const uint32_t *cnt, uint32_t *flag) {
+    for (int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x; r < R; r += (int64_t)gridDim.x * kBlock)
+        flag[r] = cnt[r] > 0 ? 1u : 0u;
+}
+
+__global__ void k_row_fill(int32_t R, const uint32_t *cnt, const uint32_t *pos, const uint32_t *off, int32_t *rid,
+                           uint32_t *rp) {
+    for (int64_t r = blockIdx.x * (int64_t)kBlock + threadIdx.x; r <= R; r += (int64_t)gridDim.x * kBlock) {
+        if (r == R) {
+            rp[pos[R]] = off[R];
+        } else if (cnt[r] > 0) {
+            rid[pos[r]] = (int32_t)r;
+            rp[pos[r]] = off[r];
+        }
+    }
+}
+
 // merge-path split points: plan[b] = (rows finished before diagonal d, edge at d)
 __global__ void k_plan(const uint32_t *rp, int32_t R, uint32_t items, int32_t ipb, int32_t blocks, uint2 *plan) {
     const uint32_t rp0 = rp[0];
@@ -978,11 +996,13 @@ __global__ __launch_bounds__(kBlock) void k_push(int t, const Ctl *ctl, int chec
 // carried in FP64.  Every row's sum meets in an LDS accumulator (a plain store
 // for a row one thread holds whole, a hardware LDS add for pieces of rows
 // shared by threads), and the tile writes its rows out together at the end, so
-// a hub row costs one global atomic per tile instead of one per thread.
+// a hub row costs one global atomic per tile instead of one per thread.  With rid,
+// the plan's rows are only those with an edge in it and rid names their targets.
 template <typename WT, typename OT, int K>
 __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int check_mode, const uint32_t *rp,
                                                  int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
-                                                 int32_t ntiles, const WT *w, OT *out, TileSkip skip) {
+                                                 int32_t ntiles, const WT *w, OT *out, const int32_t *rid,
+                                                 TileSkip skip) {
     constexpr int IPB = K * kBlock;
     static_assert(IPB < 65536, "row ends are kept as 16-bit offsets within the tile");
     // pieces of rows shared by threads meet in FP64, or in FP32 when the output is FP32
@@ -1085,7 +1105,7 @@ __global__ __launch_bounds__(kBlock) void k_pull(int t, const Ctl *ctl, int chec
         for (int32_t k = threadIdx.x; k < nr; k += kBlock) {
             double v = (double)s_acc[k];
             if (v == 0.0) continue;
-            OT *o = out + (i0 + k);
+            OT *o = out + (rid ? rid[i0 + k] : i0 + k);  // a group plan's rows map to target ids
             if (k == 0 || k == nr - 1) atomicAdd(o, (OT)v);
             else *o = (OT)((double)*o + v);
         }
@@ -1530,6 +1550,14 @@ hipError_t launch_live_fill(int32_t R, const uint32_t *in_ptr, const int32_t *in
     PRK_LAUNCH(k_live_fill, grid_for((int64_t)R * W, 1, 16384), R, in_ptr, in_src, depth, t0, slo, shi, grp, q,
                out_ptr, out_src);
 }
+hipError_t launch_row_flags(int32_t R, const uint32_t *cnt, uint32_t *flag, hipStream_t s) {
+    if (R <= 0) return hipSuccess;
+    PRK_LAUNCH(k_row_flags, grid_for(R, 4, 8192), R, cnt, flag);
+}
+hipError_t launch_row_fill(int32_t R, const uint32_t *cnt, const uint32_t *pos, const uint32_t *off, int32_t *rid,
+                           uint32_t *rp, hipStream_t s) {
+    PRK_LAUNCH(k_row_fill, grid_for((int64_t)R + 1, 4, 8192), R, cnt, pos, off, rid, rp);
+}
 hipError_t launch_plan(MPPlan &p, hipStream_t s) {
     p.blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
     PRK_LAUNCH(k_plan, grid_for((int64_t)p.blocks + 1, 1, 4096), p.rp, p.R, p.items, p.ipb, p.blocks, p.plan);
@@ -1611,7 +1639,7 @@ hipError_t launch_pull_k(int t, const Ctl *ctl, const MPPlan &p, const WT *w, OT
     auto kern = &k_pull<WT, OT, K>;
     static const int grid = resident_grid(kern);
     return launch_timed(kern, std::min(p.blocks, grid), s, ev, t, ctl, check_mode, p.rp, p.R, p.idx,
-                        (const uint2 *)p.plan, p.items, p.blocks, w, out, skip);
+                        (const uint2 *)p.plan, p.items, p.blocks, w, out, p.rid, skip);
 }
 
 template <typename WT, typename OT>

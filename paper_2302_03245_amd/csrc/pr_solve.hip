@@ -385,13 +385,15 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                             HIPCHK(launch_reserve_range<T>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg,
                                                            G.rp_nn, c, xi, ifp2 ? 1 : 0, gb.nb[q],
                                                            part + (size_t)5 * kGroupBlocks * q, s));
-                            const MPPlan &pl = ifp2 ? G.grp_pull[e][q] : G.grp_pull_all[e][q];
+                            const MPPlan &pl = G.group_rows ? (ifp2 ? G.grp_pull_rows[e][q] : G.grp_pull_all_rows[e][q])
+                                                            : (ifp2 ? G.grp_pull[e][q] : G.grp_pull_all[e][q]);
                             sweep_edges += (unsigned long long)pl.edges();
                             // the method's own bytes: every gathered in-edge (source id + weight), and
                             // each target row once per sweep (offset + residual update), shared
-                            // evenly by the group gathers that each walk all the rows
+                            // evenly by the group gathers
+                            const double rows = ifp2 ? (double)nN : (double)n;
                             const KernelEvents ev = timer.next(
-                                t, 1, (double)pl.edges() * (4.0 + sT) + (double)pl.R * (4.0 + 2.0 * sT) / (double)ngr);
+                                t, 1, (double)pl.edges() * (4.0 + sT) + rows * (4.0 + 2.0 * sT) / (double)ngr);
                             HIPCHK(launch_pull<T, T>(t, ctl, pl, w, h, 0, s, TileSkip(), ev));
                         }
                         HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, gb, part,
@@ -883,38 +885,57 @@ pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *re
     pr_opts op = o;
     op.flags = (o.flags & ~(PR_OUT_DEVICE | PR_PROFILE | PR_JACOBI)) | PR_OUT_DEVICE;
     const bool can_order = G.grp.size() > 2 && !G.grp_pull.empty();
+    const bool rows0 = G.group_rows;
     double best = INFINITY;
     int best_i = 0;
+    // times the current schedule and records it as a candidate (ordered: 0 synchronous,
+    // 1 ordered over whole-row group plans, 2 ordered over the rows each group reaches)
+    auto candidate = [&](int32_t shift) -> pr_status {
+        double ms = INFINITY;
+        int32_t sweeps = 0;
+        for (int32_t q = 0; q <= reps; ++q) {
+            pr_stats st;
+            pr_status ps = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, -1, op, out, &st)
+                                                      : solve_ifp_t<double>(G, true, nullptr, -1, op, out, &st);
+            if (ps < 0) return ps;
+            if (q > 0) ms = std::min(ms, st.seconds_solve * 1e3);
+            sweeps = st.sweeps;
+        }
+        const int i = r.candidates++;
+        r.tile_shift[i] = shift;
+        r.ordered[i] = G.prefer_ordered ? (G.group_rows ? 2 : 1) : 0;
+        r.ms[i] = ms;
+        r.sweeps[i] = sweeps;
+        if (ms < best) {
+            best = ms;
+            best_i = i;
+        }
+        return PR_OK;
+    };
     for (int32_t shift = 2; shift <= 4; ++shift) {
         pr_status ps = replan(G, 1 << shift, G.stream);
         if (ps != PR_OK) return ps;
         for (int ord = 0; ord <= (can_order ? 1 : 0); ++ord) {
             G.prefer_ordered = ord == 1;
-            double ms = INFINITY;
-            int32_t sweeps = 0;
-            for (int32_t q = 0; q <= reps; ++q) {
-                pr_stats st;
-                ps = op.residual == PR_RES_FP32 ? solve_ifp_t<float>(G, true, nullptr, -1, op, out, &st)
-                                                : solve_ifp_t<double>(G, true, nullptr, -1, op, out, &st);
-                if (ps < 0) return ps;
-                if (q > 0) ms = std::min(ms, st.seconds_solve * 1e3);
-                sweeps = st.sweeps;
-            }
-            const int i = r.candidates++;
-            r.tile_shift[i] = shift;
-            r.ordered[i] = ord;
-            r.ms[i] = ms;
-            r.sweeps[i] = sweeps;
-            if (ms < best) {
-                best = ms;
-                best_i = i;
-            }
+            ps = candidate(shift);
+            if (ps != PR_OK) return ps;
         }
+    }
+    // ordered sweeps won: the other form of the group plans at the same tile size
+    if (r.ordered[best_i] != 0) {
+        const int32_t shift = r.tile_shift[best_i];
+        pr_status ps = replan(G, 1 << shift, G.stream);
+        if (ps != PR_OK) return ps;
+        G.prefer_ordered = true;
+        G.group_rows = !rows0;
+        ps = candidate(shift);
+        if (ps != PR_OK) return ps;
     }
     r.chosen = best_i;
     pr_status ps = replan(G, 1 << r.tile_shift[best_i], G.stream);
     if (ps != PR_OK) return ps;
-    G.prefer_ordered = r.ordered[best_i] == 1;
+    G.prefer_ordered = r.ordered[best_i] != 0;
+    G.group_rows = r.ordered[best_i] == 0 ? rows0 : r.ordered[best_i] == 2;
     r.seconds = (double)clock_now_ns() * 1e-9 - t_start;
     if (rep) *rep = r;
     return PR_OK;

@@ -615,6 +615,38 @@ def test_equation_residual_and_bounds(pr):
     assert np.all(pi >= (1 - C) / g.n * (1 - 1e-6))
 
 
+@pytest.mark.parametrize("groups", [2, 4, 15])
+def test_group_gathers_over_reached_rows(pr, groups):
+    """Ordered sweeps whose group gathers walk only the rows each group reaches (the
+    default) and every row (PR_GROUP_ALL_ROWS) take the same vertices: same sweeps and
+    pushes, results equal up to rounding order, both at the oracle; the autotuner times
+    both forms when ordered sweeps win."""
+    for g in (prgen.random_digraph(70001, 420000, seed=3, dangling_frac=0.15, unref_frac=0.1),
+              prgen.workload_dag(n_layers=12, layer_size=3000, zmax=200, target_edges=300_000, back_frac=0.005,
+                                 seed=2)):
+        ref, _, _ = oracle.power(g, C, tol=1e-13)
+        dr = pr.upload(g.row_ptr, g.col, groups=groups)
+        da = pr.upload(g.row_ptr, g.col, groups=groups, group_rows=False)
+        for method in (pr.ifp2, pr.ifp1):
+            pr_, sr = method(dr, c=C, xi=1e-13)
+            pa, sa = method(da, c=C, xi=1e-13)
+            _say(f"group rows {groups} {method.__name__} n {g.n}: sweeps {sr['sweeps']} / {sa['sweeps']}")
+            assert sr["status"] == 0 and sa["status"] == 0
+            assert sr["sweeps"] == sa["sweeps"] and sr["vertex_pushes"] == sa["vertex_pushes"]
+            assert l1(pr_, pa) <= 1e-13 and l1(pr_, ref) <= 1e-9
+            for residual, tol in (("fp32", 1e-6), ("fp64", 1e-10)):
+                po, so = method(dr, c=C, l1_tol=tol, residual=residual)
+                assert so["status"] == 0 and so["l1_bound"] <= tol and l1(po, ref) <= tol
+        rep = pr.tune(da, c=C, l1_tol=1e-6, residual="fp32", reps=1)
+        forms = {(cand["ordered"], cand["group_rows"]) for cand in rep["candidates"]}
+        if rep["chosen"]["ordered"]:
+            assert {(True, True), (True, False)} <= forms, rep
+        pt, stt = pr.ifp2(da, c=C, l1_tol=1e-6, residual="fp32")
+        assert stt["status"] == 0 and l1(pt, ref) <= 1e-6
+        dr.free()
+        da.free()
+
+
 @pytest.mark.parametrize("groups", [1, 2, 4, 8, 15])
 def test_ordered_sweeps(pr, groups):
     """Global IFP2 with ordered sweeps (the vertex groups take their residuals one after
@@ -671,7 +703,13 @@ def test_autotune_keeps_results(pr):
         rep = pr.tune(dg, c=C, l1_tol=1e-6, residual="fp32", reps=1)
         _say(f"tune n={g.n}: {rep}")
         cands = rep["candidates"]
-        assert len(cands) == (3 if groups == 0 else 6)   # small graphs get no groups by default
+        # small graphs get no groups by default; when ordered sweeps win among the first six,
+        # the other form of the group gathers is timed too
+        if groups == 0:
+            assert len(cands) == 3
+        else:
+            first = min(cands[:6], key=lambda x: x["ms"])
+            assert len(cands) == (7 if first["ordered"] else 6), rep
         assert sorted({x["tile_shift"] for x in cands}) == [2, 3, 4]
         assert rep["chosen"]["ms"] == min(x["ms"] for x in cands)
         info = dg.info()
