@@ -121,6 +121,10 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--mode", default=None, choices=[None, "push", "pull"])
     ap.add_argument("--tile-shift", type=int, default=0, help="sweep tile = 256 << s items (s in 2..4; 0 default)")
+    ap.add_argument("--groups", type=int, default=0,
+                    help="vertex groups of ordered sweeps at upload (0: the library's default)")
+    ap.add_argument("--group-all-rows", action="store_true",
+                    help="group gathers over every row (to reproduce a tuned schedule with --no-tune)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--probes", action="store_true", help="also run the copy / gather / scatter probes")
     ap.add_argument("--ppr", type=int, default=16,
@@ -167,7 +171,8 @@ def main():
         wl_name = "layered DAG: 2^23 vertices in 64 layers, Zipf(2.0) out-degrees capped at 10^4, 80M forward + 2% back edges, seed 0"
         wl_key = "dag23"
     log(f"[bench] n={g.n} m={g.m} generated in {time.perf_counter() - t0:.1f}s")
-    dg = pr.upload(g.row_ptr, g.col, tile_shift=args.tile_shift)
+    dg = pr.upload(g.row_ptr, g.col, tile_shift=args.tile_shift, groups=args.groups,
+                   group_rows=not args.group_all_rows)
     log(f"[bench] uploaded: {dg.info()}")
     tuning = None
     if not args.no_tune and args.mode is None and args.tile_shift == 0:

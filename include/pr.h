@@ -212,10 +212,11 @@ pr_status pr_graph_free(pr_graph *g);
 pr_status pr_graph_info(const pr_graph *g, pr_graph_info_t *out);
 
 /* Outcome of pr_graph_tune: every candidate schedule that was timed. */
-#define PR_TUNE_MAX 8
+#define PR_TUNE_MAX 16
 typedef struct {
     int32_t candidates;               /* entries filled below */
     int32_t tile_shift[PR_TUNE_MAX];  /* sweep tiles of 256 << s rows + edges per workgroup */
+    int32_t groups[PR_TUNE_MAX];      /* vertex groups of ordered sweeps (1 for synchronous sweeps) */
     int32_t ordered[PR_TUNE_MAX];     /* 0: synchronous sweeps; ordered sweeps over the vertex groups
                                          with each group's gather over every row (1) or over only
                                          the rows that group reaches (2; graph sets: 1 only) */
@@ -231,11 +232,14 @@ typedef struct {
  * size s in {2, 3, 4} with synchronous sweeps and, when the graph has vertex groups,
  * with ordered sweeps (the split of a sweep's work between per-vertex reserve
  * passes and per-edge gathers), `reps` solves each after one warm-up (reps <= 0:
- * 2); when ordered sweeps win, the other form of the group gathers (every row, or
- * only the rows each group reaches) is timed at the same tile size.  It keeps the
- * fastest: later solves of every kind use its tile size, and global IFP2 solves use
- * ordered sweeps, with that form of gather, only if it chose them.  Results do not
- * change beyond rounding order.  No other call may use the graph meanwhile.
+ * 2); when the graph has vertex groups, the other form of the group gathers (every row,
+ * or only the rows each group reaches) is timed at the tile size of the fastest ordered
+ * candidate, and then 3, 4, 6 and 8 vertex groups in both forms (the graph's group lists
+ * are rebuilt for each).  It
+ * keeps the fastest: later solves of every kind use its tile size, and global IFP2
+ * solves use ordered sweeps, with that group count and form of gather, only if it chose
+ * them.  Results do not change beyond rounding order.  No other call may use the graph
+ * meanwhile.
  * rep may be NULL.  PR_EINVAL on bad options or forced scatter modes.
  */
 pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_report *rep);

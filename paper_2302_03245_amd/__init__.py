@@ -96,9 +96,9 @@ class GraphInfo(ctypes.Structure):
 
 
 class TuneReport(ctypes.Structure):
-    _fields_ = [("candidates", ctypes.c_int32), ("tile_shift", ctypes.c_int32 * 8), ("ordered", ctypes.c_int32 * 8),
-                ("ms", ctypes.c_double * 8), ("sweeps", ctypes.c_int32 * 8), ("chosen", ctypes.c_int32),
-                ("seconds", ctypes.c_double)]
+    _fields_ = [("candidates", ctypes.c_int32), ("tile_shift", ctypes.c_int32 * 16), ("groups", ctypes.c_int32 * 16),
+                ("ordered", ctypes.c_int32 * 16), ("ms", ctypes.c_double * 16), ("sweeps", ctypes.c_int32 * 16),
+                ("chosen", ctypes.c_int32), ("seconds", ctypes.c_double)]
 
 
 _lib = None
@@ -296,7 +296,7 @@ def tune(g: Graph, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", reps=2) -> di
         raise _err(st)
     k = r.candidates
     cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "group_rows": r.ordered[i] == 2,
-              "ms": r.ms[i], "sweeps": r.sweeps[i]} for i in range(k)]
+              "groups": r.groups[i], "ms": r.ms[i], "sweeps": r.sweeps[i]} for i in range(k)]
     return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds}
 
 
@@ -470,8 +470,8 @@ def set_tune(gs: GraphSet, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", reps=
                            ctypes.byref(r))
     if st != PR_OK:
         raise _err(st)
-    cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "ms": r.ms[i], "sweeps": r.sweeps[i]}
-             for i in range(r.candidates)]
+    cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "groups": r.groups[i], "ms": r.ms[i],
+              "sweeps": r.sweeps[i]} for i in range(r.candidates)]
     return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds}
 
 

@@ -204,6 +204,9 @@ hipError_t replan_plan(Graph &G, MPPlan &p, int32_t tile_k, hipStream_t s);
 // Every single-vector merge-path plan of the graph rebuilt for tiles of kBlock * tile_k
 // items (the batched kernels keep their own plans).
 pr_status replan(Graph &G, int32_t tile_k, hipStream_t s);
+// The vertex groups of ordered sweeps rebuilt for k groups (k <= 1: none), with their
+// whole-row and reached-row gather plans at the graph's current tile size.
+pr_status build_groups(Graph &G, int32_t k, hipStream_t s);
 
 // ---- solves (pr_solve.hip)
 template <typename T>

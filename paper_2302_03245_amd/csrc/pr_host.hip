@@ -151,6 +151,7 @@ pr_status pr_graph_free(pr_graph *g) {
     (void)hipSetDevice(g->g.device);
     if (g->g.stream) (void)hipStreamSynchronize(g->g.stream);
     for (void *p : g->g.allocs) (void)hipFree(p);
+    for (void *p : g->g.grp_allocs) (void)hipFree(p);
     if (g->g.ws_mem) (void)hipFree(g->g.ws_mem);
     if (g->g.ws_hctl) (void)hipHostFree(g->g.ws_hctl);
     if (g->g.stream) (void)hipStreamDestroy(g->g.stream);

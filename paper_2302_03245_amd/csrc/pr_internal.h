@@ -240,6 +240,8 @@ struct Graph {
     hipStream_t stream = nullptr;
     int device = 0;
     std::vector<void *> allocs;
+    std::vector<void *> grp_allocs;  // the vertex groups' lists and plans (rebuilt by the autotuner)
+    int64_t grp_bytes = 0;
     // cached solve workspace
     std::mutex ws_mu;
     bool ws_busy = false;

@@ -374,6 +374,7 @@ pr_status set_tune_impl(pr_graph_set &S, const double *cg, const pr_opts &o, int
             }
             const int i = r.candidates++;
             r.tile_shift[i] = shift;
+            r.groups[i] = ord ? S.ngr : 1;
             r.ordered[i] = ord;
             r.ms[i] = ms;
             r.sweeps[i] = sweeps;

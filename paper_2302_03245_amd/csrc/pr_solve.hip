@@ -901,8 +901,10 @@ pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *re
             if (q > 0) ms = std::min(ms, st.seconds_solve * 1e3);
             sweeps = st.sweeps;
         }
+        if (r.candidates >= PR_TUNE_MAX) return PR_OK;
         const int i = r.candidates++;
         r.tile_shift[i] = shift;
+        r.groups[i] = G.prefer_ordered ? (int32_t)G.grp.size() - 1 : 1;
         r.ordered[i] = G.prefer_ordered ? (G.group_rows ? 2 : 1) : 0;
         r.ms[i] = ms;
         r.sweeps[i] = sweeps;
@@ -921,19 +923,43 @@ pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *re
             if (ps != PR_OK) return ps;
         }
     }
-    // ordered sweeps won: the other form of the group plans at the same tile size
-    if (r.ordered[best_i] != 0) {
-        const int32_t shift = r.tile_shift[best_i];
+    // at the tile size of the fastest ordered candidate: the other form of the group plans,
+    // then other group counts in both forms (the best count grows with a sweep's work: more
+    // groups pass more mass on within a sweep but add launches and row work)
+    const int32_t k0 = can_order ? (int32_t)G.grp.size() - 1 : 1;
+    int32_t k_built = k0;
+    int best_ord = -1;
+    for (int i = 0; i < r.candidates; ++i)
+        if (r.ordered[i] != 0 && (best_ord < 0 || r.ms[i] < r.ms[best_ord])) best_ord = i;
+    if (best_ord >= 0) {
+        const int32_t shift = r.tile_shift[best_ord];
         pr_status ps = replan(G, 1 << shift, G.stream);
         if (ps != PR_OK) return ps;
         G.prefer_ordered = true;
         G.group_rows = !rows0;
         ps = candidate(shift);
         if (ps != PR_OK) return ps;
+        for (int32_t k : {3, 4, 6, 8}) {
+            if (k == k0) continue;
+            ps = build_groups(G, k, G.stream);
+            if (ps != PR_OK) return ps;
+            k_built = k;
+            if ((int32_t)G.grp.size() - 1 != k) continue;  // too few vertices for k groups
+            for (int rows = 1; rows >= 0; --rows) {
+                G.group_rows = rows == 1;
+                ps = candidate(shift);
+                if (ps != PR_OK) return ps;
+            }
+        }
     }
     r.chosen = best_i;
     pr_status ps = replan(G, 1 << r.tile_shift[best_i], G.stream);
     if (ps != PR_OK) return ps;
+    const int32_t k_best = r.ordered[best_i] != 0 ? r.groups[best_i] : k0;
+    if (k_best != k_built) {
+        ps = build_groups(G, k_best, G.stream);
+        if (ps != PR_OK) return ps;
+    }
     G.prefer_ordered = r.ordered[best_i] != 0;
     G.group_rows = r.ordered[best_i] == 0 ? rows0 : r.ordered[best_i] == 2;
     r.seconds = (double)clock_now_ns() * 1e-9 - t_start;

@@ -440,78 +440,13 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
         }
     }
 
-    // Ordered sweeps (not for graph sets): source groups of equal N -> N out-edges in
-    // the degree order, and for every epoch the in-lists of the N targets split by group.
+    // Ordered sweeps (not for graph sets): vertex groups and their gather plans
     const int32_t ngroups_req = (flags & PR_GROUPS_MASK) ? (int32_t)((flags & PR_GROUPS_MASK) >> 12)
                                                          : (G.mNN >= ((int64_t)1 << 24) ? 4 : 1);
-    if (!seg_of && G.nN > 0 && G.mNN > 0 && ngroups_req > 1) {
-        std::vector<uint32_t> h_rpnn((size_t)G.nN + 1);
-        HIPCHK(hipMemcpyAsync(h_rpnn.data(), G.rp_nn, sizeof(uint32_t) * ((size_t)G.nN + 1), hipMemcpyDeviceToHost,
-                              s));
-        HIPCHK(hipStreamSynchronize(s));
-        G.grp.push_back(0);
-        for (int32_t q = 1; q < ngroups_req; ++q) {
-            const uint32_t target = (uint32_t)((double)G.mNN * q / ngroups_req);
-            const int32_t b = (int32_t)(std::lower_bound(h_rpnn.begin(), h_rpnn.end(), target) - h_rpnn.begin());
-            if (b > G.grp.back() && b < G.nN) G.grp.push_back(b);
-        }
-        G.grp.push_back(G.nN);
-        G.group_rows = !(flags & PR_GROUP_ALL_ROWS);
-        uint32_t *d_gc, *d_flag, *d_pos;
-        HIPCHK(tmp.alloc(&d_gc, (size_t)n + 1));
-        HIPCHK(tmp.alloc(&d_flag, (size_t)n + 1));
-        HIPCHK(tmp.alloc(&d_pos, (size_t)n + 1));
-        // A group's gather over only the rows with an edge from the group (about 60 % of the
-        // non-dangling rows each on R-MAT, 70 % on the layered DAG): rid names their targets
-        // and rp their edges in the group's in-lists (off: the offsets over all R rows).
-        auto make_group_plan = [&](MPPlan &p, const uint32_t *off, const int32_t *idx, int32_t R,
-                                   int64_t edges) -> hipError_t {
-            hipError_t e = launch_row_flags(R, d_gc, d_flag, s);
-            if (e == hipSuccess) e = launch_scan_u32(d_flag, d_pos, R, d_scan, s);
-            uint32_t kept = 0;
-            if (e == hipSuccess) e = hipMemcpyAsync(&kept, d_pos + R, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
-            if (e == hipSuccess) e = hipStreamSynchronize(s);
-            if (e != hipSuccess) return e;
-            int32_t *rid = nullptr;
-            uint32_t *rpc = nullptr;
-            e = galloc(&rid, (size_t)kept);
-            if (e == hipSuccess) e = galloc(&rpc, (size_t)kept + 1);
-            if (e == hipSuccess) e = launch_row_fill(R, d_gc, d_pos, off, rid, rpc, s);
-            if (e == hipSuccess) e = make_plan(p, rpc, idx, (int32_t)kept, edges);
-            p.rid = rid;
-            return e;
-        };
-        for (size_t e = 0; e < G.epochs.size(); ++e) {
-            std::vector<MPPlan> plans, plans_all, plans_rows, plans_all_rows;
-            for (size_t q = 0; q + 1 < G.grp.size(); ++q) {
-                uint32_t *gp;
-                int32_t *gs;
-                HIPCHK(galloc(&gp, (size_t)n + 1));
-                HIPCHK(launch_live_count((int32_t)n, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
-                                         G.grp[q + 1], d_gc, s));
-                HIPCHK(launch_scan_u32(d_gc, gp, n, d_scan, s));
-                uint32_t ge[2] = {0, 0};  // edges into the non-dangling rows, into all rows
-                HIPCHK(hipMemcpyAsync(&ge[0], gp + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipMemcpyAsync(&ge[1], gp + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
-                HIPCHK(hipStreamSynchronize(s));
-                HIPCHK(galloc(&gs, (size_t)ge[1]));
-                HIPCHK(launch_live_fill((int32_t)n, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
-                                        G.grp[q + 1], gp, gs, s));
-                MPPlan pl, pla, plr, plar;
-                HIPCHK(make_plan(pl, gp, gs, G.nN, ge[0]));
-                HIPCHK(make_plan(pla, gp, gs, (int32_t)n, ge[1]));
-                HIPCHK(make_group_plan(plr, gp, gs, G.nN, ge[0]));
-                HIPCHK(make_group_plan(plar, gp, gs, (int32_t)n, ge[1]));
-                plans.push_back(pl);
-                plans_all.push_back(pla);
-                plans_rows.push_back(plr);
-                plans_all_rows.push_back(plar);
-            }
-            G.grp_pull.push_back(plans);
-            G.grp_pull_all.push_back(plans_all);
-            G.grp_pull_rows.push_back(plans_rows);
-            G.grp_pull_all_rows.push_back(plans_all_rows);
-        }
+    G.group_rows = !(flags & PR_GROUP_ALL_ROWS);
+    if (!seg_of) {
+        pr_status gs = build_groups(G, ngroups_req, s);
+        if (gs != PR_OK) return gs;
     }
 
     unsigned long long h_zero = 0;
@@ -527,6 +462,137 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
 }
 
 
+// Vertex groups of ordered sweeps: the non-dangling vertices split into k groups of equal
+// N -> N out-edge counts in the degree order, and for every depth epoch the in-lists of the
+// targets split by group, both as whole-row gather plans and as plans over only the rows
+// each group reaches.  Replaces the groups the graph had (their memory is freed; k <= 1
+// leaves none); the plans take the graph's current tile size.
+pr_status build_groups(Graph &G, int32_t k, hipStream_t s) {
+    HIPCHK(hipStreamSynchronize(s));
+    for (void *p : G.grp_allocs) (void)hipFree(p);
+    G.grp_allocs.clear();
+    G.device_bytes -= G.grp_bytes;
+    G.grp_bytes = 0;
+    G.grp.clear();
+    G.grp_pull.clear();
+    G.grp_pull_all.clear();
+    G.grp_pull_rows.clear();
+    G.grp_pull_all_rows.clear();
+    const int64_t n = G.n;
+    if (k <= 1 || G.nN == 0 || G.mNN == 0) return PR_OK;
+    // a failed build leaves no groups (the graph then sweeps synchronously)
+    struct Undo {
+        Graph &G;
+        bool keep = false;
+        ~Undo() {
+            if (keep) return;
+            G.grp.clear();
+            G.grp_pull.clear();
+            G.grp_pull_all.clear();
+            G.grp_pull_rows.clear();
+            G.grp_pull_all_rows.clear();
+        }
+    } undo{G};
+    auto galloc = [&](auto **p, size_t count) -> hipError_t {
+        using T = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
+        *p = nullptr;
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(T);
+        hipError_t e = hipMalloc((void **)p, bytes);
+        if (e == hipSuccess) {
+            G.grp_allocs.push_back((void *)*p);
+            G.grp_bytes += (int64_t)bytes;
+            G.device_bytes += (int64_t)bytes;
+        }
+        return e;
+    };
+    auto make_plan = [&](MPPlan &p, const uint32_t *rpp, const int32_t *idx, int32_t R, int64_t edges) -> hipError_t {
+        p.rp = rpp;
+        p.idx = idx;
+        p.R = R;
+        p.items = (uint32_t)(R + edges);
+        p.ipb = kBlock * G.tile_k;
+        const int32_t blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
+        hipError_t e = galloc(&p.plan, (size_t)blocks + 1);
+        if (e != hipSuccess) return e;
+        if (R == 0) {
+            p.blocks = 0;
+            return hipSuccess;
+        }
+        return launch_plan(p, s);
+    };
+    DevBufs tmp;
+    uint32_t *d_scan;
+    HIPCHK(tmp.alloc(&d_scan, scan_tmp_elems(n + 1)));
+    std::vector<uint32_t> h_rpnn((size_t)G.nN + 1);
+    HIPCHK(hipMemcpyAsync(h_rpnn.data(), G.rp_nn, sizeof(uint32_t) * ((size_t)G.nN + 1), hipMemcpyDeviceToHost,
+                          s));
+    HIPCHK(hipStreamSynchronize(s));
+    G.grp.push_back(0);
+    for (int32_t q = 1; q < k; ++q) {
+        const uint32_t target = (uint32_t)((double)G.mNN * q / k);
+        const int32_t b = (int32_t)(std::lower_bound(h_rpnn.begin(), h_rpnn.end(), target) - h_rpnn.begin());
+        if (b > G.grp.back() && b < G.nN) G.grp.push_back(b);
+    }
+    G.grp.push_back(G.nN);
+    uint32_t *d_gc, *d_flag, *d_pos;
+    HIPCHK(tmp.alloc(&d_gc, (size_t)n + 1));
+    HIPCHK(tmp.alloc(&d_flag, (size_t)n + 1));
+    HIPCHK(tmp.alloc(&d_pos, (size_t)n + 1));
+    // A group's gather over only the rows with an edge from the group (about 60 % of the
+    // non-dangling rows each on R-MAT, 70 % on the layered DAG): rid names their targets
+    // and rp their edges in the group's in-lists (off: the offsets over all R rows).
+    auto make_group_plan = [&](MPPlan &p, const uint32_t *off, const int32_t *idx, int32_t R,
+                               int64_t edges) -> hipError_t {
+        hipError_t e = launch_row_flags(R, d_gc, d_flag, s);
+        if (e == hipSuccess) e = launch_scan_u32(d_flag, d_pos, R, d_scan, s);
+        uint32_t kept = 0;
+        if (e == hipSuccess) e = hipMemcpyAsync(&kept, d_pos + R, sizeof(uint32_t), hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return e;
+        int32_t *rid = nullptr;
+        uint32_t *rpc = nullptr;
+        e = galloc(&rid, (size_t)kept);
+        if (e == hipSuccess) e = galloc(&rpc, (size_t)kept + 1);
+        if (e == hipSuccess) e = launch_row_fill(R, d_gc, d_pos, off, rid, rpc, s);
+        if (e == hipSuccess) e = make_plan(p, rpc, idx, (int32_t)kept, edges);
+        p.rid = rid;
+        return e;
+    };
+    for (size_t e = 0; e < G.epochs.size(); ++e) {
+        std::vector<MPPlan> plans, plans_all, plans_rows, plans_all_rows;
+        for (size_t q = 0; q + 1 < G.grp.size(); ++q) {
+            uint32_t *gp;
+            int32_t *gs;
+            HIPCHK(galloc(&gp, (size_t)n + 1));
+            HIPCHK(launch_live_count((int32_t)n, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
+                                     G.grp[q + 1], d_gc, s));
+            HIPCHK(launch_scan_u32(d_gc, gp, n, d_scan, s));
+            uint32_t ge[2] = {0, 0};  // edges into the non-dangling rows, into all rows
+            HIPCHK(hipMemcpyAsync(&ge[0], gp + G.nN, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipMemcpyAsync(&ge[1], gp + n, sizeof(uint32_t), hipMemcpyDeviceToHost, s));
+            HIPCHK(hipStreamSynchronize(s));
+            HIPCHK(galloc(&gs, (size_t)ge[1]));
+            HIPCHK(launch_live_fill((int32_t)n, G.in_ptr, G.in_src, G.depth, G.epochs[e].t_start, G.grp[q],
+                                    G.grp[q + 1], gp, gs, s));
+            MPPlan pl, pla, plr, plar;
+            HIPCHK(make_plan(pl, gp, gs, G.nN, ge[0]));
+            HIPCHK(make_plan(pla, gp, gs, (int32_t)n, ge[1]));
+            HIPCHK(make_group_plan(plr, gp, gs, G.nN, ge[0]));
+            HIPCHK(make_group_plan(plar, gp, gs, (int32_t)n, ge[1]));
+            plans.push_back(pl);
+            plans_all.push_back(pla);
+            plans_rows.push_back(plr);
+            plans_all_rows.push_back(plar);
+        }
+        G.grp_pull.push_back(plans);
+        G.grp_pull_all.push_back(plans_all);
+        G.grp_pull_rows.push_back(plans_rows);
+        G.grp_pull_all_rows.push_back(plans_all_rows);
+    }
+    undo.keep = true;
+    return PR_OK;
+}
+
 hipError_t replan_plan(Graph &G, MPPlan &p, int32_t tile_k, hipStream_t s) {
     const int32_t ipb = kBlock * tile_k;
     if (p.ipb == ipb) return hipSuccess;
@@ -534,14 +600,26 @@ hipError_t replan_plan(Graph &G, MPPlan &p, int32_t tile_k, hipStream_t s) {
     uint2 *np = nullptr;
     hipError_t e = hipMalloc((void **)&np, sizeof(uint2) * ((size_t)std::max(blocks, 0) + 1));
     if (e != hipSuccess) return e;
+    // the plan array belongs to the graph's own list or to its vertex groups' list
+    std::vector<void *> *owner = &G.allocs;
     auto it = std::find(G.allocs.begin(), G.allocs.end(), (void *)p.plan);
-    if (it != G.allocs.end()) {
-        G.allocs.erase(it);
+    if (it == G.allocs.end()) {
+        auto jt = std::find(G.grp_allocs.begin(), G.grp_allocs.end(), (void *)p.plan);
+        if (jt != G.grp_allocs.end()) {
+            owner = &G.grp_allocs;
+            it = jt;
+        }
+    }
+    const bool grp = owner == &G.grp_allocs;
+    if (it != owner->end()) {
+        owner->erase(it);
         G.device_bytes -= (int64_t)sizeof(uint2) * ((int64_t)p.blocks + 1);
+        if (grp) G.grp_bytes -= (int64_t)sizeof(uint2) * ((int64_t)p.blocks + 1);
     }
     (void)hipFree(p.plan);
-    G.allocs.push_back((void *)np);
+    owner->push_back((void *)np);
     G.device_bytes += (int64_t)sizeof(uint2) * ((int64_t)blocks + 1);
+    if (grp) G.grp_bytes += (int64_t)sizeof(uint2) * ((int64_t)blocks + 1);
     p.plan = np;
     p.ipb = ipb;
     if (p.R == 0) {

@@ -703,18 +703,26 @@ def test_autotune_keeps_results(pr):
         rep = pr.tune(dg, c=C, l1_tol=1e-6, residual="fp32", reps=1)
         _say(f"tune n={g.n}: {rep}")
         cands = rep["candidates"]
-        # small graphs get no groups by default; when ordered sweeps win among the first six,
-        # the other form of the group gathers is timed too
+        # small graphs get no groups by default; with groups, the other form of the group
+        # gathers and then 3, 6 and 8 groups in both forms are timed at the tile size of the
+        # fastest ordered candidate among the first six
         if groups == 0:
             assert len(cands) == 3
         else:
-            first = min(cands[:6], key=lambda x: x["ms"])
-            assert len(cands) == (7 if first["ordered"] else 6), rep
+            first = min((x for x in cands[:6] if x["ordered"]), key=lambda x: x["ms"])
+            extra = cands[6:]
+            assert 1 <= len(extra) <= 7, rep
+            assert all(x["tile_shift"] == first["tile_shift"] and x["ordered"] for x in extra), rep
+            assert {x["groups"] for x in extra} <= {3, 4, 6, 8}, rep
+            assert {(x["groups"], x["group_rows"]) for x in cands if x["ordered"]} >= {(4, True), (4, False)}
+        assert all(x["groups"] == 1 for x in cands if not x["ordered"])
         assert sorted({x["tile_shift"] for x in cands}) == [2, 3, 4]
         assert rep["chosen"]["ms"] == min(x["ms"] for x in cands)
         info = dg.info()
         assert info["tile_items"] == 256 << rep["chosen"]["tile_shift"]
         assert info["ordered"] == int(rep["chosen"]["ordered"])
+        if rep["chosen"]["ordered"]:
+            assert info["groups"] == rep["chosen"]["groups"]
         for method in ("ifp1", "ifp2"):
             for mode in (None, "push", "pull", "list"):
                 pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
