@@ -36,6 +36,11 @@ struct GroupBlocks {
     int32_t stride;
     int32_t nb[kMaxGroups];
 };
+// the vertex groups of ordered sweeps as id ranges: group q ends before end[q]
+struct GroupEnds {
+    int32_t ng;
+    int32_t end[kMaxGroups];
+};
 constexpr int32_t kDepthInf = 0x7fffffff;  // unreferenced depth of vertices on or below a cycle
 constexpr int kMaxEpochs = 8;     // compacted in-edge lists kept per graph
 constexpr int kMPK = 8;           // default merge-path items (rows + edges) per thread (4, 8 or 16)
@@ -256,7 +261,12 @@ struct Graph {
         double c;
         float *g, *q;
         double seconds;  // time taken to build them (charged as preprocessing)
+        // q restricted to the out-neighbours in the vertex's own group or an earlier one,
+        // for the vertex groups of version qle_version (see launch_amp_qle)
+        float *qle = nullptr;
+        int64_t qle_version = -1;
     };
+    int64_t grp_version = 0;  // bumped whenever the vertex groups are rebuilt
     std::mutex amp_mu;
     std::vector<Amp> amp;
     std::vector<uint64_t> dangling_bits;  // host bitmap over original ids: no out-edges
@@ -330,15 +340,18 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
                           int stop_l1, double tol, unsigned long long pull_edges_thr, int force,
                           unsigned long long pull_edges, double *part, hipStream_t s);
 // ordered sweeps: reserve of the non-dangling range [lo, hi) into nbg workgroup
-// partials (5 * nbg doubles at part); after all groups, k_sum_h + k_decide_gs
+// partials (5 * nbg doubles at part), the residual left behind weighted by ew.g and the
+// pushed mass by ew.q; after all groups, k_decide_gs (bookkeep: S_N from those sums, with
+// ew.q the reach-restricted weights of launch_amp_qle; else from a k_sum_h pass)
 template <typename T>
 hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
                                 const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2, int nbg,
-                                double *part, hipStream_t s);
+                                ErrWeights ew, double *part, hipStream_t s);
 template <typename T>
 hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, const GroupBlocks &gb,
                             const double *part, double *part_s, double c, const float *g, double kb, int stop_l1,
-                            double tol, unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s);
+                            double tol, unsigned long long pull_thr, unsigned long long pull_edges, int bookkeep,
+                            hipStream_t s);
 template <typename T>
 hipError_t launch_push(int t, const Ctl *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s,
                        TileSkip skip = TileSkip(), KernelEvents ev = KernelEvents());
@@ -371,6 +384,11 @@ hipError_t launch_zero_f64(double *p, int64_t count, hipStream_t s);
 // error weights of IFP2's stop rule (ErrWeights) for damping c: iterations of the
 // future-mass recursion from its upper bound 1 / (1 - c) over the N -> N out-edges
 // (plan push_nn), each an upper bound; f and acc: nN doubles of scratch
+// qle[u] = (sum of g over u's non-dangling out-neighbours in u's vertex group or an earlier
+// one) / deg(u), rounded up: the weight of mass u pushes in an ordered sweep that is still
+// residual when the sweep ends (a later group takes the rest within the sweep)
+hipError_t launch_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_nn, const int32_t *deg,
+                          const float *g, const GroupEnds &ge, float *qle, hipStream_t s);
 hipError_t launch_amp_weights(int32_t nN, const MPPlan &push_nn, const int32_t *deg, const uint32_t *rp_nn,
                               double c, int iters, double *f, double *acc, float *g, float *q, hipStream_t s);
 // kernel launches of the calling thread so far (counted by the launchers)

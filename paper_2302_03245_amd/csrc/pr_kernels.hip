@@ -510,18 +510,22 @@ __global__ __launch_bounds__(kBlock) void k_sum_h(int t, const Ctl *ctl, int32_t
 __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr, int ng, GroupBlocks gb,
                                                       const double *part, int nbs, const double *part_s, double c,
                                                       double kb, int stop_l1, double tol,
-                                                      unsigned long long pull_thr, unsigned long long pull_edges) {
+                                                      unsigned long long pull_thr, unsigned long long pull_edges,
+                                                      int bookkeep) {
     if (t > ctl->stop_after) return;
     // a group has at most kGroupRounds * kBlock reserve workgroups (and k_sum_h at
     // most as many): every partial of a group, or of S_N, is loaded before any is added
     constexpr int kGroupRounds = 4;
     static_assert(kGroupBlocks <= kGroupRounds * kBlock && kRedBlocks <= kGroupRounds * kBlock, "partials");
     __shared__ double sd[4 * (kBlock / W)];
+    // bookkeep: S_N from the reserves' own sums, each group's residual left behind (part 0)
+    // plus c times its pushed mass weighted by the part that stays residual to the end of
+    // the sweep (part 1); else from k_sum_h's direct sum (part_s)
     double a_sx = 0.0, a_cd = 0.0, a_ed = 0.0, sn = 0.0;
     for (int g = 0; g < ng; ++g) {
         const double *pg = part + (size_t)g * 5 * gb.stride;
         const int nb = gb.nb[g];
-        double x[kGroupRounds][3];
+        double x[kGroupRounds][5];
 #pragma unroll
         for (int r = 0; r < kGroupRounds; ++r) {
             const int b = threadIdx.x + r * kBlock;
@@ -529,6 +533,8 @@ __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr
             x[r][0] = in ? pg[2 * nb + b] : 0.0;
             x[r][1] = in ? pg[3 * nb + b] : 0.0;
             x[r][2] = in ? pg[4 * nb + b] : 0.0;
+            x[r][3] = in && bookkeep ? pg[b] : 0.0;
+            x[r][4] = in && bookkeep ? pg[nb + b] : 0.0;
         }
 #pragma unroll
         for (int r = 0; r < kGroupRounds; ++r) {
@@ -536,6 +542,7 @@ __global__ __launch_bounds__(kBlock) void k_decide_gs(int t, Ctl *ctl, Trace *tr
                 a_sx += x[r][0];
                 a_cd += x[r][1];
                 a_ed += x[r][2];
+                sn += x[r][3] + c * x[r][4];
             }
         }
     }
@@ -1430,6 +1437,25 @@ __global__ void k_amp_q(int32_t nN, const int32_t *deg, const double *acc, float
         q[i] = __double2float_ru(acc[i] / (double)deg[i] * (1.0 + 1e-6));
 }
 
+// see launch_amp_qle; one thread per vertex (built once per graph, factor and grouping)
+__global__ void k_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_nn, const int32_t *deg,
+                          const float *g, GroupEnds ge, float *qle) {
+    for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < nN; u += (int64_t)gridDim.x * kBlock) {
+        int32_t end = nN;
+        for (int q = 0; q < ge.ng; ++q)
+            if (u < ge.end[q]) {
+                end = ge.end[q];
+                break;
+            }
+        double s = 0.0;
+        for (uint32_t e = rp_nn[u]; e < rp_nn[u + 1]; ++e) {
+            const int32_t j = col_nn[e];
+            if (j < end) s += (double)g[j];
+        }
+        qle[u] = __double2float_ru(s / (double)deg[u] * (1.0 + 1e-6));
+    }
+}
+
 // fill kernels (clearing counters and sums without a memset node in the stream)
 __global__ void k_fill_u32(uint32_t *p, int64_t count, uint32_t v) {
     for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < count; i += (int64_t)gridDim.x * kBlock) p[i] = v;
@@ -1584,20 +1610,21 @@ hipError_t launch_reserve(int t, Ctl *ctl, Trace *tr, int32_t nN, T *h, T *w, do
 template <typename T>
 hipError_t launch_reserve_range(int t, Ctl *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
                                 const int32_t *deg, const uint32_t *rp_nn, double c, double xi, int ifp2, int nbg,
-                                double *part, hipStream_t s) {
+                                ErrWeights ew, double *part, hipStream_t s) {
     PRK_GGL(k_reserve<T>, dim3(nbg), dim3(kBlock), 0, s, t, (const Ctl *)ctl, lo, hi, h, w, pibar, deg,
-                       rp_nn, c, (T)xi, ifp2, ErrWeights{nullptr, nullptr}, part);
+                       rp_nn, c, (T)xi, ifp2, ew, part);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_decide_gs(int t, Ctl *ctl, Trace *tr, int32_t nN, const T *h, int ng, const GroupBlocks &gb,
                             const double *part, double *part_s, double c, const float *g, double kb, int stop_l1,
-                            double tol, unsigned long long pull_thr, unsigned long long pull_edges, hipStream_t s) {
-    const int nbs = grid_for(nN, 8, kRedBlocks);
-    PRK_GGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, g, part_s);
+                            double tol, unsigned long long pull_thr, unsigned long long pull_edges, int bookkeep,
+                            hipStream_t s) {
+    const int nbs = bookkeep ? 0 : grid_for(nN, 8, kRedBlocks);
+    if (!bookkeep) PRK_GGL(k_sum_h<T>, dim3(nbs), dim3(kBlock), 0, s, t, (const Ctl *)ctl, nN, h, g, part_s);
     PRK_GGL(k_decide_gs, dim3(1), dim3(kBlock), 0, s, t, ctl, tr, ng, gb, part, nbs,
-                       (const double *)part_s, c, kb, stop_l1, tol, pull_thr, pull_edges);
+                       (const double *)part_s, c, kb, stop_l1, tol, pull_thr, pull_edges, bookkeep);
     return hipGetLastError();
 }
 
@@ -1741,6 +1768,12 @@ hipError_t launch_amp_weights(int32_t nN, const MPPlan &push_nn, const int32_t *
     return hipGetLastError();
 }
 
+hipError_t launch_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_nn, const int32_t *deg,
+                          const float *g, const GroupEnds &ge, float *qle, hipStream_t s) {
+    if (nN <= 0) return hipSuccess;
+    PRK_LAUNCH(k_amp_qle, grid_for(nN, 1, 8192), nN, rp_nn, col_nn, deg, g, ge, qle);
+}
+
 hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t s) {
     if (count <= 0) return hipSuccess;
     PRK_LAUNCH(k_fill_u32, grid_for(count, 4, 1024), p, count, 0u);
@@ -1822,16 +1855,16 @@ template hipError_t launch_reserve<double>(int, Ctl *, Trace *, int32_t, double 
                                            hipStream_t);
 template hipError_t launch_reserve_range<float>(int, Ctl *, int32_t, int32_t, float *, float *, double *,
                                                 const int32_t *, const uint32_t *, double, double, int, int,
-                                                double *, hipStream_t);
+                                                ErrWeights, double *, hipStream_t);
 template hipError_t launch_reserve_range<double>(int, Ctl *, int32_t, int32_t, double *, double *, double *,
                                                  const int32_t *, const uint32_t *, double, double, int, int,
-                                                 double *, hipStream_t);
+                                                 ErrWeights, double *, hipStream_t);
 template hipError_t launch_decide_gs<float>(int, Ctl *, Trace *, int32_t, const float *, int, const GroupBlocks &,
                                             const double *, double *, double, const float *, double, int, double,
-                                            unsigned long long, unsigned long long, hipStream_t);
+                                            unsigned long long, unsigned long long, int, hipStream_t);
 template hipError_t launch_decide_gs<double>(int, Ctl *, Trace *, int32_t, const double *, int, const GroupBlocks &,
                                              const double *, double *, double, const float *, double, int, double,
-                                             unsigned long long, unsigned long long, hipStream_t);
+                                             unsigned long long, unsigned long long, int, hipStream_t);
 
 template hipError_t launch_push<float>(int, const Ctl *, const MPPlan &, const float *, float *, int, hipStream_t,
                                        TileSkip, KernelEvents);

@@ -83,6 +83,43 @@ static pr_status amp_weights(Graph &G, double c, bool may_alloc, hipStream_t s, 
     return PR_OK;
 }
 
+// The push weights of ordered sweeps restricted to each vertex's own and earlier groups
+// (launch_amp_qle) for factor c and the graph's current vertex groups, built on first use
+// and kept with the factor's weights; null when the factor has no weights, or when they
+// are missing and the solve may not allocate (the sweeps then sum S_N directly).
+static pr_status amp_qle(Graph &G, double c, bool may_alloc, hipStream_t s, const float **out) {
+    *out = nullptr;
+    const int32_t ng = (int32_t)G.grp.size() - 1;
+    if (ng < 2 || ng > kMaxGroups) return PR_OK;
+    std::lock_guard<std::mutex> lk(G.amp_mu);
+    for (Graph::Amp &a : G.amp) {
+        if (a.c != c) continue;
+        if (a.qle && a.qle_version == G.grp_version) {
+            *out = a.qle;
+            return PR_OK;
+        }
+        if (!may_alloc) return PR_OK;
+        if (!a.qle) {
+            DevBufs keep;
+            float *q = nullptr;
+            HIPCHK(keep.alloc(&q, (size_t)G.nN));
+            G.allocs.push_back((void *)q);
+            G.device_bytes += (int64_t)sizeof(float) * G.nN;
+            keep.ptrs.clear();
+            a.qle = q;
+        }
+        GroupEnds ge{};
+        ge.ng = ng;
+        for (int32_t q = 0; q < ng; ++q) ge.end[q] = G.grp[(size_t)q + 1];
+        HIPCHK(launch_amp_qle(G.nN, G.rp_nn, G.col_nn, G.deg, a.g, ge, a.qle, s));
+        HIPCHK(hipStreamSynchronize(s));  // other streams may take the weights from the table
+        a.qle_version = G.grp_version;
+        *out = a.qle;
+        return PR_OK;
+    }
+    return PR_OK;
+}
+
 // The stop rule's error weights for factor c built ahead of solves that may not allocate
 // (a server engine's solves run in a workspace of its own).
 pr_status stop_weights(Graph &G, double c, hipStream_t s) {
@@ -321,6 +358,15 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     const int ngr = (int)G.grp.size() - 1;
     const bool ordered_ok = ngr > 1 && ngr <= kMaxGroups && force == 0 && !(o.flags & PR_JACOBI) &&
                             !G.grp_pull.empty() && G.prefer_ordered;
+    // ordered sweeps with the stop rule's weights take S_N from the reserves' own sums,
+    // with the pushed mass weighted by the part that stays residual to the end of a sweep
+    // (no summing pass per sweep); residuals of either sign (a warm start) are summed
+    const float *qle = nullptr;
+    if (ordered_ok && ew.g && !warm) {
+        ps = amp_qle(const_cast<Graph &>(G), c, ext == nullptr, s, &qle);
+        if (ps != PR_OK) return ps;
+    }
+    const ErrWeights ew_ord = qle ? ErrWeights{ew.g, qle} : ErrWeights{nullptr, nullptr};
     bool ordered = ordered_ok && a.uniform && !warm;
     GroupBlocks gb{};
     gb.stride = kGroupBlocks;
@@ -383,7 +429,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                         unsigned long long sweep_edges = 0;
                         for (int q = 0; q < ngr; ++q) {
                             HIPCHK(launch_reserve_range<T>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg,
-                                                           G.rp_nn, c, xi, ifp2 ? 1 : 0, gb.nb[q],
+                                                           G.rp_nn, c, xi, ifp2 ? 1 : 0, gb.nb[q], ew_ord,
                                                            part + (size_t)5 * kGroupBlocks * q, s));
                             const MPPlan &pl = G.group_rows ? (ifp2 ? G.grp_pull_rows[e][q] : G.grp_pull_all_rows[e][q])
                                                             : (ifp2 ? G.grp_pull[e][q] : G.grp_pull_all[e][q]);
@@ -398,7 +444,7 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
                         }
                         HIPCHK(launch_decide_gs<T>(t, ctl, tr, nN, h, ngr, gb, part,
                                                    part + (size_t)5 * kGroupBlocks * ngr, c, ew.g, kb, l1 ? 1 : 0,
-                                                   tol_run, pull_thr, sweep_edges, s));
+                                                   tol_run, pull_thr, sweep_edges, qle ? 1 : 0, s));
                         continue;
                     }
                     HIPCHK(launch_reserve<T>(t, ctl, tr, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, ifp2 ? 1 : 0, ew, kb,

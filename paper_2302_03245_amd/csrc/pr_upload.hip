@@ -469,6 +469,7 @@ pr_status upload_impl(int64_t n, int64_t m, const int64_t *row_ptr, const int32_
 // leaves none); the plans take the graph's current tile size.
 pr_status build_groups(Graph &G, int32_t k, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
+    ++G.grp_version;  // weights derived from the old groups are stale from here
     for (void *p : G.grp_allocs) (void)hipFree(p);
     G.grp_allocs.clear();
     G.device_bytes -= G.grp_bytes;

@@ -186,3 +186,46 @@ def test_verify_weighted_bound_needs_its_factor_two():
         w, _ = _bounds(g, C, pi, p, F)
         worst = max(worst, np.abs(pi - star).sum() / w)
     assert 0.5 < worst <= 1.0 + 1e-9, worst
+
+
+@pytest.mark.parametrize("gi", range(len(GRAPHS)))
+@pytest.mark.parametrize("groups", [2, 3, 5])
+def test_ordered_sweep_residual_bookkeeping(gi, groups):
+    """An ordered sweep (vertex groups as id ranges, each reserving then pushing along its
+    non-dangling out-edges before the next group reserves) leaves sum_N g_i h_i equal to
+    the groups' residual left behind at their reserve plus c times the pushed mass weighted
+    by qle_u = (1 / deg u) sum of g over u's non-dangling out-neighbours in u's group or an
+    earlier one: the sums the library's ordered sweeps keep instead of a summing pass."""
+    g = GRAPHS[gi]
+    n = g.n
+    deg = np.diff(g.row_ptr)
+    nd = deg > 0
+    rng = np.random.default_rng(7 + gi)
+    w = rng.random(n) + 0.1          # any positive weights: the identity is linear in them
+    h = rng.random(n) * 3.0
+    xi = 1.0
+    ends = [int(round(n * (q + 1) / groups)) for q in range(groups)]
+    group = np.searchsorted(np.array(ends), np.arange(n), side="right")
+    inact, pushed = 0.0, 0.0
+    for q in range(groups):
+        lo, hi = (ends[q - 1] if q else 0), ends[q]
+        taken = []
+        for i in range(lo, hi):
+            if not nd[i]:
+                continue
+            if h[i] > xi:
+                taken.append((i, h[i]))
+                h[i] = 0.0
+            else:
+                inact += w[i] * h[i]
+        for u, v in taken:
+            qle = 0.0
+            for e in range(g.row_ptr[u], g.row_ptr[u + 1]):
+                j = g.col[e]
+                if nd[j]:
+                    h[j] += C * v / deg[u]
+                    if group[j] <= group[u]:
+                        qle += w[j]
+            pushed += v * qle / deg[u]
+    direct = float((w[nd] * h[nd]).sum())
+    assert abs(direct - (inact + C * pushed)) <= 1e-12 * max(1.0, direct), (direct, inact + C * pushed)
