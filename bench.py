@@ -19,6 +19,17 @@ import re
 import sys
 import time
 
+# The served leg runs one engine per graph, each on its own HIP stream; with HIP's default
+# of 4 hardware queues per process, 33 engines share queues and a long kernel of the big
+# graph's engine holds up the small graphs' kernels queued behind it.  The process takes
+# at least 16 queues, raising a lower setting (HIP reads it once, when it starts; the other
+# legs use one or two streams).
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _hwq = 4
+os.environ["GPU_MAX_HW_QUEUES"] = str(max(_hwq, 16))
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -476,7 +487,11 @@ def run_ppr(pr, dg, g, c, args):
             "one_at_a_time_gteps": k * g.m / t_single / 1e9, "batched_gteps": k * g.m / t_batch / 1e9,
             "speedup": t_single / t_batch, "batch_width": 16,
             "mean_sweeps_single": float(np.mean([s["sweeps"] for s in single])),
-            "mean_sweeps_batched": float(np.mean([s["sweeps"] for s in batched]))}
+            "mean_sweeps_batched": float(np.mean([s["sweeps"] for s in batched])),
+            # the batch's sweeps that gathered, and the edges its sweeps read (gathers: every
+            # live in-edge; scatters: the active edges; plus the dangling phase's in-edges)
+            "batched_gather_sweeps": int(batched[0]["pull_sweeps"]),
+            "batched_edges_traversed": int(batched[0]["edges_traversed"])}
 
 
 def run_warm(pr, prgen, dg, g, c, args):
@@ -736,7 +751,8 @@ def run_serve(pr, prgen, c, args):
             "served_over_one_at_a_time": saturated["gteps_aggregate"] / one["gteps_aggregate"],
             "ppr_graph": {"n": gp.n, "m": gp.m},
             "pool": {"graphs": len(pool), "n": sum(x.n for x in pool), "m": sum(x.m for x in pool)},
-            "ppr_share": float(is_ppr.mean()), "slots_per_graph": args.serve_slots}
+            "ppr_share": float(is_ppr.mean()), "slots_per_graph": args.serve_slots,
+            "hw_queues": int(os.environ["GPU_MAX_HW_QUEUES"])}
 
 
 def run_probes(pr, torch, g):

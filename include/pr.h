@@ -296,8 +296,12 @@ pr_status pr_solve_power(const pr_graph *g, const double *p, const pr_opts *o, d
  * for each of the k sources.  Up to 16 sources share one batched solve: their
  * residual vectors are interleaved so that every gathered in-edge serves all of
  * them, and each keeps its own stop decision (same result as one call per
- * source, within the tolerances).  On a graph uploaded with PR_PEEL every
- * source is solved alone.  With PR_OUT_DEVICE, pi is a device pointer.
+ * source, within the tolerances).  A batch starts with synchronous sweeps
+ * (each column's frontier is one vertex) and turns to ordered sweeps over the
+ * graph's vertex groups, as for global solves, once the columns' frontiers
+ * together are dense; PR_JACOBI keeps it synchronous.  On a graph uploaded with
+ * PR_PEEL every source is solved alone.  With PR_OUT_DEVICE, pi is a device
+ * pointer.
  *   sources  int32[k] host array, each in [0, n); k >= 1
  *   pi       double[k * n], row r is the PPR vector of sources[r]
  *   st       optional, k entries

@@ -12,7 +12,9 @@
  * and slots is 16.  Between rounds of sweeps a run finishes the columns that
  * met their bound (dangling phase + normalisation for those columns only) and
  * admits waiting queries into free columns while the other columns keep
- * iterating (continuous batching).  A run ends when its last column retires;
+ * iterating (continuous batching).  A round's sweeps are ordered sweeps over
+ * the graph's vertex groups (as in pr_ppr) when the last sweep's frontiers
+ * were dense, else synchronous.  A run ends when its last column retires;
  * an 8-wide run whose queue outgrows its free slots stops admitting so that
  * the next run can be 16 wide.  Engines of different graphs run concurrently
  * on the device.

@@ -47,21 +47,23 @@ __global__ void k_init_b(int64_t n, int32_t nN, const int32_t *perm, SrcSet src,
     }
 }
 
-// Reserve step for every live column (see k_reserve): partials per column,
-// layout part[(q * B + j) * nb + block] for q = inactive residual, mass sent to
-// non-dangling vertices, growth of the total mass, active vertices, their edges.
+// Reserve step of rows [lo, hi) for every live column (see k_reserve): partials per
+// column, layout part[(q * B + j) * nb + block] for q = inactive residual, mass sent to
+// non-dangling vertices, active vertices, their edges, and with qle (an ordered sweep's
+// group) the pushed mass weighted by qle: the share of a vertex's push that lands in its
+// own group or an earlier one, where it stays residual to the end of the sweep.
 template <typename T, int B>
-__global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, int32_t nN, T *h, T *w, double *pibar,
-                                                      const int32_t *deg, const uint32_t *rp_nn, double c, T xi,
-                                                      double *part) {
+__global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, int32_t lo, int32_t hi, T *h, T *w,
+                                                      double *pibar, const int32_t *deg, const uint32_t *rp_nn,
+                                                      double c, T xi, const float *qle, double *part) {
     if (t > ctl->stop_after) return;
     const int j = threadIdx.x % B;  // the grid stride is a multiple of B: a thread keeps its column
     const bool live = t <= ctl->col_stop[j];
-    double inact = 0.0, pred = 0.0, cnt = 0.0, edges = 0.0;
-    const int64_t total = (int64_t)nN * B;
+    double inact = 0.0, pred = 0.0, cnt = 0.0, edges = 0.0, stay = 0.0;
+    const int64_t first = (int64_t)lo * B, total = (int64_t)hi * B;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    // one (vertex, column) entry whose inputs are loaded (dg, r0, r1, pb read only when active)
-    auto take = [&](int64_t idx, T hv, int32_t dg, uint32_t r0, uint32_t r1, double pb) {
+    // one (vertex, column) entry whose inputs are loaded (dg, r0, r1, pb, ql read only when active)
+    auto take = [&](int64_t idx, T hv, int32_t dg, uint32_t r0, uint32_t r1, double pb, float ql) {
         if (live && hv > xi) {
             const uint32_t dnn = r1 - r0;
             const double val = (double)hv;
@@ -69,6 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, in
             h[idx] = (T)0;
             w[idx] = (T)(c * val / (double)dg);
             pred += val * ((double)dnn / (double)dg);
+            stay += val * (double)ql;
             cnt += 1.0;
             edges += (double)dnn;
         } else {
@@ -76,11 +79,11 @@ __global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, in
             inact += (double)hv;
         }
     };
-    int64_t idx = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-    if (ctl->use_pull) {
-        // dense frontier (uniform over the grid): most entries are taken, so an entry's
-        // degree, row offsets and pibar are loaded with its residual, two entries per
-        // iteration, instead of after the test; sums run in the same order
+    int64_t idx = first + blockIdx.x * (int64_t)kBlock + threadIdx.x;
+    if (ctl->use_pull || total - first <= stride) {
+        // dense frontier, or about one entry per thread (uniform over the grid): an
+        // entry's degree, row offsets and pibar are loaded with its residual, two
+        // entries per iteration, instead of after the test; sums run in the same order
         for (; idx < total; idx += 2 * stride) {
             const int64_t i2 = idx + stride;
             const bool two = i2 < total;
@@ -89,10 +92,12 @@ __global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, in
             const int32_t dg = deg[v];
             const uint32_t r0 = rp_nn[v], r1 = rp_nn[v + 1];
             const double pb = pibar[idx];
+            const float ql = qle ? qle[v] : 0.0f;
             T hv2 = (T)0;
             int32_t dg2 = 1;
             uint32_t s0 = 0, s1 = 0;
             double pb2 = 0.0;
+            float ql2 = 0.0f;
             if (two) {
                 const int64_t v2 = i2 / B;
                 hv2 = h[i2];
@@ -100,16 +105,17 @@ __global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, in
                 s0 = rp_nn[v2];
                 s1 = rp_nn[v2 + 1];
                 pb2 = pibar[i2];
+                ql2 = qle ? qle[v2] : 0.0f;
             }
-            take(idx, hv, dg, r0, r1, pb);
-            if (two) take(i2, hv2, dg2, s0, s1, pb2);
+            take(idx, hv, dg, r0, r1, pb, ql);
+            if (two) take(i2, hv2, dg2, s0, s1, pb2, ql2);
         }
     } else {
         for (; idx < total; idx += stride) {
             const int64_t v = idx / B;
             const T hv = h[idx];
-            if (live && hv > xi) take(idx, hv, deg[v], rp_nn[v], rp_nn[v + 1], pibar[idx]);
-            else take(idx, hv, 0, 0, 0, 0.0);
+            if (live && hv > xi) take(idx, hv, deg[v], rp_nn[v], rp_nn[v + 1], pibar[idx], qle ? qle[v] : 0.0f);
+            else take(idx, hv, 0, 0, 0, 0.0, 0.0f);
         }
     }
     __shared__ double sd[kBlock / W * B];
@@ -117,12 +123,14 @@ __global__ __launch_bounds__(kBlock) void k_reserve_b(int t, const CtlB *ctl, in
     const double r1 = block_sum_cols<B>(pred, sd);
     const double r3 = block_sum_cols<B>(cnt, sd);
     const double r4 = block_sum_cols<B>(edges, sd);
+    const double r5 = qle ? block_sum_cols<B>(stay, sd) : 0.0;  // qle is uniform over the grid
     if (threadIdx.x < B) {
         const int nb = gridDim.x, b = blockIdx.x, jj = threadIdx.x;
         part[(0 * B + jj) * nb + b] = r0;
         part[(1 * B + jj) * nb + b] = r1;
         part[(2 * B + jj) * nb + b] = r3;
         part[(3 * B + jj) * nb + b] = r4;
+        if (qle) part[(4 * B + jj) * nb + b] = r5;
     }
 }
 
@@ -185,6 +193,84 @@ __global__ __launch_bounds__(1024) void k_decide_b(int t, CtlB *ctl, int nb, con
     if (any_moved) {
         ctl->pull_sweeps += pull;
         ctl->tot_traversed += pull ? pull_edges : (unsigned long long)total_edges;
+    }
+    if (!any_next) ctl->stop_after = any_moved ? t : t - 1;
+}
+
+// Row sums of an ordered sweep's reserve partials: workgroup r sums row r % (5B) of
+// group r / (5B) (gb.nb[q] entries, every load issued before the first add, added in
+// index order) into sums[r].
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_rowsum_gs_b(int t, const CtlB *ctl, GroupBlocks gb, const double *part,
+                                                        double *sums) {
+    if (t > ctl->stop_after) return;
+    constexpr int kRounds = kGroupBlocks / kBlock;
+    const int q = blockIdx.x / (5 * B), r = blockIdx.x % (5 * B);
+    const int nb = gb.nb[q];
+    const double *row = part + (size_t)5 * B * gb.stride * q + (size_t)r * nb;
+    double x[kRounds];
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) {
+        const int b = threadIdx.x + k * kBlock;
+        x[k] = b < nb ? row[b] : 0.0;
+    }
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < kRounds; ++k) v += x[k];
+    __shared__ double sd[kBlock / W];
+    v = block_sum(v, sd);
+    if (threadIdx.x == 0) sums[blockIdx.x] = v;
+}
+
+// Management step of an ordered sweep for B columns (one workgroup), after every group
+// has reserved and gathered.  Column j's residual left on the non-dangling vertices is
+// what the reserves left behind plus c times the pushed mass that landed in the pushing
+// vertex's own group or an earlier one (mass pushed into a later group met that group's
+// reserve in the same sweep: taken, or counted as left behind); the stop rules are
+// those of k_decide_b.
+template <int B>
+__global__ __launch_bounds__(kBlock) void k_decide_gs_b(int t, CtlB *ctl, int ngr, const double *sums, double c,
+                                                        int stop_l1, double tol, double pull_thr,
+                                                        unsigned long long sweep_edges) {
+    if (t > ctl->stop_after) return;
+    __shared__ double s5[5 * B];
+    if (threadIdx.x < 5 * B) {
+        double v = 0.0;
+        for (int q = 0; q < ngr; ++q) v += sums[(size_t)5 * B * q + threadIdx.x];
+        s5[threadIdx.x] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    const double k = 2.0 * c / (1.0 - c);
+    bool any_moved = false, any_next = false;
+    double total_edges = 0.0;
+    for (int j = 0; j < B; ++j) {
+        if (t > ctl->col_stop[j]) continue;  // frozen column
+        const double a_in = s5[0 * B + j], a_pr = s5[1 * B + j];
+        const double a_c = s5[2 * B + j], a_e = s5[3 * B + j], a_st = s5[4 * B + j];
+        if (a_c == 0.0) {
+            ctl->col_stop[j] = t - 1;
+            ctl->last_bound[j] = k * a_in / ctl->sx[j];
+            continue;
+        }
+        any_moved = true;
+        total_edges += a_e;
+        const double sn = a_in + c * a_st;
+        const double sx = ctl->sx[j] + c * a_pr;
+        ctl->sx[j] = sx;
+        const double bound = k * sn / sx;
+        ctl->last_bound[j] = bound;
+        ctl->col_sweeps[j] = t + 1;
+        ctl->tot_pushes[j] += (unsigned long long)a_c;
+        ctl->tot_edges[j] += (unsigned long long)a_e;
+        if (stop_l1 && bound <= tol) ctl->col_stop[j] = t;
+        else any_next = true;
+    }
+    // would a synchronous sweep gather (is the frontier dense)
+    ctl->use_pull = total_edges >= pull_thr ? 1 : 0;
+    if (any_moved) {
+        ctl->pull_sweeps += 1;
+        ctl->tot_traversed += sweep_edges;
     }
     if (!any_next) ctl->stop_after = any_moved ? t : t - 1;
 }
@@ -254,11 +340,12 @@ __global__ __launch_bounds__(kBlock) void k_push_b(int t, const CtlB *ctl, int c
 // by groups meet in an LDS accumulator (FP64, FP32 when the output is FP32: the
 // sum is rounded to FP32 when it reaches the output anyway), and so do rows one
 // group holds whole; the tile then writes all its rows out in one coalesced pass,
-// rows shared by tiles through one global atomic per column and tile.
+// rows shared by tiles through one global atomic per column and tile.  With rid, plan
+// row r is target row rid[r] (a vertex group's gather over the rows it reaches).
 template <typename WT, typename OT, int B, int K>
 __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int check_mode, const uint32_t *rp,
                                                    int32_t R, const int32_t *src, const uint2 *plan, uint32_t items,
-                                                   int32_t ntiles, const WT *w, OT *out) {
+                                                   int32_t ntiles, const int32_t *rid, const WT *w, OT *out) {
     constexpr int G = kBlock / B;
     constexpr int IPB = G * K;
     static_assert(IPB <= kBlock, "one row end per thread");
@@ -343,7 +430,8 @@ __global__ __launch_bounds__(kBlock) void k_pull_b(int t, const CtlB *ctl, int c
             const double v = (double)s_acc[q];
             if (v == 0.0) continue;
             const int32_t k = q / B;
-            OT *o = out + (int64_t)i0 * B + q;
+            // plan row i0 + k is target row rid[i0 + k] when the plan keeps only some rows
+            OT *o = out + (rid ? (int64_t)rid[i0 + k] * B + q % B : (int64_t)i0 * B + q);
             if (k == 0 || k == nr - 1) atomicAdd(o, (OT)v);
             else *o = (OT)((double)*o + v);
         }
@@ -434,10 +522,32 @@ hipError_t launch_reserve_b(int t, CtlB *ctl, int32_t nN, T *h, T *w, double *pi
                             const uint32_t *rp_nn, double c, double xi, int stop_l1, double tol, double pull_thr,
                             int force, unsigned long long pull_edges, double *part, hipStream_t s) {
     const int nb = grid_for((int64_t)nN * B, 4, kRedBlocks);
-    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reserve_b<T, B>), dim3(nb), dim3(kBlock), 0, s, t, (const CtlB *)ctl, nN, h,
-                       w, pibar, deg, rp_nn, c, (T)xi, part);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reserve_b<T, B>), dim3(nb), dim3(kBlock), 0, s, t, (const CtlB *)ctl, 0, nN,
+                       h, w, pibar, deg, rp_nn, c, (T)xi, (const float *)nullptr, part);
     hipLaunchKernelGGL(HIP_KERNEL_NAME(k_decide_b<B>), dim3(1), dim3(1024), 0, s, t, ctl, nb, (const double *)part,
                        c, stop_l1, tol, pull_thr, force, pull_edges);
+    return hipGetLastError();
+}
+
+template <typename T, int B>
+hipError_t launch_reserve_range_b(int t, CtlB *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
+                                  const int32_t *deg, const uint32_t *rp_nn, double c, double xi, const float *qle,
+                                  int nb, double *part, hipStream_t s) {
+    if (hi <= lo || nb < 1 || nb > kGroupBlocks || !qle) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_reserve_b<T, B>), dim3(nb), dim3(kBlock), 0, s, t, (const CtlB *)ctl, lo, hi,
+                       h, w, pibar, deg, rp_nn, c, (T)xi, qle, part);
+    return hipGetLastError();
+}
+
+template <int B>
+hipError_t launch_decide_gs_b(int t, CtlB *ctl, int ngr, const GroupBlocks &gb, const double *part, double *sums,
+                              double c, int stop_l1, double tol, double pull_thr, unsigned long long sweep_edges,
+                              hipStream_t s) {
+    if (ngr < 1 || ngr > kMaxGroups) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_rowsum_gs_b<B>), dim3(5 * B * ngr), dim3(kBlock), 0, s, t,
+                       (const CtlB *)ctl, gb, part, sums);
+    hipLaunchKernelGGL(HIP_KERNEL_NAME(k_decide_gs_b<B>), dim3(1), dim3(kBlock), 0, s, t, ctl, ngr,
+                       (const double *)sums, c, stop_l1, tol, pull_thr, sweep_edges);
     return hipGetLastError();
 }
 
@@ -458,7 +568,7 @@ hipError_t launch_pull_b(int t, const CtlB *ctl, const MPPlan &p, const WT *w, O
     auto kern = &k_pull_b<WT, OT, B, kMPK>;
     static const int grid = resident_grid(kern);
     hipLaunchKernelGGL(kern, dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R, p.idx,
-                       (const uint2 *)p.plan, p.items, p.blocks, w, out);
+                       (const uint2 *)p.plan, p.items, p.blocks, p.rid, w, out);
     return hipGetLastError();
 }
 
@@ -503,5 +613,18 @@ PRK_BATCH_INST(float, 8)
 PRK_BATCH_INST(double, 8)
 PRK_BATCH_INST(float, 16)
 PRK_BATCH_INST(double, 16)
+
+#define PRK_BATCH_GS_INST(T, B)                                                                                     \
+    template hipError_t launch_reserve_range_b<T, B>(int, CtlB *, int32_t, int32_t, T *, T *, double *,           \
+                                                     const int32_t *, const uint32_t *, double, double,            \
+                                                     const float *, int, double *, hipStream_t);
+PRK_BATCH_GS_INST(float, 8)
+PRK_BATCH_GS_INST(double, 8)
+PRK_BATCH_GS_INST(float, 16)
+PRK_BATCH_GS_INST(double, 16)
+template hipError_t launch_decide_gs_b<8>(int, CtlB *, int, const GroupBlocks &, const double *, double *, double,
+                                          int, double, double, unsigned long long, hipStream_t);
+template hipError_t launch_decide_gs_b<16>(int, CtlB *, int, const GroupBlocks &, const double *, double *, double,
+                                           int, double, double, unsigned long long, hipStream_t);
 
 }  // namespace prk

@@ -41,6 +41,14 @@ struct GroupEnds {
     int32_t ng;
     int32_t end[kMaxGroups];
 };
+// Partial sums of a batched solve of width B with ngr vertex groups (doubles): a
+// synchronous sweep's reserve writes 4 rows of B columns, one entry per workgroup; an
+// ordered sweep's group q writes 5 rows at 5 * B * kGroupBlocks * q; the ordered
+// sweep's per-group row sums follow all of them.
+inline size_t batch_part_doubles(int B, int ngr) {
+    const size_t rows = (size_t)4 * B * kRedBlocks, grp = (size_t)5 * B * kGroupBlocks * ngr;
+    return (rows > grp ? rows : grp) + (size_t)5 * B * ngr;
+}
 constexpr int32_t kDepthInf = 0x7fffffff;  // unreferenced depth of vertices on or below a cycle
 constexpr int kMaxEpochs = 8;     // compacted in-edge lists kept per graph
 constexpr int kMPK = 8;           // default merge-path items (rows + edges) per thread (4, 8 or 16)
@@ -225,6 +233,15 @@ struct Graph {
     bool bp_ready[2] = {false, false};
     std::vector<MPPlan> bp_pull_nn[2];  // per epoch
     MPPlan bp_pull_nd[2], bp_push_nn[2];
+    // ordered sweeps of the batched kernels: per width, the gather plans of the vertex
+    // groups' in-edges over the rows each group reaches ([epoch][group], sharing the
+    // lists of grp_pull_rows), and per vertex the share of its push that stays residual
+    // to the end of an ordered sweep (launch_amp_qle with unit weights); built for the
+    // vertex groups of version bp_grp_version and owned with the groups (grp_allocs)
+    std::vector<std::vector<MPPlan>> bp_grp[2];
+    int64_t bp_grp_version[2] = {-1, -1};
+    float *bp_qle = nullptr;
+    int64_t bp_qle_version = -1;
     int32_t *depth = nullptr;     // unreferenced depth of non-dangling vertices, [nN + nP] (peeled: infinite)
     int32_t max_depth = -1;       // largest finite depth
     std::vector<Epoch> epochs;    // epochs[0] aliases the full in-edge lists
@@ -272,6 +289,27 @@ struct Graph {
     std::vector<uint64_t> dangling_bits;  // host bitmap over original ids: no out-edges
     bool dangling(int64_t v) const { return (dangling_bits[(size_t)v >> 6] >> (v & 63)) & 1u; }
 };
+
+// Ordered sweeps of a batched solve of width B (slot 0: 8, 1: 16) are possible: the graph
+// has vertex groups, prefers ordered sweeps, and its batched group plans are current.
+inline bool batch_ordered_ready(const Graph &G, int slot) {
+    const int ng = (int)G.grp.size() - 1;
+    return ng > 1 && ng <= kMaxGroups && G.prefer_ordered && G.bp_qle != nullptr &&
+           G.bp_qle_version == G.grp_version && G.bp_grp_version[slot] == G.grp_version &&
+           G.bp_grp[slot].size() == G.epochs.size();
+}
+// workgroups of each group's reserve in a batched ordered sweep of width B (about four
+// (vertex, column) entries per thread, at most kGroupBlocks)
+inline GroupBlocks batch_group_blocks(const Graph &G, int B) {
+    GroupBlocks gb{};
+    gb.stride = kGroupBlocks;
+    for (size_t q = 0; q + 1 < G.grp.size() && q < (size_t)kMaxGroups; ++q) {
+        const int64_t work = ((int64_t)G.grp[q + 1] - G.grp[q]) * B;
+        const int64_t b = (work + 4 * kBlock - 1) / (4 * kBlock);
+        gb.nb[q] = (int32_t)(b < 1 ? 1 : (b > kGroupBlocks ? kGroupBlocks : b));
+    }
+    return gb;
+}
 
 // host helpers for the query server (pr_host.hip: errors; pr_solve.hip: batched plans)
 pr_status set_error(pr_status st, const std::string &msg);
@@ -386,7 +424,8 @@ hipError_t launch_zero_f64(double *p, int64_t count, hipStream_t s);
 // (plan push_nn), each an upper bound; f and acc: nN doubles of scratch
 // qle[u] = (sum of g over u's non-dangling out-neighbours in u's vertex group or an earlier
 // one) / deg(u), rounded up: the weight of mass u pushes in an ordered sweep that is still
-// residual when the sweep ends (a later group takes the rest within the sweep)
+// residual when the sweep ends (a later group takes the rest within the sweep); with g
+// null, unit weights (the share of u's push that stays residual)
 hipError_t launch_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_nn, const int32_t *deg,
                           const float *g, const GroupEnds &ge, float *qle, hipStream_t s);
 hipError_t launch_amp_weights(int32_t nN, const MPPlan &push_nn, const int32_t *deg, const uint32_t *rp_nn,
@@ -462,6 +501,17 @@ template <typename T, int B>
 hipError_t launch_reserve_b(int t, CtlB *ctl, int32_t nN, T *h, T *w, double *pibar, const int32_t *deg,
                             const uint32_t *rp_nn, double c, double xi, int stop_l1, double tol, double pull_thr,
                             int force, unsigned long long pull_edges, double *part, hipStream_t s);
+// the reserve of rows [lo, hi) in an ordered sweep (nb workgroups, 5 partial rows of B
+// columns from part; qle: the share of each vertex's push that stays residual to the end
+// of the sweep), and the decision after all groups have reserved and gathered
+template <typename T, int B>
+hipError_t launch_reserve_range_b(int t, CtlB *ctl, int32_t lo, int32_t hi, T *h, T *w, double *pibar,
+                                  const int32_t *deg, const uint32_t *rp_nn, double c, double xi, const float *qle,
+                                  int nb, double *part, hipStream_t s);
+template <int B>
+hipError_t launch_decide_gs_b(int t, CtlB *ctl, int ngr, const GroupBlocks &gb, const double *part, double *sums,
+                              double c, int stop_l1, double tol, double pull_thr, unsigned long long sweep_edges,
+                              hipStream_t s);
 template <typename T, int B>
 hipError_t launch_push_b(int t, const CtlB *ctl, const MPPlan &p, const T *w, T *h, int check_mode, hipStream_t s);
 template <typename WT, typename OT, int B>

@@ -1437,7 +1437,8 @@ __global__ void k_amp_q(int32_t nN, const int32_t *deg, const double *acc, float
         q[i] = __double2float_ru(acc[i] / (double)deg[i] * (1.0 + 1e-6));
 }
 
-// see launch_amp_qle; one thread per vertex (built once per graph, factor and grouping)
+// see launch_amp_qle; one thread per vertex (built once per graph, factor and grouping;
+// unit weights when g is null)
 __global__ void k_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_nn, const int32_t *deg,
                           const float *g, GroupEnds ge, float *qle) {
     for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < nN; u += (int64_t)gridDim.x * kBlock) {
@@ -1450,7 +1451,7 @@ __global__ void k_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_
         double s = 0.0;
         for (uint32_t e = rp_nn[u]; e < rp_nn[u + 1]; ++e) {
             const int32_t j = col_nn[e];
-            if (j < end) s += (double)g[j];
+            if (j < end) s += g ? (double)g[j] : 1.0;
         }
         qle[u] = __double2float_ru(s / (double)deg[u] * (1.0 + 1e-6));
     }

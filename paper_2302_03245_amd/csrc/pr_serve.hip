@@ -113,8 +113,12 @@ struct Engine {
         b += align256((size_t)std::max<int32_t>(G.nD, 1) * B * 8);
         b += align256((size_t)G.nN * B * 8);
         b += align256(sizeof(CtlB));
-        b += align256((size_t)4 * B * kRedBlocks * 8);
+        b += align256(batch_part_doubles(B, batch_groups(G, B)) * 8);
         return b;
+    }
+    // vertex groups of the ordered sweeps of a batched run of width B (0: synchronous sweeps)
+    static int batch_groups(const Graph &G, int B) {
+        return batch_ordered_ready(G, B == 8 ? 0 : 1) ? (int)G.grp.size() - 1 : 0;
     }
 
     // workspace of a single-vector solve in this server's residual type
@@ -411,7 +415,12 @@ bool Engine::run() {
     double *xD = (double *)take((size_t)std::max<int32_t>(nD, 1) * Bw * 8);
     double *w2 = (double *)take((size_t)nN * Bw * 8);
     CtlB *dctl = (CtlB *)take(sizeof(CtlB));
-    double *part = (double *)take((size_t)4 * Bw * kRedBlocks * 8);
+    // ordered sweeps once the frontier is dense (see solve_ppr_batch_t)
+    const int ngr = batch_groups(g, Bw);
+    const size_t part_n = batch_part_doubles(Bw, ngr);
+    double *part = (double *)take(part_n * 8);
+    double *sums = part + (part_n - (size_t)5 * Bw * ngr);
+    const GroupBlocks gb = batch_group_blocks(g, Bw);
 
     std::shared_ptr<Request> slots[kMaxBatch];
     int t0[kMaxBatch] = {0};
@@ -488,12 +497,29 @@ bool Engine::run() {
         int youngest = INT_MAX;
         for (int j = 0; j < Bw; ++j)
             if (slots[j]) youngest = std::min(youngest, t - t0[j]);
+        const bool ordered = ngr > 1 && hctl->use_pull;  // the last decided sweep's frontier was dense
         for (int k = 0; k < S && ok && nN > 0; ++k, ++t, ++youngest) {
             size_t e = 0;
             while (e + 1 < g.epochs.size() && g.epochs[e + 1].t_start <= youngest) ++e;
             const MPPlan &pullp = g.bp_pull_nn[slot][e];
-            chk(launch_reserve_b<T, Bw>(t, dctl, nN, h, w, pibar, g.deg, g.rp_nn, c, xi, 1, tol,
-                                        kScatterShareBatch * (double)pullp.edges(), 0, (unsigned long long)pullp.edges(), part, s),
+            const double pull_thr = kScatterShareBatch * (double)pullp.edges();
+            if (ordered) {
+                const std::vector<MPPlan> &gp = g.bp_grp[slot][e];
+                unsigned long long sweep_edges = 0;
+                for (int q = 0; q < ngr && ok; ++q) {
+                    chk(launch_reserve_range_b<T, Bw>(t, dctl, g.grp[q], g.grp[q + 1], h, w, pibar, g.deg, g.rp_nn, c,
+                                                      xi, g.bp_qle, gb.nb[q], part + (size_t)5 * Bw * kGroupBlocks * q,
+                                                      s),
+                        "reserve");
+                    sweep_edges += (unsigned long long)gp[q].edges();
+                    chk(launch_pull_b<T, T, Bw>(t, dctl, gp[q], w, h, 0, s), "pull");
+                }
+                chk(launch_decide_gs_b<Bw>(t, dctl, ngr, gb, part, sums, c, 1, tol, pull_thr, sweep_edges, s),
+                    "decision");
+                continue;
+            }
+            chk(launch_reserve_b<T, Bw>(t, dctl, nN, h, w, pibar, g.deg, g.rp_nn, c, xi, 1, tol, pull_thr, 0,
+                                        (unsigned long long)pullp.edges(), part, s),
                 "reserve");
             chk(launch_push_b<T, Bw>(t, dctl, g.bp_push_nn[slot], w, h, 1, s), "push");
             chk(launch_pull_b<T, T, Bw>(t, dctl, pullp, w, h, 1, s), "pull");

@@ -755,13 +755,65 @@ pr_status solve_power_t(const Graph &G, const double *p, const pr_opts &o, doubl
     return stopped ? PR_OK : PR_ENOCONV;
 }
 
+// Ordered sweeps of the batched kernels of width B for the graph's current vertex groups:
+// the groups' gathers over the rows they reach with tiles of (kBlock / B) * kMPK items,
+// and the unit-weight qle of the sweeps' S_N bookkeeping.  Owned with the groups (freed
+// and rebuilt with them); the caller holds bp_mu.
+template <int B>
+pr_status ensure_batch_groups(Graph &G, hipStream_t s) {
+    constexpr int slot = B == 8 ? 0 : 1;
+    const int32_t ng = (int32_t)G.grp.size() - 1;
+    if (ng < 2 || ng > kMaxGroups || G.grp_pull_rows.size() != G.epochs.size()) return PR_OK;
+    if (G.bp_grp_version[slot] == G.grp_version && (int)G.bp_grp[slot].size() == (int)G.epochs.size()) return PR_OK;
+    auto galloc = [&](auto **p, size_t count) -> hipError_t {
+        using U = std::remove_pointer_t<std::remove_reference_t<decltype(*p)>>;
+        *p = nullptr;
+        const size_t bytes = std::max<size_t>(count, 1) * sizeof(U);
+        hipError_t e = hipMalloc((void **)p, bytes);
+        if (e == hipSuccess) {
+            G.grp_allocs.push_back((void *)*p);
+            G.grp_bytes += (int64_t)bytes;
+            G.device_bytes += (int64_t)bytes;
+        }
+        return e;
+    };
+    if (G.bp_qle_version != G.grp_version || !G.bp_qle) {
+        float *q = nullptr;
+        HIPCHK(galloc(&q, (size_t)G.nN));
+        GroupEnds ge{};
+        ge.ng = ng;
+        for (int32_t k = 0; k < ng; ++k) ge.end[k] = G.grp[(size_t)k + 1];
+        HIPCHK(launch_amp_qle(G.nN, G.rp_nn, G.col_nn, G.deg, nullptr, ge, q, s));
+        G.bp_qle = q;
+        G.bp_qle_version = G.grp_version;
+    }
+    std::vector<std::vector<MPPlan>> plans;
+    for (const std::vector<MPPlan> &ep : G.grp_pull_rows) {
+        std::vector<MPPlan> row;
+        for (const MPPlan &g1 : ep) {
+            MPPlan p = g1;  // the same lists and rows, batched tiles
+            p.ipb = (kBlock / B) * kMPK;
+            p.blocks = 0;
+            const int32_t blocks = (int32_t)(((int64_t)p.items + p.ipb - 1) / p.ipb);
+            HIPCHK(galloc(&p.plan, (size_t)blocks + 1));
+            if (p.R > 0) HIPCHK(launch_plan(p, s));
+            row.push_back(p);
+        }
+        plans.push_back(row);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    G.bp_grp[slot] = plans;
+    G.bp_grp_version[slot] = G.grp_version;
+    return PR_OK;
+}
+
 // Plans for the batched kernels of width B (tiles of (kBlock / B) * kMPK items),
 // built once per graph and width on the first batched solve.
 template <int B>
 pr_status ensure_batch_plans_impl(Graph &G, hipStream_t s) {
     constexpr int slot = B == 8 ? 0 : 1;
     std::lock_guard<std::mutex> lk(G.bp_mu);
-    if (G.bp_ready[slot]) return PR_OK;
+    if (G.bp_ready[slot]) return ensure_batch_groups<B>(G, s);
     auto mk = [&](MPPlan &p, const uint32_t *rpp, const int32_t *idx, int32_t R, int64_t edges) -> hipError_t {
         p.rp = rpp;
         p.idx = idx;
@@ -789,7 +841,7 @@ pr_status ensure_batch_plans_impl(Graph &G, hipStream_t s) {
     HIPCHK(mk(G.bp_push_nn[slot], G.rp_nn, G.col_nn, G.nN, G.mNN));
     HIPCHK(hipStreamSynchronize(s));
     G.bp_ready[slot] = true;
-    return PR_OK;
+    return ensure_batch_groups<B>(G, s);
 }
 
 // IFP2 for kb <= kBatch single-source PPR queries at once (pr_batch.hip):
@@ -813,10 +865,15 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     const double tol = l1 ? o.l1_tol * (1.0 - 1e-6) : 0.0;
     const int max_sweeps = o.max_sweeps > 0 ? o.max_sweeps : 100000;
 
+    const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
+    // ordered sweeps (the vertex groups' gathers one after another, each group reserving
+    // after the earlier groups' gathers of the same sweep) once the frontier is dense
+    const bool ordered_ok = force == 0 && !(o.flags & PR_JACOBI) && nN > 0 && batch_ordered_ready(G, slot);
+    const int ngr = ordered_ok ? (int)G.grp.size() - 1 : 0;
+    const size_t part_n = batch_part_doubles(B, ngr);
     size_t bytes = carve_size<T>((size_t)n * B) + carve_size<T>((size_t)nN * B) + carve_size<double>((size_t)nN * B) +
                    carve_size<double>((size_t)nD * B) + carve_size<double>((size_t)nN * B) +
-                   carve_size<double>(out_dev ? 0 : (size_t)kb * n) + carve_size<CtlB>(1) +
-                   carve_size<double>((size_t)4 * B * kRedBlocks);
+                   carve_size<double>(out_dev ? 0 : (size_t)kb * n) + carve_size<CtlB>(1) + carve_size<double>(part_n);
     Workspace ws;
     ps = acquire_ws(G, bytes, ws, s);
     if (ps != PR_OK) return ps;
@@ -828,7 +885,9 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     double *w2 = cv.take<double>((size_t)nN * B);
     double *outbuf = cv.take<double>(out_dev ? 0 : (size_t)kb * n);
     CtlB *ctl = cv.take<CtlB>(1);
-    double *part = cv.take<double>((size_t)4 * B * kRedBlocks);
+    double *part = cv.take<double>(part_n);
+    double *sums = part + (part_n - (size_t)5 * B * ngr);  // an ordered sweep's row sums
+    const GroupBlocks gb = batch_group_blocks(G, B);
     CtlB *hc = nullptr;
     HIPCHK(hipHostMalloc((void **)&hc, sizeof(CtlB), hipHostMallocDefault));
     std::unique_ptr<CtlB, void (*)(CtlB *)> hc_guard(hc, [](CtlB *p) { (void)hipHostFree(p); });
@@ -847,17 +906,20 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
     const uint32_t kmask = (uint32_t)((1ull << kb) - 1ull);
     HIPCHK(launch_init_b<T, B>(n, nN, G.perm, ss, kmask, h, pibar, s));
 
-    const int force = (o.flags & PR_FORCE_PUSH) ? 1 : ((o.flags & PR_FORCE_PULL) ? 2 : 0);
     const int check_mode = force == 0;
-    auto pull_plan = [&](int t) -> const MPPlan & {
+    auto epoch_of = [&](int t) {
         size_t e = 0;
         while (e + 1 < G.epochs.size() && G.epochs[e + 1].t_start <= t) ++e;
-        return G.bp_pull_nn[slot][e];
+        return e;
     };
+    auto pull_plan = [&](int t) -> const MPPlan & { return G.bp_pull_nn[slot][epoch_of(t)]; };
     int t = 0;
     bool stopped = false;
     if (nN > 0) {
-        int batch = l1 ? 8 : 16;
+        // single-source columns start with a frontier of one vertex each: synchronous
+        // sweeps (scatters) first, the host looking every two sweeps for a dense frontier
+        bool ordered = false;
+        int batch = ordered_ok ? 2 : (l1 ? 8 : 16);
         double bound_prev = -1.0;
         int t_prev = 0;
         while (t < max_sweeps) {
@@ -866,6 +928,20 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
                 const MPPlan &pullp = pull_plan(t);
                 // a gather serves every column; scatter when the active (vertex, column) edges are few
                 const double pull_thr = kScatterShareBatch * (double)pullp.edges();
+                if (ordered) {
+                    const std::vector<MPPlan> &gp = G.bp_grp[slot][epoch_of(t)];
+                    unsigned long long sweep_edges = 0;
+                    for (int q = 0; q < ngr; ++q) {
+                        HIPCHK((launch_reserve_range_b<T, B>(t, ctl, G.grp[q], G.grp[q + 1], h, w, pibar, G.deg,
+                                                             G.rp_nn, c, xi, G.bp_qle, gb.nb[q],
+                                                             part + (size_t)5 * B * kGroupBlocks * q, s)));
+                        sweep_edges += (unsigned long long)gp[q].edges();
+                        HIPCHK((launch_pull_b<T, T, B>(t, ctl, gp[q], w, h, 0, s)));
+                    }
+                    HIPCHK(launch_decide_gs_b<B>(t, ctl, ngr, gb, part, sums, c, l1 ? 1 : 0, tol, pull_thr,
+                                                 sweep_edges, s));
+                    continue;
+                }
                 HIPCHK(launch_reserve_b<T, B>(t, ctl, nN, h, w, pibar, G.deg, G.rp_nn, c, xi, l1 ? 1 : 0, tol,
                                               pull_thr, force, (unsigned long long)pullp.edges(), part, s));
                 if (force != 2) HIPCHK(launch_push_b<T, B>(t, ctl, G.bp_push_nn[slot], w, h, check_mode, s));
@@ -880,7 +956,9 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
             double worst = 0.0;
             for (int j = 0; j < kb; ++j)
                 if (hc->col_stop[j] >= t) worst = std::max(worst, hc->last_bound[j]);
+            ordered = ordered_ok && hc->use_pull;  // dense frontier: ordered sweeps from here
             batch = next_batch(batch, bound_prev, worst, t - t_prev, tol, l1);
+            if (ordered_ok && !ordered) batch = std::min(batch, 2);
             bound_prev = worst;
             t_prev = t;
         }

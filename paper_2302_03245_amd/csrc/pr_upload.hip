@@ -479,6 +479,8 @@ pr_status build_groups(Graph &G, int32_t k, hipStream_t s) {
     G.grp_pull_all.clear();
     G.grp_pull_rows.clear();
     G.grp_pull_all_rows.clear();
+    for (int b = 0; b < 2; ++b) G.bp_grp[b].clear();  // built for the batched kernels from the groups
+    G.bp_qle = nullptr;
     const int64_t n = G.n;
     if (k <= 1 || G.nN == 0 || G.mNN == 0) return PR_OK;
     // a failed build leaves no groups (the graph then sweeps synchronously)

@@ -190,18 +190,23 @@ def test_verify_weighted_bound_needs_its_factor_two():
 
 @pytest.mark.parametrize("gi", range(len(GRAPHS)))
 @pytest.mark.parametrize("groups", [2, 3, 5])
-def test_ordered_sweep_residual_bookkeeping(gi, groups):
+@pytest.mark.parametrize("unit", [False, True])
+def test_ordered_sweep_residual_bookkeeping(gi, groups, unit):
     """An ordered sweep (vertex groups as id ranges, each reserving then pushing along its
     non-dangling out-edges before the next group reserves) leaves sum_N g_i h_i equal to
     the groups' residual left behind at their reserve plus c times the pushed mass weighted
     by qle_u = (1 / deg u) sum of g over u's non-dangling out-neighbours in u's group or an
-    earlier one: the sums the library's ordered sweeps keep instead of a summing pass."""
+    earlier one: the sums the library's ordered sweeps keep instead of a summing pass (with
+    the stop rule's weights for single solves; with unit weights, S_N itself, for batched
+    solves)."""
     g = GRAPHS[gi]
     n = g.n
     deg = np.diff(g.row_ptr)
     nd = deg > 0
     rng = np.random.default_rng(7 + gi)
     w = rng.random(n) + 0.1          # any positive weights: the identity is linear in them
+    if unit:
+        w = np.ones(n)
     h = rng.random(n) * 3.0
     xi = 1.0
     ends = [int(round(n * (q + 1) / groups)) for q in range(groups)]

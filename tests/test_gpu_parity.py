@@ -268,6 +268,37 @@ def test_ppr_batches(pr, mode):
         assert l1(out32[r], ref) <= 1e-6, (r, s)
 
 
+@pytest.mark.parametrize("gi", [0, 1])
+def test_ppr_batch_ordered_sweeps(pr, gi):
+    """Batches of sixteen and of five sources on graphs uploaded with four vertex groups
+    turn to ordered sweeps once their columns' frontiers are dense; their S_N comes
+    from the reserves' own sums.  Every column, FP64 to an empty frontier and FP32 to the
+    certified L1 bound, against the oracle, and against the same batch kept synchronous
+    (jacobi), which needs more sweeps.  Graph 1 has unreferenced vertices (gathers over
+    later epochs' in-lists)."""
+    g = [prgen.workload_rmat_small(seed=5),
+         prgen.random_digraph(20011, 150000, seed=3, dangling_frac=0.2, unref_frac=0.1)][gi]
+    dg = pr.upload(g.row_ptr, g.col, groups=4)
+    assert dg.info()["groups"] == 4
+    deg = np.diff(g.row_ptr)
+    srcs = [int(x) for x in np.random.default_rng(21 + gi).choice(np.flatnonzero(deg > 0), 21, replace=False)]
+    out, st = pr.ppr(dg, srcs, c=C, xi=1e-12)
+    outj, stj = pr.ppr(dg, srcs, c=C, xi=1e-12, jacobi=True)
+    out32, st32 = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32")
+    out32j, st32j = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32", jacobi=True)
+    sw = [sum(x["sweeps"] for x in z) for z in (st, stj, st32, st32j)]
+    _say(f"ppr batch ordered / synchronous sweeps: FP64 {sw[0]} / {sw[1]}, FP32 {sw[2]} / {sw[3]}")
+    assert sw[0] < sw[1] and sw[2] < sw[3]
+    for r, s in enumerate(srcs):
+        p = np.zeros(g.n)
+        p[s] = 1.0
+        ref, _, _ = oracle.power(g, C, p, tol=1e-13)
+        assert st[r]["status"] == 0 and st32[r]["status"] == 0
+        assert l1(out[r], ref) <= 1e-9 and l1(outj[r], ref) <= 1e-9, (r, s)
+        assert st32[r]["l1_bound"] <= 1e-6
+        assert l1(out32[r], ref) <= 1e-6 and l1(out32j[r], ref) <= 1e-6, (r, s)
+
+
 def _dyadic_graph(n, seed):
     """Random digraph whose out-degrees are powers of two (1, 2, 4, 8): with c = 1/2 every
     push weight c v / deg(i) is exact in FP64, so two sweeps that take the same vertices
