@@ -34,6 +34,22 @@ def l1(a, b):
     return float(np.abs(np.asarray(a, dtype=np.float64) - np.asarray(b, dtype=np.float64)).sum())
 
 
+def covered(st, got, ref, tol, ref_err=1e-12):
+    """L1 distance of a result from the oracle's, checked against the run's gate tol and
+    against the run's own reported bound, which must cover the error: l1_verified when the
+    run checked its result (PR_VERIFY, a bound for the computed vector in any residual
+    precision), else l1_bound (the stop rule's: a certificate with FP64 residuals; with
+    FP32 residuals an estimate that leaves out the rounding of the pushes, so FP32 runs
+    whose target is near FP32's rounding floor must verify).  ref_err: the reference's own
+    error (c / (1 - c) times the oracle's power-method tolerance, or FP64 rounding against
+    an exact vector).  Returns the distance."""
+    d = l1(got, ref)
+    assert d <= tol, (d, tol)
+    b = st["l1_verified"] if st.get("l1_verified", 0.0) > 0.0 else st["l1_bound"]
+    assert b >= d - ref_err, (st["l1_verified"], st["l1_bound"], d)
+    return d
+
+
 # caps on eps_inf = max |got - ref| for the top-k tie rule, by residual precision
 EPS_CAP = {"fp64": 1e-12, "fp32": 1e-9}
 

@@ -12,7 +12,7 @@ import pytest
 
 import oracle
 import prgen
-from conftest import l1, topk_agree
+from conftest import covered, l1, topk_agree
 
 pytestmark = pytest.mark.gpu
 
@@ -90,8 +90,9 @@ def test_exact_fixtures(pr, case):
     ref = np.array(case["pi"])
     for fn in (pr.ifp1, pr.ifp2):
         for res, tol in (("fp64", 1e-12), ("fp32", 1e-6)):
-            pi, st = fn(dg, p=p, c=c, xi=1e-15 if res == "fp64" else 1e-9, residual=res)
-            assert l1(pi, ref) <= tol
+            # FP32 at xi = 1e-9 stops below FP32's rounding floor: the run verifies itself
+            pi, st = fn(dg, p=p, c=c, xi=1e-15 if res == "fp64" else 1e-9, residual=res, verify=res == "fp32")
+            covered(st, pi, ref, tol, ref_err=1e-15)
     pi, st = pr.power(dg, p=p, c=c, l1_tol=1e-12)
     assert l1(pi, ref) <= 1e-12
 
@@ -123,11 +124,11 @@ def test_random_graphs(pr, name, kw):
             assert ok, (swaps, eps)
             pi32, st32 = getattr(pr, method)(dg, c=C, l1_tol=1e-6, residual="fp32", mode=mode)
             assert st32["status"] == 0 and st32["l1_bound"] <= 1e-6
-            assert l1(pi32, ref) <= 1e-6
+            covered(st32, pi32, ref, 1e-6)
     pi, st = pr.power(dg, c=C, l1_tol=1e-11)
     assert l1(pi, ref) <= 1e-9
     pi, st = pr.power(dg, c=C, l1_tol=1e-6, residual="fp32")
-    assert l1(pi, ref) <= 1e-6
+    covered(st, pi, ref, 1e-6)
 
 
 @pytest.mark.parametrize("shift", [2, 3, 4])
@@ -157,8 +158,8 @@ def test_depth_epochs_on_a_dag(pr):
             pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
             assert st["status"] == 0
             assert l1(pi, ref) <= 1e-9
-            pi32, _ = getattr(pr, method)(dg, c=C, l1_tol=1e-6, residual="fp32", mode=mode)
-            assert l1(pi32, ref) <= 1e-6
+            pi32, st32 = getattr(pr, method)(dg, c=C, l1_tol=1e-6, residual="fp32", mode=mode)
+            covered(st32, pi32, ref, 1e-6)
     p = prgen.random_p(g.n, seed=3, zero_frac=0.5)
     ref_p, _, _ = oracle.power(g, C, p, tol=1e-13)
     pi, _ = pr.ifp2(dg, p=p, c=C, xi=1e-13, mode="pull")
@@ -241,10 +242,10 @@ def test_ppr_sources(pr):
         ref, _, _ = oracle.power(g, C, p, tol=1e-13)
         _say(f"ppr source {s}: sweeps {stats[r]['sweeps']}")
         assert l1(out[r], ref) <= 1e-9
-    out32, _ = pr.ppr(dg, srcs[:1], c=C, l1_tol=1e-6, residual="fp32")
+    out32, st32 = pr.ppr(dg, srcs[:1], c=C, l1_tol=1e-6, residual="fp32")
     p = np.zeros(g.n)
     p[srcs[0]] = 1.0
-    assert l1(out32[0], oracle.power(g, C, p, tol=1e-13)[0]) <= 1e-6
+    covered(st32[0], out32[0], oracle.power(g, C, p, tol=1e-13)[0], 1e-6)
 
 
 @pytest.mark.parametrize("mode", [None, "push", "pull", "list"])
@@ -265,7 +266,7 @@ def test_ppr_batches(pr, mode):
         assert stats[r]["status"] == 0
         assert l1(out[r], ref) <= 1e-9, (r, s)
         assert stats32[r]["l1_bound"] <= 1e-6
-        assert l1(out32[r], ref) <= 1e-6, (r, s)
+        covered(stats32[r], out32[r], ref, 1e-6)
 
 
 @pytest.mark.parametrize("gi", [0, 1])
@@ -296,7 +297,8 @@ def test_ppr_batch_ordered_sweeps(pr, gi):
         assert st[r]["status"] == 0 and st32[r]["status"] == 0
         assert l1(out[r], ref) <= 1e-9 and l1(outj[r], ref) <= 1e-9, (r, s)
         assert st32[r]["l1_bound"] <= 1e-6
-        assert l1(out32[r], ref) <= 1e-6 and l1(out32j[r], ref) <= 1e-6, (r, s)
+        covered(st32[r], out32[r], ref, 1e-6)
+        covered(st32j[r], out32j[r], ref, 1e-6)
 
 
 def _dyadic_graph(n, seed):
@@ -351,7 +353,7 @@ def test_list_sweeps_sparse_then_dense(pr):
         out, sts = pr.ppr(dg, [s], c=C, xi=1e-13)
         assert sts[0]["status"] == 0 and l1(out[0], ref) <= 1e-9, s
         out32, sts32 = pr.ppr(dg, [s], c=C, l1_tol=1e-6, residual="fp32")
-        assert l1(out32[0], ref) <= 1e-6, s
+        covered(sts32[0], out32[0], ref, 1e-6)
     p = np.zeros(g.n)
     p[np.random.default_rng(1).choice(g.n, 5, replace=False)] = 1.0
     ref = oracle.power(g, C, p, tol=1e-13)[0]
@@ -518,7 +520,8 @@ def test_tiles_of_row_ends_only(pr, shift):
         _say(f"shift {shift} {method}: sweeps {st['sweeps']} L1 {l1(pi, ref):.2e}")
         assert st["status"] == 0 and l1(pi, ref) <= 1e-9
         pi32, st32 = getattr(pr, method)(dg, c=C, l1_tol=1e-6, residual="fp32", mode="pull")
-        assert st32["l1_bound"] <= 1e-6 and l1(pi32, ref) <= 1e-6
+        assert st32["l1_bound"] <= 1e-6
+        covered(st32, pi32, ref, 1e-6)
     pw, _ = pr.power(dg, c=C, l1_tol=1e-12)
     assert l1(pw, ref) <= 1e-11
     dg.free()
@@ -537,7 +540,8 @@ def test_batched_tiles_of_row_ends_only(pr):
             p[s] = 1.0
             ref, _, _ = oracle.power(g, C, p, tol=1e-13)
             assert stats[r]["status"] == 0 and l1(out[r], ref) <= 1e-9, (len(srcs), s)
-            assert stats32[r]["l1_bound"] <= 1e-6 and l1(out32[r], ref) <= 1e-6, (len(srcs), s)
+            assert stats32[r]["l1_bound"] <= 1e-6, (len(srcs), s)
+            covered(stats32[r], out32[r], ref, 1e-6)
     dg.free()
 
 
@@ -673,7 +677,8 @@ def test_group_gathers_over_reached_rows(pr, groups):
         if rep["chosen"]["ordered"]:
             assert {(True, True), (True, False)} <= forms, rep
         pt, stt = pr.ifp2(da, c=C, l1_tol=1e-6, residual="fp32")
-        assert stt["status"] == 0 and l1(pt, ref) <= 1e-6
+        assert stt["status"] == 0
+        covered(stt, pt, ref, 1e-6)
         dr.free()
         da.free()
 
@@ -699,7 +704,8 @@ def test_ordered_sweeps(pr, groups):
             po, so = pr.ifp2(dg, c=C, l1_tol=tol, residual=residual)
             pj, sj = pr.ifp2(dg, c=C, l1_tol=tol, residual=residual, jacobi=True)
             assert so["status"] == 0 and so["l1_bound"] <= tol and sj["l1_bound"] <= tol
-            assert l1(po, ref) <= tol and l1(pj, ref) <= tol
+            covered(so, po, ref, tol)
+            covered(sj, pj, ref, tol)
             assert l1(po, pj) <= 2 * tol
             assert abs(po.sum() - 1) < 1e-12
             if groups == 1:
@@ -715,7 +721,8 @@ def test_ordered_sweeps(pr, groups):
             po, so = pr.ifp1(dg, c=C, l1_tol=tol, residual=residual)
             pj, sj = pr.ifp1(dg, c=C, l1_tol=tol, residual=residual, jacobi=True)
             assert so["status"] == 0 and so["l1_bound"] <= tol and sj["l1_bound"] <= tol
-            assert l1(po, ref) <= tol and l1(pj, ref) <= tol
+            covered(so, po, ref, tol)
+            covered(sj, pj, ref, tol)
             if groups == 1:
                 assert so["sweeps"] == sj["sweeps"]
             else:
@@ -759,7 +766,8 @@ def test_autotune_keeps_results(pr):
                 pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
                 assert l1(pi, ref) <= 1e-9, (method, mode)
         pi, st = pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32")
-        assert st["l1_bound"] <= 1e-6 and l1(pi, ref) <= 1e-6
+        assert st["l1_bound"] <= 1e-6
+        covered(st, pi, ref, 1e-6)
         pw, _ = pr.power(dg, c=C, l1_tol=1e-11)
         assert l1(pw, ref) <= 1e-9
         srcs = [0, g.n // 2, g.n - 1]
@@ -789,7 +797,8 @@ def test_ordered_sweeps_after_a_sparse_start(pr):
         assert l1(out[0], ref) <= 1e-9 and l1(outj[0], ref) <= 1e-9
         assert st[0]["sweeps"] <= stj[0]["sweeps"] + 1, (st[0]["sweeps"], stj[0]["sweeps"])
         o32, s32 = pr.ppr(dg, [int(s)], c=C, l1_tol=1e-6, residual="fp32")
-        assert s32[0]["l1_bound"] <= 1e-6 and l1(o32[0], ref) <= 1e-6
+        assert s32[0]["l1_bound"] <= 1e-6
+        covered(s32[0], o32[0], ref, 1e-6)
     p = prgen.random_p(g.n, seed=4, zero_frac=0.3)
     ref = oracle.power(g, C, p, tol=1e-13)[0]
     for method in (pr.ifp2, pr.ifp1):
