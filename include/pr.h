@@ -224,6 +224,10 @@ typedef struct {
     int32_t sweeps[PR_TUNE_MAX];
     int32_t chosen;                   /* index of the candidate the graph keeps */
     double seconds;                   /* wall time spent tuning */
+    int32_t batch_ordered;            /* pr_graph_tune: whether batched solves (pr_ppr batches, the
+                                         query server's batched runs) turn to ordered sweeps (1) or
+                                         stay synchronous (0); -1 not measured (no ordered sweeps) */
+    double batch_ms[2];               /* the 16-source PPR batch timed for that choice: ordered, synchronous */
 } pr_tune_report;
 
 /*
@@ -238,8 +242,12 @@ typedef struct {
  * are rebuilt for each).  It
  * keeps the fastest: later solves of every kind use its tile size, and global IFP2
  * solves use ordered sweeps, with that group count and form of gather, only if it chose
- * them.  Results do not change beyond rounding order.  No other call may use the graph
- * meanwhile.
+ * them.  If it did, on a graph uploaded without PR_PEEL (pr_ppr solves a peeled graph's
+ * sources one at a time), it then times a batch of 16 single-source PPR queries (non-dangling
+ * sources spread over the ids, o's stop rule and residual type) with ordered and with
+ * synchronous sweeps, and batched solves keep the faster (an ordered sweep of a batch
+ * costs more than a synchronous one, and on some graphs saves few sweeps).  Results do
+ * not change beyond rounding order.  No other call may use the graph meanwhile.
  * rep may be NULL.  PR_EINVAL on bad options or forced scatter modes.
  */
 pr_status pr_graph_tune(pr_graph *g, const pr_opts *o, int32_t reps, pr_tune_report *rep);

@@ -98,7 +98,8 @@ class GraphInfo(ctypes.Structure):
 class TuneReport(ctypes.Structure):
     _fields_ = [("candidates", ctypes.c_int32), ("tile_shift", ctypes.c_int32 * 16), ("groups", ctypes.c_int32 * 16),
                 ("ordered", ctypes.c_int32 * 16), ("ms", ctypes.c_double * 16), ("sweeps", ctypes.c_int32 * 16),
-                ("chosen", ctypes.c_int32), ("seconds", ctypes.c_double)]
+                ("chosen", ctypes.c_int32), ("seconds", ctypes.c_double), ("batch_ordered", ctypes.c_int32),
+                ("batch_ms", ctypes.c_double * 2)]
 
 
 _lib = None
@@ -297,7 +298,8 @@ def tune(g: Graph, c=0.85, xi=1e-12, l1_tol=None, residual="fp64", reps=2) -> di
     k = r.candidates
     cands = [{"tile_shift": r.tile_shift[i], "ordered": bool(r.ordered[i]), "group_rows": r.ordered[i] == 2,
               "groups": r.groups[i], "ms": r.ms[i], "sweeps": r.sweeps[i]} for i in range(k)]
-    return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds}
+    return {"candidates": cands, "chosen": cands[r.chosen], "seconds": r.seconds,
+            "batch_ordered": r.batch_ordered, "batch_ms": {"ordered": r.batch_ms[0], "synchronous": r.batch_ms[1]}}
 
 
 class State:

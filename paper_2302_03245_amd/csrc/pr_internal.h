@@ -252,6 +252,9 @@ struct Graph {
     // serving both since the non-dangling rows come first
     std::vector<int32_t> grp;
     bool prefer_ordered = true;                     // set by the autotuner
+    // batched solves (PPR batches, the server's batched runs) turn to ordered sweeps once
+    // dense: -1 not measured (they do), 0 / 1 as the autotuner measured (see tune_impl)
+    int32_t batch_order = -1;
     std::vector<std::vector<MPPlan>> grp_pull;      // [epoch][group], rows [0, nN)
     std::vector<std::vector<MPPlan>> grp_pull_all;  // [epoch][group], rows [0, n)
     // the same gathers over only the rows each group reaches (MPPlan::rid)
@@ -291,10 +294,11 @@ struct Graph {
 };
 
 // Ordered sweeps of a batched solve of width B (slot 0: 8, 1: 16) are possible: the graph
-// has vertex groups, prefers ordered sweeps, and its batched group plans are current.
+// has vertex groups, prefers ordered sweeps (for batches too, unless the autotuner found
+// them slower there), and its batched group plans are current.
 inline bool batch_ordered_ready(const Graph &G, int slot) {
     const int ng = (int)G.grp.size() - 1;
-    return ng > 1 && ng <= kMaxGroups && G.prefer_ordered && G.bp_qle != nullptr &&
+    return ng > 1 && ng <= kMaxGroups && G.prefer_ordered && G.batch_order != 0 && G.bp_qle != nullptr &&
            G.bp_qle_version == G.grp_version && G.bp_grp_version[slot] == G.grp_version &&
            G.bp_grp[slot].size() == G.epochs.size();
 }

@@ -852,6 +852,10 @@ pr_status solve_ppr_batch_t(const Graph &Gc, const int32_t *srcs, int kb, const 
                             pr_stats *st) {
     constexpr int slot = B == 8 ? 0 : 1;
     Graph &G = const_cast<Graph &>(Gc);
+    // the batched dangling phase gathers from the swept vertices only: on a graph with
+    // peeled vertices, whose in-edges into the deferred region also start at peeled
+    // vertices, it would read past the swept vertices' weights
+    if (G.nP > 0) return set_error(PR_EINVAL, "batched solves need a graph uploaded without PR_PEEL");
     hipStream_t s = o.stream ? (hipStream_t)o.stream : G.stream;
     pr_status ps = ensure_batch_plans_impl<B>(G, s);
     if (ps != PR_OK) return ps;
@@ -1086,6 +1090,40 @@ pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *re
     }
     G.prefer_ordered = r.ordered[best_i] != 0;
     G.group_rows = r.ordered[best_i] == 0 ? rows0 : r.ordered[best_i] == 2;
+    // Batched solves under the chosen schedule: an ordered sweep of a batch gathers every
+    // group over the rows it reaches for all columns, which costs more than one synchronous
+    // gather, and single-source columns gain fewer sweeps from the ordering on some graphs
+    // (the layered DAG) than on others; time a 16-source PPR batch both ways, keep the faster
+    r.batch_ordered = -1;
+    if (G.prefer_ordered && G.nN > 0 && G.nP == 0) {  // a peeled graph's PPR runs one source at a time
+        int32_t srcs[kBatch];
+        for (int j = 0; j < kBatch; ++j) {
+            // the first non-dangling vertex at or after an evenly spaced original id
+            int64_t v = (int64_t)((2 * j + 1) * (double)G.n / (2 * kBatch));
+            for (int64_t k = 0; k < G.n && G.dangling(v); ++k) v = (v + 1) % G.n;
+            srcs[j] = (int32_t)v;
+        }
+        double *outb = nullptr;
+        HIPCHK(hipMalloc((void **)&outb, sizeof(double) * kBatch * (size_t)G.n));
+        Free fb{outb};
+        double ms2[2] = {INFINITY, INFINITY};
+        G.batch_order = 1;
+        for (int form = 0; form < 2; ++form) {  // 0: ordered once dense, 1: synchronous
+            pr_opts ob = op;
+            if (form == 1) ob.flags |= PR_JACOBI;
+            for (int32_t q = 0; q <= reps; ++q) {
+                pr_stats st[kBatch];
+                ps = op.residual == PR_RES_FP32 ? solve_ppr_batch_t<float, kBatch>(G, srcs, kBatch, ob, outb, st)
+                                                : solve_ppr_batch_t<double, kBatch>(G, srcs, kBatch, ob, outb, st);
+                if (ps < 0) return ps;
+                if (q > 0) ms2[form] = std::min(ms2[form], st[0].seconds_solve * 1e3);
+            }
+        }
+        G.batch_order = ms2[0] <= ms2[1] ? 1 : 0;
+        r.batch_ordered = G.batch_order;
+        r.batch_ms[0] = ms2[0];
+        r.batch_ms[1] = ms2[1];
+    }
     r.seconds = (double)clock_now_ns() * 1e-9 - t_start;
     if (rep) *rep = r;
     return PR_OK;

@@ -40,7 +40,8 @@ def covered(st, got, ref, tol, ref_err=1e-12):
     run checked its result (PR_VERIFY, a bound for the computed vector in any residual
     precision), else l1_bound (the stop rule's: a certificate with FP64 residuals; with
     FP32 residuals an estimate that leaves out the rounding of the pushes, so FP32 runs
-    whose target is near FP32's rounding floor must verify).  ref_err: the reference's own
+    whose target is near FP32's rounding floor, or whose residuals may all drain to zero,
+    must verify or be checked against the gate alone).  ref_err: the reference's own
     error (c / (1 - c) times the oracle's power-method tolerance, or FP64 rounding against
     an exact vector).  Returns the distance."""
     d = l1(got, ref)

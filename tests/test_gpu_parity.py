@@ -761,6 +761,12 @@ def test_autotune_keeps_results(pr):
         assert info["ordered"] == int(rep["chosen"]["ordered"])
         if rep["chosen"]["ordered"]:
             assert info["groups"] == rep["chosen"]["groups"]
+            # batched solves: a 16-source PPR batch timed both ways, the faster kept
+            bm = rep["batch_ms"]
+            assert rep["batch_ordered"] in (0, 1) and bm["ordered"] > 0 and bm["synchronous"] > 0, rep
+            assert (bm["ordered"] <= bm["synchronous"]) == (rep["batch_ordered"] == 1), rep
+        else:
+            assert rep["batch_ordered"] == -1, rep
         for method in ("ifp1", "ifp2"):
             for mode in (None, "push", "pull", "list"):
                 pi, st = getattr(pr, method)(dg, c=C, xi=1e-13, mode=mode)
@@ -776,6 +782,17 @@ def test_autotune_keeps_results(pr):
             p = np.zeros(g.n)
             p[s] = 1.0
             assert l1(out[r], oracle.power(g, C, p, tol=1e-13)[0]) <= 1e-9
+        # a batch of sixteen under the batched sweeps the tuner kept (the gate only: a batched
+        # FP32 column does not verify itself, and one whose residuals all drain to zero
+        # reports an estimate of 0 against an error of FP32 rounding, about 1e-9)
+        deg = np.diff(g.row_ptr)
+        srcs = [int(x) for x in np.random.default_rng(3).choice(np.flatnonzero(deg > 0), 16, replace=False)]
+        out, sts = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32")
+        for r, s in enumerate(srcs[:4]):
+            p = np.zeros(g.n)
+            p[s] = 1.0
+            assert sts[r]["status"] == 0 and sts[r]["l1_bound"] <= 1e-6
+            assert l1(out[r], oracle.power(g, C, p, tol=1e-13)[0]) <= 1e-6
     o = pr._opts(C, 1e-12, 1e-6, "fp32", 0, None, False, "push", False)
     assert pr.lib().pr_graph_tune(dg.handle, o, 1, None) == pr.PR_EINVAL
     assert "automatic" in pr.lib().pr_last_error().decode()

@@ -143,6 +143,8 @@ def test_tiles_groups_and_tuning(pr, shift, groups):
     if groups:
         rep = pr.tune(dg, c=C, l1_tol=1e-6, residual="fp32", reps=1)
         _say(f"tune on a peeled graph: {rep}")
+        # pr_ppr solves a peeled graph's sources one at a time: the tuner times no batch
+        assert rep["batch_ordered"] == -1, rep
         pi, st = pr.ifp2(dg, c=C, l1_tol=1e-6, residual="fp32")
         assert st["l1_bound"] <= 1e-6 and l1(pi, ref) <= 1e-6
 
