@@ -144,7 +144,8 @@ typedef struct {
                                    gives a bound that holds for the computed result */
     double seconds_solve;       /* device time from initialisation to the written result */
     double seconds_preprocess;  /* one-time per-graph preprocessing charged to this method (seconds): for
-                                   folded IFP2 the edge split and the stop rule's weights for c */
+                                   folded IFP2 the edge split and the stop rule's weights for c (with
+                                   ordered sweeps, also their restriction to the vertex groups) */
     /* PR_PROFILE only (else 0): the scatter (push) and gather (pull) kernels of the sweeps,
        timed with HIP events on the solve stream; launches that did work, their summed
        duration, and their algorithmic bytes (edge-index stream + residual traffic) */

@@ -285,6 +285,7 @@ struct Graph {
         // for the vertex groups of version qle_version (see launch_amp_qle)
         float *qle = nullptr;
         int64_t qle_version = -1;
+        double qle_seconds = 0.0;  // time taken to build qle (charged as preprocessing)
     };
     int64_t grp_version = 0;  // bumped whenever the vertex groups are rebuilt
     std::mutex amp_mu;

@@ -1437,23 +1437,36 @@ __global__ void k_amp_q(int32_t nN, const int32_t *deg, const double *acc, float
         q[i] = __double2float_ru(acc[i] / (double)deg[i] * (1.0 + 1e-6));
 }
 
-// see launch_amp_qle; one thread per vertex (built once per graph, factor and grouping;
-// unit weights when g is null)
-__global__ void k_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_nn, const int32_t *deg,
-                          const float *g, GroupEnds ge, float *qle) {
-    for (int64_t u = blockIdx.x * (int64_t)kBlock + threadIdx.x; u < nN; u += (int64_t)gridDim.x * kBlock) {
+// see launch_amp_qle; one wave per vertex, its out-list split over the lanes with eight
+// edges per lane in flight (a hub's list of 10^5 edges would take one thread milliseconds);
+// built once per graph, factor and grouping; unit weights when g is null
+__global__ __launch_bounds__(kBlock) void k_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_nn,
+                                                    const int32_t *deg, const float *g, GroupEnds ge, float *qle) {
+    constexpr int U = 8;
+    const int lane = lane_id();
+    const int64_t nwaves = (int64_t)gridDim.x * (kBlock / W);
+    for (int64_t u = blockIdx.x * (int64_t)(kBlock / W) + threadIdx.x / W; u < nN; u += nwaves) {
         int32_t end = nN;
         for (int q = 0; q < ge.ng; ++q)
             if (u < ge.end[q]) {
                 end = ge.end[q];
                 break;
             }
+        const uint32_t e0 = rp_nn[u], e1 = rp_nn[u + 1];
         double s = 0.0;
-        for (uint32_t e = rp_nn[u]; e < rp_nn[u + 1]; ++e) {
-            const int32_t j = col_nn[e];
-            if (j < end) s += g ? (double)g[j] : 1.0;
+        for (uint32_t e = e0 + (uint32_t)lane; e < e1; e += U * W) {
+            int32_t j[U];
+#pragma unroll
+            for (int k = 0; k < U; ++k) {
+                const uint32_t ek = e + (uint32_t)(k * W);
+                j[k] = ek < e1 ? col_nn[ek] : end;  // past the row: a target that is not counted
+            }
+#pragma unroll
+            for (int k = 0; k < U; ++k)
+                if (j[k] < end) s += g ? (double)g[j[k]] : 1.0;
         }
-        qle[u] = __double2float_ru(s / (double)deg[u] * (1.0 + 1e-6));
+        s = wave_sum(s);
+        if (lane == 0) qle[u] = __double2float_ru(s / (double)deg[u] * (1.0 + 1e-6));
     }
 }
 
@@ -1772,7 +1785,7 @@ hipError_t launch_amp_weights(int32_t nN, const MPPlan &push_nn, const int32_t *
 hipError_t launch_amp_qle(int32_t nN, const uint32_t *rp_nn, const int32_t *col_nn, const int32_t *deg,
                           const float *g, const GroupEnds &ge, float *qle, hipStream_t s) {
     if (nN <= 0) return hipSuccess;
-    PRK_LAUNCH(k_amp_qle, grid_for(nN, 1, 8192), nN, rp_nn, col_nn, deg, g, ge, qle);
+    PRK_LAUNCH(k_amp_qle, grid_for((int64_t)nN * W, 1, 16384), nN, rp_nn, col_nn, deg, g, ge, qle);
 }
 
 hipError_t launch_zero_u32(uint32_t *p, int64_t count, hipStream_t s) {

@@ -87,8 +87,9 @@ static pr_status amp_weights(Graph &G, double c, bool may_alloc, hipStream_t s, 
 // (launch_amp_qle) for factor c and the graph's current vertex groups, built on first use
 // and kept with the factor's weights; null when the factor has no weights, or when they
 // are missing and the solve may not allocate (the sweeps then sum S_N directly).
-static pr_status amp_qle(Graph &G, double c, bool may_alloc, hipStream_t s, const float **out) {
+static pr_status amp_qle(Graph &G, double c, bool may_alloc, hipStream_t s, const float **out, double *seconds) {
     *out = nullptr;
+    *seconds = 0.0;
     const int32_t ng = (int32_t)G.grp.size() - 1;
     if (ng < 2 || ng > kMaxGroups) return PR_OK;
     std::lock_guard<std::mutex> lk(G.amp_mu);
@@ -96,6 +97,7 @@ static pr_status amp_qle(Graph &G, double c, bool may_alloc, hipStream_t s, cons
         if (a.c != c) continue;
         if (a.qle && a.qle_version == G.grp_version) {
             *out = a.qle;
+            *seconds = a.qle_seconds;
             return PR_OK;
         }
         if (!may_alloc) return PR_OK;
@@ -111,10 +113,14 @@ static pr_status amp_qle(Graph &G, double c, bool may_alloc, hipStream_t s, cons
         GroupEnds ge{};
         ge.ng = ng;
         for (int32_t q = 0; q < ng; ++q) ge.end[q] = G.grp[(size_t)q + 1];
+        const auto t0 = std::chrono::steady_clock::now();
+        HIPCHK(hipStreamSynchronize(s));
         HIPCHK(launch_amp_qle(G.nN, G.rp_nn, G.col_nn, G.deg, a.g, ge, a.qle, s));
         HIPCHK(hipStreamSynchronize(s));  // other streams may take the weights from the table
+        a.qle_seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
         a.qle_version = G.grp_version;
         *out = a.qle;
+        *seconds = a.qle_seconds;
         return PR_OK;
     }
     return PR_OK;
@@ -363,8 +369,10 @@ pr_status solve_ifp_t(const Graph &G, bool ifp2, const double *p, int32_t source
     // (no summing pass per sweep); residuals of either sign (a warm start) are summed
     const float *qle = nullptr;
     if (ordered_ok && ew.g && !warm) {
-        ps = amp_qle(const_cast<Graph &>(G), c, ext == nullptr, s, &qle);
+        double seconds_qle = 0.0;
+        ps = amp_qle(const_cast<Graph &>(G), c, ext == nullptr, s, &qle, &seconds_qle);
         if (ps != PR_OK) return ps;
+        seconds_weights += seconds_qle;  // built once per graph, factor and grouping: preprocessing
     }
     const ErrWeights ew_ord = qle ? ErrWeights{ew.g, qle} : ErrWeights{nullptr, nullptr};
     bool ordered = ordered_ok && a.uniform && !warm;
