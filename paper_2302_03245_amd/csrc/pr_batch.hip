@@ -565,6 +565,7 @@ template <typename WT, typename OT, int B>
 hipError_t launch_pull_b(int t, const CtlB *ctl, const MPPlan &p, const WT *w, OT *out, int check_mode,
                          hipStream_t s) {
     if (p.blocks == 0 || p.edges() == 0) return hipSuccess;
+    if (p.ipb != (kBlock / B) * kMPK) return hipErrorInvalidValue;  // the plan's tiles are the kernel's
     auto kern = &k_pull_b<WT, OT, B, kMPK>;
     static const int grid = resident_grid(kern);
     hipLaunchKernelGGL(kern, dim3(std::min(p.blocks, grid)), dim3(kBlock), 0, s, t, ctl, check_mode, p.rp, p.R, p.idx,
