@@ -206,13 +206,34 @@ def test_ppr_batch_scale22(pr_lib):
         p = np.zeros(g.n)
         p[srcs[r]] = 1.0
         refs.append((g, C, p, 1e-12))
-    for r, ref in enumerate(oracle_many(refs)):
+    refv = list(oracle_many(refs))
+    for r, ref in enumerate(refv):
         d = l1(out[r], ref)
         print(f"ppr column {r} (source {srcs[r]}): sweeps {sts[r]['sweeps']} L1 vs oracle {d:.3e} "
               f"bound {sts[r]['l1_bound']:.3e}", flush=True)
         assert d <= 1e-6
         assert sts[r]["l1_bound"] >= d - C / (1 - C) * 1e-12, (r, sts[r]["l1_bound"], d)
+    # Once the autotuner keeps ordered sweeps it times a 16-source batch both ways, and
+    # batches then run as it chose.  The same graph uploaded with PR_PEEL times no batch:
+    # pr_ppr solves a peeled graph's sources one at a time.
+    rep = pr.tune(dg, c=C, l1_tol=1e-6, residual="fp32", reps=1)
+    print(f"tuned: {rep['chosen']} batch_ordered {rep['batch_ordered']} {rep['batch_ms']}", flush=True)
+    if rep["chosen"]["ordered"]:
+        bm = rep["batch_ms"]
+        assert rep["batch_ordered"] in (0, 1) and bm["ordered"] > 0 and bm["synchronous"] > 0, rep
+        assert (bm["ordered"] <= bm["synchronous"]) == (rep["batch_ordered"] == 1), rep
+    out2, sts2 = pr.ppr(dg, srcs, c=C, l1_tol=1e-6, residual="fp32")
+    for r, ref in enumerate(refv):
+        assert sts2[r]["status"] == 0 and l1(out2[r], ref) <= 1e-6, r
     dg.free()
+    dp = pr.upload(g.row_ptr, g.col, peel=True)
+    rp = pr.tune(dp, c=C, l1_tol=1e-6, residual="fp32", reps=1)
+    print(f"tuned peeled: {rp['chosen']} batch_ordered {rp['batch_ordered']}", flush=True)
+    assert rp["batch_ordered"] == -1, rp
+    outp, stp = pr.ppr(dp, srcs[:2], c=C, l1_tol=1e-6, residual="fp32")
+    for r in range(2):
+        assert stp[r]["status"] == 0 and l1(outp[r], refv[r]) <= 1e-6, r
+    dp.free()
 
 
 @pytest.mark.timeout(600)
