@@ -227,7 +227,8 @@ typedef struct {
     double seconds;                   /* wall time spent tuning */
     int32_t batch_ordered;            /* pr_graph_tune: whether batched solves (pr_ppr batches, the
                                          query server's batched runs) turn to ordered sweeps (1) or
-                                         stay synchronous (0); -1 not measured (no ordered sweeps) */
+                                         stay synchronous (0); -1 not measured (no ordered sweeps, a
+                                         peeled graph, or no room for the batch's output) */
     double batch_ms[2];               /* the 16-source PPR batch timed for that choice: ordered, synchronous */
 } pr_tune_report;
 

@@ -1111,12 +1111,14 @@ pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *re
             for (int64_t k = 0; k < G.n && G.dangling(v); ++k) v = (v + 1) % G.n;
             srcs[j] = (int32_t)v;
         }
+        // the batch's output: when the device cannot hold it, batches keep their default
         double *outb = nullptr;
-        HIPCHK(hipMalloc((void **)&outb, sizeof(double) * kBatch * (size_t)G.n));
+        const bool room = hipMalloc((void **)&outb, sizeof(double) * kBatch * (size_t)G.n) == hipSuccess;
+        if (!room) (void)hipGetLastError();
         Free fb{outb};
         double ms2[2] = {INFINITY, INFINITY};
-        G.batch_order = 1;
-        for (int form = 0; form < 2; ++form) {  // 0: ordered once dense, 1: synchronous
+        if (room) G.batch_order = 1;
+        for (int form = 0; room && form < 2; ++form) {  // 0: ordered once dense, 1: synchronous
             pr_opts ob = op;
             if (form == 1) ob.flags |= PR_JACOBI;
             for (int32_t q = 0; q <= reps; ++q) {
@@ -1127,10 +1129,12 @@ pr_status tune_impl(Graph &G, const pr_opts &o, int32_t reps, pr_tune_report *re
                 if (q > 0) ms2[form] = std::min(ms2[form], st[0].seconds_solve * 1e3);
             }
         }
-        G.batch_order = ms2[0] <= ms2[1] ? 1 : 0;
-        r.batch_ordered = G.batch_order;
-        r.batch_ms[0] = ms2[0];
-        r.batch_ms[1] = ms2[1];
+        if (room) {
+            G.batch_order = ms2[0] <= ms2[1] ? 1 : 0;
+            r.batch_ordered = G.batch_order;
+            r.batch_ms[0] = ms2[0];
+            r.batch_ms[1] = ms2[1];
+        }
     }
     r.seconds = (double)clock_now_ns() * 1e-9 - t_start;
     if (rep) *rep = r;
