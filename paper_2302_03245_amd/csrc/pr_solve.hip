@@ -821,7 +821,15 @@ template <int B>
 pr_status ensure_batch_plans_impl(Graph &G, hipStream_t s) {
     constexpr int slot = B == 8 ? 0 : 1;
     std::lock_guard<std::mutex> lk(G.bp_mu);
-    if (G.bp_ready[slot]) return ensure_batch_groups<B>(G, s);
+    // without room for the groups' batched plans, batches sweep synchronously
+    auto groups = [&]() -> pr_status {
+        const pr_status gs = ensure_batch_groups<B>(G, s);
+        if (gs != PR_ENOMEM) return gs;
+        (void)hipGetLastError();  // the refused allocation must not read as a later launch's error
+        clear_error();
+        return PR_OK;
+    };
+    if (G.bp_ready[slot]) return groups();
     auto mk = [&](MPPlan &p, const uint32_t *rpp, const int32_t *idx, int32_t R, int64_t edges) -> hipError_t {
         p.rp = rpp;
         p.idx = idx;
@@ -849,7 +857,7 @@ pr_status ensure_batch_plans_impl(Graph &G, hipStream_t s) {
     HIPCHK(mk(G.bp_push_nn[slot], G.rp_nn, G.col_nn, G.nN, G.mNN));
     HIPCHK(hipStreamSynchronize(s));
     G.bp_ready[slot] = true;
-    return ensure_batch_groups<B>(G, s);
+    return groups();
 }
 
 // IFP2 for kb <= kBatch single-source PPR queries at once (pr_batch.hip):
